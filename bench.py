@@ -1,0 +1,203 @@
+"""Benchmark: reduced-camera-system solves/s on the F-1936-shaped banded workload.
+
+One step = one complete solve of S dx_p = -b~ from x0 = 0 to a 1e-6 relative
+residual (all device kernels of the chosen solver; the system is built once,
+outside the timed region, with its inputs resident in HBM).  Prints one JSON
+line.  See the design doc for the workload recipe and the roofline accounting.
+
+    python bench.py [--steps K] [--warmup W] [--solver mcg|pcg] [--N 16] [--tau 3.3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, vendor figure
+COUNTERS = os.path.join(ROOT, "profiles", "schur1_fp64_walk1936_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2110_04015_amd", "csrc", "k_schur.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the chunk kernel from committed rocprofv3 counters, or None
+    when the counters were taken on another version of the kernel source."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_src_sha256_16") != kernel_hash():
+        return None
+    return c.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--solver", choices=["mcg", "pcg"], default="mcg")
+    ap.add_argument("--N", type=int, default=16)
+    ap.add_argument("--tau", type=float, default=3.3)
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2110_04015_amd as ba
+    import synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(3)
+    torch.cuda.set_device(0)
+    t = time.time()
+    p = synth.config1(seed=args.seed)
+    log(f"generated {p.name}: {p.n_cams} cameras, {p.n_lms} landmarks, {p.n_obs} observations "
+        f"in {time.time() - t:.1f} s")
+    t = time.time()
+    g = ba.System.from_problem(p)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    info = g.info()
+    log(f"built system in {build_s:.2f} s: {info}")
+
+    def step(precision=args.precision, solver=args.solver, N=args.N, tau=args.tau):
+        if solver == "pcg":
+            return g.pcg(eps=1e-6, max_iter=1000, precision=precision)
+        return g.mcg(N, tau, eps=1e-6, max_iter=1000, precision=precision)
+
+    for i in range(args.warmup):
+        x, st = step()
+        log(f"warmup {i}: {st.iterations} iterations, {st.multi_steps} multidirectional, "
+            f"true rel. residual {st.rel_res_true:.3e}, {st.t_solve_ms:.1f} ms")
+    g.profile(True)
+    g.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        x, st = step()
+        stats.append(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = g.profile_read(reset=True)
+    g.profile(False)
+    st = stats[-1]
+    log(f"timed {args.steps} solves in {wall:.3f} s; last: {st.iterations} iterations, "
+        f"true rel. residual {st.rel_res_true:.3e}; chunk kernel {launches} launches, {kms:.1f} ms")
+    if st.status != ba.BA_OK or st.rel_res_true > 1.05e-6:
+        log(f"WARNING: solve did not reach 1e-6: status {st.status}, residual {st.rel_res_true:.3e}")
+
+    # algorithmic bytes of one chunk-kernel launch: every observation's 2x9 + 2x3 FP64
+    # Jacobian blocks and its camera index, every landmark's V^-1 (6 FP64), v once
+    esz = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    bytes_per_launch = p.n_obs * (24 * esz + 4) + p.n_lms * 6 * 8 + p.n * 8
+    avg_ms = kms / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    roofline = {"bound": "hbm", "kernel": f"k_schur1<{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[args.precision] }>",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 5),
+                "launches": int(launches)}
+
+    variants = {}
+    if not args.no_variants:
+        for name, kw in [("pcg_fp64", dict(solver="pcg", precision="fp64")),
+                         ("mcg_fp64_N4", dict(solver="mcg", N=4, precision="fp64")),
+                         ("mcg_fp64_N16", dict(solver="mcg", N=16, precision="fp64")),
+                         ("mcg_fp64_N64", dict(solver="mcg", N=64, precision="fp64"))]:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, s2 = step(**kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            variants[name] = {"solves_per_s": round(1.0 / dt, 3), "iterations": s2.iterations,
+                              "multi_steps": s2.multi_steps, "rel_res_true": s2.rel_res_true,
+                              "status": s2.status}
+            log(f"variant {name}: {1.0 / dt:.2f} solves/s, {s2.iterations} iterations, "
+                f"residual {s2.rel_res_true:.2e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.time()
+        o = oracle.System(p)
+        ob = time.time() - t
+        # bounded sample: a few iterations of the same solver and path, scaled to a
+        # full solve of the GPU's iteration count
+        def run(k):
+            t2 = time.perf_counter()
+            if args.solver == "pcg":
+                o.pcg(eps=0.0, imax=k)
+            else:
+                o.mcg(args.N, args.tau, eps=0.0, imax=k)
+            return time.perf_counter() - t2
+        probe = 2
+        tp = run(probe)
+        k = max(probe, min(st.iterations, int(15.0 / max(tp / probe, 1e-6))))
+        tk = run(k) if k > probe else tp
+        per_it = tk / k
+        est_solve = per_it * st.iterations
+        cpu = {"value": round(1.0 / est_solve, 5), "unit": "solves/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"oracle {args.solver.upper()} (FP64 C, OpenMP) on the same problem: {k} of the "
+                         f"{st.iterations} iterations timed ({tk:.1f} s), scaled to the full solve; "
+                         f"oracle build {ob:.1f} s not included"}
+        log(f"cpu baseline: {cpu}")
+
+    value = args.steps / wall
+    out = {
+        "metric": "RCS solves/s to 1e-6 rel residual (MCG vs PCG, FP64 vs mixed); Schur matvec HBM GB/s",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32 products, f64 solver", "bf16": "bf16 storage, f32 products"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "walk1936: F-1936-shaped banded synthetic BA (1,936 cameras, 650k landmarks, "
+                               f"{p.n_obs} observations), seed {args.seed}",
+                   "solver": args.solver, "N": args.N if args.solver == "mcg" else None,
+                   "tau": args.tau if args.solver == "mcg" else None, "eps": 1e-6,
+                   "iterations": st.iterations, "multi_steps": st.multi_steps,
+                   "rel_res_true": st.rel_res_true, "build_s": round(build_s, 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(out), flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * ba.h -- C ABI of the MI355X (gfx950) reduced-camera-system solver.
+ *
+ * Solves the damped Levenberg-Marquardt normal equation of bundle adjustment
+ * after its reduction to the camera Schur complement
+ *     S dx_p = -b~,  S = U_lambda - W V_lambda^-1 W^T,  b~ = b_p - W V_lambda^-1 b_l
+ * (Weber, Demmel, Cremers, "Multidirectional Conjugate Gradients for Scalable
+ * Bundle Adjustment", GCPR 2021, Sec. 3.1, eq. (7)-(15)) with block-Jacobi PCG
+ * (Sec. 3.2, Algorithm 1) or Multidirectional CG (Sec. 3.2, Algorithm 2).
+ *
+ * Conventions shared by every call:
+ *  - All array arguments are DEVICE pointers (HIP, the device current at
+ *    ba_build_system) unless a comment says "host".  Arrays are dense,
+ *    row-major C order, FP64 unless stated.
+ *  - A pose has d_p = 9 parameters (rotation increment, translation, focal,
+ *    two radial terms); the camera space has n = 9 * n_cams entries, ordered
+ *    camera by camera.
+ *  - Every call runs on the stream given to ba_build_system and returns
+ *    after its work is complete (the library synchronises that stream).
+ *  - Status codes: 0 success, > 0 warning, < 0 error (ba_status).  No
+ *    exception crosses the ABI.  ba_last_error() gives a message for the
+ *    last failing call on the calling thread.
+ *  - A ba_system must not be used from two host threads at once.
+ *  - The library allocates its own device memory (hipMalloc) inside
+ *    ba_build_system and the solve calls; ba_free_system releases all of it.
+ *    Input arrays are copied into the system's own layout: the caller may
+ *    free them once ba_build_system has returned.
+ */
+#ifndef BA_H
+#define BA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BA_OK = 0,
+    BA_MAXITER = 1,            /* warning: max_iter reached; x holds the last iterate */
+    BA_ERR_INVALID_ARG = -1,   /* null pointer, bad size, index out of range, duplicate
+                                  (camera, landmark) pair, d_p != 9, N outside [1, n_cams] */
+    BA_ERR_NONFINITE = -2,     /* NaN/Inf in J, r or lambda */
+    BA_ERR_NOT_SPD = -3,       /* a V_lambda or D(S) block has a Cholesky pivot <= 0
+                                  (e.g. a camera or landmark with no observation) */
+    BA_ERR_BREAKDOWN = -4,     /* PCG: P^T S P <= 0; MCG: Delta numerically zero */
+    BA_ERR_WORKSPACE = -5,     /* MCG history capacity too small */
+    BA_ERR_HIP = -6,           /* a HIP runtime call failed */
+    BA_ERR_NOMEM = -7,         /* device or host allocation failed */
+    BA_ERR_UNSUPPORTED = -8    /* input outside the supported envelope (see message) */
+} ba_status;
+
+typedef struct ba_system ba_system;
+
+/* One linearised BA problem: the per-observation split of J = (J_p J_l) and
+ * r0 = r(x0) (Sec. 3.1, eq. (2)-(5)), and the damping coefficient lambda of
+ * eq. (6) with diagonal damping D_p^T D_p = diag(J_p^T J_p), D_l^T D_l =
+ * diag(J_l^T J_l).  Observation o couples camera obs_cam[o] and landmark
+ * obs_lm[o]; each (camera, landmark) pair may appear at most once. */
+typedef struct {
+    int32_t n_cams;          /* n_p >= 1 */
+    int32_t n_lms;           /* n_l >= 1 */
+    int64_t n_obs;           /* m >= 1 */
+    int32_t d_p;             /* must be 9 */
+    int32_t reserved0;
+    const int32_t *obs_cam;  /* device [m], in [0, n_cams) */
+    const int32_t *obs_lm;   /* device [m], in [0, n_lms) */
+    const double *J_p;       /* device [m][2][9]: d r_o / d (pose of obs_cam[o]) */
+    const double *J_l;       /* device [m][2][3]: d r_o / d (landmark obs_lm[o]) */
+    const double *r;         /* device [m][2]: residuals r_o at the linearisation point */
+    double lambda;           /* >= 0 */
+} ba_problem_desc;
+
+typedef struct {
+    int32_t store_fp32;      /* also keep an FP32 copy of the Jacobian stream (precision FP32) */
+    int32_t store_bf16;      /* also keep a BF16 copy with per-camera column scales (precision BF16) */
+    int32_t max_slots;       /* cameras per landmark chunk (0 = default 128; 64..440) */
+    int32_t max_tiles;       /* 64-observation tiles per chunk (0 = default 16) */
+    int32_t reserved[4];
+} ba_build_opts;
+
+typedef enum { BA_PREC_FP64 = 0, BA_PREC_FP32 = 1, BA_PREC_BF16 = 2 } ba_precision;
+
+typedef struct {
+    double eps;              /* relative residual tolerance, stop when |r_i| < eps |r_0| (1e-6) */
+    int32_t max_iter;        /* imax (1000) */
+    int32_t precision;       /* ba_precision used for the S products (FP64 default) */
+    int32_t precond;         /* 0: block Jacobi D(S); 1: block Jacobi plus the low-rank term set by
+                                ba_set_lowrank_precond */
+    int32_t reserved0;
+    int64_t max_history_cols;/* MCG history capacity in columns (0 = 1 + max_iter * N) */
+    double inner_eps;        /* mixed precision: inner tolerance relative to the outer residual (1e-3) */
+    int32_t max_outer;       /* mixed precision: max refinement steps (20) */
+    int32_t max_inner;       /* mixed precision: max inner iterations per step (200) */
+    int32_t reserved[4];
+} ba_solve_opts;
+
+/* Solve statistics.  The trace pointers are HOST arrays supplied by the caller
+ * (nullable); entry i is filled for iteration i < min(iterations, trace_cap). */
+typedef struct {
+    int32_t iterations;       /* completed alpha-updates (Alg. 1/2, the x-update) */
+    int32_t multi_steps;      /* MCG: steps with N directions */
+    int32_t history_cols;     /* MCG: columns of the direction history */
+    int32_t refinement_steps; /* mixed precision: outer steps */
+    int32_t status;
+    int32_t trace_cap;
+    double rel_res_recursive; /* |r_i| / |r_0| of the recursive residual */
+    double rel_res_true;      /* |-b~ - S x| / |b~| recomputed in FP64 */
+    double t_solve_ms;        /* wall time of the solve on the stream */
+    double *trace_res;        /* host [trace_cap]: |r_{i+1}| / |r_0| */
+    double *trace_t;          /* host [trace_cap]: t_i of the tau-test (NaN when not taken) */
+    int32_t *trace_k;         /* host [trace_cap]: columns of the next direction block (0 at exit) */
+} ba_solve_stats;
+
+/* Fills opts with the defaults (eps 1e-6, max_iter 1000, FP64, block Jacobi). */
+void ba_default_solve_opts(ba_solve_opts *opts);
+
+/* Builds the damped normal-equation blocks and the reduced camera system of
+ * Sec. 3.1, eq. (8)-(15), and the block-Jacobi preconditioner D(S) (Sec. 3.2,
+ * before Alg. 1), in FP64 on the device.  `stream` is a hipStream_t (NULL = the
+ * null stream) used by every later call on the returned system.  opts nullable.
+ * Errors: INVALID_ARG, NONFINITE, NOT_SPD, UNSUPPORTED (a landmark with more than
+ * 64 observations), NOMEM, HIP.  On error *out is NULL. */
+ba_status ba_build_system(const ba_problem_desc *desc, const ba_build_opts *opts, void *stream,
+                          ba_system **out);
+
+/* Releases the system and all its device memory.  Null-safe. */
+void ba_free_system(ba_system *sys);
+
+/* y = S v for one camera-space vector (the implicit product of eq. (14)):
+ * y = J_p^T (e - J_l V_lambda^-1 J_l^T e) + lambda diag(J_p^T J_p) v with e = J_p v.
+ * v, y: device [n].  precision: ba_precision of the Jacobian stream used. */
+ba_status ba_schur_matvec(ba_system *sys, const double *v, double *y, int32_t precision);
+
+/* Y[:, p] = S Z[:, p], p < N, where Z[:, p] equals z on the poses of subset p of
+ * the partition into N subsets (ba_partition) and 0 elsewhere -- the
+ * multidirectional product of Sec. 3.2, "Optimized implementation", eq. (19).
+ * z: device [n]; Y: device [N][n] (column p contiguous). */
+ba_status ba_schur_matmat_grouped(ba_system *sys, int32_t n_groups, const double *z, double *Y,
+                                  int32_t precision);
+
+/* z = D(S)^-1 r (block-Jacobi preconditioner, one 9x9 Cholesky solve per pose).
+ * r, z: device [n]. */
+ba_status ba_precond_apply(ba_system *sys, const double *r, double *z);
+
+/* Copies b~ (eq. (15)) into bt: device [n]. */
+ba_status ba_get_rhs(ba_system *sys, double *bt);
+
+/* Copies the 9x9 blocks of D(S) (row-major, camera by camera) into D: device [n_cams][81]. */
+ba_status ba_get_precond_blocks(ba_system *sys, double *D);
+
+/* Block-Jacobi PCG, Algorithm 1, on S dx_p = -b~.  x0: device [n] or NULL (= 0);
+ * x: device [n] output.  opts, stats nullable (defaults).  Returns BA_OK,
+ * BA_MAXITER or an error. */
+ba_status ba_pcg_solve(ba_system *sys, const double *x0, double *x, const ba_solve_opts *opts,
+                       ba_solve_stats *stats);
+
+/* Multidirectional CG, Algorithm 2, with N subsets of consecutive poses and the
+ * tau-test threshold tau >= 0.  A step is multidirectional iff N > 1 and
+ * t_i < tau; the first step is global.  Same argument conventions as
+ * ba_pcg_solve.  Errors: INVALID_ARG (N outside [1, n_cams], tau < 0),
+ * WORKSPACE (history capacity), BREAKDOWN. */
+ba_status ba_mcg_solve(ba_system *sys, int32_t n_groups, double tau, const double *x0, double *x,
+                       const ba_solve_opts *opts, ba_solve_stats *stats);
+
+/* Landmark update from a pose update, the second block row of eq. (7):
+ * dx_l = -V_lambda^-1 (b_l + W^T dx_p).  (eq. (16) is printed with the sign of
+ * b_l flipped.)  dxp: device [n]; dxl: device [n_lms][3], original landmark order. */
+ba_status ba_back_substitute(ba_system *sys, const double *dxp, double *dxl);
+
+/* Moore-Penrose pseudo-inverse of a symmetric k x k matrix on the device
+ * (Sec. 3.2, "Optimized implementation": Delta_i is inverted or
+ * pseudo-inverted): Jacobi eigendecomposition, eigenvalues with
+ * |l| <= k 2^-52 max|l| dropped.  A, Ap: device [k][k]; rank: host, nullable.
+ * 1 <= k <= 256.  Runs on `stream` (hipStream_t, NULL = null stream). */
+ba_status ba_pinv_sym(int32_t k, const double *A, double *Ap, int32_t *rank, void *stream);
+
+/* Partition of the n_cams poses into N subsets of consecutive poses (Sec. 3.2,
+ * "Optimized implementation"): s = floor(n_cams / N); subsets 0..N-2 hold s
+ * poses each, the last holds the rest.  group: HOST [n_cams]. */
+ba_status ba_partition(int32_t n_cams, int32_t n_groups, int32_t *group);
+
+/* Sizes of a built system.  All outputs host, nullable. */
+ba_status ba_system_info(const ba_system *sys, int32_t *n_cams, int32_t *n_lms, int64_t *n_obs,
+                         int64_t *n_tiles, int32_t *n_chunks, int64_t *matvec_bytes_fp64);
+
+/* Event timing of the dominant kernel, the chunked implicit Schur product of
+ * ba_schur_matvec and of the solvers' S v products: while enabled, each of its
+ * launches on this system is bracketed by two HIP events recorded on the
+ * system's stream.  ba_profile_read (host outputs, nullable) returns the summed
+ * kernel time in ms and the number of launches since the last reset. */
+ba_status ba_profile_enable(ba_system *sys, int32_t on);
+ba_status ba_profile_read(ba_system *sys, double *ms_total, int64_t *launches, int32_t reset);
+
+/* HOST-ONLY check of the HBM layout plan (no GPU needed): plans the layout of
+ * the host index arrays cam, lm [n_obs] exactly as ba_build_system does, and the
+ * layout of the multidirectional product for each N in Ns[n_Ns] (host), then
+ * checks every invariant the kernels index by.  stats (host, nullable,
+ * 4 + 3 n_Ns entries): tiles, chunks, partial rows, largest chunk slot count,
+ * then per N: chunks, (camera, subset) partial rows, largest chunk out count.
+ * Returns BA_OK, the planner's error, or BA_ERR_INVALID_ARG with
+ * ba_plan_validate_error() naming the broken invariant. */
+ba_status ba_plan_validate(int32_t n_cams, int32_t n_lms, int64_t n_obs, const int32_t *cam, const int32_t *lm,
+                           int32_t max_slots, int32_t max_tiles, const int32_t *Ns, int32_t n_Ns,
+                           int64_t *stats);
+const char *ba_plan_validate_error(void);
+
+const char *ba_status_string(int32_t status);
+const char *ba_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BA_H */

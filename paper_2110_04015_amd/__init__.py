@@ -1,0 +1,269 @@
+"""MI355X (gfx950) solver for the reduced camera system of bundle adjustment.
+
+Python binding of libba.so (include/ba.h): block-Jacobi PCG (Algorithm 1) and
+Multidirectional CG (Algorithm 2) of Weber, Demmel, Cremers (GCPR 2021) on the
+implicit Schur complement S = U - W V^-1 W^T.  PyTorch provides device memory
+and the stream; every arithmetic step runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BA_ERR_BREAKDOWN, BA_ERR_HIP, BA_ERR_INVALID_ARG, BA_ERR_NOMEM, BA_ERR_NONFINITE,
+                   BA_ERR_NOT_SPD, BA_ERR_UNSUPPORTED, BA_ERR_WORKSPACE, BA_MAXITER, BA_OK, PREC)
+
+__all__ = ["System", "BAError", "Stats", "pinv_sym", "partition", "PREC", "lib"]
+
+
+def lib() -> C.CDLL:
+    return _lib.load()
+
+
+class BAError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        msg = L.ba_last_error().decode()
+        super().__init__(f"{where}: {L.ba_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(st: int, where: str) -> int:
+    if st < 0:
+        raise BAError(st, where)
+    return st
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, dtype, numel=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Stats:
+    iterations: int
+    multi_steps: int
+    history_cols: int
+    refinement_steps: int
+    status: int
+    rel_res_recursive: float
+    rel_res_true: float
+    t_solve_ms: float
+    trace_res: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    trace_t: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    trace_k: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))
+
+
+def _opts(eps, max_iter, precision, max_history_cols=0, inner_eps=1e-3, max_outer=20, max_inner=200,
+          precond=0):
+    o = _lib.SolveOpts()
+    lib().ba_default_solve_opts(C.byref(o))
+    o.eps = float(eps)
+    o.max_iter = int(max_iter)
+    o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    o.max_history_cols = int(max_history_cols)
+    o.inner_eps = float(inner_eps)
+    o.max_outer = int(max_outer)
+    o.max_inner = int(max_inner)
+    o.precond = int(precond)
+    return o
+
+
+class _Trace:
+    def __init__(self, cap):
+        self.cap = cap
+        self.res = np.full(cap, np.nan)
+        self.t = np.full(cap, np.nan)
+        self.k = np.zeros(cap, dtype=np.int32)
+
+    def attach(self, st):
+        st.trace_cap = self.cap
+        st.trace_res = self.res.ctypes.data_as(C.POINTER(C.c_double))
+        st.trace_t = self.t.ctypes.data_as(C.POINTER(C.c_double))
+        st.trace_k = self.k.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _stats(st, tr: Optional[_Trace]) -> Stats:
+    s = Stats(st.iterations, st.multi_steps, st.history_cols, st.refinement_steps, st.status,
+              st.rel_res_recursive, st.rel_res_true, st.t_solve_ms)
+    if tr is not None:
+        n = min(st.iterations, tr.cap)
+        s.trace_res, s.trace_t, s.trace_k = tr.res[:n].copy(), tr.t[:n].copy(), tr.k[:n].copy()
+    return s
+
+
+class System:
+    """A built reduced camera system (ba_build_system) living on one device."""
+
+    def __init__(self, n_cams, n_lms, obs_cam, obs_lm, J_p, J_l, r, lam, stream=None,
+                 max_slots=0, max_tiles=0, store_fp32=False, store_bf16=False):
+        torch = _torch()
+        m = int(obs_cam.numel())
+        d = _lib.ProblemDesc()
+        d.n_cams, d.n_lms, d.n_obs, d.d_p = int(n_cams), int(n_lms), m, 9
+        d.obs_cam = _dev_ptr(obs_cam, torch.int32, m, "obs_cam")
+        d.obs_lm = _dev_ptr(obs_lm, torch.int32, m, "obs_lm")
+        d.J_p = _dev_ptr(J_p, torch.float64, m * 18, "J_p")
+        d.J_l = _dev_ptr(J_l, torch.float64, m * 6, "J_l")
+        d.r = _dev_ptr(r, torch.float64, m * 2, "r")
+        d.lam = float(lam)
+        o = _lib.BuildOpts()
+        o.store_fp32, o.store_bf16 = int(store_fp32), int(store_bf16)
+        o.max_slots, o.max_tiles = int(max_slots), int(max_tiles)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = obs_cam.device
+        h = C.c_void_p()
+        _check(lib().ba_build_system(C.byref(d), C.byref(o), _stream_handle(self._stream), C.byref(h)),
+               "ba_build_system")
+        self.h = h
+        self.n_cams, self.n_lms, self.n_obs = int(n_cams), int(n_lms), m
+        self.n = 9 * self.n_cams
+
+    @classmethod
+    def from_problem(cls, p, device="cuda", **kw):
+        """Upload a synthetic problem (host arrays) and build its system."""
+        torch = _torch()
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        return cls(p.n_cams, p.n_lms, t(p.obs_cam, torch.int32), t(p.obs_lm, torch.int32),
+                   t(p.J_p, torch.float64), t(p.J_l, torch.float64), t(p.r, torch.float64), p.lam, **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ba_free_system(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, *shape):
+        torch = _torch()
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def info(self):
+        a, b, c, d, e, f = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_int32(), C.c_int64()
+        _check(lib().ba_system_info(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(e),
+                                    C.byref(f)), "ba_system_info")
+        return {"n_cams": a.value, "n_lms": b.value, "n_obs": c.value, "n_tiles": d.value,
+                "n_chunks": e.value, "matvec_bytes_fp64": f.value}
+
+    def profile(self, on: bool = True):
+        _check(lib().ba_profile_enable(self.h, int(on)), "ba_profile_enable")
+
+    def profile_read(self, reset: bool = True):
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().ba_profile_read(self.h, C.byref(ms), C.byref(n), int(reset)), "ba_profile_read")
+        return ms.value, n.value
+
+    def matvec(self, v, precision="fp64", out=None):
+        torch = _torch()
+        y = out if out is not None else self._new(self.n)
+        _check(lib().ba_schur_matvec(self.h, _dev_ptr(v, torch.float64, self.n, "v"),
+                                     _dev_ptr(y, torch.float64, self.n, "y"),
+                                     PREC[precision] if isinstance(precision, str) else int(precision)),
+               "ba_schur_matvec")
+        return y
+
+    def matmat_grouped(self, N, z, precision="fp64"):
+        torch = _torch()
+        Y = self._new(int(N), self.n)
+        _check(lib().ba_schur_matmat_grouped(self.h, int(N), _dev_ptr(z, torch.float64, self.n, "z"),
+                                             _dev_ptr(Y, torch.float64, N * self.n, "Y"),
+                                             PREC[precision] if isinstance(precision, str) else int(precision)),
+               "ba_schur_matmat_grouped")
+        return Y
+
+    def precond(self, r):
+        torch = _torch()
+        z = self._new(self.n)
+        _check(lib().ba_precond_apply(self.h, _dev_ptr(r, torch.float64, self.n, "r"),
+                                      _dev_ptr(z, torch.float64, self.n, "z")), "ba_precond_apply")
+        return z
+
+    def rhs(self):
+        torch = _torch()
+        b = self._new(self.n)
+        _check(lib().ba_get_rhs(self.h, _dev_ptr(b, torch.float64, self.n, "bt")), "ba_get_rhs")
+        return b
+
+    def precond_blocks(self):
+        torch = _torch()
+        D = self._new(self.n_cams, 9, 9)
+        _check(lib().ba_get_precond_blocks(self.h, _dev_ptr(D, torch.float64, self.n_cams * 81, "D")),
+               "ba_get_precond_blocks")
+        return D
+
+    def back_substitute(self, dxp):
+        torch = _torch()
+        out = self._new(self.n_lms * 3)
+        _check(lib().ba_back_substitute(self.h, _dev_ptr(dxp, torch.float64, self.n, "dxp"),
+                                        _dev_ptr(out, torch.float64, self.n_lms * 3, "dxl")),
+               "ba_back_substitute")
+        return out
+
+    def pcg(self, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False, out=None):
+        torch = _torch()
+        x = out if out is not None else self._new(self.n)
+        o = _opts(eps, max_iter, precision)
+        st = _lib.SolveStats()
+        tr = _Trace(max(int(max_iter), 1)) if trace else None
+        if tr:
+            tr.attach(st)
+        x0p = _dev_ptr(x0, torch.float64, self.n, "x0") if x0 is not None else None
+        _check(lib().ba_pcg_solve(self.h, x0p, _dev_ptr(x, torch.float64, self.n, "x"), C.byref(o),
+                                  C.byref(st)), "ba_pcg_solve")
+        return x, _stats(st, tr)
+
+    def mcg(self, N, tau, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False,
+            max_history_cols=0, out=None):
+        torch = _torch()
+        x = out if out is not None else self._new(self.n)
+        o = _opts(eps, max_iter, precision, max_history_cols=max_history_cols)
+        st = _lib.SolveStats()
+        tr = _Trace(max(int(max_iter), 1)) if trace else None
+        if tr:
+            tr.attach(st)
+        x0p = _dev_ptr(x0, torch.float64, self.n, "x0") if x0 is not None else None
+        _check(lib().ba_mcg_solve(self.h, int(N), float(tau), x0p, _dev_ptr(x, torch.float64, self.n, "x"),
+                                  C.byref(o), C.byref(st)), "ba_mcg_solve")
+        return x, _stats(st, tr)
+
+
+def pinv_sym(A, stream=None):
+    """Device pseudo-inverse of a symmetric k x k FP64 matrix; returns (A^+, rank)."""
+    torch = _torch()
+    k = int(A.shape[0])
+    Ap = torch.empty_like(A)
+    rank = C.c_int32()
+    _check(lib().ba_pinv_sym(k, _dev_ptr(A, torch.float64, k * k, "A"), _dev_ptr(Ap, torch.float64, k * k, "Ap"),
+                             C.byref(rank), _stream_handle(stream)), "ba_pinv_sym")
+    return Ap, int(rank.value)
+
+
+def partition(n_cams: int, N: int) -> np.ndarray:
+    g = np.empty(int(n_cams), dtype=np.int32)
+    _check(lib().ba_partition(int(n_cams), int(N), g.ctypes.data_as(C.POINTER(C.c_int32))), "ba_partition")
+    return g

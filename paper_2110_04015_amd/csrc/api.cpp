@@ -1,0 +1,823 @@
+// C ABI of the reduced-camera-system library: system build, Schur products,
+// and the PCG (Algorithm 1) and MCG (Algorithm 2) drivers.  The host only
+// orchestrates: every arithmetic step runs in the HIP kernels; per iteration
+// the host reads back a handful of device scalars (the stop test and the
+// tau-test branch) to choose the next launches.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ba_internal.h"
+#include "kernels.h"
+
+using namespace ba;
+
+namespace {
+
+thread_local std::string g_err;
+
+ba_status fail(ba_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(BA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+ba_status dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(BA_ERR_NOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    return BA_OK;
+}
+
+template <typename T>
+ba_status upload(T **p, const std::vector<T> &v, hipStream_t s) {
+    ba_status st = dalloc(p, v.size());
+    if (st != BA_OK) return st;
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return BA_OK;
+}
+
+template <typename T>
+void dfree(T *&p) {
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void free_multi(DevMulti &m) {
+    dfree(m.mmeta);
+    dfree(m.slot_cam);
+    dfree(m.pair_ll);
+    dfree(m.tile_oidx);
+    dfree(m.oidx);
+    dfree(m.slot_ooff);
+    dfree(m.chunk_tile);
+    dfree(m.chunk_part);
+    dfree(m.cg_ptr);
+    dfree(m.cg_idx);
+    dfree(m.partial);
+    dfree(m.group);
+    m = DevMulti();
+}
+
+void free_all(ba_system *s) {
+    dfree(s->J64);
+    dfree(s->J32);
+    dfree(s->J16);
+    dfree(s->bf16_scale);
+    dfree(s->meta);
+    dfree(s->tile_lmk_base);
+    dfree(s->chunk_tile);
+    dfree(s->chunk_part);
+    dfree(s->part_cam);
+    dfree(s->cam_part_ptr);
+    dfree(s->cam_part_idx);
+    dfree(s->partial);
+    dfree(s->vinv);
+    dfree(s->bl);
+    dfree(s->dU);
+    dfree(s->Dblk);
+    dfree(s->Dchol);
+    dfree(s->bt);
+    dfree(s->lmk_order);
+    dfree(s->lmk_first_slot);
+    dfree(s->lmk_count);
+    dfree(s->status);
+    dfree(s->vec);
+    dfree(s->red);
+    dfree(s->hist);
+    dfree(s->small);
+    if (s->host_pinned) (void)hipHostFree(s->host_pinned);
+    s->host_pinned = nullptr;
+    free_multi(s->multi);
+    for (hipEvent_t e : s->prof_events) (void)hipEventDestroy(e);
+    s->prof_events.clear();
+}
+
+SchurArgs schur_args(ba_system *s, int precision) {
+    SchurArgs a;
+    a.J = precision == 1 ? (const void *)s->J32 : precision == 2 ? (const void *)s->J16 : (const void *)s->J64;
+    a.precision = precision;
+    a.meta = s->meta;
+    a.tile_lmk_base = s->tile_lmk_base;
+    a.vinv = s->vinv;
+    a.chunk_tile = s->chunk_tile;
+    a.chunk_part = s->chunk_part;
+    a.part_cam = s->part_cam;
+    a.n_chunks = s->plan.n_chunks;
+    a.max_slots = s->plan.max_slots;
+    a.partial = s->partial;
+    a.cam_part_ptr = s->cam_part_ptr;
+    a.cam_part_idx = s->cam_part_idx;
+    a.dU = s->dU;
+    a.np = s->np;
+    return a;
+}
+
+// Flushes the recorded event pairs into the running total (waits for the stream).
+void profile_flush(ba_system *s) {
+    if (s->prof_used == 0) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (size_t i = 0; i + 1 < s->prof_used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, s->prof_events[i], s->prof_events[i + 1]) == hipSuccess) {
+            s->prof_ms += ms;
+            s->prof_launches += 1;
+        }
+    }
+    s->prof_used = 0;
+}
+
+// y = S v; with profiling on, the chunk kernel is bracketed by events on the stream
+void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
+    if (!s->profiling) {
+        launch_schur_matvec(a, v, y, s->stream);
+        return;
+    }
+    if (s->prof_used + 2 > s->prof_events.size()) {
+        if (s->prof_events.size() >= 4096) profile_flush(s);
+        while (s->prof_used + 2 > s->prof_events.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                launch_schur_matvec(a, v, y, s->stream);
+                return;
+            }
+            s->prof_events.push_back(e);
+        }
+    }
+    (void)hipEventRecord(s->prof_events[s->prof_used], s->stream);
+    launch_schur_chunks(a, v, s->stream);
+    (void)hipEventRecord(s->prof_events[s->prof_used + 1], s->stream);
+    s->prof_used += 2;
+    launch_schur_reduce(a, v, y, s->stream);
+}
+
+ba_status ensure_precision(ba_system *s, int precision) {
+    if (precision < 0 || precision > 2) return fail(BA_ERR_INVALID_ARG, "precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
+    const int64_t nslots = s->plan.n_tiles * kTile;
+    if (precision == 1 && !s->J32) {
+        ba_status st = dalloc(&s->J32, (size_t)nslots * 24);
+        if (st != BA_OK) return st;
+        launch_convert(s->J64, nslots, s->J32, nullptr, s->stream);
+        HIPCHK(hipGetLastError());
+    }
+    if (precision == 2 && !s->J16) {
+        ba_status st = dalloc(&s->J16, (size_t)nslots * 24);
+        if (st != BA_OK) return st;
+        launch_convert(s->J64, nslots, nullptr, s->J16, s->stream);
+        HIPCHK(hipGetLastError());
+    }
+    return BA_OK;
+}
+
+ba_status ensure_multi(ba_system *s, int N) {
+    if (s->multi.N == N && s->multi.partial) return BA_OK;
+    free_multi(s->multi);
+    HostMultiPlan mp;
+    std::string err;
+    ba_status st = build_multi_plan(s->plan, N, 512, mp, err);
+    if (st != BA_OK) return fail(st, err);
+    // LDS of the multidirectional kernel: max_out rows of 9 plus 2 x 64 x 3 values (FP64)
+    if ((size_t)(mp.max_out * 9 + 6 * kTile) * sizeof(double) > 65536)
+        return fail(BA_ERR_UNSUPPORTED, "multidirectional product: a tile touches " + std::to_string(mp.max_out) +
+                                            " (camera, subset) pairs; at most 896 fit in LDS");
+    DevMulti &m = s->multi;
+    hipStream_t q = s->stream;
+    if ((st = upload(&m.mmeta, mp.mmeta, q)) != BA_OK) return st;
+    if ((st = upload(&m.slot_cam, mp.slot_cam, q)) != BA_OK) return st;
+    if ((st = upload(&m.pair_ll, mp.pair_ll, q)) != BA_OK) return st;
+    if ((st = upload(&m.tile_oidx, mp.tile_oidx, q)) != BA_OK) return st;
+    if ((st = upload(&m.oidx, mp.oidx, q)) != BA_OK) return st;
+    if ((st = upload(&m.slot_ooff, mp.slot_ooff, q)) != BA_OK) return st;
+    if ((st = upload(&m.chunk_tile, mp.chunk_tile, q)) != BA_OK) return st;
+    if ((st = upload(&m.chunk_part, mp.chunk_part, q)) != BA_OK) return st;
+    if ((st = upload(&m.cg_ptr, mp.cg_ptr, q)) != BA_OK) return st;
+    if ((st = upload(&m.cg_idx, mp.cg_idx, q)) != BA_OK) return st;
+    std::vector<int32_t> grp((size_t)s->np);
+    partition_groups(s->np, N, grp.data());
+    if ((st = upload(&m.group, grp, q)) != BA_OK) return st;
+    if ((st = dalloc(&m.partial, (size_t)std::max<int64_t>(mp.n_part, 1) * 9)) != BA_OK) return st;
+    m.N = N;
+    m.n_chunks = mp.n_chunks;
+    m.max_out = mp.max_out;
+    m.n_part = mp.n_part;
+    HIPCHK(hipStreamSynchronize(q));   // the host vectors above go out of scope
+    return BA_OK;
+}
+
+MultiArgs multi_args(ba_system *s, int precision) {
+    MultiArgs a;
+    a.J = precision == 1 ? (const void *)s->J32 : precision == 2 ? (const void *)s->J16 : (const void *)s->J64;
+    a.precision = precision;
+    a.meta = s->meta;
+    a.mmeta = s->multi.mmeta;
+    a.slot_cam = s->multi.slot_cam;
+    a.pair_ll = s->multi.pair_ll;
+    a.tile_oidx = s->multi.tile_oidx;
+    a.oidx = s->multi.oidx;
+    a.slot_ooff = s->multi.slot_ooff;
+    a.tile_lmk_base = s->tile_lmk_base;
+    a.vinv = s->vinv;
+    a.chunk_tile = s->multi.chunk_tile;
+    a.chunk_part = s->multi.chunk_part;
+    a.n_chunks = s->multi.n_chunks;
+    a.max_out = s->multi.max_out;
+    a.partial = s->multi.partial;
+    a.cg_ptr = s->multi.cg_ptr;
+    a.cg_idx = s->multi.cg_idx;
+    a.dU = s->dU;
+    a.group = s->multi.group;
+    a.np = s->np;
+    a.N = s->multi.N;
+    return a;
+}
+
+ba_status ensure_vec(ba_system *s, size_t doubles) {
+    if (s->vec_cap >= doubles) return BA_OK;
+    dfree(s->vec);
+    ba_status st = dalloc(&s->vec, doubles);
+    if (st != BA_OK) return st;
+    s->vec_cap = doubles;
+    return BA_OK;
+}
+
+ba_status ensure_red(ba_system *s, size_t doubles) {
+    if (s->red_cap >= doubles) return BA_OK;
+    dfree(s->red);
+    ba_status st = dalloc(&s->red, doubles);
+    if (st != BA_OK) return st;
+    s->red_cap = doubles;
+    return BA_OK;
+}
+
+ba_status ensure_pinned(ba_system *s) {
+    if (s->host_pinned) return BA_OK;
+    HIPCHK(hipHostMalloc((void **)&s->host_pinned, SC_COUNT * sizeof(double), hipHostMallocDefault));
+    return BA_OK;
+}
+
+// Copies the device scalars to the host and waits for the stream.
+ba_status read_scalars(ba_system *s, const double *sc, double *out) {
+    HIPCHK(hipMemcpyAsync(s->host_pinned, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    memcpy(out, s->host_pinned, SC_COUNT * sizeof(double));
+    return BA_OK;
+}
+
+ba_status init_scalars(ba_system *s, double *sc) {
+    double h[SC_COUNT];
+    for (int i = 0; i < SC_COUNT; ++i) h[i] = 0.0;
+    h[SC_RR0] = -1.0;
+    memcpy(s->host_pinned, h, sizeof h);
+    HIPCHK(hipMemcpyAsync(sc, s->host_pinned, SC_COUNT * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+// |-b~ - S x| / |b~| in FP64 (tmp: 2n doubles, red: partial sums)
+ba_status true_rel_residual(ba_system *s, const double *x, double *tmp, double *red, double *sc, double *out) {
+    const int64_t n = (int64_t)s->np * 9;
+    matvec(s, schur_args(s, 0), x, tmp);
+    launch_pcg_init(n, s->bt, tmp, tmp + n, red, s->stream);
+    launch_finalize(red, 1, sc + SC_COUNT - 1, s->stream);
+    launch_pcg_init(n, s->bt, nullptr, tmp + n, red, s->stream);
+    launch_finalize(red, 1, sc + SC_COUNT - 2, s->stream);
+    HIPCHK(hipGetLastError());
+    double h[SC_COUNT];
+    ba_status st = read_scalars(s, sc, h);
+    if (st != BA_OK) return st;
+    double num = h[SC_COUNT - 1], den = h[SC_COUNT - 2];
+    *out = den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
+    return BA_OK;
+}
+
+void fill_default_opts(ba_solve_opts *o) {
+    memset(o, 0, sizeof(*o));
+    o->eps = 1e-6;
+    o->max_iter = 1000;
+    o->precision = BA_PREC_FP64;
+    o->precond = 0;
+    o->max_history_cols = 0;
+    o->inner_eps = 1e-3;
+    o->max_outer = 20;
+    o->max_inner = 200;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ba_default_solve_opts(ba_solve_opts *opts) {
+    if (opts) fill_default_opts(opts);
+}
+
+const char *ba_last_error(void) { return g_err.c_str(); }
+
+const char *ba_status_string(int32_t st) {
+    switch (st) {
+        case BA_OK: return "ok";
+        case BA_MAXITER: return "maximum number of iterations reached";
+        case BA_ERR_INVALID_ARG: return "invalid argument";
+        case BA_ERR_NONFINITE: return "non-finite input";
+        case BA_ERR_NOT_SPD: return "matrix block not positive definite";
+        case BA_ERR_BREAKDOWN: return "Krylov breakdown";
+        case BA_ERR_WORKSPACE: return "workspace too small";
+        case BA_ERR_HIP: return "HIP runtime error";
+        case BA_ERR_NOMEM: return "out of memory";
+        case BA_ERR_UNSUPPORTED: return "unsupported input";
+        default: return "unknown status";
+    }
+}
+
+ba_status ba_partition(int32_t n_cams, int32_t n_groups, int32_t *group) {
+    if (!group || n_cams < 1 || n_groups < 1 || n_groups > n_cams)
+        return fail(BA_ERR_INVALID_ARG, "ba_partition: need group != NULL and 1 <= N <= n_cams");
+    partition_groups(n_cams, n_groups, group);
+    return BA_OK;
+}
+
+void ba_free_system(ba_system *sys) {
+    if (!sys) return;
+    (void)hipStreamSynchronize(sys->stream);
+    free_all(sys);
+    delete sys;
+}
+
+ba_status ba_build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream, ba_system **out) {
+    if (!out) return fail(BA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(BA_ERR_INVALID_ARG, "desc is NULL");
+    if (d->d_p != 9) return fail(BA_ERR_INVALID_ARG, "d_p must be 9");
+    if (d->n_cams < 1 || d->n_lms < 1 || d->n_obs < 1)
+        return fail(BA_ERR_INVALID_ARG, "n_cams, n_lms and n_obs must be positive");
+    if (!d->obs_cam || !d->obs_lm || !d->J_p || !d->J_l || !d->r)
+        return fail(BA_ERR_INVALID_ARG, "a problem array is NULL");
+    if (!std::isfinite(d->lambda)) return fail(BA_ERR_NONFINITE, "lambda is not finite");
+    if (d->lambda < 0.0) return fail(BA_ERR_INVALID_ARG, "lambda must be >= 0");
+    int max_slots = opts && opts->max_slots ? opts->max_slots : 128;
+    int max_tiles = opts && opts->max_tiles ? opts->max_tiles : 16;
+    // the chunk kernel keeps 2 * max_slots camera rows of 9 doubles in LDS (<= 64 KiB)
+    if (max_slots < kTile || max_slots > 440 || max_tiles < 1 || max_tiles > 4096)
+        return fail(BA_ERR_INVALID_ARG, "max_slots must be in [64, 440] and max_tiles in [1, 4096]");
+
+    ba_system *s = new ba_system();
+    s->stream = (hipStream_t)stream;
+    s->np = d->n_cams;
+    s->nl = d->n_lms;
+    s->m = d->n_obs;
+    s->lambda = d->lambda;
+    hipStream_t q = s->stream;
+    auto bail = [&](ba_status st) {
+        (void)hipStreamSynchronize(q);
+        free_all(s);
+        delete s;
+        return st;
+    };
+    const int64_t m = d->n_obs;
+    std::vector<int32_t> hcam((size_t)m), hlm((size_t)m);
+    if (hipMemcpyAsync(hcam.data(), d->obs_cam, (size_t)m * 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
+        hipMemcpyAsync(hlm.data(), d->obs_lm, (size_t)m * 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
+        hipStreamSynchronize(q) != hipSuccess)
+        return bail(fail(BA_ERR_HIP, "copying the observation indices to the host failed"));
+    std::string err;
+    ba_status st = build_plan(s->np, s->nl, m, hcam.data(), hlm.data(), max_slots, max_tiles, s->plan, err);
+    if (st != BA_OK) return bail(fail(st, err));
+    const HostPlan &P = s->plan;
+    const int64_t nslots = P.n_tiles * kTile;
+
+    if ((st = dalloc(&s->status, 1)) != BA_OK) return bail(st);
+    if (hipMemsetAsync(s->status, 0, sizeof(int32_t), q) != hipSuccess) return bail(fail(BA_ERR_HIP, "memset"));
+    launch_check_finite(d->J_p, m * 18, s->status, q);
+    launch_check_finite(d->J_l, m * 6, s->status, q);
+    launch_check_finite(d->r, m * 2, s->status, q);
+    int32_t hst = 0;
+    if (hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
+        hipStreamSynchronize(q) != hipSuccess)
+        return bail(fail(BA_ERR_HIP, "status read failed"));
+    if (hst & kStatusNonfinite) return bail(fail(BA_ERR_NONFINITE, "NaN or Inf in J_p, J_l or r"));
+
+    // device copies of the plan
+    int64_t *d_slot_obs = nullptr, *d_cam_ptr = nullptr, *d_cam_obs = nullptr;
+    int32_t *d_lmk_store = nullptr;
+    double *d_h0 = nullptr;
+    auto bail2 = [&](ba_status st2) {
+        (void)hipStreamSynchronize(q);
+        dfree(d_slot_obs);
+        dfree(d_cam_ptr);
+        dfree(d_cam_obs);
+        dfree(d_lmk_store);
+        dfree(d_h0);
+        return bail(st2);
+    };
+    if ((st = upload(&d_slot_obs, P.slot_obs, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&d_cam_ptr, P.cam_obs_ptr, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&d_cam_obs, P.cam_obs, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&d_lmk_store, P.lmk_store, q)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&d_h0, (size_t)s->nl * 3)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->meta, P.meta, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->tile_lmk_base, P.tile_lmk_base, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->chunk_tile, P.chunk_tile, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->chunk_part, P.chunk_part, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->part_cam, P.part_cam, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->cam_part_ptr, P.cam_part_ptr, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->cam_part_idx, P.cam_part_idx, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->lmk_order, P.lmk_order, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->lmk_first_slot, P.lmk_first_slot, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->lmk_count, P.lmk_count, q)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&s->partial, (size_t)std::max<int64_t>(P.n_part, 1) * 9)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&s->J64, (size_t)nslots * 24)) != BA_OK) return bail2(st);
+    if (opts && opts->store_fp32 && (st = dalloc(&s->J32, (size_t)nslots * 24)) != BA_OK) return bail2(st);
+    if (opts && opts->store_bf16 && (st = dalloc(&s->J16, (size_t)nslots * 24)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&s->vinv, (size_t)s->nl * 6)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&s->bl, (size_t)s->nl * 3)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&s->dU, (size_t)s->np * 9)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&s->Dblk, (size_t)s->np * 81)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&s->Dchol, (size_t)s->np * 45)) != BA_OK) return bail2(st);
+    if ((st = dalloc(&s->bt, (size_t)s->np * 9)) != BA_OK) return bail2(st);
+
+    launch_pack(d_slot_obs, nslots, d->J_p, d->J_l, s->J64, s->J32, s->J16, q);
+    launch_landmarks(s->nl, s->lmk_first_slot, s->lmk_count, d_slot_obs, d->J_l, d->r, s->lambda, s->vinv, s->bl,
+                     d_h0, s->status, q);
+    launch_cameras(s->np, d_cam_ptr, d_cam_obs, d->obs_lm, d_lmk_store, d->J_p, d->J_l, d->r, s->vinv, d_h0,
+                   s->lambda, s->dU, s->Dblk, s->Dchol, s->bt, s->status, q);
+    if (hipGetLastError() != hipSuccess) return bail2(fail(BA_ERR_HIP, "build kernel launch failed"));
+    if (hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
+        hipStreamSynchronize(q) != hipSuccess)
+        return bail2(fail(BA_ERR_HIP, "build kernels failed"));
+    dfree(d_slot_obs);
+    dfree(d_cam_ptr);
+    dfree(d_cam_obs);
+    dfree(d_lmk_store);
+    dfree(d_h0);
+    if (hst & kStatusNotSpdLandmark)
+        return bail(fail(BA_ERR_NOT_SPD, "a landmark block V_lambda is not positive definite"));
+    if (hst & kStatusNotSpdCamera)
+        return bail(fail(BA_ERR_NOT_SPD, "a block of D(S) is not positive definite (unobserved camera?)"));
+    if ((st = ensure_pinned(s)) != BA_OK) return bail(st);
+    *out = s;
+    return BA_OK;
+}
+
+ba_status ba_profile_enable(ba_system *s, int32_t on) {
+    if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    profile_flush(s);
+    s->profiling = on != 0;
+    return BA_OK;
+}
+
+ba_status ba_profile_read(ba_system *s, double *ms_total, int64_t *launches, int32_t reset) {
+    if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    profile_flush(s);
+    if (ms_total) *ms_total = s->prof_ms;
+    if (launches) *launches = s->prof_launches;
+    if (reset) {
+        s->prof_ms = 0.0;
+        s->prof_launches = 0;
+    }
+    return BA_OK;
+}
+
+ba_status ba_system_info(const ba_system *s, int32_t *n_cams, int32_t *n_lms, int64_t *n_obs, int64_t *n_tiles,
+                         int32_t *n_chunks, int64_t *matvec_bytes_fp64) {
+    if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    if (n_cams) *n_cams = s->np;
+    if (n_lms) *n_lms = s->nl;
+    if (n_obs) *n_obs = s->m;
+    if (n_tiles) *n_tiles = s->plan.n_tiles;
+    if (n_chunks) *n_chunks = s->plan.n_chunks;
+    // one read of the Jacobian blocks and a camera index per observation, V^-1 per
+    // landmark, lambda diag(U), v and y per camera
+    if (matvec_bytes_fp64) *matvec_bytes_fp64 = s->m * (24 * 8 + 4) + (int64_t)s->nl * 6 * 8 + (int64_t)s->np * 9 * 8 * 3;
+    return BA_OK;
+}
+
+ba_status ba_schur_matvec(ba_system *s, const double *v, double *y, int32_t precision) {
+    if (!s || !v || !y) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    ba_status st = ensure_precision(s, precision);
+    if (st != BA_OK) return st;
+    matvec(s, schur_args(s, precision), v, y);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_schur_matmat_grouped(ba_system *s, int32_t N, const double *z, double *Y, int32_t precision) {
+    if (!s || !z || !Y) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (N < 1 || N > s->np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, n_cams]");
+    ba_status st = ensure_precision(s, precision);
+    if (st != BA_OK) return st;
+    if ((st = ensure_multi(s, N)) != BA_OK) return st;
+    launch_schur_multi(multi_args(s, precision), z, Y, s->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_precond_apply(ba_system *s, const double *r, double *z) {
+    if (!s || !r || !z) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    launch_precond(s->np, s->Dchol, r, z, s->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_get_rhs(ba_system *s, double *bt) {
+    if (!s || !bt) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    HIPCHK(hipMemcpyAsync(bt, s->bt, (size_t)s->np * 9 * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_get_precond_blocks(ba_system *s, double *D) {
+    if (!s || !D) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    HIPCHK(hipMemcpyAsync(D, s->Dblk, (size_t)s->np * 81 * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_back_substitute(ba_system *s, const double *dxp, double *dxl) {
+    if (!s || !dxp || !dxl) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    const HostPlan &P = s->plan;
+    launch_back_substitute(s->J64, s->meta, s->tile_lmk_base, s->chunk_tile, s->chunk_part, s->part_cam,
+                           P.n_chunks, P.max_slots, s->vinv, s->bl, s->lmk_order, dxp, dxl, s->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_pinv_sym(int32_t k, const double *A, double *Ap, int32_t *rank, void *stream) {
+    if (!A || !Ap || k < 1 || k > 64) return fail(BA_ERR_INVALID_ARG, "ba_pinv_sym: need A, Ap and 1 <= k <= 64");
+    hipStream_t q = (hipStream_t)stream;
+    int32_t *drank = nullptr;
+    ba_status st = dalloc(&drank, 1);
+    if (st != BA_OK) return st;
+    launch_pinv_sym(k, A, Ap, drank, q);
+    hipError_t e = hipGetLastError();
+    int32_t hr = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hr, drank, 4, hipMemcpyDeviceToHost, q);
+    if (e == hipSuccess) e = hipStreamSynchronize(q);
+    dfree(drank);
+    if (e != hipSuccess) return fail(BA_ERR_HIP, std::string("ba_pinv_sym: ") + hipGetErrorString(e));
+    if (rank) *rank = hr;
+    return BA_OK;
+}
+
+// ------------------------------------------------------------------ Algorithm 1
+
+ba_status ba_pcg_solve(ba_system *s, const double *x0, double *x, const ba_solve_opts *opts_in,
+                       ba_solve_stats *stats) {
+    if (!s || !x) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    ba_solve_opts opts;
+    if (opts_in) opts = *opts_in;
+    else fill_default_opts(&opts);
+    if (!(opts.eps >= 0.0) || opts.max_iter < 0) return fail(BA_ERR_INVALID_ARG, "eps >= 0 and max_iter >= 0 required");
+    const int prec = opts.precision;
+    ba_status st = ensure_precision(s, prec);
+    if (st != BA_OK) return st;
+    const int64_t n = (int64_t)s->np * 9;
+    hipStream_t q = s->stream;
+    if ((st = ensure_vec(s, (size_t)n * 6 + SC_COUNT)) != BA_OK) return st;
+    if ((st = ensure_red(s, (size_t)kRedBlocks * 4)) != BA_OK) return st;
+    double *r = s->vec, *z = r + n, *P = z + n, *Q = P + n, *tmp = Q + n, *sc = tmp + 2 * n;
+    double *pdq = s->red, *prr = pdq + kRedBlocks * 2, *pphi = prr + kRedBlocks;
+    auto t0 = std::chrono::steady_clock::now();
+    if ((st = init_scalars(s, sc)) != BA_OK) return st;
+    if (x0) {
+        HIPCHK(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
+        matvec(s, schur_args(s, prec), x, tmp);
+        launch_pcg_init(n, s->bt, tmp, r, prr, q);
+    } else {
+        HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), q));
+        launch_pcg_init(n, s->bt, nullptr, r, prr, q);
+    }
+    launch_pcg_rr(prr, sc, q);
+    HIPCHK(hipGetLastError());
+    double h[SC_COUNT];
+    if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
+    const double rr0 = h[SC_RR0];
+    double rr = rr0;
+    int it = 0;
+    ba_status result = BA_OK;
+    if (rr0 > 0.0) {
+        launch_precond(s->np, s->Dchol, r, P, q);
+        result = BA_MAXITER;
+        const SchurArgs sa = schur_args(s, prec);
+        for (it = 0; it < opts.max_iter;) {
+            matvec(s, sa, P, Q);                                         // Q_i = S P_i
+            launch_dot2(n, Q, P, P, r, pdq, q);                          // Delta_i, gamma_i
+            launch_pcg_update_xr(n, pdq, sc, x, r, P, Q, prr, q);        // alpha_i, x, r
+            launch_pcg_rr(prr, sc, q);
+            HIPCHK(hipGetLastError());
+            if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
+            if (h[SC_BREAK] != 0.0) {
+                result = BA_ERR_BREAKDOWN;
+                g_err = "PCG breakdown: P^T S P <= 0";
+                break;
+            }
+            ++it;
+            rr = h[SC_RR];
+            if (stats && stats->trace_res && it - 1 < stats->trace_cap) stats->trace_res[it - 1] = std::sqrt(rr / rr0);
+            if (std::sqrt(rr) < opts.eps * std::sqrt(rr0)) {
+                result = BA_OK;
+                break;
+            }
+            launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, q);  // Z_{i+1}, Phi_i
+            launch_pcg_update_p(n, pphi, sc, z, P, q);                   // beta_i, P_{i+1}
+        }
+    }
+    HIPCHK(hipStreamSynchronize(q));
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) {
+        stats->iterations = it;
+        stats->multi_steps = 0;
+        stats->history_cols = it;
+        stats->refinement_steps = 0;
+        stats->status = result;
+        stats->rel_res_recursive = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
+        stats->t_solve_ms = ms;
+        double tr = 0.0;
+        if ((st = true_rel_residual(s, x, tmp, pdq, sc, &tr)) != BA_OK) return st;
+        stats->rel_res_true = tr;
+    }
+    return result;
+}
+
+// ------------------------------------------------------------------ Algorithm 2
+
+ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, double *x,
+                       const ba_solve_opts *opts_in, ba_solve_stats *stats) {
+    if (!s || !x) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (N < 1 || N > s->np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, n_cams]");
+    if (N > 64) return fail(BA_ERR_UNSUPPORTED, "at most 64 subsets are supported");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(BA_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    ba_solve_opts opts;
+    if (opts_in) opts = *opts_in;
+    else fill_default_opts(&opts);
+    if (!(opts.eps >= 0.0) || opts.max_iter < 0) return fail(BA_ERR_INVALID_ARG, "eps >= 0 and max_iter >= 0 required");
+    const int prec = opts.precision;
+    ba_status st = ensure_precision(s, prec);
+    if (st != BA_OK) return st;
+    if (N > 1 && (st = ensure_multi(s, N)) != BA_OK) return st;
+    const int64_t n = (int64_t)s->np * 9;
+    hipStream_t q = s->stream;
+    const int64_t cap = opts.max_history_cols > 0 ? opts.max_history_cols : 1 + (int64_t)opts.max_iter * N;
+    if (cap < 1) return fail(BA_ERR_WORKSPACE, "history capacity must hold at least one column");
+    if (s->hist_cap_cols < cap) {
+        dfree(s->hist);
+        s->hist_cap_cols = 0;
+        if ((st = dalloc(&s->hist, (size_t)(2 * cap) * (size_t)n)) != BA_OK) return st;
+        s->hist_cap_cols = cap;
+    }
+    const int64_t hc = s->hist_cap_cols;
+    double *Ph = s->hist, *Qh = s->hist + hc * n;
+    // small storage: Dp (64 * cap), Phi (cap * N), beta (cap * N), gamma, alpha (64 each), block tables
+    const size_t small_need = (size_t)(64 * hc + 2 * hc * N + 128) + (size_t)(3 * hc + 8);
+    if (s->small_cap < small_need) {
+        dfree(s->small);
+        s->small_cap = 0;
+        if ((st = dalloc(&s->small, small_need)) != BA_OK) return st;
+        s->small_cap = small_need;
+    }
+    double *Dp = s->small, *Phi = Dp + 64 * hc, *beta = Phi + hc * N, *gamma = beta + hc * N, *alpha = gamma + 64;
+    int32_t *blk_off = reinterpret_cast<int32_t *>(alpha + 64);
+    int32_t *blk_k = blk_off + hc;
+    int64_t *blk_dp = reinterpret_cast<int64_t *>(blk_k + hc + 2);
+    if ((st = ensure_vec(s, (size_t)n * 4 + SC_COUNT)) != BA_OK) return st;
+    if ((st = ensure_red(s, (size_t)kRedBlocks * (64 * 64 + 64))) != BA_OK) return st;
+    double *r = s->vec, *z = r + n, *tmp = z + n, *sc = tmp + 2 * n;
+    double *red = s->red;
+    const int gs = s->np / N;
+    const SchurArgs sa = schur_args(s, prec);
+    const MultiArgs ma = N > 1 ? multi_args(s, prec) : MultiArgs();
+
+    auto t0 = std::chrono::steady_clock::now();
+    if ((st = init_scalars(s, sc)) != BA_OK) return st;
+    if (x0) {
+        HIPCHK(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
+        matvec(s, sa, x, tmp);
+        launch_pcg_init(n, s->bt, tmp, r, red, q);
+    } else {
+        HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), q));
+        launch_pcg_init(n, s->bt, nullptr, r, red, q);
+    }
+    launch_pcg_rr(red, sc, q);
+    HIPCHK(hipGetLastError());
+    double h[SC_COUNT];
+    if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
+    const double rr0 = h[SC_RR0];
+    double rr = rr0;
+    int it = 0, multi_steps = 0;
+    int64_t hcols = 0;
+    ba_status result = BA_OK;
+    if (rr0 > 0.0) {
+        // P_0 = Z_0 = D(S)^-1 r_0 ; Q_0 = S P_0
+        launch_precond(s->np, s->Dchol, r, Ph, q);
+        matvec(s, sa, Ph, Qh);
+        std::vector<int32_t> hoff{0}, hk{1};
+        std::vector<int64_t> hdp{0};
+        HIPCHK(hipMemcpyAsync(blk_off, hoff.data(), 4, hipMemcpyHostToDevice, q));
+        HIPCHK(hipMemcpyAsync(blk_k, hk.data(), 4, hipMemcpyHostToDevice, q));
+        HIPCHK(hipMemcpyAsync(blk_dp, hdp.data(), 8, hipMemcpyHostToDevice, q));
+        int64_t dp_used = 1;
+        hcols = 1;
+        result = BA_MAXITER;
+        for (it = 0; it < opts.max_iter;) {
+            const int nb = (int)hoff.size();
+            const int off = hoff.back(), k = hk.back();
+            const int64_t dpo = hdp.back();
+            // Delta_i = Q_i^T P_i, gamma_i = P_i^T r_i, alpha_i = Delta_i^+ gamma_i
+            launch_gram(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, r, red, q);
+            launch_pinv_alpha(k, red, kRedBlocks, Dp + dpo, gamma, alpha, sc, q);
+            // x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i
+            launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
+            launch_pcg_rr(red, sc, q);
+            HIPCHK(hipGetLastError());
+            if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
+            if (h[SC_RANK] == 0.0) {
+                result = BA_ERR_BREAKDOWN;
+                g_err = "MCG breakdown: Delta_i is numerically zero";
+                break;
+            }
+            ++it;
+            rr = h[SC_RR];
+            const int ti = it - 1;
+            if (stats && ti < stats->trace_cap) {
+                if (stats->trace_res) stats->trace_res[ti] = std::sqrt(rr / rr0);
+                if (stats->trace_t) stats->trace_t[ti] = NAN;
+                if (stats->trace_k) stats->trace_k[ti] = 0;
+            }
+            if (std::sqrt(rr) < opts.eps * std::sqrt(rr0)) {
+                result = BA_OK;
+                break;
+            }
+            // tau-test: t_i = gamma_i^T alpha_i / (r^T D^-1 r)
+            launch_precond_rho(s->np, s->Dchol, r, z, red, q);
+            launch_tau(k, red, gamma, alpha, sc, q);
+            HIPCHK(hipGetLastError());
+            if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
+            const double t_i = h[SC_T];
+            const bool multi = N > 1 && t_i < tau;
+            const int kn = multi ? N : 1;
+            if (stats && ti < stats->trace_cap) {
+                if (stats->trace_t) stats->trace_t[ti] = t_i;
+                if (stats->trace_k) stats->trace_k[ti] = kn;
+            }
+            if (hcols + kn > hc) {
+                result = fail(BA_ERR_WORKSPACE, "MCG direction history is full (raise max_history_cols)");
+                break;
+            }
+            double *Pn = Ph + hcols * n, *Qn = Qh + hcols * n;
+            if (multi) launch_schur_multi(ma, z, Qn, q);                 // S Z_{i+1}
+            // Phi_{i,j} = Q_j^T Z_{i+1}, beta_{i,j} = Delta_j^+ Phi_{i,j}
+            launch_phi(n, (int)hcols, Qh, z, multi ? 1 : 0, N, gs, Phi, q);
+            launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, kn, beta, q);
+            // P_{i+1} = Z - sum P_j beta ; multidirectional: Q_{i+1} = S Z - sum Q_j beta (eq. (19))
+            launch_update_pq(n, (int)hcols, kn, Ph, Qh, beta, z, multi ? 1 : 0, gs, N, multi ? Qn : nullptr, Pn,
+                             multi ? Qn : nullptr, q);
+            if (!multi) matvec(s, sa, Pn, Qn);                           // Q_{i+1} = S P_{i+1}
+            HIPCHK(hipGetLastError());
+            hoff.push_back((int32_t)hcols);
+            hk.push_back(kn);
+            hdp.push_back(dp_used);
+            HIPCHK(hipMemcpyAsync(blk_off + nb, &hoff[nb], 4, hipMemcpyHostToDevice, q));
+            HIPCHK(hipMemcpyAsync(blk_k + nb, &hk[nb], 4, hipMemcpyHostToDevice, q));
+            HIPCHK(hipMemcpyAsync(blk_dp + nb, &hdp[nb], 8, hipMemcpyHostToDevice, q));
+            HIPCHK(hipStreamSynchronize(q));   // the block entries above are host memory
+            dp_used += (int64_t)kn * kn;
+            hcols += kn;
+            multi_steps += multi;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(q));
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) {
+        stats->iterations = it;
+        stats->multi_steps = multi_steps;
+        stats->history_cols = (int32_t)hcols;
+        stats->refinement_steps = 0;
+        stats->status = result;
+        stats->rel_res_recursive = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
+        stats->t_solve_ms = ms;
+        double tr = 0.0;
+        if ((st = true_rel_residual(s, x, tmp, red, sc, &tr)) != BA_OK) return st;
+        stats->rel_res_true = tr;
+    }
+    return result;
+}
+
+}  // extern "C"

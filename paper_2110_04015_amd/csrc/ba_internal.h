@@ -1,0 +1,145 @@
+// Internal declarations of the reduced-camera-system library (gfx950).
+//
+// Layout of the Jacobian stream in HBM ("tiles"):
+//   Observations are grouped by landmark; landmarks are packed into tiles of
+//   64 observation slots (one slot per lane of a wavefront) without straddling
+//   a tile boundary; unused slots are padding.  A tile stores its 24 Jacobian
+//   scalars per observation component-pair-major: for pair q (0..11) and lane l
+//   the two doubles J[2q], J[2q+1] sit at ((tile*12 + q)*64 + l)*2, so a
+//   wavefront loads each pair with one fully coalesced 1 KiB access.
+//   Components 0..17 are J_p (2x9 row-major), 18..23 are J_l (2x3 row-major).
+//   Consecutive tiles form a "chunk", processed by one wavefront, whose
+//   cameras are numbered by chunk-local slots; the wavefront accumulates its
+//   camera contributions in LDS and writes one partial row per slot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ba.h"
+
+namespace ba {
+
+constexpr int kTile = 64;          // observation slots per tile (= wavefront width)
+constexpr int kPairs = 12;         // 16-byte component pairs per observation
+constexpr uint32_t kPad = 0xFFFFFFFFu;
+
+// Per-slot metadata word: bits 0..15 chunk-local camera slot, bits 16..21 the
+// landmark's index inside its tile.  Padding slots hold kPad.
+__host__ __device__ inline uint32_t meta_pack(uint32_t slot, uint32_t ll) { return slot | (ll << 16); }
+
+struct HostPlan {
+    int np = 0, nl = 0;
+    int64_t m = 0;
+    int64_t n_tiles = 0;
+    int n_chunks = 0;
+    int64_t n_part = 0;
+    int max_slots = 128, max_tiles = 16;
+    std::vector<int32_t> lmk_order;       // storage index -> landmark id
+    std::vector<int32_t> lmk_store;       // landmark id -> storage index
+    std::vector<int64_t> slot_obs;        // tile slot -> observation index or -1
+    std::vector<uint32_t> meta;           // tile slot -> meta word
+    std::vector<int32_t> tile_lmk_base;   // tile -> storage index of its first landmark
+    std::vector<int64_t> lmk_first_slot;  // storage index -> first tile slot
+    std::vector<int32_t> lmk_count;       // storage index -> observations
+    std::vector<int32_t> chunk_tile;      // [n_chunks + 1]
+    std::vector<int32_t> chunk_part;      // [n_chunks + 1] first partial row
+    std::vector<int32_t> part_cam;        // partial row -> camera
+    std::vector<int32_t> cam_part_ptr;    // [np + 1]
+    std::vector<int32_t> cam_part_idx;    // partial rows, camera-major, ascending
+    std::vector<int64_t> cam_obs_ptr;     // [np + 1]
+    std::vector<int64_t> cam_obs;         // observation indices, camera-major
+    std::vector<int32_t> obs_cam;         // host copy of the camera of each observation
+};
+
+// Plan of the multidirectional product for one partition (N subsets).
+struct HostMultiPlan {
+    int N = 0;
+    int n_chunks = 0;
+    int64_t n_part = 0;
+    int max_out = 0;                      // largest out-pair count of a chunk
+    std::vector<uint32_t> mmeta;          // tile slot -> own pair | first pair << 8 | pairs << 16
+    std::vector<int32_t> slot_cam;        // tile slot -> camera (0 for padding)
+    std::vector<uint8_t> pair_ll;         // tile * 64 + pair -> landmark index in tile
+    std::vector<uint32_t> tile_oidx;      // [n_tiles + 1] first entry of the tile in oidx
+    std::vector<uint16_t> oidx;           // (slot, j-th pair of its landmark) -> chunk out-pair
+    std::vector<uint16_t> slot_ooff;      // tile slot -> offset of its entries in the tile's oidx
+    std::vector<int32_t> chunk_tile;      // [n_chunks + 1]
+    std::vector<int32_t> chunk_part;      // [n_chunks + 1]
+    std::vector<int32_t> cg_ptr;          // [np * N + 1] partial rows of (camera, subset)
+    std::vector<int32_t> cg_idx;
+};
+
+struct DevMulti {
+    int N = 0, n_chunks = 0, max_out = 0;
+    int64_t n_part = 0;
+    uint32_t *mmeta = nullptr;
+    int32_t *slot_cam = nullptr;
+    uint8_t *pair_ll = nullptr;
+    uint32_t *tile_oidx = nullptr;
+    uint16_t *oidx = nullptr;
+    uint16_t *slot_ooff = nullptr;
+    int32_t *chunk_tile = nullptr, *chunk_part = nullptr;
+    int32_t *cg_ptr = nullptr, *cg_idx = nullptr;
+    double *partial = nullptr;
+    int32_t *group = nullptr;             // camera -> subset
+};
+
+// Plan construction (host, plan.cpp).  Returns BA_OK or an error with message.
+ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_t *lm,
+                     int max_slots, int max_tiles, HostPlan &plan, std::string &err);
+ba_status build_multi_plan(const HostPlan &plan, int N, int max_out, HostMultiPlan &mp,
+                           std::string &err);
+void partition_groups(int np, int N, int32_t *group);
+
+}  // namespace ba
+
+// The system handle.
+struct ba_system {
+    hipStream_t stream = nullptr;
+    int np = 0, nl = 0;
+    int64_t m = 0;
+    double lambda = 0.0;
+    ba::HostPlan plan;
+    // device arrays
+    double *J64 = nullptr;          // n_tiles * 64 * 24
+    float *J32 = nullptr;           // optional FP32 copy
+    uint16_t *J16 = nullptr;        // optional BF16 copy (scaled)
+    float *bf16_scale = nullptr;    // [np][9] column scales of the BF16 copy
+    uint32_t *meta = nullptr;
+    int32_t *tile_lmk_base = nullptr;
+    int32_t *chunk_tile = nullptr, *chunk_part = nullptr, *part_cam = nullptr;
+    int32_t *cam_part_ptr = nullptr, *cam_part_idx = nullptr;
+    double *partial = nullptr;      // n_part * 9
+    double *vinv = nullptr;         // nl * 6 (storage order): V_lambda^-1, symmetric
+    double *bl = nullptr;           // nl * 3 (storage order)
+    double *dU = nullptr;           // np * 9: lambda * diag(J_p^T J_p)
+    double *Dblk = nullptr;         // np * 81: D(S)
+    double *Dchol = nullptr;        // np * 45: packed lower Cholesky factor of D(S)
+    double *bt = nullptr;           // n: b~
+    int32_t *lmk_order = nullptr;   // storage index -> landmark id
+    int64_t *lmk_first_slot = nullptr;
+    int32_t *lmk_count = nullptr;
+    int32_t *status = nullptr;      // device status word
+    // solver scratch (allocated on demand)
+    double *vec = nullptr;          // work vectors
+    size_t vec_cap = 0;
+    double *red = nullptr;          // reduction partials
+    size_t red_cap = 0;
+    double *hist = nullptr;         // MCG history (P then Q)
+    int64_t hist_cap_cols = 0;
+    double *small = nullptr;        // MCG small dense storage
+    size_t small_cap = 0;
+    double *host_pinned = nullptr;  // pinned host scalars
+    ba::DevMulti multi;
+    std::vector<int32_t> multi_group;
+    // optional event timing of the chunked Schur-product kernel
+    bool profiling = false;
+    std::vector<hipEvent_t> prof_events;  // start/stop pairs
+    size_t prof_used = 0;                 // events recorded since the last flush
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
+};

@@ -1,0 +1,307 @@
+// System build kernels: the damped normal-equation blocks and the reduced
+// camera system of Sec. 3.1, eq. (8)-(15), and the block-Jacobi preconditioner
+// D(S) of Sec. 3.2 (before Algorithm 1), all in FP64.
+#include "ba_internal.h"
+#include "kernels.h"
+
+namespace ba {
+
+// ---------------------------------------------------------------- validation
+
+__global__ void k_check_finite(const double *__restrict__ a, int64_t count, int32_t *status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (; i < count; i += stride) bad |= !isfinite(a[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, kStatusNonfinite);
+}
+
+// ---------------------------------------------------------------- packing
+
+// One thread per tile slot: gathers the observation's 2x9 and 2x3 blocks and
+// writes them in the component-pair-major tile layout (plus FP32 / BF16 copies).
+__global__ void k_pack(const int64_t *__restrict__ slot_obs, int64_t nslots, const double *__restrict__ Jp,
+                       const double *__restrict__ Jl, double *__restrict__ J64, float *__restrict__ J32,
+                       uint16_t *__restrict__ J16) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslots) return;
+    int64_t o = slot_obs[s];
+    double v[24];
+    if (o >= 0) {
+        for (int k = 0; k < 18; ++k) v[k] = Jp[o * 18 + k];
+        for (int k = 0; k < 6; ++k) v[18 + k] = Jl[o * 6 + k];
+    } else {
+        for (int k = 0; k < 24; ++k) v[k] = 0.0;
+    }
+    int64_t tile = s / kTile;
+    int lane = (int)(s % kTile);
+    double2 *d2 = reinterpret_cast<double2 *>(J64);
+    for (int q = 0; q < 12; ++q) d2[(tile * 12 + q) * kTile + lane] = make_double2(v[2 * q], v[2 * q + 1]);
+    if (J32) {
+        float4 *f4 = reinterpret_cast<float4 *>(J32);
+        for (int q = 0; q < 6; ++q)
+            f4[(tile * 6 + q) * kTile + lane] =
+                make_float4((float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]);
+    }
+    if (J16) {
+        uint4 *u4 = reinterpret_cast<uint4 *>(J16);
+        for (int q = 0; q < 3; ++q) {
+            uint32_t w[4];
+            for (int h = 0; h < 4; ++h)
+                w[h] = (uint32_t)f32_to_bf16((float)v[8 * q + 2 * h]) |
+                       ((uint32_t)f32_to_bf16((float)v[8 * q + 2 * h + 1]) << 16);
+            u4[(tile * 3 + q) * kTile + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+// Lower-precision copies of an existing FP64 tile stream (one thread per slot).
+__global__ void k_convert(const double *__restrict__ J64, int64_t nslots, float *__restrict__ J32,
+                          uint16_t *__restrict__ J16) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslots) return;
+    int64_t tile = s / kTile;
+    int lane = (int)(s % kTile);
+    const double2 *d2 = reinterpret_cast<const double2 *>(J64);
+    double v[24];
+    for (int q = 0; q < 12; ++q) {
+        double2 d = d2[(tile * 12 + q) * kTile + lane];
+        v[2 * q] = d.x;
+        v[2 * q + 1] = d.y;
+    }
+    if (J32) {
+        float4 *f4 = reinterpret_cast<float4 *>(J32);
+        for (int q = 0; q < 6; ++q)
+            f4[(tile * 6 + q) * kTile + lane] =
+                make_float4((float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]);
+    }
+    if (J16) {
+        uint4 *u4 = reinterpret_cast<uint4 *>(J16);
+        for (int q = 0; q < 3; ++q) {
+            uint32_t w[4];
+            for (int h = 0; h < 4; ++h)
+                w[h] = (uint32_t)f32_to_bf16((float)v[8 * q + 2 * h]) |
+                       ((uint32_t)f32_to_bf16((float)v[8 * q + 2 * h + 1]) << 16);
+            u4[(tile * 3 + q) * kTile + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+void launch_convert(const double *J64, int64_t nslots, float *J32, uint16_t *J16, hipStream_t s) {
+    if (nslots <= 0) return;
+    hipLaunchKernelGGL(k_convert, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, J64, nslots, J32, J16);
+}
+
+// ---------------------------------------------------------------- landmarks
+
+// One thread per landmark (storage order): V_lambda = J_l^T J_l + lambda diag(J_l^T J_l)
+// (eq. (10)), b_l = J_l^T r0 (eq. (12)), V_lambda^-1 (symmetric, 6 entries) and
+// h0 = V_lambda^-1 b_l.
+__global__ void k_landmarks(int nl, const int64_t *__restrict__ first_slot, const int32_t *__restrict__ count,
+                            const int64_t *__restrict__ slot_obs, const double *__restrict__ Jl,
+                            const double *__restrict__ r, double lambda, double *__restrict__ vinv,
+                            double *__restrict__ bl, double *__restrict__ h0, int32_t *status) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nl) return;
+    double V[6] = {0, 0, 0, 0, 0, 0};   // 00 01 02 11 12 22
+    double b[3] = {0, 0, 0};
+    int64_t f = first_slot[s];
+    int c = count[s];
+    for (int q = 0; q < c; ++q) {
+        int64_t o = slot_obs[f + q];
+        const double *j = Jl + o * 6;
+        double r0 = r[o * 2], r1 = r[o * 2 + 1];
+        V[0] += j[0] * j[0] + j[3] * j[3];
+        V[1] += j[0] * j[1] + j[3] * j[4];
+        V[2] += j[0] * j[2] + j[3] * j[5];
+        V[3] += j[1] * j[1] + j[4] * j[4];
+        V[4] += j[1] * j[2] + j[4] * j[5];
+        V[5] += j[2] * j[2] + j[5] * j[5];
+        b[0] += j[0] * r0 + j[3] * r1;
+        b[1] += j[1] * r0 + j[4] * r1;
+        b[2] += j[2] * r0 + j[5] * r1;
+    }
+    V[0] += lambda * V[0];
+    V[3] += lambda * V[3];
+    V[5] += lambda * V[5];
+    // 3x3 Cholesky V = L L^T
+    double l00 = V[0];
+    bool ok = l00 > 0.0;
+    l00 = sqrt(ok ? l00 : 1.0);
+    double l10 = V[1] / l00, l20 = V[2] / l00;
+    double l11 = V[3] - l10 * l10;
+    ok = ok && l11 > 0.0;
+    l11 = sqrt(ok ? l11 : 1.0);
+    double l21 = (V[4] - l20 * l10) / l11;
+    double l22 = V[5] - l20 * l20 - l21 * l21;
+    ok = ok && l22 > 0.0;
+    l22 = sqrt(ok ? l22 : 1.0);
+    if (!ok) atomicOr(status, kStatusNotSpdLandmark);
+    // L^-1 (lower), then V^-1 = L^-T L^-1
+    double i00 = 1.0 / l00, i11 = 1.0 / l11, i22 = 1.0 / l22;
+    double i10 = -l10 * i00 * i11;
+    double i21 = -l21 * i11 * i22;
+    double i20 = -(l20 * i00 + l21 * i10) * i22;
+    double w[6];
+    w[0] = i00 * i00 + i10 * i10 + i20 * i20;
+    w[1] = i11 * i10 + i21 * i20;
+    w[2] = i22 * i20;
+    w[3] = i11 * i11 + i21 * i21;
+    w[4] = i22 * i21;
+    w[5] = i22 * i22;
+    for (int k = 0; k < 6; ++k) vinv[(int64_t)s * 6 + k] = w[k];
+    for (int k = 0; k < 3; ++k) bl[(int64_t)s * 3 + k] = b[k];
+    h0[(int64_t)s * 3 + 0] = w[0] * b[0] + w[1] * b[1] + w[2] * b[2];
+    h0[(int64_t)s * 3 + 1] = w[1] * b[0] + w[3] * b[1] + w[4] * b[2];
+    h0[(int64_t)s * 3 + 2] = w[2] * b[0] + w[4] * b[1] + w[5] * b[2];
+}
+
+// ---------------------------------------------------------------- cameras
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One wavefront per camera.  Pass 1: U = J_p^T J_p and b_p = J_p^T r0 over the
+// camera's observations (eq. (9), (11)).  Pass 2: E = sum_o W_o V^-1 W_o^T and
+// w = sum_o W_o V^-1 b_l with W_o = J_p,o^T J_l,o.  Then
+//   D(S)_c = U + lambda diag(U) - E   (diagonal block of eq. (14))
+//   b~_c   = b_p - w                  (eq. (15))
+// and the Cholesky factor of D(S)_c.
+__global__ __launch_bounds__(64) void k_cameras(int np, const int64_t *__restrict__ cam_ptr,
+                                                const int64_t *__restrict__ cam_obs,
+                                                const int32_t *__restrict__ obs_lm,
+                                                const int32_t *__restrict__ lmk_store,
+                                                const double *__restrict__ Jp, const double *__restrict__ Jl,
+                                                const double *__restrict__ r, const double *__restrict__ vinv,
+                                                const double *__restrict__ h0, double lambda,
+                                                double *__restrict__ dU, double *__restrict__ Dblk,
+                                                double *__restrict__ Dchol, double *__restrict__ bt,
+                                                int32_t *status) {
+    int c = blockIdx.x;
+    int lane = threadIdx.x;
+    if (c >= np) return;
+    __shared__ double red[54];
+    int64_t a = cam_ptr[c], b = cam_ptr[c + 1];
+    double acc[54];
+    // pass 1: U (upper triangle, 45) and b_p (9)
+    for (int k = 0; k < 54; ++k) acc[k] = 0.0;
+    for (int64_t q = a + lane; q < b; q += 64) {
+        int64_t o = cam_obs[q];
+        const double *j = Jp + o * 18;
+        double r0 = r[o * 2], r1 = r[o * 2 + 1];
+        int t = 0;
+        for (int i = 0; i < 9; ++i)
+            for (int k = i; k < 9; ++k) acc[t++] += j[i] * j[k] + j[9 + i] * j[9 + k];
+        for (int i = 0; i < 9; ++i) acc[45 + i] += j[i] * r0 + j[9 + i] * r1;
+    }
+    for (int k = 0; k < 54; ++k) {
+        double v = wave_sum(acc[k]);
+        if (lane == 0) red[k] = v;
+    }
+    __syncthreads();
+    double U[45], bp[9];
+    for (int k = 0; k < 45; ++k) U[k] = red[k];
+    for (int k = 0; k < 9; ++k) bp[k] = red[45 + k];
+    __syncthreads();
+    // pass 2: E = sum W V^-1 W^T (upper, 45) and w = sum W h0 (9)
+    for (int k = 0; k < 54; ++k) acc[k] = 0.0;
+    for (int64_t q = a + lane; q < b; q += 64) {
+        int64_t o = cam_obs[q];
+        const double *jp = Jp + o * 18, *jl = Jl + o * 6;
+        int64_t ls = lmk_store[obs_lm[o]];
+        const double *vi = vinv + ls * 6;
+        const double *hh = h0 + ls * 3;
+        double W[27];
+        for (int i = 0; i < 9; ++i)
+            for (int k = 0; k < 3; ++k) W[i * 3 + k] = jp[i] * jl[k] + jp[9 + i] * jl[3 + k];
+        double VW[27];   // (V^-1 W^T)^T = W V^-1, rows i
+        for (int i = 0; i < 9; ++i) {
+            double w0 = W[i * 3], w1 = W[i * 3 + 1], w2 = W[i * 3 + 2];
+            VW[i * 3 + 0] = w0 * vi[0] + w1 * vi[1] + w2 * vi[2];
+            VW[i * 3 + 1] = w0 * vi[1] + w1 * vi[3] + w2 * vi[4];
+            VW[i * 3 + 2] = w0 * vi[2] + w1 * vi[4] + w2 * vi[5];
+        }
+        int t = 0;
+        for (int i = 0; i < 9; ++i)
+            for (int k = i; k < 9; ++k)
+                acc[t++] += VW[i * 3] * W[k * 3] + VW[i * 3 + 1] * W[k * 3 + 1] + VW[i * 3 + 2] * W[k * 3 + 2];
+        for (int i = 0; i < 9; ++i) acc[45 + i] += W[i * 3] * hh[0] + W[i * 3 + 1] * hh[1] + W[i * 3 + 2] * hh[2];
+    }
+    for (int k = 0; k < 54; ++k) {
+        double v = wave_sum(acc[k]);
+        if (lane == 0) red[k] = v;
+    }
+    __syncthreads();
+    if (lane != 0) return;
+    double D[81];
+    int t = 0;
+    for (int i = 0; i < 9; ++i) {
+        for (int k = i; k < 9; ++k, ++t) {
+            double u = U[t];
+            if (k == i) u += lambda * U[t];
+            double d = u - red[t];
+            D[i * 9 + k] = d;
+            D[k * 9 + i] = d;
+        }
+    }
+    t = 0;
+    for (int i = 0; i < 9; ++i) {
+        int diag = i * 9 - (i * (i - 1)) / 2;   // index of (i, i) in the packed upper triangle
+        dU[(int64_t)c * 9 + i] = lambda * U[diag];
+        bt[(int64_t)c * 9 + i] = bp[i] - red[45 + i];
+    }
+    for (int k = 0; k < 81; ++k) Dblk[(int64_t)c * 81 + k] = D[k];
+    // packed lower Cholesky factor, row i holds L[i][0..i]
+    double L[45];
+    bool ok = true;
+    for (int j = 0; j < 9; ++j) {
+        double d = D[j * 9 + j];
+        for (int p = 0; p < j; ++p) d -= L[j * (j + 1) / 2 + p] * L[j * (j + 1) / 2 + p];
+        if (!(d > 0.0)) {
+            ok = false;
+            d = 1.0;
+        }
+        d = sqrt(d);
+        L[j * (j + 1) / 2 + j] = d;
+        for (int i = j + 1; i < 9; ++i) {
+            double s = D[i * 9 + j];
+            for (int p = 0; p < j; ++p) s -= L[i * (i + 1) / 2 + p] * L[j * (j + 1) / 2 + p];
+            L[i * (i + 1) / 2 + j] = s / d;
+        }
+    }
+    if (!ok) atomicOr(status, kStatusNotSpdCamera);
+    for (int k = 0; k < 45; ++k) Dchol[(int64_t)c * 45 + k] = L[k];
+}
+
+// ---------------------------------------------------------------- launchers
+
+void launch_check_finite(const double *a, int64_t count, int32_t *status, hipStream_t s) {
+    if (count <= 0) return;
+    int blocks = (int)std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_check_finite, dim3(blocks), dim3(256), 0, s, a, count, status);
+}
+
+void launch_pack(const int64_t *slot_obs, int64_t nslots, const double *Jp, const double *Jl, double *J64,
+                 float *J32, uint16_t *J16, hipStream_t s) {
+    int blocks = (int)((nslots + 255) / 256);
+    hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, s, slot_obs, nslots, Jp, Jl, J64, J32, J16);
+}
+
+void launch_landmarks(int nl, const int64_t *first_slot, const int32_t *count, const int64_t *slot_obs,
+                      const double *Jl, const double *r, double lambda, double *vinv, double *bl, double *h0,
+                      int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_landmarks, dim3((nl + 255) / 256), dim3(256), 0, s, nl, first_slot, count, slot_obs, Jl,
+                       r, lambda, vinv, bl, h0, status);
+}
+
+void launch_cameras(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const int32_t *obs_lm,
+                    const int32_t *lmk_store, const double *Jp, const double *Jl, const double *r,
+                    const double *vinv, const double *h0, double lambda, double *dU, double *Dblk,
+                    double *Dchol, double *bt, int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_cameras, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, obs_lm, lmk_store, Jp, Jl, r,
+                       vinv, h0, lambda, dU, Dblk, Dchol, bt, status);
+}
+
+}  // namespace ba

@@ -1,0 +1,350 @@
+// Implicit Schur products of the reduced camera system (Sec. 3.1, eq. (14)):
+//   S v = U_lambda v - W V_lambda^-1 W^T v
+// computed from the per-observation Jacobian blocks without forming W or S:
+//   e_o = J_p,o v_c                    (2)
+//   g_l = sum_{o in l} J_l,o^T e_o     (3)   = (W^T v)_l
+//   h_l = V_l^-1 g_l
+//   y_c = sum_{o in c} J_p,o^T (e_o - J_l,o h_l) + lambda diag(U_c) v_c
+// One wavefront owns one chunk of landmark tiles: landmark sums are reduced in
+// LDS inside the tile, camera sums in a per-wavefront LDS accumulator indexed
+// by chunk-local camera slot.  Each chunk writes one partial row per slot and a
+// second kernel adds the partial rows of every camera in a fixed order, so the
+// result does not depend on scheduling and no global atomics are used.
+//
+// The multidirectional product (Sec. 3.2, "Optimized implementation",
+// eq. (19)) applies S to the N columns Z[:, p] = z restricted to the poses of
+// subset p.  An observation of camera c in subset q contributes e_o to column q
+// only; its landmark then carries one h_{l,p} per subset p among its observers,
+// and every observation of l receives a contribution in each such column.
+#include "ba_internal.h"
+#include "kernels.h"
+
+namespace ba {
+
+typedef double dbl2_t __attribute__((ext_vector_type(2)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+template <int PREC>
+struct Loader;
+
+template <>
+struct Loader<0> {   // FP64, 12 x 16 B per observation
+    template <typename T>
+    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[24]) {
+        const dbl2_t *p = reinterpret_cast<const dbl2_t *>(J) + tile * 12 * kTile + lane;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            dbl2_t d = __builtin_nontemporal_load(p + q * kTile);
+            v[2 * q] = (T)d.x;
+            v[2 * q + 1] = (T)d.y;
+        }
+    }
+};
+
+template <>
+struct Loader<1> {   // FP32, 6 x 16 B per observation
+    template <typename T>
+    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[24]) {
+        const flt4_t *p = reinterpret_cast<const flt4_t *>(J) + tile * 6 * kTile + lane;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            flt4_t f = __builtin_nontemporal_load(p + q * kTile);
+            v[4 * q] = (T)f.x;
+            v[4 * q + 1] = (T)f.y;
+            v[4 * q + 2] = (T)f.z;
+            v[4 * q + 3] = (T)f.w;
+        }
+    }
+};
+
+template <>
+struct Loader<2> {   // BF16, 3 x 16 B per observation
+    template <typename T>
+    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[24]) {
+        const u32x4_t *p = reinterpret_cast<const u32x4_t *>(J) + tile * 3 * kTile + lane;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            u32x4_t u = __builtin_nontemporal_load(p + q * kTile);
+            uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                v[8 * q + 2 * h] = (T)bf16_to_f32(w[h] & 0xFFFFu);
+                v[8 * q + 2 * h + 1] = (T)bf16_to_f32(w[h] >> 16);
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------- one column
+
+template <int PREC, typename T>
+__global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__restrict__ v) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *vloc = reinterpret_cast<T *>(smem);
+    T *yloc = vloc + a.max_slots * 9;
+    T *gloc = yloc + a.max_slots * 9;
+    const int chunk = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int pb = a.chunk_part[chunk];
+    const int ns = a.chunk_part[chunk + 1] - pb;
+    for (int i = lane; i < ns * 9; i += kTile) {
+        vloc[i] = (T)v[(int64_t)a.part_cam[pb + i / 9] * 9 + i % 9];
+        yloc[i] = (T)0;
+    }
+    __syncthreads();
+    const int t1 = a.chunk_tile[chunk + 1];
+    for (int t = a.chunk_tile[chunk]; t < t1; ++t) {
+        T J[24];
+        Loader<PREC>::load(a.J, t, lane, J);
+        const uint32_t mt = a.meta[(int64_t)t * kTile + lane];
+        const int lmk0 = a.tile_lmk_base[t];
+        const bool valid = mt != kPad;
+        const int slot = valid ? (int)(mt & 0xFFFFu) : 0;
+        const int ll = valid ? (int)((mt >> 16) & 63u) : 0;
+        T vc[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) vc[k] = vloc[slot * 9 + k];
+        T e0 = 0, e1 = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            e0 += J[k] * vc[k];
+            e1 += J[9 + k] * vc[k];
+        }
+        gloc[lane * 3 + 0] = 0;
+        gloc[lane * 3 + 1] = 0;
+        gloc[lane * 3 + 2] = 0;
+        __syncthreads();
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], J[18 + k] * e0 + J[21 + k] * e1);
+        }
+        __syncthreads();
+        if (valid) {
+            const double *vi = a.vinv + (int64_t)(lmk0 + ll) * 6;
+            const T w0 = (T)vi[0], w1 = (T)vi[1], w2 = (T)vi[2], w3 = (T)vi[3], w4 = (T)vi[4], w5 = (T)vi[5];
+            const T g0 = gloc[ll * 3], g1 = gloc[ll * 3 + 1], g2 = gloc[ll * 3 + 2];
+            const T h0 = w0 * g0 + w1 * g1 + w2 * g2;
+            const T h1 = w1 * g0 + w3 * g1 + w4 * g2;
+            const T h2 = w2 * g0 + w4 * g1 + w5 * g2;
+            const T f0 = e0 - (J[18] * h0 + J[19] * h1 + J[20] * h2);
+            const T f1 = e1 - (J[21] * h0 + J[22] * h1 + J[23] * h2);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) atomicAdd(&yloc[slot * 9 + k], J[k] * f0 + J[9 + k] * f1);
+        }
+        __syncthreads();
+    }
+    double *out = a.partial + (int64_t)pb * 9;
+    for (int i = lane; i < ns * 9; i += kTile) out[i] = (double)yloc[i];
+}
+
+// y_c = lambda diag(U_c) v_c + sum of the partial rows of camera c (ascending row order)
+__global__ void k_reduce1(int np, const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                          const double *__restrict__ partial, const double *__restrict__ dU,
+                          const double *__restrict__ v, double *__restrict__ y) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np * 9) return;
+    int c = i / 9, k = i - c * 9;
+    double s = dU[i] * v[i];
+    for (int j = ptr[c]; j < ptr[c + 1]; ++j) s += partial[(int64_t)idx[j] * 9 + k];
+    y[i] = s;
+}
+
+void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
+    if (a.n_chunks > 0) {
+        size_t esz = a.precision == 0 ? sizeof(double) : sizeof(float);
+        size_t lds = (size_t)(2 * a.max_slots * 9 + 3 * kTile) * esz;
+        switch (a.precision) {
+            case 0: hipLaunchKernelGGL((k_schur1<0, double>), dim3(a.n_chunks), dim3(kTile), lds, s, a, v); break;
+            case 1: hipLaunchKernelGGL((k_schur1<1, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, v); break;
+            default: hipLaunchKernelGGL((k_schur1<2, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, v); break;
+        }
+    }
+}
+
+void launch_schur_reduce(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
+    int n = a.np * 9;
+    hipLaunchKernelGGL(k_reduce1, dim3((n + 255) / 256), dim3(256), 0, s, a.np, a.cam_part_ptr, a.cam_part_idx,
+                       a.partial, a.dU, v, y);
+}
+
+void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
+    launch_schur_chunks(a, v, s);
+    launch_schur_reduce(a, v, y, s);
+}
+
+// ---------------------------------------------------------------- N columns
+
+template <int PREC, typename T>
+__global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *__restrict__ z) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *yloc = reinterpret_cast<T *>(smem);
+    T *gloc = yloc + a.max_out * 9;
+    T *hloc = gloc + 3 * kTile;
+    const int chunk = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int pb = a.chunk_part[chunk];
+    const int no = a.chunk_part[chunk + 1] - pb;
+    for (int i = lane; i < no * 9; i += kTile) yloc[i] = (T)0;
+    __syncthreads();
+    const int t1 = a.chunk_tile[chunk + 1];
+    for (int t = a.chunk_tile[chunk]; t < t1; ++t) {
+        T J[24];
+        Loader<PREC>::load(a.J, t, lane, J);
+        const int64_t sidx = (int64_t)t * kTile + lane;
+        const uint32_t mt = a.meta[sidx];
+        const uint32_t mm = a.mmeta[sidx];
+        const int lmk0 = a.tile_lmk_base[t];
+        const bool valid = mt != kPad;
+        const int cam = a.slot_cam[sidx];
+        T e0 = 0, e1 = 0;
+        if (valid) {
+            const double *zc = z + (int64_t)cam * 9;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                T zk = (T)zc[k];
+                e0 += J[k] * zk;
+                e1 += J[9 + k] * zk;
+            }
+        }
+        const int own = (int)(mm & 0xFFu);
+        gloc[lane * 3 + 0] = 0;
+        gloc[lane * 3 + 1] = 0;
+        gloc[lane * 3 + 2] = 0;
+        __syncthreads();
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], J[18 + k] * e0 + J[21 + k] * e1);
+        }
+        __syncthreads();
+        const uint8_t pll = a.pair_ll[sidx];
+        if (pll != 0xFF) {
+            const double *vi = a.vinv + (int64_t)(lmk0 + pll) * 6;
+            const T g0 = gloc[lane * 3], g1 = gloc[lane * 3 + 1], g2 = gloc[lane * 3 + 2];
+            hloc[lane * 3 + 0] = (T)vi[0] * g0 + (T)vi[1] * g1 + (T)vi[2] * g2;
+            hloc[lane * 3 + 1] = (T)vi[1] * g0 + (T)vi[3] * g1 + (T)vi[4] * g2;
+            hloc[lane * 3 + 2] = (T)vi[2] * g0 + (T)vi[4] * g1 + (T)vi[5] * g2;
+        }
+        __syncthreads();
+        if (valid) {
+            const int base = (int)((mm >> 8) & 0xFFu), cnt = (int)((mm >> 16) & 0xFFu);
+            const uint16_t *oi = a.oidx + a.tile_oidx[t] + a.slot_ooff[sidx];
+            for (int j = 0; j < cnt; ++j) {
+                const int pj = base + j;
+                const T h0 = hloc[pj * 3], h1 = hloc[pj * 3 + 1], h2 = hloc[pj * 3 + 2];
+                T f0 = -(J[18] * h0 + J[19] * h1 + J[20] * h2);
+                T f1 = -(J[21] * h0 + J[22] * h1 + J[23] * h2);
+                if (pj == own) {
+                    f0 += e0;
+                    f1 += e1;
+                }
+                const int o = oi[j];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) atomicAdd(&yloc[o * 9 + k], J[k] * f0 + J[9 + k] * f1);
+            }
+        }
+        __syncthreads();
+    }
+    double *out = a.partial + (int64_t)pb * 9;
+    for (int i = lane; i < no * 9; i += kTile) out[i] = (double)yloc[i];
+}
+
+// Y[p][c] = [group(c) == p] lambda diag(U_c) z_c + sum of the partial rows of (c, p)
+__global__ void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                               const double *__restrict__ partial, const double *__restrict__ dU,
+                               const int32_t *__restrict__ group, const double *__restrict__ z,
+                               double *__restrict__ Y) {
+    int64_t n = (int64_t)np * 9;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * N) return;
+    int p = (int)(i / n);
+    int rem = (int)(i - (int64_t)p * n);
+    int c = rem / 9, k = rem - c * 9;
+    double s = group[c] == p ? dU[rem] * z[rem] : 0.0;
+    int64_t key = (int64_t)c * N + p;
+    for (int j = ptr[key]; j < ptr[key + 1]; ++j) s += partial[(int64_t)idx[j] * 9 + k];
+    Y[i] = s;
+}
+
+void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s) {
+    if (a.n_chunks > 0) {
+        size_t esz = a.precision == 0 ? sizeof(double) : sizeof(float);
+        size_t lds = (size_t)(a.max_out * 9 + 6 * kTile) * esz;
+        switch (a.precision) {
+            case 0: hipLaunchKernelGGL((k_schur_multi<0, double>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;
+            case 1: hipLaunchKernelGGL((k_schur_multi<1, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;
+            default: hipLaunchKernelGGL((k_schur_multi<2, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;
+        }
+    }
+    int64_t total = (int64_t)a.np * 9 * a.N;
+    hipLaunchKernelGGL(k_reduce_multi, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.np, a.N, a.cg_ptr,
+                       a.cg_idx, a.partial, a.dU, a.group, z, Y);
+}
+
+// ---------------------------------------------------------------- eq. (16)
+
+// dx_l = -V^-1 (b_l + W^T dx_p) for every landmark; the first observation of a
+// landmark inside its tile writes the result.
+__global__ __launch_bounds__(64) void k_backsub(const double *__restrict__ J64, const uint32_t *__restrict__ meta,
+                                                const int32_t *__restrict__ tile_lmk_base,
+                                                const int32_t *__restrict__ chunk_tile,
+                                                const int32_t *__restrict__ chunk_part,
+                                                const int32_t *__restrict__ part_cam, int max_slots,
+                                                const double *__restrict__ vinv, const double *__restrict__ bl,
+                                                const int32_t *__restrict__ lmk_order,
+                                                const double *__restrict__ dxp, double *__restrict__ dxl) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *vloc = reinterpret_cast<double *>(smem);
+    double *gloc = vloc + max_slots * 9;
+    const int chunk = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int pb = chunk_part[chunk];
+    const int ns = chunk_part[chunk + 1] - pb;
+    for (int i = lane; i < ns * 9; i += kTile) vloc[i] = dxp[(int64_t)part_cam[pb + i / 9] * 9 + i % 9];
+    __syncthreads();
+    for (int t = chunk_tile[chunk]; t < chunk_tile[chunk + 1]; ++t) {
+        double J[24];
+        Loader<0>::load(J64, t, lane, J);
+        const uint32_t mt = meta[(int64_t)t * kTile + lane];
+        const bool valid = mt != kPad;
+        const int slot = valid ? (int)(mt & 0xFFFFu) : 0;
+        const int ll = valid ? (int)((mt >> 16) & 63u) : 0;
+        const uint32_t prev = lane > 0 ? meta[(int64_t)t * kTile + lane - 1] : kPad;
+        const bool first = valid && (prev == kPad || ((prev >> 16) & 63u) != (uint32_t)ll);
+        double e0 = 0, e1 = 0;
+        for (int k = 0; k < 9; ++k) {
+            e0 += J[k] * vloc[slot * 9 + k];
+            e1 += J[9 + k] * vloc[slot * 9 + k];
+        }
+        gloc[lane * 3 + 0] = 0;
+        gloc[lane * 3 + 1] = 0;
+        gloc[lane * 3 + 2] = 0;
+        __syncthreads();
+        if (valid)
+            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], J[18 + k] * e0 + J[21 + k] * e1);
+        __syncthreads();
+        if (first) {
+            const int64_t ls = tile_lmk_base[t] + ll;
+            const double *vi = vinv + ls * 6;
+            const double g0 = gloc[ll * 3] + bl[ls * 3], g1 = gloc[ll * 3 + 1] + bl[ls * 3 + 1],
+                         g2 = gloc[ll * 3 + 2] + bl[ls * 3 + 2];
+            double *o = dxl + (int64_t)lmk_order[ls] * 3;
+            o[0] = -(vi[0] * g0 + vi[1] * g1 + vi[2] * g2);
+            o[1] = -(vi[1] * g0 + vi[3] * g1 + vi[4] * g2);
+            o[2] = -(vi[2] * g0 + vi[4] * g1 + vi[5] * g2);
+        }
+        __syncthreads();
+    }
+}
+
+void launch_back_substitute(const double *J64, const uint32_t *meta, const int32_t *tile_lmk_base,
+                            const int32_t *chunk_tile, const int32_t *chunk_part, const int32_t *part_cam,
+                            int n_chunks, int max_slots, const double *vinv, const double *bl,
+                            const int32_t *lmk_order, const double *dxp, double *dxl, hipStream_t s) {
+    if (n_chunks <= 0) return;
+    size_t lds = (size_t)(max_slots * 9 + 3 * kTile) * sizeof(double);
+    hipLaunchKernelGGL(k_backsub, dim3(n_chunks), dim3(kTile), lds, s, J64, meta, tile_lmk_base, chunk_tile,
+                       chunk_part, part_cam, max_slots, vinv, bl, lmk_order, dxp, dxl);
+}
+
+}  // namespace ba

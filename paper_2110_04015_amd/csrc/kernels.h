@@ -1,0 +1,149 @@
+// Device helpers and kernel launchers of the reduced-camera-system library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace ba {
+
+// slots of the device scalar array of the solvers
+enum {
+    SC_RR0 = 0,      // |r_0|^2
+    SC_RR = 1,       // |r_i|^2
+    SC_DELTA = 2,    // Delta_i (PCG)
+    SC_GAMMA = 3,    // gamma_i (PCG)
+    SC_ALPHA = 4,    // alpha_i (PCG)
+    SC_PHI = 5,      // Phi_i (PCG)
+    SC_BETA = 6,     // beta_i (PCG)
+    SC_BREAK = 7,    // 1 when P^T S P <= 0 (PCG)
+    SC_T = 8,        // t_i of the tau-test (MCG)
+    SC_RHO = 9,      // r^T D^-1 r (MCG)
+    SC_RANK = 10,    // numerical rank of Delta_i (MCG)
+    SC_COUNT = 16
+};
+
+// device status word bits
+constexpr int32_t kStatusNonfinite = 1;
+constexpr int32_t kStatusNotSpdLandmark = 2;
+constexpr int32_t kStatusNotSpdCamera = 4;
+
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)0x7FC0;   // NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);                                   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__host__ __device__ inline float bf16_to_f32(uint32_t h) {
+    uint32_t u = h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// ---- build (k_build.hip)
+void launch_check_finite(const double *a, int64_t count, int32_t *status, hipStream_t s);
+void launch_pack(const int64_t *slot_obs, int64_t nslots, const double *Jp, const double *Jl, double *J64,
+                 float *J32, uint16_t *J16, hipStream_t s);
+void launch_convert(const double *J64, int64_t nslots, float *J32, uint16_t *J16, hipStream_t s);
+void launch_landmarks(int nl, const int64_t *first_slot, const int32_t *count, const int64_t *slot_obs,
+                      const double *Jl, const double *r, double lambda, double *vinv, double *bl, double *h0,
+                      int32_t *status, hipStream_t s);
+void launch_cameras(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const int32_t *obs_lm,
+                    const int32_t *lmk_store, const double *Jp, const double *Jl, const double *r,
+                    const double *vinv, const double *h0, double lambda, double *dU, double *Dblk,
+                    double *Dchol, double *bt, int32_t *status, hipStream_t s);
+
+// ---- Schur products (k_schur.hip)
+struct SchurArgs {
+    const void *J;                 // tile stream in the chosen precision
+    int precision;                 // 0 FP64, 1 FP32, 2 BF16
+    const uint32_t *meta;
+    const int32_t *tile_lmk_base;
+    const double *vinv;
+    const int32_t *chunk_tile, *chunk_part, *part_cam;
+    int n_chunks;
+    int max_slots;
+    double *partial;
+    const int32_t *cam_part_ptr, *cam_part_idx;
+    const double *dU;
+    int np;
+};
+// y = S v (partials then the camera reduction)
+void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s);
+void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s);
+void launch_schur_reduce(const SchurArgs &a, const double *v, double *y, hipStream_t s);
+
+struct MultiArgs {
+    const void *J;
+    int precision;
+    const uint32_t *meta;          // for the landmark index inside the tile
+    const uint32_t *mmeta;
+    const int32_t *slot_cam;
+    const uint8_t *pair_ll;
+    const uint32_t *tile_oidx;
+    const uint16_t *oidx;
+    const uint16_t *slot_ooff;
+    const int32_t *tile_lmk_base;
+    const double *vinv;
+    const int32_t *chunk_tile, *chunk_part;
+    int n_chunks, max_out;
+    double *partial;
+    const int32_t *cg_ptr, *cg_idx;
+    const double *dU;
+    const int32_t *group;
+    int np, N;
+};
+// Y[p] = S (z restricted to subset p), Y column-major [N][n]
+void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s);
+
+// dx_l = -V^-1 (b_l + W^T dx_p), written in original landmark order
+void launch_back_substitute(const double *J64, const uint32_t *meta, const int32_t *tile_lmk_base,
+                            const int32_t *chunk_tile, const int32_t *chunk_part, const int32_t *part_cam,
+                            int n_chunks, int max_slots, const double *vinv, const double *bl,
+                            const int32_t *lmk_order, const double *dxp, double *dxl, hipStream_t s);
+
+// ---- vectors, reductions, small dense (k_vec.hip)
+constexpr int kRedBlocks = 120;    // fixed grid of the deterministic reductions
+
+void launch_precond(int np, const double *Dchol, const double *r, double *z, hipStream_t s);
+// partial dots: out[b * 2 + d] over blocks b < kRedBlocks
+void launch_dot2(int64_t n, const double *a0, const double *b0, const double *a1, const double *b1,
+                 double *partials, hipStream_t s);
+// finalize: out[d] = sum_b partials[b * nd + d] (fixed order), d < nd
+void launch_finalize(const double *partials, int nd, double *out, hipStream_t s);
+
+// PCG steps (scalars in sc[]: see k_vec.hip for the slot map)
+void launch_pcg_init(int64_t n, const double *bt, const double *Sx, double *r, double *partials, hipStream_t s);
+void launch_pcg_update_xr(int64_t n, const double *partials_dq, double *sc, double *x, double *r,
+                          const double *P, const double *Q, double *partials_rr, hipStream_t s);
+void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const double *Q, double *z,
+                            double *partials, hipStream_t s);
+void launch_pcg_update_p(int64_t n, const double *partials_phi, double *sc, const double *z, double *P,
+                         hipStream_t s);
+void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s);
+
+// MCG steps
+void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
+                 hipStream_t s);
+void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, double *gamma, double *alpha,
+                       double *sc, hipStream_t s);
+void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, const double *alpha, double *x,
+                          double *r, double *partials, hipStream_t s);
+void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials,
+                        hipStream_t s);
+void launch_tau(int k, const double *partials_rho, const double *gamma, const double *alpha, double *sc,
+                hipStream_t s);
+void launch_phi(int64_t n, int h, const double *Qh, const double *z, int multi, int N, int gs,
+                double *Phi, hipStream_t s);
+void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int64_t *blk_dp, const double *Dp,
+                 const double *Phi, int kn, double *beta, hipStream_t s);
+void launch_update_pq(int64_t n, int h, int kn, const double *Ph, const double *Qh, const double *beta,
+                      const double *z, int multi, int gs, int N, const double *Y, double *Pn, double *Qn,
+                      hipStream_t s);
+void launch_pinv_sym(int k, const double *A, double *Ap, int32_t *rank, hipStream_t s);
+
+}  // namespace ba
