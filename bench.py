@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--matvec-only", type=int, default=0, metavar="K",
+                    help="profiling mode: K FP64 S v products and one 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -85,6 +87,28 @@ def main():
     build_s = time.time() - t
     info = g.info()
     log(f"built system in {build_s:.2f} s: {info}")
+
+    if args.matvec_only:
+        v = torch.randn(g.n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(v)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.matvec_only):
+            g.matvec(v, out=y)
+        torch.cuda.synchronize()
+        t_mv = (time.perf_counter() - t1) / args.matvec_only
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t_cp = time.perf_counter() - t1
+        print(json.dumps({"mode": "matvec-only", "matvecs": args.matvec_only, "ms_per_matvec": 1e3 * t_mv,
+                          "copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                          "copy_ms": 1e3 * t_cp, "info": info}), flush=True)
+        g.close()
+        return
 
     def step(precision=args.precision, solver=args.solver, N=args.N, tau=args.tau):
         if solver == "pcg":
