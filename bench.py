@@ -155,15 +155,18 @@ def main():
         for name, kw in [("pcg_fp64", dict(solver="pcg", precision="fp64")),
                          ("mcg_fp64_N4", dict(solver="mcg", N=4, precision="fp64")),
                          ("mcg_fp64_N16", dict(solver="mcg", N=16, precision="fp64")),
-                         ("mcg_fp64_N64", dict(solver="mcg", N=64, precision="fp64"))]:
+                         ("mcg_fp64_N64", dict(solver="mcg", N=64, precision="fp64")),
+                         ("pcg_fp32_refined", dict(solver="pcg", precision="fp32")),
+                         ("pcg_bf16_refined", dict(solver="pcg", precision="bf16")),
+                         ("mcg_fp32_refined_N16", dict(solver="mcg", N=16, precision="fp32"))]:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             x, s2 = step(**kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
             variants[name] = {"solves_per_s": round(1.0 / dt, 3), "iterations": s2.iterations,
-                              "multi_steps": s2.multi_steps, "rel_res_true": s2.rel_res_true,
-                              "status": s2.status}
+                              "multi_steps": s2.multi_steps, "refinement_steps": s2.refinement_steps,
+                              "rel_res_true": s2.rel_res_true, "status": s2.status}
             log(f"variant {name}: {1.0 / dt:.2f} solves/s, {s2.iterations} iterations, "
                 f"residual {s2.rel_res_true:.2e}")
 

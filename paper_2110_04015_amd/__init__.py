@@ -224,10 +224,13 @@ class System:
                "ba_back_substitute")
         return out
 
-    def pcg(self, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False, out=None):
+    def pcg(self, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False, out=None,
+            inner_eps=1e-3, max_outer=20, max_inner=200):
+        """Algorithm 1.  precision "fp32"/"bf16": FP64 iterative refinement around inner
+        solves with reduced-precision S products (inner_eps, max_outer, max_inner)."""
         torch = _torch()
         x = out if out is not None else self._new(self.n)
-        o = _opts(eps, max_iter, precision)
+        o = _opts(eps, max_iter, precision, inner_eps=inner_eps, max_outer=max_outer, max_inner=max_inner)
         st = _lib.SolveStats()
         tr = _Trace(max(int(max_iter), 1)) if trace else None
         if tr:
@@ -238,10 +241,12 @@ class System:
         return x, _stats(st, tr)
 
     def mcg(self, N, tau, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False,
-            max_history_cols=0, out=None):
+            max_history_cols=0, out=None, inner_eps=1e-3, max_outer=20, max_inner=200):
+        """Algorithm 2 with N subsets and threshold tau (mixed precision as in pcg)."""
         torch = _torch()
         x = out if out is not None else self._new(self.n)
-        o = _opts(eps, max_iter, precision, max_history_cols=max_history_cols)
+        o = _opts(eps, max_iter, precision, max_history_cols=max_history_cols, inner_eps=inner_eps,
+                  max_outer=max_outer, max_inner=max_inner)
         st = _lib.SolveStats()
         tr = _Trace(max(int(max_iter), 1)) if trace else None
         if tr:

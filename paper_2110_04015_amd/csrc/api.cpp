@@ -21,6 +21,8 @@ namespace {
 
 thread_local std::string g_err;
 
+constexpr int64_t kHistScratch = 4 << 20;   // doubles of split-K partials of the history products (32 MiB)
+
 ba_status fail(ba_status st, const std::string &msg) {
     g_err = msg;
     return st;
@@ -70,6 +72,7 @@ void free_multi(DevMulti &m) {
     dfree(m.chunk_part);
     dfree(m.cg_ptr);
     dfree(m.cg_idx);
+    dfree(m.part_dst);
     dfree(m.partial);
     dfree(m.group);
     m = DevMulti();
@@ -87,6 +90,7 @@ void free_all(ba_system *s) {
     dfree(s->part_cam);
     dfree(s->cam_part_ptr);
     dfree(s->cam_part_idx);
+    dfree(s->part_dst);
     dfree(s->partial);
     dfree(s->vinv);
     dfree(s->bl);
@@ -102,6 +106,8 @@ void free_all(ba_system *s) {
     dfree(s->red);
     dfree(s->hist);
     dfree(s->small);
+    dfree(s->hscratch);
+    dfree(s->refine_buf);
     if (s->host_pinned) (void)hipHostFree(s->host_pinned);
     s->host_pinned = nullptr;
     free_multi(s->multi);
@@ -119,11 +125,11 @@ SchurArgs schur_args(ba_system *s, int precision) {
     a.chunk_tile = s->chunk_tile;
     a.chunk_part = s->chunk_part;
     a.part_cam = s->part_cam;
+    a.part_dst = s->part_dst;
     a.n_chunks = s->plan.n_chunks;
     a.max_slots = s->plan.max_slots;
     a.partial = s->partial;
     a.cam_part_ptr = s->cam_part_ptr;
-    a.cam_part_idx = s->cam_part_idx;
     a.dU = s->dU;
     a.np = s->np;
     return a;
@@ -208,6 +214,7 @@ ba_status ensure_multi(ba_system *s, int N) {
     if ((st = upload(&m.chunk_part, mp.chunk_part, q)) != BA_OK) return st;
     if ((st = upload(&m.cg_ptr, mp.cg_ptr, q)) != BA_OK) return st;
     if ((st = upload(&m.cg_idx, mp.cg_idx, q)) != BA_OK) return st;
+    if ((st = upload(&m.part_dst, mp.part_dst, q)) != BA_OK) return st;
     std::vector<int32_t> grp((size_t)s->np);
     partition_groups(s->np, N, grp.data());
     if ((st = upload(&m.group, grp, q)) != BA_OK) return st;
@@ -238,8 +245,8 @@ MultiArgs multi_args(ba_system *s, int precision) {
     a.n_chunks = s->multi.n_chunks;
     a.max_out = s->multi.max_out;
     a.partial = s->multi.partial;
+    a.part_dst = s->multi.part_dst;
     a.cg_ptr = s->multi.cg_ptr;
-    a.cg_idx = s->multi.cg_idx;
     a.dU = s->dU;
     a.group = s->multi.group;
     a.np = s->np;
@@ -436,6 +443,7 @@ ba_status ba_build_system(const ba_problem_desc *d, const ba_build_opts *opts, v
     if ((st = upload(&s->part_cam, P.part_cam, q)) != BA_OK) return bail2(st);
     if ((st = upload(&s->cam_part_ptr, P.cam_part_ptr, q)) != BA_OK) return bail2(st);
     if ((st = upload(&s->cam_part_idx, P.cam_part_idx, q)) != BA_OK) return bail2(st);
+    if ((st = upload(&s->part_dst, P.part_dst, q)) != BA_OK) return bail2(st);
     if ((st = upload(&s->lmk_order, P.lmk_order, q)) != BA_OK) return bail2(st);
     if ((st = upload(&s->lmk_first_slot, P.lmk_first_slot, q)) != BA_OK) return bail2(st);
     if ((st = upload(&s->lmk_count, P.lmk_count, q)) != BA_OK) return bail2(st);
@@ -579,13 +587,10 @@ ba_status ba_pinv_sym(int32_t k, const double *A, double *Ap, int32_t *rank, voi
 
 // ------------------------------------------------------------------ Algorithm 1
 
-ba_status ba_pcg_solve(ba_system *s, const double *x0, double *x, const ba_solve_opts *opts_in,
-                       ba_solve_stats *stats) {
-    if (!s || !x) return fail(BA_ERR_INVALID_ARG, "NULL argument");
-    ba_solve_opts opts;
-    if (opts_in) opts = *opts_in;
-    else fill_default_opts(&opts);
-    if (!(opts.eps >= 0.0) || opts.max_iter < 0) return fail(BA_ERR_INVALID_ARG, "eps >= 0 and max_iter >= 0 required");
+// Algorithm 1 on S x = -bt (bt: device [n]).  report_true: also recompute the true
+// residual of the system's own b~ into stats.
+static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, const double *x0, double *x,
+                          const ba_solve_opts &opts, ba_solve_stats *stats) {
     const int prec = opts.precision;
     ba_status st = ensure_precision(s, prec);
     if (st != BA_OK) return st;
@@ -600,10 +605,10 @@ ba_status ba_pcg_solve(ba_system *s, const double *x0, double *x, const ba_solve
     if (x0) {
         HIPCHK(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
         matvec(s, schur_args(s, prec), x, tmp);
-        launch_pcg_init(n, s->bt, tmp, r, prr, q);
+        launch_pcg_init(n, bt, tmp, r, prr, q);
     } else {
         HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), q));
-        launch_pcg_init(n, s->bt, nullptr, r, prr, q);
+        launch_pcg_init(n, bt, nullptr, r, prr, q);
     }
     launch_pcg_rr(prr, sc, q);
     HIPCHK(hipGetLastError());
@@ -613,31 +618,60 @@ ba_status ba_pcg_solve(ba_system *s, const double *x0, double *x, const ba_solve
     double rr = rr0;
     int it = 0;
     ba_status result = BA_OK;
-    if (rr0 > 0.0) {
+    if (rr0 > 0.0 && opts.max_iter > 0) {
+        // Iterations are enqueued in batches; the stop test runs on the device and
+        // turns the remaining kernels of the batch into no-ops, so the host waits
+        // only once per batch.
+        double *trace_dev = nullptr;
+        const bool want_trace = stats && stats->trace_res && stats->trace_cap > 0;
+        if (want_trace && (st = dalloc(&trace_dev, (size_t)opts.max_iter)) != BA_OK) return st;
         launch_precond(s->np, s->Dchol, r, P, q);
-        result = BA_MAXITER;
-        const SchurArgs sa = schur_args(s, prec);
-        for (it = 0; it < opts.max_iter;) {
-            matvec(s, sa, P, Q);                                         // Q_i = S P_i
-            launch_dot2(n, Q, P, P, r, pdq, q);                          // Delta_i, gamma_i
-            launch_pcg_update_xr(n, pdq, sc, x, r, P, Q, prr, q);        // alpha_i, x, r
-            launch_pcg_rr(prr, sc, q);
-            HIPCHK(hipGetLastError());
-            if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
-            if (h[SC_BREAK] != 0.0) {
-                result = BA_ERR_BREAKDOWN;
-                g_err = "PCG breakdown: P^T S P <= 0";
-                break;
+        SchurArgs sa = schur_args(s, prec);
+        sa.done = sc + SC_DONE;
+        int enqueued = 0, batch = 4;
+        const size_t prof_mark = s->prof_used;
+        double rr_prev = rr0;
+        for (;;) {
+            const int nb = std::min(batch, opts.max_iter - enqueued);
+            for (int b = 0; b < nb; ++b) {
+                matvec(s, sa, P, Q);                                         // Q_i = S P_i
+                launch_dot2(n, Q, P, P, r, pdq, sc + SC_DONE, q);            // Delta_i, gamma_i
+                launch_pcg_update_xr(n, pdq, sc, x, r, P, Q, prr, q);        // alpha_i, x_{i+1}, r_{i+1}
+                launch_pcg_step_end(prr, sc, opts.eps, opts.max_iter, trace_dev, q);
+                launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q);  // Z_{i+1}, Phi_i
+                launch_pcg_update_p(n, pphi, sc, z, P, q);                   // beta_i, P_{i+1}
             }
-            ++it;
-            rr = h[SC_RR];
-            if (stats && stats->trace_res && it - 1 < stats->trace_cap) stats->trace_res[it - 1] = std::sqrt(rr / rr0);
-            if (std::sqrt(rr) < opts.eps * std::sqrt(rr0)) {
-                result = BA_OK;
-                break;
+            enqueued += nb;
+            if (hipGetLastError() != hipSuccess) {
+                dfree(trace_dev);
+                return fail(BA_ERR_HIP, "PCG kernel launch failed");
             }
-            launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, q);  // Z_{i+1}, Phi_i
-            launch_pcg_update_p(n, pphi, sc, z, P, q);                   // beta_i, P_{i+1}
+            if ((st = read_scalars(s, sc, h)) != BA_OK) {
+                dfree(trace_dev);
+                return st;
+            }
+            if (h[SC_DONE] != 0.0 || enqueued >= opts.max_iter) break;
+            // next batch: the iterations still needed at the observed rate of decrease
+            const double rate = h[SC_RR] > 0.0 && rr_prev > 0.0 ? std::pow(h[SC_RR] / rr_prev, 1.0 / nb) : 1.0;
+            const double goal = opts.eps * opts.eps * rr0;
+            int need = 4;
+            if (rate < 1.0 && h[SC_RR] > goal) need = (int)std::ceil(std::log(goal / h[SC_RR]) / std::log(rate));
+            batch = std::max(1, std::min(need, 32));
+            rr_prev = h[SC_RR];
+        }
+        it = (int)h[SC_ITER];
+        // event pairs of launches after the stop test (no-ops) are not kernel work
+        if (s->profiling && s->prof_used > prof_mark + 2 * (size_t)it) s->prof_used = prof_mark + 2 * (size_t)it;
+        rr = h[SC_RR];
+        result = h[SC_DONE] != 0.0 ? (ba_status)(int)h[SC_STATUS] : BA_MAXITER;
+        if (result == BA_ERR_BREAKDOWN) g_err = "PCG breakdown: P^T S P <= 0";
+        if (want_trace && it > 0) {
+            hipError_t e = hipMemcpy(stats->trace_res, trace_dev, sizeof(double) * (size_t)std::min(it, stats->trace_cap),
+                                     hipMemcpyDeviceToHost);
+            dfree(trace_dev);
+            if (e != hipSuccess) return fail(BA_ERR_HIP, "trace copy failed");
+        } else {
+            dfree(trace_dev);
         }
     }
     HIPCHK(hipStreamSynchronize(q));
@@ -650,8 +684,8 @@ ba_status ba_pcg_solve(ba_system *s, const double *x0, double *x, const ba_solve
         stats->status = result;
         stats->rel_res_recursive = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
         stats->t_solve_ms = ms;
-        double tr = 0.0;
-        if ((st = true_rel_residual(s, x, tmp, pdq, sc, &tr)) != BA_OK) return st;
+        double tr = stats->rel_res_recursive;
+        if (report_true && (st = true_rel_residual(s, x, tmp, pdq, sc, &tr)) != BA_OK) return st;
         stats->rel_res_true = tr;
     }
     return result;
@@ -659,16 +693,9 @@ ba_status ba_pcg_solve(ba_system *s, const double *x0, double *x, const ba_solve
 
 // ------------------------------------------------------------------ Algorithm 2
 
-ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, double *x,
-                       const ba_solve_opts *opts_in, ba_solve_stats *stats) {
-    if (!s || !x) return fail(BA_ERR_INVALID_ARG, "NULL argument");
-    if (N < 1 || N > s->np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, n_cams]");
-    if (N > 64) return fail(BA_ERR_UNSUPPORTED, "at most 64 subsets are supported");
-    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(BA_ERR_INVALID_ARG, "tau must be finite and >= 0");
-    ba_solve_opts opts;
-    if (opts_in) opts = *opts_in;
-    else fill_default_opts(&opts);
-    if (!(opts.eps >= 0.0) || opts.max_iter < 0) return fail(BA_ERR_INVALID_ARG, "eps >= 0 and max_iter >= 0 required");
+// Algorithm 2 on S x = -bt (arguments as pcg_core).
+static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int N, double tau, const double *x0,
+                          double *x, const ba_solve_opts &opts, ba_solve_stats *stats) {
     const int prec = opts.precision;
     ba_status st = ensure_precision(s, prec);
     if (st != BA_OK) return st;
@@ -699,6 +726,7 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
     int64_t *blk_dp = reinterpret_cast<int64_t *>(blk_k + hc + 2);
     if ((st = ensure_vec(s, (size_t)n * 4 + SC_COUNT)) != BA_OK) return st;
     if ((st = ensure_red(s, (size_t)kRedBlocks * (64 * 64 + 64))) != BA_OK) return st;
+    if (!s->hscratch && (st = dalloc(&s->hscratch, (size_t)kHistScratch)) != BA_OK) return st;
     double *r = s->vec, *z = r + n, *tmp = z + n, *sc = tmp + 2 * n;
     double *red = s->red;
     const int gs = s->np / N;
@@ -710,10 +738,10 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
     if (x0) {
         HIPCHK(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
         matvec(s, sa, x, tmp);
-        launch_pcg_init(n, s->bt, tmp, r, red, q);
+        launch_pcg_init(n, bt, tmp, r, red, q);
     } else {
         HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), q));
-        launch_pcg_init(n, s->bt, nullptr, r, red, q);
+        launch_pcg_init(n, bt, nullptr, r, red, q);
     }
     launch_pcg_rr(red, sc, q);
     HIPCHK(hipGetLastError());
@@ -730,9 +758,7 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
         matvec(s, sa, Ph, Qh);
         std::vector<int32_t> hoff{0}, hk{1};
         std::vector<int64_t> hdp{0};
-        HIPCHK(hipMemcpyAsync(blk_off, hoff.data(), 4, hipMemcpyHostToDevice, q));
-        HIPCHK(hipMemcpyAsync(blk_k, hk.data(), 4, hipMemcpyHostToDevice, q));
-        HIPCHK(hipMemcpyAsync(blk_dp, hdp.data(), 8, hipMemcpyHostToDevice, q));
+        launch_set_block(blk_off, blk_k, blk_dp, 0, 0, 1, 0, q);
         int64_t dp_used = 1;
         hcols = 1;
         result = BA_MAXITER;
@@ -746,6 +772,10 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
             // x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i
             launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
             launch_pcg_rr(red, sc, q);
+            // tau-test scalars, computed before the single read-back of the iteration:
+            // t_i = gamma_i^T alpha_i / (r_{i+1}^T D^-1 r_{i+1})
+            launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q);
+            launch_tau(k, red + kRedBlocks, gamma, alpha, sc, q);
             HIPCHK(hipGetLastError());
             if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
             if (h[SC_RANK] == 0.0) {
@@ -765,11 +795,6 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
                 result = BA_OK;
                 break;
             }
-            // tau-test: t_i = gamma_i^T alpha_i / (r^T D^-1 r)
-            launch_precond_rho(s->np, s->Dchol, r, z, red, q);
-            launch_tau(k, red, gamma, alpha, sc, q);
-            HIPCHK(hipGetLastError());
-            if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
             const double t_i = h[SC_T];
             const bool multi = N > 1 && t_i < tau;
             const int kn = multi ? N : 1;
@@ -788,16 +813,13 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
             launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, kn, beta, q);
             // P_{i+1} = Z - sum P_j beta ; multidirectional: Q_{i+1} = S Z - sum Q_j beta (eq. (19))
             launch_update_pq(n, (int)hcols, kn, Ph, Qh, beta, z, multi ? 1 : 0, gs, N, multi ? Qn : nullptr, Pn,
-                             multi ? Qn : nullptr, q);
+                             multi ? Qn : nullptr, s->hscratch, kHistScratch, q);
             if (!multi) matvec(s, sa, Pn, Qn);                           // Q_{i+1} = S P_{i+1}
             HIPCHK(hipGetLastError());
             hoff.push_back((int32_t)hcols);
             hk.push_back(kn);
             hdp.push_back(dp_used);
-            HIPCHK(hipMemcpyAsync(blk_off + nb, &hoff[nb], 4, hipMemcpyHostToDevice, q));
-            HIPCHK(hipMemcpyAsync(blk_k + nb, &hk[nb], 4, hipMemcpyHostToDevice, q));
-            HIPCHK(hipMemcpyAsync(blk_dp + nb, &hdp[nb], 8, hipMemcpyHostToDevice, q));
-            HIPCHK(hipStreamSynchronize(q));   // the block entries above are host memory
+            launch_set_block(blk_off, blk_k, blk_dp, nb, hoff[nb], hk[nb], hdp[nb], q);
             dp_used += (int64_t)kn * kn;
             hcols += kn;
             multi_steps += multi;
@@ -813,11 +835,120 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
         stats->status = result;
         stats->rel_res_recursive = rr0 > 0.0 ? std::sqrt(rr / rr0) : 0.0;
         stats->t_solve_ms = ms;
-        double tr = 0.0;
-        if ((st = true_rel_residual(s, x, tmp, red, sc, &tr)) != BA_OK) return st;
+        double tr = stats->rel_res_recursive;
+        if (report_true && (st = true_rel_residual(s, x, tmp, red, sc, &tr)) != BA_OK) return st;
         stats->rel_res_true = tr;
     }
     return result;
+}
+
+// Mixed precision: FP64 iterative refinement around inner solves whose S products
+// use the FP32 or BF16 Jacobian stream (all vectors and Krylov scalars stay FP64).
+//   r = -b~ - S x (FP64 product);  stop when |r| < eps |b~|;
+//   inner solve S d = r to inner_eps |r| (at most max_inner iterations);  x += d.
+static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const double *x0, double *x,
+                        const ba_solve_opts &opts, ba_solve_stats *stats) {
+    const int64_t n = (int64_t)s->np * 9;
+    hipStream_t q = s->stream;
+    ba_status st = ensure_precision(s, opts.precision);
+    if (st != BA_OK) return st;
+    if (!s->refine_buf && (st = dalloc(&s->refine_buf, (size_t)n * 4 + 8)) != BA_OK) return st;
+    double *r = s->refine_buf, *btp = r + n, *d = btp + n, *tmp = d + n;
+    auto t0 = std::chrono::steady_clock::now();
+    if (x0) HIPCHK(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
+    else HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), q));
+    ba_solve_opts in = opts;
+    in.eps = opts.inner_eps;
+    in.max_iter = opts.max_inner;
+    int total_it = 0, total_multi = 0, outer = 0;
+    double rel = 0.0, prev = INFINITY;
+    ba_status result = BA_MAXITER;
+    const int trace_cap = stats ? stats->trace_cap : 0;
+    for (;;) {
+        // outer residual in FP64: r = -b~ - S x, btp = -r (so that S d = r reads S d = -btp)
+        rel = 0.0;
+        if ((st = ensure_red(s, (size_t)kRedBlocks * 4)) != BA_OK) return st;
+        matvec(s, schur_args(s, 0), x, tmp);
+        launch_residual_refine(n, s->bt, tmp, r, btp, s->red, q);
+        double *sc2 = tmp + n;   // 8 scratch doubles after the four work vectors
+        launch_finalize(s->red, 2, sc2, q);
+        HIPCHK(hipGetLastError());
+        double hh[2];
+        HIPCHK(hipMemcpyAsync(hh, sc2, sizeof hh, hipMemcpyDeviceToHost, q));
+        HIPCHK(hipStreamSynchronize(q));
+        rel = hh[1] > 0.0 ? std::sqrt(hh[0] / hh[1]) : 0.0;
+        if (rel < opts.eps || hh[0] == 0.0) {
+            result = BA_OK;
+            break;
+        }
+        if (outer >= opts.max_outer || total_it >= opts.max_iter || !(rel < prev)) break;
+        prev = rel;
+        ba_solve_stats is;
+        memset(&is, 0, sizeof is);
+        if (stats && stats->trace_res && total_it < trace_cap) {
+            is.trace_cap = trace_cap - total_it;
+            is.trace_res = stats->trace_res + total_it;
+            is.trace_t = stats->trace_t ? stats->trace_t + total_it : nullptr;
+            is.trace_k = stats->trace_k ? stats->trace_k + total_it : nullptr;
+        }
+        in.max_iter = std::min(opts.max_inner, opts.max_iter - total_it);
+        ba_status ist = use_mcg ? mcg_core(s, btp, false, N, tau, nullptr, d, in, &is)
+                                : pcg_core(s, btp, false, nullptr, d, in, &is);
+        if (ist < 0 && ist != BA_ERR_BREAKDOWN) return ist;
+        total_it += is.iterations;
+        total_multi += is.multi_steps;
+        ++outer;
+        launch_axpy(n, 1.0, d, x, q);
+        HIPCHK(hipGetLastError());
+        if (is.iterations == 0) break;
+    }
+    HIPCHK(hipStreamSynchronize(q));
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) {
+        stats->iterations = total_it;
+        stats->multi_steps = total_multi;
+        stats->history_cols = 0;
+        stats->refinement_steps = outer;
+        stats->status = result;
+        stats->rel_res_recursive = rel;
+        stats->rel_res_true = rel;
+        stats->t_solve_ms = ms;
+    }
+    return result;
+}
+
+static ba_status check_opts(const ba_solve_opts *opts_in, ba_solve_opts *opts) {
+    if (opts_in) *opts = *opts_in;
+    else fill_default_opts(opts);
+    if (!(opts->eps >= 0.0) || opts->max_iter < 0) return fail(BA_ERR_INVALID_ARG, "eps >= 0 and max_iter >= 0 required");
+    if (opts->precision < 0 || opts->precision > 2) return fail(BA_ERR_INVALID_ARG, "precision must be 0, 1 or 2");
+    if (opts->precision != 0 && (!(opts->inner_eps > 0.0) || opts->inner_eps >= 1.0 || opts->max_outer < 1 ||
+                                 opts->max_inner < 1))
+        return fail(BA_ERR_INVALID_ARG, "mixed precision needs 0 < inner_eps < 1, max_outer >= 1, max_inner >= 1");
+    return BA_OK;
+}
+
+ba_status ba_pcg_solve(ba_system *s, const double *x0, double *x, const ba_solve_opts *opts_in,
+                       ba_solve_stats *stats) {
+    if (!s || !x) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    ba_solve_opts opts;
+    ba_status st = check_opts(opts_in, &opts);
+    if (st != BA_OK) return st;
+    if (opts.precision != 0) return refine(s, false, 0, 0.0, x0, x, opts, stats);
+    return pcg_core(s, s->bt, true, x0, x, opts, stats);
+}
+
+ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, double *x,
+                       const ba_solve_opts *opts_in, ba_solve_stats *stats) {
+    if (!s || !x) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (N < 1 || N > s->np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, n_cams]");
+    if (N > 64) return fail(BA_ERR_UNSUPPORTED, "at most 64 subsets are supported");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(BA_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    ba_solve_opts opts;
+    ba_status st = check_opts(opts_in, &opts);
+    if (st != BA_OK) return st;
+    if (opts.precision != 0) return refine(s, true, N, tau, x0, x, opts, stats);
+    return mcg_core(s, s->bt, true, N, tau, x0, x, opts, stats);
 }
 
 }  // extern "C"

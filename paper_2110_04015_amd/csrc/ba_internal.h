@@ -50,6 +50,7 @@ struct HostPlan {
     std::vector<int32_t> part_cam;        // partial row -> camera
     std::vector<int32_t> cam_part_ptr;    // [np + 1]
     std::vector<int32_t> cam_part_idx;    // partial rows, camera-major, ascending
+    std::vector<int32_t> part_dst;        // partial row -> its position in camera-major order
     std::vector<int64_t> cam_obs_ptr;     // [np + 1]
     std::vector<int64_t> cam_obs;         // observation indices, camera-major
     std::vector<int32_t> obs_cam;         // host copy of the camera of each observation
@@ -71,6 +72,7 @@ struct HostMultiPlan {
     std::vector<int32_t> chunk_part;      // [n_chunks + 1]
     std::vector<int32_t> cg_ptr;          // [np * N + 1] partial rows of (camera, subset)
     std::vector<int32_t> cg_idx;
+    std::vector<int32_t> part_dst;        // out-pair row -> position in (camera, subset)-major order
 };
 
 struct DevMulti {
@@ -83,7 +85,7 @@ struct DevMulti {
     uint16_t *oidx = nullptr;
     uint16_t *slot_ooff = nullptr;
     int32_t *chunk_tile = nullptr, *chunk_part = nullptr;
-    int32_t *cg_ptr = nullptr, *cg_idx = nullptr;
+    int32_t *cg_ptr = nullptr, *cg_idx = nullptr, *part_dst = nullptr;
     double *partial = nullptr;
     int32_t *group = nullptr;             // camera -> subset
 };
@@ -112,8 +114,8 @@ struct ba_system {
     uint32_t *meta = nullptr;
     int32_t *tile_lmk_base = nullptr;
     int32_t *chunk_tile = nullptr, *chunk_part = nullptr, *part_cam = nullptr;
-    int32_t *cam_part_ptr = nullptr, *cam_part_idx = nullptr;
-    double *partial = nullptr;      // n_part * 9
+    int32_t *cam_part_ptr = nullptr, *cam_part_idx = nullptr, *part_dst = nullptr;
+    double *partial = nullptr;      // n_part * 9, camera-major
     double *vinv = nullptr;         // nl * 6 (storage order): V_lambda^-1, symmetric
     double *bl = nullptr;           // nl * 3 (storage order)
     double *dU = nullptr;           // np * 9: lambda * diag(J_p^T J_p)
@@ -132,6 +134,8 @@ struct ba_system {
     double *hist = nullptr;         // MCG history (P then Q)
     int64_t hist_cap_cols = 0;
     double *small = nullptr;        // MCG small dense storage
+    double *hscratch = nullptr;     // split-K partials of the history products
+    double *refine_buf = nullptr;   // mixed precision: outer residual, inner right-hand side, update
     size_t small_cap = 0;
     double *host_pinned = nullptr;  // pinned host scalars
     ba::DevMulti multi;

@@ -80,6 +80,7 @@ struct Loader<2> {   // BF16, 3 x 16 B per observation
 
 template <int PREC, typename T>
 __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__restrict__ v) {
+    if (a.done && *a.done != 0.0) return;
     extern __shared__ __align__(16) unsigned char smem[];
     T *vloc = reinterpret_cast<T *>(smem);
     T *yloc = vloc + a.max_slots * 9;
@@ -134,20 +135,38 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
         }
         __syncthreads();
     }
-    double *out = a.partial + (int64_t)pb * 9;
-    for (int i = lane; i < ns * 9; i += kTile) out[i] = (double)yloc[i];
+    // row of slot k goes to its camera-major position
+    for (int i = lane; i < ns * 9; i += kTile) {
+        const int64_t row = a.part_dst[pb + i / 9];
+        a.partial[row * 9 + i % 9] = (double)yloc[i];
+    }
 }
 
-// y_c = lambda diag(U_c) v_c + sum of the partial rows of camera c (ascending row order)
-__global__ void k_reduce1(int np, const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                          const double *__restrict__ partial, const double *__restrict__ dU,
-                          const double *__restrict__ v, double *__restrict__ y) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np * 9) return;
-    int c = i / 9, k = i - c * 9;
-    double s = dU[i] * v[i];
-    for (int j = ptr[c]; j < ptr[c + 1]; ++j) s += partial[(int64_t)idx[j] * 9 + k];
-    y[i] = s;
+// y_c = lambda diag(U_c) v_c + sum of the partial rows of camera c, which are
+// contiguous (camera-major).  One wavefront per camera: lane l < 63 adds
+// component l % 9 of rows l / 9, l / 9 + 7, ...; the seven lanes of a component
+// are then added in lane order.
+__global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restrict__ ptr,
+                                                 const double *__restrict__ partial,
+                                                 const double *__restrict__ dU, const double *__restrict__ v,
+                                                 double *__restrict__ y, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    __shared__ double sh[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + w;
+    double s = 0.0;
+    if (c < np && lane < 63) {
+        const int r0 = lane / 9, k = lane - r0 * 9;
+        const int64_t a = ptr[c], b = ptr[c + 1];
+        for (int64_t j = a + r0; j < b; j += 7) s += partial[j * 9 + k];
+    }
+    sh[w][lane] = s;
+    __syncthreads();
+    if (c < np && lane < 9) {
+        double t = dU[(int64_t)c * 9 + lane] * v[(int64_t)c * 9 + lane];
+        for (int m = 0; m < 7; ++m) t += sh[w][lane + 9 * m];
+        y[(int64_t)c * 9 + lane] = t;
+    }
 }
 
 void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
@@ -163,9 +182,8 @@ void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
 }
 
 void launch_schur_reduce(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
-    int n = a.np * 9;
-    hipLaunchKernelGGL(k_reduce1, dim3((n + 255) / 256), dim3(256), 0, s, a.np, a.cam_part_ptr, a.cam_part_idx,
-                       a.partial, a.dU, v, y);
+    hipLaunchKernelGGL(k_reduce1, dim3((a.np + 3) / 4), dim3(256), 0, s, a.np, a.cam_part_ptr, a.partial, a.dU, v,
+                       y, a.done);
 }
 
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
@@ -245,12 +263,15 @@ __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *_
         }
         __syncthreads();
     }
-    double *out = a.partial + (int64_t)pb * 9;
-    for (int i = lane; i < no * 9; i += kTile) out[i] = (double)yloc[i];
+    for (int i = lane; i < no * 9; i += kTile) {
+        const int64_t row = a.part_dst[pb + i / 9];
+        a.partial[row * 9 + i % 9] = (double)yloc[i];
+    }
 }
 
-// Y[p][c] = [group(c) == p] lambda diag(U_c) z_c + sum of the partial rows of (c, p)
-__global__ void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+// Y[p][c] = [group(c) == p] lambda diag(U_c) z_c + sum of the partial rows of (c, p),
+// which are contiguous ((camera, subset)-major)
+__global__ void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr,
                                const double *__restrict__ partial, const double *__restrict__ dU,
                                const int32_t *__restrict__ group, const double *__restrict__ z,
                                double *__restrict__ Y) {
@@ -262,7 +283,7 @@ __global__ void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr, c
     int c = rem / 9, k = rem - c * 9;
     double s = group[c] == p ? dU[rem] * z[rem] : 0.0;
     int64_t key = (int64_t)c * N + p;
-    for (int j = ptr[key]; j < ptr[key + 1]; ++j) s += partial[(int64_t)idx[j] * 9 + k];
+    for (int j = ptr[key]; j < ptr[key + 1]; ++j) s += partial[(int64_t)j * 9 + k];
     Y[i] = s;
 }
 
@@ -278,7 +299,7 @@ void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStrea
     }
     int64_t total = (int64_t)a.np * 9 * a.N;
     hipLaunchKernelGGL(k_reduce_multi, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.np, a.N, a.cg_ptr,
-                       a.cg_idx, a.partial, a.dU, a.group, z, Y);
+                       a.partial, a.dU, a.group, z, Y);
 }
 
 // ---------------------------------------------------------------- eq. (16)

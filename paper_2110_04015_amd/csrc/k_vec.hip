@@ -62,7 +62,9 @@ void launch_precond(int np, const double *Dchol, const double *r, double *z, hip
 // z = D^-1 r and per-block partial sums of sum_i a[i] * z[i]
 __global__ __launch_bounds__(kNT) void k_precond_dot(int np, const double *__restrict__ Dchol,
                                                      const double *__restrict__ r, const double *__restrict__ a,
-                                                     double *__restrict__ z, double *__restrict__ partials) {
+                                                     double *__restrict__ z, double *__restrict__ partials,
+                                                     const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     __shared__ double sh[kNT];
     double acc = 0.0;
     for (int c = blockIdx.x * kNT + threadIdx.x; c < np; c += gridDim.x * kNT) {
@@ -79,20 +81,22 @@ __global__ __launch_bounds__(kNT) void k_precond_dot(int np, const double *__res
 }
 
 void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const double *Q, double *z,
-                            double *partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_precond_dot, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, Q, z, partials);
+                            double *partials, const double *done, hipStream_t s) {
+    hipLaunchKernelGGL(k_precond_dot, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, Q, z, partials, done);
 }
 
 void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_precond_dot, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, r, z, partials);
+    hipLaunchKernelGGL(k_precond_dot, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, r, z, partials,
+                       (const double *)nullptr);
 }
 
 // ---------------------------------------------------------------- reductions
 
 __global__ __launch_bounds__(kNT) void k_dot2(int64_t n, const double *__restrict__ a0, const double *__restrict__ b0,
                                               const double *__restrict__ a1, const double *__restrict__ b1,
-                                              double *__restrict__ partials) {
+                                              double *__restrict__ partials, const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
     __shared__ double sh[kNT];
     double s0 = 0.0, s1 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
@@ -108,8 +112,8 @@ __global__ __launch_bounds__(kNT) void k_dot2(int64_t n, const double *__restric
 }
 
 void launch_dot2(int64_t n, const double *a0, const double *b0, const double *a1, const double *b1,
-                 double *partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kNT), 0, s, n, a0, b0, a1, b1, partials);
+                 double *partials, const double *done, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kNT), 0, s, n, a0, b0, a1, b1, partials, done);
 }
 
 __global__ void k_finalize(const double *__restrict__ partials, int nd, double *__restrict__ out) {
@@ -122,6 +126,43 @@ __global__ void k_finalize(const double *__restrict__ partials, int nd, double *
 
 void launch_finalize(const double *partials, int nd, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, partials, nd, out);
+}
+
+// ---------------------------------------------------------------- refinement
+
+// r = -bt - Sx, btp = -r; partials of |r|^2 and |bt|^2 (2 per block)
+__global__ __launch_bounds__(kNT) void k_residual_refine(int64_t n, const double *__restrict__ bt,
+                                                         const double *__restrict__ Sx, double *__restrict__ r,
+                                                         double *__restrict__ btp, double *__restrict__ partials) {
+    __shared__ double sh[kNT];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
+        const double v = -bt[i] - Sx[i];
+        r[i] = v;
+        btp[i] = -v;
+        a += v * v;
+        b += bt[i] * bt[i];
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x * 2] = a;
+        partials[blockIdx.x * 2 + 1] = b;
+    }
+}
+
+void launch_residual_refine(int64_t n, const double *bt, const double *Sx, double *r, double *btp,
+                            double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_residual_refine, dim3(kRedBlocks), dim3(kNT), 0, s, n, bt, Sx, r, btp, partials);
+}
+
+__global__ void k_axpy(int64_t n, double a, const double *__restrict__ x, double *__restrict__ y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
+void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy, dim3(kRedBlocks), dim3(kNT), 0, s, n, a, x, y);
 }
 
 // ---------------------------------------------------------------- Algorithm 1
@@ -158,6 +199,39 @@ void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_rr, dim3(1), dim3(64), 0, s, partials_rr, sc);
 }
 
+// End of a PCG iteration on the device: |r_{i+1}|^2 from the partials, the
+// iteration count, the stop test |r_{i+1}| < eps |r_0| (Alg. 1) and the iteration
+// cap.  Sets sc[SC_DONE] (after which every kernel of later iterations returns at
+// once) and sc[SC_STATUS].  trace (nullable) receives |r_{i+1}| / |r_0|.
+__global__ void k_pcg_step_end(const double *__restrict__ partials, double *__restrict__ sc, double eps,
+                               int max_iter, double *__restrict__ trace) {
+    if (threadIdx.x != 0 || sc[SC_DONE] != 0.0) return;
+    if (sc[SC_BREAK] != 0.0) {
+        sc[SC_DONE] = 1.0;
+        sc[SC_STATUS] = (double)BA_ERR_BREAKDOWN;
+        return;
+    }
+    double s = 0.0;
+    for (int b = 0; b < kRedBlocks; ++b) s += partials[b];
+    const double it = sc[SC_ITER] + 1.0;
+    sc[SC_ITER] = it;
+    sc[SC_RR] = s;
+    const double rr0 = sc[SC_RR0];
+    if (trace) trace[(int)it - 1] = sqrt(s / rr0);
+    if (sqrt(s) < eps * sqrt(rr0)) {
+        sc[SC_DONE] = 1.0;
+        sc[SC_STATUS] = (double)BA_OK;
+    } else if (it >= (double)max_iter) {
+        sc[SC_DONE] = 1.0;
+        sc[SC_STATUS] = (double)BA_MAXITER;
+    }
+}
+
+void launch_pcg_step_end(const double *partials_rr, double *sc, double eps, int max_iter, double *trace,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_step_end, dim3(1), dim3(64), 0, s, partials_rr, sc, eps, max_iter, trace);
+}
+
 // Delta = Q^T P, gamma = P^T r from the partials; alpha = gamma / Delta;
 // x += alpha P, r -= alpha Q; partial |r|^2
 __global__ __launch_bounds__(kNT) void k_pcg_update_xr(int64_t n, const double *__restrict__ pdq,
@@ -165,6 +239,7 @@ __global__ __launch_bounds__(kNT) void k_pcg_update_xr(int64_t n, const double *
                                                        double *__restrict__ r, const double *__restrict__ P,
                                                        const double *__restrict__ Q,
                                                        double *__restrict__ partials) {
+    if (sc[SC_DONE] != 0.0) return;
     __shared__ double sh[kNT];
     __shared__ double s_alpha;
     if (threadIdx.x == 0) {
@@ -205,6 +280,7 @@ void launch_pcg_update_xr(int64_t n, const double *partials_dq, double *sc, doub
 __global__ __launch_bounds__(kNT) void k_pcg_update_p(int64_t n, const double *__restrict__ pphi,
                                                       double *__restrict__ sc, const double *__restrict__ z,
                                                       double *__restrict__ P) {
+    if (sc[SC_DONE] != 0.0) return;
     __shared__ double s_beta;
     if (threadIdx.x == 0) {
         double phi = 0.0;
@@ -389,25 +465,102 @@ __device__ void jacobi_eig(int k, double *A, double *V, double *cs, double *sn, 
     }
 }
 
-// A^+ = sum over |l_e| > k 2^-52 max|l| of v_e v_e^T / l_e ; returns rank via *rank_out
-__device__ void pinv_from_eig(int k, const double *A, const double *V, double *Ap, int *rank_sh) {
+// Lower Cholesky factor of the k x k matrix M in place (right-looking, LDS);
+// returns false when a pivot is not positive.
+__device__ bool chol_lds(int k, double *M, int *flag) {
     const int tid = threadIdx.x;
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (tid == 0) {
+            double d = M[j * k + j];
+            if (!(d > 0.0)) {
+                *flag = 1;
+                d = 1.0;
+            }
+            M[j * k + j] = sqrt(d);
+        }
+        __syncthreads();
+        const double piv = M[j * k + j];
+        for (int i = j + 1 + tid; i < k; i += kNT) M[i * k + j] /= piv;
+        __syncthreads();
+        const int rem = k - j - 1;
+        for (int w = tid; w < rem * rem; w += kNT) {
+            const int i = j + 1 + w / rem, m = j + 1 + w % rem;
+            if (m <= i) M[i * k + m] -= M[i * k + j] * M[m * k + j];
+        }
+        __syncthreads();
+    }
+    return *flag == 0;
+}
+
+// Moore-Penrose pseudo-inverse of the symmetric k x k matrix A (LDS, left intact),
+// result in G; V is scratch.  When the Cholesky factorisation succeeds and
+// |A|_F |A^-1|_F < 1e-4 / (k eps), every eigenvalue lies above the drop threshold
+// k eps max|l| (l_min >= 1 / |A^-1|_F, l_max <= |A|_F), so A^+ = A^-1 = L^-T L^-1 is
+// taken from the factor; otherwise the Jacobi eigendecomposition decides.
+__device__ void pinv_sym_lds(int k, const double *A, double *V, double *G, double *sh, double *cs, double *sn,
+                             int *flag, int *rank_sh) {
+    const int tid = threadIdx.x;
+    for (int w = tid; w < k * k; w += kNT) V[w] = A[w];
+    __syncthreads();
+    bool ok = chol_lds(k, V, flag);
+    if (ok) {
+        // G = L^-1, one column per thread
+        if (tid < k) {
+            const int c = tid;
+            for (int i = 0; i < c; ++i) G[i * k + c] = 0.0;
+            G[c * k + c] = 1.0 / V[c * k + c];
+            for (int i = c + 1; i < k; ++i) {
+                double s = 0.0;
+                for (int m = c; m < i; ++m) s += V[i * k + m] * G[m * k + c];
+                G[i * k + c] = -s / V[i * k + i];
+            }
+        }
+        __syncthreads();
+        // V = A^-1 = G^T G
+        double fa = 0.0, fi = 0.0;
+        for (int w = tid; w < k * k; w += kNT) {
+            const int i = w / k, j = w - i * k;
+            double s = 0.0;
+            for (int m = (i > j ? i : j); m < k; ++m) s += G[m * k + i] * G[m * k + j];
+            V[w] = s;
+            fi += s * s;
+            fa += A[w] * A[w];
+        }
+        fa = block_sum(fa, sh);
+        fi = block_sum(fi, sh);
+        ok = sqrt(fa) * sqrt(fi) < 1e-4 / ((double)k * 2.220446049250313e-16);
+        if (ok) {
+            for (int w = tid; w < k * k; w += kNT) G[w] = V[w];
+            if (tid == 0) *rank_sh = k;
+            __syncthreads();
+            return;
+        }
+    }
+    // V and G are free again: eigendecomposition of a copy of A
+    for (int w = tid; w < k * k; w += kNT) G[w] = A[w];
+    __syncthreads();
+    jacobi_eig(k, G, V, cs, sn, flag);
+    // eigenvalues (diagonal of G) are copied out before G is overwritten
+    __shared__ double lam[kMaxK];
+    for (int e = tid; e < k; e += kNT) lam[e] = G[e * k + e];
+    __syncthreads();
+    const double *Lm = lam;
     double lmax = 0.0;
-    for (int e = 0; e < k; ++e) lmax = fmax(lmax, fabs(A[e * k + e]));
+    for (int e = 0; e < k; ++e) lmax = fmax(lmax, fabs(Lm[e]));
     const double thr = (double)k * 2.220446049250313e-16 * lmax;
     if (tid == 0) {
         int rk = 0;
-        for (int e = 0; e < k; ++e) rk += fabs(A[e * k + e]) > thr;
+        for (int e = 0; e < k; ++e) rk += fabs(Lm[e]) > thr;
         *rank_sh = rk;
     }
     for (int w = tid; w < k * k; w += kNT) {
-        int i = w / k, j = w - i * k;
+        const int i = w / k, j = w - i * k;
         double s = 0.0;
-        for (int e = 0; e < k; ++e) {
-            double l = A[e * k + e];
-            if (fabs(l) > thr) s += V[i * k + e] * (1.0 / l) * V[j * k + e];
-        }
-        Ap[w] = s;
+        for (int e = 0; e < k; ++e)
+            if (fabs(Lm[e]) > thr) s += V[i * k + e] * (1.0 / Lm[e]) * V[j * k + e];
+        G[w] = s;
     }
     __syncthreads();
 }
@@ -417,7 +570,7 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
                                                     double *__restrict__ Dp, double *__restrict__ gamma,
                                                     double *__restrict__ alpha, double *__restrict__ sc) {
     __shared__ double A[kMaxK * kMaxK], V[kMaxK * kMaxK], G[kMaxK * kMaxK];
-    __shared__ double gam[kMaxK], cs[kMaxK], sn[kMaxK];
+    __shared__ double gam[kMaxK], cs[kMaxK], sn[kMaxK], sh[kNT];
     __shared__ int flag, rank;
     const int tid = threadIdx.x;
     const int tot = k * k + k;
@@ -433,8 +586,7 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
         A[w] = 0.5 * (G[i * k + j] + G[j * k + i]);
     }
     __syncthreads();
-    jacobi_eig(k, A, V, cs, sn, &flag);
-    pinv_from_eig(k, A, V, G, &rank);
+    pinv_sym_lds(k, A, V, G, sh, cs, sn, &flag, &rank);
     for (int w = tid; w < k * k; w += kNT) Dp[w] = G[w];
     for (int a = tid; a < k; a += kNT) {
         double s = 0.0;
@@ -453,13 +605,13 @@ void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, d
 // Stand-alone symmetric pseudo-inverse (test entry point).
 __global__ __launch_bounds__(kNT) void k_pinv_sym(int k, const double *__restrict__ Ain, double *__restrict__ Ap,
                                                   int32_t *__restrict__ rank_out) {
-    __shared__ double A[kMaxK * kMaxK], V[kMaxK * kMaxK];
-    __shared__ double cs[kMaxK], sn[kMaxK];
+    __shared__ double A[kMaxK * kMaxK], V[kMaxK * kMaxK], G[kMaxK * kMaxK];
+    __shared__ double cs[kMaxK], sn[kMaxK], sh[kNT];
     __shared__ int flag, rank;
     for (int w = threadIdx.x; w < k * k; w += kNT) A[w] = Ain[w];
     __syncthreads();
-    jacobi_eig(k, A, V, cs, sn, &flag);
-    pinv_from_eig(k, A, V, Ap, &rank);
+    pinv_sym_lds(k, A, V, G, sh, cs, sn, &flag, &rank);
+    for (int w = threadIdx.x; w < k * k; w += kNT) Ap[w] = G[w];
     if (threadIdx.x == 0 && rank_out) *rank_out = rank;
 }
 
@@ -539,6 +691,18 @@ void launch_phi(int64_t n, int h, const double *Qh, const double *z, int multi, 
     hipLaunchKernelGGL(k_phi, dim3(h, multi ? N : 1), dim3(kNT), 0, s, n, Qh, z, multi, N, gs, Phi);
 }
 
+// records history block j (first column, width, offset of its Delta^+) on the device
+__global__ void k_set_block(int32_t *blk_off, int32_t *blk_k, int64_t *blk_dp, int j, int off, int kj, int64_t dp) {
+    blk_off[j] = off;
+    blk_k[j] = kj;
+    blk_dp[j] = dp;
+}
+
+void launch_set_block(int32_t *blk_off, int32_t *blk_k, int64_t *blk_dp, int j, int off, int kj, int64_t dp,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_set_block, dim3(1), dim3(1), 0, s, blk_off, blk_k, blk_dp, j, off, kj, dp);
+}
+
 // beta rows of history block j: beta[off_j + a][p] = sum_b Delta_j^+[a][b] Phi[off_j + b][p]
 __global__ __launch_bounds__(kNT) void k_beta(const int32_t *__restrict__ blk_off, const int32_t *__restrict__ blk_k,
                                               const int64_t *__restrict__ blk_dp, const double *__restrict__ Dp,
@@ -559,55 +723,111 @@ void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int
     hipLaunchKernelGGL(k_beta, dim3(nb), dim3(kNT), 0, s, blk_off, blk_k, blk_dp, Dp, Phi, kn, beta);
 }
 
-// Out[:, p] = Base[:, p] - sum_col H[:, col] beta[col][p] for p in [p0, p0 + 16).
-// Base is Z (z restricted to subset p, or z itself for one column) when Y is null,
-// otherwise the block Y (S Z, eq. (19)).
-constexpr int kUpdCols = 16;
-__global__ __launch_bounds__(kNT) void k_update_hist(int64_t n, int h, int kn, const double *__restrict__ H,
+// History products of the reorthogonalisation, Out[:, p] = Base[:, p] - sum_col H[:, col] beta[col][p]
+// (Alg. 2: P_{i+1} = Z - sum_j P_j beta_{i,j}; eq. (19): Q_{i+1} = S Z - sum_j Q_j beta_{i,j}).
+// Pass 1: one wavefront per (64-row tile, column slice, block of KB outputs) accumulates
+// its slice; beta is wave-uniform (scalar loads).  Pass 2 adds the slices in slice order
+// and subtracts from the base, so the result is independent of scheduling.
+template <int KB>
+__global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, int kn, int slice_cols,
+                                                     const double *__restrict__ H,
                                                      const double *__restrict__ beta,
-                                                     const double *__restrict__ z, int multi, int gs, int N,
-                                                     const double *__restrict__ Y, double *__restrict__ Out) {
-    __shared__ double sb[64][kUpdCols];
-    const int64_t row = (int64_t)blockIdx.x * kNT + threadIdx.x;
-    const int p0 = blockIdx.y * kUpdCols;
-    const int pc = min(kUpdCols, kn - p0);
-    double acc[kUpdCols];
+                                                     double *__restrict__ scratch) {
+    const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int ks = blockIdx.y;
+    const int p0 = blockIdx.z * KB;
+    const int c0 = ks * slice_cols;
+    const int c1 = min(h, c0 + slice_cols);
+    double acc[KB];
 #pragma unroll
-    for (int j = 0; j < kUpdCols; ++j) acc[j] = 0.0;
-    for (int c0 = 0; c0 < h; c0 += 64) {
-        const int cc = min(64, h - c0);
-        __syncthreads();
-        for (int w = threadIdx.x; w < 64 * kUpdCols; w += kNT) {
-            int c = w / kUpdCols, j = w - c * kUpdCols;
-            sb[c][j] = (c < cc && j < pc) ? beta[(int64_t)(c0 + c) * kn + p0 + j] : 0.0;
-        }
-        __syncthreads();
-        if (row < n) {
-            for (int c = 0; c < cc; ++c) {
-                const double hv = H[(int64_t)(c0 + c) * n + row];
+    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+    if (row < n) {
+        const double *hp = H + row;
+        int c = c0;
+        for (; c + 4 <= c1; c += 4) {
+            const double h0 = hp[(int64_t)c * n], h1 = hp[(int64_t)(c + 1) * n];
+            const double h2 = hp[(int64_t)(c + 2) * n], h3 = hp[(int64_t)(c + 3) * n];
+            const double *b0 = beta + (int64_t)c * kn + p0;
 #pragma unroll
-                for (int j = 0; j < kUpdCols; ++j) acc[j] += hv * sb[c][j];
+            for (int j = 0; j < KB; ++j) {
+                if (p0 + j < kn) {
+                    acc[j] += h0 * b0[j];
+                    acc[j] += h1 * b0[kn + j];
+                    acc[j] += h2 * b0[2 * kn + j];
+                    acc[j] += h3 * b0[3 * kn + j];
+                }
             }
         }
+        for (; c < c1; ++c) {
+            const double hv = hp[(int64_t)c * n];
+            const double *b0 = beta + (int64_t)c * kn + p0;
+#pragma unroll
+            for (int j = 0; j < KB; ++j)
+                if (p0 + j < kn) acc[j] += hv * b0[j];
+        }
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            if (p0 + j < kn) scratch[((int64_t)ks * kn + p0 + j) * n + row] = acc[j];
     }
-    if (row >= n) return;
-    int cam_grp = multi ? min((int)(row / 9) / gs, N - 1) : 0;
-    for (int j = 0; j < pc; ++j) {
-        const int p = p0 + j;
-        double base;
-        if (Y) base = Y[(int64_t)p * n + row];
-        else base = (!multi || cam_grp == p) ? z[row] : 0.0;
-        Out[(int64_t)p * n + row] = base - acc[j];
+}
+
+__global__ void k_hist_final(int64_t n, int kn, int nslices, const double *__restrict__ scratch,
+                             const double *__restrict__ z, int multi, int gs, int N, const double *__restrict__ Y,
+                             double *__restrict__ Out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * kn) return;
+    const int p = (int)(i / n);
+    const int64_t row = i - (int64_t)p * n;
+    double s = 0.0;
+    for (int ks = 0; ks < nslices; ++ks) s += scratch[((int64_t)ks * kn + p) * n + row];
+    double base;
+    if (Y) {
+        base = Y[i];
+    } else {
+        const int grp = multi ? min((int)(row / 9) / gs, N - 1) : 0;
+        base = (!multi || grp == p) ? z[row] : 0.0;
     }
+    Out[i] = base - s;
+}
+
+int hist_slices(int64_t n, int h, int kn, int64_t scratch_doubles) {
+    const int64_t tiles = (n + 63) / 64;
+    int s = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
+    s = std::min(s, std::max(1, h / 16));
+    s = std::min(s, 64);
+    const int64_t per = (int64_t)kn * n;
+    if (per > 0) s = (int)std::max<int64_t>(1, std::min<int64_t>(s, scratch_doubles / per));
+    return std::max(1, s);
+}
+
+static void launch_hist(int64_t n, int h, int kn, const double *H, const double *beta, const double *z, int multi,
+                        int gs, int N, const double *Y, double *Out, double *scratch, int64_t scratch_doubles,
+                        hipStream_t s) {
+    const int slices = hist_slices(n, h, kn, scratch_doubles);
+    const int slice_cols = (h + slices - 1) / slices;
+    const unsigned tiles = (unsigned)((n + 63) / 64);
+    if (h > 0) {
+        if (kn == 1) {
+            hipLaunchKernelGGL((k_hist_partial<1>), dim3(tiles, slices, 1), dim3(64), 0, s, n, h, kn, slice_cols, H,
+                               beta, scratch);
+        } else if (kn <= 16) {
+            hipLaunchKernelGGL((k_hist_partial<16>), dim3(tiles, slices, 1), dim3(64), 0, s, n, h, kn, slice_cols, H,
+                               beta, scratch);
+        } else {
+            hipLaunchKernelGGL((k_hist_partial<32>), dim3(tiles, slices, (kn + 31) / 32), dim3(64), 0, s, n, h, kn,
+                               slice_cols, H, beta, scratch);
+        }
+    }
+    const int64_t tot = n * kn;
+    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, kn, h > 0 ? slices : 0,
+                       scratch, z, multi, gs, N, Y, Out);
 }
 
 void launch_update_pq(int64_t n, int h, int kn, const double *Ph, const double *Qh, const double *beta,
                       const double *z, int multi, int gs, int N, const double *Y, double *Pn, double *Qn,
-                      hipStream_t s) {
-    dim3 grid((unsigned)((n + kNT - 1) / kNT), (unsigned)((kn + kUpdCols - 1) / kUpdCols));
-    hipLaunchKernelGGL(k_update_hist, grid, dim3(kNT), 0, s, n, h, kn, Ph, beta, z, multi, gs, N,
-                       (const double *)nullptr, Pn);
-    if (Y && Qn) hipLaunchKernelGGL(k_update_hist, grid, dim3(kNT), 0, s, n, h, kn, Qh, beta, z, multi, gs, N, Y, Qn);
+                      double *scratch, int64_t scratch_doubles, hipStream_t s) {
+    launch_hist(n, h, kn, Ph, beta, z, multi, gs, N, nullptr, Pn, scratch, scratch_doubles, s);
+    if (Y && Qn) launch_hist(n, h, kn, Qh, beta, z, multi, gs, N, Y, Qn, scratch, scratch_doubles, s);
 }
 
 }  // namespace ba

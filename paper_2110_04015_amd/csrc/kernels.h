@@ -21,6 +21,9 @@ enum {
     SC_T = 8,        // t_i of the tau-test (MCG)
     SC_RHO = 9,      // r^T D^-1 r (MCG)
     SC_RANK = 10,    // numerical rank of Delta_i (MCG)
+    SC_DONE = 11,    // 1 once the PCG loop has stopped (device-side stop test)
+    SC_ITER = 12,    // completed PCG iterations
+    SC_STATUS = 13,  // ba_status of the PCG loop
     SC_COUNT = 16
 };
 
@@ -64,13 +67,14 @@ struct SchurArgs {
     const uint32_t *meta;
     const int32_t *tile_lmk_base;
     const double *vinv;
-    const int32_t *chunk_tile, *chunk_part, *part_cam;
+    const int32_t *chunk_tile, *chunk_part, *part_cam, *part_dst;
     int n_chunks;
     int max_slots;
     double *partial;
-    const int32_t *cam_part_ptr, *cam_part_idx;
+    const int32_t *cam_part_ptr;
     const double *dU;
     int np;
+    const double *done;            // nullable: when *done != 0 the launch does nothing
 };
 // y = S v (partials then the camera reduction)
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s);
@@ -92,7 +96,8 @@ struct MultiArgs {
     const int32_t *chunk_tile, *chunk_part;
     int n_chunks, max_out;
     double *partial;
-    const int32_t *cg_ptr, *cg_idx;
+    const int32_t *part_dst;
+    const int32_t *cg_ptr;
     const double *dU;
     const int32_t *group;
     int np, N;
@@ -112,16 +117,23 @@ constexpr int kRedBlocks = 120;    // fixed grid of the deterministic reductions
 void launch_precond(int np, const double *Dchol, const double *r, double *z, hipStream_t s);
 // partial dots: out[b * 2 + d] over blocks b < kRedBlocks
 void launch_dot2(int64_t n, const double *a0, const double *b0, const double *a1, const double *b1,
-                 double *partials, hipStream_t s);
+                 double *partials, const double *done, hipStream_t s);
 // finalize: out[d] = sum_b partials[b * nd + d] (fixed order), d < nd
 void launch_finalize(const double *partials, int nd, double *out, hipStream_t s);
+
+// mixed-precision refinement
+void launch_residual_refine(int64_t n, const double *bt, const double *Sx, double *r, double *btp,
+                            double *partials, hipStream_t s);
+void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 
 // PCG steps (scalars in sc[]: see k_vec.hip for the slot map)
 void launch_pcg_init(int64_t n, const double *bt, const double *Sx, double *r, double *partials, hipStream_t s);
 void launch_pcg_update_xr(int64_t n, const double *partials_dq, double *sc, double *x, double *r,
                           const double *P, const double *Q, double *partials_rr, hipStream_t s);
 void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const double *Q, double *z,
-                            double *partials, hipStream_t s);
+                            double *partials, const double *done, hipStream_t s);
+void launch_pcg_step_end(const double *partials_rr, double *sc, double eps, int max_iter, double *trace,
+                         hipStream_t s);
 void launch_pcg_update_p(int64_t n, const double *partials_phi, double *sc, const double *z, double *P,
                          hipStream_t s);
 void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s);
@@ -143,6 +155,8 @@ void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int
                  const double *Phi, int kn, double *beta, hipStream_t s);
 void launch_update_pq(int64_t n, int h, int kn, const double *Ph, const double *Qh, const double *beta,
                       const double *z, int multi, int gs, int N, const double *Y, double *Pn, double *Qn,
+                      double *scratch, int64_t scratch_doubles, hipStream_t s);
+void launch_set_block(int32_t *blk_off, int32_t *blk_k, int64_t *blk_dp, int j, int off, int kj, int64_t dp,
                       hipStream_t s);
 void launch_pinv_sym(int k, const double *A, double *Ap, int32_t *rank, hipStream_t s);
 

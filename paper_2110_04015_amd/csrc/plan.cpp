@@ -85,51 +85,59 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
         for (int k = 0; k <= np; ++k) cnt[k + 1] += cnt[k];
         P.lmk_order.resize((size_t)nl);
         for (int l = 0; l < nl; ++l) P.lmk_order[(size_t)cnt[(size_t)minc[l]]++] = l;
+    }
+    // tiles: landmarks never straddle a tile boundary.  Tiles are filled from a
+    // window of the next kWindow landmarks of the sorted order: a landmark that
+    // does not fit the current tile waits while later ones fill the gap, and the
+    // oldest waiting landmark always opens the next tile.  The storage order of
+    // the landmarks becomes their placement order.
+    {
+        constexpr int kWindow = 48;
+        std::vector<int32_t> sorted = P.lmk_order;
+        std::vector<int32_t> pending;
+        pending.reserve(kWindow);
+        P.lmk_order.clear();
+        P.lmk_order.reserve((size_t)nl);
+        P.lmk_first_slot.resize((size_t)nl);
+        P.lmk_count.resize((size_t)nl);
+        P.slot_obs.clear();
+        P.meta.clear();
+        P.tile_lmk_base.clear();
+        size_t next = 0;
+        int64_t t = 0;
+        while (next < (size_t)nl || !pending.empty()) {
+            while (pending.size() < (size_t)kWindow && next < (size_t)nl) pending.push_back(sorted[next++]);
+            P.tile_lmk_base.push_back((int32_t)P.lmk_order.size());
+            P.slot_obs.resize((size_t)(t + 1) * kTile, -1);
+            P.meta.resize((size_t)(t + 1) * kTile, kPad);
+            int used = 0, ll = 0;
+            size_t keep = 0;
+            for (size_t i = 0; i < pending.size(); ++i) {
+                int l = pending[i];
+                int c = (int)(lptr[l + 1] - lptr[l]);
+                if (used + c > kTile) {
+                    pending[keep++] = l;
+                    continue;
+                }
+                int s_new = (int)P.lmk_order.size();
+                P.lmk_order.push_back(l);
+                P.lmk_first_slot[(size_t)s_new] = t * kTile + used;
+                P.lmk_count[(size_t)s_new] = c;
+                for (int q = 0; q < c; ++q) {
+                    P.slot_obs[(size_t)(t * kTile + used + q)] = lobs[(size_t)(lptr[l] + q)];
+                    P.meta[(size_t)(t * kTile + used + q)] = meta_pack(0, (uint32_t)ll);
+                }
+                used += c;
+                ++ll;
+            }
+            pending.resize(keep);
+            ++t;
+        }
         P.lmk_store.resize((size_t)nl);
         for (int s = 0; s < nl; ++s) P.lmk_store[(size_t)P.lmk_order[s]] = s;
     }
-    // tiles: landmarks never straddle a tile boundary
-    P.lmk_first_slot.resize((size_t)nl);
-    P.lmk_count.resize((size_t)nl);
-    int64_t tiles = 0;
-    {
-        int used = kTile;
-        for (int s = 0; s < nl; ++s) {
-            int l = P.lmk_order[s];
-            int c = (int)(lptr[l + 1] - lptr[l]);
-            if (used + c > kTile) {
-                ++tiles;
-                used = 0;
-            }
-            used += c;
-        }
-    }
+    const int64_t tiles = (int64_t)P.tile_lmk_base.size();
     P.n_tiles = tiles;
-    P.slot_obs.assign((size_t)tiles * kTile, -1);
-    P.meta.assign((size_t)tiles * kTile, kPad);
-    P.tile_lmk_base.assign((size_t)tiles, 0);
-    {
-        int64_t t = -1;
-        int used = kTile, ll = 0;
-        for (int s = 0; s < nl; ++s) {
-            int l = P.lmk_order[s];
-            int c = (int)(lptr[l + 1] - lptr[l]);
-            if (used + c > kTile) {
-                ++t;
-                used = 0;
-                ll = 0;
-                P.tile_lmk_base[(size_t)t] = s;
-            }
-            P.lmk_first_slot[(size_t)s] = t * kTile + used;
-            P.lmk_count[(size_t)s] = c;
-            for (int q = 0; q < c; ++q) {
-                P.slot_obs[(size_t)(t * kTile + used + q)] = lobs[(size_t)(lptr[l] + q)];
-                P.meta[(size_t)(t * kTile + used + q)] = meta_pack(0, (uint32_t)ll);
-            }
-            used += c;
-            ++ll;
-        }
-    }
     // chunks of consecutive tiles with at most max_slots distinct cameras
     {
         std::vector<int32_t> stamp((size_t)np, -1), slot_of((size_t)np, 0);
@@ -183,6 +191,9 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
         for (int c = 0; c <= np; ++c) P.cam_part_ptr[c] = (int32_t)ptr[c];
         P.cam_part_idx.resize((size_t)P.n_part);
         for (int64_t i = 0; i < P.n_part; ++i) P.cam_part_idx[(size_t)i] = (int32_t)idx[(size_t)i];
+        // a chunk writes its partial row straight into the camera-major position
+        P.part_dst.resize((size_t)P.n_part);
+        for (int64_t j = 0; j < P.n_part; ++j) P.part_dst[(size_t)P.cam_part_idx[(size_t)j]] = (int32_t)j;
     }
     counting_csr(cam, m, np, P.cam_obs_ptr, P.cam_obs);
     return BA_OK;
@@ -305,6 +316,8 @@ ba_status build_multi_plan(const HostPlan &P, int N, int max_out, HostMultiPlan 
     M.cg_idx.resize(part_key.size());
     std::vector<int32_t> fill(M.cg_ptr.begin(), M.cg_ptr.end() - 1);
     for (size_t i = 0; i < part_key.size(); ++i) M.cg_idx[(size_t)fill[(size_t)part_key[i]]++] = (int32_t)i;
+    M.part_dst.resize(part_key.size());
+    for (size_t j = 0; j < part_key.size(); ++j) M.part_dst[(size_t)M.cg_idx[j]] = (int32_t)j;
     return BA_OK;
 }
 

@@ -79,6 +79,7 @@ bool check_plan(const HostPlan &P, const int32_t *cam, const int32_t *lm) {
             int row = P.cam_part_idx[(size_t)j];
             if (row < 0 || row >= P.n_part || P.part_cam[(size_t)row] != c) return bad("partial CSR row", c, row);
             if (j > P.cam_part_ptr[(size_t)c] && row <= P.cam_part_idx[(size_t)j - 1]) return bad("CSR order", c, j);
+            if (P.part_dst[(size_t)row] != j) return bad("partial destination", row, j);
         }
     }
     return true;
@@ -139,7 +140,8 @@ bool check_multi(const HostPlan &P, const HostMultiPlan &M, const int32_t *cam) 
         if (part_key[(size_t)i] < 0) return bad("unused out-pair", i);
     for (int64_t k = 0; k < (int64_t)P.np * N; ++k)
         for (int j = M.cg_ptr[(size_t)k]; j < M.cg_ptr[(size_t)k + 1]; ++j)
-            if (part_key[(size_t)M.cg_idx[(size_t)j]] != k) return bad("(camera, subset) CSR", k, j);
+            if (part_key[(size_t)M.cg_idx[(size_t)j]] != k || M.part_dst[(size_t)M.cg_idx[(size_t)j]] != j)
+                return bad("(camera, subset) CSR", k, j);
     return true;
 }
 }  // namespace

@@ -339,3 +339,29 @@ def test_build_errors():
     assert e.value.status == ba.BA_ERR_UNSUPPORTED
     g = ba.System.from_problem(p)
     g.close()
+
+
+# ---------------------------------------------------------------- A11 mixed precision
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("solver", ["pcg", "mcg"])
+def test_mixed_precision_refinement(pair, prec, solver):
+    """FP64 refinement around reduced-precision S products: the result meets the FP64
+    residual target, and run to 1e-10 its error against the dense solution is <= 1e-6
+    (energy norm) -- the stated bound for the mixed form."""
+    name, p, o, g = pair
+    N = min(4, p.n_cams)
+    run = (lambda **kw: g.pcg(precision=prec, **kw)) if solver == "pcg" else \
+        (lambda **kw: g.mcg(N, 10.0, precision=prec, **kw))
+    x, st = run(max_iter=5000, max_outer=40)
+    assert st.status == ba.BA_OK, st
+    bt = o.rhs()
+    xh = _h(x)
+    true = np.linalg.norm(-bt - o.matvec(xh)) / np.linalg.norm(bt)
+    assert true < 1e-6 and abs(true - st.rel_res_true) < 1e-9
+    assert st.refinement_steps >= 1
+    S, xs = dense(name, o)
+    x, st = run(eps=1e-10, max_iter=20000, max_outer=60)
+    assert st.status == ba.BA_OK, st
+    assert energy_err(S, _h(x), xs) <= 1e-6
