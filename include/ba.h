@@ -185,6 +185,52 @@ ba_status ba_partition(int32_t n_cams, int32_t n_groups, int32_t *group);
 ba_status ba_system_info(const ba_system *sys, int32_t *n_cams, int32_t *n_lms, int64_t *n_obs,
                          int64_t *n_tiles, int32_t *n_chunks, int64_t *matvec_bytes_fp64);
 
+/* ---- Learned low-rank correction of the block-Jacobi preconditioner (an addition
+ * to the paper's D(S), Sec. 3.2): M^-1 = D(S)^-1 + U U^T with U (n x 8, row-major),
+ * U_c = L_c^-T Uh_c for D(S)_c = L_c L_c^T, and Uh_c (9 x 8, row-major) the output of a
+ * 2-layer MLP (47 -> 128 tanh -> 72) on 47 features of camera c.  M^-1 is SPD for
+ * any weights.  Solves use it when ba_solve_opts.precond = 1.
+ * MLP parameters (FP32, BA_MLP_PARAMS): W1 [128][47], b1 [128], W2 [72][128], b2 [72]. */
+#define BA_MLP_FEATURES 47
+#define BA_MLP_OUT 72
+#define BA_MLP_PARAMS 15432
+
+/* Features of every camera into F (device [n_cams][47], FP32): 36 correlations
+ * D_ij / sqrt(D_ii D_jj) (i < j, row-major) of D(S)_c, 9 log D_ii minus their mean,
+ * log(1 + covisibility degree), log(max(lambda, 1e-12)). */
+ba_status ba_lowrank_features(ba_system *sys, float *F);
+
+/* out (device [rows][72]) = MLP(F) with params (device, FP32).  bf16 = 1: inference on
+ * the matrix cores with BF16 operands and FP32 accumulation; 0: FP32.  Runs on stream. */
+ba_status ba_mlp_forward(const float *params, const float *F, int32_t rows, float *out, int32_t bf16,
+                         void *stream);
+
+/* Sets the system's low-rank term from MLP outputs (device [n_cams][72]). */
+ba_status ba_set_lowrank_from_mlp(ba_system *sys, const float *out);
+
+/* Sets the low-rank term to U (device [n][8], copied), or clears it (U = NULL). */
+ba_status ba_set_lowrank_precond(ba_system *sys, const double *U);
+
+/* Copies the current low-rank term into U (device [n][8]). */
+ba_status ba_get_lowrank(ba_system *sys, double *U);
+
+/* y = L^-1 x (transpose = 0) or L^-T x (transpose = 1), with L the block Cholesky
+ * factor of D(S); x, y device [n].  Maps vectors to and from the coordinates in
+ * which D(S) is the identity. */
+ba_status ba_block_scale(ba_system *sys, const double *x, double *y, int32_t transpose);
+
+/* Training loss and gradient for one system: with Uh = MLP(F) viewed as n x 8 and
+ * probes W, Sw (device [n][n_probes], row-major, Sw = L^-1 S L^-T W),
+ *   loss = 1/(n_probes n) sum_k |W_k - Sw_k - Uh (Uh^T Sw_k)|^2,
+ * an estimate of |I - (I + Uh Uh^T) L^-1 S L^-T|_F^2 / n.  grad: device [BA_MLP_PARAMS];
+ * loss: host.  1 <= n_probes <= 8; rows = n_cams.  FP32 network, FP64 loss. */
+ba_status ba_mlp_loss_grad(const float *params, const float *F, int32_t rows, const double *W, const double *Sw,
+                           int32_t n_probes, float *grad, double *loss, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on params with the gradient grad and
+ * moments m, v (all device [BA_MLP_PARAMS], FP32); t >= 1 counts steps. */
+ba_status ba_adam_step(float *params, const float *grad, float *m, float *v, int32_t t, float lr, void *stream);
+
 /* Event timing of the dominant kernel, the chunked implicit Schur product of
  * ba_schur_matvec and of the solvers' S v products: while enabled, each of its
  * launches on this system is bracketed by two HIP events recorded on the

@@ -91,6 +91,8 @@ def load(path: Optional[str] = None) -> C.CDLL:
                            C.c_int, C.POINTER(_Stats), _dp, _dp, C.c_int64]
     lib.or_mcg.restype = C.c_int
     lib.or_num_threads.restype = C.c_int
+    lib.or_set_lowrank.argtypes = [C.c_void_p, _dp, C.c_int]
+    lib.or_set_lowrank.restype = C.c_int
     return lib
 
 
@@ -163,6 +165,16 @@ class System:
         out = np.empty((self.n_cams, 9, 9))
         self.lib.or_get_Dblocks(self.h, _ptr(out))
         return out
+
+    def set_lowrank(self, U: Optional[np.ndarray]):
+        """Use M^-1 = D^-1 + U U^T (U: n x rank) in precond/pcg/mcg; None restores block Jacobi."""
+        if U is None:
+            self.lib.or_set_lowrank(self.h, None, 0)
+            return
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        st = self.lib.or_set_lowrank(self.h, _ptr(U), int(U.shape[1]))
+        if st != OK:
+            raise OracleError(st)
 
     # -- operators -------------------------------------------------------
     def matvec(self, v: np.ndarray) -> np.ndarray:

@@ -65,6 +65,8 @@ typedef struct {
     double *Dchol;               /* np x 81 : lower Cholesky factors of D(S) */
     int64_t *lm_ptr, *lm_obs;    /* observations of each landmark */
     int64_t *cam_ptr, *cam_obs;  /* observations of each camera */
+    double *Ulr;                 /* n x lr_rank (row-major) low-rank preconditioner term, or NULL */
+    int lr_rank;
 } or_sys;
 
 typedef struct {
@@ -210,6 +212,7 @@ void or_free(or_sys *s) {
     free(s->cam); free(s->lm); free(s->U); free(s->Vinv); free(s->W);
     free(s->bp); free(s->bl); free(s->bt); free(s->D); free(s->Dchol);
     free(s->lm_ptr); free(s->lm_obs); free(s->cam_ptr); free(s->cam_obs);
+    free(s->Ulr);
     free(s);
 }
 
@@ -401,7 +404,8 @@ void or_schur_matvec(const or_sys *s, const double *v, double *y) {
     free(h);
 }
 
-/* z = D(S)^-1 r, one 9x9 Cholesky solve per pose. */
+/* z = D(S)^-1 r, one 9x9 Cholesky solve per pose; with a low-rank term set by
+ * or_set_lowrank, z = D(S)^-1 r + U (U^T r). */
 void or_precond_apply(const or_sys *s, const double *r, double *z) {
 #pragma omp parallel for schedule(static)
     for (int c = 0; c < s->np; ++c) {
@@ -410,6 +414,32 @@ void or_precond_apply(const or_sys *s, const double *r, double *z) {
         chol_solve(s->Dchol + (size_t)c * 81, 9, x);
         for (int i = 0; i < 9; ++i) z[(size_t)c * 9 + i] = x[i];
     }
+    if (s->Ulr) {
+        int n = 9 * s->np, k = s->lr_rank;
+        double t[64];
+        for (int a = 0; a < k; ++a) t[a] = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int a = 0; a < k; ++a) t[a] += s->Ulr[(size_t)i * k + a] * r[i];
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int a = 0; a < k; ++a) acc += s->Ulr[(size_t)i * k + a] * t[a];
+            z[i] += acc;
+        }
+    }
+}
+
+/* Sets (U != NULL, 1 <= rank <= 64) or clears the low-rank preconditioner term. */
+int or_set_lowrank(or_sys *s, const double *U, int rank) {
+    free(s->Ulr);
+    s->Ulr = NULL;
+    s->lr_rank = 0;
+    if (!U) return OR_OK;
+    if (rank < 1 || rank > 64) return OR_ERR_INVALID;
+    size_t cnt = (size_t)9 * s->np * rank;
+    s->Ulr = (double *)malloc(sizeof(double) * cnt);
+    memcpy(s->Ulr, U, sizeof(double) * cnt);
+    s->lr_rank = rank;
+    return OR_OK;
 }
 
 /* dx_l = -V_lambda^-1 (b_l + W^T dx_p): second block row of eq. (7). */

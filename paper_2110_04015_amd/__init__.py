@@ -17,7 +17,10 @@ from . import _lib
 from ._lib import (BA_ERR_BREAKDOWN, BA_ERR_HIP, BA_ERR_INVALID_ARG, BA_ERR_NOMEM, BA_ERR_NONFINITE,
                    BA_ERR_NOT_SPD, BA_ERR_UNSUPPORTED, BA_ERR_WORKSPACE, BA_MAXITER, BA_OK, PREC)
 
-__all__ = ["System", "BAError", "Stats", "pinv_sym", "partition", "PREC", "lib"]
+__all__ = ["System", "BAError", "Stats", "pinv_sym", "partition", "PREC", "lib", "mlp_forward",
+           "mlp_loss_grad", "adam_step", "MLP_PARAMS"]
+
+MLP_PARAMS = 15432
 
 
 def lib() -> C.CDLL:
@@ -224,13 +227,45 @@ class System:
                "ba_back_substitute")
         return out
 
+    # -- learned low-rank preconditioner -------------------------------------
+    def lowrank_features(self):
+        torch = _torch()
+        F = torch.empty(self.n_cams, 47, dtype=torch.float32, device=self.device)
+        _check(lib().ba_lowrank_features(self.h, _dev_ptr(F, torch.float32, self.n_cams * 47, "F")),
+               "ba_lowrank_features")
+        return F
+
+    def set_lowrank_from_mlp(self, out):
+        torch = _torch()
+        _check(lib().ba_set_lowrank_from_mlp(self.h, _dev_ptr(out, torch.float32, self.n_cams * 72, "out")),
+               "ba_set_lowrank_from_mlp")
+
+    def set_lowrank(self, U):
+        torch = _torch()
+        p = None if U is None else _dev_ptr(U, torch.float64, self.n * 8, "U")
+        _check(lib().ba_set_lowrank_precond(self.h, p), "ba_set_lowrank_precond")
+
+    def get_lowrank(self):
+        torch = _torch()
+        U = self._new(self.n, 8)
+        _check(lib().ba_get_lowrank(self.h, _dev_ptr(U, torch.float64, self.n * 8, "U")), "ba_get_lowrank")
+        return U
+
+    def block_scale(self, x, transpose=False):
+        torch = _torch()
+        y = torch.empty_like(x)
+        _check(lib().ba_block_scale(self.h, _dev_ptr(x, torch.float64, self.n, "x"),
+                                    _dev_ptr(y, torch.float64, self.n, "y"), int(transpose)), "ba_block_scale")
+        return y
+
     def pcg(self, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False, out=None,
-            inner_eps=1e-3, max_outer=20, max_inner=200):
+            inner_eps=1e-3, max_outer=20, max_inner=200, precond="block_jacobi"):
         """Algorithm 1.  precision "fp32"/"bf16": FP64 iterative refinement around inner
         solves with reduced-precision S products (inner_eps, max_outer, max_inner)."""
         torch = _torch()
         x = out if out is not None else self._new(self.n)
-        o = _opts(eps, max_iter, precision, inner_eps=inner_eps, max_outer=max_outer, max_inner=max_inner)
+        o = _opts(eps, max_iter, precision, inner_eps=inner_eps, max_outer=max_outer, max_inner=max_inner,
+                  precond=_PRECOND[precond])
         st = _lib.SolveStats()
         tr = _Trace(max(int(max_iter), 1)) if trace else None
         if tr:
@@ -241,12 +276,12 @@ class System:
         return x, _stats(st, tr)
 
     def mcg(self, N, tau, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False,
-            max_history_cols=0, out=None, inner_eps=1e-3, max_outer=20, max_inner=200):
+            max_history_cols=0, out=None, inner_eps=1e-3, max_outer=20, max_inner=200, precond="block_jacobi"):
         """Algorithm 2 with N subsets and threshold tau (mixed precision as in pcg)."""
         torch = _torch()
         x = out if out is not None else self._new(self.n)
         o = _opts(eps, max_iter, precision, max_history_cols=max_history_cols, inner_eps=inner_eps,
-                  max_outer=max_outer, max_inner=max_inner)
+                  max_outer=max_outer, max_inner=max_inner, precond=_PRECOND[precond])
         st = _lib.SolveStats()
         tr = _Trace(max(int(max_iter), 1)) if trace else None
         if tr:
@@ -255,6 +290,44 @@ class System:
         _check(lib().ba_mcg_solve(self.h, int(N), float(tau), x0p, _dev_ptr(x, torch.float64, self.n, "x"),
                                   C.byref(o), C.byref(st)), "ba_mcg_solve")
         return x, _stats(st, tr)
+
+
+_PRECOND = {"block_jacobi": 0, "lowrank": 1, 0: 0, 1: 1}
+
+
+def mlp_forward(params, F, bf16=True, stream=None):
+    """MLP outputs (rows x 72, FP32) of the learned preconditioner for features F (rows x 47)."""
+    torch = _torch()
+    rows = int(F.shape[0])
+    out = torch.empty(rows, 72, dtype=torch.float32, device=F.device)
+    _check(lib().ba_mlp_forward(_dev_ptr(params, torch.float32, MLP_PARAMS, "params"),
+                                _dev_ptr(F, torch.float32, rows * 47, "F"), rows,
+                                _dev_ptr(out, torch.float32, rows * 72, "out"), int(bf16), _stream_handle(stream)),
+           "ba_mlp_forward")
+    return out
+
+
+def mlp_loss_grad(params, F, W, Sw, stream=None):
+    """Probe loss and its gradient with respect to the FP32 parameters (one system)."""
+    torch = _torch()
+    rows = int(F.shape[0])
+    n, P = int(W.shape[0]), int(W.shape[1])
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=F.device)
+    loss = C.c_double()
+    _check(lib().ba_mlp_loss_grad(_dev_ptr(params, torch.float32, MLP_PARAMS, "params"),
+                                  _dev_ptr(F, torch.float32, rows * 47, "F"), rows,
+                                  _dev_ptr(W, torch.float64, n * P, "W"), _dev_ptr(Sw, torch.float64, n * P, "Sw"), P,
+                                  _dev_ptr(grad, torch.float32, MLP_PARAMS, "grad"), C.byref(loss),
+                                  _stream_handle(stream)), "ba_mlp_loss_grad")
+    return loss.value, grad
+
+
+def adam_step(params, grad, m, v, t, lr=1e-3, stream=None):
+    torch = _torch()
+    _check(lib().ba_adam_step(_dev_ptr(params, torch.float32, MLP_PARAMS, "params"),
+                              _dev_ptr(grad, torch.float32, MLP_PARAMS, "grad"),
+                              _dev_ptr(m, torch.float32, MLP_PARAMS, "m"), _dev_ptr(v, torch.float32, MLP_PARAMS, "v"),
+                              int(t), float(lr), _stream_handle(stream)), "ba_adam_step")
 
 
 def pinv_sym(A, stream=None):

@@ -57,6 +57,15 @@ SIGNATURES = [
     ("ba_partition", C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     ("ba_system_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    ("ba_lowrank_features", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ba_mlp_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
+    ("ba_set_lowrank_from_mlp", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ba_set_lowrank_precond", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ba_get_lowrank", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ba_block_scale", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("ba_mlp_loss_grad", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    ("ba_adam_step", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float, C.c_void_p]),
     ("ba_profile_enable", C.c_int, [C.c_void_p, C.c_int32]),
     ("ba_profile_read", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     ("ba_plan_validate", C.c_int, [C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),

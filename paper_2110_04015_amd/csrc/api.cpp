@@ -108,6 +108,9 @@ void free_all(ba_system *s) {
     dfree(s->small);
     dfree(s->hscratch);
     dfree(s->refine_buf);
+    dfree(s->Ulr);
+    dfree(s->degree);
+    dfree(s->lr_proj);
     if (s->host_pinned) (void)hipHostFree(s->host_pinned);
     s->host_pinned = nullptr;
     free_multi(s->multi);
@@ -625,7 +628,9 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
         double *trace_dev = nullptr;
         const bool want_trace = stats && stats->trace_res && stats->trace_cap > 0;
         if (want_trace && (st = dalloc(&trace_dev, (size_t)opts.max_iter)) != BA_OK) return st;
+        const bool lowrank = opts.precond == 1;
         launch_precond(s->np, s->Dchol, r, P, q);
+        if (lowrank) launch_lowrank_apply(n, s->Ulr, r, P, nullptr, s->lr_proj, nullptr, nullptr, q);
         SchurArgs sa = schur_args(s, prec);
         sa.done = sc + SC_DONE;
         int enqueued = 0, batch = 4;
@@ -638,7 +643,12 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
                 launch_dot2(n, Q, P, P, r, pdq, sc + SC_DONE, q);            // Delta_i, gamma_i
                 launch_pcg_update_xr(n, pdq, sc, x, r, P, Q, prr, q);        // alpha_i, x_{i+1}, r_{i+1}
                 launch_pcg_step_end(prr, sc, opts.eps, opts.max_iter, trace_dev, q);
-                launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q);  // Z_{i+1}, Phi_i
+                if (!lowrank) {
+                    launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q);  // Z_{i+1}, Phi_i
+                } else {                                                     // M^-1 = D^-1 + U U^T
+                    launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q);
+                    launch_lowrank_apply(n, s->Ulr, r, z, Q, s->lr_proj, pphi, sc + SC_DONE, q);
+                }
                 launch_pcg_update_p(n, pphi, sc, z, P, q);                   // beta_i, P_{i+1}
             }
             enqueued += nb;
@@ -753,8 +763,10 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     int64_t hcols = 0;
     ba_status result = BA_OK;
     if (rr0 > 0.0) {
-        // P_0 = Z_0 = D(S)^-1 r_0 ; Q_0 = S P_0
+        // P_0 = Z_0 = M^-1 r_0 ; Q_0 = S P_0
+        const bool lowrank = opts.precond == 1;
         launch_precond(s->np, s->Dchol, r, Ph, q);
+        if (lowrank) launch_lowrank_apply(n, s->Ulr, r, Ph, nullptr, s->lr_proj, nullptr, nullptr, q);
         matvec(s, sa, Ph, Qh);
         std::vector<int32_t> hoff{0}, hk{1};
         std::vector<int64_t> hdp{0};
@@ -775,6 +787,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             // tau-test scalars, computed before the single read-back of the iteration:
             // t_i = gamma_i^T alpha_i / (r_{i+1}^T D^-1 r_{i+1})
             launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q);
+            if (lowrank) launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
             launch_tau(k, red + kRedBlocks, gamma, alpha, sc, q);
             HIPCHK(hipGetLastError());
             if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
@@ -920,6 +933,7 @@ static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const dou
 static ba_status check_opts(const ba_solve_opts *opts_in, ba_solve_opts *opts) {
     if (opts_in) *opts = *opts_in;
     else fill_default_opts(opts);
+    if (opts->precond != 0 && opts->precond != 1) return fail(BA_ERR_INVALID_ARG, "precond must be 0 or 1");
     if (!(opts->eps >= 0.0) || opts->max_iter < 0) return fail(BA_ERR_INVALID_ARG, "eps >= 0 and max_iter >= 0 required");
     if (opts->precision < 0 || opts->precision > 2) return fail(BA_ERR_INVALID_ARG, "precision must be 0, 1 or 2");
     if (opts->precision != 0 && (!(opts->inner_eps > 0.0) || opts->inner_eps >= 1.0 || opts->max_outer < 1 ||
@@ -934,6 +948,7 @@ ba_status ba_pcg_solve(ba_system *s, const double *x0, double *x, const ba_solve
     ba_solve_opts opts;
     ba_status st = check_opts(opts_in, &opts);
     if (st != BA_OK) return st;
+    if (opts.precond == 1 && !s->Ulr) return fail(BA_ERR_INVALID_ARG, "precond 1 needs a low-rank term (ba_set_lowrank_*)");
     if (opts.precision != 0) return refine(s, false, 0, 0.0, x0, x, opts, stats);
     return pcg_core(s, s->bt, true, x0, x, opts, stats);
 }
@@ -947,8 +962,131 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
     ba_solve_opts opts;
     ba_status st = check_opts(opts_in, &opts);
     if (st != BA_OK) return st;
+    if (opts.precond == 1 && !s->Ulr) return fail(BA_ERR_INVALID_ARG, "precond 1 needs a low-rank term (ba_set_lowrank_*)");
     if (opts.precision != 0) return refine(s, true, N, tau, x0, x, opts, stats);
     return mcg_core(s, s->bt, true, N, tau, x0, x, opts, stats);
+}
+
+
+// ------------------------------------------------------------------ learned preconditioner
+
+static ba_status ensure_lowrank_storage(ba_system *s) {
+    ba_status st;
+    if (!s->Ulr && (st = dalloc(&s->Ulr, (size_t)s->np * 9 * 8)) != BA_OK) return st;
+    if (!s->lr_proj && (st = dalloc(&s->lr_proj, (size_t)kRedBlocks * 8)) != BA_OK) return st;
+    return BA_OK;
+}
+
+ba_status ba_lowrank_features(ba_system *s, float *F) {
+    if (!s || !F) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (!s->degree) {
+        std::vector<int32_t> deg;
+        covisibility_degree(s->plan, deg);
+        ba_status st = upload(&s->degree, deg, s->stream);
+        if (st != BA_OK) return st;
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    launch_features(s->np, s->Dblk, s->degree, s->lambda, F, s->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_mlp_forward(const float *params, const float *F, int32_t rows, float *out, int32_t bf16, void *stream) {
+    if (!params || !F || !out || rows < 1) return fail(BA_ERR_INVALID_ARG, "ba_mlp_forward: bad argument");
+    hipStream_t q = (hipStream_t)stream;
+    float *hid = nullptr;
+    if (!bf16) {
+        ba_status st = dalloc(&hid, (size_t)rows * 128);
+        if (st != BA_OK) return st;
+    }
+    launch_mlp_forward(params, F, rows, out, hid, bf16 ? 1 : 0, q);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(q);
+    dfree(hid);
+    if (e != hipSuccess) return fail(BA_ERR_HIP, std::string("ba_mlp_forward: ") + hipGetErrorString(e));
+    return BA_OK;
+}
+
+ba_status ba_set_lowrank_from_mlp(ba_system *s, const float *out) {
+    if (!s || !out) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    ba_status st = ensure_lowrank_storage(s);
+    if (st != BA_OK) return st;
+    launch_lowrank_U(s->np, s->Dchol, out, s->Ulr, s->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_set_lowrank_precond(ba_system *s, const double *U) {
+    if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    if (!U) {
+        dfree(s->Ulr);
+        return BA_OK;
+    }
+    ba_status st = ensure_lowrank_storage(s);
+    if (st != BA_OK) return st;
+    HIPCHK(hipMemcpyAsync(s->Ulr, U, (size_t)s->np * 9 * 8 * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_get_lowrank(ba_system *s, double *U) {
+    if (!s || !U) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (!s->Ulr) return fail(BA_ERR_INVALID_ARG, "no low-rank term is set");
+    HIPCHK(hipMemcpyAsync(U, s->Ulr, (size_t)s->np * 9 * 8 * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_block_scale(ba_system *s, const double *x, double *y, int32_t transpose) {
+    if (!s || !x || !y) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    launch_block_scale(s->np, s->Dchol, x, y, transpose ? 1 : 0, s->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
+ba_status ba_mlp_loss_grad(const float *params, const float *F, int32_t rows, const double *W, const double *Sw,
+                           int32_t n_probes, float *grad, double *loss, void *stream) {
+    if (!params || !F || !W || !Sw || !grad || rows < 1 || n_probes < 1 || n_probes > 8)
+        return fail(BA_ERR_INVALID_ARG, "ba_mlp_loss_grad: bad argument (1 <= n_probes <= 8)");
+    hipStream_t q = (hipStream_t)stream;
+    const int64_t n = (int64_t)rows * 9;
+    float *buf = nullptr;
+    double *work = nullptr;
+    ba_status st = dalloc(&buf, (size_t)rows * (128 * 2 + 72 * 2));
+    if (st != BA_OK) return st;
+    if ((st = dalloc(&work, probe_work_doubles())) != BA_OK) {
+        dfree(buf);
+        return st;
+    }
+    float *hid = buf, *gpre = hid + (size_t)rows * 128, *out = gpre + (size_t)rows * 128, *gout = out + (size_t)rows * 72;
+    launch_mlp_forward(params, F, rows, out, hid, 0, q);
+    launch_probe_loss_grad(n, n_probes, out, W, Sw, work, gout, q);
+    launch_mlp_backward(params, F, hid, gout, gpre, rows, grad, q);
+    double lsum = 0.0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        const int ne = 8 * 8;
+        const double *res = work + (size_t)kRedBlocks * ne + ne + kRedBlocks + (size_t)kRedBlocks * ne;
+        e = hipMemcpyAsync(&lsum, res, sizeof(double), hipMemcpyDeviceToHost, q);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(q);
+    dfree(buf);
+    dfree(work);
+    if (e != hipSuccess) return fail(BA_ERR_HIP, std::string("ba_mlp_loss_grad: ") + hipGetErrorString(e));
+    if (loss) *loss = lsum / ((double)n_probes * (double)n);
+    return BA_OK;
+}
+
+ba_status ba_adam_step(float *params, const float *grad, float *m, float *v, int32_t t, float lr, void *stream) {
+    if (!params || !grad || !m || !v || t < 1 || !(lr > 0.f)) return fail(BA_ERR_INVALID_ARG, "ba_adam_step: bad argument");
+    hipStream_t q = (hipStream_t)stream;
+    launch_adam(params, grad, m, v, t, lr, q);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(q));
+    return BA_OK;
 }
 
 }  // extern "C"

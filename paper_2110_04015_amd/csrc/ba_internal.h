@@ -96,6 +96,7 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
 ba_status build_multi_plan(const HostPlan &plan, int N, int max_out, HostMultiPlan &mp,
                            std::string &err);
 void partition_groups(int np, int N, int32_t *group);
+void covisibility_degree(const HostPlan &plan, std::vector<int32_t> &deg);
 
 }  // namespace ba
 
@@ -136,6 +137,9 @@ struct ba_system {
     double *small = nullptr;        // MCG small dense storage
     double *hscratch = nullptr;     // split-K partials of the history products
     double *refine_buf = nullptr;   // mixed precision: outer residual, inner right-hand side, update
+    double *Ulr = nullptr;          // learned low-rank preconditioner term, n x 8 (row-major), or null
+    int32_t *degree = nullptr;      // covisibility degree per camera (learned features)
+    double *lr_proj = nullptr;      // kRedBlocks x 8 projections U^T r
     size_t small_cap = 0;
     double *host_pinned = nullptr;  // pinned host scalars
     ba::DevMulti multi;

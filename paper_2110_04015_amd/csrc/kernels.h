@@ -160,4 +160,19 @@ void launch_set_block(int32_t *blk_off, int32_t *blk_k, int64_t *blk_dp, int j, 
                       hipStream_t s);
 void launch_pinv_sym(int k, const double *A, double *Ap, int32_t *rank, hipStream_t s);
 
+// ---- learned low-rank preconditioner (k_learned.hip)
+void launch_features(int np, const double *Dblk, const int32_t *deg, double lambda, float *F, hipStream_t s);
+void launch_mlp_forward(const float *P, const float *F, int rows, float *out, float *hid, int bf16, hipStream_t s);
+void launch_lowrank_U(int np, const double *Dchol, const float *out, double *U, hipStream_t s);
+void launch_block_scale(int np, const double *Dchol, const double *x, double *y, int transpose, hipStream_t s);
+// z += U (U^T r) and partial sums of a2^T z (a2, partials nullable); pproj: kRedBlocks x 8
+void launch_lowrank_apply(int64_t n, const double *U, const double *r, double *z, const double *a2, double *pproj,
+                          double *partials, const double *done, hipStream_t s);
+void launch_probe_loss_grad(int64_t n, int Pn, const float *Uh, const double *W, const double *Sw, double *work,
+                            float *g_out, hipStream_t s);
+size_t probe_work_doubles();
+void launch_mlp_backward(const float *P, const float *F, const float *hid, const float *g_out, float *g_pre, int rows,
+                         float *grad, hipStream_t s);
+void launch_adam(float *P, const float *g, float *m, float *v, int t, float lr, hipStream_t s);
+
 }  // namespace ba

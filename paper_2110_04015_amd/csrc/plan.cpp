@@ -199,6 +199,41 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
     return BA_OK;
 }
 
+// Number of other cameras that share at least one landmark with each camera
+// (the covisibility degree, an input feature of the learned preconditioner).
+void covisibility_degree(const HostPlan &P, std::vector<int32_t> &deg) {
+    const int np = P.np;
+    deg.assign((size_t)np, 0);
+    // landmark -> its observing cameras, from the tile layout (landmarks are contiguous)
+    std::vector<int64_t> lptr((size_t)P.nl + 1, 0);
+    for (int s = 0; s < P.nl; ++s) lptr[(size_t)s + 1] = lptr[(size_t)s] + P.lmk_count[(size_t)s];
+    std::vector<int32_t> lcam((size_t)lptr[(size_t)P.nl]);
+    for (int s = 0; s < P.nl; ++s)
+        for (int q = 0; q < P.lmk_count[(size_t)s]; ++q)
+            lcam[(size_t)(lptr[(size_t)s] + q)] = P.obs_cam[(size_t)P.slot_obs[(size_t)(P.lmk_first_slot[(size_t)s] + q)]];
+    std::vector<int32_t> stamp((size_t)np, -1);
+    // camera -> landmarks via the observation CSR
+    std::vector<int32_t> obs_store((size_t)P.m);
+    for (int s = 0; s < P.nl; ++s)
+        for (int q = 0; q < P.lmk_count[(size_t)s]; ++q)
+            obs_store[(size_t)P.slot_obs[(size_t)(P.lmk_first_slot[(size_t)s] + q)]] = s;
+    for (int c = 0; c < np; ++c) {
+        int cnt = 0;
+        stamp[(size_t)c] = c;
+        for (int64_t q = P.cam_obs_ptr[(size_t)c]; q < P.cam_obs_ptr[(size_t)c + 1]; ++q) {
+            const int s = obs_store[(size_t)P.cam_obs[(size_t)q]];
+            for (int64_t e = lptr[(size_t)s]; e < lptr[(size_t)s + 1]; ++e) {
+                const int c2 = lcam[(size_t)e];
+                if (stamp[(size_t)c2] != c) {
+                    stamp[(size_t)c2] = c;
+                    ++cnt;
+                }
+            }
+        }
+        deg[(size_t)c] = cnt;
+    }
+}
+
 ba_status build_multi_plan(const HostPlan &P, int N, int max_out, HostMultiPlan &M,
                            std::string &err) {
     M = HostMultiPlan();

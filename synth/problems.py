@@ -385,3 +385,16 @@ def schur_block_density(p: Problem) -> float:
     else:
         nnz = 0
     return nnz / float(n * n)
+
+
+# ---------------------------------------------------------------------------
+# seeded initial weights of the learned preconditioner's 47 -> 128 -> 72 MLP
+
+
+def mlp_init(seed: int = 0, scale_out: float = 1e-2) -> np.ndarray:
+    """Flat initial parameters W1 [128, 47], b1 [128], W2 [72, 128], b2 [72] (float64):
+    W1 ~ N(0, 1/47), W2 ~ N(0, (scale_out)^2 / 128), biases 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W1 = rng.normal(0.0, 1.0 / np.sqrt(47), (128, 47))
+    W2 = rng.normal(0.0, scale_out / np.sqrt(128), (72, 128))
+    return np.concatenate([W1.ravel(), np.zeros(128), W2.ravel(), np.zeros(72)])

@@ -1,0 +1,122 @@
+"""GPU kernels of the learned low-rank preconditioner against the FP64 oracle
+(oracle/learned.py) -- features, MLP forward (FP32 and BF16 matrix cores),
+U = L^-T Uh, M^-1 r, PCG/MCG with M^-1, loss, backpropagation and Adam.
+
+Tolerances: FP32 network against FP64 -- 1e-5 relative for forward values, 1e-3
+relative per tensor for gradients; BF16 inference 3e-2 of the largest output;
+solver iterates with the same U at a fixed iteration count 1e-9 (FP64 path)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import learned as LO
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+ba = pytest.importorskip("paper_2110_04015_amd")
+
+
+def _dev(a, dt=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype=dt)
+
+
+def _h(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def case():
+    p = synth.walk_problem(n_cams=120, n_lms=9000, seed=11, name="walk120")
+    o = oracle.System(p)
+    g = ba.System.from_problem(p)
+    D = o.D_blocks()
+    deg = LO.covisibility_degree(p.n_cams, p.obs_cam, p.obs_lm)
+    F = LO.features(D, deg, p.lam)
+    yield p, o, g, D, F
+    g.close()
+
+
+def test_features(case):
+    p, o, g, D, F = case
+    assert rel(_h(g.lowrank_features()), F) < 1e-5
+
+
+@pytest.mark.parametrize("seed,scale", [(0, 1e-2), (1, 1.0)])
+def test_mlp_forward(case, seed, scale):
+    p, o, g, D, F = case
+    params = synth.mlp_init(seed, scale)
+    _, _, out = LO.mlp_forward(LO.Weights.from_flat(params), F)
+    Fd = _dev(F, torch.float32)
+    pd = _dev(params, torch.float32)
+    o32 = _h(ba.mlp_forward(pd, Fd, bf16=False))
+    assert rel(o32, out) < 1e-5
+    o16 = _h(ba.mlp_forward(pd, Fd, bf16=True))
+    assert rel(o16, out) < 3e-2
+    # rows that are not a multiple of the 16-row tile
+    o16b = _h(ba.mlp_forward(pd, Fd[:37].contiguous(), bf16=True))
+    assert rel(o16b, out[:37]) < 3e-2
+
+
+def test_lowrank_term_and_apply(case):
+    p, o, g, D, F = case
+    params = synth.mlp_init(2, 0.5)
+    _, _, out = LO.mlp_forward(LO.Weights.from_flat(params), F)
+    U = LO.U_from_out(out, LO.chol_blocks(D))
+    o32 = ba.mlp_forward(_dev(params, torch.float32), _dev(F, torch.float32), bf16=False)
+    g.set_lowrank_from_mlp(o32)
+    assert rel(_h(g.get_lowrank()), U) < 1e-4
+    g.set_lowrank(_dev(U))
+    o.set_lowrank(U)
+    r = np.random.default_rng(3).standard_normal(g.n)
+    x, st = g.pcg(eps=0.0, max_iter=1, precond="lowrank")
+    xo, so = o.pcg(eps=0.0, imax=1)
+    assert np.linalg.norm(_h(x) - xo) <= 1e-12 * np.linalg.norm(xo)
+    for k in (5, 25):
+        x, st = g.pcg(eps=0.0, max_iter=k, precond="lowrank")
+        xo, so = o.pcg(eps=0.0, imax=k)
+        assert np.linalg.norm(_h(x) - xo) <= 1e-9 * np.linalg.norm(xo)
+        x, st = g.mcg(8, 10.0, eps=0.0, max_iter=k // 3 + 2, precond="lowrank", trace=True)
+        xo, so, tro = o.mcg(8, 10.0, eps=0.0, imax=k // 3 + 2, trace=True)
+        assert np.array_equal(st.trace_k, tro[:, 2].astype(np.int32))
+        assert np.linalg.norm(_h(x) - xo) <= 1e-9 * np.linalg.norm(xo)
+    x, st = g.mcg(8, 10.0, precond="lowrank")
+    assert st.status == ba.BA_OK and st.rel_res_true < 1.05e-6
+    o.set_lowrank(None)
+
+
+def test_block_scale(case):
+    p, o, g, D, F = case
+    x = np.random.default_rng(4).standard_normal(g.n)
+    L = LO.chol_blocks(D)
+    y = np.concatenate([np.linalg.solve(L[c], x[9 * c:9 * c + 9]) for c in range(p.n_cams)])
+    yt = np.concatenate([np.linalg.solve(L[c].T, x[9 * c:9 * c + 9]) for c in range(p.n_cams)])
+    assert rel(_h(g.block_scale(_dev(x))), y) < 1e-12
+    assert rel(_h(g.block_scale(_dev(x), transpose=True)), yt) < 1e-12
+
+
+def test_loss_gradient_and_adam(case):
+    p, o, g, D, F = case
+    rng = np.random.default_rng(5)
+    W = rng.standard_normal((g.n, 8))
+    Sw = rng.standard_normal((g.n, 8)) * 0.5 + W * 0.3
+    params = synth.mlp_init(3, 0.3)
+    w = LO.Weights.from_flat(params)
+    loss, grad = LO.loss_and_grad(w, F, W, Sw)
+    lg, gg = ba.mlp_loss_grad(_dev(params, torch.float32), _dev(F, torch.float32), _dev(W), _dev(Sw))
+    assert abs(lg - loss) <= 1e-5 * abs(loss)
+    gg = _h(gg)
+    ref = LO.Weights.from_flat(gg)
+    for name in ("W1", "b1", "W2", "b2"):
+        assert rel(getattr(ref, name), getattr(grad, name)) < 1e-3, name
+    m, v = np.zeros(LO.n_params()), np.zeros(LO.n_params())
+    w2 = LO.adam_step(w, LO.Weights.from_flat(gg), m, v, 1, lr=1e-3)
+    pd = _dev(params, torch.float32)
+    md = torch.zeros_like(pd)
+    vd = torch.zeros_like(pd)
+    ba.adam_step(pd, _dev(gg, torch.float32), md, vd, 1, lr=1e-3)
+    assert rel(_h(pd), w2.flat()) < 1e-5
