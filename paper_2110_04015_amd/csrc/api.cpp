@@ -119,7 +119,7 @@ void free_all(ba_system *s) {
 }
 
 SchurArgs schur_args(ba_system *s, int precision) {
-    SchurArgs a;
+    SchurArgs a{};
     a.J = precision == 1 ? (const void *)s->J32 : precision == 2 ? (const void *)s->J16 : (const void *)s->J64;
     a.precision = precision;
     a.meta = s->meta;
@@ -135,6 +135,7 @@ SchurArgs schur_args(ba_system *s, int precision) {
     a.cam_part_ptr = s->cam_part_ptr;
     a.dU = s->dU;
     a.np = s->np;
+    a.done = nullptr;
     return a;
 }
 
@@ -231,7 +232,7 @@ ba_status ensure_multi(ba_system *s, int N) {
 }
 
 MultiArgs multi_args(ba_system *s, int precision) {
-    MultiArgs a;
+    MultiArgs a{};
     a.J = precision == 1 ? (const void *)s->J32 : precision == 2 ? (const void *)s->J16 : (const void *)s->J64;
     a.precision = precision;
     a.meta = s->meta;
@@ -736,7 +737,14 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     int64_t *blk_dp = reinterpret_cast<int64_t *>(blk_k + hc + 2);
     if ((st = ensure_vec(s, (size_t)n * 4 + SC_COUNT)) != BA_OK) return st;
     if ((st = ensure_red(s, (size_t)kRedBlocks * (64 * 64 + 64))) != BA_OK) return st;
-    if (!s->hscratch && (st = dalloc(&s->hscratch, (size_t)kHistScratch)) != BA_OK) return st;
+    // split-K scratch of the history products: at least one column slice of 64 outputs
+    const int64_t hs_need = std::max<int64_t>(kHistScratch, 64 * n);
+    if (s->hscratch_cap < hs_need) {
+        dfree(s->hscratch);
+        s->hscratch_cap = 0;
+        if ((st = dalloc(&s->hscratch, (size_t)hs_need)) != BA_OK) return st;
+        s->hscratch_cap = hs_need;
+    }
     double *r = s->vec, *z = r + n, *tmp = z + n, *sc = tmp + 2 * n;
     double *red = s->red;
     const int gs = s->np / N;
@@ -826,7 +834,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, kn, beta, q);
             // P_{i+1} = Z - sum P_j beta ; multidirectional: Q_{i+1} = S Z - sum Q_j beta (eq. (19))
             launch_update_pq(n, (int)hcols, kn, Ph, Qh, beta, z, multi ? 1 : 0, gs, N, multi ? Qn : nullptr, Pn,
-                             multi ? Qn : nullptr, s->hscratch, kHistScratch, q);
+                             multi ? Qn : nullptr, s->hscratch, s->hscratch_cap, q);
             if (!multi) matvec(s, sa, Pn, Qn);                           // Q_{i+1} = S P_{i+1}
             HIPCHK(hipGetLastError());
             hoff.push_back((int32_t)hcols);

@@ -136,6 +136,7 @@ struct ba_system {
     int64_t hist_cap_cols = 0;
     double *small = nullptr;        // MCG small dense storage
     double *hscratch = nullptr;     // split-K partials of the history products
+    int64_t hscratch_cap = 0;       // doubles
     double *refine_buf = nullptr;   // mixed precision: outer residual, inner right-hand side, update
     double *Ulr = nullptr;          // learned low-rank preconditioner term, n x 8 (row-major), or null
     int32_t *degree = nullptr;      // covisibility degree per camera (learned features)

@@ -795,6 +795,7 @@ int hist_slices(int64_t n, int h, int kn, int64_t scratch_doubles) {
     int s = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
     s = std::min(s, std::max(1, h / 16));
     s = std::min(s, 64);
+    // the caller guarantees scratch_doubles >= kn * n (one slice)
     const int64_t per = (int64_t)kn * n;
     if (per > 0) s = (int)std::max<int64_t>(1, std::min<int64_t>(s, scratch_doubles / per));
     return std::max(1, s);

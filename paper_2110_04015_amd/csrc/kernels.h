@@ -62,19 +62,19 @@ void launch_cameras(int np, const int64_t *cam_ptr, const int64_t *cam_obs, cons
 
 // ---- Schur products (k_schur.hip)
 struct SchurArgs {
-    const void *J;                 // tile stream in the chosen precision
-    int precision;                 // 0 FP64, 1 FP32, 2 BF16
-    const uint32_t *meta;
-    const int32_t *tile_lmk_base;
-    const double *vinv;
-    const int32_t *chunk_tile, *chunk_part, *part_cam, *part_dst;
-    int n_chunks;
-    int max_slots;
-    double *partial;
-    const int32_t *cam_part_ptr;
-    const double *dU;
-    int np;
-    const double *done;            // nullable: when *done != 0 the launch does nothing
+    const void *J = nullptr;                 // tile stream in the chosen precision
+    int precision = 0;                       // 0 FP64, 1 FP32, 2 BF16
+    const uint32_t *meta = nullptr;
+    const int32_t *tile_lmk_base = nullptr;
+    const double *vinv = nullptr;
+    const int32_t *chunk_tile = nullptr, *chunk_part = nullptr, *part_cam = nullptr, *part_dst = nullptr;
+    int n_chunks = 0;
+    int max_slots = 0;
+    double *partial = nullptr;
+    const int32_t *cam_part_ptr = nullptr;
+    const double *dU = nullptr;
+    int np = 0;
+    const double *done = nullptr;            // nullable: when *done != 0 the launch does nothing
 };
 // y = S v (partials then the camera reduction)
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s);
@@ -82,25 +82,25 @@ void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s);
 void launch_schur_reduce(const SchurArgs &a, const double *v, double *y, hipStream_t s);
 
 struct MultiArgs {
-    const void *J;
-    int precision;
-    const uint32_t *meta;          // for the landmark index inside the tile
-    const uint32_t *mmeta;
-    const int32_t *slot_cam;
-    const uint8_t *pair_ll;
-    const uint32_t *tile_oidx;
-    const uint16_t *oidx;
-    const uint16_t *slot_ooff;
-    const int32_t *tile_lmk_base;
-    const double *vinv;
-    const int32_t *chunk_tile, *chunk_part;
-    int n_chunks, max_out;
-    double *partial;
-    const int32_t *part_dst;
-    const int32_t *cg_ptr;
-    const double *dU;
-    const int32_t *group;
-    int np, N;
+    const void *J = nullptr;
+    int precision = 0;
+    const uint32_t *meta = nullptr;          // for the landmark index inside the tile
+    const uint32_t *mmeta = nullptr;
+    const int32_t *slot_cam = nullptr;
+    const uint8_t *pair_ll = nullptr;
+    const uint32_t *tile_oidx = nullptr;
+    const uint16_t *oidx = nullptr;
+    const uint16_t *slot_ooff = nullptr;
+    const int32_t *tile_lmk_base = nullptr;
+    const double *vinv = nullptr;
+    const int32_t *chunk_tile = nullptr, *chunk_part = nullptr;
+    int n_chunks = 0, max_out = 0;
+    double *partial = nullptr;
+    const int32_t *part_dst = nullptr;
+    const int32_t *cg_ptr = nullptr;
+    const double *dU = nullptr;
+    const int32_t *group = nullptr;
+    int np = 0, N = 0;
 };
 // Y[p] = S (z restricted to subset p), Y column-major [N][n]
 void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s);
