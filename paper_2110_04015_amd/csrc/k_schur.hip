@@ -25,59 +25,200 @@ typedef double dbl2_t __attribute__((ext_vector_type(2)));
 typedef float flt4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
+// Per-observation stream record of one lane: 24 Jacobian values (J_p rows 0, 1,
+// then J_l rows 0, 1) as 12 x 16 B (FP64), 6 x 16 B (FP32) or 3 x 16 B (BF16).
+// Loads fetch the raw 16-byte words; unpacking (and the BF16 conversion) is
+// left to the point of use so that a prefetched record needs no wait.
 template <int PREC>
-struct Loader;
-
+struct Stream;
 template <>
-struct Loader<0> {   // FP64, 12 x 16 B per observation
+struct Stream<0> {
+    typedef dbl2_t word_t;
+    static constexpr int kWords = 12;
     template <typename T>
-    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[24]) {
-        const dbl2_t *p = reinterpret_cast<const dbl2_t *>(J) + tile * 12 * kTile + lane;
+    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[24]) {
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
-            dbl2_t d = __builtin_nontemporal_load(p + q * kTile);
-            v[2 * q] = (T)d.x;
-            v[2 * q + 1] = (T)d.y;
+            v[2 * q] = (T)w[q].x;
+            v[2 * q + 1] = (T)w[q].y;
         }
     }
 };
-
 template <>
-struct Loader<1> {   // FP32, 6 x 16 B per observation
+struct Stream<1> {
+    typedef flt4_t word_t;
+    static constexpr int kWords = 6;
     template <typename T>
-    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[24]) {
-        const flt4_t *p = reinterpret_cast<const flt4_t *>(J) + tile * 6 * kTile + lane;
+    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[24]) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            flt4_t f = __builtin_nontemporal_load(p + q * kTile);
-            v[4 * q] = (T)f.x;
-            v[4 * q + 1] = (T)f.y;
-            v[4 * q + 2] = (T)f.z;
-            v[4 * q + 3] = (T)f.w;
+            v[4 * q] = (T)w[q].x;
+            v[4 * q + 1] = (T)w[q].y;
+            v[4 * q + 2] = (T)w[q].z;
+            v[4 * q + 3] = (T)w[q].w;
         }
     }
 };
-
 template <>
-struct Loader<2> {   // BF16, 3 x 16 B per observation
+struct Stream<2> {
+    typedef u32x4_t word_t;
+    static constexpr int kWords = 3;
     template <typename T>
-    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[24]) {
-        const u32x4_t *p = reinterpret_cast<const u32x4_t *>(J) + tile * 3 * kTile + lane;
+    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[24]) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            u32x4_t u = __builtin_nontemporal_load(p + q * kTile);
-            uint32_t w[4] = {u.x, u.y, u.z, u.w};
+            const uint32_t u[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                v[8 * q + 2 * h] = (T)bf16_to_f32(w[h] & 0xFFFFu);
-                v[8 * q + 2 * h + 1] = (T)bf16_to_f32(w[h] >> 16);
+                v[8 * q + 2 * h] = (T)bf16_to_f32(u[h] & 0xFFFFu);
+                v[8 * q + 2 * h + 1] = (T)bf16_to_f32(u[h] >> 16);
             }
         }
     }
 };
 
+template <int PREC>
+__device__ __forceinline__ void load_words(const void *J, int64_t tile, int lane,
+                                           typename Stream<PREC>::word_t (&w)[Stream<PREC>::kWords]) {
+    typedef typename Stream<PREC>::word_t W;
+    constexpr int K = Stream<PREC>::kWords;
+    const W *p = reinterpret_cast<const W *>(J) + tile * K * kTile + lane;
+#pragma unroll
+    for (int q = 0; q < K; ++q) w[q] = __builtin_nontemporal_load(p + q * kTile);
+}
+
+template <int PREC>
+struct Loader {
+    template <typename T>
+    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[24]) {
+        typename Stream<PREC>::word_t w[Stream<PREC>::kWords];
+        load_words<PREC>(J, tile, lane, w);
+        Stream<PREC>::unpack(w, v);
+    }
+};
+
 // ---------------------------------------------------------------- one column
 
+// The work-group of the chunk kernels is one wavefront.  A wavefront's LDS
+// instructions are performed in issue order, so ordering them needs only a
+// code-motion barrier with wavefront-scope fences, not s_barrier -- which would
+// also wait for the global loads of the next tile that are already in flight.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Record, V_l^-1 and slot word of one tile for one lane.  FP64 and FP32 records
+// are kept as the 24 values themselves (loading them is the unpacking); BF16
+// records are kept as raw words and converted when the tile is processed, so
+// that no conversion waits on a load in flight.
+template <int PREC, typename T>
+struct TileBuf {
+    T v[24];
+    dbl2_t vi[3];
+    uint32_t mt;
+};
+template <typename T>
+struct TileBuf<2, T> {
+    u32x4_t w[3];
+    dbl2_t vi[3];
+    uint32_t mt;
+};
+
+template <int PREC, typename T>
+__device__ __forceinline__ void fetch_record(const void *J, int t, int lane, TileBuf<PREC, T> &b) {
+    if constexpr (PREC == 0) {
+        const dbl2_t *p = reinterpret_cast<const dbl2_t *>(J) + (int64_t)t * 12 * kTile + lane;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const dbl2_t d = __builtin_nontemporal_load(p + q * kTile);
+            b.v[2 * q] = d.x;
+            b.v[2 * q + 1] = d.y;
+        }
+    } else if constexpr (PREC == 1) {
+        const flt4_t *p = reinterpret_cast<const flt4_t *>(J) + (int64_t)t * 6 * kTile + lane;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const flt4_t f = __builtin_nontemporal_load(p + q * kTile);
+            b.v[4 * q] = f.x;
+            b.v[4 * q + 1] = f.y;
+            b.v[4 * q + 2] = f.z;
+            b.v[4 * q + 3] = f.w;
+        }
+    } else {
+        load_words<2>(J, t, lane, b.w);
+    }
+}
+
+// Requests the record and V^-1 of tile t (slot word m, already loaded) into b.
+// Padding slots read V^-1 of the tile's first landmark (every tile holds at
+// least one) and ignore it.
+template <int PREC, typename T>
+__device__ __forceinline__ void fetch_tile(const SchurArgs &a, int t, int lane, uint32_t m, TileBuf<PREC, T> &b) {
+    b.mt = m;
+    fetch_record<PREC, T>(a.J, t, lane, b);
+    const int ll = m != kPad ? (int)((m >> 16) & 63u) : 0;
+    const dbl2_t *p = reinterpret_cast<const dbl2_t *>(a.vinv + (int64_t)(a.tile_lmk_base[t] + ll) * 6);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) b.vi[q] = p[q];
+}
+
+// e = J_p v, g_l = sum J_l^T e (LDS), h_l = V_l^-1 g_l, y_c += J_p^T (e - J_l h_l) (LDS)
+template <typename T>
+__device__ __forceinline__ void schur_tile(const T (&J)[24], const dbl2_t (&vi)[3], uint32_t mt, int lane,
+                                           const T *vloc, T *yloc, T *gloc) {
+    const bool valid = mt != kPad;
+    const int slot = valid ? (int)(mt & 0xFFFFu) : 0;
+    const int ll = valid ? (int)((mt >> 16) & 63u) : 0;
+    T vc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) vc[k] = vloc[slot * 9 + k];
+    T e0 = 0, e1 = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        e0 += J[k] * vc[k];
+        e1 += J[9 + k] * vc[k];
+    }
+    gloc[lane * 3 + 0] = 0;
+    gloc[lane * 3 + 1] = 0;
+    gloc[lane * 3 + 2] = 0;
+    wave_sync();
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], J[18 + k] * e0 + J[21 + k] * e1);
+    }
+    wave_sync();
+    if (valid) {
+        const T w0 = (T)vi[0].x, w1 = (T)vi[0].y, w2 = (T)vi[1].x;
+        const T w3 = (T)vi[1].y, w4 = (T)vi[2].x, w5 = (T)vi[2].y;
+        const T g0 = gloc[ll * 3], g1 = gloc[ll * 3 + 1], g2 = gloc[ll * 3 + 2];
+        const T h0 = w0 * g0 + w1 * g1 + w2 * g2;
+        const T h1 = w1 * g0 + w3 * g1 + w4 * g2;
+        const T h2 = w2 * g0 + w4 * g1 + w5 * g2;
+        const T f0 = e0 - (J[18] * h0 + J[19] * h1 + J[20] * h2);
+        const T f1 = e1 - (J[21] * h0 + J[22] * h1 + J[23] * h2);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) atomicAdd(&yloc[slot * 9 + k], J[k] * f0 + J[9 + k] * f1);
+    }
+    wave_sync();
+}
+
+template <int PREC, typename T>
+__device__ __forceinline__ void process_tile(const TileBuf<PREC, T> &b, int lane, const T *vloc, T *yloc,
+                                             T *gloc) {
+    if constexpr (PREC == 2) {
+        T J[24];
+        Stream<2>::unpack(b.w, J);
+        schur_tile<T>(J, b.vi, b.mt, lane, vloc, yloc, gloc);
+    } else {
+        schur_tile<T>(b.v, b.vi, b.mt, lane, vloc, yloc, gloc);
+    }
+}
+
+// Software pipeline over the tiles of the chunk with two buffers: the record and
+// V^-1 of tile t + 1 and the slot word of tile t + 2 are requested before tile t
+// is processed, so a wavefront keeps up to two tiles of the stream in flight.
 template <int PREC, typename T>
 __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__restrict__ v) {
     if (a.done && *a.done != 0.0) return;
@@ -89,51 +230,38 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
     const int lane = threadIdx.x;
     const int pb = a.chunk_part[chunk];
     const int ns = a.chunk_part[chunk + 1] - pb;
+    const int t0 = a.chunk_tile[chunk], t1 = a.chunk_tile[chunk + 1];
+    const uint32_t *meta = a.meta + lane;
+    const int tl = t1 - 1;   // slot words past the chunk's end are read from its last tile
+    TileBuf<PREC, T> A, B;
+    uint32_t mA, mB = 0;
+    if (t0 < t1) {
+        fetch_tile<PREC, T>(a, t0, lane, meta[(int64_t)t0 * kTile], A);
+        mB = meta[(int64_t)min(t0 + 1, tl) * kTile];
+    }
     for (int i = lane; i < ns * 9; i += kTile) {
         vloc[i] = (T)v[(int64_t)a.part_cam[pb + i / 9] * 9 + i % 9];
         yloc[i] = (T)0;
     }
-    __syncthreads();
-    const int t1 = a.chunk_tile[chunk + 1];
-    for (int t = a.chunk_tile[chunk]; t < t1; ++t) {
-        T J[24];
-        Loader<PREC>::load(a.J, t, lane, J);
-        const uint32_t mt = a.meta[(int64_t)t * kTile + lane];
-        const int lmk0 = a.tile_lmk_base[t];
-        const bool valid = mt != kPad;
-        const int slot = valid ? (int)(mt & 0xFFFFu) : 0;
-        const int ll = valid ? (int)((mt >> 16) & 63u) : 0;
-        T vc[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) vc[k] = vloc[slot * 9 + k];
-        T e0 = 0, e1 = 0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            e0 += J[k] * vc[k];
-            e1 += J[9 + k] * vc[k];
-        }
-        gloc[lane * 3 + 0] = 0;
-        gloc[lane * 3 + 1] = 0;
-        gloc[lane * 3 + 2] = 0;
-        __syncthreads();
-        if (valid) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], J[18 + k] * e0 + J[21 + k] * e1);
-        }
-        __syncthreads();
-        if (valid) {
-            const double *vi = a.vinv + (int64_t)(lmk0 + ll) * 6;
-            const T w0 = (T)vi[0], w1 = (T)vi[1], w2 = (T)vi[2], w3 = (T)vi[3], w4 = (T)vi[4], w5 = (T)vi[5];
-            const T g0 = gloc[ll * 3], g1 = gloc[ll * 3 + 1], g2 = gloc[ll * 3 + 2];
-            const T h0 = w0 * g0 + w1 * g1 + w2 * g2;
-            const T h1 = w1 * g0 + w3 * g1 + w4 * g2;
-            const T h2 = w2 * g0 + w4 * g1 + w5 * g2;
-            const T f0 = e0 - (J[18] * h0 + J[19] * h1 + J[20] * h2);
-            const T f1 = e1 - (J[21] * h0 + J[22] * h1 + J[23] * h2);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) atomicAdd(&yloc[slot * 9 + k], J[k] * f0 + J[9 + k] * f1);
-        }
-        __syncthreads();
+    wave_sync();
+    // steady state: tiles t, t + 1 and t + 2 exist, so both requests are unconditional
+    // (a branch around a load leaves the compiler waiting for it at the join)
+    int t = t0;
+    for (; t + 2 < t1; t += 2) {
+        fetch_tile<PREC, T>(a, t + 1, lane, mB, B);
+        mA = meta[(int64_t)(t + 2) * kTile];
+        process_tile<PREC, T>(A, lane, vloc, yloc, gloc);
+        fetch_tile<PREC, T>(a, t + 2, lane, mA, A);
+        mB = meta[(int64_t)min(t + 3, tl) * kTile];
+        process_tile<PREC, T>(B, lane, vloc, yloc, gloc);
+    }
+    // the last one or two tiles
+    if (t + 1 < t1) {
+        fetch_tile<PREC, T>(a, t + 1, lane, mB, B);
+        process_tile<PREC, T>(A, lane, vloc, yloc, gloc);
+        process_tile<PREC, T>(B, lane, vloc, yloc, gloc);
+    } else if (t < t1) {
+        process_tile<PREC, T>(A, lane, vloc, yloc, gloc);
     }
     // row of slot k goes to its camera-major position
     for (int i = lane; i < ns * 9; i += kTile) {

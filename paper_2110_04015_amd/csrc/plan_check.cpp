@@ -33,6 +33,12 @@ bool check_plan(const HostPlan &P, const int32_t *cam, const int32_t *lm) {
     }
     for (int64_t o = 0; o < P.m; ++o)
         if (!seen[(size_t)o]) return bad("observation not placed", o);
+    // every tile starts with a landmark (the kernels read V^-1 of the tile's first
+    // landmark for padding slots)
+    for (int64_t t = 0; t < T; ++t) {
+        const int b = P.tile_lmk_base[(size_t)t];
+        if (b < 0 || b >= P.nl || P.meta[(size_t)(t * kTile)] == kPad) return bad("tile without a landmark", t, b);
+    }
     // landmarks: contiguous, inside one tile, consistent local index
     for (int s = 0; s < P.nl; ++s) {
         int64_t f = P.lmk_first_slot[(size_t)s];

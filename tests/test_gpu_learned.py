@@ -72,10 +72,22 @@ def test_lowrank_term_and_apply(case):
     assert rel(_h(g.get_lowrank()), U) < 1e-4
     g.set_lowrank(_dev(U))
     o.set_lowrank(U)
-    r = np.random.default_rng(3).standard_normal(g.n)
-    x, st = g.pcg(eps=0.0, max_iter=1, precond="lowrank")
-    xo, so = o.pcg(eps=0.0, imax=1)
-    assert np.linalg.norm(_h(x) - xo) <= 1e-12 * np.linalg.norm(xo)
+    # A large random correction (|U| = 4.4) makes the Krylov recurrence unstable: the oracle
+    # and a NumPy PCG part by 2e-2 after 12 steps.  Iterates are compared over a few steps
+    # with it, and over many with a correction of the initial weights' size (|U| = 0.06),
+    # where the two stay within 2e-12 for 25 steps.
+    for k in (1, 5):
+        x, st = g.pcg(eps=0.0, max_iter=k, precond="lowrank")
+        xo, so = o.pcg(eps=0.0, imax=k)
+        assert np.linalg.norm(_h(x) - xo) <= 1e-12 * k * np.linalg.norm(xo)
+    x, st = g.mcg(8, 10.0, precond="lowrank")
+    assert st.status == ba.BA_OK and st.rel_res_true < 1.05e-6
+    x, st = g.pcg(precond="lowrank")
+    assert st.status == ba.BA_OK and st.rel_res_true < 1.05e-6
+    _, _, out = LO.mlp_forward(LO.Weights.from_flat(synth.mlp_init(0, 1e-2)), F)
+    U = LO.U_from_out(out, LO.chol_blocks(D))
+    g.set_lowrank(_dev(U))
+    o.set_lowrank(U)
     for k in (5, 25):
         x, st = g.pcg(eps=0.0, max_iter=k, precond="lowrank")
         xo, so = o.pcg(eps=0.0, imax=k)
@@ -84,8 +96,6 @@ def test_lowrank_term_and_apply(case):
         xo, so, tro = o.mcg(8, 10.0, eps=0.0, imax=k // 3 + 2, trace=True)
         assert np.array_equal(st.trace_k, tro[:, 2].astype(np.int32))
         assert np.linalg.norm(_h(x) - xo) <= 1e-9 * np.linalg.norm(xo)
-    x, st = g.mcg(8, 10.0, precond="lowrank")
-    assert st.status == ba.BA_OK and st.rel_res_true < 1.05e-6
     o.set_lowrank(None)
 
 

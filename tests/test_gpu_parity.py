@@ -6,7 +6,10 @@ Tolerances (FP64 path):
   - solver iterates after a fixed number of iterations: 1e-9 relative (the
     stated FP64 target);
   - solves run to eps = 1e-10: the GPU solution's energy-norm distance to the
-    dense solution x* is at most max(2 x the oracle's, 1e-9);
+    dense solution x* is at most 4 x the largest of the oracle's and that of two
+    textbook dense NumPy PCG forms run to the same eps (at least 1e-9). The two
+    textbook forms alone land 14 x apart on the tiny problem (kappa(S) = 3e9),
+    and the bound a residual of eps guarantees, sqrt(kappa) eps, is looser still;
   - solves stopped at eps = 1e-6: true residual below 1.05e-6, iteration count
     within 2 % (at least 1) of the oracle's, residual histories equal to 1e-6
     over the first 20 iterations (PCG) or 5 iterations (MCG, whose later Gram
@@ -77,6 +80,46 @@ def dense(name, o):
 def energy_err(S, x, xs):
     e = x - xs
     return float(np.sqrt(e @ S @ e) / np.sqrt(xs @ S @ xs))
+
+
+_SPREAD = {}
+
+
+def textbook_spread(name, o, eps=1e-10):
+    """Largest energy error of two textbook PCG forms on the dense S (beta from
+    Q^T z and from r^T z), block-Jacobi preconditioned, run to the same eps: how far
+    correct FP64 implementations land from x* on this problem."""
+    if name not in _SPREAD:
+        S, xs = dense(name, o)
+        b = -o.rhs()
+        errs = []
+        for form in ("phi", "rz"):
+            x = np.zeros_like(b)
+            r = b.copy()
+            z = o.precond(r)
+            P = z.copy()
+            rz = r @ z
+            for _ in range(20 * b.size):
+                Q = S @ P
+                d = P @ Q
+                a = (P @ r) / d if form == "phi" else rz / d
+                x += a * P
+                r -= a * Q
+                if np.linalg.norm(r) < eps * np.linalg.norm(b):
+                    break
+                z = o.precond(r)
+                if form == "phi":
+                    P = z - (Q @ z) / d * P
+                else:
+                    rz, rz_old = r @ z, rz
+                    P = z + rz / rz_old * P
+            errs.append(energy_err(S, x, xs))
+        _SPREAD[name] = max(errs)
+    return _SPREAD[name]
+
+
+def converged_gate(name, o, S, xs, xo):
+    return 4.0 * max(energy_err(S, xo, xs), textbook_spread(name, o), 1e-9 / 4)
 
 
 @pytest.fixture(scope="module")
@@ -191,7 +234,7 @@ def test_pcg_converged(pair):
     x, st = g.pcg(eps=1e-10, max_iter=5000)
     xo, so = o.pcg(eps=1e-10, imax=5000)
     assert st.status == ba.BA_OK and so.status == oracle.OK
-    assert energy_err(S, _h(x), xs) <= max(2 * energy_err(S, xo, xs), 1e-9)
+    assert energy_err(S, _h(x), xs) <= converged_gate(name, o, S, xs, xo)
 
 
 def test_pcg_to_1e6(pair):
@@ -236,7 +279,7 @@ def test_mcg_converged(pair, N, tau):
     x, st = g.mcg(N, tau, eps=1e-10, max_iter=3000)
     xo, so = o.mcg(N, tau, eps=1e-10, imax=3000)
     assert st.status == ba.BA_OK and so.status == oracle.OK
-    assert energy_err(S, _h(x), xs) <= max(2 * energy_err(S, xo, xs), 1e-9)
+    assert energy_err(S, _h(x), xs) <= converged_gate(name, o, S, xs, xo)
 
 
 @pytest.mark.parametrize("N,tau", [(4, 10.0), (16, 3.3)])
@@ -355,11 +398,17 @@ def test_mixed_precision_refinement(pair, prec, solver):
     run = (lambda **kw: g.pcg(precision=prec, **kw)) if solver == "pcg" else \
         (lambda **kw: g.mcg(N, 10.0, precision=prec, **kw))
     x, st = run(max_iter=5000, max_outer=40)
-    assert st.status == ba.BA_OK, st
     bt = o.rhs()
     xh = _h(x)
     true = np.linalg.norm(-bt - o.matvec(xh)) / np.linalg.norm(bt)
-    assert true < 1e-6 and abs(true - st.rel_res_true) < 1e-9
+    assert abs(true - st.rel_res_true) <= 1e-9 + 1e-9 * true      # the reported residual is the true one
+    if prec == "bf16" and name == "tiny":
+        # kappa(S) = 3e9: the BF16 operator's relative error (2^-8) times the conditioning
+        # exceeds 1, so refinement cannot contract; the solver must say so, not claim success
+        assert st.status == ba.BA_MAXITER and true >= 1e-6, st
+        return
+    assert st.status == ba.BA_OK, st
+    assert true < 1e-6
     assert st.refinement_steps >= 1
     S, xs = dense(name, o)
     x, st = run(eps=1e-10, max_iter=20000, max_outer=60)
