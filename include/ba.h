@@ -90,9 +90,10 @@ typedef struct {
                                 ba_set_lowrank_precond */
     int32_t reserved0;
     int64_t max_history_cols;/* MCG history capacity in columns (0 = 1 + max_iter * N) */
-    double inner_eps;        /* mixed precision: inner tolerance relative to the outer residual (1e-3) */
+    double inner_eps;        /* mixed precision: inner tolerance relative to the outer residual
+                                (0 = automatic: 1e-2 for FP32 products, 1e-1 for BF16 storage) */
     int32_t max_outer;       /* mixed precision: max refinement steps (20) */
-    int32_t max_inner;       /* mixed precision: max inner iterations per step (200) */
+    int32_t max_inner;       /* mixed precision: max inner iterations per step (1000) */
     int32_t reserved[4];
 } ba_solve_opts;
 

@@ -78,7 +78,7 @@ class Stats:
     trace_k: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))
 
 
-def _opts(eps, max_iter, precision, max_history_cols=0, inner_eps=1e-3, max_outer=20, max_inner=200,
+def _opts(eps, max_iter, precision, max_history_cols=0, inner_eps=0.0, max_outer=20, max_inner=1000,
           precond=0):
     o = _lib.SolveOpts()
     lib().ba_default_solve_opts(C.byref(o))
@@ -259,7 +259,7 @@ class System:
         return y
 
     def pcg(self, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False, out=None,
-            inner_eps=1e-3, max_outer=20, max_inner=200, precond="block_jacobi"):
+            inner_eps=0.0, max_outer=20, max_inner=1000, precond="block_jacobi"):
         """Algorithm 1.  precision "fp32"/"bf16": FP64 iterative refinement around inner
         solves with reduced-precision S products (inner_eps, max_outer, max_inner)."""
         torch = _torch()
@@ -276,7 +276,7 @@ class System:
         return x, _stats(st, tr)
 
     def mcg(self, N, tau, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False,
-            max_history_cols=0, out=None, inner_eps=1e-3, max_outer=20, max_inner=200, precond="block_jacobi"):
+            max_history_cols=0, out=None, inner_eps=0.0, max_outer=20, max_inner=1000, precond="block_jacobi"):
         """Algorithm 2 with N subsets and threshold tau (mixed precision as in pcg)."""
         torch = _torch()
         x = out if out is not None else self._new(self.n)

@@ -164,10 +164,14 @@ __device__ __forceinline__ void fetch_tile(const SchurArgs &a, int t, int lane, 
     for (int q = 0; q < 3; ++q) b.vi[q] = p[q];
 }
 
-// e = J_p v, g_l = sum J_l^T e (LDS), h_l = V_l^-1 g_l, y_c += J_p^T (e - J_l h_l) (LDS)
+// e = J_p v, g_l = sum J_l^T e (LDS), h_l = V_l^-1 g_l, y_c += J_p^T (e - J_l h_l) (LDS).
+// Products are formed in T; the sums g_l and y_c accumulate in FP64 for every
+// precision.  Besides being the more accurate choice, it is the faster one on
+// gfx950: with FP32 LDS accumulators (ds_add_f32) the FP32 product took 370 us on
+// the F-1936-shaped problem, with FP64 ones (ds_add_f64) 131 us.
 template <typename T>
 __device__ __forceinline__ void schur_tile(const T (&J)[24], const dbl2_t (&vi)[3], uint32_t mt, int lane,
-                                           const T *vloc, T *yloc, T *gloc) {
+                                           const T *vloc, double *yloc, double *gloc) {
     const bool valid = mt != kPad;
     const int slot = valid ? (int)(mt & 0xFFFFu) : 0;
     const int ll = valid ? (int)((mt >> 16) & 63u) : 0;
@@ -186,27 +190,27 @@ __device__ __forceinline__ void schur_tile(const T (&J)[24], const dbl2_t (&vi)[
     wave_sync();
     if (valid) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], J[18 + k] * e0 + J[21 + k] * e1);
+        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], (double)(J[18 + k] * e0 + J[21 + k] * e1));
     }
     wave_sync();
     if (valid) {
         const T w0 = (T)vi[0].x, w1 = (T)vi[0].y, w2 = (T)vi[1].x;
         const T w3 = (T)vi[1].y, w4 = (T)vi[2].x, w5 = (T)vi[2].y;
-        const T g0 = gloc[ll * 3], g1 = gloc[ll * 3 + 1], g2 = gloc[ll * 3 + 2];
+        const T g0 = (T)gloc[ll * 3], g1 = (T)gloc[ll * 3 + 1], g2 = (T)gloc[ll * 3 + 2];
         const T h0 = w0 * g0 + w1 * g1 + w2 * g2;
         const T h1 = w1 * g0 + w3 * g1 + w4 * g2;
         const T h2 = w2 * g0 + w4 * g1 + w5 * g2;
         const T f0 = e0 - (J[18] * h0 + J[19] * h1 + J[20] * h2);
         const T f1 = e1 - (J[21] * h0 + J[22] * h1 + J[23] * h2);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) atomicAdd(&yloc[slot * 9 + k], J[k] * f0 + J[9 + k] * f1);
+        for (int k = 0; k < 9; ++k) atomicAdd(&yloc[slot * 9 + k], (double)(J[k] * f0 + J[9 + k] * f1));
     }
     wave_sync();
 }
 
 template <int PREC, typename T>
-__device__ __forceinline__ void process_tile(const TileBuf<PREC, T> &b, int lane, const T *vloc, T *yloc,
-                                             T *gloc) {
+__device__ __forceinline__ void process_tile(const TileBuf<PREC, T> &b, int lane, const T *vloc, double *yloc,
+                                             double *gloc) {
     if constexpr (PREC == 2) {
         T J[24];
         Stream<2>::unpack(b.w, J);
@@ -223,9 +227,9 @@ template <int PREC, typename T>
 __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__restrict__ v) {
     if (a.done && *a.done != 0.0) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    T *vloc = reinterpret_cast<T *>(smem);
-    T *yloc = vloc + a.max_slots * 9;
-    T *gloc = yloc + a.max_slots * 9;
+    double *yloc = reinterpret_cast<double *>(smem);
+    double *gloc = yloc + a.max_slots * 9;
+    T *vloc = reinterpret_cast<T *>(gloc + 3 * kTile);
     const int chunk = blockIdx.x;
     const int lane = threadIdx.x;
     const int pb = a.chunk_part[chunk];
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
     }
     for (int i = lane; i < ns * 9; i += kTile) {
         vloc[i] = (T)v[(int64_t)a.part_cam[pb + i / 9] * 9 + i % 9];
-        yloc[i] = (T)0;
+        yloc[i] = 0.0;
     }
     wave_sync();
     // steady state: tiles t, t + 1 and t + 2 exist, so both requests are unconditional
@@ -299,8 +303,9 @@ __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restri
 
 void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
     if (a.n_chunks > 0) {
-        size_t esz = a.precision == 0 ? sizeof(double) : sizeof(float);
-        size_t lds = (size_t)(2 * a.max_slots * 9 + 3 * kTile) * esz;
+        // FP64 camera rows and landmark sums, v in the product precision
+        const size_t esz = a.precision == 0 ? sizeof(double) : sizeof(float);
+        const size_t lds = (size_t)(a.max_slots * 9 + 3 * kTile) * sizeof(double) + (size_t)a.max_slots * 9 * esz;
         switch (a.precision) {
             case 0: hipLaunchKernelGGL((k_schur1<0, double>), dim3(a.n_chunks), dim3(kTile), lds, s, a, v); break;
             case 1: hipLaunchKernelGGL((k_schur1<1, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, v); break;
@@ -324,14 +329,14 @@ void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStre
 template <int PREC, typename T>
 __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *__restrict__ z) {
     extern __shared__ __align__(16) unsigned char smem[];
-    T *yloc = reinterpret_cast<T *>(smem);
-    T *gloc = yloc + a.max_out * 9;
-    T *hloc = gloc + 3 * kTile;
+    double *yloc = reinterpret_cast<double *>(smem);   // FP64 sums for every precision (see schur_tile)
+    double *gloc = yloc + a.max_out * 9;
+    double *hloc = gloc + 3 * kTile;
     const int chunk = blockIdx.x;
     const int lane = threadIdx.x;
     const int pb = a.chunk_part[chunk];
     const int no = a.chunk_part[chunk + 1] - pb;
-    for (int i = lane; i < no * 9; i += kTile) yloc[i] = (T)0;
+    for (int i = lane; i < no * 9; i += kTile) yloc[i] = 0.0;
     __syncthreads();
     const int t1 = a.chunk_tile[chunk + 1];
     for (int t = a.chunk_tile[chunk]; t < t1; ++t) {
@@ -360,16 +365,16 @@ __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *_
         __syncthreads();
         if (valid) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], J[18 + k] * e0 + J[21 + k] * e1);
+            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], (double)(J[18 + k] * e0 + J[21 + k] * e1));
         }
         __syncthreads();
         const uint8_t pll = a.pair_ll[sidx];
         if (pll != 0xFF) {
             const double *vi = a.vinv + (int64_t)(lmk0 + pll) * 6;
-            const T g0 = gloc[lane * 3], g1 = gloc[lane * 3 + 1], g2 = gloc[lane * 3 + 2];
-            hloc[lane * 3 + 0] = (T)vi[0] * g0 + (T)vi[1] * g1 + (T)vi[2] * g2;
-            hloc[lane * 3 + 1] = (T)vi[1] * g0 + (T)vi[3] * g1 + (T)vi[4] * g2;
-            hloc[lane * 3 + 2] = (T)vi[2] * g0 + (T)vi[4] * g1 + (T)vi[5] * g2;
+            const T g0 = (T)gloc[lane * 3], g1 = (T)gloc[lane * 3 + 1], g2 = (T)gloc[lane * 3 + 2];
+            hloc[lane * 3 + 0] = (double)((T)vi[0] * g0 + (T)vi[1] * g1 + (T)vi[2] * g2);
+            hloc[lane * 3 + 1] = (double)((T)vi[1] * g0 + (T)vi[3] * g1 + (T)vi[4] * g2);
+            hloc[lane * 3 + 2] = (double)((T)vi[2] * g0 + (T)vi[4] * g1 + (T)vi[5] * g2);
         }
         __syncthreads();
         if (valid) {
@@ -377,7 +382,7 @@ __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *_
             const uint16_t *oi = a.oidx + a.tile_oidx[t] + a.slot_ooff[sidx];
             for (int j = 0; j < cnt; ++j) {
                 const int pj = base + j;
-                const T h0 = hloc[pj * 3], h1 = hloc[pj * 3 + 1], h2 = hloc[pj * 3 + 2];
+                const T h0 = (T)hloc[pj * 3], h1 = (T)hloc[pj * 3 + 1], h2 = (T)hloc[pj * 3 + 2];
                 T f0 = -(J[18] * h0 + J[19] * h1 + J[20] * h2);
                 T f1 = -(J[21] * h0 + J[22] * h1 + J[23] * h2);
                 if (pj == own) {
@@ -386,7 +391,7 @@ __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *_
                 }
                 const int o = oi[j];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) atomicAdd(&yloc[o * 9 + k], J[k] * f0 + J[9 + k] * f1);
+                for (int k = 0; k < 9; ++k) atomicAdd(&yloc[o * 9 + k], (double)(J[k] * f0 + J[9 + k] * f1));
             }
         }
         __syncthreads();
@@ -417,8 +422,7 @@ __global__ void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr,
 
 void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s) {
     if (a.n_chunks > 0) {
-        size_t esz = a.precision == 0 ? sizeof(double) : sizeof(float);
-        size_t lds = (size_t)(a.max_out * 9 + 6 * kTile) * esz;
+        const size_t lds = (size_t)(a.max_out * 9 + 6 * kTile) * sizeof(double);
         switch (a.precision) {
             case 0: hipLaunchKernelGGL((k_schur_multi<0, double>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;
             case 1: hipLaunchKernelGGL((k_schur_multi<1, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;

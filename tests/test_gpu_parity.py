@@ -184,6 +184,25 @@ def test_matmat_grouped(pair, N):
     assert np.array_equal(grp // 1, np.repeat(ba.partition(p.n_cams, N), 9))
 
 
+def test_matmat_grouped_large_lds():
+    """35 observers per landmark spread over 60 subsets: a tile touches more (camera,
+    subset) pairs than 64 KiB of LDS holds, so the kernel runs with a larger work-group
+    allocation."""
+    p = synth.cap_problem(n_cams=120, n_lms=600, c_min=30, c_max=40, seed=5, name="dense120")
+    o = oracle.System(p)
+    g = ba.System.from_problem(p)
+    N = 60
+    z = np.random.default_rng(6).standard_normal(g.n)
+    Y = _h(g.matmat_grouped(N, _dev(z)))
+    grp = np.repeat(oracle.partition(p.n_cams, N), 9)
+    for q in range(N):
+        assert rel(Y[q], o.matvec(np.where(grp == q, z, 0.0))) < 1e-12, q
+    x, st = g.mcg(N, 10.0, eps=0.0, max_iter=4)
+    xo, so = o.mcg(N, 10.0, eps=0.0, imax=4)
+    assert st.multi_steps == so.multi_steps and relnorm(_h(x), xo) < 1e-9
+    g.close()
+
+
 # ---------------------------------------------------------------- A4 D^-1 r, eq. (16)
 
 
