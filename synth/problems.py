@@ -388,6 +388,41 @@ def schur_block_density(p: Problem) -> float:
 
 
 # ---------------------------------------------------------------------------
+# outer Levenberg-Marquardt loop support (Sec. 4.1): moving the state by a solved
+# step and linearising again.  No solver arithmetic lives here; the step comes from
+# whichever solver the caller runs.
+
+
+def cost(p: Problem) -> float:
+    """F(x) = |r(x)|^2 at the problem's linearisation point (eq. (1))."""
+    return float(np.einsum("mi,mi->", p.r, p.r))
+
+
+def relinearize(p: Problem, dx_p: np.ndarray, dx_l: np.ndarray, lam: Optional[float] = None) -> Problem:
+    """The problem linearised at the state moved by the step (dx_p, dx_l).
+
+    Camera c's 9 step entries follow J_p's parametrisation: a left rigid motion
+    (rotation vector w, translation dt: R <- exp(w) R, t <- exp(w) t + dt), then f,
+    k1, k2 added; points move by dx_l.  Observations and their pixels are kept.
+    """
+    if p.cams is None or p.points is None or p.u_obs is None:
+        raise ValueError("the problem carries no linearisation state")
+    d = np.asarray(dx_p, dtype=np.float64).reshape(p.n_cams, 9)
+    E = so3_exp(d[:, 0:3])
+    cams = {"R": np.einsum("nij,njk->nik", E, p.cams["R"]),
+            "t": np.einsum("nij,nj->ni", E, p.cams["t"]) + d[:, 3:6],
+            "f": p.cams["f"] + d[:, 6], "k1": p.cams["k1"] + d[:, 7], "k2": p.cams["k2"] + d[:, 8]}
+    X = p.points + np.asarray(dx_l, dtype=np.float64).reshape(p.n_lms, 3)
+    cam = p.obs_cam.astype(np.int64)
+    lm = p.obs_lm.astype(np.int64)
+    u, J_p, J_l, _ = project(cams, X, cam, lm)
+    return Problem(name=p.name, seed=p.seed, n_cams=p.n_cams, n_lms=p.n_lms, obs_cam=p.obs_cam,
+                   obs_lm=p.obs_lm, J_p=np.ascontiguousarray(J_p), J_l=np.ascontiguousarray(J_l),
+                   r=np.ascontiguousarray(u - p.u_obs), lam=p.lam if lam is None else float(lam),
+                   cams=cams, points=X, u_obs=p.u_obs, info=dict(p.info))
+
+
+# ---------------------------------------------------------------------------
 # seeded initial weights of the learned preconditioner's 47 -> 128 -> 72 MLP
 
 

@@ -130,3 +130,21 @@ def test_loss_gradient_and_adam(case):
     vd = torch.zeros_like(pd)
     ba.adam_step(pd, _dev(gg, torch.float32), md, vd, 1, lr=1e-3)
     assert rel(_h(pd), w2.flat()) < 1e-5
+
+
+def test_training_on_lm_systems_and_gain():
+    """Train on the systems of short LM runs (device forward, backward and Adam), then
+    compare MCG with and without the learned term on held-out seeds.  The trained network
+    must lower the probe loss and leave every solve converged; the measured gain is
+    reported (it is an outcome, not a gate)."""
+    from paper_2110_04015_amd import learned as LN
+    samples = LN.collect(range(3), lm_iters=2, n_cams=120)
+    assert len(samples) == 6
+    tr = LN.train(samples, epochs=8, lr=1e-4)
+    hist = tr["loss_history"]
+    assert hist[-1] < hist[0]
+    ev = LN.evaluate(tr["params"], range(10_000, 10_002), n_cams=120)
+    assert ev["all_converged"]
+    assert ev["learned_res"] < 1.05e-6 and ev["plain_res"] < 1.05e-6
+    print(f"\nprobe loss {hist[0]:.4f} -> {hist[-1]:.4f}; MCG iterations plain {ev['plain_iters']:.1f} "
+          f"learned {ev['learned_iters']:.1f}; ms plain {ev['plain_ms']:.2f} learned {ev['learned_ms']:.2f}")
