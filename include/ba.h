@@ -253,6 +253,53 @@ ba_status ba_plan_validate(int32_t n_cams, int32_t n_lms, int64_t n_obs, const i
                            int64_t *stats);
 const char *ba_plan_validate_error(void);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent problems solved at once, each by Algorithm 2 (Sec. 3.2) with
+ * its own tau-test, Gram blocks, Delta^+ and direction history.  The batch is the
+ * block-diagonal system over the concatenated problems: problem p holds cameras
+ * [c_p, c_p + cams_per_problem[p]) (c_p the sum of the counts before it) and
+ * rows [9 c_p, 9 (c_p + cams_per_problem[p])) of every batch vector. */
+typedef struct ba_batch ba_batch;
+
+typedef struct {
+    int32_t iterations;       /* inner iterations, all refinement steps together */
+    int32_t multi_steps;
+    int32_t history_cols;     /* history columns of the last inner solve */
+    int32_t refinement_steps; /* mixed precision: inner solves */
+    int32_t status;           /* ba_status of this problem */
+    int32_t reserved;
+    double rel_res_recursive; /* last inner solve, |r_i| / |r_0| */
+    double rel_res_true;      /* |b~ + S x| / |b~|, FP64 */
+    double done_ms;           /* ms from the solve's start until this problem was seen stopped */
+} ba_batch_stats;
+
+/* Builds the batch from the concatenated problem `all` (device arrays as in
+ * ba_build_system; camera and landmark indices global over the batch, every
+ * landmark observed by cameras of one problem only, one lambda for all) and the
+ * HOST array cams_per_problem[n_problems].  Tiles and chunks of the HBM layout
+ * never mix problems.  Errors as ba_build_system, plus BA_ERR_INVALID_ARG when
+ * the counts do not add up to all->n_cams or a landmark spans two problems. */
+ba_status ba_batch_build(const ba_problem_desc *all, int32_t n_problems, const int32_t *cams_per_problem,
+                         const ba_build_opts *opts, void *stream, ba_batch **out);
+void ba_batch_free(ba_batch *batch);
+/* The block-diagonal system of the batch (owned by the batch): S products,
+ * right-hand side, preconditioner blocks of all problems at once. */
+ba_system *ba_batch_system(ba_batch *batch);
+
+/* Algorithm 2 for every problem of the batch on S_p x_p = -b~_p.  x: device
+ * [9 * total cameras] (batch layout); N subsets per problem (1..64, at most the
+ * cameras of the smallest problem), tau the threshold of the tau-test.  opts as
+ * ba_mcg_solve (precision != FP64: FP64 refinement per problem around inner
+ * solves with reduced-precision S products; precond must be 0).  Every
+ * iteration is one fixed sequence of launches for all running problems, with all
+ * solver state on the device; graph_window > 0 captures that many iterations
+ * into one HIP graph per launch (0: eager launches, stop flags read every 8
+ * iterations).  stats: HOST array [n_problems] (nullable); elapsed_ms (host,
+ * nullable): wall time of the call.  Returns BA_OK when every problem reached
+ * eps, BA_MAXITER when some did not, else the first error. */
+ba_status ba_batch_mcg_solve(ba_batch *batch, int32_t N, double tau, double *x, const ba_solve_opts *opts,
+                             int32_t graph_window, ba_batch_stats *stats, double *elapsed_ms);
+
 const char *ba_status_string(int32_t status);
 const char *ba_last_error(void);
 

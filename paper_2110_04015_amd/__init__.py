@@ -17,8 +17,8 @@ from . import _lib
 from ._lib import (BA_ERR_BREAKDOWN, BA_ERR_HIP, BA_ERR_INVALID_ARG, BA_ERR_NOMEM, BA_ERR_NONFINITE,
                    BA_ERR_NOT_SPD, BA_ERR_UNSUPPORTED, BA_ERR_WORKSPACE, BA_MAXITER, BA_OK, PREC)
 
-__all__ = ["System", "BAError", "Stats", "pinv_sym", "partition", "PREC", "lib", "mlp_forward",
-           "mlp_loss_grad", "adam_step", "MLP_PARAMS"]
+__all__ = ["System", "Batch", "BatchStats", "BAError", "Stats", "pinv_sym", "partition", "PREC", "lib",
+           "mlp_forward", "mlp_loss_grad", "adam_step", "MLP_PARAMS"]
 
 MLP_PARAMS = 15432
 
@@ -151,9 +151,22 @@ class System:
         return cls(p.n_cams, p.n_lms, t(p.obs_cam, torch.int32), t(p.obs_lm, torch.int32),
                    t(p.J_p, torch.float64), t(p.J_l, torch.float64), t(p.r, torch.float64), p.lam, **kw)
 
+    @classmethod
+    def _view(cls, h, n_cams, n_lms, n_obs, device, stream):
+        """A System object over a system owned elsewhere (the block-diagonal system of a batch)."""
+        obj = cls.__new__(cls)
+        obj.h = C.c_void_p(h)
+        obj._owned = False
+        obj._stream = stream
+        obj.device = device
+        obj.n_cams, obj.n_lms, obj.n_obs = int(n_cams), int(n_lms), int(n_obs)
+        obj.n = 9 * obj.n_cams
+        return obj
+
     def close(self):
         if getattr(self, "h", None):
-            lib().ba_free_system(self.h)
+            if getattr(self, "_owned", True):
+                lib().ba_free_system(self.h)
             self.h = None
 
     def __del__(self):
@@ -345,3 +358,92 @@ def partition(n_cams: int, N: int) -> np.ndarray:
     g = np.empty(int(n_cams), dtype=np.int32)
     _check(lib().ba_partition(int(n_cams), int(N), g.ctypes.data_as(C.POINTER(C.c_int32))), "ba_partition")
     return g
+
+
+@dataclass
+class BatchStats:
+    iterations: int
+    multi_steps: int
+    history_cols: int
+    refinement_steps: int
+    status: int
+    rel_res_recursive: float
+    rel_res_true: float
+    done_ms: float
+
+
+class Batch:
+    """Independent problems solved together (ba_batch_*): one block-diagonal system,
+    Algorithm 2 per problem with all solver state on the device."""
+
+    def __init__(self, problems, device="cuda", stream=None, max_slots=0, max_tiles=0, store_fp32=False,
+                 store_bf16=False):
+        torch = _torch()
+        lams = {float(p.lam) for p in problems}
+        if len(lams) != 1:
+            raise ValueError("the problems of a batch share one lambda")
+        cams = np.array([p.n_cams for p in problems], dtype=np.int32)
+        lms = np.array([p.n_lms for p in problems], dtype=np.int64)
+        c0 = np.concatenate([[0], np.cumsum(cams)[:-1]])
+        l0 = np.concatenate([[0], np.cumsum(lms)[:-1]])
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        obs_cam = t(np.concatenate([p.obs_cam.astype(np.int64) + c for p, c in zip(problems, c0)]), torch.int32)
+        obs_lm = t(np.concatenate([p.obs_lm.astype(np.int64) + l for p, l in zip(problems, l0)]), torch.int32)
+        J_p = t(np.concatenate([p.J_p for p in problems]), torch.float64)
+        J_l = t(np.concatenate([p.J_l for p in problems]), torch.float64)
+        r = t(np.concatenate([p.r for p in problems]), torch.float64)
+        m = int(obs_cam.numel())
+        d = _lib.ProblemDesc()
+        d.n_cams, d.n_lms, d.n_obs, d.d_p = int(cams.sum()), int(lms.sum()), m, 9
+        d.obs_cam = _dev_ptr(obs_cam, torch.int32, m, "obs_cam")
+        d.obs_lm = _dev_ptr(obs_lm, torch.int32, m, "obs_lm")
+        d.J_p = _dev_ptr(J_p, torch.float64, m * 18, "J_p")
+        d.J_l = _dev_ptr(J_l, torch.float64, m * 6, "J_l")
+        d.r = _dev_ptr(r, torch.float64, m * 2, "r")
+        d.lam = lams.pop()
+        o = _lib.BuildOpts()
+        o.store_fp32, o.store_bf16 = int(store_fp32), int(store_bf16)
+        o.max_slots, o.max_tiles = int(max_slots), int(max_tiles)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = obs_cam.device
+        h = C.c_void_p()
+        cp = np.ascontiguousarray(cams)
+        _check(lib().ba_batch_build(C.byref(d), len(problems), cp.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(o),
+                                    _stream_handle(self._stream), C.byref(h)), "ba_batch_build")
+        self.h = h
+        self.B = len(problems)
+        self.cams = cams
+        self.row0 = (9 * c0).astype(np.int64)
+        self.n = 9 * int(cams.sum())
+        self.system = System._view(lib().ba_batch_system(h), d.n_cams, d.n_lms, m, self.device, self._stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ba_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def split(self, v):
+        """Per-problem views of a batch vector."""
+        return [v[int(a):int(a) + 9 * int(c)] for a, c in zip(self.row0, self.cams)]
+
+    def mcg(self, N, tau, eps=1e-6, max_iter=1000, precision="fp64", graph_window=8, inner_eps=0.0,
+            max_outer=20, max_inner=1000, max_history_cols=0, out=None):
+        """Algorithm 2 for every problem; returns (x, [BatchStats], elapsed ms, worst status)."""
+        torch = _torch()
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device=self.device)
+        o = _opts(eps, max_iter, precision, max_history_cols=max_history_cols, inner_eps=inner_eps,
+                  max_outer=max_outer, max_inner=max_inner)
+        st = (_lib.BatchStats * self.B)()
+        ms = C.c_double()
+        rc = _check(lib().ba_batch_mcg_solve(self.h, int(N), float(tau), _dev_ptr(x, torch.float64, self.n, "x"),
+                                             C.byref(o), int(graph_window), st, C.byref(ms)), "ba_batch_mcg_solve")
+        stats = [BatchStats(s.iterations, s.multi_steps, s.history_cols, s.refinement_steps, s.status,
+                            s.rel_res_recursive, s.rel_res_true, s.done_ms) for s in st]
+        return x, stats, ms.value, rc
+

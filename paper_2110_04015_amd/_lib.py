@@ -39,6 +39,12 @@ class SolveStats(C.Structure):
                 ("trace_t", C.POINTER(C.c_double)), ("trace_k", C.POINTER(C.c_int32))]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("multi_steps", C.c_int32), ("history_cols", C.c_int32),
+                ("refinement_steps", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double), ("done_ms", C.c_double)]
+
+
 # (name, restype, argtypes) for every entry point of include/ba.h
 SIGNATURES = [
     ("ba_default_solve_opts", None, [C.POINTER(SolveOpts)]),
@@ -71,6 +77,12 @@ SIGNATURES = [
     ("ba_plan_validate", C.c_int, [C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                    C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int64)]),
     ("ba_plan_validate_error", C.c_char_p, []),
+    ("ba_batch_build", C.c_int, [C.POINTER(ProblemDesc), C.c_int32, C.POINTER(C.c_int32), C.POINTER(BuildOpts),
+                                 C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("ba_batch_free", None, [C.c_void_p]),
+    ("ba_batch_system", C.c_void_p, [C.c_void_p]),
+    ("ba_batch_mcg_solve", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
+                                     C.POINTER(BatchStats), C.POINTER(C.c_double)]),
     ("ba_status_string", C.c_char_p, [C.c_int32]),
     ("ba_last_error", C.c_char_p, []),
 ]

@@ -75,6 +75,7 @@ void free_multi(DevMulti &m) {
     dfree(m.part_dst);
     dfree(m.partial);
     dfree(m.group);
+    dfree(m.chunk_seg);
     m = DevMulti();
 }
 
@@ -111,6 +112,8 @@ void free_all(ba_system *s) {
     dfree(s->Ulr);
     dfree(s->degree);
     dfree(s->lr_proj);
+    dfree(s->seg_cam);
+    dfree(s->seg_chunk);
     if (s->host_pinned) (void)hipHostFree(s->host_pinned);
     s->host_pinned = nullptr;
     free_multi(s->multi);
@@ -200,7 +203,21 @@ ba_status ensure_multi(ba_system *s, int N) {
     free_multi(s->multi);
     HostMultiPlan mp;
     std::string err;
-    ba_status st = build_multi_plan(s->plan, N, 512, mp, err);
+    // subsets: Sec. 3.2's partition of the poses; in a batch, of each problem's poses
+    std::vector<int32_t> grp((size_t)s->np);
+    const std::vector<int32_t> &seg = s->plan.cam_seg;
+    if (seg.empty()) {
+        partition_groups(s->np, N, grp.data());
+    } else {
+        for (int c0 = 0; c0 < s->np;) {
+            int c1 = c0;
+            while (c1 < s->np && seg[(size_t)c1] == seg[(size_t)c0]) ++c1;
+            if (c1 - c0 < N) return fail(BA_ERR_INVALID_ARG, "N exceeds the cameras of a problem of the batch");
+            partition_groups(c1 - c0, N, grp.data() + c0);
+            c0 = c1;
+        }
+    }
+    ba_status st = build_multi_plan(s->plan, N, 512, mp, err, grp.data());
     if (st != BA_OK) return fail(st, err);
     // LDS of the multidirectional kernel: max_out rows of 9 plus 2 x 64 x 3 values (FP64),
     // up to the device's work-group limit (160 KiB on gfx950: 2,232 rows)
@@ -226,9 +243,8 @@ ba_status ensure_multi(ba_system *s, int N) {
     if ((st = upload(&m.cg_ptr, mp.cg_ptr, q)) != BA_OK) return st;
     if ((st = upload(&m.cg_idx, mp.cg_idx, q)) != BA_OK) return st;
     if ((st = upload(&m.part_dst, mp.part_dst, q)) != BA_OK) return st;
-    std::vector<int32_t> grp((size_t)s->np);
-    partition_groups(s->np, N, grp.data());
     if ((st = upload(&m.group, grp, q)) != BA_OK) return st;
+    if ((st = upload(&m.chunk_seg, mp.chunk_seg, q)) != BA_OK) return st;
     if ((st = dalloc(&m.partial, (size_t)std::max<int64_t>(mp.n_part, 1) * 9)) != BA_OK) return st;
     m.N = N;
     m.n_chunks = mp.n_chunks;
@@ -376,7 +392,8 @@ void ba_free_system(ba_system *sys) {
     delete sys;
 }
 
-ba_status ba_build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream, ba_system **out) {
+static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream,
+                              const int32_t *cam_seg, ba_system **out) {
     if (!out) return fail(BA_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!d) return fail(BA_ERR_INVALID_ARG, "desc is NULL");
@@ -413,8 +430,13 @@ ba_status ba_build_system(const ba_problem_desc *d, const ba_build_opts *opts, v
         hipStreamSynchronize(q) != hipSuccess)
         return bail(fail(BA_ERR_HIP, "copying the observation indices to the host failed"));
     std::string err;
-    ba_status st = build_plan(s->np, s->nl, m, hcam.data(), hlm.data(), max_slots, max_tiles, s->plan, err);
+    ba_status st = build_plan(s->np, s->nl, m, hcam.data(), hlm.data(), max_slots, max_tiles, s->plan, err,
+                              cam_seg);
     if (st != BA_OK) return bail(fail(st, err));
+    if (cam_seg) {
+        if ((st = upload(&s->seg_cam, s->plan.cam_seg, q)) != BA_OK) return bail(st);
+        if ((st = upload(&s->seg_chunk, s->plan.chunk_seg, q)) != BA_OK) return bail(st);
+    }
     const HostPlan &P = s->plan;
     const int64_t nslots = P.n_tiles * kTile;
 
@@ -490,6 +512,10 @@ ba_status ba_build_system(const ba_problem_desc *d, const ba_build_opts *opts, v
     if ((st = ensure_pinned(s)) != BA_OK) return bail(st);
     *out = s;
     return BA_OK;
+}
+
+ba_status ba_build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream, ba_system **out) {
+    return build_system(d, opts, stream, nullptr, out);
 }
 
 ba_status ba_profile_enable(ba_system *s, int32_t on) {
@@ -1106,6 +1132,426 @@ ba_status ba_adam_step(float *params, const float *grad, float *m, float *v, int
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(q));
     return BA_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+//
+// A batch is one block-diagonal system over the concatenated problems (tiles and
+// chunks never mix problems), solved by Algorithm 2 per problem with all state on
+// the device: an iteration is a fixed launch sequence (no read-back), enqueued
+// eagerly or captured into a graph window by window; the host looks at the
+// per-problem stop flags once per window.
+
+struct ba_batch {
+    ba_system *sys = nullptr;
+    int B = 0;
+    std::vector<int32_t> cam0, np;
+    // workspace for (N, cap)
+    int N = 0;
+    int64_t cap = 0;
+    BatchProb *prob = nullptr;
+    BatchDyn *dyn = nullptr;
+    int32_t *skip_single = nullptr, *skip_multi = nullptr, *off = nullptr, *count = nullptr;
+    double *alpha = nullptr, *gamma = nullptr, *gpart = nullptr, *upart = nullptr, *resid = nullptr;
+    double *r = nullptr, *z = nullptr, *pstage = nullptr, *qstage = nullptr, *Y = nullptr;
+    double *Ph = nullptr, *Qh = nullptr, *Dp = nullptr, *Phi = nullptr, *beta = nullptr;
+    int32_t *blk_off = nullptr, *blk_k = nullptr;
+    int64_t *blk_dp = nullptr;
+    double *btp = nullptr, *d = nullptr, *tmp = nullptr;
+    int32_t *host_i = nullptr;      // pinned
+    double *host_d = nullptr;       // pinned [2B]
+    // graph windows are captured on a stream of the batch (the caller's stream may be
+    // the legacy default stream, which cannot be captured), ordered by events
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+void free_batch_ws(ba_batch *b) {
+    dfree(b->prob);
+    dfree(b->dyn);
+    dfree(b->skip_single);
+    dfree(b->skip_multi);
+    dfree(b->off);
+    dfree(b->count);
+    dfree(b->alpha);
+    dfree(b->gamma);
+    dfree(b->gpart);
+    dfree(b->upart);
+    dfree(b->resid);
+    dfree(b->r);
+    dfree(b->z);
+    dfree(b->pstage);
+    dfree(b->qstage);
+    dfree(b->Y);
+    dfree(b->Ph);
+    dfree(b->Qh);
+    dfree(b->Dp);
+    dfree(b->Phi);
+    dfree(b->beta);
+    dfree(b->blk_off);
+    dfree(b->blk_k);
+    dfree(b->blk_dp);
+    dfree(b->btp);
+    dfree(b->d);
+    dfree(b->tmp);
+    b->N = 0;
+    b->cap = 0;
+}
+
+ba_status ensure_batch_ws(ba_batch *b, int N, int64_t cap) {
+    if (b->N == N && b->cap >= cap && b->prob) return BA_OK;
+    free_batch_ws(b);
+    const int B = b->B;
+    const int64_t ntot = (int64_t)b->sys->np * 9;
+    std::vector<BatchProb> hp((size_t)B);
+    int64_t hb = 0, cb = 0;
+    for (int i = 0; i < B; ++i) {
+        BatchProb &p = hp[(size_t)i];
+        p.row0 = (int64_t)b->cam0[(size_t)i] * 9;
+        p.n = b->np[(size_t)i] * 9;
+        p.np = b->np[(size_t)i];
+        p.cam0 = b->cam0[(size_t)i];
+        p.gs = std::max(1, p.np / N);
+        p.cap = (int32_t)cap;
+        p.hbase = hb;
+        p.colbase = cb;
+        p.pad = 0;
+        hb += cap * (int64_t)p.n;
+        cb += cap;
+    }
+    hipStream_t q = b->sys->stream;
+    ba_status st;
+    if ((st = upload(&b->prob, hp, q)) != BA_OK) return st;
+    if ((st = dalloc(&b->dyn, (size_t)B)) != BA_OK) return st;
+    if ((st = dalloc(&b->skip_single, (size_t)B)) != BA_OK) return st;
+    if ((st = dalloc(&b->skip_multi, (size_t)B)) != BA_OK) return st;
+    if ((st = dalloc(&b->off, (size_t)B)) != BA_OK) return st;
+    if ((st = dalloc(&b->count, 1)) != BA_OK) return st;
+    if ((st = dalloc(&b->alpha, (size_t)B * kMaxBlock)) != BA_OK) return st;
+    if ((st = dalloc(&b->gamma, (size_t)B * kMaxBlock)) != BA_OK) return st;
+    if ((st = dalloc(&b->gpart, (size_t)B * kBatchGramBlocks * (size_t)(N * N + N))) != BA_OK) return st;
+    if ((st = dalloc(&b->upart, (size_t)B * kBatchVecBlocks * 2)) != BA_OK) return st;
+    if ((st = dalloc(&b->resid, (size_t)B * 2)) != BA_OK) return st;
+    for (double **v : {&b->r, &b->z, &b->pstage, &b->qstage, &b->btp, &b->d, &b->tmp})
+        if ((st = dalloc(v, (size_t)ntot)) != BA_OK) return st;
+    if ((st = dalloc(&b->Y, (size_t)ntot * N)) != BA_OK) return st;
+    if ((st = dalloc(&b->Ph, (size_t)hb)) != BA_OK) return st;
+    if ((st = dalloc(&b->Qh, (size_t)hb)) != BA_OK) return st;
+    if ((st = dalloc(&b->Dp, (size_t)cb * N)) != BA_OK) return st;
+    if ((st = dalloc(&b->Phi, (size_t)cb * N)) != BA_OK) return st;
+    if ((st = dalloc(&b->beta, (size_t)cb * N)) != BA_OK) return st;
+    if ((st = dalloc(&b->blk_off, (size_t)cb)) != BA_OK) return st;
+    if ((st = dalloc(&b->blk_k, (size_t)cb)) != BA_OK) return st;
+    if ((st = dalloc(&b->blk_dp, (size_t)cb)) != BA_OK) return st;
+    HIPCHK(hipStreamSynchronize(q));   // hp goes out of scope
+    b->N = N;
+    b->cap = cap;
+    return BA_OK;
+}
+
+BatchLaunch batch_launch(ba_batch *b, double *x) {
+    BatchLaunch L;
+    L.B = b->B;
+    L.N = b->N;
+    for (int i = 0; i < b->B; ++i) {
+        L.max_np = std::max(L.max_np, b->np[(size_t)i]);
+        L.max_n = std::max<int64_t>(L.max_n, (int64_t)b->np[(size_t)i] * 9);
+    }
+    L.ntot = (int64_t)b->sys->np * 9;
+    L.prob = b->prob;
+    L.dyn = b->dyn;
+    L.Dchol = b->sys->Dchol;
+    L.x = x;
+    L.r = b->r;
+    L.z = b->z;
+    L.pstage = b->pstage;
+    L.qstage = b->qstage;
+    L.Y = b->Y;
+    L.Ph = b->Ph;
+    L.Qh = b->Qh;
+    L.Dp = b->Dp;
+    L.Phi = b->Phi;
+    L.beta = b->beta;
+    L.alpha = b->alpha;
+    L.gamma = b->gamma;
+    L.gpart = b->gpart;
+    L.upart = b->upart;
+    L.blk_off = b->blk_off;
+    L.blk_k = b->blk_k;
+    L.blk_dp = b->blk_dp;
+    L.skip_single = b->skip_single;
+    L.skip_multi = b->skip_multi;
+    return L;
+}
+
+// one iteration of Algorithm 2 for every running problem (it = iterations done so far)
+void batch_iteration(ba_batch *b, const BatchLaunch &L, const SchurArgs &sa, const MultiArgs &ma, double tau,
+                     double eps, int max_iter, int it, hipStream_t q) {
+    launch_biter_head(L, tau, eps, max_iter, q);
+    if (L.N > 1) launch_schur_multi(ma, L.z, L.Y, q);
+    const int64_t hmax = std::min<int64_t>(b->cap, 1 + (int64_t)it * L.N);
+    launch_biter_tail(L, (int)hmax, it + 1, q);
+    launch_schur_matvec(sa, L.pstage, L.qstage, q);
+    launch_bqcopy_advance(L, q);
+}
+
+// Algorithm 2 on S x = -bt for every problem with off[b] == 0 (x of the others is set
+// to zero); at most max_iter iterations; window > 0 captures window iterations per graph.
+// Per-problem stop times (ms from t0) go to done_ms when it is given.
+ba_status batch_core(ba_batch *b, int precision, const double *bt, double *x, const int32_t *off, double tau,
+                     double eps, int max_iter, int window, std::chrono::steady_clock::time_point t0,
+                     std::vector<double> *done_ms) {
+    ba_system *s = b->sys;
+    hipStream_t q = s->stream;
+    BatchLaunch L = batch_launch(b, x);
+    SchurArgs sa = schur_args(s, precision);
+    sa.chunk_seg = s->seg_chunk;
+    sa.cam_seg = s->seg_cam;
+    sa.seg_skip = b->skip_single;
+    MultiArgs ma = b->N > 1 ? multi_args(s, precision) : MultiArgs();
+    if (b->N > 1) {
+        ma.chunk_seg = s->multi.chunk_seg;
+        ma.cam_seg = s->seg_cam;
+        ma.seg_skip = b->skip_multi;
+    }
+    launch_bstart(L, bt, nullptr, off, q);
+    launch_schur_matvec(sa, L.pstage, L.qstage, q);   // Q_0 = S P_0
+    launch_bqcopy_advance(L, q);
+    HIPCHK(hipGetLastError());
+    const int B = b->B;
+    std::vector<int32_t> was_done((size_t)B, 0);
+    const int W = window > 0 ? window : 8;
+    for (int it = 0; it < max_iter;) {
+        const int w = std::min(W, max_iter - it);
+        if (window > 0) {
+            hipStream_t gs = b->gstream;
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIPCHK(hipEventRecord(b->ev_in, q));
+            HIPCHK(hipStreamWaitEvent(gs, b->ev_in, 0));
+            HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < w; ++k) batch_iteration(b, L, sa, ma, tau, eps, max_iter, it + k, gs);
+            hipError_t e = hipStreamEndCapture(gs, &g);
+            if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) e = hipGraphLaunch(ge, gs);
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (g) (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(BA_ERR_HIP, std::string("batch graph: ") + hipGetErrorString(e));
+            HIPCHK(hipEventRecord(b->ev_out, gs));
+            HIPCHK(hipStreamWaitEvent(q, b->ev_out, 0));
+        } else {
+            for (int k = 0; k < w; ++k) batch_iteration(b, L, sa, ma, tau, eps, max_iter, it + k, q);
+        }
+        it += w;
+        HIPCHK(hipGetLastError());
+        // stop flags of every problem (one read-back per window)
+        std::vector<BatchDyn> hd((size_t)B);
+        HIPCHK(hipMemcpyAsync(hd.data(), b->dyn, sizeof(BatchDyn) * (size_t)B, hipMemcpyDeviceToHost, q));
+        HIPCHK(hipStreamSynchronize(q));
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        int running = 0;
+        for (int i = 0; i < B; ++i) {
+            if (hd[(size_t)i].done && !was_done[(size_t)i]) {
+                was_done[(size_t)i] = 1;
+                if (done_ms) (*done_ms)[(size_t)i] = ms;
+            }
+            running += !hd[(size_t)i].done;
+        }
+        if (running == 0) break;
+    }
+    return BA_OK;
+}
+
+ba_status batch_stats_from_device(ba_batch *b, std::vector<BatchDyn> &hd) {
+    hd.resize((size_t)b->B);
+    HIPCHK(hipMemcpyAsync(hd.data(), b->dyn, sizeof(BatchDyn) * (size_t)b->B, hipMemcpyDeviceToHost, b->sys->stream));
+    HIPCHK(hipStreamSynchronize(b->sys->stream));
+    return BA_OK;
+}
+
+// per-problem true relative residual |bt + S x| / |bt| in FP64; btp = bt + S x when given
+ba_status batch_true_residual(ba_batch *b, const double *x, double *btp, std::vector<double> &rel) {
+    ba_system *s = b->sys;
+    hipStream_t q = s->stream;
+    BatchLaunch L = batch_launch(b, nullptr);
+    launch_schur_matvec(schur_args(s, 0), x, b->tmp, q);
+    launch_bresidual(L, s->bt, b->tmp, btp, b->resid, q);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(b->host_d, b->resid, sizeof(double) * 2 * (size_t)b->B, hipMemcpyDeviceToHost, q));
+    HIPCHK(hipStreamSynchronize(q));
+    rel.resize((size_t)b->B);
+    for (int i = 0; i < b->B; ++i) {
+        const double a0 = b->host_d[2 * i], a1 = b->host_d[2 * i + 1];
+        rel[(size_t)i] = a1 > 0.0 ? std::sqrt(a0 / a1) : 0.0;
+    }
+    return BA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ba_status ba_batch_build(const ba_problem_desc *all, int32_t n_problems, const int32_t *cams_per_problem,
+                         const ba_build_opts *opts, void *stream, ba_batch **out) {
+    if (!out) return fail(BA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!all || !cams_per_problem || n_problems < 1) return fail(BA_ERR_INVALID_ARG, "empty batch");
+    std::vector<int32_t> seg((size_t)std::max(all->n_cams, 0));
+    ba_batch *b = new ba_batch();
+    b->B = n_problems;
+    int64_t c0 = 0;
+    for (int i = 0; i < n_problems; ++i) {
+        const int c = cams_per_problem[i];
+        if (c < 1 || c0 + c > all->n_cams) {
+            delete b;
+            return fail(BA_ERR_INVALID_ARG, "camera counts of the batch do not add up to n_cams");
+        }
+        b->cam0.push_back((int32_t)c0);
+        b->np.push_back(c);
+        for (int k = 0; k < c; ++k) seg[(size_t)(c0 + k)] = i;
+        c0 += c;
+    }
+    if (c0 != all->n_cams) {
+        delete b;
+        return fail(BA_ERR_INVALID_ARG, "camera counts of the batch do not add up to n_cams");
+    }
+    ba_status st = build_system(all, opts, stream, seg.data(), &b->sys);
+    if (st != BA_OK) {
+        delete b;
+        return st;
+    }
+    if (hipHostMalloc((void **)&b->host_i, sizeof(int32_t) * 4) != hipSuccess ||
+        hipHostMalloc((void **)&b->host_d, sizeof(double) * 2 * (size_t)n_problems) != hipSuccess) {
+        ba_batch_free(b);
+        return fail(BA_ERR_NOMEM, "pinned host buffers");
+    }
+    if (hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        ba_batch_free(b);
+        return fail(BA_ERR_HIP, "batch stream or events");
+    }
+    *out = b;
+    return BA_OK;
+}
+
+void ba_batch_free(ba_batch *b) {
+    if (!b) return;
+    if (b->sys) (void)hipStreamSynchronize(b->sys->stream);
+    free_batch_ws(b);
+    if (b->host_i) (void)hipHostFree(b->host_i);
+    if (b->host_d) (void)hipHostFree(b->host_d);
+    if (b->gstream) {
+        (void)hipStreamSynchronize(b->gstream);
+        (void)hipStreamDestroy(b->gstream);
+    }
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    ba_free_system(b->sys);
+    delete b;
+}
+
+ba_system *ba_batch_system(ba_batch *b) { return b ? b->sys : nullptr; }
+
+ba_status ba_batch_mcg_solve(ba_batch *b, int32_t N, double tau, double *x, const ba_solve_opts *opts_in,
+                             int32_t graph_window, ba_batch_stats *stats, double *elapsed_ms) {
+    if (!b || !x) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    ba_solve_opts opts;
+    ba_status st = check_opts(opts_in, &opts);
+    if (st != BA_OK) return st;
+    if (opts.precond != 0) return fail(BA_ERR_UNSUPPORTED, "batches use the block-Jacobi preconditioner");
+    int min_np = b->np[0];
+    for (int i = 1; i < b->B; ++i) min_np = std::min(min_np, b->np[(size_t)i]);
+    if (N < 1 || N > kMaxBlock || N > min_np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, min(64, cameras of every problem)]");
+    if (!(tau >= 0.0) || graph_window < 0) return fail(BA_ERR_INVALID_ARG, "tau >= 0 and graph_window >= 0 required");
+    ba_system *s = b->sys;
+    hipStream_t q = s->stream;
+    if ((st = ensure_precision(s, opts.precision)) != BA_OK) return st;
+    if (N > 1 && (st = ensure_multi(s, N)) != BA_OK) return st;
+    const int inner_max = opts.precision == 0 ? opts.max_iter : std::min(opts.max_inner, opts.max_iter);
+    const int64_t cap = opts.max_history_cols > 0 ? opts.max_history_cols : 1 + (int64_t)inner_max * N;
+    if ((st = ensure_batch_ws(b, N, cap)) != BA_OK) return st;
+    const int B = b->B;
+    std::vector<double> done_ms((size_t)B, 0.0), rel;
+    std::vector<int32_t> iters((size_t)B, 0), multis((size_t)B, 0), outer((size_t)B, 0), status((size_t)B, BA_MAXITER);
+    std::vector<BatchDyn> hd;
+    auto t0 = std::chrono::steady_clock::now();
+    if (opts.precision == 0) {
+        if ((st = batch_core(b, 0, s->bt, x, nullptr, tau, opts.eps, opts.max_iter, graph_window, t0, &done_ms)) != BA_OK)
+            return st;
+        if ((st = batch_stats_from_device(b, hd)) != BA_OK) return st;
+        for (int i = 0; i < B; ++i) {
+            iters[(size_t)i] = hd[(size_t)i].iters;
+            multis[(size_t)i] = hd[(size_t)i].multi_steps;
+            status[(size_t)i] = hd[(size_t)i].status;
+        }
+        if ((st = batch_true_residual(b, x, nullptr, rel)) != BA_OK) return st;
+    } else {
+        // FP64 iterative refinement around reduced-precision inner solves, per problem
+        const double ieps = opts.inner_eps > 0.0 ? opts.inner_eps : (opts.precision == BA_PREC_FP32 ? 1e-2 : 1e-1);
+        HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * (size_t)s->np * 9, q));
+        std::vector<int32_t> offh((size_t)B, 0);
+        std::vector<double> prev((size_t)B, INFINITY);
+        for (int o = 0;; ++o) {
+            if ((st = batch_true_residual(b, x, b->btp, rel)) != BA_OK) return st;
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            int running = 0;
+            for (int i = 0; i < B; ++i) {
+                if (offh[(size_t)i]) continue;
+                if (rel[(size_t)i] < opts.eps) {
+                    status[(size_t)i] = BA_OK;
+                    offh[(size_t)i] = 1;
+                } else if (o >= opts.max_outer || iters[(size_t)i] >= opts.max_iter || !(rel[(size_t)i] < prev[(size_t)i])) {
+                    status[(size_t)i] = BA_MAXITER;
+                    offh[(size_t)i] = 1;
+                }
+                if (offh[(size_t)i]) done_ms[(size_t)i] = ms;
+                prev[(size_t)i] = rel[(size_t)i];
+                running += !offh[(size_t)i];
+            }
+            if (running == 0) break;
+            HIPCHK(hipMemcpyAsync(b->off, offh.data(), sizeof(int32_t) * (size_t)B, hipMemcpyHostToDevice, q));
+            if ((st = batch_core(b, opts.precision, b->btp, b->d, b->off, tau, ieps, inner_max, graph_window, t0,
+                                 nullptr)) != BA_OK)
+                return st;
+            launch_axpy((int64_t)s->np * 9, 1.0, b->d, x, q);
+            HIPCHK(hipGetLastError());
+            if ((st = batch_stats_from_device(b, hd)) != BA_OK) return st;
+            for (int i = 0; i < B; ++i) {
+                if (offh[(size_t)i]) continue;
+                iters[(size_t)i] += hd[(size_t)i].iters;
+                multis[(size_t)i] += hd[(size_t)i].multi_steps;
+                outer[(size_t)i] += 1;
+                if (hd[(size_t)i].status < 0 && hd[(size_t)i].status != BA_ERR_BREAKDOWN) status[(size_t)i] = hd[(size_t)i].status;
+            }
+            (void)hipStreamSynchronize(q);   // offh is rewritten next pass
+        }
+    }
+    HIPCHK(hipStreamSynchronize(q));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (elapsed_ms) *elapsed_ms = ms;
+    int worst = BA_OK;
+    for (int i = 0; i < B; ++i) {
+        if (stats) {
+            ba_batch_stats &o = stats[i];
+            o.iterations = iters[(size_t)i];
+            o.multi_steps = multis[(size_t)i];
+            o.history_cols = hd.empty() ? 0 : hd[(size_t)i].hcols;
+            o.refinement_steps = outer[(size_t)i];
+            o.status = status[(size_t)i];
+            o.reserved = 0;
+            o.rel_res_recursive = hd.empty() || hd[(size_t)i].rr0 <= 0.0 ? 0.0 : std::sqrt(hd[(size_t)i].rr / hd[(size_t)i].rr0);
+            o.rel_res_true = rel[(size_t)i];
+            o.done_ms = done_ms[(size_t)i] > 0.0 ? done_ms[(size_t)i] : ms;
+        }
+        if (status[(size_t)i] < 0) worst = std::min(worst, status[(size_t)i]);
+        else if (status[(size_t)i] == BA_MAXITER && worst == BA_OK) worst = BA_MAXITER;
+    }
+    return (ba_status)worst;
 }
 
 }  // extern "C"

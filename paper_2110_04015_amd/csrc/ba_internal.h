@@ -54,6 +54,9 @@ struct HostPlan {
     std::vector<int64_t> cam_obs_ptr;     // [np + 1]
     std::vector<int64_t> cam_obs;         // observation indices, camera-major
     std::vector<int32_t> obs_cam;         // host copy of the camera of each observation
+    // batches: problem of every camera (nondecreasing), of every tile and of every chunk;
+    // tiles and chunks never mix problems.  Empty for a single problem.
+    std::vector<int32_t> cam_seg, tile_seg, chunk_seg;
 };
 
 // Plan of the multidirectional product for one partition (N subsets).
@@ -73,6 +76,7 @@ struct HostMultiPlan {
     std::vector<int32_t> cg_ptr;          // [np * N + 1] partial rows of (camera, subset)
     std::vector<int32_t> cg_idx;
     std::vector<int32_t> part_dst;        // out-pair row -> position in (camera, subset)-major order
+    std::vector<int32_t> chunk_seg;       // batches: problem of every chunk
 };
 
 struct DevMulti {
@@ -88,13 +92,17 @@ struct DevMulti {
     int32_t *cg_ptr = nullptr, *cg_idx = nullptr, *part_dst = nullptr;
     double *partial = nullptr;
     int32_t *group = nullptr;             // camera -> subset
+    int32_t *chunk_seg = nullptr;         // batches: chunk -> problem
 };
 
 // Plan construction (host, plan.cpp).  Returns BA_OK or an error with message.
+// cam_seg (nullable, host, [np], nondecreasing): problem of every camera of a batch
 ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_t *lm,
-                     int max_slots, int max_tiles, HostPlan &plan, std::string &err);
+                     int max_slots, int max_tiles, HostPlan &plan, std::string &err,
+                     const int32_t *cam_seg = nullptr);
+// group (nullable, host, [np]): subset of every camera; default partition_groups(np, N)
 ba_status build_multi_plan(const HostPlan &plan, int N, int max_out, HostMultiPlan &mp,
-                           std::string &err);
+                           std::string &err, const int32_t *group = nullptr);
 void partition_groups(int np, int N, int32_t *group);
 void covisibility_degree(const HostPlan &plan, std::vector<int32_t> &deg);
 
@@ -144,7 +152,8 @@ struct ba_system {
     size_t small_cap = 0;
     double *host_pinned = nullptr;  // pinned host scalars
     ba::DevMulti multi;
-    std::vector<int32_t> multi_group;
+    // batches: problem of every camera and of every chunk of the S product (device)
+    int32_t *seg_cam = nullptr, *seg_chunk = nullptr;
     // optional event timing of the chunked Schur-product kernel
     bool profiling = false;
     std::vector<hipEvent_t> prof_events;  // start/stop pairs

@@ -1,0 +1,249 @@
+// Device linear algebra shared by the FP64 solver kernels: fixed-order block
+// reductions, the 9x9 block-Jacobi solve, and the LDS pseudo-inverse of the k x k
+// Gram matrices of Algorithm 2 (Cholesky fast path, Jacobi eigendecomposition).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ba {
+
+constexpr int kMaxK = 64;   // widest direction block (Delta_i is at most 64 x 64)
+
+constexpr int kNT = 256;   // threads of the reduction blocks
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kNT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// z_c = D_c^-1 r_c with the packed lower Cholesky factor (row i holds L[i][0..i])
+__device__ __forceinline__ void chol9_solve(const double *__restrict__ L, const double *r, double *z) {
+    double x[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        double s = r[i];
+#pragma unroll
+        for (int p = 0; p < i; ++p) s -= L[i * (i + 1) / 2 + p] * x[p];
+        x[i] = s / L[i * (i + 1) / 2 + i];
+    }
+#pragma unroll
+    for (int i = 8; i >= 0; --i) {
+        double s = x[i];
+#pragma unroll
+        for (int p = i + 1; p < 9; ++p) s -= L[p * (p + 1) / 2 + i] * x[p];
+        x[i] = s / L[i * (i + 1) / 2 + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) z[i] = x[i];
+}
+
+// Symmetric Jacobi eigendecomposition of the k x k matrix in LDS (k <= 64), with
+// disjoint rotations applied in parallel (round-robin ordering).  A rotation of
+// the pair (p, q) is skipped when |a_pq| <= (eps / 2) sqrt(|a_pp a_qq|); sweeps stop
+// when a sweep rotates nothing.  On return A holds the eigenvalues on its
+// diagonal and V the eigenvectors in its columns.
+__device__ inline void jacobi_eig(int k, double *A, double *V, double *cs, double *sn, int *flag) {
+    const int tid = threadIdx.x;
+    const int kp = k + (k & 1);
+    for (int w = tid; w < k * k; w += kNT) V[w] = (w / k == w % k) ? 1.0 : 0.0;
+    __syncthreads();
+    if (k < 2) return;
+    const int half = kp / 2;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        if (tid == 0) *flag = 0;
+        __syncthreads();
+        for (int step = 0; step < kp - 1; ++step) {
+            // pair t of this step: (step, kp-1) for t = 0, otherwise (step+t, step-t) mod (kp-1)
+            if (tid < half) {
+                int p, q;
+                if (tid == 0) {
+                    p = step;
+                    q = kp - 1;
+                } else {
+                    p = (step + tid) % (kp - 1);
+                    q = (step - tid + (kp - 1)) % (kp - 1);
+                }
+                if (p > q) {
+                    int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, s = 0.0;
+                if (q < k) {
+                    double apq = A[p * k + q], app = A[p * k + p], aqq = A[q * k + q];
+                    if (!(fabs(apq) <= 1e-300) && !(fabs(apq) <= 2.2e-16 * 0.5 * sqrt(fabs(app) * fabs(aqq)))) {
+                        double theta = (aqq - app) / (2.0 * apq);
+                        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                        *flag = 1;
+                    }
+                }
+                cs[tid] = c;
+                sn[tid] = s;
+            }
+            __syncthreads();
+            // columns: A <- A J and V <- V J
+            for (int w = tid; w < k * half; w += kNT) {
+                int row = w / half, t = w - row * half;
+                int p, q;
+                if (t == 0) {
+                    p = step;
+                    q = kp - 1;
+                } else {
+                    p = (step + t) % (kp - 1);
+                    q = (step - t + (kp - 1)) % (kp - 1);
+                }
+                if (p > q) {
+                    int tt = p;
+                    p = q;
+                    q = tt;
+                }
+                if (q >= k) continue;
+                double c = cs[t], s = sn[t];
+                if (s == 0.0) continue;
+                double arp = A[row * k + p], arq = A[row * k + q];
+                A[row * k + p] = c * arp - s * arq;
+                A[row * k + q] = s * arp + c * arq;
+                double vrp = V[row * k + p], vrq = V[row * k + q];
+                V[row * k + p] = c * vrp - s * vrq;
+                V[row * k + q] = s * vrp + c * vrq;
+            }
+            __syncthreads();
+            // rows: A <- J^T A, rotated off-diagonal entries set to zero
+            for (int w = tid; w < k * half; w += kNT) {
+                int col = w / half, t = w - col * half;
+                int p, q;
+                if (t == 0) {
+                    p = step;
+                    q = kp - 1;
+                } else {
+                    p = (step + t) % (kp - 1);
+                    q = (step - t + (kp - 1)) % (kp - 1);
+                }
+                if (p > q) {
+                    int tt = p;
+                    p = q;
+                    q = tt;
+                }
+                if (q >= k) continue;
+                double c = cs[t], s = sn[t];
+                if (s == 0.0) continue;
+                double apc = A[p * k + col], aqc = A[q * k + col];
+                A[p * k + col] = (col == q) ? 0.0 : c * apc - s * aqc;
+                A[q * k + col] = (col == p) ? 0.0 : s * apc + c * aqc;
+            }
+            __syncthreads();
+        }
+        if (*flag == 0) break;
+        __syncthreads();
+    }
+}
+
+// Lower Cholesky factor of the k x k matrix M in place (right-looking, LDS);
+// returns false when a pivot is not positive.
+__device__ inline bool chol_lds(int k, double *M, int *flag) {
+    const int tid = threadIdx.x;
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (tid == 0) {
+            double d = M[j * k + j];
+            if (!(d > 0.0)) {
+                *flag = 1;
+                d = 1.0;
+            }
+            M[j * k + j] = sqrt(d);
+        }
+        __syncthreads();
+        const double piv = M[j * k + j];
+        for (int i = j + 1 + tid; i < k; i += kNT) M[i * k + j] /= piv;
+        __syncthreads();
+        const int rem = k - j - 1;
+        for (int w = tid; w < rem * rem; w += kNT) {
+            const int i = j + 1 + w / rem, m = j + 1 + w % rem;
+            if (m <= i) M[i * k + m] -= M[i * k + j] * M[m * k + j];
+        }
+        __syncthreads();
+    }
+    return *flag == 0;
+}
+
+// Moore-Penrose pseudo-inverse of the symmetric k x k matrix A (LDS, left intact),
+// result in G; V is scratch.  When the Cholesky factorisation succeeds and
+// |A|_F |A^-1|_F < 1e-4 / (k eps), every eigenvalue lies above the drop threshold
+// k eps max|l| (l_min >= 1 / |A^-1|_F, l_max <= |A|_F), so A^+ = A^-1 = L^-T L^-1 is
+// taken from the factor; otherwise the Jacobi eigendecomposition decides.
+__device__ inline void pinv_sym_lds(int k, const double *A, double *V, double *G, double *sh, double *cs, double *sn,
+                             int *flag, int *rank_sh) {
+    const int tid = threadIdx.x;
+    for (int w = tid; w < k * k; w += kNT) V[w] = A[w];
+    __syncthreads();
+    bool ok = chol_lds(k, V, flag);
+    if (ok) {
+        // G = L^-1, one column per thread
+        if (tid < k) {
+            const int c = tid;
+            for (int i = 0; i < c; ++i) G[i * k + c] = 0.0;
+            G[c * k + c] = 1.0 / V[c * k + c];
+            for (int i = c + 1; i < k; ++i) {
+                double s = 0.0;
+                for (int m = c; m < i; ++m) s += V[i * k + m] * G[m * k + c];
+                G[i * k + c] = -s / V[i * k + i];
+            }
+        }
+        __syncthreads();
+        // V = A^-1 = G^T G
+        double fa = 0.0, fi = 0.0;
+        for (int w = tid; w < k * k; w += kNT) {
+            const int i = w / k, j = w - i * k;
+            double s = 0.0;
+            for (int m = (i > j ? i : j); m < k; ++m) s += G[m * k + i] * G[m * k + j];
+            V[w] = s;
+            fi += s * s;
+            fa += A[w] * A[w];
+        }
+        fa = block_sum(fa, sh);
+        fi = block_sum(fi, sh);
+        ok = sqrt(fa) * sqrt(fi) < 1e-4 / ((double)k * 2.220446049250313e-16);
+        if (ok) {
+            for (int w = tid; w < k * k; w += kNT) G[w] = V[w];
+            if (tid == 0) *rank_sh = k;
+            __syncthreads();
+            return;
+        }
+    }
+    // V and G are free again: eigendecomposition of a copy of A
+    for (int w = tid; w < k * k; w += kNT) G[w] = A[w];
+    __syncthreads();
+    jacobi_eig(k, G, V, cs, sn, flag);
+    // eigenvalues (diagonal of G) are copied out before G is overwritten
+    __shared__ double lam[kMaxK];
+    for (int e = tid; e < k; e += kNT) lam[e] = G[e * k + e];
+    __syncthreads();
+    const double *Lm = lam;
+    double lmax = 0.0;
+    for (int e = 0; e < k; ++e) lmax = fmax(lmax, fabs(Lm[e]));
+    const double thr = (double)k * 2.220446049250313e-16 * lmax;
+    if (tid == 0) {
+        int rk = 0;
+        for (int e = 0; e < k; ++e) rk += fabs(Lm[e]) > thr;
+        *rank_sh = rk;
+    }
+    for (int w = tid; w < k * k; w += kNT) {
+        const int i = w / k, j = w - i * k;
+        double s = 0.0;
+        for (int e = 0; e < k; ++e)
+            if (fabs(Lm[e]) > thr) s += V[i * k + e] * (1.0 / Lm[e]) * V[j * k + e];
+        G[w] = s;
+    }
+    __syncthreads();
+}
+
+}  // namespace ba

@@ -226,6 +226,7 @@ __device__ __forceinline__ void process_tile(const TileBuf<PREC, T> &b, int lane
 template <int PREC, typename T>
 __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__restrict__ v) {
     if (a.done && *a.done != 0.0) return;
+    if (a.seg_skip && a.seg_skip[a.chunk_seg[blockIdx.x]]) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double *yloc = reinterpret_cast<double *>(smem);
     double *gloc = yloc + a.max_slots * 9;
@@ -281,20 +282,23 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
 __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restrict__ ptr,
                                                  const double *__restrict__ partial,
                                                  const double *__restrict__ dU, const double *__restrict__ v,
-                                                 double *__restrict__ y, const double *__restrict__ done) {
+                                                 double *__restrict__ y, const double *__restrict__ done,
+                                                 const int32_t *__restrict__ cam_seg,
+                                                 const int32_t *__restrict__ seg_skip) {
     if (done && *done != 0.0) return;
     __shared__ double sh[4][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + w;
+    const bool live = c < np && !(seg_skip && seg_skip[cam_seg[c]]);
     double s = 0.0;
-    if (c < np && lane < 63) {
+    if (live && lane < 63) {
         const int r0 = lane / 9, k = lane - r0 * 9;
         const int64_t a = ptr[c], b = ptr[c + 1];
         for (int64_t j = a + r0; j < b; j += 7) s += partial[j * 9 + k];
     }
     sh[w][lane] = s;
     __syncthreads();
-    if (c < np && lane < 9) {
+    if (live && lane < 9) {
         double t = dU[(int64_t)c * 9 + lane] * v[(int64_t)c * 9 + lane];
         for (int m = 0; m < 7; ++m) t += sh[w][lane + 9 * m];
         y[(int64_t)c * 9 + lane] = t;
@@ -316,7 +320,7 @@ void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
 
 void launch_schur_reduce(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce1, dim3((a.np + 3) / 4), dim3(256), 0, s, a.np, a.cam_part_ptr, a.partial, a.dU, v,
-                       y, a.done);
+                       y, a.done, a.cam_seg, a.seg_skip);
 }
 
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
@@ -328,6 +332,7 @@ void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStre
 
 template <int PREC, typename T>
 __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *__restrict__ z) {
+    if (a.seg_skip && a.seg_skip[a.chunk_seg[blockIdx.x]]) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double *yloc = reinterpret_cast<double *>(smem);   // FP64 sums for every precision (see schur_tile)
     double *gloc = yloc + a.max_out * 9;
@@ -407,13 +412,15 @@ __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *_
 __global__ void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr,
                                const double *__restrict__ partial, const double *__restrict__ dU,
                                const int32_t *__restrict__ group, const double *__restrict__ z,
-                               double *__restrict__ Y) {
+                               double *__restrict__ Y, const int32_t *__restrict__ cam_seg,
+                               const int32_t *__restrict__ seg_skip) {
     int64_t n = (int64_t)np * 9;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * N) return;
     int p = (int)(i / n);
     int rem = (int)(i - (int64_t)p * n);
     int c = rem / 9, k = rem - c * 9;
+    if (seg_skip && seg_skip[cam_seg[c]]) return;
     double s = group[c] == p ? dU[rem] * z[rem] : 0.0;
     int64_t key = (int64_t)c * N + p;
     for (int j = ptr[key]; j < ptr[key + 1]; ++j) s += partial[(int64_t)j * 9 + k];
@@ -431,7 +438,7 @@ void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStrea
     }
     int64_t total = (int64_t)a.np * 9 * a.N;
     hipLaunchKernelGGL(k_reduce_multi, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.np, a.N, a.cg_ptr,
-                       a.partial, a.dU, a.group, z, Y);
+                       a.partial, a.dU, a.group, z, Y, a.cam_seg, a.seg_skip);
 }
 
 // ---------------------------------------------------------------- eq. (16)

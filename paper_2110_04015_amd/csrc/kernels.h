@@ -75,6 +75,8 @@ struct SchurArgs {
     const double *dU = nullptr;
     int np = 0;
     const double *done = nullptr;            // nullable: when *done != 0 the launch does nothing
+    // batches (nullable): a chunk / camera of problem b does nothing when seg_skip[b] != 0
+    const int32_t *chunk_seg = nullptr, *cam_seg = nullptr, *seg_skip = nullptr;
 };
 // y = S v (partials then the camera reduction)
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s);
@@ -101,6 +103,8 @@ struct MultiArgs {
     const double *dU = nullptr;
     const int32_t *group = nullptr;
     int np = 0, N = 0;
+    // batches (nullable): a chunk / camera of problem b does nothing when seg_skip[b] != 0
+    const int32_t *chunk_seg = nullptr, *cam_seg = nullptr, *seg_skip = nullptr;
 };
 // Y[p] = S (z restricted to subset p), Y column-major [N][n]
 void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s);
@@ -175,4 +179,51 @@ void launch_mlp_backward(const float *P, const float *F, const float *hid, const
                          float *grad, hipStream_t s);
 void launch_adam(float *P, const float *g, float *m, float *v, int t, float lr, hipStream_t s);
 
+
+// ---------------------------------------------------------------- batches (Algorithm 2 per problem)
+
+struct BatchProb {            // problem b of a batch (static)
+    int64_t row0;             // first row in the batch vectors (9 x first camera)
+    int64_t hbase;            // history column 0 in Ph and Qh (doubles)
+    int64_t colbase;          // first history slot: block tables at colbase, Phi / beta / Delta^+ at colbase * N
+    int32_t n, np;            // rows, cameras
+    int32_t cam0, gs;         // first camera; poses per subset (the last subset takes the rest)
+    int32_t cap, pad;         // history capacity (columns)
+};
+
+struct BatchDyn {             // per-problem solver state, advanced by the kernels
+    int32_t hcols, nblk, cur_off, kcur;   // history columns and blocks; current block (first column, width)
+    int32_t kn, multi, done, status;      // width of the next block, tau-test outcome, stopped, ba_status
+    int32_t iters, multi_steps, rank, pad;
+    int64_t dp_used;                      // Delta^+ storage used (doubles)
+    double rr0, rr, rho, t;
+};
+
+struct BatchLaunch {
+    int B = 0, N = 1, max_np = 0;
+    int64_t max_n = 0, ntot = 0;
+    const BatchProb *prob = nullptr;
+    BatchDyn *dyn = nullptr;
+    const double *Dchol = nullptr;
+    double *x = nullptr, *r = nullptr, *z = nullptr, *pstage = nullptr, *qstage = nullptr, *Y = nullptr;
+    double *Ph = nullptr, *Qh = nullptr, *Dp = nullptr, *Phi = nullptr, *beta = nullptr;
+    double *alpha = nullptr, *gamma = nullptr, *gpart = nullptr, *upart = nullptr;
+    int32_t *blk_off = nullptr, *blk_k = nullptr;
+    int64_t *blk_dp = nullptr;
+    int32_t *skip_single = nullptr, *skip_multi = nullptr;
+};
+constexpr int kMaxBlock = 64;         // widest direction block of Algorithm 2
+constexpr int kBatchGramBlocks = 16;   // partial blocks per problem of the Gram and update reductions
+constexpr int kBatchVecBlocks = 8;
+// r = -bt, x = x0 (or 0), rr0; problems with off[b] != 0 stay stopped; P_0 = D^-1 r_0
+void launch_bstart(const BatchLaunch &L, const double *bt, const double *x0, const int32_t *off, hipStream_t s);
+// Gram, Delta^+ / alpha, x / r / z update, stop and tau tests
+void launch_biter_head(const BatchLaunch &L, double tau, double eps, int max_iter, hipStream_t s);
+// Phi, beta and the new history block (hmax, bmax: bounds of history columns and blocks)
+void launch_biter_tail(const BatchLaunch &L, int hmax, int bmax, hipStream_t s);
+// Q of one-column blocks from the staging product; the new block becomes current
+void launch_bqcopy_advance(const BatchLaunch &L, hipStream_t s);
+// per-problem |bt + Sx|^2 and |bt|^2 (out [B][2]) and, when btp is given, btp = bt + Sx
+void launch_bresidual(const BatchLaunch &L, const double *bt, const double *Sx, double *btp, double *out,
+                      hipStream_t s);
 }  // namespace ba

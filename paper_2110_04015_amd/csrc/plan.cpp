@@ -30,7 +30,7 @@ static void counting_csr(const int32_t *key, int64_t m, int nk, std::vector<int6
 }
 
 ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_t *lm,
-                     int max_slots, int max_tiles, HostPlan &P, std::string &err) {
+                     int max_slots, int max_tiles, HostPlan &P, std::string &err, const int32_t *cam_seg) {
     char buf[256];
     P = HostPlan();
     P.np = np;
@@ -76,7 +76,21 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
             return BA_ERR_NOT_SPD;
         }
         minc[l] = cam[lobs[a]];
+        if (cam_seg && cam_seg[cam[lobs[b - 1]]] != cam_seg[minc[l]]) {
+            snprintf(buf, sizeof buf, "landmark %d is observed by cameras of two problems of the batch", l);
+            err = buf;
+            return BA_ERR_INVALID_ARG;
+        }
     }
+    if (cam_seg) {
+        for (int c = 1; c < np; ++c)
+            if (cam_seg[c] < cam_seg[c - 1]) {
+                err = "the problems of a batch must hold consecutive cameras";
+                return BA_ERR_INVALID_ARG;
+            }
+        P.cam_seg.assign(cam_seg, cam_seg + np);
+    }
+    auto seg_of_lmk = [&](int l) { return cam_seg ? cam_seg[minc[(size_t)l]] : 0; };
     // landmark storage order: by smallest observing camera (stable counting sort), so
     // that consecutive landmarks share cameras on banded problems
     {
@@ -110,12 +124,15 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
             P.tile_lmk_base.push_back((int32_t)P.lmk_order.size());
             P.slot_obs.resize((size_t)(t + 1) * kTile, -1);
             P.meta.resize((size_t)(t + 1) * kTile, kPad);
+            // a tile holds landmarks of one problem: that of the oldest waiting landmark
+            const int tseg = seg_of_lmk(pending[0]);
+            P.tile_seg.push_back(tseg);
             int used = 0, ll = 0;
             size_t keep = 0;
             for (size_t i = 0; i < pending.size(); ++i) {
                 int l = pending[i];
                 int c = (int)(lptr[l + 1] - lptr[l]);
-                if (used + c > kTile) {
+                if (used + c > kTile || seg_of_lmk(l) != tseg) {
                     pending[keep++] = l;
                     continue;
                 }
@@ -144,6 +161,7 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
         std::vector<int64_t> tstamp((size_t)np, -1);
         P.chunk_tile.clear();
         P.chunk_part.clear();
+        P.chunk_seg.clear();
         P.part_cam.clear();
         int chunk = -1, slots = 0, ntiles_in = 0;
         for (int64_t t = 0; t < tiles; ++t) {
@@ -157,12 +175,14 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
                     ++fresh;
                 }
             }
-            if (chunk < 0 || slots + fresh > max_slots || ntiles_in >= max_tiles) {
+            if (chunk < 0 || slots + fresh > max_slots || ntiles_in >= max_tiles ||
+                P.tile_seg[(size_t)t] != P.chunk_seg.back()) {
                 ++chunk;
                 slots = 0;
                 ntiles_in = 0;
                 P.chunk_tile.push_back((int32_t)t);
                 P.chunk_part.push_back((int32_t)P.part_cam.size());
+                P.chunk_seg.push_back(P.tile_seg[(size_t)t]);
             }
             for (int q = 0; q < kTile; ++q) {
                 size_t sidx = (size_t)(t * kTile + q);
@@ -235,12 +255,13 @@ void covisibility_degree(const HostPlan &P, std::vector<int32_t> &deg) {
 }
 
 ba_status build_multi_plan(const HostPlan &P, int N, int max_out, HostMultiPlan &M,
-                           std::string &err) {
+                           std::string &err, const int32_t *group_in) {
     M = HostMultiPlan();
     M.N = N;
     const int np = P.np;
     std::vector<int32_t> group((size_t)np);
-    partition_groups(np, N, group.data());
+    if (group_in) group.assign(group_in, group_in + np);
+    else partition_groups(np, N, group.data());
     const int64_t T = P.n_tiles;
     M.mmeta.assign((size_t)T * kTile, kPad);
     M.slot_cam.assign((size_t)T * kTile, 0);
@@ -302,12 +323,14 @@ ba_status build_multi_plan(const HostPlan &P, int N, int max_out, HostMultiPlan 
         if (chunk >= 0)
             for (int64_t k : need) fresh += stamp[(size_t)k] != chunk;
         if ((int)need.size() > max_out) max_out = (int)need.size();
-        if (chunk < 0 || outs + fresh > max_out || ntiles_in >= P.max_tiles) {
+        if (chunk < 0 || outs + fresh > max_out || ntiles_in >= P.max_tiles ||
+            P.tile_seg[(size_t)t] != M.chunk_seg.back()) {
             ++chunk;
             outs = 0;
             ntiles_in = 0;
             M.chunk_tile.push_back((int32_t)t);
             M.chunk_part.push_back((int32_t)part_key.size());
+            M.chunk_seg.push_back(P.tile_seg[(size_t)t]);
         }
         for (int64_t k : need) {
             if (stamp[(size_t)k] != chunk) {
