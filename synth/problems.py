@@ -205,11 +205,27 @@ def ring_problem(n_cams=50, n_lms=5000, c_lo=2, c_hi=8, radius=20.0, half=5.0, s
     X = rng.uniform(-half, half, (n_lms, 3))
     c = rng.integers(c_lo, min(c_hi, n_cams) + 1, n_lms)
     phi = np.arctan2(X[:, 1], X[:, 0])
-    d = np.abs(np.angle(np.exp(1j * (phi[:, None] - th[None, :]))))   # [nl, np]
-    order, take = _topc(d, c)
     lm = np.repeat(np.arange(n_lms), c)
-    cam = order[take]
+    cam = _ring_nearest(phi, th, c, c_hi)
     return _finish(name, seed, rng, cams, X, cam, lm, lam, {"geometry": 0.0}, shuffle)
+
+
+def _ring_nearest(phi: np.ndarray, th: np.ndarray, c: np.ndarray, c_hi: int, full: bool = False) -> np.ndarray:
+    """The c[i] cameras nearest in azimuth to each landmark, nearest first, flattened.
+
+    The cameras are evenly spaced, so the nearest ones form an arc around the
+    closest camera: only a window of 2 (c_hi + 2) + 1 candidates is ranked (the
+    full ranking gives the same cameras in the same order; `full` forces it)."""
+    n = th.shape[0]
+    w = c_hi + 2
+    if full or 2 * w + 1 >= n:
+        cand = np.broadcast_to(np.arange(n)[None, :], (phi.shape[0], n))
+    else:
+        k0 = np.rint(phi / (2.0 * np.pi / n)).astype(np.int64)
+        cand = (k0[:, None] + np.arange(-w, w + 1)[None, :]) % n
+    d = np.abs(np.angle(np.exp(1j * (phi[:, None] - th[cand]))))
+    order, take = _topc(d, c)
+    return np.take_along_axis(cand, order, 1)[take]
 
 
 def walk_problem(n_cams=1936, n_lms=650_000, c_max=60, geo_p=1.0 / 7.0, window=10,
@@ -346,15 +362,32 @@ def config2(seed=0, **kw) -> Problem:
     return cap_problem(n_cams=571, n_lms=100_000, seed=seed, name="cap571", **kw)
 
 
-def config4(seed=0, count=64, lo=50, hi=800, **kw) -> List[Problem]:
+def config4_sizes(seed=0, count=64, lo=50, hi=800) -> np.ndarray:
+    """Camera counts of the batch workload (config4) without generating it."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.integers(lo, hi + 1, count)
+
+
+def _config4_member(args) -> Problem:
+    n, s, kw = args
+    return ring_problem(n_cams=int(n), n_lms=200 * int(n), c_lo=2, c_hi=20, radius=20.0, seed=int(s),
+                        name=f"ring{n}", **kw)
+
+
+def config4(seed=0, count=64, lo=50, hi=800, workers: int = 1, **kw) -> List[Problem]:
     """Batch of uneven ring problems: cameras ~ U{lo..hi}, 200 landmarks per camera,
-    2-20 observers per landmark."""
+    2-20 observers per landmark.  Each problem has its own seed, so `workers`
+    processes generate exactly the same problems."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sizes = rng.integers(lo, hi + 1, count)
     seeds = rng.integers(0, 2 ** 31 - 1, count)
-    return [ring_problem(n_cams=int(n), n_lms=200 * int(n), c_lo=2, c_hi=20,
-                         radius=20.0, seed=int(s), name=f"ring{n}", **kw)
-            for n, s in zip(sizes, seeds)]
+    jobs = [(int(n), int(s), kw) for n, s in zip(sizes, seeds)]
+    if workers <= 1:
+        return [_config4_member(j) for j in jobs]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_config4_member, jobs))
 
 
 def tiny(n_cams=4, n_lms=30, seed=0, c_lo=2, c_hi=4, **kw) -> Problem:
