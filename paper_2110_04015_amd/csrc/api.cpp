@@ -133,7 +133,9 @@ SchurArgs schur_args(ba_system *s, int precision) {
     a.part_cam = s->part_cam;
     a.part_dst = s->part_dst;
     a.n_chunks = s->plan.n_chunks;
-    a.max_slots = s->plan.max_slots;
+    // LDS rows per chunk: the most cameras any chunk holds (often well below the
+    // max_slots limit, which leaves room for more resident wavefronts)
+    a.max_slots = s->plan.max_used_slots;
     a.partial = s->partial;
     a.cam_part_ptr = s->cam_part_ptr;
     a.dU = s->dU;
@@ -599,7 +601,7 @@ ba_status ba_back_substitute(ba_system *s, const double *dxp, double *dxl) {
     if (!s || !dxp || !dxl) return fail(BA_ERR_INVALID_ARG, "NULL argument");
     const HostPlan &P = s->plan;
     launch_back_substitute(s->J64, s->meta, s->tile_lmk_base, s->chunk_tile, s->chunk_part, s->part_cam,
-                           P.n_chunks, P.max_slots, s->vinv, s->bl, s->lmk_order, dxp, dxl, s->stream);
+                           P.n_chunks, P.max_used_slots, s->vinv, s->bl, s->lmk_order, dxp, dxl, s->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return BA_OK;
@@ -756,15 +758,17 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     }
     const int64_t hc = s->hist_cap_cols;
     double *Ph = s->hist, *Qh = s->hist + hc * n;
-    // small storage: Dp (64 * cap), Phi (cap * N), beta (cap * N), gamma, alpha (64 each), block tables
-    const size_t small_need = (size_t)(64 * hc + 2 * hc * N + 128) + (size_t)(3 * hc + 8);
+    // small storage: Dp (64 * cap), Phi (cap * max(N, kPhiSeg)), beta (cap * N), gamma, alpha (64 each),
+    // block tables
+    const int phiw = std::max(N, kPhiSeg);
+    const size_t small_need = (size_t)(64 * hc + hc * phiw + hc * N + 128) + (size_t)(3 * hc + 8);
     if (s->small_cap < small_need) {
         dfree(s->small);
         s->small_cap = 0;
         if ((st = dalloc(&s->small, small_need)) != BA_OK) return st;
         s->small_cap = small_need;
     }
-    double *Dp = s->small, *Phi = Dp + 64 * hc, *beta = Phi + hc * N, *gamma = beta + hc * N, *alpha = gamma + 64;
+    double *Dp = s->small, *Phi = Dp + 64 * hc, *beta = Phi + hc * phiw, *gamma = beta + hc * N, *alpha = gamma + 64;
     int32_t *blk_off = reinterpret_cast<int32_t *>(alpha + 64);
     int32_t *blk_k = blk_off + hc;
     int64_t *blk_dp = reinterpret_cast<int64_t *>(blk_k + hc + 2);

@@ -38,6 +38,7 @@ struct HostPlan {
     int n_chunks = 0;
     int64_t n_part = 0;
     int max_slots = 128, max_tiles = 16;
+    int max_used_slots = 0;               // most cameras of one chunk (sizes the chunk kernels' LDS)
     std::vector<int32_t> lmk_order;       // storage index -> landmark id
     std::vector<int32_t> lmk_store;       // landmark id -> storage index
     std::vector<int64_t> slot_obs;        // tile slot -> observation index or -1

@@ -22,6 +22,25 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return r;
 }
 
+// Sum over the lanes of a wavefront by a fixed butterfly.  Partners add the same two
+// values (in swapped order, which is exact), so every lane ends with the same sum,
+// independent of scheduling.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of nb block partials a[b * stride] by the calling wavefront (all 64 lanes must
+// call): lane l adds entries l, l + 64, ... in order, then the butterfly.  The loads of
+// all lanes are in flight together instead of one after another in a single thread.
+__device__ __forceinline__ double wave_partials(const double *__restrict__ a, int64_t stride, int nb) {
+    const int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int b = lane; b < nb; b += 64) s += a[(int64_t)b * stride];
+    return wave_sum(s);
+}
+
 // z_c = D_c^-1 r_c with the packed lower Cholesky factor (row i holds L[i][0..i])
 __device__ __forceinline__ void chol9_solve(const double *__restrict__ L, const double *r, double *z) {
     double x[9];

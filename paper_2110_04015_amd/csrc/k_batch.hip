@@ -18,13 +18,6 @@ namespace ba {
 constexpr int kBGX = kBatchGramBlocks;
 constexpr int kBUX = kBatchVecBlocks;
 
-__device__ __forceinline__ double wave_sum(double v) {
-    // fixed butterfly: every lane ends with the same, order-independent-of-scheduling sum
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 __device__ __forceinline__ int subset_of(int cam_local, int gs, int N) { return min(cam_local / gs, N - 1); }
 
 // rr0 partials: sum of r^2 over the rows of problem b (r = -bt)

@@ -82,16 +82,16 @@ void launch_dot2(int64_t n, const double *a0, const double *b0, const double *a1
     hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kNT), 0, s, n, a0, b0, a1, b1, partials, done);
 }
 
-__global__ void k_finalize(const double *__restrict__ partials, int nd, double *__restrict__ out) {
-    int d = threadIdx.x;
-    if (d >= nd) return;
-    double s = 0.0;
-    for (int b = 0; b < kRedBlocks; ++b) s += partials[b * nd + d];
-    out[d] = s;
+// one wavefront per output d
+__global__ __launch_bounds__(64) void k_finalize(const double *__restrict__ partials, int nd,
+                                                 double *__restrict__ out) {
+    const int d = blockIdx.x;
+    const double s = wave_partials(partials + d, nd, kRedBlocks);
+    if (threadIdx.x == 0) out[d] = s;
 }
 
 void launch_finalize(const double *partials, int nd, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, partials, nd, out);
+    hipLaunchKernelGGL(k_finalize, dim3(nd), dim3(64), 0, s, partials, nd, out);
 }
 
 // ---------------------------------------------------------------- refinement
@@ -153,10 +153,9 @@ void launch_pcg_init(int64_t n, const double *bt, const double *Sx, double *r, d
 }
 
 // sc[SC_RR] = sum of the partials; the first call (sc[SC_RR0] < 0) also sets SC_RR0
-__global__ void k_pcg_rr(const double *__restrict__ partials, double *__restrict__ sc) {
+__global__ __launch_bounds__(64) void k_pcg_rr(const double *__restrict__ partials, double *__restrict__ sc) {
+    const double s = wave_partials(partials, 1, kRedBlocks);
     if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int b = 0; b < kRedBlocks; ++b) s += partials[b];
     sc[SC_RR] = s;
     if (sc[SC_RR0] < 0.0) sc[SC_RR0] = s;
 }
@@ -169,16 +168,16 @@ void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s) {
 // iteration count, the stop test |r_{i+1}| < eps |r_0| (Alg. 1) and the iteration
 // cap.  Sets sc[SC_DONE] (after which every kernel of later iterations returns at
 // once) and sc[SC_STATUS].  trace (nullable) receives |r_{i+1}| / |r_0|.
-__global__ void k_pcg_step_end(const double *__restrict__ partials, double *__restrict__ sc, double eps,
-                               int max_iter, double *__restrict__ trace) {
-    if (threadIdx.x != 0 || sc[SC_DONE] != 0.0) return;
+__global__ __launch_bounds__(64) void k_pcg_step_end(const double *__restrict__ partials, double *__restrict__ sc,
+                                                     double eps, int max_iter, double *__restrict__ trace) {
+    if (sc[SC_DONE] != 0.0) return;
+    const double s = wave_partials(partials, 1, kRedBlocks);
+    if (threadIdx.x != 0) return;
     if (sc[SC_BREAK] != 0.0) {
         sc[SC_DONE] = 1.0;
         sc[SC_STATUS] = (double)BA_ERR_BREAKDOWN;
         return;
     }
-    double s = 0.0;
-    for (int b = 0; b < kRedBlocks; ++b) s += partials[b];
     const double it = sc[SC_ITER] + 1.0;
     sc[SC_ITER] = it;
     sc[SC_RR] = s;
@@ -208,15 +207,12 @@ __global__ __launch_bounds__(kNT) void k_pcg_update_xr(int64_t n, const double *
     if (sc[SC_DONE] != 0.0) return;
     __shared__ double sh[kNT];
     __shared__ double s_alpha;
-    if (threadIdx.x == 0) {
-        double D = 0.0, g = 0.0;
-        for (int b = 0; b < kRedBlocks; ++b) {
-            D += pdq[b * 2];
-            g += pdq[b * 2 + 1];
-        }
-        double al = D > 0.0 ? g / D : 0.0;
-        s_alpha = al;
-        if (blockIdx.x == 0) {
+    if (threadIdx.x < 64) {
+        const double D = wave_partials(pdq, 2, kRedBlocks);
+        const double g = wave_partials(pdq + 1, 2, kRedBlocks);
+        const double al = D > 0.0 ? g / D : 0.0;
+        if (threadIdx.x == 0) s_alpha = al;
+        if (threadIdx.x == 0 && blockIdx.x == 0) {
             sc[SC_DELTA] = D;
             sc[SC_GAMMA] = g;
             sc[SC_ALPHA] = al;
@@ -248,12 +244,11 @@ __global__ __launch_bounds__(kNT) void k_pcg_update_p(int64_t n, const double *_
                                                       double *__restrict__ P) {
     if (sc[SC_DONE] != 0.0) return;
     __shared__ double s_beta;
-    if (threadIdx.x == 0) {
-        double phi = 0.0;
-        for (int b = 0; b < kRedBlocks; ++b) phi += pphi[b];
-        double be = phi / sc[SC_DELTA];
-        s_beta = be;
-        if (blockIdx.x == 0) {
+    if (threadIdx.x < 64) {
+        const double phi = wave_partials(pphi, 1, kRedBlocks);
+        const double be = phi / sc[SC_DELTA];
+        if (threadIdx.x == 0) s_beta = be;
+        if (threadIdx.x == 0 && blockIdx.x == 0) {
             sc[SC_PHI] = phi;
             sc[SC_BETA] = be;
         }
@@ -337,8 +332,15 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
     const int tid = threadIdx.x;
     const int tot = k * k + k;
     for (int idx = tid; idx < tot; idx += kNT) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * tot + idx];
+        // eight independent running sums keep eight loads in flight per thread
+        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = 0;
+        for (; b + 8 <= nblocks; b += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += partials[(int64_t)(b + u) * tot + idx];
+        }
+        for (; b < nblocks; ++b) acc[0] += partials[(int64_t)b * tot + idx];
+        const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
         if (idx < k * k) G[idx] = s;
         else gam[idx - k * k] = s;
     }
@@ -412,11 +414,10 @@ void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, co
 }
 
 // rho = r^T D^-1 r from the partials; t = gamma^T alpha / rho (the tau-test of Alg. 2)
-__global__ void k_tau(int k, const double *__restrict__ prho, const double *__restrict__ gamma,
-                      const double *__restrict__ alpha, double *__restrict__ sc) {
+__global__ __launch_bounds__(64) void k_tau(int k, const double *__restrict__ prho, const double *__restrict__ gamma,
+                                            const double *__restrict__ alpha, double *__restrict__ sc) {
+    const double rho = wave_partials(prho, 1, kRedBlocks);
     if (threadIdx.x != 0) return;
-    double rho = 0.0;
-    for (int b = 0; b < kRedBlocks; ++b) rho += prho[b];
     double ga = 0.0;
     for (int a = 0; a < k; ++a) ga += gamma[a] * alpha[a];
     sc[SC_RHO] = rho;
@@ -429,28 +430,33 @@ void launch_tau(int k, const double *partials_rho, const double *gamma, const do
 }
 
 // Phi[col][p] = Q_hist[:, col]^T Z[:, p]: for a multidirectional Z only the rows of
-// subset p contribute (gs poses per subset, the last subset takes the rest).
+// subset p contribute (gs poses per subset, the last subset takes the rest).  For a
+// one-column Z the dot product is split into kPhiSeg row segments (one block each,
+// for parallelism); k_beta adds the segments in order.
 __global__ __launch_bounds__(kNT) void k_phi(int64_t n, const double *__restrict__ Qh,
                                              const double *__restrict__ z, int multi, int N, int gs,
                                              double *__restrict__ Phi) {
     __shared__ double sh[kNT];
     const int col = blockIdx.x;
     const int p = blockIdx.y;
-    int64_t lo = 0, hi = n;
+    int64_t lo, hi;
     if (multi) {
         lo = (int64_t)p * gs * 9;
         hi = (p == N - 1) ? n : (int64_t)(p + 1) * gs * 9;
+    } else {
+        lo = n * p / kPhiSeg;
+        hi = n * (p + 1) / kPhiSeg;
     }
     const double *q = Qh + (int64_t)col * n;
     double acc = 0.0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kNT) acc += q[i] * z[i];
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) Phi[(int64_t)col * (multi ? N : 1) + p] = acc;
+    if (threadIdx.x == 0) Phi[(int64_t)col * (multi ? N : kPhiSeg) + p] = acc;
 }
 
 void launch_phi(int64_t n, int h, const double *Qh, const double *z, int multi, int N, int gs, double *Phi,
                 hipStream_t s) {
-    hipLaunchKernelGGL(k_phi, dim3(h, multi ? N : 1), dim3(kNT), 0, s, n, Qh, z, multi, N, gs, Phi);
+    hipLaunchKernelGGL(k_phi, dim3(h, multi ? N : kPhiSeg), dim3(kNT), 0, s, n, Qh, z, multi, N, gs, Phi);
 }
 
 // records history block j (first column, width, offset of its Delta^+) on the device
@@ -475,7 +481,16 @@ __global__ __launch_bounds__(kNT) void k_beta(const int32_t *__restrict__ blk_of
     for (int w = threadIdx.x; w < kj * kn; w += kNT) {
         int a = w / kn, p = w - a * kn;
         double s = 0.0;
-        for (int b = 0; b < kj; ++b) s += D[a * kj + b] * Phi[(int64_t)(off + b) * kn + p];
+        for (int b = 0; b < kj; ++b) {
+            double f;
+            if (kn == 1) {   // one-column Z: the segments of k_phi, in order
+                f = 0.0;
+                for (int g = 0; g < kPhiSeg; ++g) f += Phi[(int64_t)(off + b) * kPhiSeg + g];
+            } else {
+                f = Phi[(int64_t)(off + b) * kn + p];
+            }
+            s += D[a * kj + b] * f;
+        }
         beta[(int64_t)(off + a) * kn + p] = s;
     }
 }

@@ -117,6 +117,7 @@ void launch_back_substitute(const double *J64, const uint32_t *meta, const int32
 
 // ---- vectors, reductions, small dense (k_vec.hip)
 constexpr int kRedBlocks = 120;    // fixed grid of the deterministic reductions
+constexpr int kPhiSeg = 16;        // row segments of a one-column Phi (Alg. 2 reorthogonalisation)
 
 void launch_precond(int np, const double *Dchol, const double *r, double *z, hipStream_t s);
 // partial dots: out[b * 2 + d] over blocks b < kRedBlocks

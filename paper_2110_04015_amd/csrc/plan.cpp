@@ -202,6 +202,9 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
         P.chunk_tile.push_back((int32_t)tiles);
         P.chunk_part.push_back((int32_t)P.part_cam.size());
         P.n_part = (int64_t)P.part_cam.size();
+        P.max_used_slots = 1;
+        for (int ch = 0; ch < P.n_chunks; ++ch)
+            P.max_used_slots = std::max(P.max_used_slots, P.chunk_part[(size_t)ch + 1] - P.chunk_part[(size_t)ch]);
     }
     // camera-major CSR over partial rows (ascending row order = fixed summation order)
     {
