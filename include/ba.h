@@ -77,7 +77,10 @@ typedef struct {
     int32_t store_bf16;      /* also keep a BF16 copy with per-camera column scales (precision BF16) */
     int32_t max_slots;       /* cameras per landmark chunk (0 = default 128; 64..440) */
     int32_t max_tiles;       /* 64-observation tiles per chunk (0 = default 16) */
-    int32_t reserved[4];
+    int32_t explicit_schur;  /* also form S explicitly in 9x9 block-sparse rows (the paper's representation,
+                                Sec. 3.2 and 4.1); FP64 S products then read it instead of the Jacobians.
+                                BA_ERR_UNSUPPORTED when a block row exceeds the LDS of the assembly (251 blocks) */
+    int32_t reserved[3];
 } ba_build_opts;
 
 typedef enum { BA_PREC_FP64 = 0, BA_PREC_FP32 = 1, BA_PREC_BF16 = 2 } ba_precision;
@@ -299,6 +302,11 @@ ba_system *ba_batch_system(ba_batch *batch);
  * eps, BA_MAXITER when some did not, else the first error. */
 ba_status ba_batch_mcg_solve(ba_batch *batch, int32_t N, double tau, double *x, const ba_solve_opts *opts,
                              int32_t graph_window, ba_batch_stats *stats, double *elapsed_ms);
+
+/* Explicit S (ba_build_opts.explicit_schur): nonzero 9x9 blocks, bytes of the block
+ * values, and the assembly time in ms (host outputs, nullable).  BA_ERR_INVALID_ARG
+ * when the system was built without it. */
+ba_status ba_explicit_schur_info(const ba_system *sys, int64_t *nnz_blocks, int64_t *bytes, double *assembly_ms);
 
 const char *ba_status_string(int32_t status);
 const char *ba_last_error(void);

@@ -120,7 +120,7 @@ class System:
     """A built reduced camera system (ba_build_system) living on one device."""
 
     def __init__(self, n_cams, n_lms, obs_cam, obs_lm, J_p, J_l, r, lam, stream=None,
-                 max_slots=0, max_tiles=0, store_fp32=False, store_bf16=False):
+                 max_slots=0, max_tiles=0, store_fp32=False, store_bf16=False, explicit_schur=False):
         torch = _torch()
         m = int(obs_cam.numel())
         d = _lib.ProblemDesc()
@@ -134,6 +134,7 @@ class System:
         o = _lib.BuildOpts()
         o.store_fp32, o.store_bf16 = int(store_fp32), int(store_bf16)
         o.max_slots, o.max_tiles = int(max_slots), int(max_tiles)
+        o.explicit_schur = int(explicit_schur)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         self.device = obs_cam.device
         h = C.c_void_p()
@@ -185,6 +186,12 @@ class System:
                                     C.byref(f)), "ba_system_info")
         return {"n_cams": a.value, "n_lms": b.value, "n_obs": c.value, "n_tiles": d.value,
                 "n_chunks": e.value, "matvec_bytes_fp64": f.value}
+
+    def explicit_schur_info(self):
+        """(nonzero 9x9 blocks, bytes of their values, assembly ms) of the explicit S."""
+        nb, by, ms = C.c_int64(), C.c_int64(), C.c_double()
+        _check(lib().ba_explicit_schur_info(self.h, C.byref(nb), C.byref(by), C.byref(ms)), "ba_explicit_schur_info")
+        return {"nnz_blocks": nb.value, "bytes": by.value, "assembly_ms": ms.value}
 
     def profile(self, on: bool = True):
         _check(lib().ba_profile_enable(self.h, int(on)), "ba_profile_enable")

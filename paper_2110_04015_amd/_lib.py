@@ -21,7 +21,7 @@ class ProblemDesc(C.Structure):
 
 class BuildOpts(C.Structure):
     _fields_ = [("store_fp32", C.c_int32), ("store_bf16", C.c_int32), ("max_slots", C.c_int32),
-                ("max_tiles", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("max_tiles", C.c_int32), ("explicit_schur", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class SolveOpts(C.Structure):
@@ -83,6 +83,8 @@ SIGNATURES = [
     ("ba_batch_system", C.c_void_p, [C.c_void_p]),
     ("ba_batch_mcg_solve", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
                                      C.POINTER(BatchStats), C.POINTER(C.c_double)]),
+    ("ba_explicit_schur_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_double)]),
     ("ba_status_string", C.c_char_p, [C.c_int32]),
     ("ba_last_error", C.c_char_p, []),
 ]

@@ -114,6 +114,9 @@ void free_all(ba_system *s) {
     dfree(s->lr_proj);
     dfree(s->seg_cam);
     dfree(s->seg_chunk);
+    dfree(s->bsr_ptr);
+    dfree(s->bsr_col);
+    dfree(s->bsr_val);
     if (s->host_pinned) (void)hipHostFree(s->host_pinned);
     s->host_pinned = nullptr;
     free_multi(s->multi);
@@ -158,8 +161,23 @@ void profile_flush(ba_system *s) {
     s->prof_used = 0;
 }
 
-// y = S v; with profiling on, the chunk kernel is bracketed by events on the stream
+// S v from the explicit block-sparse S (FP64 products of a system built with it)
+inline bool use_bsr(const ba_system *s, const SchurArgs &a) {
+    return s->bsr_val && a.precision == 0 && !a.seg_skip;
+}
+
+// y = S v; with profiling on, the dominant kernel is bracketed by events on the stream
 void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
+    if (use_bsr(s, a)) {
+        const bool ev = s->profiling && s->prof_used + 2 <= s->prof_events.size();
+        if (ev) (void)hipEventRecord(s->prof_events[s->prof_used], s->stream);
+        launch_bsr_mv(s->np, s->bsr_ptr, s->bsr_col, s->bsr_val, v, y, a.done, s->stream);
+        if (ev) {
+            (void)hipEventRecord(s->prof_events[s->prof_used + 1], s->stream);
+            s->prof_used += 2;
+        }
+        return;
+    }
     if (!s->profiling) {
         launch_schur_matvec(a, v, y, s->stream);
         return;
@@ -498,6 +516,52 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
                      d_h0, s->status, q);
     launch_cameras(s->np, d_cam_ptr, d_cam_obs, d->obs_lm, d_lmk_store, d->J_p, d->J_l, d->r, s->vinv, d_h0,
                    s->lambda, s->dU, s->Dblk, s->Dchol, s->bt, s->status, q);
+    if (opts && opts->explicit_schur) {
+        // explicit S in block-sparse rows, assembled from the same blocks (Sec. 3.2, 4.1)
+        if (cam_seg) return bail2(fail(BA_ERR_UNSUPPORTED, "batches use the implicit S products"));
+        std::vector<int32_t> rp, cl;
+        int max_row = 0;
+        build_bsr_pattern(P, hlm.data(), rp, cl, max_row);
+        int dev = 0, lds_max = 65536;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return bail2(fail(BA_ERR_HIP, "device attribute query failed"));
+        if ((size_t)max_row * 81 * sizeof(double) > (size_t)lds_max)
+            return bail2(fail(BA_ERR_UNSUPPORTED, "explicit S: a camera is covisible with " + std::to_string(max_row) +
+                                                      " cameras, more than one work-group's LDS holds"));
+        if (nslots > (int64_t)INT32_MAX) return bail2(fail(BA_ERR_UNSUPPORTED, "explicit S: too many observations"));
+        std::vector<int64_t> pptr;
+        std::vector<int32_t> prs;
+        build_bsr_pairs(P, hlm.data(), rp, cl, pptr, prs);
+        int64_t *d_pptr = nullptr;
+        int32_t *d_pairs = nullptr;
+        auto bail3 = [&](ba_status st3) {
+            (void)hipStreamSynchronize(q);
+            dfree(d_pptr);
+            dfree(d_pairs);
+            return bail2(st3);
+        };
+        if ((st = upload(&s->bsr_ptr, rp, q)) != BA_OK) return bail3(st);
+        if ((st = upload(&s->bsr_col, cl, q)) != BA_OK) return bail3(st);
+        if ((st = upload(&d_pptr, pptr, q)) != BA_OK) return bail3(st);
+        if ((st = upload(&d_pairs, prs, q)) != BA_OK) return bail3(st);
+        s->bsr_nnzb = (int64_t)cl.size();
+        if ((st = dalloc(&s->bsr_val, (size_t)s->bsr_nnzb * 81)) != BA_OK) return bail3(st);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        if (e0) (void)hipEventRecord(e0, q);
+        launch_bsr_assemble(s->np, d_pptr, d_pairs, s->J64, s->vinv, s->Dblk, s->bsr_ptr, s->bsr_col, max_row,
+                            s->bsr_val, q);
+        if (e1) (void)hipEventRecord(e1, q);
+        if (hipStreamSynchronize(q) != hipSuccess) return bail3(fail(BA_ERR_HIP, "explicit S assembly failed"));
+        dfree(d_pptr);
+        dfree(d_pairs);
+        float ms = 0.f;
+        if (e0 && e1 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) s->bsr_build_ms = ms;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
     if (hipGetLastError() != hipSuccess) return bail2(fail(BA_ERR_HIP, "build kernel launch failed"));
     if (hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
         hipStreamSynchronize(q) != hipSuccess)
@@ -569,7 +633,10 @@ ba_status ba_schur_matmat_grouped(ba_system *s, int32_t N, const double *z, doub
     ba_status st = ensure_precision(s, precision);
     if (st != BA_OK) return st;
     if ((st = ensure_multi(s, N)) != BA_OK) return st;
-    launch_schur_multi(multi_args(s, precision), z, Y, s->stream);
+    if (s->bsr_val && precision == 0 && N <= kMaxBlock)   // the grouped kernel keeps N x 9 sums in LDS
+        launch_bsr_mm_grouped(s->np, N, s->bsr_ptr, s->bsr_col, s->bsr_val, s->multi.group, z, Y, s->stream);
+    else
+        launch_schur_multi(multi_args(s, precision), z, Y, s->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return BA_OK;
@@ -865,7 +932,12 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 break;
             }
             double *Pn = Ph + hcols * n, *Qn = Qh + hcols * n;
-            if (multi) launch_schur_multi(ma, z, Qn, q);                 // S Z_{i+1}
+            if (multi) {                                                 // S Z_{i+1}
+                if (s->bsr_val && prec == 0 && N <= kMaxBlock)
+                    launch_bsr_mm_grouped(s->np, N, s->bsr_ptr, s->bsr_col, s->bsr_val, s->multi.group, z, Qn, q);
+                else
+                    launch_schur_multi(ma, z, Qn, q);
+            }
             // Phi_{i,j} = Q_j^T Z_{i+1}, beta_{i,j} = Delta_j^+ Phi_{i,j}
             launch_phi(n, (int)hcols, Qh, z, multi ? 1 : 0, N, gs, Phi, q);
             launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, kn, beta, q);
@@ -1460,6 +1532,15 @@ void ba_batch_free(ba_batch *b) {
 }
 
 ba_system *ba_batch_system(ba_batch *b) { return b ? b->sys : nullptr; }
+
+ba_status ba_explicit_schur_info(const ba_system *s, int64_t *nnz_blocks, int64_t *bytes, double *assembly_ms) {
+    if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    if (!s->bsr_val) return fail(BA_ERR_INVALID_ARG, "the system was built without the explicit S");
+    if (nnz_blocks) *nnz_blocks = s->bsr_nnzb;
+    if (bytes) *bytes = s->bsr_nnzb * 81 * (int64_t)sizeof(double);
+    if (assembly_ms) *assembly_ms = s->bsr_build_ms;
+    return BA_OK;
+}
 
 ba_status ba_batch_mcg_solve(ba_batch *b, int32_t N, double tau, double *x, const ba_solve_opts *opts_in,
                              int32_t graph_window, ba_batch_stats *stats, double *elapsed_ms) {

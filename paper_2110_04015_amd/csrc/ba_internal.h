@@ -97,6 +97,17 @@ struct DevMulti {
 };
 
 // Plan construction (host, plan.cpp).  Returns BA_OK or an error with message.
+// Block pattern of the explicit S: for camera j, the sorted cameras sharing a landmark
+// with it (j included).  max_row: most blocks in a row.
+void build_bsr_pattern(const HostPlan &plan, const int32_t *lm, std::vector<int32_t> &row_ptr,
+                       std::vector<int32_t> &col, int &max_row);
+// Off-diagonal contributions of every block row, in the row's observation order and then
+// observer order: (slot of camera j's observation, slot of the co-observer, landmark
+// storage index, block of the co-observer in the row), four int32 each, padded with
+// block -1 to 64 per row; pair_ptr[j] is the row's first pair.
+void build_bsr_pairs(const HostPlan &plan, const int32_t *lm, const std::vector<int32_t> &row_ptr,
+                     const std::vector<int32_t> &col, std::vector<int64_t> &pair_ptr,
+                     std::vector<int32_t> &pairs);
 // cam_seg (nullable, host, [np], nondecreasing): problem of every camera of a batch
 ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_t *lm,
                      int max_slots, int max_tiles, HostPlan &plan, std::string &err,
@@ -155,6 +166,11 @@ struct ba_system {
     ba::DevMulti multi;
     // batches: problem of every camera and of every chunk of the S product (device)
     int32_t *seg_cam = nullptr, *seg_chunk = nullptr;
+    // explicit S in block-sparse rows (optional)
+    int32_t *bsr_ptr = nullptr, *bsr_col = nullptr;
+    double *bsr_val = nullptr;
+    int64_t bsr_nnzb = 0;
+    double bsr_build_ms = 0.0;
     // optional event timing of the chunked Schur-product kernel
     bool profiling = false;
     std::vector<hipEvent_t> prof_events;  // start/stop pairs

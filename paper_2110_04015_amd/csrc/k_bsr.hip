@@ -1,0 +1,179 @@
+// Explicit reduced camera system in block-sparse rows (9 x 9 FP64 blocks), the
+// paper's own representation of S (Sec. 3.2, "Optimized implementation": S_jk is
+// nonzero iff cameras j and k observe a common point; Sec. 4.1 forms it as a
+// row-major sparse matrix).
+//   S_jj = D(S)_j                                   (already formed by the build)
+//   S_jk = - sum_{l observed by j and k} W_jl V_l^-1 W_kl^T,   W_jl = J_p,jl^T J_l,jl
+// Assembly: one wavefront per block row j holds the row's blocks in LDS and adds the
+// row's contributions, 64 at a time, in a fixed order.
+#include "ba_internal.h"
+#include "kernels.h"
+
+namespace ba {
+
+typedef double dbl2b_t __attribute__((ext_vector_type(2)));
+
+// W = J_p^T J_l (9 x 3) of the observation in tile-stream slot s (record layout of
+// the S product: 12 x 16 B words per slot, 64 slots per tile)
+__device__ __forceinline__ void w_of_slot(const double *__restrict__ J64, int64_t s, double W[27]) {
+    const dbl2b_t *p = reinterpret_cast<const dbl2b_t *>(J64) + (s >> 6) * 12 * 64 + (s & 63);
+    double v[24];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const dbl2b_t d = p[q * 64];
+        v[2 * q] = d.x;
+        v[2 * q + 1] = d.y;
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) W[r * 3 + c] = v[r] * v[18 + c] + v[9 + r] * v[21 + c];
+}
+
+// One wavefront per block row j.  Its contributions (o, q) -- camera j's observation o
+// of landmark l and co-observer q, in observation then observer order -- come 64 per
+// step; lane i adds -W_o V_l^-1 W_q^T into the row's block of q's camera with LDS
+// atomics.  One wavefront issues all of them, so the additions into one block happen
+// in program order and, within an instruction, in lane order: the sums are
+// reproducible.
+__global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__ pair_ptr,
+                                                     const int4 *__restrict__ pairs, const double *__restrict__ J64,
+                                                     const double *__restrict__ vinv, const double *__restrict__ Dblk,
+                                                     const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col, double *__restrict__ val) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int b0 = row_ptr[j], nb = row_ptr[j + 1] - b0;
+    double *acc = reinterpret_cast<double *>(smem);
+    for (int e = lane; e < nb * 81; e += 64) acc[e] = 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int64_t t = pair_ptr[j] + lane; t < pair_ptr[j + 1]; t += 64) {
+        const int4 pr = pairs[t];
+        if (pr.w >= 0) {
+            double Wo[27], Wq[27], G[27];
+            w_of_slot(J64, pr.x, Wo);
+            w_of_slot(J64, pr.y, Wq);
+            const double *vi = vinv + (int64_t)pr.z * 6;
+            const double v0 = vi[0], v1 = vi[1], v2 = vi[2], v3 = vi[3], v4 = vi[4], v5 = vi[5];
+#pragma unroll
+            for (int r = 0; r < 9; ++r) {   // G = W_o V^-1 (V^-1 symmetric, packed)
+                const double x0 = Wo[r * 3], x1 = Wo[r * 3 + 1], x2 = Wo[r * 3 + 2];
+                G[r * 3] = x0 * v0 + x1 * v1 + x2 * v2;
+                G[r * 3 + 1] = x0 * v1 + x1 * v3 + x2 * v4;
+                G[r * 3 + 2] = x0 * v2 + x1 * v4 + x2 * v5;
+            }
+            double *blk = acc + (size_t)pr.w * 81;
+#pragma unroll
+            for (int r = 0; r < 9; ++r)
+#pragma unroll
+                for (int c = 0; c < 9; ++c)
+                    atomicAdd(&blk[r * 9 + c],
+                              -(G[r * 3] * Wq[c * 3] + G[r * 3 + 1] * Wq[c * 3 + 1] + G[r * 3 + 2] * Wq[c * 3 + 2]));
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // diagonal block: D(S)_j, formed by the build from the same sums
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[b0 + mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int e = lane; e < 81; e += 64) acc[(size_t)lo * 81 + e] = Dblk[(int64_t)j * 81 + e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < nb * 81; e += 64) val[(int64_t)b0 * 81 + e] = acc[e];
+}
+
+// y_j = sum_t S_(j, col t) v_(col t): one wavefront per block row; lane (t0, r), t0 < 7,
+// r < 9, adds row r of blocks t0, t0 + 7, ...; the seven partial sums of a row are then
+// added in t0 order.  When `done` is set and nonzero, the launch does nothing.
+__global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                const double *__restrict__ v, double *__restrict__ y,
+                                                const double *__restrict__ done) {
+    if (done && *done != 0.0) return;
+    __shared__ double sh[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + w;
+    double acc = 0.0;
+    if (j < np && lane < 63) {
+        const int t0 = lane / 9, r = lane - t0 * 9;
+        for (int t = row_ptr[j] + t0; t < row_ptr[j + 1]; t += 7) {
+            const double *S = val + (int64_t)t * 81 + r * 9;
+            const double *vk = v + (int64_t)col[t] * 9;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) acc += S[c] * vk[c];
+        }
+    }
+    sh[w][lane] = acc;
+    __syncthreads();
+    if (j < np && lane < 9) {
+        double s = 0.0;
+        for (int t0 = 0; t0 < 7; ++t0) s += sh[w][t0 * 9 + lane];
+        y[(int64_t)j * 9 + lane] = s;
+    }
+}
+
+// Y[p][row of j] = sum over blocks t of row j with group(col t) == p of S_(j, col t) z_(col t)
+// (the multidirectional product of eq. (19)'s input): one wavefront per block row,
+// per-subset sums in the wavefront's LDS (one wavefront: program and lane order fixed).
+__global__ __launch_bounds__(64) void k_bsr_mm_grouped(int np, int N, int64_t n, const int32_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val,
+                                                       const int32_t *__restrict__ group,
+                                                       const double *__restrict__ z, double *__restrict__ Y) {
+    __shared__ double yl[kMaxBlock * 9];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (int e = lane; e < N * 9; e += 64) yl[e] = 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 63) {
+        const int t0 = lane / 9, r = lane - t0 * 9;
+        for (int t = row_ptr[j] + t0; t < row_ptr[j + 1]; t += 7) {
+            const int k = col[t];
+            const double *S = val + (int64_t)t * 81 + r * 9;
+            const double *zk = z + (int64_t)k * 9;
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) s += S[c] * zk[c];
+            atomicAdd(&yl[group[k] * 9 + r], s);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < N * 9; e += 64) {
+        const int p = e / 9, r = e - p * 9;
+        Y[(int64_t)p * n + (int64_t)j * 9 + r] = yl[e];
+    }
+}
+
+void launch_bsr_assemble(int np, const int64_t *pair_ptr, const int32_t *pairs, const double *J64, const double *vinv,
+                         const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, double *val,
+                         hipStream_t s) {
+    const size_t lds = (size_t)max_row * 81 * sizeof(double);
+    hipLaunchKernelGGL(k_bsr_assemble, dim3(np), dim3(64), lds, s, pair_ptr, reinterpret_cast<const int4 *>(pairs),
+                       J64, vinv, Dblk, row_ptr, col, val);
+}
+
+void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,
+                   const double *done, hipStream_t s) {
+    hipLaunchKernelGGL(k_bsr_mv, dim3((np + 3) / 4), dim3(256), 0, s, np, row_ptr, col, val, v, y, done);
+}
+
+void launch_bsr_mm_grouped(int np, int N, const int32_t *row_ptr, const int32_t *col, const double *val,
+                           const int32_t *group, const double *z, double *Y, hipStream_t s) {
+    hipLaunchKernelGGL(k_bsr_mm_grouped, dim3(np), dim3(64), 0, s, np, N, (int64_t)np * 9, row_ptr, col, val, group, z,
+                       Y);
+}
+
+}  // namespace ba

@@ -181,6 +181,16 @@ void launch_mlp_backward(const float *P, const float *F, const float *hid, const
 void launch_adam(float *P, const float *g, float *m, float *v, int t, float lr, hipStream_t s);
 
 
+// ---------------------------------------------------------------- explicit S (block-sparse rows)
+// rows assembled from the contribution pairs of build_bsr_pairs (pairs: 4 int32 each)
+void launch_bsr_assemble(int np, const int64_t *pair_ptr, const int32_t *pairs, const double *J64, const double *vinv,
+                         const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, double *val,
+                         hipStream_t s);
+void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,
+                   const double *done, hipStream_t s);
+void launch_bsr_mm_grouped(int np, int N, const int32_t *row_ptr, const int32_t *col, const double *val,
+                           const int32_t *group, const double *z, double *Y, hipStream_t s);
+
 // ---------------------------------------------------------------- batches (Algorithm 2 per problem)
 
 struct BatchProb {            // problem b of a batch (static)
