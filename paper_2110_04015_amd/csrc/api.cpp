@@ -882,7 +882,6 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
         matvec(s, sa, Ph, Qh);
         std::vector<int32_t> hoff{0}, hk{1};
         std::vector<int64_t> hdp{0};
-        launch_set_block(blk_off, blk_k, blk_dp, 0, 0, 1, 0, q);
         int64_t dp_used = 1;
         hcols = 1;
         result = BA_MAXITER;
@@ -892,15 +891,21 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             const int64_t dpo = hdp.back();
             // Delta_i = Q_i^T P_i, gamma_i = P_i^T r_i, alpha_i = Delta_i^+ gamma_i
             launch_gram(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, r, red, q);
-            launch_pinv_alpha(k, red, kRedBlocks, Dp + dpo, gamma, alpha, sc, q);
-            // x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i
-            launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
-            launch_pcg_rr(red, sc, q);
-            // tau-test scalars, computed before the single read-back of the iteration:
+            BlockEntry be;       // the current block's history table entry, written with its Delta^+
+            be.off = blk_off;
+            be.k = blk_k;
+            be.dp = blk_dp;
+            be.j = nb - 1;
+            be.first = off;
+            be.dpo = dpo;
+            launch_pinv_alpha(k, red, kRedBlocks, Dp + dpo, gamma, alpha, sc, q, be);
+            // x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i ; Z = D^-1 r_{i+1}, and the
+            // tau-test scalars before the single read-back of the iteration:
             // t_i = gamma_i^T alpha_i / (r_{i+1}^T D^-1 r_{i+1})
+            launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
             launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q);
             if (lowrank) launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
-            launch_tau(k, red + kRedBlocks, gamma, alpha, sc, q);
+            launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, q);
             HIPCHK(hipGetLastError());
             if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
             if (h[SC_RANK] == 0.0) {
@@ -949,7 +954,6 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             hoff.push_back((int32_t)hcols);
             hk.push_back(kn);
             hdp.push_back(dp_used);
-            launch_set_block(blk_off, blk_k, blk_dp, nb, hoff[nb], hk[nb], hdp[nb], q);
             dp_used += (int64_t)kn * kn;
             hcols += kn;
             multi_steps += multi;

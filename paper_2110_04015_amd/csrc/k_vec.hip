@@ -51,6 +51,7 @@ void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const 
     hipLaunchKernelGGL(k_precond_dot, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, Q, z, partials, done);
 }
 
+
 void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_precond_dot, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, r, z, partials,
@@ -325,7 +326,8 @@ void launch_gram(int64_t n, int k, const double *P, const double *Q, const doubl
 // Delta (symmetrised) and gamma from the Gram partials; Delta^+; alpha = Delta^+ gamma
 __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restrict__ partials, int nblocks,
                                                     double *__restrict__ Dp, double *__restrict__ gamma,
-                                                    double *__restrict__ alpha, double *__restrict__ sc) {
+                                                    double *__restrict__ alpha, double *__restrict__ sc,
+                                                    BlockEntry blk) {
     __shared__ double A[kMaxK * kMaxK], V[kMaxK * kMaxK], G[kMaxK * kMaxK];
     __shared__ double gam[kMaxK], cs[kMaxK], sn[kMaxK], sh[kNT];
     __shared__ int flag, rank;
@@ -358,12 +360,19 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
         alpha[a] = s;
         gamma[a] = gam[a];
     }
-    if (tid == 0) sc[SC_RANK] = (double)rank;
+    if (tid == 0) {
+        sc[SC_RANK] = (double)rank;
+        if (blk.off) {   // history block table entry of the current block
+            blk.off[blk.j] = blk.first;
+            blk.k[blk.j] = k;
+            blk.dp[blk.j] = blk.dpo;
+        }
+    }
 }
 
 void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, double *gamma, double *alpha,
-                       double *sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_pinv_alpha, dim3(1), dim3(kNT), 0, s, k, partials, nblocks, Dp, gamma, alpha, sc);
+                       double *sc, hipStream_t s, BlockEntry blk) {
+    hipLaunchKernelGGL(k_pinv_alpha, dim3(1), dim3(kNT), 0, s, k, partials, nblocks, Dp, gamma, alpha, sc, blk);
 }
 
 // Stand-alone symmetric pseudo-inverse (test entry point).
@@ -413,20 +422,24 @@ void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, co
     hipLaunchKernelGGL(k_update_xr_blk, dim3(kRedBlocks), dim3(kNT), 0, s, n, k, P, Q, alpha, x, r, partials);
 }
 
-// rho = r^T D^-1 r from the partials; t = gamma^T alpha / rho (the tau-test of Alg. 2)
-__global__ __launch_bounds__(64) void k_tau(int k, const double *__restrict__ prho, const double *__restrict__ gamma,
-                                            const double *__restrict__ alpha, double *__restrict__ sc) {
+// sc[SC_RR] from the |r|^2 partials; rho = r^T M^-1 r from its partials; t = gamma^T alpha / rho
+__global__ __launch_bounds__(64) void k_mcg_scalars(int k, const double *__restrict__ prr,
+                                                    const double *__restrict__ prho,
+                                                    const double *__restrict__ gamma,
+                                                    const double *__restrict__ alpha, double *__restrict__ sc) {
+    const double rr = wave_partials(prr, 1, kRedBlocks);
     const double rho = wave_partials(prho, 1, kRedBlocks);
     if (threadIdx.x != 0) return;
     double ga = 0.0;
     for (int a = 0; a < k; ++a) ga += gamma[a] * alpha[a];
+    sc[SC_RR] = rr;
     sc[SC_RHO] = rho;
     sc[SC_T] = rho > 0.0 ? ga / rho : INFINITY;
 }
 
-void launch_tau(int k, const double *partials_rho, const double *gamma, const double *alpha, double *sc,
-                hipStream_t s) {
-    hipLaunchKernelGGL(k_tau, dim3(1), dim3(64), 0, s, k, partials_rho, gamma, alpha, sc);
+void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
+                        double *sc, hipStream_t s) {
+    hipLaunchKernelGGL(k_mcg_scalars, dim3(1), dim3(64), 0, s, k, prr, prho, gamma, alpha, sc);
 }
 
 // Phi[col][p] = Q_hist[:, col]^T Z[:, p]: for a multidirectional Z only the rows of
@@ -457,18 +470,6 @@ __global__ __launch_bounds__(kNT) void k_phi(int64_t n, const double *__restrict
 void launch_phi(int64_t n, int h, const double *Qh, const double *z, int multi, int N, int gs, double *Phi,
                 hipStream_t s) {
     hipLaunchKernelGGL(k_phi, dim3(h, multi ? N : kPhiSeg), dim3(kNT), 0, s, n, Qh, z, multi, N, gs, Phi);
-}
-
-// records history block j (first column, width, offset of its Delta^+) on the device
-__global__ void k_set_block(int32_t *blk_off, int32_t *blk_k, int64_t *blk_dp, int j, int off, int kj, int64_t dp) {
-    blk_off[j] = off;
-    blk_k[j] = kj;
-    blk_dp[j] = dp;
-}
-
-void launch_set_block(int32_t *blk_off, int32_t *blk_k, int64_t *blk_dp, int j, int off, int kj, int64_t dp,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(k_set_block, dim3(1), dim3(1), 0, s, blk_off, blk_k, blk_dp, j, off, kj, dp);
 }
 
 // beta rows of history block j: beta[off_j + a][p] = sum_b Delta_j^+[a][b] Phi[off_j + b][p]

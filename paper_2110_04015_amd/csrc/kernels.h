@@ -146,14 +146,23 @@ void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s);
 // MCG steps
 void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
                  hipStream_t s);
+// history block table entry written by the pseudo-inverse kernel (off == nullptr: none)
+struct BlockEntry {
+    int32_t *off = nullptr, *k = nullptr;
+    int64_t *dp = nullptr;
+    int j = 0, first = 0;
+    int64_t dpo = 0;
+};
 void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, double *gamma, double *alpha,
-                       double *sc, hipStream_t s);
+                       double *sc, hipStream_t s, BlockEntry blk = BlockEntry());
+// x += P alpha, r -= Q alpha (n x k, column-major); |r|^2 partials
 void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, const double *alpha, double *x,
                           double *r, double *partials, hipStream_t s);
-void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials,
-                        hipStream_t s);
-void launch_tau(int k, const double *partials_rho, const double *gamma, const double *alpha, double *sc,
-                hipStream_t s);
+// z = D^-1 r and partials of r^T z
+void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials, hipStream_t s);
+// sc[SC_RR], sc[SC_RHO], sc[SC_T] from the partials (Alg. 2's stop and tau tests)
+void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
+                        double *sc, hipStream_t s);
 void launch_phi(int64_t n, int h, const double *Qh, const double *z, int multi, int N, int gs,
                 double *Phi, hipStream_t s);
 void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int64_t *blk_dp, const double *Dp,
@@ -161,8 +170,6 @@ void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int
 void launch_update_pq(int64_t n, int h, int kn, const double *Ph, const double *Qh, const double *beta,
                       const double *z, int multi, int gs, int N, const double *Y, double *Pn, double *Qn,
                       double *scratch, int64_t scratch_doubles, hipStream_t s);
-void launch_set_block(int32_t *blk_off, int32_t *blk_k, int64_t *blk_dp, int j, int off, int kj, int64_t dp,
-                      hipStream_t s);
 void launch_pinv_sym(int k, const double *A, double *Ap, int32_t *rank, hipStream_t s);
 
 // ---- learned low-rank preconditioner (k_learned.hip)
