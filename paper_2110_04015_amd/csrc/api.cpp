@@ -119,6 +119,8 @@ void free_all(ba_system *s) {
     dfree(s->bsr_val);
     if (s->host_pinned) (void)hipHostFree(s->host_pinned);
     s->host_pinned = nullptr;
+    if (s->sc_event) (void)hipEventDestroy(s->sc_event);
+    s->sc_event = nullptr;
     free_multi(s->multi);
     for (hipEvent_t e : s->prof_events) (void)hipEventDestroy(e);
     s->prof_events.clear();
@@ -320,8 +322,24 @@ ba_status ensure_red(ba_system *s, size_t doubles) {
 }
 
 ba_status ensure_pinned(ba_system *s) {
-    if (s->host_pinned) return BA_OK;
-    HIPCHK(hipHostMalloc((void **)&s->host_pinned, SC_COUNT * sizeof(double), hipHostMallocDefault));
+    if (!s->host_pinned)
+        HIPCHK(hipHostMalloc((void **)&s->host_pinned, SC_COUNT * sizeof(double), hipHostMallocDefault));
+    if (!s->sc_event) HIPCHK(hipEventCreateWithFlags(&s->sc_event, hipEventDisableTiming));
+    return BA_OK;
+}
+
+// Enqueues the copy of the device scalars to the host behind the work enqueued so far
+// and marks that point; scalars_wait() then waits for it only, so kernels launched in
+// between keep the device busy while the host waits.
+static ba_status scalars_post(ba_system *s, const double *sc) {
+    HIPCHK(hipMemcpyAsync(s->host_pinned, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipEventRecord(s->sc_event, s->stream));
+    return BA_OK;
+}
+
+static ba_status scalars_wait(ba_system *s, double *out) {
+    HIPCHK(hipEventSynchronize(s->sc_event));
+    memcpy(out, s->host_pinned, SC_COUNT * sizeof(double));
     return BA_OK;
 }
 
@@ -854,6 +872,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     const int gs = s->np / N;
     const SchurArgs sa = schur_args(s, prec);
     const MultiArgs ma = N > 1 ? multi_args(s, prec) : MultiArgs();
+    const bool use_bsr_multi = N > 1 && s->bsr_val && prec == 0 && N <= kMaxBlock;
 
     auto t0 = std::chrono::steady_clock::now();
     if ((st = init_scalars(s, sc)) != BA_OK) return st;
@@ -905,9 +924,27 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
             launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q);
             if (lowrank) launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
-            launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, q);
+            launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, N, tau, opts.eps, q);
+            if ((st = scalars_post(s, sc)) != BA_OK) return st;
+            // Work that does not wait for the tau-test goes ahead of the read-back, so the
+            // device is busy while the host waits for it: Phi_{i,j} = Q_j^T Z_{i+1} per
+            // subset (valid for either outcome), and S Z_{i+1} of a multidirectional step,
+            // which the kernels skip on the device when sc[SC_SKIPM] says the step is not one.
+            double *Pn = Ph + hcols * n, *Qn = Qh + hcols * n;
+            const bool ahead = N > 1 && hcols + N <= hc;
+            launch_phi(n, (int)hcols, Qh, z, N, gs, Phi, q);
+            if (ahead) {
+                if (use_bsr_multi) {
+                    launch_bsr_mm_grouped(s->np, N, s->bsr_ptr, s->bsr_col, s->bsr_val, s->multi.group, z, Qn, q,
+                                          sc + SC_SKIPM);
+                } else {
+                    MultiArgs mp = ma;
+                    mp.skip = sc + SC_SKIPM;
+                    launch_schur_multi(mp, z, Qn, q);
+                }
+            }
             HIPCHK(hipGetLastError());
-            if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
+            if ((st = scalars_wait(s, h)) != BA_OK) return st;
             if (h[SC_RANK] == 0.0) {
                 result = BA_ERR_BREAKDOWN;
                 g_err = "MCG breakdown: Delta_i is numerically zero";
@@ -926,7 +963,14 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 break;
             }
             const double t_i = h[SC_T];
-            const bool multi = N > 1 && t_i < tau;
+            if (N > 1 && t_i < tau && !ahead) {
+                result = fail(BA_ERR_WORKSPACE, "MCG direction history is full (raise max_history_cols)");
+                break;
+            }
+            // The branch is the one the device took for S Z_{i+1}: the same t_i < tau test on
+            // the same value; its stop test only differs from the host's at an exact tie,
+            // where a one-column step is taken.
+            const bool multi = ahead && h[SC_SKIPM] == 0.0;
             const int kn = multi ? N : 1;
             if (stats && ti < stats->trace_cap) {
                 if (stats->trace_t) stats->trace_t[ti] = t_i;
@@ -936,16 +980,8 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 result = fail(BA_ERR_WORKSPACE, "MCG direction history is full (raise max_history_cols)");
                 break;
             }
-            double *Pn = Ph + hcols * n, *Qn = Qh + hcols * n;
-            if (multi) {                                                 // S Z_{i+1}
-                if (s->bsr_val && prec == 0 && N <= kMaxBlock)
-                    launch_bsr_mm_grouped(s->np, N, s->bsr_ptr, s->bsr_col, s->bsr_val, s->multi.group, z, Qn, q);
-                else
-                    launch_schur_multi(ma, z, Qn, q);
-            }
-            // Phi_{i,j} = Q_j^T Z_{i+1}, beta_{i,j} = Delta_j^+ Phi_{i,j}
-            launch_phi(n, (int)hcols, Qh, z, multi ? 1 : 0, N, gs, Phi, q);
-            launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, kn, beta, q);
+            // beta_{i,j} = Delta_j^+ Phi_{i,j}
+            launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, kn, N, beta, q);
             // P_{i+1} = Z - sum P_j beta ; multidirectional: Q_{i+1} = S Z - sum Q_j beta (eq. (19))
             launch_update_pq(n, (int)hcols, kn, Ph, Qh, beta, z, multi ? 1 : 0, gs, N, multi ? Qn : nullptr, Pn,
                              multi ? Qn : nullptr, s->hscratch, s->hscratch_cap, q);

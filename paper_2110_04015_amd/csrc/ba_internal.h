@@ -163,6 +163,7 @@ struct ba_system {
     double *lr_proj = nullptr;      // kRedBlocks x 8 projections U^T r
     size_t small_cap = 0;
     double *host_pinned = nullptr;  // pinned host scalars
+    hipEvent_t sc_event = nullptr;  // marks the point of the stream where host_pinned was filled
     ba::DevMulti multi;
     // batches: problem of every camera and of every chunk of the S product (device)
     int32_t *seg_cam = nullptr, *seg_chunk = nullptr;

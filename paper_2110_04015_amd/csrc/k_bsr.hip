@@ -128,7 +128,9 @@ __global__ __launch_bounds__(64) void k_bsr_mm_grouped(int np, int N, int64_t n,
                                                        const int32_t *__restrict__ col,
                                                        const double *__restrict__ val,
                                                        const int32_t *__restrict__ group,
-                                                       const double *__restrict__ z, double *__restrict__ Y) {
+                                                       const double *__restrict__ z, double *__restrict__ Y,
+                                                       const double *__restrict__ skip) {
+    if (skip && *skip != 0.0) return;
     __shared__ double yl[kMaxBlock * 9];
     const int j = blockIdx.x;
     const int lane = threadIdx.x;
@@ -171,9 +173,9 @@ void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const dou
 }
 
 void launch_bsr_mm_grouped(int np, int N, const int32_t *row_ptr, const int32_t *col, const double *val,
-                           const int32_t *group, const double *z, double *Y, hipStream_t s) {
+                           const int32_t *group, const double *z, double *Y, hipStream_t s, const double *skip) {
     hipLaunchKernelGGL(k_bsr_mm_grouped, dim3(np), dim3(64), 0, s, np, N, (int64_t)np * 9, row_ptr, col, val, group, z,
-                       Y);
+                       Y, skip);
 }
 
 }  // namespace ba

@@ -332,6 +332,7 @@ void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStre
 
 template <int PREC, typename T>
 __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *__restrict__ z) {
+    if (a.skip && *a.skip != 0.0) return;
     if (a.seg_skip && a.seg_skip[a.chunk_seg[blockIdx.x]]) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double *yloc = reinterpret_cast<double *>(smem);   // FP64 sums for every precision (see schur_tile)
@@ -413,7 +414,8 @@ __global__ void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr,
                                const double *__restrict__ partial, const double *__restrict__ dU,
                                const int32_t *__restrict__ group, const double *__restrict__ z,
                                double *__restrict__ Y, const int32_t *__restrict__ cam_seg,
-                               const int32_t *__restrict__ seg_skip) {
+                               const int32_t *__restrict__ seg_skip, const double *__restrict__ skip) {
+    if (skip && *skip != 0.0) return;
     int64_t n = (int64_t)np * 9;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * N) return;
@@ -438,7 +440,7 @@ void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStrea
     }
     int64_t total = (int64_t)a.np * 9 * a.N;
     hipLaunchKernelGGL(k_reduce_multi, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.np, a.N, a.cg_ptr,
-                       a.partial, a.dU, a.group, z, Y, a.cam_seg, a.seg_skip);
+                       a.partial, a.dU, a.group, z, Y, a.cam_seg, a.seg_skip, a.skip);
 }
 
 // ---------------------------------------------------------------- eq. (16)

@@ -426,79 +426,106 @@ void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, co
 __global__ __launch_bounds__(64) void k_mcg_scalars(int k, const double *__restrict__ prr,
                                                     const double *__restrict__ prho,
                                                     const double *__restrict__ gamma,
-                                                    const double *__restrict__ alpha, double *__restrict__ sc) {
+                                                    const double *__restrict__ alpha, double *__restrict__ sc,
+                                                    int N, double tau, double eps) {
     const double rr = wave_partials(prr, 1, kRedBlocks);
     const double rho = wave_partials(prho, 1, kRedBlocks);
     if (threadIdx.x != 0) return;
     double ga = 0.0;
     for (int a = 0; a < k; ++a) ga += gamma[a] * alpha[a];
+    const double t = rho > 0.0 ? ga / rho : INFINITY;
     sc[SC_RR] = rr;
     sc[SC_RHO] = rho;
-    sc[SC_T] = rho > 0.0 ? ga / rho : INFINITY;
+    sc[SC_T] = t;
+    const bool converged = sqrt(rr) < eps * sqrt(sc[SC_RR0]);
+    sc[SC_SKIPM] = (N > 1 && t < tau && !converged) ? 0.0 : 1.0;
 }
 
 void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
-                        double *sc, hipStream_t s) {
-    hipLaunchKernelGGL(k_mcg_scalars, dim3(1), dim3(64), 0, s, k, prr, prho, gamma, alpha, sc);
+                        double *sc, int N, double tau, double eps, hipStream_t s) {
+    hipLaunchKernelGGL(k_mcg_scalars, dim3(1), dim3(64), 0, s, k, prr, prho, gamma, alpha, sc, N, tau, eps);
 }
 
-// Phi[col][p] = Q_hist[:, col]^T Z[:, p]: for a multidirectional Z only the rows of
-// subset p contribute (gs poses per subset, the last subset takes the rest).  For a
-// one-column Z the dot product is split into kPhiSeg row segments (one block each,
-// for parallelism); k_beta adds the segments in order.
-__global__ __launch_bounds__(kNT) void k_phi(int64_t n, const double *__restrict__ Qh,
-                                             const double *__restrict__ z, int multi, int N, int gs,
+// Phi[col][p] = Q_hist[:, col]^T z restricted to segment p: with N > 1 subsets the
+// segments are the subsets (gs poses each, the last takes the rest), which is Phi of a
+// multidirectional Z; a one-column Z = D^-1 r needs their sum, which k_beta forms.  So
+// Phi does not depend on the tau-test and can run before its outcome is known.  With
+// N = 1 the rows are split into kPhiSeg equal segments (for parallelism only).  One
+// wavefront per (column, segment); four per block.
+__global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const double *__restrict__ Qh,
+                                             const double *__restrict__ z, int N, int gs,
                                              double *__restrict__ Phi) {
-    __shared__ double sh[kNT];
-    const int col = blockIdx.x;
-    const int p = blockIdx.y;
+    const int64_t w = (int64_t)blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= (int64_t)h * seg) return;
+    const int64_t col = w / seg;
+    const int p = (int)(w - col * seg);
     int64_t lo, hi;
-    if (multi) {
+    if (N > 1) {
         lo = (int64_t)p * gs * 9;
         hi = (p == N - 1) ? n : (int64_t)(p + 1) * gs * 9;
     } else {
-        lo = n * p / kPhiSeg;
-        hi = n * (p + 1) / kPhiSeg;
+        lo = n * p / seg;
+        hi = n * (p + 1) / seg;
     }
-    const double *q = Qh + (int64_t)col * n;
-    double acc = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kNT) acc += q[i] * z[i];
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) Phi[(int64_t)col * (multi ? N : kPhiSeg) + p] = acc;
+    const double *q = Qh + col * n;
+    double a0 = 0.0, a1 = 0.0;
+    int64_t i = lo + lane;
+    for (; i + 64 < hi; i += 128) {
+        a0 += q[i] * z[i];
+        a1 += q[i + 64] * z[i + 64];
+    }
+    if (i < hi) a0 += q[i] * z[i];
+    const double acc = wave_sum(a0 + a1);
+    if (lane == 0) Phi[w] = acc;
 }
 
-void launch_phi(int64_t n, int h, const double *Qh, const double *z, int multi, int N, int gs, double *Phi,
-                hipStream_t s) {
-    hipLaunchKernelGGL(k_phi, dim3(h, multi ? N : kPhiSeg), dim3(kNT), 0, s, n, Qh, z, multi, N, gs, Phi);
+int phi_segments(int N) { return N > 1 ? N : kPhiSeg; }
+
+void launch_phi(int64_t n, int h, const double *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s) {
+    if (h <= 0) return;
+    const int seg = phi_segments(N);
+    const int64_t waves = (int64_t)h * seg;
+    const int per = kNT / 64;
+    hipLaunchKernelGGL(k_phi, dim3((unsigned)((waves + per - 1) / per)), dim3(kNT), 0, s, n, h, seg, Qh, z, N, gs,
+                       Phi);
 }
 
 // beta rows of history block j: beta[off_j + a][p] = sum_b Delta_j^+[a][b] Phi[off_j + b][p]
 __global__ __launch_bounds__(kNT) void k_beta(const int32_t *__restrict__ blk_off, const int32_t *__restrict__ blk_k,
                                               const int64_t *__restrict__ blk_dp, const double *__restrict__ Dp,
-                                              const double *__restrict__ Phi, int kn, double *__restrict__ beta) {
+                                              const double *__restrict__ Phi, int kn, int seg,
+                                              double *__restrict__ beta) {
+    __shared__ double f1[kMaxK];
     const int j = blockIdx.x;
     const int off = blk_off[j], kj = blk_k[j];
     const double *D = Dp + blk_dp[j];
-    for (int w = threadIdx.x; w < kj * kn; w += kNT) {
-        int a = w / kn, p = w - a * kn;
-        double s = 0.0;
-        for (int b = 0; b < kj; ++b) {
-            double f;
-            if (kn == 1) {   // one-column Z: the segments of k_phi, in order
-                f = 0.0;
-                for (int g = 0; g < kPhiSeg; ++g) f += Phi[(int64_t)(off + b) * kPhiSeg + g];
-            } else {
-                f = Phi[(int64_t)(off + b) * kn + p];
-            }
-            s += D[a * kj + b] * f;
+    if (kn == 1) {   // one-column Z: Phi of column off + b is the sum of its segments, in order
+        for (int b = threadIdx.x; b < kj; b += kNT) {
+            const double *ph = Phi + (int64_t)(off + b) * seg;
+            double f = 0.0;
+            for (int g = 0; g < seg; ++g) f += ph[g];
+            f1[b] = f;
         }
+        __syncthreads();
+        for (int a = threadIdx.x; a < kj; a += kNT) {
+            double s = 0.0;
+            for (int b = 0; b < kj; ++b) s += D[a * kj + b] * f1[b];
+            beta[off + a] = s;
+        }
+        return;
+    }
+    for (int w = threadIdx.x; w < kj * kn; w += kNT) {   // multidirectional: segment p is subset p
+        const int a = w / kn, p = w - a * kn;
+        double s = 0.0;
+        for (int b = 0; b < kj; ++b) s += D[a * kj + b] * Phi[(int64_t)(off + b) * seg + p];
         beta[(int64_t)(off + a) * kn + p] = s;
     }
 }
 
 void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int64_t *blk_dp, const double *Dp,
-                 const double *Phi, int kn, double *beta, hipStream_t s) {
-    hipLaunchKernelGGL(k_beta, dim3(nb), dim3(kNT), 0, s, blk_off, blk_k, blk_dp, Dp, Phi, kn, beta);
+                 const double *Phi, int kn, int N, double *beta, hipStream_t s) {
+    hipLaunchKernelGGL(k_beta, dim3(nb), dim3(kNT), 0, s, blk_off, blk_k, blk_dp, Dp, Phi, kn, phi_segments(N), beta);
 }
 
 // History products of the reorthogonalisation, Out[:, p] = Base[:, p] - sum_col H[:, col] beta[col][p]

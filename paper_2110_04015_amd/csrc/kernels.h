@@ -24,6 +24,7 @@ enum {
     SC_DONE = 11,    // 1 once the PCG loop has stopped (device-side stop test)
     SC_ITER = 12,    // completed PCG iterations
     SC_STATUS = 13,  // ba_status of the PCG loop
+    SC_SKIPM = 14,   // MCG: 1 unless the next block is multidirectional (t < tau, not converged)
     SC_COUNT = 16
 };
 
@@ -105,6 +106,7 @@ struct MultiArgs {
     int np = 0, N = 0;
     // batches (nullable): a chunk / camera of problem b does nothing when seg_skip[b] != 0
     const int32_t *chunk_seg = nullptr, *cam_seg = nullptr, *seg_skip = nullptr;
+    const double *skip = nullptr;             // nullable: when *skip != 0 the launch does nothing
 };
 // Y[p] = S (z restricted to subset p), Y column-major [N][n]
 void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s);
@@ -160,13 +162,17 @@ void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, co
                           double *r, double *partials, hipStream_t s);
 // z = D^-1 r and partials of r^T z
 void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials, hipStream_t s);
-// sc[SC_RR], sc[SC_RHO], sc[SC_T] from the partials (Alg. 2's stop and tau tests)
+// sc[SC_RR], sc[SC_RHO], sc[SC_T] from the partials (Alg. 2's stop and tau tests), and
+// sc[SC_SKIPM]: 0 when the next block is multidirectional (N > 1, t < tau, not converged)
 void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
-                        double *sc, hipStream_t s);
-void launch_phi(int64_t n, int h, const double *Qh, const double *z, int multi, int N, int gs,
-                double *Phi, hipStream_t s);
+                        double *sc, int N, double tau, double eps, hipStream_t s);
+// Phi segments per history column: the N subsets when N > 1 (the same for one-column
+// and multidirectional steps), kPhiSeg row segments when N = 1
+int phi_segments(int N);
+void launch_phi(int64_t n, int h, const double *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s);
+// beta = Delta^+ Phi per history block; kn = 1 adds Phi's segments, kn = N takes them apart
 void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int64_t *blk_dp, const double *Dp,
-                 const double *Phi, int kn, double *beta, hipStream_t s);
+                 const double *Phi, int kn, int N, double *beta, hipStream_t s);
 void launch_update_pq(int64_t n, int h, int kn, const double *Ph, const double *Qh, const double *beta,
                       const double *z, int multi, int gs, int N, const double *Y, double *Pn, double *Qn,
                       double *scratch, int64_t scratch_doubles, hipStream_t s);
@@ -196,7 +202,8 @@ void launch_bsr_assemble(int np, const int64_t *pair_ptr, const int32_t *pairs, 
 void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,
                    const double *done, hipStream_t s);
 void launch_bsr_mm_grouped(int np, int N, const int32_t *row_ptr, const int32_t *col, const double *val,
-                           const int32_t *group, const double *z, double *Y, hipStream_t s);
+                           const int32_t *group, const double *z, double *Y, hipStream_t s,
+                           const double *skip = nullptr);
 
 // ---------------------------------------------------------------- batches (Algorithm 2 per problem)
 
