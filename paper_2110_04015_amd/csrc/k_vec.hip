@@ -267,45 +267,73 @@ void launch_pcg_update_p(int64_t n, const double *partials_phi, double *sc, cons
 
 // ---------------------------------------------------------------- Algorithm 2
 
-constexpr int kGramRows = 16;
 constexpr int kGramOut = (kMaxK * kMaxK + kMaxK + kNT - 1) / kNT;   // outputs per thread
+constexpr int kGramLds = 64 * 1024;                                   // bytes of one row chunk
 
-// partials[b][a * k + c] = sum_rows Q[:, a] . P[:, c] ; partials[b][k*k + a] = sum_rows P[:, a] . r
-__global__ __launch_bounds__(kNT) void k_gram(int64_t n, int k, const double *__restrict__ P,
+// k = 1: partials[b][0] = Q . P, partials[b][1] = P . r over a grid-stride share of
+// the rows (wavefront butterflies, then the four wavefronts in order)
+__global__ __launch_bounds__(kNT) void k_gram1(int64_t n, const double *__restrict__ P,
+                                               const double *__restrict__ Q, const double *__restrict__ r,
+                                               double *__restrict__ partials) {
+    __shared__ double sh[2][kNT / 64];
+    double qp = 0.0, pr = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kNT;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
+        const double p = P[i];
+        qp += Q[i] * p;
+        pr += p * r[i];
+    }
+    qp = wave_sum(qp);
+    pr = wave_sum(pr);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = qp;
+        sh[1][w] = pr;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double s = 0.0;
+        for (int u = 0; u < kNT / 64; ++u) s += sh[threadIdx.x][u];
+        partials[(int64_t)blockIdx.x * 2 + threadIdx.x] = s;
+    }
+}
+
+// k > 1: partials[b][a * k + c] = sum_rows Q[:, a] . P[:, c] ; partials[b][k*k + a] = sum_rows P[:, a] . r
+// over block b's contiguous row range.  The range is staged through LDS in chunks of R
+// rows (R (2k + 1) doubles fit kGramLds), each chunk loaded in one pass so that all its
+// loads are in flight together.
+__global__ __launch_bounds__(kNT) void k_gram(int64_t n, int k, int R, const double *__restrict__ P,
                                               const double *__restrict__ Q, const double *__restrict__ r,
                                               double *__restrict__ partials) {
-    __shared__ double sP[kGramRows][kMaxK], sQ[kGramRows][kMaxK], sr[kGramRows];
+    extern __shared__ double gsm[];
+    double *sP = gsm, *sQ = gsm + (int64_t)R * k, *sr = sQ + (int64_t)R * k;
     const int tot = k * k + k;
     double acc[kGramOut];
 #pragma unroll
     for (int o = 0; o < kGramOut; ++o) acc[o] = 0.0;
-    const int64_t ntiles = (n + kGramRows - 1) / kGramRows;
-    for (int64_t it = blockIdx.x; it < ntiles; it += gridDim.x) {
-        const int64_t r0 = it * kGramRows;
-        for (int w = threadIdx.x; w < kGramRows * k; w += kNT) {
-            int a = w / kGramRows, rr = w % kGramRows;
-            int64_t row = r0 + rr;
-            bool in = row < n;
-            sP[rr][a] = in ? P[(int64_t)a * n + row] : 0.0;
-            sQ[rr][a] = in ? Q[(int64_t)a * n + row] : 0.0;
+    const int64_t lo = n * blockIdx.x / gridDim.x, hi = n * (blockIdx.x + 1) / gridDim.x;
+    for (int64_t r0 = lo; r0 < hi; r0 += R) {
+        const int rows = (int)(hi - r0 < R ? hi - r0 : R);
+#pragma unroll 4
+        for (int w = threadIdx.x; w < rows * k; w += kNT) {
+            const int a = w / rows, rr = w - a * rows;   // consecutive threads: consecutive rows of column a
+            sP[rr * k + a] = P[(int64_t)a * n + r0 + rr];
+            sQ[rr * k + a] = Q[(int64_t)a * n + r0 + rr];
         }
-        if (threadIdx.x < kGramRows) {
-            int64_t row = r0 + threadIdx.x;
-            sr[threadIdx.x] = row < n ? r[row] : 0.0;
-        }
+        for (int rr = threadIdx.x; rr < rows; rr += kNT) sr[rr] = r[r0 + rr];
         __syncthreads();
 #pragma unroll
         for (int o = 0; o < kGramOut; ++o) {
-            int idx = threadIdx.x + o * kNT;
+            const int idx = threadIdx.x + o * kNT;
             if (idx < k * k) {
-                int a = idx / k, c = idx - a * k;
+                const int a = idx / k, c = idx - a * k;
                 double s = 0.0;
-                for (int rr = 0; rr < kGramRows; ++rr) s += sQ[rr][a] * sP[rr][c];
+                for (int rr = 0; rr < rows; ++rr) s += sQ[rr * k + a] * sP[rr * k + c];
                 acc[o] += s;
             } else if (idx < tot) {
-                int a = idx - k * k;
+                const int a = idx - k * k;
                 double s = 0.0;
-                for (int rr = 0; rr < kGramRows; ++rr) s += sP[rr][a] * sr[rr];
+                for (int rr = 0; rr < rows; ++rr) s += sP[rr * k + a] * sr[rr];
                 acc[o] += s;
             }
         }
@@ -313,14 +341,22 @@ __global__ __launch_bounds__(kNT) void k_gram(int64_t n, int k, const double *__
     }
 #pragma unroll
     for (int o = 0; o < kGramOut; ++o) {
-        int idx = threadIdx.x + o * kNT;
+        const int idx = threadIdx.x + o * kNT;
         if (idx < tot) partials[(int64_t)blockIdx.x * tot + idx] = acc[o];
     }
 }
 
 void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
                  hipStream_t s) {
-    hipLaunchKernelGGL(k_gram, dim3(kRedBlocks), dim3(kNT), 0, s, n, k, P, Q, r, partials);
+    if (k == 1) {
+        hipLaunchKernelGGL(k_gram1, dim3(kRedBlocks), dim3(kNT), 0, s, n, P, Q, r, partials);
+        return;
+    }
+    const int64_t per = (n + kRedBlocks - 1) / kRedBlocks;
+    const int64_t cap = kGramLds / (int64_t)((2 * k + 1) * sizeof(double));
+    const int R = (int)std::max<int64_t>(1, std::min(per, cap));
+    const size_t lds = (size_t)R * (2 * k + 1) * sizeof(double);
+    hipLaunchKernelGGL(k_gram, dim3(kRedBlocks), dim3(kNT), lds, s, n, k, R, P, Q, r, partials);
 }
 
 // Delta (symmetrised) and gamma from the Gram partials; Delta^+; alpha = Delta^+ gamma
@@ -333,18 +369,29 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
     __shared__ int flag, rank;
     const int tid = threadIdx.x;
     const int tot = k * k + k;
-    for (int idx = tid; idx < tot; idx += kNT) {
-        // eight independent running sums keep eight loads in flight per thread
-        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int b = 0;
-        for (; b + 8 <= nblocks; b += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += partials[(int64_t)(b + u) * tot + idx];
+    if (tot <= 2 * (kNT / 64)) {
+        // few outputs: one wavefront per output, all partials of an output loaded at once
+        for (int idx = tid >> 6; idx < tot; idx += kNT / 64) {
+            const double s = wave_partials(partials + idx, tot, nblocks);
+            if ((tid & 63) == 0) {
+                if (idx < k * k) G[idx] = s;
+                else gam[idx - k * k] = s;
+            }
         }
-        for (; b < nblocks; ++b) acc[0] += partials[(int64_t)b * tot + idx];
-        const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-        if (idx < k * k) G[idx] = s;
-        else gam[idx - k * k] = s;
+    } else {
+        for (int idx = tid; idx < tot; idx += kNT) {
+            // eight independent running sums keep eight loads in flight per thread
+            double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int b = 0;
+            for (; b + 8 <= nblocks; b += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc[u] += partials[(int64_t)(b + u) * tot + idx];
+            }
+            for (; b < nblocks; ++b) acc[0] += partials[(int64_t)b * tot + idx];
+            const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+            if (idx < k * k) G[idx] = s;
+            else gam[idx - k * k] = s;
+        }
     }
     __syncthreads();
     for (int w = tid; w < k * k; w += kNT) {
