@@ -158,10 +158,10 @@ def _perturb(cams, X, rng):
     return est, Xe
 
 
-def _finish(name, seed, rng, cams, X, cam, lm, lam, info, shuffle=False) -> Problem:
+def _finish(name, seed, rng, cams, X, cam, lm, lam, info, shuffle=False, noise_px=NOISE_PX) -> Problem:
     """Observe with noise at the true state, linearise at a perturbed state."""
     u_true, _, _, _ = project(cams, X, cam, lm)
-    u_obs = u_true + rng.normal(0.0, NOISE_PX, u_true.shape)
+    u_obs = u_true + rng.normal(0.0, noise_px, u_true.shape)
     est, Xe = _perturb(cams, X, rng)
     u, J_p, J_l, _ = project(est, Xe, cam, lm)
     r = u - u_obs
@@ -191,11 +191,12 @@ def _topc(keys: np.ndarray, c: np.ndarray) -> np.ndarray:
 
 
 def ring_problem(n_cams=50, n_lms=5000, c_lo=2, c_hi=8, radius=20.0, half=5.0, seed=0,
-                 lam=LAMBDA_DEFAULT, name="ring", shuffle=False) -> Problem:
+                 lam=LAMBDA_DEFAULT, name="ring", shuffle=False, noise_px=NOISE_PX) -> Problem:
     """Cameras on a ring in z=0 facing the origin, landmarks uniform in a cube.
 
     Every landmark is seen by c ~ U{c_lo..c_hi} cameras, the ones nearest to it in
     azimuth.  radius > sqrt(3)*half keeps every landmark in front of every camera.
+    noise_px = 0 gives exact observations of the true state (same random stream).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     th = 2.0 * np.pi * np.arange(n_cams) / n_cams
@@ -207,7 +208,7 @@ def ring_problem(n_cams=50, n_lms=5000, c_lo=2, c_hi=8, radius=20.0, half=5.0, s
     phi = np.arctan2(X[:, 1], X[:, 0])
     lm = np.repeat(np.arange(n_lms), c)
     cam = _ring_nearest(phi, th, c, c_hi)
-    return _finish(name, seed, rng, cams, X, cam, lm, lam, {"geometry": 0.0}, shuffle)
+    return _finish(name, seed, rng, cams, X, cam, lm, lam, {"geometry": 0.0}, shuffle, noise_px)
 
 
 def _ring_nearest(phi: np.ndarray, th: np.ndarray, c: np.ndarray, c_hi: int, full: bool = False) -> np.ndarray:
@@ -424,6 +425,13 @@ def schur_block_density(p: Problem) -> float:
 # outer Levenberg-Marquardt loop support (Sec. 4.1): moving the state by a solved
 # step and linearising again.  No solver arithmetic lives here; the step comes from
 # whichever solver the caller runs.
+
+
+def camera_array(cams: Dict[str, np.ndarray]) -> np.ndarray:
+    """The cameras as rows of 15 numbers: R row-major (9), t (3), f, k1, k2."""
+    n = cams["R"].shape[0]
+    return np.ascontiguousarray(np.concatenate([cams["R"].reshape(n, 9), cams["t"], cams["f"][:, None],
+                                                cams["k1"][:, None], cams["k2"][:, None]], axis=1))
 
 
 def cost(p: Problem) -> float:
