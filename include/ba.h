@@ -308,6 +308,95 @@ ba_status ba_batch_mcg_solve(ba_batch *batch, int32_t N, double tau, double *x, 
  * when the system was built without it. */
 ba_status ba_explicit_schur_info(const ba_system *sys, int64_t *nnz_blocks, int64_t *bytes, double *assembly_ms);
 
+/* New values for the same observations: the LM loop's relinearisation at a moved
+ * state, or its new damping lambda (Sec. 4.1), on a built system.  J_p, J_l, r:
+ * device arrays as in ba_problem_desc, in the observation order of the build.  The
+ * layout (tiles, chunks, partitions, explicit-S pattern) is kept; every value the
+ * build forms is recomputed (eq. (8)-(15), D(S) and its factor, the FP32/BF16
+ * copies the system holds, the explicit S).  A low-rank preconditioner term set
+ * before stays as set.  Errors: INVALID_ARG (batch systems, lambda < 0),
+ * NONFINITE (nothing changed), NOT_SPD (the values are undefined until a
+ * successful update). */
+ba_status ba_update_system(ba_system *sys, const double *J_p, const double *J_l, const double *r, double lambda);
+
+/* ------------------------------------------------------------------ LM outer loop
+ * The Levenberg-Marquardt loop of Sec. 4.1 around the solvers above, for the
+ * nine-parameter camera (Sec. 3.1, d_p = 9).  Camera c is 15 doubles: R
+ * (row-major 3x3), t (3), f, k1, k2; landmark l is X_l (3).  Observation o of
+ * landmark obs_lm[o] in camera obs_cam[o] has the residual
+ *   r_o = f s p - u_obs[o],  P = R X + t,  p = P_xy / P_z,  s = 1 + k1 |p|^2 + k2 |p|^4,
+ * and F = sum_o |r_o|^2 (eq. (1)).  A step (dx_p, dx_l) moves camera c by a left
+ * rigid motion, R <- exp([w]x) R, t <- exp([w]x) t + dt with (w, dt) its first 6
+ * entries, adds the last 3 to (f, k1, k2), and adds dx_l to the landmarks. */
+typedef struct {
+    int32_t n_cams;
+    int32_t n_lms;
+    int64_t n_obs;
+    const int32_t *obs_cam;  /* device [m] */
+    const int32_t *obs_lm;   /* device [m]; each (camera, landmark) pair at most once */
+    const double *u_obs;     /* device [m][2]: observed pixel positions */
+} ba_scene_desc;
+
+typedef struct {
+    int32_t max_iter;        /* LM iterations (25) */
+    int32_t solver;          /* 0: PCG (Alg. 1); 1: MCG (Alg. 2) */
+    int32_t n_groups;        /* MCG: N */
+    int32_t reserved0;
+    double tau;              /* MCG: tau */
+    double lambda0;          /* first damping (1e-4) */
+    double ftol;             /* stop after an iteration with |F - F_new| / F < ftol (1e-6) */
+    double lambda_factor;    /* lambda / factor after an accepted step, x factor after a rejected one (10) */
+    ba_solve_opts solve;     /* the linear solves (ba_default_solve_opts) */
+    ba_build_opts build;     /* the reduced camera system (zeros: defaults) */
+} ba_lm_opts;
+
+typedef struct {
+    int32_t iterations;      /* LM iterations done */
+    int32_t accepted;        /* of which moved the state */
+    int32_t status;          /* BA_OK, or the error that ended the loop */
+    int32_t solver_iterations; /* linear-solver iterations, all LM iterations together */
+    double cost0;            /* F at the start */
+    double cost;             /* F at the returned state */
+    double t_total_ms;       /* wall time of the call */
+    double t_solve_ms;       /* of which in the linear solves */
+    double t_linearize_ms;   /* of which in residuals, Jacobians and system values */
+    int32_t trace_cap;       /* entries of the HOST trace arrays below (nullable) */
+    int32_t reserved;
+    double *trace_lambda;    /* lambda of iteration i's solve */
+    double *trace_cost;      /* F at the moved state of iteration i */
+    int32_t *trace_accepted; /* 1 when iteration i moved the state */
+    int32_t *trace_solver_iterations;
+    double *trace_solve_ms;
+} ba_lm_stats;
+
+/* Fills opts with the defaults above (PCG, N = 1, tau = 3.3). */
+void ba_default_lm_opts(ba_lm_opts *opts);
+
+/* Residuals r (device [m][2], nullable) and, when J_p is not NULL, the Jacobian
+ * blocks J_p (device [m][2][9]) and J_l (device [m][2][3]) in the step coordinates
+ * above, at the state (cams: device [n_cams][15], X: device [n_lms][3]); F to
+ * *cost (host, nullable).  Runs on `stream` and waits for it. */
+ba_status ba_project(const ba_scene_desc *scene, const double *cams, const double *X, double *J_p, double *J_l,
+                     double *r, double *cost, void *stream);
+
+/* The state moved by the step: cams_out, X_out (device, the shapes of cams, X) from
+ * dxp (device [9 n_cams]) and dxl (device [3 n_lms]).  Asynchronous on `stream`. */
+ba_status ba_apply_step(int32_t n_cams, int32_t n_lms, const double *cams, const double *X, const double *dxp,
+                        const double *dxl, double *cams_out, double *X_out, void *stream);
+
+/* The LM loop of Sec. 4.1: lambda starts at lambda0; each iteration solves the
+ * damped normal equation through the reduced camera system (Alg. 1 or 2 with
+ * opts->solve), back-substitutes the landmarks, and evaluates F at the moved state;
+ * the move is kept when F decreases (lambda / factor, the system is relinearised)
+ * and dropped otherwise (lambda x factor, same linearisation).  It stops after
+ * max_iter iterations, after an iteration with |F - F_new| / F < ftol, or at F = 0.
+ * cams, X: device, the start state on entry and the final state on return.  A
+ * linear solve that ends at its iteration limit still gives a step; any other
+ * solver error ends the loop with that status (the state is the last accepted one).
+ * stats: host, nullable. */
+ba_status ba_lm_solve(const ba_scene_desc *scene, double *cams, double *X, const ba_lm_opts *opts, void *stream,
+                      ba_lm_stats *stats);
+
 const char *ba_status_string(int32_t status);
 const char *ba_last_error(void);
 

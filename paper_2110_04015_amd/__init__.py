@@ -18,7 +18,7 @@ from ._lib import (BA_ERR_BREAKDOWN, BA_ERR_HIP, BA_ERR_INVALID_ARG, BA_ERR_NOME
                    BA_ERR_NOT_SPD, BA_ERR_UNSUPPORTED, BA_ERR_WORKSPACE, BA_MAXITER, BA_OK, PREC)
 
 __all__ = ["System", "Batch", "BatchStats", "BAError", "Stats", "pinv_sym", "partition", "PREC", "lib",
-           "mlp_forward", "mlp_loss_grad", "adam_step", "MLP_PARAMS"]
+           "mlp_forward", "mlp_loss_grad", "adam_step", "MLP_PARAMS", "Scene", "LMStats"]
 
 MLP_PARAMS = 15432
 
@@ -239,6 +239,14 @@ class System:
                "ba_get_precond_blocks")
         return D
 
+    def update(self, J_p, J_l, r, lam):
+        """New values for the same observations (ba_update_system): relinearisation or a new lambda."""
+        torch = _torch()
+        m = self.n_obs
+        _check(lib().ba_update_system(self.h, _dev_ptr(J_p, torch.float64, m * 18, "J_p"),
+                                      _dev_ptr(J_l, torch.float64, m * 6, "J_l"),
+                                      _dev_ptr(r, torch.float64, m * 2, "r"), float(lam)), "ba_update_system")
+
     def back_substitute(self, dxp):
         torch = _torch()
         out = self._new(self.n_lms * 3)
@@ -454,3 +462,115 @@ class Batch:
                             s.rel_res_recursive, s.rel_res_true, s.done_ms) for s in st]
         return x, stats, ms.value, rc
 
+
+
+# ------------------------------------------------------------------ LM outer loop
+
+@dataclass
+class LMStats:
+    iterations: int
+    accepted: int
+    status: int
+    solver_iterations: int
+    cost0: float
+    cost: float
+    t_total_ms: float
+    t_solve_ms: float
+    t_linearize_ms: float
+    trace_lambda: np.ndarray
+    trace_cost: np.ndarray
+    trace_accepted: np.ndarray
+    trace_solver_iterations: np.ndarray
+    trace_solve_ms: np.ndarray
+
+
+class Scene:
+    """Observations of a bundle-adjustment scene on one device (ba_scene_desc): the
+    nine-parameter camera model, its residuals and Jacobians, and the LM loop of
+    Sec. 4.1.  Cameras are [n_cams, 15] (R row-major, t, f, k1, k2), landmarks [n_lms, 3]."""
+
+    def __init__(self, n_cams, n_lms, obs_cam, obs_lm, u_obs, stream=None):
+        torch = _torch()
+        self.n_cams, self.n_lms, self.n_obs = int(n_cams), int(n_lms), int(obs_cam.numel())
+        m = self.n_obs
+        self._keep = (obs_cam, obs_lm, u_obs)
+        d = _lib.SceneDesc()
+        d.n_cams, d.n_lms, d.n_obs = self.n_cams, self.n_lms, m
+        d.obs_cam = _dev_ptr(obs_cam, torch.int32, m, "obs_cam")
+        d.obs_lm = _dev_ptr(obs_lm, torch.int32, m, "obs_lm")
+        d.u_obs = _dev_ptr(u_obs, torch.float64, m * 2, "u_obs")
+        self.desc = d
+        self.device = obs_cam.device
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+
+    @classmethod
+    def from_problem(cls, p, device="cuda", **kw):
+        """The scene of a synthetic problem that carries its state (cams, points, u_obs);
+        returns (scene, cams [n_cams, 15], X [n_lms, 3]) on the device."""
+        torch = _torch()
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        R = np.asarray(p.cams["R"]).reshape(p.n_cams, 9)
+        cams = np.concatenate([R, p.cams["t"], p.cams["f"][:, None], p.cams["k1"][:, None], p.cams["k2"][:, None]], 1)
+        sc = cls(p.n_cams, p.n_lms, t(p.obs_cam, torch.int32), t(p.obs_lm, torch.int32), t(p.u_obs, torch.float64), **kw)
+        return sc, t(cams, torch.float64), t(p.points, torch.float64)
+
+    def _state(self, cams, X):
+        torch = _torch()
+        return (_dev_ptr(cams, torch.float64, self.n_cams * 15, "cams"),
+                _dev_ptr(X, torch.float64, self.n_lms * 3, "X"))
+
+    def project(self, cams, X, jacobians=True):
+        """(r [m, 2], J_p [m, 2, 9], J_l [m, 2, 3], F) at the state; J_* None without jacobians."""
+        torch = _torch()
+        m = self.n_obs
+        r = torch.empty(m, 2, dtype=torch.float64, device=self.device)
+        Jp = torch.empty(m, 2, 9, dtype=torch.float64, device=self.device) if jacobians else None
+        Jl = torch.empty(m, 2, 3, dtype=torch.float64, device=self.device) if jacobians else None
+        F = C.c_double()
+        pc, px = self._state(cams, X)
+        _check(lib().ba_project(C.byref(self.desc), pc, px, C.c_void_p(Jp.data_ptr()) if jacobians else None,
+                                C.c_void_p(Jl.data_ptr()) if jacobians else None, C.c_void_p(r.data_ptr()),
+                                C.byref(F), _stream_handle(self._stream)), "ba_project")
+        return r, Jp, Jl, F.value
+
+    def apply_step(self, cams, X, dxp, dxl):
+        """The state moved by (dxp, dxl) (ba_apply_step)."""
+        torch = _torch()
+        co, Xo = torch.empty_like(cams), torch.empty_like(X)
+        pc, px = self._state(cams, X)
+        _check(lib().ba_apply_step(self.n_cams, self.n_lms, pc, px,
+                                   _dev_ptr(dxp, torch.float64, 9 * self.n_cams, "dxp"),
+                                   _dev_ptr(dxl, torch.float64, 3 * self.n_lms, "dxl"),
+                                   C.c_void_p(co.data_ptr()), C.c_void_p(Xo.data_ptr()),
+                                   _stream_handle(self._stream)), "ba_apply_step")
+        return co, Xo
+
+    def lm(self, cams, X, solver="pcg", N=1, tau=3.3, max_iter=25, lambda0=1e-4, ftol=1e-6, lambda_factor=10.0,
+           eps=1e-6, solver_max_iter=1000, precision="fp64", max_slots=0, max_tiles=0, explicit_schur=False):
+        """ba_lm_solve on copies of (cams, X); returns (cams, X, LMStats)."""
+        cams, X = cams.clone(), X.clone()
+        o = _lib.LMOpts()
+        lib().ba_default_lm_opts(C.byref(o))
+        o.max_iter, o.solver, o.n_groups, o.tau = int(max_iter), {"pcg": 0, "mcg": 1}[solver], int(N), float(tau)
+        o.lambda0, o.ftol, o.lambda_factor = float(lambda0), float(ftol), float(lambda_factor)
+        o.solve = _opts(eps, solver_max_iter, precision)
+        o.build.max_slots, o.build.max_tiles = int(max_slots), int(max_tiles)
+        o.build.store_fp32 = int(precision == "fp32")
+        o.build.store_bf16 = int(precision == "bf16")
+        o.build.explicit_schur = int(explicit_schur)
+        cap = max(int(max_iter), 1)
+        tl, tc, ts = np.full(cap, np.nan), np.full(cap, np.nan), np.full(cap, np.nan)
+        ta, ti = np.zeros(cap, np.int32), np.zeros(cap, np.int32)
+        st = _lib.LMStats()
+        st.trace_cap = cap
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+        st.trace_lambda, st.trace_cost, st.trace_solve_ms = dp(tl), dp(tc), dp(ts)
+        st.trace_accepted, st.trace_solver_iterations = ip(ta), ip(ti)
+        pc, px = self._state(cams, X)
+        _check(lib().ba_lm_solve(C.byref(self.desc), pc, px, C.byref(o), _stream_handle(self._stream), C.byref(st)),
+               "ba_lm_solve")
+        n = st.iterations
+        return cams, X, LMStats(st.iterations, st.accepted, st.status, st.solver_iterations, st.cost0, st.cost,
+                                st.t_total_ms, st.t_solve_ms, st.t_linearize_ms, tl[:n].copy(), tc[:n].copy(),
+                                ta[:n].copy(), ti[:n].copy(), ts[:n].copy())

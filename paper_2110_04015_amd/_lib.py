@@ -45,6 +45,26 @@ class BatchStats(C.Structure):
                 ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double), ("done_ms", C.c_double)]
 
 
+class SceneDesc(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("n_lms", C.c_int32), ("n_obs", C.c_int64), ("obs_cam", C.c_void_p),
+                ("obs_lm", C.c_void_p), ("u_obs", C.c_void_p)]
+
+
+class LMOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("solver", C.c_int32), ("n_groups", C.c_int32), ("reserved0", C.c_int32),
+                ("tau", C.c_double), ("lambda0", C.c_double), ("ftol", C.c_double), ("lambda_factor", C.c_double),
+                ("solve", SolveOpts), ("build", BuildOpts)]
+
+
+class LMStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("accepted", C.c_int32), ("status", C.c_int32),
+                ("solver_iterations", C.c_int32), ("cost0", C.c_double), ("cost", C.c_double),
+                ("t_total_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_linearize_ms", C.c_double),
+                ("trace_cap", C.c_int32), ("reserved", C.c_int32), ("trace_lambda", C.POINTER(C.c_double)),
+                ("trace_cost", C.POINTER(C.c_double)), ("trace_accepted", C.POINTER(C.c_int32)),
+                ("trace_solver_iterations", C.POINTER(C.c_int32)), ("trace_solve_ms", C.POINTER(C.c_double))]
+
+
 # (name, restype, argtypes) for every entry point of include/ba.h
 SIGNATURES = [
     ("ba_default_solve_opts", None, [C.POINTER(SolveOpts)]),
@@ -83,6 +103,14 @@ SIGNATURES = [
     ("ba_batch_system", C.c_void_p, [C.c_void_p]),
     ("ba_batch_mcg_solve", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
                                      C.POINTER(BatchStats), C.POINTER(C.c_double)]),
+    ("ba_update_system", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
+    ("ba_default_lm_opts", None, [C.POINTER(LMOpts)]),
+    ("ba_project", C.c_int, [C.POINTER(SceneDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.POINTER(C.c_double), C.c_void_p]),
+    ("ba_apply_step", C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_void_p]),
+    ("ba_lm_solve", C.c_int, [C.POINTER(SceneDesc), C.c_void_p, C.c_void_p, C.POINTER(LMOpts), C.c_void_p,
+                              C.POINTER(LMStats)]),
     ("ba_explicit_schur_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_double)]),
     ("ba_status_string", C.c_char_p, [C.c_int32]),

@@ -83,7 +83,14 @@ void free_all(ba_system *s) {
     dfree(s->J64);
     dfree(s->J32);
     dfree(s->J16);
-    dfree(s->bf16_scale);
+    dfree(s->slot_obs);
+    dfree(s->cam_obs_ptr);
+    dfree(s->cam_obs);
+    dfree(s->lmk_store);
+    dfree(s->obs_lm);
+    dfree(s->h0);
+    dfree(s->bsr_pair_ptr);
+    dfree(s->bsr_pairs);
     dfree(s->meta);
     dfree(s->tile_lmk_base);
     dfree(s->chunk_tile);
@@ -392,6 +399,10 @@ void fill_default_opts(ba_solve_opts *o) {
 
 }  // namespace
 
+namespace ba {
+ba_status set_error(ba_status st, const std::string &msg) { return fail(st, msg); }
+}  // namespace ba
+
 extern "C" {
 
 void ba_default_solve_opts(ba_solve_opts *opts) {
@@ -428,6 +439,52 @@ void ba_free_system(ba_system *sys) {
     (void)hipStreamSynchronize(sys->stream);
     free_all(sys);
     delete sys;
+}
+
+// Values of a system whose layout is set: checks J_p, J_l, r (device, observation
+// order of the build) for NaN/Inf, packs the Jacobian stream, and forms V_lambda^-1,
+// b_l, U_lambda's damping, D(S), its factor and b~ (eq. (9)-(15)) for s->lambda; the
+// explicit S too when the system keeps one.  Waits for the stream.
+static ba_status fill_values(ba_system *s, const double *J_p, const double *J_l, const double *r) {
+    hipStream_t q = s->stream;
+    const int64_t m = s->m;
+    const int64_t nslots = s->plan.n_tiles * kTile;
+    HIPCHK(hipMemsetAsync(s->status, 0, sizeof(int32_t), q));
+    launch_check_finite(J_p, m * 18, s->status, q);
+    launch_check_finite(J_l, m * 6, s->status, q);
+    launch_check_finite(r, m * 2, s->status, q);
+    int32_t hst = 0;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q));
+    HIPCHK(hipStreamSynchronize(q));
+    if (hst & kStatusNonfinite) return fail(BA_ERR_NONFINITE, "NaN or Inf in J_p, J_l or r");
+    launch_pack(s->slot_obs, nslots, J_p, J_l, s->J64, s->J32, s->J16, q);
+    launch_landmarks(s->nl, s->lmk_first_slot, s->lmk_count, s->slot_obs, J_l, r, s->lambda, s->vinv, s->bl, s->h0,
+                     s->status, q);
+    launch_cameras(s->np, s->cam_obs_ptr, s->cam_obs, s->obs_lm, s->lmk_store, J_p, J_l, r, s->vinv, s->h0,
+                   s->lambda, s->dU, s->Dblk, s->Dchol, s->bt, s->status, q);
+    if (s->bsr_val) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        if (e0) (void)hipEventRecord(e0, q);
+        launch_bsr_assemble(s->np, s->bsr_pair_ptr, s->bsr_pairs, s->J64, s->vinv, s->Dblk, s->bsr_ptr, s->bsr_col,
+                            s->bsr_max_row, s->bsr_val, q);
+        if (e1) (void)hipEventRecord(e1, q);
+        if (hipStreamSynchronize(q) == hipSuccess && e0 && e1) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) s->bsr_build_ms = ms;
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q));
+    HIPCHK(hipStreamSynchronize(q));
+    if (hst & kStatusNotSpdLandmark) return fail(BA_ERR_NOT_SPD, "a landmark block V_lambda is not positive definite");
+    if (hst & kStatusNotSpdCamera)
+        return fail(BA_ERR_NOT_SPD, "a block of D(S) is not positive definite (unobserved camera?)");
+    return BA_OK;
 }
 
 static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream,
@@ -479,120 +536,63 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
     const int64_t nslots = P.n_tiles * kTile;
 
     if ((st = dalloc(&s->status, 1)) != BA_OK) return bail(st);
-    if (hipMemsetAsync(s->status, 0, sizeof(int32_t), q) != hipSuccess) return bail(fail(BA_ERR_HIP, "memset"));
-    launch_check_finite(d->J_p, m * 18, s->status, q);
-    launch_check_finite(d->J_l, m * 6, s->status, q);
-    launch_check_finite(d->r, m * 2, s->status, q);
-    int32_t hst = 0;
-    if (hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
-        hipStreamSynchronize(q) != hipSuccess)
-        return bail(fail(BA_ERR_HIP, "status read failed"));
-    if (hst & kStatusNonfinite) return bail(fail(BA_ERR_NONFINITE, "NaN or Inf in J_p, J_l or r"));
-
-    // device copies of the plan
-    int64_t *d_slot_obs = nullptr, *d_cam_ptr = nullptr, *d_cam_obs = nullptr;
-    int32_t *d_lmk_store = nullptr;
-    double *d_h0 = nullptr;
-    auto bail2 = [&](ba_status st2) {
-        (void)hipStreamSynchronize(q);
-        dfree(d_slot_obs);
-        dfree(d_cam_ptr);
-        dfree(d_cam_obs);
-        dfree(d_lmk_store);
-        dfree(d_h0);
-        return bail(st2);
-    };
-    if ((st = upload(&d_slot_obs, P.slot_obs, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&d_cam_ptr, P.cam_obs_ptr, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&d_cam_obs, P.cam_obs, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&d_lmk_store, P.lmk_store, q)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&d_h0, (size_t)s->nl * 3)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->meta, P.meta, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->tile_lmk_base, P.tile_lmk_base, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->chunk_tile, P.chunk_tile, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->chunk_part, P.chunk_part, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->part_cam, P.part_cam, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->cam_part_ptr, P.cam_part_ptr, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->cam_part_idx, P.cam_part_idx, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->part_dst, P.part_dst, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->lmk_order, P.lmk_order, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->lmk_first_slot, P.lmk_first_slot, q)) != BA_OK) return bail2(st);
-    if ((st = upload(&s->lmk_count, P.lmk_count, q)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&s->partial, (size_t)std::max<int64_t>(P.n_part, 1) * 9)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&s->J64, (size_t)nslots * 24)) != BA_OK) return bail2(st);
-    if (opts && opts->store_fp32 && (st = dalloc(&s->J32, (size_t)nslots * 24)) != BA_OK) return bail2(st);
-    if (opts && opts->store_bf16 && (st = dalloc(&s->J16, (size_t)nslots * 24)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&s->vinv, (size_t)s->nl * 6)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&s->bl, (size_t)s->nl * 3)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&s->dU, (size_t)s->np * 9)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&s->Dblk, (size_t)s->np * 81)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&s->Dchol, (size_t)s->np * 45)) != BA_OK) return bail2(st);
-    if ((st = dalloc(&s->bt, (size_t)s->np * 9)) != BA_OK) return bail2(st);
-
-    launch_pack(d_slot_obs, nslots, d->J_p, d->J_l, s->J64, s->J32, s->J16, q);
-    launch_landmarks(s->nl, s->lmk_first_slot, s->lmk_count, d_slot_obs, d->J_l, d->r, s->lambda, s->vinv, s->bl,
-                     d_h0, s->status, q);
-    launch_cameras(s->np, d_cam_ptr, d_cam_obs, d->obs_lm, d_lmk_store, d->J_p, d->J_l, d->r, s->vinv, d_h0,
-                   s->lambda, s->dU, s->Dblk, s->Dchol, s->bt, s->status, q);
+    // layout on the device (kept for ba_update_system)
+    if ((st = upload(&s->slot_obs, P.slot_obs, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->cam_obs_ptr, P.cam_obs_ptr, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->cam_obs, P.cam_obs, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->lmk_store, P.lmk_store, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->obs_lm, hlm, q)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->h0, (size_t)s->nl * 3)) != BA_OK) return bail(st);
+    if ((st = upload(&s->meta, P.meta, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->tile_lmk_base, P.tile_lmk_base, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->chunk_tile, P.chunk_tile, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->chunk_part, P.chunk_part, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->part_cam, P.part_cam, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->cam_part_ptr, P.cam_part_ptr, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->cam_part_idx, P.cam_part_idx, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->part_dst, P.part_dst, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->lmk_order, P.lmk_order, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->lmk_first_slot, P.lmk_first_slot, q)) != BA_OK) return bail(st);
+    if ((st = upload(&s->lmk_count, P.lmk_count, q)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->partial, (size_t)std::max<int64_t>(P.n_part, 1) * 9)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->J64, (size_t)nslots * 24)) != BA_OK) return bail(st);
+    if (opts && opts->store_fp32 && (st = dalloc(&s->J32, (size_t)nslots * 24)) != BA_OK) return bail(st);
+    if (opts && opts->store_bf16 && (st = dalloc(&s->J16, (size_t)nslots * 24)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->vinv, (size_t)s->nl * 6)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->bl, (size_t)s->nl * 3)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->dU, (size_t)s->np * 9)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->Dblk, (size_t)s->np * 81)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->Dchol, (size_t)s->np * 45)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->bt, (size_t)s->np * 9)) != BA_OK) return bail(st);
     if (opts && opts->explicit_schur) {
-        // explicit S in block-sparse rows, assembled from the same blocks (Sec. 3.2, 4.1)
-        if (cam_seg) return bail2(fail(BA_ERR_UNSUPPORTED, "batches use the implicit S products"));
+        // explicit S in block-sparse rows, assembled from the same blocks (Sec. 3.2, 4.1): the
+        // pattern and the contribution pairs depend on the observations only
+        if (cam_seg) return bail(fail(BA_ERR_UNSUPPORTED, "batches use the implicit S products"));
         std::vector<int32_t> rp, cl;
         int max_row = 0;
         build_bsr_pattern(P, hlm.data(), rp, cl, max_row);
         int dev = 0, lds_max = 65536;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-            return bail2(fail(BA_ERR_HIP, "device attribute query failed"));
+            return bail(fail(BA_ERR_HIP, "device attribute query failed"));
         if ((size_t)max_row * 81 * sizeof(double) > (size_t)lds_max)
-            return bail2(fail(BA_ERR_UNSUPPORTED, "explicit S: a camera is covisible with " + std::to_string(max_row) +
-                                                      " cameras, more than one work-group's LDS holds"));
-        if (nslots > (int64_t)INT32_MAX) return bail2(fail(BA_ERR_UNSUPPORTED, "explicit S: too many observations"));
+            return bail(fail(BA_ERR_UNSUPPORTED, "explicit S: a camera is covisible with " + std::to_string(max_row) +
+                                                     " cameras, more than one work-group's LDS holds"));
+        if (nslots > (int64_t)INT32_MAX) return bail(fail(BA_ERR_UNSUPPORTED, "explicit S: too many observations"));
         std::vector<int64_t> pptr;
         std::vector<int32_t> prs;
         build_bsr_pairs(P, hlm.data(), rp, cl, pptr, prs);
-        int64_t *d_pptr = nullptr;
-        int32_t *d_pairs = nullptr;
-        auto bail3 = [&](ba_status st3) {
-            (void)hipStreamSynchronize(q);
-            dfree(d_pptr);
-            dfree(d_pairs);
-            return bail2(st3);
-        };
-        if ((st = upload(&s->bsr_ptr, rp, q)) != BA_OK) return bail3(st);
-        if ((st = upload(&s->bsr_col, cl, q)) != BA_OK) return bail3(st);
-        if ((st = upload(&d_pptr, pptr, q)) != BA_OK) return bail3(st);
-        if ((st = upload(&d_pairs, prs, q)) != BA_OK) return bail3(st);
+        if ((st = upload(&s->bsr_ptr, rp, q)) != BA_OK) return bail(st);
+        if ((st = upload(&s->bsr_col, cl, q)) != BA_OK) return bail(st);
+        if ((st = upload(&s->bsr_pair_ptr, pptr, q)) != BA_OK) return bail(st);
+        if ((st = upload(&s->bsr_pairs, prs, q)) != BA_OK) return bail(st);
         s->bsr_nnzb = (int64_t)cl.size();
-        if ((st = dalloc(&s->bsr_val, (size_t)s->bsr_nnzb * 81)) != BA_OK) return bail3(st);
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
-        if (e0) (void)hipEventRecord(e0, q);
-        launch_bsr_assemble(s->np, d_pptr, d_pairs, s->J64, s->vinv, s->Dblk, s->bsr_ptr, s->bsr_col, max_row,
-                            s->bsr_val, q);
-        if (e1) (void)hipEventRecord(e1, q);
-        if (hipStreamSynchronize(q) != hipSuccess) return bail3(fail(BA_ERR_HIP, "explicit S assembly failed"));
-        dfree(d_pptr);
-        dfree(d_pairs);
-        float ms = 0.f;
-        if (e0 && e1 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) s->bsr_build_ms = ms;
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
+        s->bsr_max_row = max_row;
+        if ((st = dalloc(&s->bsr_val, (size_t)s->bsr_nnzb * 81)) != BA_OK) return bail(st);
+        if (hipStreamSynchronize(q) != hipSuccess)   // the host vectors above go out of scope
+            return bail(fail(BA_ERR_HIP, "explicit S: pattern upload failed"));
     }
-    if (hipGetLastError() != hipSuccess) return bail2(fail(BA_ERR_HIP, "build kernel launch failed"));
-    if (hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q) != hipSuccess ||
-        hipStreamSynchronize(q) != hipSuccess)
-        return bail2(fail(BA_ERR_HIP, "build kernels failed"));
-    dfree(d_slot_obs);
-    dfree(d_cam_ptr);
-    dfree(d_cam_obs);
-    dfree(d_lmk_store);
-    dfree(d_h0);
-    if (hst & kStatusNotSpdLandmark)
-        return bail(fail(BA_ERR_NOT_SPD, "a landmark block V_lambda is not positive definite"));
-    if (hst & kStatusNotSpdCamera)
-        return bail(fail(BA_ERR_NOT_SPD, "a block of D(S) is not positive definite (unobserved camera?)"));
+    if ((st = fill_values(s, d->J_p, d->J_l, d->r)) != BA_OK) return bail(st);
     if ((st = ensure_pinned(s)) != BA_OK) return bail(st);
     *out = s;
     return BA_OK;
@@ -600,6 +600,18 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
 
 ba_status ba_build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream, ba_system **out) {
     return build_system(d, opts, stream, nullptr, out);
+}
+
+ba_status ba_update_system(ba_system *s, const double *J_p, const double *J_l, const double *r, double lambda) {
+    if (!s || !J_p || !J_l || !r) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (s->seg_cam) return fail(BA_ERR_INVALID_ARG, "batch systems are not updated in place");
+    if (!std::isfinite(lambda)) return fail(BA_ERR_NONFINITE, "lambda is not finite");
+    if (lambda < 0.0) return fail(BA_ERR_INVALID_ARG, "lambda must be >= 0");
+    const double prev = s->lambda;
+    s->lambda = lambda;
+    const ba_status st = fill_values(s, J_p, J_l, r);
+    if (st == BA_ERR_NONFINITE) s->lambda = prev;   // rejected before any value changed
+    return st;
 }
 
 ba_status ba_profile_enable(ba_system *s, int32_t on) {

@@ -118,6 +118,9 @@ ba_status build_multi_plan(const HostPlan &plan, int N, int max_out, HostMultiPl
 void partition_groups(int np, int N, int32_t *group);
 void covisibility_degree(const HostPlan &plan, std::vector<int32_t> &deg);
 
+// Records msg as the text of ba_last_error() and returns st.
+ba_status set_error(ba_status st, const std::string &msg);
+
 }  // namespace ba
 
 // The system handle.
@@ -131,7 +134,6 @@ struct ba_system {
     double *J64 = nullptr;          // n_tiles * 64 * 24
     float *J32 = nullptr;           // optional FP32 copy
     uint16_t *J16 = nullptr;        // optional BF16 copy (scaled)
-    float *bf16_scale = nullptr;    // [np][9] column scales of the BF16 copy
     uint32_t *meta = nullptr;
     int32_t *tile_lmk_base = nullptr;
     int32_t *chunk_tile = nullptr, *chunk_part = nullptr, *part_cam = nullptr;
@@ -147,6 +149,16 @@ struct ba_system {
     int64_t *lmk_first_slot = nullptr;
     int32_t *lmk_count = nullptr;
     int32_t *status = nullptr;      // device status word
+    // layout arrays of the build, kept for new values of the same observations
+    int64_t *slot_obs = nullptr;    // tile slot -> observation (or -1)
+    int64_t *cam_obs_ptr = nullptr; // camera -> range of cam_obs
+    int64_t *cam_obs = nullptr;     // observations camera by camera
+    int32_t *lmk_store = nullptr;   // observation -> storage index of its landmark
+    int32_t *obs_lm = nullptr;      // copy of the observations' landmarks
+    double *h0 = nullptr;           // nl * 3: V^-1 b_l (storage order)
+    int64_t *bsr_pair_ptr = nullptr;// explicit S: contribution pairs per block row
+    int32_t *bsr_pairs = nullptr;
+    int bsr_max_row = 0;
     // solver scratch (allocated on demand)
     double *vec = nullptr;          // work vectors
     size_t vec_cap = 0;

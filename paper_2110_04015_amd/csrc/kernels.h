@@ -251,4 +251,12 @@ void launch_bqcopy_advance(const BatchLaunch &L, hipStream_t s);
 // per-problem |bt + Sx|^2 and |bt|^2 (out [B][2]) and, when btp is given, btp = bt + Sx
 void launch_bresidual(const BatchLaunch &L, const double *bt, const double *Sx, double *btp, double *out,
                       hipStream_t s);
+// LM outer loop (k_lm.hip): residuals, Jacobian blocks and F of a state; the moved state
+int project_blocks(int64_t m);   // doubles of `partials` launch_project needs
+void launch_project(int64_t m, const int32_t *obs_cam, const int32_t *obs_lm, const double *cams, const double *X,
+                    const double *u_obs, double *Jp, double *Jl, double *r, double *partials, double *cost,
+                    hipStream_t s);
+void launch_apply_step(int np, int nl, const double *cams, const double *X, const double *dxp, const double *dxl,
+                       double *cams_out, double *X_out, hipStream_t s);
+
 }  // namespace ba
