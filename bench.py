@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched-serving workload")
+    ap.add_argument("--no-lm", action="store_true", help="skip the LM outer-loop runs")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="K",
                     help="profiling mode: K FP64 S v products and one 1 GiB copy (counter calibration)")
     args = ap.parse_args()
@@ -280,6 +281,27 @@ def main():
         log(f"explicit S: {explicit}")
         ge.close()
 
+    lm = None
+    if not args.no_lm and not args.no_variants:
+        # the LM outer loop of Sec. 4.1 from the generator's perturbed state, PCG against MCG
+        # (the analogue of the paper's global runtime ratio), implicit and explicit S
+        sc, cams0, X0 = ba.Scene.from_problem(p)
+        lm = {}
+        for name, kw in [("pcg", dict(solver="pcg")), ("mcg_N16", dict(solver="mcg", N=16, tau=args.tau)),
+                         ("pcg_explicit", dict(solver="pcg", explicit_schur=True)),
+                         ("mcg_N4_explicit", dict(solver="mcg", N=4, tau=args.tau, explicit_schur=True))]:
+            c1, X1, ls = sc.lm(cams0, X0, **kw)
+            lm[name] = {"iterations": ls.iterations, "accepted": ls.accepted, "status": ls.status,
+                        "cost0": ls.cost0, "cost": ls.cost, "solver_iterations": ls.solver_iterations,
+                        "t_total_ms": round(ls.t_total_ms, 2), "t_solve_ms": round(ls.t_solve_ms, 2),
+                        "t_linearize_ms": round(ls.t_linearize_ms, 2)}
+            log(f"LM {name}: {lm[name]}")
+            del c1, X1
+        for a, b in [("mcg_N16", "pcg"), ("mcg_N4_explicit", "pcg_explicit")]:
+            lm[f"ratio_{a}_vs_{b}"] = {"total": round(lm[a]["t_total_ms"] / lm[b]["t_total_ms"], 4),
+                                       "solve": round(lm[a]["t_solve_ms"] / lm[b]["t_solve_ms"], 4)}
+        del sc, cams0, X0
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -338,6 +360,7 @@ def main():
         "variants": variants,
         "explicit_schur": explicit,
         "batch": batch,
+        "lm": lm,
     }
     print(json.dumps(out), flush=True)
     if batch is None:

@@ -227,8 +227,10 @@ ba_status ensure_precision(ba_system *s, int precision) {
     return BA_OK;
 }
 
-ba_status ensure_multi(ba_system *s, int N) {
-    if (s->multi.N == N && s->multi.partial) return BA_OK;
+// The partition into N subsets and, with `plan`, the layout of the implicit
+// multidirectional product (the explicit S's grouped product needs the partition only).
+ba_status ensure_multi(ba_system *s, int N, bool plan = true) {
+    if (s->multi.N == N && s->multi.group && (!plan || s->multi.partial)) return BA_OK;
     free_multi(s->multi);
     HostMultiPlan mp;
     std::string err;
@@ -246,7 +248,14 @@ ba_status ensure_multi(ba_system *s, int N) {
             c0 = c1;
         }
     }
-    ba_status st = build_multi_plan(s->plan, N, 512, mp, err, grp.data());
+    ba_status st;
+    if (!plan) {
+        if ((st = upload(&s->multi.group, grp, s->stream)) != BA_OK) return st;
+        s->multi.N = N;
+        HIPCHK(hipStreamSynchronize(s->stream));   // grp goes out of scope
+        return BA_OK;
+    }
+    st = build_multi_plan(s->plan, N, 512, mp, err, grp.data());
     if (st != BA_OK) return fail(st, err);
     // LDS of the multidirectional kernel: max_out rows of 9 plus 2 x 64 x 3 values (FP64),
     // up to the device's work-group limit (160 KiB on gfx950: 2,232 rows)
@@ -401,6 +410,14 @@ void fill_default_opts(ba_solve_opts *o) {
 
 namespace ba {
 ba_status set_error(ba_status st, const std::string &msg) { return fail(st, msg); }
+
+ba_status prepare_mcg(ba_system *s, int N, int precision) {
+    ba_status st = ensure_precision(s, precision);
+    if (st != BA_OK || N <= 1) return st;
+    if (N > s->np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, n_cams]");
+    const bool bsr = s->bsr_val && precision == 0 && N <= kMaxBlock;
+    return ensure_multi(s, N, !bsr);
+}
 }  // namespace ba
 
 extern "C" {
@@ -662,8 +679,9 @@ ba_status ba_schur_matmat_grouped(ba_system *s, int32_t N, const double *z, doub
     if (N < 1 || N > s->np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, n_cams]");
     ba_status st = ensure_precision(s, precision);
     if (st != BA_OK) return st;
-    if ((st = ensure_multi(s, N)) != BA_OK) return st;
-    if (s->bsr_val && precision == 0 && N <= kMaxBlock)   // the grouped kernel keeps N x 9 sums in LDS
+    const bool bsr = s->bsr_val && precision == 0 && N <= kMaxBlock;   // the grouped kernel keeps N x 9 sums in LDS
+    if ((st = ensure_multi(s, N, !bsr)) != BA_OK) return st;
+    if (bsr)
         launch_bsr_mm_grouped(s->np, N, s->bsr_ptr, s->bsr_col, s->bsr_val, s->multi.group, z, Y, s->stream);
     else
         launch_schur_multi(multi_args(s, precision), z, Y, s->stream);
@@ -842,7 +860,8 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     const int prec = opts.precision;
     ba_status st = ensure_precision(s, prec);
     if (st != BA_OK) return st;
-    if (N > 1 && (st = ensure_multi(s, N)) != BA_OK) return st;
+    const bool use_bsr_multi = N > 1 && s->bsr_val && prec == 0 && N <= kMaxBlock;
+    if (N > 1 && (st = ensure_multi(s, N, !use_bsr_multi)) != BA_OK) return st;
     const int64_t n = (int64_t)s->np * 9;
     hipStream_t q = s->stream;
     const int64_t cap = opts.max_history_cols > 0 ? opts.max_history_cols : 1 + (int64_t)opts.max_iter * N;
@@ -883,8 +902,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     double *red = s->red;
     const int gs = s->np / N;
     const SchurArgs sa = schur_args(s, prec);
-    const MultiArgs ma = N > 1 ? multi_args(s, prec) : MultiArgs();
-    const bool use_bsr_multi = N > 1 && s->bsr_val && prec == 0 && N <= kMaxBlock;
+    const MultiArgs ma = N > 1 && !use_bsr_multi ? multi_args(s, prec) : MultiArgs();
 
     auto t0 = std::chrono::steady_clock::now();
     if ((st = init_scalars(s, sc)) != BA_OK) return st;

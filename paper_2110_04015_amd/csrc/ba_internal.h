@@ -120,6 +120,9 @@ void covisibility_degree(const HostPlan &plan, std::vector<int32_t> &deg);
 
 // Records msg as the text of ba_last_error() and returns st.
 ba_status set_error(ba_status st, const std::string &msg);
+// Lays out what Algorithm 2 with N subsets needs on the system (the reduced-precision
+// Jacobian copy, the partition, the multidirectional product's layout), ahead of the solves.
+ba_status prepare_mcg(ba_system *s, int N, int precision);
 
 }  // namespace ba
 

@@ -92,7 +92,8 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
 }
 
 // y_j = sum_t S_(j, col t) v_(col t): one wavefront per block row; lane (t0, r), t0 < 7,
-// r < 9, adds row r of blocks t0, t0 + 7, ...; the seven partial sums of a row are then
+// r < 9, adds row r of blocks t0, t0 + 7, ... into two running sums (blocks t0 + 14 i
+// and t0 + 7 + 14 i, two blocks in flight); the fourteen partial sums of a row are then
 // added in t0 order.  When `done` is set and nonzero, the launch does nothing.
 __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
@@ -102,17 +103,30 @@ __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restric
     __shared__ double sh[4][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = blockIdx.x * 4 + w;
-    double acc = 0.0;
+    double acc = 0.0, acc1 = 0.0;
     if (j < np && lane < 63) {
         const int t0 = lane / 9, r = lane - t0 * 9;
-        for (int t = row_ptr[j] + t0; t < row_ptr[j + 1]; t += 7) {
+        const int end = row_ptr[j + 1];
+        int t = row_ptr[j] + t0;
+        for (; t + 7 < end; t += 14) {
+            const double *S = val + (int64_t)t * 81 + r * 9;
+            const double *S1 = S + 7 * 81;
+            const double *vk = v + (int64_t)col[t] * 9;
+            const double *vk1 = v + (int64_t)col[t + 7] * 9;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                acc += S[c] * vk[c];
+                acc1 += S1[c] * vk1[c];
+            }
+        }
+        if (t < end) {
             const double *S = val + (int64_t)t * 81 + r * 9;
             const double *vk = v + (int64_t)col[t] * 9;
 #pragma unroll
             for (int c = 0; c < 9; ++c) acc += S[c] * vk[c];
         }
     }
-    sh[w][lane] = acc;
+    sh[w][lane] = acc + acc1;
     __syncthreads();
     if (j < np && lane < 9) {
         double s = 0.0;

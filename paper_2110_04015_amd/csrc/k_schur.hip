@@ -275,10 +275,35 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
     }
 }
 
+// Sum of the 9-vectors rows[a..b) by the calling wavefront, component k = lane % 9 on
+// lanes < 63: lane l adds rows a + l / 9 + 7 i into two running sums (even and odd i,
+// so that two loads are in flight), then the 14 sums of a component are added in a
+// fixed order through sh (64 doubles of the wavefront).  Every lane returns its
+// component's total (lanes 63 and above return component 0's).
+__device__ __forceinline__ double wave_rows9(const double *__restrict__ rows, int64_t a, int64_t b, double *sh) {
+    const int lane = threadIdx.x & 63;
+    double s0 = 0.0, s1 = 0.0;
+    if (lane < 63) {
+        const int r0 = lane / 9, k = lane - r0 * 9;
+        int64_t j = a + r0;
+        for (; j + 7 < b; j += 14) {
+            s0 += rows[j * 9 + k];
+            s1 += rows[(j + 7) * 9 + k];
+        }
+        if (j < b) s0 += rows[j * 9 + k];
+    }
+    sh[lane] = s0 + s1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int k = lane < 63 ? lane % 9 : 0;
+    double t = 0.0;
+    for (int m = 0; m < 7; ++m) t += sh[k + 9 * m];
+    return t;
+}
+
 // y_c = lambda diag(U_c) v_c + sum of the partial rows of camera c, which are
-// contiguous (camera-major).  One wavefront per camera: lane l < 63 adds
-// component l % 9 of rows l / 9, l / 9 + 7, ...; the seven lanes of a component
-// are then added in lane order.
+// contiguous (camera-major); one wavefront per camera (wave_rows9).
 __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restrict__ ptr,
                                                  const double *__restrict__ partial,
                                                  const double *__restrict__ dU, const double *__restrict__ v,
@@ -289,20 +314,9 @@ __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restri
     __shared__ double sh[4][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + w;
-    const bool live = c < np && !(seg_skip && seg_skip[cam_seg[c]]);
-    double s = 0.0;
-    if (live && lane < 63) {
-        const int r0 = lane / 9, k = lane - r0 * 9;
-        const int64_t a = ptr[c], b = ptr[c + 1];
-        for (int64_t j = a + r0; j < b; j += 7) s += partial[j * 9 + k];
-    }
-    sh[w][lane] = s;
-    __syncthreads();
-    if (live && lane < 9) {
-        double t = dU[(int64_t)c * 9 + lane] * v[(int64_t)c * 9 + lane];
-        for (int m = 0; m < 7; ++m) t += sh[w][lane + 9 * m];
-        y[(int64_t)c * 9 + lane] = t;
-    }
+    if (c >= np || (seg_skip && seg_skip[cam_seg[c]])) return;   // uniform per wavefront
+    const double t = wave_rows9(partial, ptr[c], ptr[c + 1], sh[w]);
+    if (lane < 9) y[(int64_t)c * 9 + lane] = dU[(int64_t)c * 9 + lane] * v[(int64_t)c * 9 + lane] + t;
 }
 
 void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
@@ -409,24 +423,27 @@ __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *_
 }
 
 // Y[p][c] = [group(c) == p] lambda diag(U_c) z_c + sum of the partial rows of (c, p),
-// which are contiguous ((camera, subset)-major)
-__global__ void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr,
-                               const double *__restrict__ partial, const double *__restrict__ dU,
-                               const int32_t *__restrict__ group, const double *__restrict__ z,
-                               double *__restrict__ Y, const int32_t *__restrict__ cam_seg,
-                               const int32_t *__restrict__ seg_skip, const double *__restrict__ skip) {
+// which are contiguous ((camera, subset)-major); one wavefront per (c, p) (wave_rows9)
+__global__ __launch_bounds__(256) void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr,
+                                                      const double *__restrict__ partial,
+                                                      const double *__restrict__ dU,
+                                                      const int32_t *__restrict__ group,
+                                                      const double *__restrict__ z, double *__restrict__ Y,
+                                                      const int32_t *__restrict__ cam_seg,
+                                                      const int32_t *__restrict__ seg_skip,
+                                                      const double *__restrict__ skip) {
     if (skip && *skip != 0.0) return;
-    int64_t n = (int64_t)np * 9;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * N) return;
-    int p = (int)(i / n);
-    int rem = (int)(i - (int64_t)p * n);
-    int c = rem / 9, k = rem - c * 9;
+    __shared__ double sh[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t key = (int64_t)blockIdx.x * 4 + w;   // c * N + p
+    if (key >= (int64_t)np * N) return;                 // uniform per wavefront
+    const int c = (int)(key / N), p = (int)(key - (int64_t)c * N);
     if (seg_skip && seg_skip[cam_seg[c]]) return;
-    double s = group[c] == p ? dU[rem] * z[rem] : 0.0;
-    int64_t key = (int64_t)c * N + p;
-    for (int j = ptr[key]; j < ptr[key + 1]; ++j) s += partial[(int64_t)j * 9 + k];
-    Y[i] = s;
+    const double t = wave_rows9(partial, ptr[key], ptr[key + 1], sh[w]);
+    if (lane < 9) {
+        const int64_t rem = (int64_t)c * 9 + lane;
+        Y[(int64_t)p * np * 9 + rem] = (group[c] == p ? dU[rem] * z[rem] : 0.0) + t;
+    }
 }
 
 void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s) {
@@ -438,8 +455,8 @@ void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStrea
             default: hipLaunchKernelGGL((k_schur_multi<2, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;
         }
     }
-    int64_t total = (int64_t)a.np * 9 * a.N;
-    hipLaunchKernelGGL(k_reduce_multi, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.np, a.N, a.cg_ptr,
+    const int64_t keys = (int64_t)a.np * a.N;
+    hipLaunchKernelGGL(k_reduce_multi, dim3((unsigned)((keys + 3) / 4)), dim3(256), 0, s, a.np, a.N, a.cg_ptr,
                        a.partial, a.dU, a.group, z, Y, a.cam_seg, a.seg_skip, a.skip);
 }
 

@@ -153,6 +153,11 @@ ba_status ba_lm_solve(const ba_scene_desc *sc, double *cams, double *X, const ba
     d.lambda = lam;
     ba_system *sys = nullptr;
     if ((st = ba_build_system(&d, &o.build, stream, &sys)) != BA_OK) return st;
+    // the subsets' layout depends on the observations only: set up once, with the system
+    if (o.solver == 1 && (st = prepare_mcg(sys, o.n_groups, o.solve.precision)) != BA_OK) {
+        ba_free_system(sys);
+        return st;
+    }
     t_lin += ms_since(tl);
     const double cost0 = F;
     int it = 0, accepted_n = 0;
