@@ -1052,8 +1052,8 @@ static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const dou
     hipStream_t q = s->stream;
     ba_status st = ensure_precision(s, opts.precision);
     if (st != BA_OK) return st;
-    if (!s->refine_buf && (st = dalloc(&s->refine_buf, (size_t)n * 4 + 8)) != BA_OK) return st;
-    double *r = s->refine_buf, *btp = r + n, *d = btp + n, *tmp = d + n;
+    if (!s->refine_buf && (st = dalloc(&s->refine_buf, (size_t)n * 5 + 8)) != BA_OK) return st;
+    double *r = s->refine_buf, *btp = r + n, *d = btp + n, *tmp = d + n, *xprev = tmp + n + 8;
     auto t0 = std::chrono::steady_clock::now();
     if (x0) HIPCHK(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
     else HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), q));
@@ -1085,7 +1085,15 @@ static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const dou
             result = BA_OK;
             break;
         }
-        if (outer >= opts.max_outer || total_it >= opts.max_iter || !(rel < prev)) break;
+        if (outer > 0 && !(rel < prev)) {
+            // the last correction did not reduce the FP64 residual (the inner solve on the
+            // reduced-precision operator failed to contract, or diverged): keep the iterate
+            // from before it
+            HIPCHK(hipMemcpyAsync(x, xprev, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
+            rel = prev;
+            break;
+        }
+        if (outer >= opts.max_outer || total_it >= opts.max_iter) break;
         prev = rel;
         ba_solve_stats is;
         memset(&is, 0, sizeof is);
@@ -1102,6 +1110,7 @@ static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const dou
         total_it += is.iterations;
         total_multi += is.multi_steps;
         ++outer;
+        HIPCHK(hipMemcpyAsync(xprev, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
         launch_axpy(n, 1.0, d, x, q);
         HIPCHK(hipGetLastError());
         if (is.iterations == 0) break;
@@ -1305,7 +1314,7 @@ struct ba_batch {
     double *Ph = nullptr, *Qh = nullptr, *Dp = nullptr, *Phi = nullptr, *beta = nullptr;
     int32_t *blk_off = nullptr, *blk_k = nullptr;
     int64_t *blk_dp = nullptr;
-    double *btp = nullptr, *d = nullptr, *tmp = nullptr;
+    double *btp = nullptr, *d = nullptr, *tmp = nullptr, *xprev = nullptr;
     int32_t *host_i = nullptr;      // pinned
     double *host_d = nullptr;       // pinned [2B]
     // graph windows are captured on a stream of the batch (the caller's stream may be
@@ -1344,6 +1353,7 @@ void free_batch_ws(ba_batch *b) {
     dfree(b->btp);
     dfree(b->d);
     dfree(b->tmp);
+    dfree(b->xprev);
     b->N = 0;
     b->cap = 0;
 }
@@ -1382,7 +1392,7 @@ ba_status ensure_batch_ws(ba_batch *b, int N, int64_t cap) {
     if ((st = dalloc(&b->gpart, (size_t)B * kBatchGramBlocks * (size_t)(N * N + N))) != BA_OK) return st;
     if ((st = dalloc(&b->upart, (size_t)B * kBatchVecBlocks * 2)) != BA_OK) return st;
     if ((st = dalloc(&b->resid, (size_t)B * 2)) != BA_OK) return st;
-    for (double **v : {&b->r, &b->z, &b->pstage, &b->qstage, &b->btp, &b->d, &b->tmp})
+    for (double **v : {&b->r, &b->z, &b->pstage, &b->qstage, &b->btp, &b->d, &b->tmp, &b->xprev})
         if ((st = dalloc(v, (size_t)ntot)) != BA_OK) return st;
     if ((st = dalloc(&b->Y, (size_t)ntot * N)) != BA_OK) return st;
     if ((st = dalloc(&b->Ph, (size_t)hb)) != BA_OK) return st;
@@ -1660,7 +1670,15 @@ ba_status ba_batch_mcg_solve(ba_batch *b, int32_t N, double tau, double *x, cons
                 if (rel[(size_t)i] < opts.eps) {
                     status[(size_t)i] = BA_OK;
                     offh[(size_t)i] = 1;
-                } else if (o >= opts.max_outer || iters[(size_t)i] >= opts.max_iter || !(rel[(size_t)i] < prev[(size_t)i])) {
+                } else if (o > 0 && !(rel[(size_t)i] < prev[(size_t)i])) {
+                    // the last correction did not reduce this problem's FP64 residual: keep
+                    // its iterate from before the correction
+                    const size_t r0 = (size_t)b->cam0[(size_t)i] * 9, len = (size_t)b->np[(size_t)i] * 9;
+                    HIPCHK(hipMemcpyAsync(x + r0, b->xprev + r0, len * sizeof(double), hipMemcpyDeviceToDevice, q));
+                    rel[(size_t)i] = prev[(size_t)i];
+                    status[(size_t)i] = BA_MAXITER;
+                    offh[(size_t)i] = 1;
+                } else if (o >= opts.max_outer || iters[(size_t)i] >= opts.max_iter) {
                     status[(size_t)i] = BA_MAXITER;
                     offh[(size_t)i] = 1;
                 }
@@ -1673,6 +1691,7 @@ ba_status ba_batch_mcg_solve(ba_batch *b, int32_t N, double tau, double *x, cons
             if ((st = batch_core(b, opts.precision, b->btp, b->d, b->off, tau, ieps, inner_max, graph_window, t0,
                                  nullptr)) != BA_OK)
                 return st;
+            HIPCHK(hipMemcpyAsync(b->xprev, x, sizeof(double) * (size_t)s->np * 9, hipMemcpyDeviceToDevice, q));
             launch_axpy((int64_t)s->np * 9, 1.0, b->d, x, q);
             HIPCHK(hipGetLastError());
             if ((st = batch_stats_from_device(b, hd)) != BA_OK) return st;

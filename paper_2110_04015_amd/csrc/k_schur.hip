@@ -344,6 +344,125 @@ void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStre
 
 // ---------------------------------------------------------------- N columns
 
+// Slot words of one lane of a tile for the multidirectional product: the pair word
+// (own pair, first pair of the landmark, pair count; kPad on padding slots), the
+// camera, the pair's landmark (0xFF past the tile's pairs) and the offset of the
+// slot's output indices.
+struct MultiSlot {
+    uint32_t mm;
+    int32_t cam;
+    uint32_t pll;
+    uint32_t ooff;
+};
+
+__device__ __forceinline__ MultiSlot fetch_mslot(const MultiArgs &a, int64_t sidx) {
+    MultiSlot m;
+    m.mm = a.mmeta[sidx];
+    m.cam = a.slot_cam[sidx];
+    m.pll = a.pair_ll[sidx];
+    m.ooff = a.slot_ooff[sidx];
+    return m;
+}
+
+// Record, z of the slot's camera, V^-1 of the lane's pair landmark and the slot words
+// of one tile (see TileBuf).  Padding slots read camera 0's z and the tile's first
+// landmark's V^-1 and ignore them.
+template <int PREC, typename T>
+struct MultiBuf {
+    TileBuf<PREC, T> r;   // record (r.vi and r.mt unused)
+    dbl2_t z[5];          // z_c (9 values, the 10th unused)
+    dbl2_t vi[3];
+    MultiSlot m;
+    uint32_t obase;       // tile_oidx of the tile
+};
+
+template <int PREC, typename T>
+__device__ __forceinline__ void fetch_mtile(const MultiArgs &a, const double *__restrict__ z, int t, int lane,
+                                            const MultiSlot &m, MultiBuf<PREC, T> &b) {
+    b.m = m;
+    fetch_record<PREC, T>(a.J, t, lane, b.r);
+    const bool valid = m.mm != kPad;
+    const double *zc = z + (int64_t)(valid ? m.cam : 0) * 9;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b.z[k] = dbl2_t{zc[2 * k], zc[2 * k + 1]};
+    b.z[4] = dbl2_t{zc[8], 0.0};
+    const int ll = m.pll != 0xFFu ? (int)m.pll : 0;
+    const dbl2_t *p = reinterpret_cast<const dbl2_t *>(a.vinv + (int64_t)(a.tile_lmk_base[t] + ll) * 6);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) b.vi[q] = p[q];
+    b.obase = a.tile_oidx[t];
+}
+
+// One tile: e = J_p z_c; g per (landmark, subset) pair = sum over the pair's
+// observations of J_l^T e (LDS); h = V^-1 g on the pair's lane; every observation of
+// the landmark adds J_p^T (e [own pair] - J_l h_pair) to its (camera, pair subset) row.
+template <typename T>
+__device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[24], const dbl2_t (&zb)[5],
+                                           const dbl2_t (&vi)[3], const MultiSlot &m, uint32_t obase, int lane,
+                                           double *yloc, double *gloc, double *hloc) {
+    const bool valid = m.mm != kPad;
+    const T zc[9] = {(T)zb[0].x, (T)zb[0].y, (T)zb[1].x, (T)zb[1].y, (T)zb[2].x,
+                     (T)zb[2].y, (T)zb[3].x, (T)zb[3].y, (T)zb[4].x};
+    T e0 = 0, e1 = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        e0 += J[k] * zc[k];
+        e1 += J[9 + k] * zc[k];
+    }
+    const int own = (int)(m.mm & 0xFFu);
+    gloc[lane * 3 + 0] = 0;
+    gloc[lane * 3 + 1] = 0;
+    gloc[lane * 3 + 2] = 0;
+    wave_sync();
+    if (valid) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], (double)(J[18 + k] * e0 + J[21 + k] * e1));
+    }
+    wave_sync();
+    if (m.pll != 0xFFu) {
+        const T w0 = (T)vi[0].x, w1 = (T)vi[0].y, w2 = (T)vi[1].x;
+        const T w3 = (T)vi[1].y, w4 = (T)vi[2].x, w5 = (T)vi[2].y;
+        const T g0 = (T)gloc[lane * 3], g1 = (T)gloc[lane * 3 + 1], g2 = (T)gloc[lane * 3 + 2];
+        hloc[lane * 3 + 0] = (double)(w0 * g0 + w1 * g1 + w2 * g2);
+        hloc[lane * 3 + 1] = (double)(w1 * g0 + w3 * g1 + w4 * g2);
+        hloc[lane * 3 + 2] = (double)(w2 * g0 + w4 * g1 + w5 * g2);
+    }
+    wave_sync();
+    if (valid) {
+        const int base = (int)((m.mm >> 8) & 0xFFu), cnt = (int)((m.mm >> 16) & 0xFFu);
+        const uint16_t *oi = a.oidx + obase + m.ooff;
+        for (int j = 0; j < cnt; ++j) {
+            const int pj = base + j;
+            const T h0 = (T)hloc[pj * 3], h1 = (T)hloc[pj * 3 + 1], h2 = (T)hloc[pj * 3 + 2];
+            T f0 = -(J[18] * h0 + J[19] * h1 + J[20] * h2);
+            T f1 = -(J[21] * h0 + J[22] * h1 + J[23] * h2);
+            if (pj == own) {
+                f0 += e0;
+                f1 += e1;
+            }
+            const int o = oi[j];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) atomicAdd(&yloc[o * 9 + k], (double)(J[k] * f0 + J[9 + k] * f1));
+        }
+    }
+    wave_sync();
+}
+
+template <int PREC, typename T>
+__device__ __forceinline__ void process_mtile(const MultiArgs &a, const MultiBuf<PREC, T> &b, int lane,
+                                              double *yloc, double *gloc, double *hloc) {
+    if constexpr (PREC == 2) {
+        T J[24];
+        Stream<2>::unpack(b.r.w, J);
+        multi_tile<T>(a, J, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
+    } else {
+        multi_tile<T>(a, b.r.v, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
+    }
+}
+
+// One wavefront per chunk of tiles, software-pipelined as k_schur1: the record, z
+// gather and V^-1 of tile t + 1 and the slot words of tile t + 2 are requested before
+// tile t is processed.
 template <int PREC, typename T>
 __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *__restrict__ z) {
     if (a.skip && *a.skip != 0.0) return;
@@ -356,65 +475,31 @@ __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *_
     const int lane = threadIdx.x;
     const int pb = a.chunk_part[chunk];
     const int no = a.chunk_part[chunk + 1] - pb;
+    const int t0 = a.chunk_tile[chunk], t1 = a.chunk_tile[chunk + 1];
+    const int tl = t1 - 1;   // slot words past the chunk's end are read from its last tile
+    MultiBuf<PREC, T> A, B;
+    MultiSlot mA, mB{};
+    if (t0 < t1) {
+        fetch_mtile<PREC, T>(a, z, t0, lane, fetch_mslot(a, (int64_t)t0 * kTile + lane), A);
+        mB = fetch_mslot(a, (int64_t)min(t0 + 1, tl) * kTile + lane);
+    }
     for (int i = lane; i < no * 9; i += kTile) yloc[i] = 0.0;
-    __syncthreads();
-    const int t1 = a.chunk_tile[chunk + 1];
-    for (int t = a.chunk_tile[chunk]; t < t1; ++t) {
-        T J[24];
-        Loader<PREC>::load(a.J, t, lane, J);
-        const int64_t sidx = (int64_t)t * kTile + lane;
-        const uint32_t mt = a.meta[sidx];
-        const uint32_t mm = a.mmeta[sidx];
-        const int lmk0 = a.tile_lmk_base[t];
-        const bool valid = mt != kPad;
-        const int cam = a.slot_cam[sidx];
-        T e0 = 0, e1 = 0;
-        if (valid) {
-            const double *zc = z + (int64_t)cam * 9;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                T zk = (T)zc[k];
-                e0 += J[k] * zk;
-                e1 += J[9 + k] * zk;
-            }
-        }
-        const int own = (int)(mm & 0xFFu);
-        gloc[lane * 3 + 0] = 0;
-        gloc[lane * 3 + 1] = 0;
-        gloc[lane * 3 + 2] = 0;
-        __syncthreads();
-        if (valid) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], (double)(J[18 + k] * e0 + J[21 + k] * e1));
-        }
-        __syncthreads();
-        const uint8_t pll = a.pair_ll[sidx];
-        if (pll != 0xFF) {
-            const double *vi = a.vinv + (int64_t)(lmk0 + pll) * 6;
-            const T g0 = (T)gloc[lane * 3], g1 = (T)gloc[lane * 3 + 1], g2 = (T)gloc[lane * 3 + 2];
-            hloc[lane * 3 + 0] = (double)((T)vi[0] * g0 + (T)vi[1] * g1 + (T)vi[2] * g2);
-            hloc[lane * 3 + 1] = (double)((T)vi[1] * g0 + (T)vi[3] * g1 + (T)vi[4] * g2);
-            hloc[lane * 3 + 2] = (double)((T)vi[2] * g0 + (T)vi[4] * g1 + (T)vi[5] * g2);
-        }
-        __syncthreads();
-        if (valid) {
-            const int base = (int)((mm >> 8) & 0xFFu), cnt = (int)((mm >> 16) & 0xFFu);
-            const uint16_t *oi = a.oidx + a.tile_oidx[t] + a.slot_ooff[sidx];
-            for (int j = 0; j < cnt; ++j) {
-                const int pj = base + j;
-                const T h0 = (T)hloc[pj * 3], h1 = (T)hloc[pj * 3 + 1], h2 = (T)hloc[pj * 3 + 2];
-                T f0 = -(J[18] * h0 + J[19] * h1 + J[20] * h2);
-                T f1 = -(J[21] * h0 + J[22] * h1 + J[23] * h2);
-                if (pj == own) {
-                    f0 += e0;
-                    f1 += e1;
-                }
-                const int o = oi[j];
-#pragma unroll
-                for (int k = 0; k < 9; ++k) atomicAdd(&yloc[o * 9 + k], (double)(J[k] * f0 + J[9 + k] * f1));
-            }
-        }
-        __syncthreads();
+    wave_sync();
+    int t = t0;
+    for (; t + 2 < t1; t += 2) {
+        fetch_mtile<PREC, T>(a, z, t + 1, lane, mB, B);
+        mA = fetch_mslot(a, (int64_t)(t + 2) * kTile + lane);
+        process_mtile<PREC, T>(a, A, lane, yloc, gloc, hloc);
+        fetch_mtile<PREC, T>(a, z, t + 2, lane, mA, A);
+        mB = fetch_mslot(a, (int64_t)min(t + 3, tl) * kTile + lane);
+        process_mtile<PREC, T>(a, B, lane, yloc, gloc, hloc);
+    }
+    if (t + 1 < t1) {
+        fetch_mtile<PREC, T>(a, z, t + 1, lane, mB, B);
+        process_mtile<PREC, T>(a, A, lane, yloc, gloc, hloc);
+        process_mtile<PREC, T>(a, B, lane, yloc, gloc, hloc);
+    } else if (t < t1) {
+        process_mtile<PREC, T>(a, A, lane, yloc, gloc, hloc);
     }
     for (int i = lane; i < no * 9; i += kTile) {
         const int64_t row = a.part_dst[pb + i / 9];

@@ -13,7 +13,7 @@ from typing import Dict, List, Sequence, Tuple
 
 from . import Batch, System
 
-CANDIDATES: Tuple[Tuple[int, int], ...] = ((128, 4), (128, 8), (128, 16), (128, 32), (256, 16), (64, 16))
+CANDIDATES: Tuple[Tuple[int, int], ...] = ((128, 4), (128, 8), (128, 16), (128, 32), (128, 64), (256, 16), (64, 16))
 
 
 def _time_products(system: System, precision: str, reps: int) -> float:
