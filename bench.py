@@ -220,6 +220,11 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 5),
                 "launches": int(launches)}
+    # practical ceiling: a pure read of as many bytes in the same access pattern
+    ceiling = ba.stream_read_gbs(bytes_per_launch, reps=10)
+    roofline["stream_read_ceiling"] = round(ceiling, 1)
+    roofline["frac_of_ceiling"] = round(achieved / ceiling, 4)
+    log(f"stream-read ceiling {ceiling:.0f} GB/s; chunk kernel at {achieved / ceiling:.3f} of it")
 
     variants = {}
     if not args.no_variants:

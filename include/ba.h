@@ -397,6 +397,13 @@ ba_status ba_apply_step(int32_t n_cams, int32_t n_lms, const double *cams, const
 ba_status ba_lm_solve(const ba_scene_desc *scene, double *cams, double *X, const ba_lm_opts *opts, void *stream,
                       ba_lm_stats *stats);
 
+/* Measurement helper (not part of the method): the HBM read rate in GB/s (host
+ * output) of a kernel that streams a zero-filled buffer of `bytes` (device memory
+ * allocated and freed by the call) in the S-product kernel's access pattern (one
+ * wavefront per 16 tiles of 12 coalesced 1 KiB loads), timed with HIP events over
+ * `reps` launches on `stream`.  The practical ceiling for that kernel's bandwidth. */
+ba_status ba_stream_read_gbs(int64_t bytes, int32_t reps, double *gbs, void *stream);
+
 const char *ba_status_string(int32_t status);
 const char *ba_last_error(void);
 

@@ -358,6 +358,13 @@ def adam_step(params, grad, m, v, t, lr=1e-3, stream=None):
                               int(t), float(lr), _stream_handle(stream)), "ba_adam_step")
 
 
+def stream_read_gbs(nbytes: int, reps: int = 10, stream=None) -> float:
+    """HBM read rate (GB/s) of a pure stream in the S-product kernel's access pattern."""
+    g = C.c_double()
+    _check(lib().ba_stream_read_gbs(int(nbytes), int(reps), C.byref(g), _stream_handle(stream)), "ba_stream_read_gbs")
+    return g.value
+
+
 def pinv_sym(A, stream=None):
     """Device pseudo-inverse of a symmetric k x k FP64 matrix; returns (A^+, rank)."""
     torch = _torch()

@@ -325,16 +325,24 @@ __global__ __launch_bounds__(kNT) void k_gram(int64_t n, int k, int R, const dou
 #pragma unroll
         for (int o = 0; o < kGramOut; ++o) {
             const int idx = threadIdx.x + o * kNT;
-            if (idx < k * k) {
-                const int a = idx / k, c = idx - a * k;
-                double s = 0.0;
-                for (int rr = 0; rr < rows; ++rr) s += sQ[rr * k + a] * sP[rr * k + c];
-                acc[o] += s;
-            } else if (idx < tot) {
-                const int a = idx - k * k;
-                double s = 0.0;
-                for (int rr = 0; rr < rows; ++rr) s += sP[rr * k + a] * sr[rr];
-                acc[o] += s;
+            if (idx < tot) {
+                // Q[:, a] . P[:, c], or P[:, a] . r for the last k outputs; four running sums
+                // keep four LDS reads of each operand in flight
+                const bool pr = idx >= k * k;
+                const int a = pr ? idx - k * k : idx / k;
+                const double *x = pr ? sP + a : sQ + a;
+                const double *y = pr ? sr : sP + (idx - a * k);
+                const int sy = pr ? 1 : k;
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                int rr = 0;
+                for (; rr + 4 <= rows; rr += 4) {
+                    s0 += x[rr * k] * y[rr * sy];
+                    s1 += x[(rr + 1) * k] * y[(rr + 1) * sy];
+                    s2 += x[(rr + 2) * k] * y[(rr + 2) * sy];
+                    s3 += x[(rr + 3) * k] * y[(rr + 3) * sy];
+                }
+                for (; rr < rows; ++rr) s0 += x[rr * k] * y[rr * sy];
+                acc[o] += (s0 + s1) + (s2 + s3);
             }
         }
         __syncthreads();
@@ -516,14 +524,16 @@ __global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const do
         hi = n * (p + 1) / seg;
     }
     const double *q = Qh + col * n;
-    double a0 = 0.0, a1 = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int64_t i = lo + lane;
-    for (; i + 64 < hi; i += 128) {
+    for (; i + 192 < hi; i += 256) {   // four rows per lane in flight
         a0 += q[i] * z[i];
         a1 += q[i + 64] * z[i + 64];
+        a2 += q[i + 128] * z[i + 128];
+        a3 += q[i + 192] * z[i + 192];
     }
-    if (i < hi) a0 += q[i] * z[i];
-    const double acc = wave_sum(a0 + a1);
+    for (; i < hi; i += 64) a0 += q[i] * z[i];
+    const double acc = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) Phi[w] = acc;
 }
 
@@ -596,17 +606,17 @@ __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, int kn, i
     if (row < n) {
         const double *hp = H + row;
         int c = c0;
-        for (; c + 4 <= c1; c += 4) {
-            const double h0 = hp[(int64_t)c * n], h1 = hp[(int64_t)(c + 1) * n];
-            const double h2 = hp[(int64_t)(c + 2) * n], h3 = hp[(int64_t)(c + 3) * n];
+        // eight columns per step: eight loads of the history in flight per lane
+        for (; c + 8 <= c1; c += 8) {
+            double hv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) hv[u] = hp[(int64_t)(c + u) * n];
             const double *b0 = beta + (int64_t)c * kn + p0;
 #pragma unroll
             for (int j = 0; j < KB; ++j) {
                 if (p0 + j < kn) {
-                    acc[j] += h0 * b0[j];
-                    acc[j] += h1 * b0[kn + j];
-                    acc[j] += h2 * b0[2 * kn + j];
-                    acc[j] += h3 * b0[3 * kn + j];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc[j] += hv[u] * b0[u * kn + j];
                 }
             }
         }
