@@ -74,6 +74,9 @@ def load(path: Optional[str] = None) -> C.CDLL:
     lib = C.CDLL(path)
     lib.or_build.restype = C.c_void_p
     lib.or_build.argtypes = [C.c_int, C.c_int, C.c_int64, _ip, _ip, _dp, _dp, _dp, C.c_double, _ip]
+    lib.or_build_dp.restype = C.c_void_p
+    lib.or_build_dp.argtypes = [C.c_int, C.c_int, C.c_int64, _ip, _ip, _dp, _dp, _dp, C.c_double, C.c_int, _ip]
+    lib.or_dp.argtypes = [C.c_void_p]
     lib.or_free.argtypes = [C.c_void_p]
     lib.or_n.argtypes = [C.c_void_p]
     for name in ("or_get_rhs", "or_get_U", "or_get_Vinv", "or_get_Dblocks"):
@@ -113,13 +116,15 @@ class OracleError(RuntimeError):
 
 
 class System:
-    """The oracle's damped normal equation and reduced camera system for one problem."""
+    """The oracle's damped normal equation and reduced camera system for one problem;
+    the pose dimension d_p (6 or 9, Sec. 3.1) is the last axis of J_p."""
 
     def __init__(self, problem, lam: Optional[float] = None, libobj: Optional[C.CDLL] = None):
         self.lib = libobj or lib()
         p = problem
         self.n_cams, self.n_lms = p.n_cams, p.n_lms
-        self.n = 9 * p.n_cams
+        self.dp = int(np.shape(p.J_p)[-1])
+        self.n = self.dp * p.n_cams
         self._keep = [np.ascontiguousarray(p.obs_cam, dtype=np.int32),
                       np.ascontiguousarray(p.obs_lm, dtype=np.int32),
                       np.ascontiguousarray(p.J_p, dtype=np.float64),
@@ -127,9 +132,9 @@ class System:
                       np.ascontiguousarray(p.r, dtype=np.float64)]
         cam, lm, Jp, Jl, r = self._keep
         st = C.c_int(0)
-        self.h = self.lib.or_build(p.n_cams, p.n_lms, cam.shape[0], _ptr(cam, _ip), _ptr(lm, _ip),
-                                   _ptr(Jp), _ptr(Jl), _ptr(r),
-                                   float(p.lam if lam is None else lam), C.byref(st))
+        self.h = self.lib.or_build_dp(p.n_cams, p.n_lms, cam.shape[0], _ptr(cam, _ip), _ptr(lm, _ip),
+                                      _ptr(Jp), _ptr(Jl), _ptr(r),
+                                      float(p.lam if lam is None else lam), self.dp, C.byref(st))
         self._keep = None
         if not self.h:
             raise OracleError(st.value)
@@ -152,7 +157,7 @@ class System:
         return bp, bl
 
     def U_blocks(self) -> np.ndarray:
-        out = np.empty((self.n_cams, 9, 9))
+        out = np.empty((self.n_cams, self.dp, self.dp))
         self.lib.or_get_U(self.h, _ptr(out))
         return out
 
@@ -162,7 +167,7 @@ class System:
         return out
 
     def D_blocks(self) -> np.ndarray:
-        out = np.empty((self.n_cams, 9, 9))
+        out = np.empty((self.n_cams, self.dp, self.dp))
         self.lib.or_get_Dblocks(self.h, _ptr(out))
         return out
 

@@ -51,18 +51,21 @@
 #define OR_ERR_BREAKDOWN (-4)
 #define OR_ERR_NOMEM (-7)
 
+#define DPMAX 9   /* largest pose dimension d_p (Sec. 3.1: 6 extrinsics, 9 with intrinsics) */
+
 typedef struct {
     int np, nl;
+    int dp;                      /* pose dimension d_p: 6 or 9 */
     int64_t m;
     double lambda;
     const double *Jp, *Jl, *r;   /* kept for the build only; not owned */
     int *cam, *lm;               /* owned copies */
-    double *U;                   /* np x 81 : U_lambda blocks */
-    double *Vinv;                /* nl x 9  : V_lambda^-1 */
-    double *W;                   /* m x 27  : W_o = J_p,o^T J_l,o (9x3 row-major) */
-    double *bp, *bl, *bt;        /* 9 np, 3 nl, 9 np */
-    double *D;                   /* np x 81 : D(S) blocks */
-    double *Dchol;               /* np x 81 : lower Cholesky factors of D(S) */
+    double *U;                   /* np x dp^2 : U_lambda blocks */
+    double *Vinv;                /* nl x 9    : V_lambda^-1 (3x3) */
+    double *W;                   /* m x 3 dp  : W_o = J_p,o^T J_l,o (dp x 3 row-major) */
+    double *bp, *bl, *bt;        /* dp np, 3 nl, dp np */
+    double *D;                   /* np x dp^2 : D(S) blocks */
+    double *Dchol;               /* np x dp^2 : lower Cholesky factors of D(S) */
     int64_t *lm_ptr, *lm_obs;    /* observations of each landmark */
     int64_t *cam_ptr, *cam_obs;  /* observations of each camera */
     double *Ulr;                 /* n x lr_rank (row-major) low-rank preconditioner term, or NULL */
@@ -217,12 +220,14 @@ void or_free(or_sys *s) {
 }
 
 /* Build every block of the damped normal equation (eq. (8)-(12)) and of the
- * reduced camera system (eq. (14)-(15)), plus the block-Jacobi blocks D(S).
- * Host arrays: cam, lm [m]; Jp [m][2][9]; Jl [m][2][3]; r [m][2]. */
-or_sys *or_build(int np, int nl, int64_t m, const int *cam, const int *lm, const double *Jp,
-                 const double *Jl, const double *r, double lambda, int *status) {
+ * reduced camera system (eq. (14)-(15)), plus the block-Jacobi blocks D(S), for
+ * poses of dimension dp (6: extrinsics only; 9: with intrinsics; Sec. 3.1).
+ * Host arrays: cam, lm [m]; Jp [m][2][dp]; Jl [m][2][3]; r [m][2]. */
+or_sys *or_build_dp(int np, int nl, int64_t m, const int *cam, const int *lm, const double *Jp,
+                    const double *Jl, const double *r, double lambda, int dp, int *status) {
     *status = OR_OK;
-    if (np <= 0 || nl <= 0 || m < 0 || !(lambda >= 0.0) || !cam || !lm || !Jp || !Jl || !r) {
+    if (np <= 0 || nl <= 0 || m < 0 || !(lambda >= 0.0) || !cam || !lm || !Jp || !Jl || !r ||
+        (dp != 6 && dp != 9)) {
         *status = OR_ERR_INVALID;
         return NULL;
     }
@@ -232,12 +237,12 @@ or_sys *or_build(int np, int nl, int64_t m, const int *cam, const int *lm, const
             return NULL;
         }
     }
-    for (int64_t i = 0; i < m * 18; ++i) if (!isfinite(Jp[i])) { *status = OR_ERR_NONFINITE; return NULL; }
+    for (int64_t i = 0; i < m * 2 * dp; ++i) if (!isfinite(Jp[i])) { *status = OR_ERR_NONFINITE; return NULL; }
     for (int64_t i = 0; i < m * 6; ++i) if (!isfinite(Jl[i])) { *status = OR_ERR_NONFINITE; return NULL; }
     for (int64_t i = 0; i < m * 2; ++i) if (!isfinite(r[i])) { *status = OR_ERR_NONFINITE; return NULL; }
 
     or_sys *s = (or_sys *)calloc(1, sizeof(or_sys));
-    s->np = np; s->nl = nl; s->m = m; s->lambda = lambda;
+    s->np = np; s->nl = nl; s->m = m; s->lambda = lambda; s->dp = dp;
     s->cam = (int *)malloc(sizeof(int) * (size_t)(m > 0 ? m : 1));
     s->lm = (int *)malloc(sizeof(int) * (size_t)(m > 0 ? m : 1));
     memcpy(s->cam, cam, sizeof(int) * (size_t)m);
@@ -259,43 +264,43 @@ or_sys *or_build(int np, int nl, int64_t m, const int *cam, const int *lm, const
     }
     if (bad) { or_free(s); *status = OR_ERR_INVALID; return NULL; }
 
-    int n = 9 * np;
-    s->U = (double *)calloc((size_t)np * 81, sizeof(double));
+    int n = dp * np;
+    s->U = (double *)calloc((size_t)np * dp * dp, sizeof(double));
     s->Vinv = (double *)calloc((size_t)nl * 9, sizeof(double));
-    s->W = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * 27);
+    s->W = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1) * 3 * dp);
     s->bp = (double *)calloc((size_t)n, sizeof(double));
     s->bl = (double *)calloc((size_t)nl * 3, sizeof(double));
     s->bt = (double *)calloc((size_t)n, sizeof(double));
-    s->D = (double *)calloc((size_t)np * 81, sizeof(double));
-    s->Dchol = (double *)calloc((size_t)np * 81, sizeof(double));
+    s->D = (double *)calloc((size_t)np * dp * dp, sizeof(double));
+    s->Dchol = (double *)calloc((size_t)np * dp * dp, sizeof(double));
     if (!s->U || !s->Vinv || !s->W || !s->bp || !s->bl || !s->bt || !s->D || !s->Dchol) {
         or_free(s); *status = OR_ERR_NOMEM; return NULL;
     }
 
-    /* eq. (11): W = J_p^T J_l, one 9x3 block per observation (camera, landmark) */
+    /* eq. (11): W = J_p^T J_l, one dp x 3 block per observation (camera, landmark) */
 #pragma omp parallel for schedule(static)
     for (int64_t o = 0; o < m; ++o) {
-        const double *jp = Jp + o * 18, *jl = Jl + o * 6;
-        double *w = s->W + o * 27;
-        for (int i = 0; i < 9; ++i)
+        const double *jp = Jp + o * 2 * dp, *jl = Jl + o * 6;
+        double *w = s->W + o * 3 * dp;
+        for (int i = 0; i < dp; ++i)
             for (int j = 0; j < 3; ++j)
-                w[i * 3 + j] = jp[0 * 9 + i] * jl[0 * 3 + j] + jp[1 * 9 + i] * jl[1 * 3 + j];
+                w[i * 3 + j] = jp[0 * dp + i] * jl[0 * 3 + j] + jp[1 * dp + i] * jl[1 * 3 + j];
     }
 
     /* eq. (9), (11): U_lambda = J_p^T J_p + lambda D_p^T D_p, b_p = J_p^T r0 */
 #pragma omp parallel for schedule(dynamic, 16)
     for (int c = 0; c < np; ++c) {
-        double *U = s->U + (size_t)c * 81;
-        double *bp = s->bp + (size_t)c * 9;
+        double *U = s->U + (size_t)c * dp * dp;
+        double *bp = s->bp + (size_t)c * dp;
         for (int64_t q = s->cam_ptr[c]; q < s->cam_ptr[c + 1]; ++q) {
             int64_t o = s->cam_obs[q];
-            const double *jp = Jp + o * 18, *ro = r + o * 2;
-            for (int i = 0; i < 9; ++i) {
-                for (int j = 0; j < 9; ++j) U[i * 9 + j] += jp[i] * jp[j] + jp[9 + i] * jp[9 + j];
-                bp[i] += jp[i] * ro[0] + jp[9 + i] * ro[1];
+            const double *jp = Jp + o * 2 * dp, *ro = r + o * 2;
+            for (int i = 0; i < dp; ++i) {
+                for (int j = 0; j < dp; ++j) U[i * dp + j] += jp[i] * jp[j] + jp[dp + i] * jp[dp + j];
+                bp[i] += jp[i] * ro[0] + jp[dp + i] * ro[1];
             }
         }
-        for (int i = 0; i < 9; ++i) U[i * 9 + i] += lambda * U[i * 9 + i];
+        for (int i = 0; i < dp; ++i) U[i * dp + i] += lambda * U[i * dp + i];
     }
 
     /* eq. (10), (12): V_lambda = J_l^T J_l + lambda D_l^T D_l, b_l = J_l^T r0 */
@@ -329,47 +334,53 @@ or_sys *or_build(int np, int nl, int64_t m, const int *cam, const int *lm, const
     /* eq. (15): b~ = b_p - W V^-1 b_l ;  D(S) = diagonal blocks of eq. (14) */
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : spd_fail)
     for (int c = 0; c < np; ++c) {
-        double *bt = s->bt + (size_t)c * 9;
-        double *D = s->D + (size_t)c * 81;
-        for (int i = 0; i < 9; ++i) bt[i] = s->bp[(size_t)c * 9 + i];
-        for (int i = 0; i < 81; ++i) D[i] = s->U[(size_t)c * 81 + i];
+        double *bt = s->bt + (size_t)c * dp;
+        double *D = s->D + (size_t)c * dp * dp;
+        for (int i = 0; i < dp; ++i) bt[i] = s->bp[(size_t)c * dp + i];
+        for (int i = 0; i < dp * dp; ++i) D[i] = s->U[(size_t)c * dp * dp + i];
         for (int64_t q = s->cam_ptr[c]; q < s->cam_ptr[c + 1]; ++q) {
             int64_t o = s->cam_obs[q];
             int l = s->lm[o];
-            const double *w = s->W + o * 27, *Vi = s->Vinv + (size_t)l * 9, *bl = s->bl + (size_t)l * 3;
-            double vb[3], WV[27];
+            const double *w = s->W + o * 3 * dp, *Vi = s->Vinv + (size_t)l * 9, *bl = s->bl + (size_t)l * 3;
+            double vb[3], WV[DPMAX * 3];
             for (int i = 0; i < 3; ++i) vb[i] = Vi[i * 3 + 0] * bl[0] + Vi[i * 3 + 1] * bl[1] + Vi[i * 3 + 2] * bl[2];
-            for (int i = 0; i < 9; ++i) bt[i] -= w[i * 3 + 0] * vb[0] + w[i * 3 + 1] * vb[1] + w[i * 3 + 2] * vb[2];
-            for (int i = 0; i < 9; ++i)
+            for (int i = 0; i < dp; ++i) bt[i] -= w[i * 3 + 0] * vb[0] + w[i * 3 + 1] * vb[1] + w[i * 3 + 2] * vb[2];
+            for (int i = 0; i < dp; ++i)
                 for (int j = 0; j < 3; ++j)
                     WV[i * 3 + j] = w[i * 3 + 0] * Vi[0 * 3 + j] + w[i * 3 + 1] * Vi[1 * 3 + j] + w[i * 3 + 2] * Vi[2 * 3 + j];
-            for (int i = 0; i < 9; ++i)
-                for (int j = 0; j < 9; ++j)
-                    D[i * 9 + j] -= WV[i * 3 + 0] * w[j * 3 + 0] + WV[i * 3 + 1] * w[j * 3 + 1] + WV[i * 3 + 2] * w[j * 3 + 2];
+            for (int i = 0; i < dp; ++i)
+                for (int j = 0; j < dp; ++j)
+                    D[i * dp + j] -= WV[i * 3 + 0] * w[j * 3 + 0] + WV[i * 3 + 1] * w[j * 3 + 1] + WV[i * 3 + 2] * w[j * 3 + 2];
         }
-        double *L = s->Dchol + (size_t)c * 81;
-        memcpy(L, D, sizeof(double) * 81);
-        if (chol(L, 9) != 0) spd_fail = 1;
+        double *L = s->Dchol + (size_t)c * dp * dp;
+        memcpy(L, D, sizeof(double) * dp * dp);
+        if (chol(L, dp) != 0) spd_fail = 1;
     }
     if (spd_fail) { or_free(s); *status = OR_ERR_NOT_SPD; return NULL; }
     return s;
 }
 
-int or_n(const or_sys *s) { return 9 * s->np; }
-void or_get_rhs(const or_sys *s, double *bt) { memcpy(bt, s->bt, sizeof(double) * 9 * (size_t)s->np); }
+or_sys *or_build(int np, int nl, int64_t m, const int *cam, const int *lm, const double *Jp,
+                 const double *Jl, const double *r, double lambda, int *status) {
+    return or_build_dp(np, nl, m, cam, lm, Jp, Jl, r, lambda, 9, status);
+}
+
+int or_dp(const or_sys *s) { return s->dp; }
+int or_n(const or_sys *s) { return s->dp * s->np; }
+void or_get_rhs(const or_sys *s, double *bt) { memcpy(bt, s->bt, sizeof(double) * s->dp * (size_t)s->np); }
 void or_get_bp_bl(const or_sys *s, double *bp, double *bl) {
-    memcpy(bp, s->bp, sizeof(double) * 9 * (size_t)s->np);
+    memcpy(bp, s->bp, sizeof(double) * s->dp * (size_t)s->np);
     memcpy(bl, s->bl, sizeof(double) * 3 * (size_t)s->nl);
 }
-void or_get_U(const or_sys *s, double *U) { memcpy(U, s->U, sizeof(double) * 81 * (size_t)s->np); }
+void or_get_U(const or_sys *s, double *U) { memcpy(U, s->U, sizeof(double) * s->dp * s->dp * (size_t)s->np); }
 void or_get_Vinv(const or_sys *s, double *V) { memcpy(V, s->Vinv, sizeof(double) * 9 * (size_t)s->nl); }
-void or_get_Dblocks(const or_sys *s, double *D) { memcpy(D, s->D, sizeof(double) * 81 * (size_t)s->np); }
+void or_get_Dblocks(const or_sys *s, double *D) { memcpy(D, s->D, sizeof(double) * s->dp * s->dp * (size_t)s->np); }
 
 /* ------------------------------------------------------------------ operators */
 
 /* y = S v with S = U_lambda - W V_lambda^-1 W^T (eq. (14)), applied factor by factor. */
 void or_schur_matvec(const or_sys *s, const double *v, double *y) {
-    int np = s->np, nl = s->nl;
+    int np = s->np, nl = s->nl, dp = s->dp;
     double *h = (double *)malloc(sizeof(double) * 3 * (size_t)nl);
     /* h = V^-1 (W^T v) */
 #pragma omp parallel for schedule(dynamic, 256)
@@ -377,9 +388,9 @@ void or_schur_matvec(const or_sys *s, const double *v, double *y) {
         double g[3] = {0, 0, 0};
         for (int64_t q = s->lm_ptr[l]; q < s->lm_ptr[l + 1]; ++q) {
             int64_t o = s->lm_obs[q];
-            const double *w = s->W + o * 27, *vc = v + (size_t)s->cam[o] * 9;
+            const double *w = s->W + o * 3 * dp, *vc = v + (size_t)s->cam[o] * dp;
             for (int j = 0; j < 3; ++j)
-                for (int i = 0; i < 9; ++i) g[j] += w[i * 3 + j] * vc[i];
+                for (int i = 0; i < dp; ++i) g[j] += w[i * 3 + j] * vc[i];
         }
         const double *Vi = s->Vinv + (size_t)l * 9;
         for (int i = 0; i < 3; ++i) h[(size_t)l * 3 + i] = Vi[i * 3 + 0] * g[0] + Vi[i * 3 + 1] * g[1] + Vi[i * 3 + 2] * g[2];
@@ -387,35 +398,36 @@ void or_schur_matvec(const or_sys *s, const double *v, double *y) {
     /* y = U_lambda v - W h */
 #pragma omp parallel for schedule(dynamic, 16)
     for (int c = 0; c < np; ++c) {
-        const double *U = s->U + (size_t)c * 81, *vc = v + (size_t)c * 9;
-        double yc[9];
-        for (int i = 0; i < 9; ++i) {
+        const double *U = s->U + (size_t)c * dp * dp, *vc = v + (size_t)c * dp;
+        double yc[DPMAX];
+        for (int i = 0; i < dp; ++i) {
             double a = 0.0;
-            for (int j = 0; j < 9; ++j) a += U[i * 9 + j] * vc[j];
+            for (int j = 0; j < dp; ++j) a += U[i * dp + j] * vc[j];
             yc[i] = a;
         }
         for (int64_t q = s->cam_ptr[c]; q < s->cam_ptr[c + 1]; ++q) {
             int64_t o = s->cam_obs[q];
-            const double *w = s->W + o * 27, *hl = h + (size_t)s->lm[o] * 3;
-            for (int i = 0; i < 9; ++i) yc[i] -= w[i * 3 + 0] * hl[0] + w[i * 3 + 1] * hl[1] + w[i * 3 + 2] * hl[2];
+            const double *w = s->W + o * 3 * dp, *hl = h + (size_t)s->lm[o] * 3;
+            for (int i = 0; i < dp; ++i) yc[i] -= w[i * 3 + 0] * hl[0] + w[i * 3 + 1] * hl[1] + w[i * 3 + 2] * hl[2];
         }
-        for (int i = 0; i < 9; ++i) y[(size_t)c * 9 + i] = yc[i];
+        for (int i = 0; i < dp; ++i) y[(size_t)c * dp + i] = yc[i];
     }
     free(h);
 }
 
-/* z = D(S)^-1 r, one 9x9 Cholesky solve per pose; with a low-rank term set by
+/* z = D(S)^-1 r, one dp x dp Cholesky solve per pose; with a low-rank term set by
  * or_set_lowrank, z = D(S)^-1 r + U (U^T r). */
 void or_precond_apply(const or_sys *s, const double *r, double *z) {
+    const int dp = s->dp;
 #pragma omp parallel for schedule(static)
     for (int c = 0; c < s->np; ++c) {
-        double x[9];
-        for (int i = 0; i < 9; ++i) x[i] = r[(size_t)c * 9 + i];
-        chol_solve(s->Dchol + (size_t)c * 81, 9, x);
-        for (int i = 0; i < 9; ++i) z[(size_t)c * 9 + i] = x[i];
+        double x[DPMAX];
+        for (int i = 0; i < dp; ++i) x[i] = r[(size_t)c * dp + i];
+        chol_solve(s->Dchol + (size_t)c * dp * dp, dp, x);
+        for (int i = 0; i < dp; ++i) z[(size_t)c * dp + i] = x[i];
     }
     if (s->Ulr) {
-        int n = 9 * s->np, k = s->lr_rank;
+        int n = dp * s->np, k = s->lr_rank;
         double t[64];
         for (int a = 0; a < k; ++a) t[a] = 0.0;
         for (int i = 0; i < n; ++i)
@@ -435,7 +447,7 @@ int or_set_lowrank(or_sys *s, const double *U, int rank) {
     s->lr_rank = 0;
     if (!U) return OR_OK;
     if (rank < 1 || rank > 64) return OR_ERR_INVALID;
-    size_t cnt = (size_t)9 * s->np * rank;
+    size_t cnt = (size_t)s->dp * s->np * rank;
     s->Ulr = (double *)malloc(sizeof(double) * cnt);
     memcpy(s->Ulr, U, sizeof(double) * cnt);
     s->lr_rank = rank;
@@ -450,9 +462,9 @@ void or_back_substitute(const or_sys *s, const double *dxp, double *dxl) {
         for (int j = 0; j < 3; ++j) g[j] = s->bl[(size_t)l * 3 + j];
         for (int64_t q = s->lm_ptr[l]; q < s->lm_ptr[l + 1]; ++q) {
             int64_t o = s->lm_obs[q];
-            const double *w = s->W + o * 27, *vc = dxp + (size_t)s->cam[o] * 9;
+            const double *w = s->W + o * 3 * s->dp, *vc = dxp + (size_t)s->cam[o] * s->dp;
             for (int j = 0; j < 3; ++j)
-                for (int i = 0; i < 9; ++i) g[j] += w[i * 3 + j] * vc[i];
+                for (int i = 0; i < s->dp; ++i) g[j] += w[i * 3 + j] * vc[i];
         }
         const double *Vi = s->Vinv + (size_t)l * 9;
         for (int i = 0; i < 3; ++i)
@@ -467,7 +479,7 @@ static double dot(const double *a, const double *b, int n) {
 }
 
 static double true_rel_residual(const or_sys *s, const double *x) {
-    int n = 9 * s->np;
+    int n = s->dp * s->np;
     double *y = (double *)malloc(sizeof(double) * (size_t)n);
     or_schur_matvec(s, x, y);
     double num = 0.0, den = 0.0;
@@ -486,7 +498,7 @@ static double true_rel_residual(const or_sys *s, const double *x) {
  * trace (nullable, length imax) receives |r_{i+1}| / |r_0| per iteration. */
 int or_pcg(const or_sys *s, const double *x0, double *x, double eps, int imax, or_stats *st,
            double *trace) {
-    int n = 9 * s->np;
+    int n = s->dp * s->np;
     double *r = (double *)malloc(sizeof(double) * n), *Z = (double *)malloc(sizeof(double) * n);
     double *P = (double *)malloc(sizeof(double) * n), *Q = (double *)malloc(sizeof(double) * n);
     memset(st, 0, sizeof(*st));
@@ -539,7 +551,7 @@ typedef struct {
  * receives the direction history; the number of columns is stats.history_cols. */
 int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, double eps, int imax,
            int q_mode, or_stats *st, double *trace, double *P_out, int64_t P_cap) {
-    int n = 9 * s->np, np = s->np;
+    int n = s->dp * s->np, np = s->np, dp = s->dp;
     memset(st, 0, sizeof(*st));
     if (N < 1 || N > np || !(tau >= 0.0)) { st->status = OR_ERR_INVALID; return OR_ERR_INVALID; }
     int *group = (int *)malloc(sizeof(int) * np);
@@ -613,7 +625,7 @@ int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, doub
         double *Z = (double *)calloc((size_t)n * kn, sizeof(double));
         if (is_multi) {
             for (int c = 0; c < np; ++c)
-                for (int q = 0; q < 9; ++q) Z[(size_t)group[c] * n + (size_t)c * 9 + q] = z[(size_t)c * 9 + q];
+                for (int q = 0; q < dp; ++q) Z[(size_t)group[c] * n + (size_t)c * dp + q] = z[(size_t)c * dp + q];
         } else {
             memcpy(Z, z, sizeof(double) * n);
         }
@@ -647,7 +659,7 @@ int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, doub
                     /* columns of Z are zero outside their subset: sum only the nonzero rows */
                     for (int c = 0; c < np; ++c) {
                         double sacc = 0.0;
-                        for (int q = 0; q < 9; ++q) sacc += Qa[(size_t)c * 9 + q] * z[(size_t)c * 9 + q];
+                        for (int q = 0; q < dp; ++q) sacc += Qa[(size_t)c * dp + q] * z[(size_t)c * dp + q];
                         Phi[(size_t)a * kn + group[c]] += sacc;
                     }
                 } else {

@@ -56,8 +56,13 @@ class Problem:
         return int(self.obs_cam.shape[0])
 
     @property
+    def d_p(self) -> int:
+        """Pose dimension: 9 (extrinsics and intrinsics) or 6 (extrinsics only)."""
+        return int(self.J_p.shape[-1])
+
+    @property
     def n(self) -> int:
-        return 9 * self.n_cams
+        return self.d_p * self.n_cams
 
 
 # ---------------------------------------------------------------------------
@@ -425,6 +430,14 @@ def schur_block_density(p: Problem) -> float:
 # outer Levenberg-Marquardt loop support (Sec. 4.1): moving the state by a solved
 # step and linearising again.  No solver arithmetic lives here; the step comes from
 # whichever solver the caller runs.
+
+
+def extrinsics_only(p: Problem) -> Problem:
+    """The same problem with the intrinsics (f, k1, k2) held fixed: poses of dimension
+    d_p = 6 (Sec. 3.1), i.e. the first six columns of every pose block."""
+    return Problem(name=p.name + "_dp6", seed=p.seed, n_cams=p.n_cams, n_lms=p.n_lms, obs_cam=p.obs_cam,
+                   obs_lm=p.obs_lm, J_p=np.ascontiguousarray(p.J_p[:, :, :6]), J_l=p.J_l, r=p.r, lam=p.lam,
+                   cams=p.cams, points=p.points, u_obs=p.u_obs, info=dict(p.info, d_p=6))
 
 
 def camera_array(cams: Dict[str, np.ndarray]) -> np.ndarray:

@@ -114,12 +114,12 @@ def zr_apply(S, v, nc):
 
 
 MUTANTS = {
-    "no_U_damping": ("for (int i = 0; i < 9; ++i) U[i * 9 + i] += lambda * U[i * 9 + i];", ""),
+    "no_U_damping": ("for (int i = 0; i < dp; ++i) U[i * dp + i] += lambda * U[i * dp + i];", ""),
     "no_V_damping": ("for (int i = 0; i < 3; ++i) V[i * 3 + i] += lambda * V[i * 3 + i];", ""),
     "rhs_sign": ("bt[i] -= w[i * 3 + 0] * vb[0]", "bt[i] += w[i * 3 + 0] * vb[0]"),
     "matvec_transposed_W": ("g[j] += w[i * 3 + j] * vc[i];\n        }\n        const double *Vi = s->Vinv + (size_t)l * 9;\n        for (int i = 0; i < 3; ++i) h[",
                             "g[j] += w[(i % 3) * 3 + (j % 3)] * vc[i];\n        }\n        const double *Vi = s->Vinv + (size_t)l * 9;\n        for (int i = 0; i < 3; ++i) h["),
-    "matvec_drop_U": ("for (int j = 0; j < 9; ++j) a += U[i * 9 + j] * vc[j];", "(void)U;"),
+    "matvec_drop_U": ("for (int j = 0; j < dp; ++j) a += U[i * dp + j] * vc[j];", "(void)U;"),
     "matvec_Vinv_transposed_index": ("h[(size_t)l * 3 + i] = Vi[i * 3 + 0] * g[0] + Vi[i * 3 + 1] * g[1] + Vi[i * 3 + 2] * g[2];",
                                      "h[(size_t)l * 3 + i] = Vi[0 * 3 + i] * g[0] + Vi[0 * 3 + i] * g[1] + Vi[2 * 3 + i] * g[2];"),
     "pcg_beta_sign": ("for (int i = 0; i < n; ++i) P[i] = Z[i] - beta * P[i];",
@@ -132,13 +132,13 @@ MUTANTS = {
                            "for (int j = nb - 1; j < nb; ++j) {\n            blk_t *Bj = &H[j];"),
     "mcg_beta_without_pinv": ("for (int b = 0; b < kj; ++b) t += Bj->Dp[a * kj + b] * Phi[(size_t)b * kn + p];",
                               "t = Phi[(size_t)a * kn + p];"),
-    "mcg_split_wrong_group": ("Z[(size_t)group[c] * n + (size_t)c * 9 + q] = z[(size_t)c * 9 + q];",
-                              "Z[(size_t)((group[c] + 1) % kn) * n + (size_t)c * 9 + q] = z[(size_t)c * 9 + q];"),
+    "mcg_split_wrong_group": ("Z[(size_t)group[c] * n + (size_t)c * dp + q] = z[(size_t)c * dp + q];",
+                              "Z[(size_t)((group[c] + 1) % kn) * n + (size_t)c * dp + q] = z[(size_t)c * dp + q];"),
     "pinv_rotation_sign": ("a[r * k + p] = c * arp - s * arq;", "a[r * k + p] = c * arp + s * arq;"),
     "pinv_keeps_null_space": ("if (!(fabs(l) > thr)) continue;", "if (l == 0.0) l = 1e-300;"),
     "precond_lower_only": ("for (int i = k - 1; i >= 0; --i) {\n        double s = x[i];",
                            "for (int i = -1; i >= 0; --i) {\n        double s = x[i];"),
-    "D_missing_schur_term": ("D[i * 9 + j] -= WV[i * 3 + 0] * w[j * 3 + 0]", "D[i * 9 + j] -= 0.0 * WV[i * 3 + 0] * w[j * 3 + 0]"),
+    "D_missing_schur_term": ("D[i * dp + j] -= WV[i * 3 + 0] * w[j * 3 + 0]", "D[i * dp + j] -= 0.0 * WV[i * 3 + 0] * w[j * 3 + 0]"),
 }
 
 

@@ -24,11 +24,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 def dense_system(p, lam=None):
     """Dense H = J^T J + lam diag(J^T J) and b = J^T r0 (eq. (6)-(12) with Marquardt D)."""
     lam = p.lam if lam is None else lam
-    m, n, nl = p.n_obs, p.n, p.n_lms
+    m, n, nl, dp = p.n_obs, p.n, p.n_lms, p.d_p
     J = np.zeros((2 * m, n + 3 * nl))
     for o in range(m):
         c, l = int(p.obs_cam[o]), int(p.obs_lm[o])
-        J[2 * o:2 * o + 2, 9 * c:9 * c + 9] = p.J_p[o]
+        J[2 * o:2 * o + 2, dp * c:dp * c + dp] = p.J_p[o]
         J[2 * o:2 * o + 2, n + 3 * l:n + 3 * l + 3] = p.J_l[o]
     JtJ = J.T @ J
     H = JtJ + lam * np.diag(np.diag(JtJ))
@@ -48,11 +48,15 @@ TINY = [dict(n_cams=3, n_lms=12, seed=0), dict(n_cams=4, n_lms=30, seed=1),
         dict(n_cams=5, n_lms=40, seed=2, c_hi=5), dict(n_cams=6, n_lms=25, seed=7, c_hi=3)]
 
 
-@pytest.fixture(params=range(len(TINY)), ids=lambda i: f"tiny{i}")
+@pytest.fixture(params=[(i, dp) for dp in (9, 6) for i in range(len(TINY))],
+                ids=lambda a: f"tiny{a[0]}_dp{a[1]}")
 def tiny_case(request):
-    kw = dict(TINY[request.param])
-    shuffle = request.param % 2 == 1
+    i, dp = request.param
+    kw = dict(TINY[i])
+    shuffle = i % 2 == 1
     p = synth.tiny(shuffle=shuffle, **kw)
+    if dp == 6:
+        p = synth.extrinsics_only(p)
     H, b, n = dense_system(p)
     S, bt = dense_schur(H, b, n)
     return p, H, b, n, S, bt
@@ -76,8 +80,9 @@ def test_normal_equation_blocks_match_dense(tiny_case):
     p, H, b, n, S, bt = tiny_case
     o = oracle.System(p)
     U = o.U_blocks()
+    dp = p.d_p
     for c in range(p.n_cams):
-        assert rel(U[c], H[9 * c:9 * c + 9, 9 * c:9 * c + 9]) < 1e-13
+        assert rel(U[c], H[dp * c:dp * c + dp, dp * c:dp * c + dp]) < 1e-13
     Vi = o.Vinv_blocks()
     for l in range(p.n_lms):
         blk = H[n + 3 * l:n + 3 * l + 3, n + 3 * l:n + 3 * l + 3]
@@ -86,7 +91,7 @@ def test_normal_equation_blocks_match_dense(tiny_case):
     assert rel(bp, b[:n]) < 1e-13 and rel(bl, b[n:]) < 1e-13
     D = o.D_blocks()
     for c in range(p.n_cams):
-        assert rel(D[c], S[9 * c:9 * c + 9, 9 * c:9 * c + 9]) < 1e-12
+        assert rel(D[c], S[dp * c:dp * c + dp, dp * c:dp * c + dp]) < 1e-12
 
 
 def test_schur_symmetric_positive_definite(tiny_case):
@@ -149,9 +154,11 @@ def _scipy_pcg_iterates(o, k):
     return its
 
 
-@pytest.mark.parametrize("k", [1, 5, 25])
-def test_pcg_matches_textbook_cg(k):
+@pytest.mark.parametrize("k,dp", [(1, 9), (5, 9), (25, 9), (5, 6), (25, 6)])
+def test_pcg_matches_textbook_cg(k, dp):
     p = synth.config0(seed=1)
+    if dp == 6:
+        p = synth.extrinsics_only(p)
     o = oracle.System(p)
     ref = _scipy_pcg_iterates(o, k)
     x, st = o.pcg(eps=0.0, imax=k)
@@ -205,8 +212,10 @@ def test_pcg_zero_rhs_and_warm_start():
 # ---------------------------------------------------------------- Algorithm 2
 
 
-def test_mcg_single_subset_is_pcg():
-    o = oracle.System(synth.config0(seed=3))
+@pytest.mark.parametrize("dp", [9, 6])
+def test_mcg_single_subset_is_pcg(dp):
+    p = synth.config0(seed=3)
+    o = oracle.System(p if dp == 9 else synth.extrinsics_only(p))
     for k in (3, 20):
         xp, _ = o.pcg(eps=0.0, imax=k)
         xm, st = o.mcg(1, 10.0, eps=0.0, imax=k)
@@ -225,10 +234,12 @@ def test_mcg_tau_zero_is_pcg():
     assert np.linalg.norm(xm - xp) <= 1e-9 * np.linalg.norm(xp)
 
 
-@pytest.mark.parametrize("N,tau", [(3, 10.0), (6, 3.0)])
-def test_mcg_galerkin_projection(N, tau):
+@pytest.mark.parametrize("N,tau,dp", [(3, 10.0, 9), (6, 3.0, 9), (3, 10.0, 6)])
+def test_mcg_galerkin_projection(N, tau, dp):
     """Block CG with full conjugation: x_m = x0 + P (P^T S P)^+ P^T r0 and P^T r_m = 0."""
     p = synth.tiny(n_cams=8, n_lms=120, seed=4, c_hi=5)
+    if dp == 6:
+        p = synth.extrinsics_only(p)
     o = oracle.System(p)
     S = o.dense_S()
     bt = o.rhs()
