@@ -12,9 +12,10 @@
  *  - All array arguments are DEVICE pointers (HIP, the device current at
  *    ba_build_system) unless a comment says "host".  Arrays are dense,
  *    row-major C order, FP64 unless stated.
- *  - A pose has d_p = 9 parameters (rotation increment, translation, focal,
- *    two radial terms); the camera space has n = 9 * n_cams entries, ordered
- *    camera by camera.
+ *  - A pose has d_p parameters (Sec. 3.1): 9 (rotation increment,
+ *    translation, focal, two radial terms) or 6 (rotation increment and
+ *    translation, intrinsics fixed); the camera space has n = d_p * n_cams
+ *    entries, ordered camera by camera.
  *  - Every call runs on the stream given to ba_build_system and returns
  *    after its work is complete (the library synchronises that stream).
  *  - Status codes: 0 success, > 0 warning, < 0 error (ba_status).  No
@@ -40,7 +41,7 @@ typedef enum {
     BA_OK = 0,
     BA_MAXITER = 1,            /* warning: max_iter reached; x holds the last iterate */
     BA_ERR_INVALID_ARG = -1,   /* null pointer, bad size, index out of range, duplicate
-                                  (camera, landmark) pair, d_p != 9, N outside [1, n_cams] */
+                                  (camera, landmark) pair, d_p not 6 or 9, N outside [1, n_cams] */
     BA_ERR_NONFINITE = -2,     /* NaN/Inf in J, r or lambda */
     BA_ERR_NOT_SPD = -3,       /* a V_lambda or D(S) block has a Cholesky pivot <= 0
                                   (e.g. a camera or landmark with no observation) */
@@ -62,11 +63,12 @@ typedef struct {
     int32_t n_cams;          /* n_p >= 1 */
     int32_t n_lms;           /* n_l >= 1 */
     int64_t n_obs;           /* m >= 1 */
-    int32_t d_p;             /* must be 9 */
+    int32_t d_p;             /* pose dimension (Sec. 3.1): 9 (extrinsics and intrinsics) or 6 (extrinsics
+                                only); the explicit S, batches and the learned preconditioner need 9 */
     int32_t reserved0;
     const int32_t *obs_cam;  /* device [m], in [0, n_cams) */
     const int32_t *obs_lm;   /* device [m], in [0, n_lms) */
-    const double *J_p;       /* device [m][2][9]: d r_o / d (pose of obs_cam[o]) */
+    const double *J_p;       /* device [m][2][d_p]: d r_o / d (pose of obs_cam[o]) */
     const double *J_l;       /* device [m][2][3]: d r_o / d (landmark obs_lm[o]) */
     const double *r;         /* device [m][2]: residuals r_o at the linearisation point */
     double lambda;           /* >= 0 */
@@ -151,7 +153,7 @@ ba_status ba_precond_apply(ba_system *sys, const double *r, double *z);
 /* Copies b~ (eq. (15)) into bt: device [n]. */
 ba_status ba_get_rhs(ba_system *sys, double *bt);
 
-/* Copies the 9x9 blocks of D(S) (row-major, camera by camera) into D: device [n_cams][81]. */
+/* Copies the d_p x d_p blocks of D(S) (row-major, camera by camera) into D: device [n_cams][d_p][d_p]. */
 ba_status ba_get_precond_blocks(ba_system *sys, double *D);
 
 /* Block-Jacobi PCG, Algorithm 1, on S dx_p = -b~.  x0: device [n] or NULL (= 0);

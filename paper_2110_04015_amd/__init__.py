@@ -123,11 +123,13 @@ class System:
                  max_slots=0, max_tiles=0, store_fp32=False, store_bf16=False, explicit_schur=False):
         torch = _torch()
         m = int(obs_cam.numel())
+        # pose dimension (Sec. 3.1): 9, or 6 for extrinsics only, from the size of J_p
+        dp = int(J_p.numel()) // max(2 * m, 1)
         d = _lib.ProblemDesc()
-        d.n_cams, d.n_lms, d.n_obs, d.d_p = int(n_cams), int(n_lms), m, 9
+        d.n_cams, d.n_lms, d.n_obs, d.d_p = int(n_cams), int(n_lms), m, dp
         d.obs_cam = _dev_ptr(obs_cam, torch.int32, m, "obs_cam")
         d.obs_lm = _dev_ptr(obs_lm, torch.int32, m, "obs_lm")
-        d.J_p = _dev_ptr(J_p, torch.float64, m * 18, "J_p")
+        d.J_p = _dev_ptr(J_p, torch.float64, m * 2 * dp, "J_p")
         d.J_l = _dev_ptr(J_l, torch.float64, m * 6, "J_l")
         d.r = _dev_ptr(r, torch.float64, m * 2, "r")
         d.lam = float(lam)
@@ -142,7 +144,8 @@ class System:
                "ba_build_system")
         self.h = h
         self.n_cams, self.n_lms, self.n_obs = int(n_cams), int(n_lms), m
-        self.n = 9 * self.n_cams
+        self.d_p = dp
+        self.n = dp * self.n_cams
 
     @classmethod
     def from_problem(cls, p, device="cuda", **kw):
@@ -161,6 +164,7 @@ class System:
         obj._stream = stream
         obj.device = device
         obj.n_cams, obj.n_lms, obj.n_obs = int(n_cams), int(n_lms), int(n_obs)
+        obj.d_p = 9
         obj.n = 9 * obj.n_cams
         return obj
 
@@ -234,8 +238,8 @@ class System:
 
     def precond_blocks(self):
         torch = _torch()
-        D = self._new(self.n_cams, 9, 9)
-        _check(lib().ba_get_precond_blocks(self.h, _dev_ptr(D, torch.float64, self.n_cams * 81, "D")),
+        D = self._new(self.n_cams, self.d_p, self.d_p)
+        _check(lib().ba_get_precond_blocks(self.h, _dev_ptr(D, torch.float64, self.n_cams * self.d_p * self.d_p, "D")),
                "ba_get_precond_blocks")
         return D
 
@@ -243,7 +247,7 @@ class System:
         """New values for the same observations (ba_update_system): relinearisation or a new lambda."""
         torch = _torch()
         m = self.n_obs
-        _check(lib().ba_update_system(self.h, _dev_ptr(J_p, torch.float64, m * 18, "J_p"),
+        _check(lib().ba_update_system(self.h, _dev_ptr(J_p, torch.float64, m * 2 * self.d_p, "J_p"),
                                       _dev_ptr(J_l, torch.float64, m * 6, "J_l"),
                                       _dev_ptr(r, torch.float64, m * 2, "r"), float(lam)), "ba_update_system")
 

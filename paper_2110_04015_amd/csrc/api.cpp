@@ -153,6 +153,7 @@ SchurArgs schur_args(ba_system *s, int precision) {
     a.dU = s->dU;
     a.np = s->np;
     a.done = nullptr;
+    a.dp = s->dp;
     return a;
 }
 
@@ -215,13 +216,13 @@ ba_status ensure_precision(ba_system *s, int precision) {
     if (precision == 1 && !s->J32) {
         ba_status st = dalloc(&s->J32, (size_t)nslots * 24);
         if (st != BA_OK) return st;
-        launch_convert(s->J64, nslots, s->J32, nullptr, s->stream);
+        launch_convert(s->J64, nslots, s->J32, nullptr, s->stream, s->dp);
         HIPCHK(hipGetLastError());
     }
     if (precision == 2 && !s->J16) {
         ba_status st = dalloc(&s->J16, (size_t)nslots * 24);
         if (st != BA_OK) return st;
-        launch_convert(s->J64, nslots, nullptr, s->J16, s->stream);
+        launch_convert(s->J64, nslots, nullptr, s->J16, s->stream, s->dp);
         HIPCHK(hipGetLastError());
     }
     return BA_OK;
@@ -262,11 +263,11 @@ ba_status ensure_multi(ba_system *s, int N, bool plan = true) {
     int dev = 0, lds_max = 65536;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t lds_need = (size_t)(mp.max_out * 9 + 6 * kTile) * sizeof(double);
+    const size_t lds_need = (size_t)(mp.max_out * s->dp + 6 * kTile) * sizeof(double);
     if (lds_need > (size_t)lds_max)
         return fail(BA_ERR_UNSUPPORTED, "multidirectional product: a tile touches " + std::to_string(mp.max_out) +
                                             " (camera, subset) pairs; at most " +
-                                            std::to_string(((size_t)lds_max / sizeof(double) - 6 * kTile) / 9) +
+                                            std::to_string(((size_t)lds_max / sizeof(double) - 6 * kTile) / s->dp) +
                                             " fit in LDS");
     DevMulti &m = s->multi;
     hipStream_t q = s->stream;
@@ -283,7 +284,7 @@ ba_status ensure_multi(ba_system *s, int N, bool plan = true) {
     if ((st = upload(&m.part_dst, mp.part_dst, q)) != BA_OK) return st;
     if ((st = upload(&m.group, grp, q)) != BA_OK) return st;
     if ((st = upload(&m.chunk_seg, mp.chunk_seg, q)) != BA_OK) return st;
-    if ((st = dalloc(&m.partial, (size_t)std::max<int64_t>(mp.n_part, 1) * 9)) != BA_OK) return st;
+    if ((st = dalloc(&m.partial, (size_t)std::max<int64_t>(mp.n_part, 1) * s->dp)) != BA_OK) return st;
     m.N = N;
     m.n_chunks = mp.n_chunks;
     m.max_out = mp.max_out;
@@ -316,6 +317,7 @@ MultiArgs multi_args(ba_system *s, int precision) {
     a.group = s->multi.group;
     a.np = s->np;
     a.N = s->multi.N;
+    a.dp = s->dp;
     return a;
 }
 
@@ -379,7 +381,7 @@ ba_status init_scalars(ba_system *s, double *sc) {
 
 // |-b~ - S x| / |b~| in FP64 (tmp: 2n doubles, red: partial sums)
 ba_status true_rel_residual(ba_system *s, const double *x, double *tmp, double *red, double *sc, double *out) {
-    const int64_t n = (int64_t)s->np * 9;
+    const int64_t n = (int64_t)s->np * s->dp;
     matvec(s, schur_args(s, 0), x, tmp);
     launch_pcg_init(n, s->bt, tmp, tmp + n, red, s->stream);
     launch_finalize(red, 1, sc + SC_COUNT - 1, s->stream);
@@ -467,7 +469,7 @@ static ba_status fill_values(ba_system *s, const double *J_p, const double *J_l,
     const int64_t m = s->m;
     const int64_t nslots = s->plan.n_tiles * kTile;
     HIPCHK(hipMemsetAsync(s->status, 0, sizeof(int32_t), q));
-    launch_check_finite(J_p, m * 18, s->status, q);
+    launch_check_finite(J_p, m * 2 * s->dp, s->status, q);
     launch_check_finite(J_l, m * 6, s->status, q);
     launch_check_finite(r, m * 2, s->status, q);
     int32_t hst = 0;
@@ -475,11 +477,11 @@ static ba_status fill_values(ba_system *s, const double *J_p, const double *J_l,
     HIPCHK(hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q));
     HIPCHK(hipStreamSynchronize(q));
     if (hst & kStatusNonfinite) return fail(BA_ERR_NONFINITE, "NaN or Inf in J_p, J_l or r");
-    launch_pack(s->slot_obs, nslots, J_p, J_l, s->J64, s->J32, s->J16, q);
+    launch_pack(s->slot_obs, nslots, J_p, J_l, s->J64, s->J32, s->J16, q, s->dp);
     launch_landmarks(s->nl, s->lmk_first_slot, s->lmk_count, s->slot_obs, J_l, r, s->lambda, s->vinv, s->bl, s->h0,
                      s->status, q);
     launch_cameras(s->np, s->cam_obs_ptr, s->cam_obs, s->obs_lm, s->lmk_store, J_p, J_l, r, s->vinv, s->h0,
-                   s->lambda, s->dU, s->Dblk, s->Dchol, s->bt, s->status, q);
+                   s->lambda, s->dU, s->Dblk, s->Dchol, s->bt, s->status, q, s->dp);
     if (s->bsr_val) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         (void)hipEventCreate(&e0);
@@ -509,7 +511,10 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
     if (!out) return fail(BA_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!d) return fail(BA_ERR_INVALID_ARG, "desc is NULL");
-    if (d->d_p != 9) return fail(BA_ERR_INVALID_ARG, "d_p must be 9");
+    if (d->d_p != 9 && d->d_p != 6) return fail(BA_ERR_INVALID_ARG, "d_p must be 9 or 6");
+    if (d->d_p == 6 && cam_seg) return fail(BA_ERR_UNSUPPORTED, "batches take poses with d_p = 9");
+    if (d->d_p == 6 && opts && opts->explicit_schur)
+        return fail(BA_ERR_UNSUPPORTED, "the explicit S is formed for d_p = 9 only");
     if (d->n_cams < 1 || d->n_lms < 1 || d->n_obs < 1)
         return fail(BA_ERR_INVALID_ARG, "n_cams, n_lms and n_obs must be positive");
     if (!d->obs_cam || !d->obs_lm || !d->J_p || !d->J_l || !d->r)
@@ -528,6 +533,7 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
     s->nl = d->n_lms;
     s->m = d->n_obs;
     s->lambda = d->lambda;
+    s->dp = d->d_p;
     hipStream_t q = s->stream;
     auto bail = [&](ba_status st) {
         (void)hipStreamSynchronize(q);
@@ -571,16 +577,17 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
     if ((st = upload(&s->lmk_order, P.lmk_order, q)) != BA_OK) return bail(st);
     if ((st = upload(&s->lmk_first_slot, P.lmk_first_slot, q)) != BA_OK) return bail(st);
     if ((st = upload(&s->lmk_count, P.lmk_count, q)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->partial, (size_t)std::max<int64_t>(P.n_part, 1) * 9)) != BA_OK) return bail(st);
+    const int dp = s->dp;
+    if ((st = dalloc(&s->partial, (size_t)std::max<int64_t>(P.n_part, 1) * dp)) != BA_OK) return bail(st);
     if ((st = dalloc(&s->J64, (size_t)nslots * 24)) != BA_OK) return bail(st);
     if (opts && opts->store_fp32 && (st = dalloc(&s->J32, (size_t)nslots * 24)) != BA_OK) return bail(st);
     if (opts && opts->store_bf16 && (st = dalloc(&s->J16, (size_t)nslots * 24)) != BA_OK) return bail(st);
     if ((st = dalloc(&s->vinv, (size_t)s->nl * 6)) != BA_OK) return bail(st);
     if ((st = dalloc(&s->bl, (size_t)s->nl * 3)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->dU, (size_t)s->np * 9)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->Dblk, (size_t)s->np * 81)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->Dchol, (size_t)s->np * 45)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->bt, (size_t)s->np * 9)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->dU, (size_t)s->np * dp)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->Dblk, (size_t)s->np * dp * dp)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->Dchol, (size_t)s->np * (dp * (dp + 1) / 2))) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->bt, (size_t)s->np * dp)) != BA_OK) return bail(st);
     if (opts && opts->explicit_schur) {
         // explicit S in block-sparse rows, assembled from the same blocks (Sec. 3.2, 4.1): the
         // pattern and the contribution pairs depend on the observations only
@@ -660,7 +667,8 @@ ba_status ba_system_info(const ba_system *s, int32_t *n_cams, int32_t *n_lms, in
     if (n_chunks) *n_chunks = s->plan.n_chunks;
     // one read of the Jacobian blocks and a camera index per observation, V^-1 per
     // landmark, lambda diag(U), v and y per camera
-    if (matvec_bytes_fp64) *matvec_bytes_fp64 = s->m * (24 * 8 + 4) + (int64_t)s->nl * 6 * 8 + (int64_t)s->np * 9 * 8 * 3;
+    if (matvec_bytes_fp64)
+        *matvec_bytes_fp64 = s->m * ((2 * s->dp + 6) * 8 + 4) + (int64_t)s->nl * 6 * 8 + (int64_t)s->np * s->dp * 8 * 3;
     return BA_OK;
 }
 
@@ -692,7 +700,7 @@ ba_status ba_schur_matmat_grouped(ba_system *s, int32_t N, const double *z, doub
 
 ba_status ba_precond_apply(ba_system *s, const double *r, double *z) {
     if (!s || !r || !z) return fail(BA_ERR_INVALID_ARG, "NULL argument");
-    launch_precond(s->np, s->Dchol, r, z, s->stream);
+    launch_precond(s->np, s->Dchol, r, z, s->stream, s->dp);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return BA_OK;
@@ -700,14 +708,15 @@ ba_status ba_precond_apply(ba_system *s, const double *r, double *z) {
 
 ba_status ba_get_rhs(ba_system *s, double *bt) {
     if (!s || !bt) return fail(BA_ERR_INVALID_ARG, "NULL argument");
-    HIPCHK(hipMemcpyAsync(bt, s->bt, (size_t)s->np * 9 * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(bt, s->bt, (size_t)s->np * s->dp * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return BA_OK;
 }
 
 ba_status ba_get_precond_blocks(ba_system *s, double *D) {
     if (!s || !D) return fail(BA_ERR_INVALID_ARG, "NULL argument");
-    HIPCHK(hipMemcpyAsync(D, s->Dblk, (size_t)s->np * 81 * sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(D, s->Dblk, (size_t)s->np * s->dp * s->dp * sizeof(double), hipMemcpyDeviceToDevice,
+                          s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return BA_OK;
 }
@@ -716,7 +725,7 @@ ba_status ba_back_substitute(ba_system *s, const double *dxp, double *dxl) {
     if (!s || !dxp || !dxl) return fail(BA_ERR_INVALID_ARG, "NULL argument");
     const HostPlan &P = s->plan;
     launch_back_substitute(s->J64, s->meta, s->tile_lmk_base, s->chunk_tile, s->chunk_part, s->part_cam,
-                           P.n_chunks, P.max_used_slots, s->vinv, s->bl, s->lmk_order, dxp, dxl, s->stream);
+                           P.n_chunks, P.max_used_slots, s->vinv, s->bl, s->lmk_order, dxp, dxl, s->stream, s->dp);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return BA_OK;
@@ -748,7 +757,7 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
     const int prec = opts.precision;
     ba_status st = ensure_precision(s, prec);
     if (st != BA_OK) return st;
-    const int64_t n = (int64_t)s->np * 9;
+    const int64_t n = (int64_t)s->np * s->dp;
     hipStream_t q = s->stream;
     if ((st = ensure_vec(s, (size_t)n * 6 + SC_COUNT)) != BA_OK) return st;
     if ((st = ensure_red(s, (size_t)kRedBlocks * 4)) != BA_OK) return st;
@@ -780,7 +789,7 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
         const bool want_trace = stats && stats->trace_res && stats->trace_cap > 0;
         if (want_trace && (st = dalloc(&trace_dev, (size_t)opts.max_iter)) != BA_OK) return st;
         const bool lowrank = opts.precond == 1;
-        launch_precond(s->np, s->Dchol, r, P, q);
+        launch_precond(s->np, s->Dchol, r, P, q, s->dp);
         if (lowrank) launch_lowrank_apply(n, s->Ulr, r, P, nullptr, s->lr_proj, nullptr, nullptr, q);
         SchurArgs sa = schur_args(s, prec);
         sa.done = sc + SC_DONE;
@@ -795,9 +804,9 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
                 launch_pcg_update_xr(n, pdq, sc, x, r, P, Q, prr, q);        // alpha_i, x_{i+1}, r_{i+1}
                 launch_pcg_step_end(prr, sc, opts.eps, opts.max_iter, trace_dev, q);
                 if (!lowrank) {
-                    launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q);  // Z_{i+1}, Phi_i
+                    launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q, s->dp);  // Z_{i+1}, Phi_i
                 } else {                                                     // M^-1 = D^-1 + U U^T
-                    launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q);
+                    launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q, s->dp);
                     launch_lowrank_apply(n, s->Ulr, r, z, Q, s->lr_proj, pphi, sc + SC_DONE, q);
                 }
                 launch_pcg_update_p(n, pphi, sc, z, P, q);                   // beta_i, P_{i+1}
@@ -862,7 +871,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     if (st != BA_OK) return st;
     const bool use_bsr_multi = N > 1 && s->bsr_val && prec == 0 && N <= kMaxBlock;
     if (N > 1 && (st = ensure_multi(s, N, !use_bsr_multi)) != BA_OK) return st;
-    const int64_t n = (int64_t)s->np * 9;
+    const int64_t n = (int64_t)s->np * s->dp;
     hipStream_t q = s->stream;
     const int64_t cap = opts.max_history_cols > 0 ? opts.max_history_cols : 1 + (int64_t)opts.max_iter * N;
     if (cap < 1) return fail(BA_ERR_WORKSPACE, "history capacity must hold at least one column");
@@ -900,7 +909,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     }
     double *r = s->vec, *z = r + n, *tmp = z + n, *sc = tmp + 2 * n;
     double *red = s->red;
-    const int gs = s->np / N;
+    const int gs = (s->np / N) * s->dp;   // rows of one subset (Sec. 3.2 partition)
     const SchurArgs sa = schur_args(s, prec);
     const MultiArgs ma = N > 1 && !use_bsr_multi ? multi_args(s, prec) : MultiArgs();
 
@@ -926,7 +935,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     if (rr0 > 0.0) {
         // P_0 = Z_0 = M^-1 r_0 ; Q_0 = S P_0
         const bool lowrank = opts.precond == 1;
-        launch_precond(s->np, s->Dchol, r, Ph, q);
+        launch_precond(s->np, s->Dchol, r, Ph, q, s->dp);
         if (lowrank) launch_lowrank_apply(n, s->Ulr, r, Ph, nullptr, s->lr_proj, nullptr, nullptr, q);
         matvec(s, sa, Ph, Qh);
         std::vector<int32_t> hoff{0}, hk{1};
@@ -952,7 +961,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             // tau-test scalars before the single read-back of the iteration:
             // t_i = gamma_i^T alpha_i / (r_{i+1}^T D^-1 r_{i+1})
             launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
-            launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q);
+            launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q, s->dp);
             if (lowrank) launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
             launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, N, tau, opts.eps, q);
             if ((st = scalars_post(s, sc)) != BA_OK) return st;
@@ -1048,7 +1057,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
 //   inner solve S d = r to inner_eps |r| (at most max_inner iterations);  x += d.
 static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const double *x0, double *x,
                         const ba_solve_opts &opts, ba_solve_stats *stats) {
-    const int64_t n = (int64_t)s->np * 9;
+    const int64_t n = (int64_t)s->np * s->dp;
     hipStream_t q = s->stream;
     ba_status st = ensure_precision(s, opts.precision);
     if (st != BA_OK) return st;
@@ -1170,6 +1179,11 @@ ba_status ba_mcg_solve(ba_system *s, int32_t N, double tau, const double *x0, do
 
 // ------------------------------------------------------------------ learned preconditioner
 
+// The learned correction's features and factors are defined on 9 x 9 pose blocks.
+static ba_status lowrank_dp_check(const ba_system *s) {
+    return s->dp == 9 ? BA_OK : fail(BA_ERR_UNSUPPORTED, "the learned low-rank preconditioner needs d_p = 9");
+}
+
 static ba_status ensure_lowrank_storage(ba_system *s) {
     ba_status st;
     if (!s->Ulr && (st = dalloc(&s->Ulr, (size_t)s->np * 9 * 8)) != BA_OK) return st;
@@ -1179,6 +1193,7 @@ static ba_status ensure_lowrank_storage(ba_system *s) {
 
 ba_status ba_lowrank_features(ba_system *s, float *F) {
     if (!s || !F) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (lowrank_dp_check(s) != BA_OK) return BA_ERR_UNSUPPORTED;
     if (!s->degree) {
         std::vector<int32_t> deg;
         covisibility_degree(s->plan, deg);
@@ -1210,6 +1225,7 @@ ba_status ba_mlp_forward(const float *params, const float *F, int32_t rows, floa
 
 ba_status ba_set_lowrank_from_mlp(ba_system *s, const float *out) {
     if (!s || !out) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (lowrank_dp_check(s) != BA_OK) return BA_ERR_UNSUPPORTED;
     ba_status st = ensure_lowrank_storage(s);
     if (st != BA_OK) return st;
     launch_lowrank_U(s->np, s->Dchol, out, s->Ulr, s->stream);
@@ -1220,6 +1236,7 @@ ba_status ba_set_lowrank_from_mlp(ba_system *s, const float *out) {
 
 ba_status ba_set_lowrank_precond(ba_system *s, const double *U) {
     if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    if (U && lowrank_dp_check(s) != BA_OK) return BA_ERR_UNSUPPORTED;
     if (!U) {
         dfree(s->Ulr);
         return BA_OK;
@@ -1241,6 +1258,7 @@ ba_status ba_get_lowrank(ba_system *s, double *U) {
 
 ba_status ba_block_scale(ba_system *s, const double *x, double *y, int32_t transpose) {
     if (!s || !x || !y) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (lowrank_dp_check(s) != BA_OK) return BA_ERR_UNSUPPORTED;
     launch_block_scale(s->np, s->Dchol, x, y, transpose ? 1 : 0, s->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));

@@ -130,6 +130,7 @@ ba_status prepare_mcg(ba_system *s, int N, int precision);
 struct ba_system {
     hipStream_t stream = nullptr;
     int np = 0, nl = 0;
+    int dp = 9;                     // pose dimension d_p (9, or 6 for extrinsics only)
     int64_t m = 0;
     double lambda = 0.0;
     ba::HostPlan plan;

@@ -41,25 +41,31 @@ __device__ __forceinline__ double wave_partials(const double *__restrict__ a, in
     return wave_sum(s);
 }
 
-// z_c = D_c^-1 r_c with the packed lower Cholesky factor (row i holds L[i][0..i])
-__device__ __forceinline__ void chol9_solve(const double *__restrict__ L, const double *r, double *z) {
-    double x[9];
+// z_c = D_c^-1 r_c with the packed lower Cholesky factor of a DP x DP block (row i
+// holds L[i][0..i]; DP (DP + 1) / 2 values)
+template <int DP>
+__device__ __forceinline__ void chol_solve_packed(const double *__restrict__ L, const double *r, double *z) {
+    double x[DP];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < DP; ++i) {
         double s = r[i];
 #pragma unroll
         for (int p = 0; p < i; ++p) s -= L[i * (i + 1) / 2 + p] * x[p];
         x[i] = s / L[i * (i + 1) / 2 + i];
     }
 #pragma unroll
-    for (int i = 8; i >= 0; --i) {
+    for (int i = DP - 1; i >= 0; --i) {
         double s = x[i];
 #pragma unroll
-        for (int p = i + 1; p < 9; ++p) s -= L[p * (p + 1) / 2 + i] * x[p];
+        for (int p = i + 1; p < DP; ++p) s -= L[p * (p + 1) / 2 + i] * x[p];
         x[i] = s / L[i * (i + 1) / 2 + i];
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) z[i] = x[i];
+    for (int i = 0; i < DP; ++i) z[i] = x[i];
+}
+
+__device__ __forceinline__ void chol9_solve(const double *__restrict__ L, const double *r, double *z) {
+    chol_solve_packed<9>(L, r, z);
 }
 
 // Symmetric Jacobi eigendecomposition of the k x k matrix in LDS (k <= 64), with

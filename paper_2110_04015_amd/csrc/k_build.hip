@@ -18,78 +18,84 @@ __global__ void k_check_finite(const double *__restrict__ a, int64_t count, int3
 
 // ---------------------------------------------------------------- packing
 
-// One thread per tile slot: gathers the observation's 2x9 and 2x3 blocks and
-// writes them in the component-pair-major tile layout (plus FP32 / BF16 copies).
-__global__ void k_pack(const int64_t *__restrict__ slot_obs, int64_t nslots, const double *__restrict__ Jp,
-                       const double *__restrict__ Jl, double *__restrict__ J64, float *__restrict__ J32,
-                       uint16_t *__restrict__ J16) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslots) return;
-    int64_t o = slot_obs[s];
-    double v[24];
-    if (o >= 0) {
-        for (int k = 0; k < 18; ++k) v[k] = Jp[o * 18 + k];
-        for (int k = 0; k < 6; ++k) v[18 + k] = Jl[o * 6 + k];
-    } else {
-        for (int k = 0; k < 24; ++k) v[k] = 0.0;
+// Record of one observation in the tile stream: J_p rows 0 and 1 (DP values each),
+// then J_l rows 0 and 1 (3 each): RecordShape<DP>::kVals values, stored as FP64 pairs,
+// FP32 quads or BF16 octets (the last word zero-padded).
+template <int DP>
+__device__ __forceinline__ void write_record(const double *v, int64_t tile, int lane, double *J64, float *J32,
+                                             uint16_t *J16) {
+    typedef RecordShape<DP> R;
+    if (J64) {
+        double2 *d2 = reinterpret_cast<double2 *>(J64);
+        for (int q = 0; q < R::kW64; ++q) d2[(tile * R::kW64 + q) * kTile + lane] = make_double2(v[2 * q], v[2 * q + 1]);
     }
-    int64_t tile = s / kTile;
-    int lane = (int)(s % kTile);
-    double2 *d2 = reinterpret_cast<double2 *>(J64);
-    for (int q = 0; q < 12; ++q) d2[(tile * 12 + q) * kTile + lane] = make_double2(v[2 * q], v[2 * q + 1]);
     if (J32) {
         float4 *f4 = reinterpret_cast<float4 *>(J32);
-        for (int q = 0; q < 6; ++q)
-            f4[(tile * 6 + q) * kTile + lane] =
-                make_float4((float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]);
+        for (int q = 0; q < R::kW32; ++q) {
+            float w[4];
+            for (int h = 0; h < 4; ++h) w[h] = 4 * q + h < R::kVals ? (float)v[4 * q + h] : 0.0f;
+            f4[(tile * R::kW32 + q) * kTile + lane] = make_float4(w[0], w[1], w[2], w[3]);
+        }
     }
     if (J16) {
         uint4 *u4 = reinterpret_cast<uint4 *>(J16);
-        for (int q = 0; q < 3; ++q) {
+        for (int q = 0; q < R::kW16; ++q) {
             uint32_t w[4];
-            for (int h = 0; h < 4; ++h)
-                w[h] = (uint32_t)f32_to_bf16((float)v[8 * q + 2 * h]) |
-                       ((uint32_t)f32_to_bf16((float)v[8 * q + 2 * h + 1]) << 16);
-            u4[(tile * 3 + q) * kTile + lane] = make_uint4(w[0], w[1], w[2], w[3]);
+            for (int h = 0; h < 4; ++h) {
+                const int a = 8 * q + 2 * h;
+                const uint32_t lo = a < R::kVals ? f32_to_bf16((float)v[a]) : 0u;
+                const uint32_t hi = a + 1 < R::kVals ? f32_to_bf16((float)v[a + 1]) : 0u;
+                w[h] = lo | (hi << 16);
+            }
+            u4[(tile * R::kW16 + q) * kTile + lane] = make_uint4(w[0], w[1], w[2], w[3]);
         }
     }
 }
 
+// One thread per tile slot: gathers the observation's 2 x DP and 2 x 3 blocks and
+// writes them in the component-pair-major tile layout (plus FP32 / BF16 copies).
+template <int DP>
+__global__ void k_pack(const int64_t *__restrict__ slot_obs, int64_t nslots, const double *__restrict__ Jp,
+                       const double *__restrict__ Jl, double *__restrict__ J64, float *__restrict__ J32,
+                       uint16_t *__restrict__ J16) {
+    constexpr int NV = RecordShape<DP>::kVals;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslots) return;
+    int64_t o = slot_obs[s];
+    double v[NV];
+    if (o >= 0) {
+        for (int k = 0; k < 2 * DP; ++k) v[k] = Jp[o * 2 * DP + k];
+        for (int k = 0; k < 6; ++k) v[2 * DP + k] = Jl[o * 6 + k];
+    } else {
+        for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    }
+    write_record<DP>(v, s / kTile, (int)(s % kTile), J64, J32, J16);
+}
+
 // Lower-precision copies of an existing FP64 tile stream (one thread per slot).
+template <int DP>
 __global__ void k_convert(const double *__restrict__ J64, int64_t nslots, float *__restrict__ J32,
                           uint16_t *__restrict__ J16) {
+    typedef RecordShape<DP> R;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslots) return;
     int64_t tile = s / kTile;
     int lane = (int)(s % kTile);
     const double2 *d2 = reinterpret_cast<const double2 *>(J64);
-    double v[24];
-    for (int q = 0; q < 12; ++q) {
-        double2 d = d2[(tile * 12 + q) * kTile + lane];
+    double v[R::kVals];
+    for (int q = 0; q < R::kW64; ++q) {
+        double2 d = d2[(tile * R::kW64 + q) * kTile + lane];
         v[2 * q] = d.x;
         v[2 * q + 1] = d.y;
     }
-    if (J32) {
-        float4 *f4 = reinterpret_cast<float4 *>(J32);
-        for (int q = 0; q < 6; ++q)
-            f4[(tile * 6 + q) * kTile + lane] =
-                make_float4((float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]);
-    }
-    if (J16) {
-        uint4 *u4 = reinterpret_cast<uint4 *>(J16);
-        for (int q = 0; q < 3; ++q) {
-            uint32_t w[4];
-            for (int h = 0; h < 4; ++h)
-                w[h] = (uint32_t)f32_to_bf16((float)v[8 * q + 2 * h]) |
-                       ((uint32_t)f32_to_bf16((float)v[8 * q + 2 * h + 1]) << 16);
-            u4[(tile * 3 + q) * kTile + lane] = make_uint4(w[0], w[1], w[2], w[3]);
-        }
-    }
+    write_record<DP>(v, tile, lane, nullptr, J32, J16);
 }
 
-void launch_convert(const double *J64, int64_t nslots, float *J32, uint16_t *J16, hipStream_t s) {
+void launch_convert(const double *J64, int64_t nslots, float *J32, uint16_t *J16, hipStream_t s, int dp) {
     if (nslots <= 0) return;
-    hipLaunchKernelGGL(k_convert, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, s, J64, nslots, J32, J16);
+    const dim3 g((unsigned)((nslots + 255) / 256));
+    if (dp == 6) hipLaunchKernelGGL(k_convert<6>, g, dim3(256), 0, s, J64, nslots, J32, J16);
+    else hipLaunchKernelGGL(k_convert<9>, g, dim3(256), 0, s, J64, nslots, J32, J16);
 }
 
 // ---------------------------------------------------------------- landmarks
@@ -168,7 +174,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // w = sum_o W_o V^-1 b_l with W_o = J_p,o^T J_l,o.  Then
 //   D(S)_c = U + lambda diag(U) - E   (diagonal block of eq. (14))
 //   b~_c   = b_p - w                  (eq. (15))
-// and the Cholesky factor of D(S)_c.
+// and the Cholesky factor of D(S)_c.  DP x DP blocks (DP = 9, or 6 for extrinsics only).
+template <int DP>
 __global__ __launch_bounds__(64) void k_cameras(int np, const int64_t *__restrict__ cam_ptr,
                                                 const int64_t *__restrict__ cam_obs,
                                                 const int32_t *__restrict__ obs_lm,
@@ -179,85 +186,86 @@ __global__ __launch_bounds__(64) void k_cameras(int np, const int64_t *__restric
                                                 double *__restrict__ dU, double *__restrict__ Dblk,
                                                 double *__restrict__ Dchol, double *__restrict__ bt,
                                                 int32_t *status) {
+    constexpr int T = DP * (DP + 1) / 2;   // packed upper triangle
+    constexpr int NA = T + DP;
     int c = blockIdx.x;
     int lane = threadIdx.x;
     if (c >= np) return;
-    __shared__ double red[54];
+    __shared__ double red[NA];
     int64_t a = cam_ptr[c], b = cam_ptr[c + 1];
-    double acc[54];
-    // pass 1: U (upper triangle, 45) and b_p (9)
-    for (int k = 0; k < 54; ++k) acc[k] = 0.0;
+    double acc[NA];
+    // pass 1: U (upper triangle) and b_p
+    for (int k = 0; k < NA; ++k) acc[k] = 0.0;
     for (int64_t q = a + lane; q < b; q += 64) {
         int64_t o = cam_obs[q];
-        const double *j = Jp + o * 18;
+        const double *j = Jp + o * 2 * DP;
         double r0 = r[o * 2], r1 = r[o * 2 + 1];
         int t = 0;
-        for (int i = 0; i < 9; ++i)
-            for (int k = i; k < 9; ++k) acc[t++] += j[i] * j[k] + j[9 + i] * j[9 + k];
-        for (int i = 0; i < 9; ++i) acc[45 + i] += j[i] * r0 + j[9 + i] * r1;
+        for (int i = 0; i < DP; ++i)
+            for (int k = i; k < DP; ++k) acc[t++] += j[i] * j[k] + j[DP + i] * j[DP + k];
+        for (int i = 0; i < DP; ++i) acc[T + i] += j[i] * r0 + j[DP + i] * r1;
     }
-    for (int k = 0; k < 54; ++k) {
+    for (int k = 0; k < NA; ++k) {
         double v = wave_sum(acc[k]);
         if (lane == 0) red[k] = v;
     }
     __syncthreads();
-    double U[45], bp[9];
-    for (int k = 0; k < 45; ++k) U[k] = red[k];
-    for (int k = 0; k < 9; ++k) bp[k] = red[45 + k];
+    double U[T], bp[DP];
+    for (int k = 0; k < T; ++k) U[k] = red[k];
+    for (int k = 0; k < DP; ++k) bp[k] = red[T + k];
     __syncthreads();
-    // pass 2: E = sum W V^-1 W^T (upper, 45) and w = sum W h0 (9)
-    for (int k = 0; k < 54; ++k) acc[k] = 0.0;
+    // pass 2: E = sum W V^-1 W^T (upper) and w = sum W h0
+    for (int k = 0; k < NA; ++k) acc[k] = 0.0;
     for (int64_t q = a + lane; q < b; q += 64) {
         int64_t o = cam_obs[q];
-        const double *jp = Jp + o * 18, *jl = Jl + o * 6;
+        const double *jp = Jp + o * 2 * DP, *jl = Jl + o * 6;
         int64_t ls = lmk_store[obs_lm[o]];
         const double *vi = vinv + ls * 6;
         const double *hh = h0 + ls * 3;
-        double W[27];
-        for (int i = 0; i < 9; ++i)
-            for (int k = 0; k < 3; ++k) W[i * 3 + k] = jp[i] * jl[k] + jp[9 + i] * jl[3 + k];
-        double VW[27];   // (V^-1 W^T)^T = W V^-1, rows i
-        for (int i = 0; i < 9; ++i) {
+        double W[DP * 3];
+        for (int i = 0; i < DP; ++i)
+            for (int k = 0; k < 3; ++k) W[i * 3 + k] = jp[i] * jl[k] + jp[DP + i] * jl[3 + k];
+        double VW[DP * 3];   // (V^-1 W^T)^T = W V^-1, rows i
+        for (int i = 0; i < DP; ++i) {
             double w0 = W[i * 3], w1 = W[i * 3 + 1], w2 = W[i * 3 + 2];
             VW[i * 3 + 0] = w0 * vi[0] + w1 * vi[1] + w2 * vi[2];
             VW[i * 3 + 1] = w0 * vi[1] + w1 * vi[3] + w2 * vi[4];
             VW[i * 3 + 2] = w0 * vi[2] + w1 * vi[4] + w2 * vi[5];
         }
         int t = 0;
-        for (int i = 0; i < 9; ++i)
-            for (int k = i; k < 9; ++k)
+        for (int i = 0; i < DP; ++i)
+            for (int k = i; k < DP; ++k)
                 acc[t++] += VW[i * 3] * W[k * 3] + VW[i * 3 + 1] * W[k * 3 + 1] + VW[i * 3 + 2] * W[k * 3 + 2];
-        for (int i = 0; i < 9; ++i) acc[45 + i] += W[i * 3] * hh[0] + W[i * 3 + 1] * hh[1] + W[i * 3 + 2] * hh[2];
+        for (int i = 0; i < DP; ++i) acc[T + i] += W[i * 3] * hh[0] + W[i * 3 + 1] * hh[1] + W[i * 3 + 2] * hh[2];
     }
-    for (int k = 0; k < 54; ++k) {
+    for (int k = 0; k < NA; ++k) {
         double v = wave_sum(acc[k]);
         if (lane == 0) red[k] = v;
     }
     __syncthreads();
     if (lane != 0) return;
-    double D[81];
+    double D[DP * DP];
     int t = 0;
-    for (int i = 0; i < 9; ++i) {
-        for (int k = i; k < 9; ++k, ++t) {
+    for (int i = 0; i < DP; ++i) {
+        for (int k = i; k < DP; ++k, ++t) {
             double u = U[t];
             if (k == i) u += lambda * U[t];
             double d = u - red[t];
-            D[i * 9 + k] = d;
-            D[k * 9 + i] = d;
+            D[i * DP + k] = d;
+            D[k * DP + i] = d;
         }
     }
-    t = 0;
-    for (int i = 0; i < 9; ++i) {
-        int diag = i * 9 - (i * (i - 1)) / 2;   // index of (i, i) in the packed upper triangle
-        dU[(int64_t)c * 9 + i] = lambda * U[diag];
-        bt[(int64_t)c * 9 + i] = bp[i] - red[45 + i];
+    for (int i = 0; i < DP; ++i) {
+        int diag = i * DP - (i * (i - 1)) / 2;   // index of (i, i) in the packed upper triangle
+        dU[(int64_t)c * DP + i] = lambda * U[diag];
+        bt[(int64_t)c * DP + i] = bp[i] - red[T + i];
     }
-    for (int k = 0; k < 81; ++k) Dblk[(int64_t)c * 81 + k] = D[k];
+    for (int k = 0; k < DP * DP; ++k) Dblk[(int64_t)c * DP * DP + k] = D[k];
     // packed lower Cholesky factor, row i holds L[i][0..i]
-    double L[45];
+    double L[T];
     bool ok = true;
-    for (int j = 0; j < 9; ++j) {
-        double d = D[j * 9 + j];
+    for (int j = 0; j < DP; ++j) {
+        double d = D[j * DP + j];
         for (int p = 0; p < j; ++p) d -= L[j * (j + 1) / 2 + p] * L[j * (j + 1) / 2 + p];
         if (!(d > 0.0)) {
             ok = false;
@@ -265,14 +273,14 @@ __global__ __launch_bounds__(64) void k_cameras(int np, const int64_t *__restric
         }
         d = sqrt(d);
         L[j * (j + 1) / 2 + j] = d;
-        for (int i = j + 1; i < 9; ++i) {
-            double s = D[i * 9 + j];
+        for (int i = j + 1; i < DP; ++i) {
+            double s = D[i * DP + j];
             for (int p = 0; p < j; ++p) s -= L[i * (i + 1) / 2 + p] * L[j * (j + 1) / 2 + p];
             L[i * (i + 1) / 2 + j] = s / d;
         }
     }
     if (!ok) atomicOr(status, kStatusNotSpdCamera);
-    for (int k = 0; k < 45; ++k) Dchol[(int64_t)c * 45 + k] = L[k];
+    for (int k = 0; k < T; ++k) Dchol[(int64_t)c * T + k] = L[k];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -284,9 +292,10 @@ void launch_check_finite(const double *a, int64_t count, int32_t *status, hipStr
 }
 
 void launch_pack(const int64_t *slot_obs, int64_t nslots, const double *Jp, const double *Jl, double *J64,
-                 float *J32, uint16_t *J16, hipStream_t s) {
-    int blocks = (int)((nslots + 255) / 256);
-    hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, s, slot_obs, nslots, Jp, Jl, J64, J32, J16);
+                 float *J32, uint16_t *J16, hipStream_t s, int dp) {
+    const dim3 g((unsigned)((nslots + 255) / 256));
+    if (dp == 6) hipLaunchKernelGGL(k_pack<6>, g, dim3(256), 0, s, slot_obs, nslots, Jp, Jl, J64, J32, J16);
+    else hipLaunchKernelGGL(k_pack<9>, g, dim3(256), 0, s, slot_obs, nslots, Jp, Jl, J64, J32, J16);
 }
 
 void launch_landmarks(int nl, const int64_t *first_slot, const int32_t *count, const int64_t *slot_obs,
@@ -299,9 +308,13 @@ void launch_landmarks(int nl, const int64_t *first_slot, const int32_t *count, c
 void launch_cameras(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const int32_t *obs_lm,
                     const int32_t *lmk_store, const double *Jp, const double *Jl, const double *r,
                     const double *vinv, const double *h0, double lambda, double *dU, double *Dblk,
-                    double *Dchol, double *bt, int32_t *status, hipStream_t s) {
-    hipLaunchKernelGGL(k_cameras, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, obs_lm, lmk_store, Jp, Jl, r,
-                       vinv, h0, lambda, dU, Dblk, Dchol, bt, status);
+                    double *Dchol, double *bt, int32_t *status, hipStream_t s, int dp) {
+    if (dp == 6)
+        hipLaunchKernelGGL(k_cameras<6>, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, obs_lm, lmk_store, Jp, Jl,
+                           r, vinv, h0, lambda, dU, Dblk, Dchol, bt, status);
+    else
+        hipLaunchKernelGGL(k_cameras<9>, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, obs_lm, lmk_store, Jp, Jl,
+                           r, vinv, h0, lambda, dU, Dblk, Dchol, bt, status);
 }
 
 }  // namespace ba

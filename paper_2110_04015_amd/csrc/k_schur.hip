@@ -25,75 +25,75 @@ typedef double dbl2_t __attribute__((ext_vector_type(2)));
 typedef float flt4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
-// Per-observation stream record of one lane: 24 Jacobian values (J_p rows 0, 1,
-// then J_l rows 0, 1) as 12 x 16 B (FP64), 6 x 16 B (FP32) or 3 x 16 B (BF16).
-// Loads fetch the raw 16-byte words; unpacking (and the BF16 conversion) is
-// left to the point of use so that a prefetched record needs no wait.
-template <int PREC>
+// Per-observation stream record of one lane: 2 DP + 6 values (J_p rows 0, 1, then J_l
+// rows 0, 1; DP = 9, or 6 for extrinsics only) as RecordShape<DP> 16 B words in FP64,
+// FP32 or BF16.  Loads fetch the raw 16-byte words; unpacking (and the BF16
+// conversion) is left to the point of use so that a prefetched record needs no wait.
+template <int PREC, int DP>
 struct Stream;
-template <>
-struct Stream<0> {
+template <int DP>
+struct Stream<0, DP> {
     typedef dbl2_t word_t;
-    static constexpr int kWords = 12;
+    static constexpr int kWords = RecordShape<DP>::kW64;
     template <typename T>
-    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[24]) {
+    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[2 * DP + 6]) {
 #pragma unroll
-        for (int q = 0; q < 12; ++q) {
+        for (int q = 0; q < kWords; ++q) {
             v[2 * q] = (T)w[q].x;
             v[2 * q + 1] = (T)w[q].y;
         }
     }
 };
-template <>
-struct Stream<1> {
+template <int DP>
+struct Stream<1, DP> {
     typedef flt4_t word_t;
-    static constexpr int kWords = 6;
+    static constexpr int kWords = RecordShape<DP>::kW32;
     template <typename T>
-    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[24]) {
+    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[2 * DP + 6]) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            v[4 * q] = (T)w[q].x;
-            v[4 * q + 1] = (T)w[q].y;
-            v[4 * q + 2] = (T)w[q].z;
-            v[4 * q + 3] = (T)w[q].w;
+        for (int q = 0; q < kWords; ++q) {
+            const float x[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                if (4 * q + h < 2 * DP + 6) v[4 * q + h] = (T)x[h];
         }
     }
 };
-template <>
-struct Stream<2> {
+template <int DP>
+struct Stream<2, DP> {
     typedef u32x4_t word_t;
-    static constexpr int kWords = 3;
+    static constexpr int kWords = RecordShape<DP>::kW16;
     template <typename T>
-    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[24]) {
+    static __device__ __forceinline__ void unpack(const word_t (&w)[kWords], T (&v)[2 * DP + 6]) {
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
+        for (int q = 0; q < kWords; ++q) {
             const uint32_t u[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                v[8 * q + 2 * h] = (T)bf16_to_f32(u[h] & 0xFFFFu);
-                v[8 * q + 2 * h + 1] = (T)bf16_to_f32(u[h] >> 16);
+                if (8 * q + 2 * h < 2 * DP + 6) v[8 * q + 2 * h] = (T)bf16_to_f32(u[h] & 0xFFFFu);
+                if (8 * q + 2 * h + 1 < 2 * DP + 6) v[8 * q + 2 * h + 1] = (T)bf16_to_f32(u[h] >> 16);
             }
         }
     }
 };
 
-template <int PREC>
+template <int PREC, int DP>
 __device__ __forceinline__ void load_words(const void *J, int64_t tile, int lane,
-                                           typename Stream<PREC>::word_t (&w)[Stream<PREC>::kWords]) {
-    typedef typename Stream<PREC>::word_t W;
-    constexpr int K = Stream<PREC>::kWords;
+                                           typename Stream<PREC, DP>::word_t (&w)[Stream<PREC, DP>::kWords]) {
+    typedef typename Stream<PREC, DP>::word_t W;
+    constexpr int K = Stream<PREC, DP>::kWords;
     const W *p = reinterpret_cast<const W *>(J) + tile * K * kTile + lane;
 #pragma unroll
     for (int q = 0; q < K; ++q) w[q] = __builtin_nontemporal_load(p + q * kTile);
 }
 
-template <int PREC>
+template <int PREC, int DP>
 struct Loader {
     template <typename T>
-    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[24]) {
-        typename Stream<PREC>::word_t w[Stream<PREC>::kWords];
-        load_words<PREC>(J, tile, lane, w);
-        Stream<PREC>::unpack(w, v);
+    static __device__ __forceinline__ void load(const void *J, int64_t tile, int lane, T (&v)[2 * DP + 6]) {
+        typename Stream<PREC, DP>::word_t w[Stream<PREC, DP>::kWords];
+        load_words<PREC, DP>(J, tile, lane, w);
+        Stream<PREC, DP>::template unpack<T>(w, v);
     }
 };
 
@@ -113,51 +113,53 @@ __device__ __forceinline__ void wave_sync() {
 // are kept as the 24 values themselves (loading them is the unpacking); BF16
 // records are kept as raw words and converted when the tile is processed, so
 // that no conversion waits on a load in flight.
-template <int PREC, typename T>
+template <int PREC, typename T, int DP>
 struct TileBuf {
-    T v[24];
+    T v[2 * DP + 6];
     dbl2_t vi[3];
     uint32_t mt;
 };
-template <typename T>
-struct TileBuf<2, T> {
-    u32x4_t w[3];
+template <typename T, int DP>
+struct TileBuf<2, T, DP> {
+    u32x4_t w[RecordShape<DP>::kW16];
     dbl2_t vi[3];
     uint32_t mt;
 };
 
-template <int PREC, typename T>
-__device__ __forceinline__ void fetch_record(const void *J, int t, int lane, TileBuf<PREC, T> &b) {
+template <int PREC, typename T, int DP>
+__device__ __forceinline__ void fetch_record(const void *J, int t, int lane, TileBuf<PREC, T, DP> &b) {
     if constexpr (PREC == 0) {
-        const dbl2_t *p = reinterpret_cast<const dbl2_t *>(J) + (int64_t)t * 12 * kTile + lane;
+        constexpr int K = RecordShape<DP>::kW64;
+        const dbl2_t *p = reinterpret_cast<const dbl2_t *>(J) + (int64_t)t * K * kTile + lane;
 #pragma unroll
-        for (int q = 0; q < 12; ++q) {
+        for (int q = 0; q < K; ++q) {
             const dbl2_t d = __builtin_nontemporal_load(p + q * kTile);
             b.v[2 * q] = d.x;
             b.v[2 * q + 1] = d.y;
         }
     } else if constexpr (PREC == 1) {
-        const flt4_t *p = reinterpret_cast<const flt4_t *>(J) + (int64_t)t * 6 * kTile + lane;
+        constexpr int K = RecordShape<DP>::kW32;
+        const flt4_t *p = reinterpret_cast<const flt4_t *>(J) + (int64_t)t * K * kTile + lane;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
+        for (int q = 0; q < K; ++q) {
             const flt4_t f = __builtin_nontemporal_load(p + q * kTile);
-            b.v[4 * q] = f.x;
-            b.v[4 * q + 1] = f.y;
-            b.v[4 * q + 2] = f.z;
-            b.v[4 * q + 3] = f.w;
+            const float x[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+                if (4 * q + h < 2 * DP + 6) b.v[4 * q + h] = x[h];
         }
     } else {
-        load_words<2>(J, t, lane, b.w);
+        load_words<2, DP>(J, t, lane, b.w);
     }
 }
 
 // Requests the record and V^-1 of tile t (slot word m, already loaded) into b.
 // Padding slots read V^-1 of the tile's first landmark (every tile holds at
 // least one) and ignore it.
-template <int PREC, typename T>
-__device__ __forceinline__ void fetch_tile(const SchurArgs &a, int t, int lane, uint32_t m, TileBuf<PREC, T> &b) {
+template <int PREC, typename T, int DP>
+__device__ __forceinline__ void fetch_tile(const SchurArgs &a, int t, int lane, uint32_t m, TileBuf<PREC, T, DP> &b) {
     b.mt = m;
-    fetch_record<PREC, T>(a.J, t, lane, b);
+    fetch_record<PREC, T, DP>(a.J, t, lane, b);
     const int ll = m != kPad ? (int)((m >> 16) & 63u) : 0;
     const dbl2_t *p = reinterpret_cast<const dbl2_t *>(a.vinv + (int64_t)(a.tile_lmk_base[t] + ll) * 6);
 #pragma unroll
@@ -169,20 +171,21 @@ __device__ __forceinline__ void fetch_tile(const SchurArgs &a, int t, int lane, 
 // precision.  Besides being the more accurate choice, it is the faster one on
 // gfx950: with FP32 LDS accumulators (ds_add_f32) the FP32 product took 370 us on
 // the F-1936-shaped problem, with FP64 ones (ds_add_f64) 131 us.
-template <typename T>
-__device__ __forceinline__ void schur_tile(const T (&J)[24], const dbl2_t (&vi)[3], uint32_t mt, int lane,
+template <typename T, int DP>
+__device__ __forceinline__ void schur_tile(const T (&J)[2 * DP + 6], const dbl2_t (&vi)[3], uint32_t mt, int lane,
                                            const T *vloc, double *yloc, double *gloc) {
+    constexpr int L0 = 2 * DP, L1 = 2 * DP + 3;   // J_l rows 0 and 1
     const bool valid = mt != kPad;
     const int slot = valid ? (int)(mt & 0xFFFFu) : 0;
     const int ll = valid ? (int)((mt >> 16) & 63u) : 0;
-    T vc[9];
+    T vc[DP];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) vc[k] = vloc[slot * 9 + k];
+    for (int k = 0; k < DP; ++k) vc[k] = vloc[slot * DP + k];
     T e0 = 0, e1 = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
+    for (int k = 0; k < DP; ++k) {
         e0 += J[k] * vc[k];
-        e1 += J[9 + k] * vc[k];
+        e1 += J[DP + k] * vc[k];
     }
     gloc[lane * 3 + 0] = 0;
     gloc[lane * 3 + 1] = 0;
@@ -190,7 +193,7 @@ __device__ __forceinline__ void schur_tile(const T (&J)[24], const dbl2_t (&vi)[
     wave_sync();
     if (valid) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], (double)(J[18 + k] * e0 + J[21 + k] * e1));
+        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], (double)(J[L0 + k] * e0 + J[L1 + k] * e1));
     }
     wave_sync();
     if (valid) {
@@ -200,36 +203,36 @@ __device__ __forceinline__ void schur_tile(const T (&J)[24], const dbl2_t (&vi)[
         const T h0 = w0 * g0 + w1 * g1 + w2 * g2;
         const T h1 = w1 * g0 + w3 * g1 + w4 * g2;
         const T h2 = w2 * g0 + w4 * g1 + w5 * g2;
-        const T f0 = e0 - (J[18] * h0 + J[19] * h1 + J[20] * h2);
-        const T f1 = e1 - (J[21] * h0 + J[22] * h1 + J[23] * h2);
+        const T f0 = e0 - (J[L0] * h0 + J[L0 + 1] * h1 + J[L0 + 2] * h2);
+        const T f1 = e1 - (J[L1] * h0 + J[L1 + 1] * h1 + J[L1 + 2] * h2);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) atomicAdd(&yloc[slot * 9 + k], (double)(J[k] * f0 + J[9 + k] * f1));
+        for (int k = 0; k < DP; ++k) atomicAdd(&yloc[slot * DP + k], (double)(J[k] * f0 + J[DP + k] * f1));
     }
     wave_sync();
 }
 
-template <int PREC, typename T>
-__device__ __forceinline__ void process_tile(const TileBuf<PREC, T> &b, int lane, const T *vloc, double *yloc,
+template <int PREC, typename T, int DP>
+__device__ __forceinline__ void process_tile(const TileBuf<PREC, T, DP> &b, int lane, const T *vloc, double *yloc,
                                              double *gloc) {
     if constexpr (PREC == 2) {
-        T J[24];
-        Stream<2>::unpack(b.w, J);
-        schur_tile<T>(J, b.vi, b.mt, lane, vloc, yloc, gloc);
+        T J[2 * DP + 6];
+        Stream<2, DP>::template unpack<T>(b.w, J);
+        schur_tile<T, DP>(J, b.vi, b.mt, lane, vloc, yloc, gloc);
     } else {
-        schur_tile<T>(b.v, b.vi, b.mt, lane, vloc, yloc, gloc);
+        schur_tile<T, DP>(b.v, b.vi, b.mt, lane, vloc, yloc, gloc);
     }
 }
 
 // Software pipeline over the tiles of the chunk with two buffers: the record and
 // V^-1 of tile t + 1 and the slot word of tile t + 2 are requested before tile t
 // is processed, so a wavefront keeps up to two tiles of the stream in flight.
-template <int PREC, typename T>
+template <int PREC, typename T, int DP>
 __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__restrict__ v) {
     if (a.done && *a.done != 0.0) return;
     if (a.seg_skip && a.seg_skip[a.chunk_seg[blockIdx.x]]) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double *yloc = reinterpret_cast<double *>(smem);
-    double *gloc = yloc + a.max_slots * 9;
+    double *gloc = yloc + a.max_slots * DP;
     T *vloc = reinterpret_cast<T *>(gloc + 3 * kTile);
     const int chunk = blockIdx.x;
     const int lane = threadIdx.x;
@@ -238,14 +241,14 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
     const int t0 = a.chunk_tile[chunk], t1 = a.chunk_tile[chunk + 1];
     const uint32_t *meta = a.meta + lane;
     const int tl = t1 - 1;   // slot words past the chunk's end are read from its last tile
-    TileBuf<PREC, T> A, B;
+    TileBuf<PREC, T, DP> A, B;
     uint32_t mA, mB = 0;
     if (t0 < t1) {
-        fetch_tile<PREC, T>(a, t0, lane, meta[(int64_t)t0 * kTile], A);
+        fetch_tile<PREC, T, DP>(a, t0, lane, meta[(int64_t)t0 * kTile], A);
         mB = meta[(int64_t)min(t0 + 1, tl) * kTile];
     }
-    for (int i = lane; i < ns * 9; i += kTile) {
-        vloc[i] = (T)v[(int64_t)a.part_cam[pb + i / 9] * 9 + i % 9];
+    for (int i = lane; i < ns * DP; i += kTile) {
+        vloc[i] = (T)v[(int64_t)a.part_cam[pb + i / DP] * DP + i % DP];
         yloc[i] = 0.0;
     }
     wave_sync();
@@ -253,57 +256,61 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
     // (a branch around a load leaves the compiler waiting for it at the join)
     int t = t0;
     for (; t + 2 < t1; t += 2) {
-        fetch_tile<PREC, T>(a, t + 1, lane, mB, B);
+        fetch_tile<PREC, T, DP>(a, t + 1, lane, mB, B);
         mA = meta[(int64_t)(t + 2) * kTile];
-        process_tile<PREC, T>(A, lane, vloc, yloc, gloc);
-        fetch_tile<PREC, T>(a, t + 2, lane, mA, A);
+        process_tile<PREC, T, DP>(A, lane, vloc, yloc, gloc);
+        fetch_tile<PREC, T, DP>(a, t + 2, lane, mA, A);
         mB = meta[(int64_t)min(t + 3, tl) * kTile];
-        process_tile<PREC, T>(B, lane, vloc, yloc, gloc);
+        process_tile<PREC, T, DP>(B, lane, vloc, yloc, gloc);
     }
     // the last one or two tiles
     if (t + 1 < t1) {
-        fetch_tile<PREC, T>(a, t + 1, lane, mB, B);
-        process_tile<PREC, T>(A, lane, vloc, yloc, gloc);
-        process_tile<PREC, T>(B, lane, vloc, yloc, gloc);
+        fetch_tile<PREC, T, DP>(a, t + 1, lane, mB, B);
+        process_tile<PREC, T, DP>(A, lane, vloc, yloc, gloc);
+        process_tile<PREC, T, DP>(B, lane, vloc, yloc, gloc);
     } else if (t < t1) {
-        process_tile<PREC, T>(A, lane, vloc, yloc, gloc);
+        process_tile<PREC, T, DP>(A, lane, vloc, yloc, gloc);
     }
     // row of slot k goes to its camera-major position
-    for (int i = lane; i < ns * 9; i += kTile) {
-        const int64_t row = a.part_dst[pb + i / 9];
-        a.partial[row * 9 + i % 9] = (double)yloc[i];
+    for (int i = lane; i < ns * DP; i += kTile) {
+        const int64_t row = a.part_dst[pb + i / DP];
+        a.partial[row * DP + i % DP] = (double)yloc[i];
     }
 }
 
-// Sum of the 9-vectors rows[a..b) by the calling wavefront, component k = lane % 9 on
-// lanes < 63: lane l adds rows a + l / 9 + 7 i into two running sums (even and odd i,
-// so that two loads are in flight), then the 14 sums of a component are added in a
-// fixed order through sh (64 doubles of the wavefront).  Every lane returns its
-// component's total (lanes 63 and above return component 0's).
-__device__ __forceinline__ double wave_rows9(const double *__restrict__ rows, int64_t a, int64_t b, double *sh) {
+// Sum of the DP-vectors rows[a..b) by the calling wavefront, R = 64 / DP rows at a
+// time (7 for DP = 9, 10 for DP = 6): lane l < R DP adds component l % DP of rows
+// a + l / DP + R i into two running sums (even and odd i, so that two loads are in
+// flight), then the 2 R sums of a component are added in a fixed order through sh (64
+// doubles of the wavefront).  Every lane returns its component's total (lanes past R DP
+// return component 0's).
+template <int DP>
+__device__ __forceinline__ double wave_rows(const double *__restrict__ rows, int64_t a, int64_t b, double *sh) {
+    constexpr int R = 64 / DP;
     const int lane = threadIdx.x & 63;
     double s0 = 0.0, s1 = 0.0;
-    if (lane < 63) {
-        const int r0 = lane / 9, k = lane - r0 * 9;
+    if (lane < R * DP) {
+        const int r0 = lane / DP, k = lane - r0 * DP;
         int64_t j = a + r0;
-        for (; j + 7 < b; j += 14) {
-            s0 += rows[j * 9 + k];
-            s1 += rows[(j + 7) * 9 + k];
+        for (; j + R < b; j += 2 * R) {
+            s0 += rows[j * DP + k];
+            s1 += rows[(j + R) * DP + k];
         }
-        if (j < b) s0 += rows[j * 9 + k];
+        if (j < b) s0 += rows[j * DP + k];
     }
     sh[lane] = s0 + s1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int k = lane < 63 ? lane % 9 : 0;
+    const int k = lane < R * DP ? lane % DP : 0;
     double t = 0.0;
-    for (int m = 0; m < 7; ++m) t += sh[k + 9 * m];
+    for (int m = 0; m < R; ++m) t += sh[k + DP * m];
     return t;
 }
 
 // y_c = lambda diag(U_c) v_c + sum of the partial rows of camera c, which are
-// contiguous (camera-major); one wavefront per camera (wave_rows9).
+// contiguous (camera-major); one wavefront per camera (wave_rows).
+template <int DP>
 __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restrict__ ptr,
                                                  const double *__restrict__ partial,
                                                  const double *__restrict__ dU, const double *__restrict__ v,
@@ -315,26 +322,40 @@ __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restri
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + w;
     if (c >= np || (seg_skip && seg_skip[cam_seg[c]])) return;   // uniform per wavefront
-    const double t = wave_rows9(partial, ptr[c], ptr[c + 1], sh[w]);
-    if (lane < 9) y[(int64_t)c * 9 + lane] = dU[(int64_t)c * 9 + lane] * v[(int64_t)c * 9 + lane] + t;
+    const double t = wave_rows<DP>(partial, ptr[c], ptr[c + 1], sh[w]);
+    if (lane < DP) y[(int64_t)c * DP + lane] = dU[(int64_t)c * DP + lane] * v[(int64_t)c * DP + lane] + t;
 }
 
 void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
     if (a.n_chunks > 0) {
         // FP64 camera rows and landmark sums, v in the product precision
         const size_t esz = a.precision == 0 ? sizeof(double) : sizeof(float);
-        const size_t lds = (size_t)(a.max_slots * 9 + 3 * kTile) * sizeof(double) + (size_t)a.max_slots * 9 * esz;
-        switch (a.precision) {
-            case 0: hipLaunchKernelGGL((k_schur1<0, double>), dim3(a.n_chunks), dim3(kTile), lds, s, a, v); break;
-            case 1: hipLaunchKernelGGL((k_schur1<1, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, v); break;
-            default: hipLaunchKernelGGL((k_schur1<2, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, v); break;
+        const size_t lds =
+            (size_t)(a.max_slots * a.dp + 3 * kTile) * sizeof(double) + (size_t)a.max_slots * a.dp * esz;
+        const dim3 g(a.n_chunks), b(kTile);
+        if (a.dp == 6) {
+            switch (a.precision) {
+                case 0: hipLaunchKernelGGL((k_schur1<0, double, 6>), g, b, lds, s, a, v); break;
+                case 1: hipLaunchKernelGGL((k_schur1<1, float, 6>), g, b, lds, s, a, v); break;
+                default: hipLaunchKernelGGL((k_schur1<2, float, 6>), g, b, lds, s, a, v); break;
+            }
+        } else {
+            switch (a.precision) {
+                case 0: hipLaunchKernelGGL((k_schur1<0, double, 9>), g, b, lds, s, a, v); break;
+                case 1: hipLaunchKernelGGL((k_schur1<1, float, 9>), g, b, lds, s, a, v); break;
+                default: hipLaunchKernelGGL((k_schur1<2, float, 9>), g, b, lds, s, a, v); break;
+            }
         }
     }
 }
 
 void launch_schur_reduce(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce1, dim3((a.np + 3) / 4), dim3(256), 0, s, a.np, a.cam_part_ptr, a.partial, a.dU, v,
-                       y, a.done, a.cam_seg, a.seg_skip);
+    if (a.dp == 6)
+        hipLaunchKernelGGL(k_reduce1<6>, dim3((a.np + 3) / 4), dim3(256), 0, s, a.np, a.cam_part_ptr, a.partial, a.dU,
+                           v, y, a.done, a.cam_seg, a.seg_skip);
+    else
+        hipLaunchKernelGGL(k_reduce1<9>, dim3((a.np + 3) / 4), dim3(256), 0, s, a.np, a.cam_part_ptr, a.partial, a.dU,
+                           v, y, a.done, a.cam_seg, a.seg_skip);
 }
 
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
@@ -367,25 +388,24 @@ __device__ __forceinline__ MultiSlot fetch_mslot(const MultiArgs &a, int64_t sid
 // Record, z of the slot's camera, V^-1 of the lane's pair landmark and the slot words
 // of one tile (see TileBuf).  Padding slots read camera 0's z and the tile's first
 // landmark's V^-1 and ignore them.
-template <int PREC, typename T>
+template <int PREC, typename T, int DP>
 struct MultiBuf {
-    TileBuf<PREC, T> r;   // record (r.vi and r.mt unused)
-    dbl2_t z[5];          // z_c (9 values, the 10th unused)
+    TileBuf<PREC, T, DP> r;   // record (r.vi and r.mt unused)
+    double z[DP];             // z_c
     dbl2_t vi[3];
     MultiSlot m;
-    uint32_t obase;       // tile_oidx of the tile
+    uint32_t obase;           // tile_oidx of the tile
 };
 
-template <int PREC, typename T>
+template <int PREC, typename T, int DP>
 __device__ __forceinline__ void fetch_mtile(const MultiArgs &a, const double *__restrict__ z, int t, int lane,
-                                            const MultiSlot &m, MultiBuf<PREC, T> &b) {
+                                            const MultiSlot &m, MultiBuf<PREC, T, DP> &b) {
     b.m = m;
-    fetch_record<PREC, T>(a.J, t, lane, b.r);
+    fetch_record<PREC, T, DP>(a.J, t, lane, b.r);
     const bool valid = m.mm != kPad;
-    const double *zc = z + (int64_t)(valid ? m.cam : 0) * 9;
+    const double *zc = z + (int64_t)(valid ? m.cam : 0) * DP;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) b.z[k] = dbl2_t{zc[2 * k], zc[2 * k + 1]};
-    b.z[4] = dbl2_t{zc[8], 0.0};
+    for (int k = 0; k < DP; ++k) b.z[k] = zc[k];
     const int ll = m.pll != 0xFFu ? (int)m.pll : 0;
     const dbl2_t *p = reinterpret_cast<const dbl2_t *>(a.vinv + (int64_t)(a.tile_lmk_base[t] + ll) * 6);
 #pragma unroll
@@ -396,18 +416,17 @@ __device__ __forceinline__ void fetch_mtile(const MultiArgs &a, const double *__
 // One tile: e = J_p z_c; g per (landmark, subset) pair = sum over the pair's
 // observations of J_l^T e (LDS); h = V^-1 g on the pair's lane; every observation of
 // the landmark adds J_p^T (e [own pair] - J_l h_pair) to its (camera, pair subset) row.
-template <typename T>
-__device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[24], const dbl2_t (&zb)[5],
+template <typename T, int DP>
+__device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[2 * DP + 6], const double (&zb)[DP],
                                            const dbl2_t (&vi)[3], const MultiSlot &m, uint32_t obase, int lane,
                                            double *yloc, double *gloc, double *hloc) {
+    constexpr int L0 = 2 * DP, L1 = 2 * DP + 3;   // J_l rows 0 and 1
     const bool valid = m.mm != kPad;
-    const T zc[9] = {(T)zb[0].x, (T)zb[0].y, (T)zb[1].x, (T)zb[1].y, (T)zb[2].x,
-                     (T)zb[2].y, (T)zb[3].x, (T)zb[3].y, (T)zb[4].x};
     T e0 = 0, e1 = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        e0 += J[k] * zc[k];
-        e1 += J[9 + k] * zc[k];
+    for (int k = 0; k < DP; ++k) {
+        e0 += J[k] * (T)zb[k];
+        e1 += J[DP + k] * (T)zb[k];
     }
     const int own = (int)(m.mm & 0xFFu);
     gloc[lane * 3 + 0] = 0;
@@ -416,7 +435,7 @@ __device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[24],
     wave_sync();
     if (valid) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], (double)(J[18 + k] * e0 + J[21 + k] * e1));
+        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], (double)(J[L0 + k] * e0 + J[L1 + k] * e1));
     }
     wave_sync();
     if (m.pll != 0xFFu) {
@@ -434,42 +453,42 @@ __device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[24],
         for (int j = 0; j < cnt; ++j) {
             const int pj = base + j;
             const T h0 = (T)hloc[pj * 3], h1 = (T)hloc[pj * 3 + 1], h2 = (T)hloc[pj * 3 + 2];
-            T f0 = -(J[18] * h0 + J[19] * h1 + J[20] * h2);
-            T f1 = -(J[21] * h0 + J[22] * h1 + J[23] * h2);
+            T f0 = -(J[L0] * h0 + J[L0 + 1] * h1 + J[L0 + 2] * h2);
+            T f1 = -(J[L1] * h0 + J[L1 + 1] * h1 + J[L1 + 2] * h2);
             if (pj == own) {
                 f0 += e0;
                 f1 += e1;
             }
             const int o = oi[j];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) atomicAdd(&yloc[o * 9 + k], (double)(J[k] * f0 + J[9 + k] * f1));
+            for (int k = 0; k < DP; ++k) atomicAdd(&yloc[o * DP + k], (double)(J[k] * f0 + J[DP + k] * f1));
         }
     }
     wave_sync();
 }
 
-template <int PREC, typename T>
-__device__ __forceinline__ void process_mtile(const MultiArgs &a, const MultiBuf<PREC, T> &b, int lane,
+template <int PREC, typename T, int DP>
+__device__ __forceinline__ void process_mtile(const MultiArgs &a, const MultiBuf<PREC, T, DP> &b, int lane,
                                               double *yloc, double *gloc, double *hloc) {
     if constexpr (PREC == 2) {
-        T J[24];
-        Stream<2>::unpack(b.r.w, J);
-        multi_tile<T>(a, J, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
+        T J[2 * DP + 6];
+        Stream<2, DP>::template unpack<T>(b.r.w, J);
+        multi_tile<T, DP>(a, J, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
     } else {
-        multi_tile<T>(a, b.r.v, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
+        multi_tile<T, DP>(a, b.r.v, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
     }
 }
 
 // One wavefront per chunk of tiles, software-pipelined as k_schur1: the record, z
 // gather and V^-1 of tile t + 1 and the slot words of tile t + 2 are requested before
 // tile t is processed.
-template <int PREC, typename T>
+template <int PREC, typename T, int DP>
 __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *__restrict__ z) {
     if (a.skip && *a.skip != 0.0) return;
     if (a.seg_skip && a.seg_skip[a.chunk_seg[blockIdx.x]]) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double *yloc = reinterpret_cast<double *>(smem);   // FP64 sums for every precision (see schur_tile)
-    double *gloc = yloc + a.max_out * 9;
+    double *gloc = yloc + a.max_out * DP;
     double *hloc = gloc + 3 * kTile;
     const int chunk = blockIdx.x;
     const int lane = threadIdx.x;
@@ -477,38 +496,39 @@ __global__ __launch_bounds__(64) void k_schur_multi(MultiArgs a, const double *_
     const int no = a.chunk_part[chunk + 1] - pb;
     const int t0 = a.chunk_tile[chunk], t1 = a.chunk_tile[chunk + 1];
     const int tl = t1 - 1;   // slot words past the chunk's end are read from its last tile
-    MultiBuf<PREC, T> A, B;
+    MultiBuf<PREC, T, DP> A, B;
     MultiSlot mA, mB{};
     if (t0 < t1) {
-        fetch_mtile<PREC, T>(a, z, t0, lane, fetch_mslot(a, (int64_t)t0 * kTile + lane), A);
+        fetch_mtile<PREC, T, DP>(a, z, t0, lane, fetch_mslot(a, (int64_t)t0 * kTile + lane), A);
         mB = fetch_mslot(a, (int64_t)min(t0 + 1, tl) * kTile + lane);
     }
-    for (int i = lane; i < no * 9; i += kTile) yloc[i] = 0.0;
+    for (int i = lane; i < no * DP; i += kTile) yloc[i] = 0.0;
     wave_sync();
     int t = t0;
     for (; t + 2 < t1; t += 2) {
-        fetch_mtile<PREC, T>(a, z, t + 1, lane, mB, B);
+        fetch_mtile<PREC, T, DP>(a, z, t + 1, lane, mB, B);
         mA = fetch_mslot(a, (int64_t)(t + 2) * kTile + lane);
-        process_mtile<PREC, T>(a, A, lane, yloc, gloc, hloc);
-        fetch_mtile<PREC, T>(a, z, t + 2, lane, mA, A);
+        process_mtile<PREC, T, DP>(a, A, lane, yloc, gloc, hloc);
+        fetch_mtile<PREC, T, DP>(a, z, t + 2, lane, mA, A);
         mB = fetch_mslot(a, (int64_t)min(t + 3, tl) * kTile + lane);
-        process_mtile<PREC, T>(a, B, lane, yloc, gloc, hloc);
+        process_mtile<PREC, T, DP>(a, B, lane, yloc, gloc, hloc);
     }
     if (t + 1 < t1) {
-        fetch_mtile<PREC, T>(a, z, t + 1, lane, mB, B);
-        process_mtile<PREC, T>(a, A, lane, yloc, gloc, hloc);
-        process_mtile<PREC, T>(a, B, lane, yloc, gloc, hloc);
+        fetch_mtile<PREC, T, DP>(a, z, t + 1, lane, mB, B);
+        process_mtile<PREC, T, DP>(a, A, lane, yloc, gloc, hloc);
+        process_mtile<PREC, T, DP>(a, B, lane, yloc, gloc, hloc);
     } else if (t < t1) {
-        process_mtile<PREC, T>(a, A, lane, yloc, gloc, hloc);
+        process_mtile<PREC, T, DP>(a, A, lane, yloc, gloc, hloc);
     }
-    for (int i = lane; i < no * 9; i += kTile) {
-        const int64_t row = a.part_dst[pb + i / 9];
-        a.partial[row * 9 + i % 9] = (double)yloc[i];
+    for (int i = lane; i < no * DP; i += kTile) {
+        const int64_t row = a.part_dst[pb + i / DP];
+        a.partial[row * DP + i % DP] = (double)yloc[i];
     }
 }
 
 // Y[p][c] = [group(c) == p] lambda diag(U_c) z_c + sum of the partial rows of (c, p),
-// which are contiguous ((camera, subset)-major); one wavefront per (c, p) (wave_rows9)
+// which are contiguous ((camera, subset)-major); one wavefront per (c, p) (wave_rows)
+template <int DP>
 __global__ __launch_bounds__(256) void k_reduce_multi(int np, int N, const int32_t *__restrict__ ptr,
                                                       const double *__restrict__ partial,
                                                       const double *__restrict__ dU,
@@ -524,31 +544,46 @@ __global__ __launch_bounds__(256) void k_reduce_multi(int np, int N, const int32
     if (key >= (int64_t)np * N) return;                 // uniform per wavefront
     const int c = (int)(key / N), p = (int)(key - (int64_t)c * N);
     if (seg_skip && seg_skip[cam_seg[c]]) return;
-    const double t = wave_rows9(partial, ptr[key], ptr[key + 1], sh[w]);
-    if (lane < 9) {
-        const int64_t rem = (int64_t)c * 9 + lane;
-        Y[(int64_t)p * np * 9 + rem] = (group[c] == p ? dU[rem] * z[rem] : 0.0) + t;
+    const double t = wave_rows<DP>(partial, ptr[key], ptr[key + 1], sh[w]);
+    if (lane < DP) {
+        const int64_t rem = (int64_t)c * DP + lane;
+        Y[(int64_t)p * np * DP + rem] = (group[c] == p ? dU[rem] * z[rem] : 0.0) + t;
     }
 }
 
 void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s) {
     if (a.n_chunks > 0) {
-        const size_t lds = (size_t)(a.max_out * 9 + 6 * kTile) * sizeof(double);
-        switch (a.precision) {
-            case 0: hipLaunchKernelGGL((k_schur_multi<0, double>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;
-            case 1: hipLaunchKernelGGL((k_schur_multi<1, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;
-            default: hipLaunchKernelGGL((k_schur_multi<2, float>), dim3(a.n_chunks), dim3(kTile), lds, s, a, z); break;
+        const size_t lds = (size_t)(a.max_out * a.dp + 6 * kTile) * sizeof(double);
+        const dim3 g(a.n_chunks), b(kTile);
+        if (a.dp == 6) {
+            switch (a.precision) {
+                case 0: hipLaunchKernelGGL((k_schur_multi<0, double, 6>), g, b, lds, s, a, z); break;
+                case 1: hipLaunchKernelGGL((k_schur_multi<1, float, 6>), g, b, lds, s, a, z); break;
+                default: hipLaunchKernelGGL((k_schur_multi<2, float, 6>), g, b, lds, s, a, z); break;
+            }
+        } else {
+            switch (a.precision) {
+                case 0: hipLaunchKernelGGL((k_schur_multi<0, double, 9>), g, b, lds, s, a, z); break;
+                case 1: hipLaunchKernelGGL((k_schur_multi<1, float, 9>), g, b, lds, s, a, z); break;
+                default: hipLaunchKernelGGL((k_schur_multi<2, float, 9>), g, b, lds, s, a, z); break;
+            }
         }
     }
     const int64_t keys = (int64_t)a.np * a.N;
-    hipLaunchKernelGGL(k_reduce_multi, dim3((unsigned)((keys + 3) / 4)), dim3(256), 0, s, a.np, a.N, a.cg_ptr,
-                       a.partial, a.dU, a.group, z, Y, a.cam_seg, a.seg_skip, a.skip);
+    const dim3 g((unsigned)((keys + 3) / 4));
+    if (a.dp == 6)
+        hipLaunchKernelGGL(k_reduce_multi<6>, g, dim3(256), 0, s, a.np, a.N, a.cg_ptr, a.partial, a.dU, a.group, z, Y,
+                           a.cam_seg, a.seg_skip, a.skip);
+    else
+        hipLaunchKernelGGL(k_reduce_multi<9>, g, dim3(256), 0, s, a.np, a.N, a.cg_ptr, a.partial, a.dU, a.group, z, Y,
+                           a.cam_seg, a.seg_skip, a.skip);
 }
 
 // ---------------------------------------------------------------- eq. (16)
 
 // dx_l = -V^-1 (b_l + W^T dx_p) for every landmark; the first observation of a
 // landmark inside its tile writes the result.
+template <int DP>
 __global__ __launch_bounds__(64) void k_backsub(const double *__restrict__ J64, const uint32_t *__restrict__ meta,
                                                 const int32_t *__restrict__ tile_lmk_base,
                                                 const int32_t *__restrict__ chunk_tile,
@@ -559,16 +594,16 @@ __global__ __launch_bounds__(64) void k_backsub(const double *__restrict__ J64, 
                                                 const double *__restrict__ dxp, double *__restrict__ dxl) {
     extern __shared__ __align__(16) unsigned char smem[];
     double *vloc = reinterpret_cast<double *>(smem);
-    double *gloc = vloc + max_slots * 9;
+    double *gloc = vloc + max_slots * DP;
     const int chunk = blockIdx.x;
     const int lane = threadIdx.x;
     const int pb = chunk_part[chunk];
     const int ns = chunk_part[chunk + 1] - pb;
-    for (int i = lane; i < ns * 9; i += kTile) vloc[i] = dxp[(int64_t)part_cam[pb + i / 9] * 9 + i % 9];
+    for (int i = lane; i < ns * DP; i += kTile) vloc[i] = dxp[(int64_t)part_cam[pb + i / DP] * DP + i % DP];
     __syncthreads();
     for (int t = chunk_tile[chunk]; t < chunk_tile[chunk + 1]; ++t) {
-        double J[24];
-        Loader<0>::load(J64, t, lane, J);
+        double J[2 * DP + 6];
+        Loader<0, DP>::load(J64, t, lane, J);
         const uint32_t mt = meta[(int64_t)t * kTile + lane];
         const bool valid = mt != kPad;
         const int slot = valid ? (int)(mt & 0xFFFFu) : 0;
@@ -576,16 +611,16 @@ __global__ __launch_bounds__(64) void k_backsub(const double *__restrict__ J64, 
         const uint32_t prev = lane > 0 ? meta[(int64_t)t * kTile + lane - 1] : kPad;
         const bool first = valid && (prev == kPad || ((prev >> 16) & 63u) != (uint32_t)ll);
         double e0 = 0, e1 = 0;
-        for (int k = 0; k < 9; ++k) {
-            e0 += J[k] * vloc[slot * 9 + k];
-            e1 += J[9 + k] * vloc[slot * 9 + k];
+        for (int k = 0; k < DP; ++k) {
+            e0 += J[k] * vloc[slot * DP + k];
+            e1 += J[DP + k] * vloc[slot * DP + k];
         }
         gloc[lane * 3 + 0] = 0;
         gloc[lane * 3 + 1] = 0;
         gloc[lane * 3 + 2] = 0;
         __syncthreads();
         if (valid)
-            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], J[18 + k] * e0 + J[21 + k] * e1);
+            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], J[2 * DP + k] * e0 + J[2 * DP + 3 + k] * e1);
         __syncthreads();
         if (first) {
             const int64_t ls = tile_lmk_base[t] + ll;
@@ -604,11 +639,15 @@ __global__ __launch_bounds__(64) void k_backsub(const double *__restrict__ J64, 
 void launch_back_substitute(const double *J64, const uint32_t *meta, const int32_t *tile_lmk_base,
                             const int32_t *chunk_tile, const int32_t *chunk_part, const int32_t *part_cam,
                             int n_chunks, int max_slots, const double *vinv, const double *bl,
-                            const int32_t *lmk_order, const double *dxp, double *dxl, hipStream_t s) {
+                            const int32_t *lmk_order, const double *dxp, double *dxl, hipStream_t s, int dp) {
     if (n_chunks <= 0) return;
-    size_t lds = (size_t)(max_slots * 9 + 3 * kTile) * sizeof(double);
-    hipLaunchKernelGGL(k_backsub, dim3(n_chunks), dim3(kTile), lds, s, J64, meta, tile_lmk_base, chunk_tile,
-                       chunk_part, part_cam, max_slots, vinv, bl, lmk_order, dxp, dxl);
+    size_t lds = (size_t)(max_slots * dp + 3 * kTile) * sizeof(double);
+    if (dp == 6)
+        hipLaunchKernelGGL(k_backsub<6>, dim3(n_chunks), dim3(kTile), lds, s, J64, meta, tile_lmk_base, chunk_tile,
+                           chunk_part, part_cam, max_slots, vinv, bl, lmk_order, dxp, dxl);
+    else
+        hipLaunchKernelGGL(k_backsub<9>, dim3(n_chunks), dim3(kTile), lds, s, J64, meta, tile_lmk_base, chunk_tile,
+                           chunk_part, part_cam, max_slots, vinv, bl, lmk_order, dxp, dxl);
 }
 
 }  // namespace ba

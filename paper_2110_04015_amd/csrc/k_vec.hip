@@ -11,21 +11,26 @@ namespace ba {
 
 // ---------------------------------------------------------------- preconditioner
 
+// DP x DP blocks (pose dimension 9, or 6 for extrinsics only); the factors are packed,
+// DP (DP + 1) / 2 values per camera
+template <int DP>
 __global__ void k_precond(int np, const double *__restrict__ Dchol, const double *__restrict__ r,
                           double *__restrict__ z) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= np) return;
-    double rc[9], zc[9];
-    for (int i = 0; i < 9; ++i) rc[i] = r[(int64_t)c * 9 + i];
-    chol9_solve(Dchol + (int64_t)c * 45, rc, zc);
-    for (int i = 0; i < 9; ++i) z[(int64_t)c * 9 + i] = zc[i];
+    double rc[DP], zc[DP];
+    for (int i = 0; i < DP; ++i) rc[i] = r[(int64_t)c * DP + i];
+    chol_solve_packed<DP>(Dchol + (int64_t)c * (DP * (DP + 1) / 2), rc, zc);
+    for (int i = 0; i < DP; ++i) z[(int64_t)c * DP + i] = zc[i];
 }
 
-void launch_precond(int np, const double *Dchol, const double *r, double *z, hipStream_t s) {
-    hipLaunchKernelGGL(k_precond, dim3((np + 127) / 128), dim3(128), 0, s, np, Dchol, r, z);
+void launch_precond(int np, const double *Dchol, const double *r, double *z, hipStream_t s, int dp) {
+    if (dp == 6) hipLaunchKernelGGL(k_precond<6>, dim3((np + 127) / 128), dim3(128), 0, s, np, Dchol, r, z);
+    else hipLaunchKernelGGL(k_precond<9>, dim3((np + 127) / 128), dim3(128), 0, s, np, Dchol, r, z);
 }
 
 // z = D^-1 r and per-block partial sums of sum_i a[i] * z[i]
+template <int DP>
 __global__ __launch_bounds__(kNT) void k_precond_dot(int np, const double *__restrict__ Dchol,
                                                      const double *__restrict__ r, const double *__restrict__ a,
                                                      double *__restrict__ z, double *__restrict__ partials,
@@ -34,12 +39,12 @@ __global__ __launch_bounds__(kNT) void k_precond_dot(int np, const double *__res
     __shared__ double sh[kNT];
     double acc = 0.0;
     for (int c = blockIdx.x * kNT + threadIdx.x; c < np; c += gridDim.x * kNT) {
-        double rc[9], zc[9];
-        for (int i = 0; i < 9; ++i) rc[i] = r[(int64_t)c * 9 + i];
-        chol9_solve(Dchol + (int64_t)c * 45, rc, zc);
-        for (int i = 0; i < 9; ++i) {
-            z[(int64_t)c * 9 + i] = zc[i];
-            acc += a[(int64_t)c * 9 + i] * zc[i];
+        double rc[DP], zc[DP];
+        for (int i = 0; i < DP; ++i) rc[i] = r[(int64_t)c * DP + i];
+        chol_solve_packed<DP>(Dchol + (int64_t)c * (DP * (DP + 1) / 2), rc, zc);
+        for (int i = 0; i < DP; ++i) {
+            z[(int64_t)c * DP + i] = zc[i];
+            acc += a[(int64_t)c * DP + i] * zc[i];
         }
     }
     double s = block_sum(acc, sh);
@@ -47,15 +52,17 @@ __global__ __launch_bounds__(kNT) void k_precond_dot(int np, const double *__res
 }
 
 void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const double *Q, double *z,
-                            double *partials, const double *done, hipStream_t s) {
-    hipLaunchKernelGGL(k_precond_dot, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, Q, z, partials, done);
+                            double *partials, const double *done, hipStream_t s, int dp) {
+    if (dp == 6)
+        hipLaunchKernelGGL(k_precond_dot<6>, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, Q, z, partials, done);
+    else
+        hipLaunchKernelGGL(k_precond_dot<9>, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, Q, z, partials, done);
 }
 
 
 void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_precond_dot, dim3(kRedBlocks), dim3(kNT), 0, s, np, Dchol, r, r, z, partials,
-                       (const double *)nullptr);
+                        hipStream_t s, int dp) {
+    launch_pcg_precond_phi(np, Dchol, r, r, z, partials, nullptr, s, dp);
 }
 
 // ---------------------------------------------------------------- reductions
@@ -502,7 +509,8 @@ void launch_mcg_scalars(int k, const double *prr, const double *prho, const doub
 }
 
 // Phi[col][p] = Q_hist[:, col]^T z restricted to segment p: with N > 1 subsets the
-// segments are the subsets (gs poses each, the last takes the rest), which is Phi of a
+// segments are the subsets (gs rows each -- the rows of gs poses --, the last takes the
+// rest), which is Phi of a
 // multidirectional Z; a one-column Z = D^-1 r needs their sum, which k_beta forms.  So
 // Phi does not depend on the tau-test and can run before its outcome is known.  With
 // N = 1 the rows are split into kPhiSeg equal segments (for parallelism only).  One
@@ -517,8 +525,8 @@ __global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const do
     const int p = (int)(w - col * seg);
     int64_t lo, hi;
     if (N > 1) {
-        lo = (int64_t)p * gs * 9;
-        hi = (p == N - 1) ? n : (int64_t)(p + 1) * gs * 9;
+        lo = (int64_t)p * gs;
+        hi = (p == N - 1) ? n : (int64_t)(p + 1) * gs;
     } else {
         lo = n * p / seg;
         hi = n * (p + 1) / seg;
@@ -646,7 +654,7 @@ __global__ void k_hist_final(int64_t n, int kn, int nslices, const double *__res
     if (Y) {
         base = Y[i];
     } else {
-        const int grp = multi ? min((int)(row / 9) / gs, N - 1) : 0;
+        const int grp = multi ? min((int)(row / gs), N - 1) : 0;
         base = (!multi || grp == p) ? z[row] : 0.0;
     }
     Out[i] = base - s;

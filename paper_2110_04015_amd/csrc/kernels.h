@@ -48,18 +48,29 @@ __host__ __device__ inline float bf16_to_f32(uint32_t h) {
     return f;
 }
 
-// ---- build (k_build.hip)
+// Values of one observation's record in the tile stream (pose dimension DP = 9, or 6
+// for extrinsics only): J_p rows 0, 1 then J_l rows 0, 1; 16-byte words per slot in
+// FP64 (pairs), FP32 (quads) and BF16 (octets), the last word zero-padded.
+template <int DP>
+struct RecordShape {
+    static constexpr int kVals = 2 * DP + 6;
+    static constexpr int kW64 = kVals / 2;
+    static constexpr int kW32 = (kVals + 3) / 4;
+    static constexpr int kW16 = (kVals + 7) / 8;
+};
+
+// ---- build (k_build.hip); dp = pose dimension (9 or 6)
 void launch_check_finite(const double *a, int64_t count, int32_t *status, hipStream_t s);
 void launch_pack(const int64_t *slot_obs, int64_t nslots, const double *Jp, const double *Jl, double *J64,
-                 float *J32, uint16_t *J16, hipStream_t s);
-void launch_convert(const double *J64, int64_t nslots, float *J32, uint16_t *J16, hipStream_t s);
+                 float *J32, uint16_t *J16, hipStream_t s, int dp = 9);
+void launch_convert(const double *J64, int64_t nslots, float *J32, uint16_t *J16, hipStream_t s, int dp = 9);
 void launch_landmarks(int nl, const int64_t *first_slot, const int32_t *count, const int64_t *slot_obs,
                       const double *Jl, const double *r, double lambda, double *vinv, double *bl, double *h0,
                       int32_t *status, hipStream_t s);
 void launch_cameras(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const int32_t *obs_lm,
                     const int32_t *lmk_store, const double *Jp, const double *Jl, const double *r,
                     const double *vinv, const double *h0, double lambda, double *dU, double *Dblk,
-                    double *Dchol, double *bt, int32_t *status, hipStream_t s);
+                    double *Dchol, double *bt, int32_t *status, hipStream_t s, int dp = 9);
 
 // ---- Schur products (k_schur.hip)
 struct SchurArgs {
@@ -78,6 +89,7 @@ struct SchurArgs {
     const double *done = nullptr;            // nullable: when *done != 0 the launch does nothing
     // batches (nullable): a chunk / camera of problem b does nothing when seg_skip[b] != 0
     const int32_t *chunk_seg = nullptr, *cam_seg = nullptr, *seg_skip = nullptr;
+    int dp = 9;                              // pose dimension: 9, or 6 for extrinsics only
 };
 // y = S v (partials then the camera reduction)
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s);
@@ -107,6 +119,7 @@ struct MultiArgs {
     // batches (nullable): a chunk / camera of problem b does nothing when seg_skip[b] != 0
     const int32_t *chunk_seg = nullptr, *cam_seg = nullptr, *seg_skip = nullptr;
     const double *skip = nullptr;             // nullable: when *skip != 0 the launch does nothing
+    int dp = 9;                               // pose dimension: 9, or 6 for extrinsics only
 };
 // Y[p] = S (z restricted to subset p), Y column-major [N][n]
 void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStream_t s);
@@ -115,13 +128,14 @@ void launch_schur_multi(const MultiArgs &a, const double *z, double *Y, hipStrea
 void launch_back_substitute(const double *J64, const uint32_t *meta, const int32_t *tile_lmk_base,
                             const int32_t *chunk_tile, const int32_t *chunk_part, const int32_t *part_cam,
                             int n_chunks, int max_slots, const double *vinv, const double *bl,
-                            const int32_t *lmk_order, const double *dxp, double *dxl, hipStream_t s);
+                            const int32_t *lmk_order, const double *dxp, double *dxl, hipStream_t s, int dp = 9);
 
 // ---- vectors, reductions, small dense (k_vec.hip)
 constexpr int kRedBlocks = 120;    // fixed grid of the deterministic reductions
 constexpr int kPhiSeg = 16;        // row segments of a one-column Phi (Alg. 2 reorthogonalisation)
 
-void launch_precond(int np, const double *Dchol, const double *r, double *z, hipStream_t s);
+// DP x DP block-Jacobi solves, dp = 9 or 6 (pose dimension)
+void launch_precond(int np, const double *Dchol, const double *r, double *z, hipStream_t s, int dp = 9);
 // partial dots: out[b * 2 + d] over blocks b < kRedBlocks
 void launch_dot2(int64_t n, const double *a0, const double *b0, const double *a1, const double *b1,
                  double *partials, const double *done, hipStream_t s);
@@ -138,7 +152,7 @@ void launch_pcg_init(int64_t n, const double *bt, const double *Sx, double *r, d
 void launch_pcg_update_xr(int64_t n, const double *partials_dq, double *sc, double *x, double *r,
                           const double *P, const double *Q, double *partials_rr, hipStream_t s);
 void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const double *Q, double *z,
-                            double *partials, const double *done, hipStream_t s);
+                            double *partials, const double *done, hipStream_t s, int dp = 9);
 void launch_pcg_step_end(const double *partials_rr, double *sc, double eps, int max_iter, double *trace,
                          hipStream_t s);
 void launch_pcg_update_p(int64_t n, const double *partials_phi, double *sc, const double *z, double *P,
@@ -161,7 +175,8 @@ void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, d
 void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, const double *alpha, double *x,
                           double *r, double *partials, hipStream_t s);
 // z = D^-1 r and partials of r^T z
-void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials, hipStream_t s);
+void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials, hipStream_t s,
+                        int dp = 9);
 // sc[SC_RR], sc[SC_RHO], sc[SC_T] from the partials (Alg. 2's stop and tau tests), and
 // sc[SC_SKIPM]: 0 when the next block is multidirectional (N > 1, t < tau, not converged)
 void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
@@ -169,6 +184,7 @@ void launch_mcg_scalars(int k, const double *prr, const double *prho, const doub
 // Phi segments per history column: the N subsets when N > 1 (the same for one-column
 // and multidirectional steps), kPhiSeg row segments when N = 1
 int phi_segments(int N);
+// gs: rows of one subset (subset poses times the pose dimension)
 void launch_phi(int64_t n, int h, const double *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s);
 // beta = Delta^+ Phi per history block; kn = 1 adds Phi's segments, kn = N takes them apart
 void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int64_t *blk_dp, const double *Dp,
