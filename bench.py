@@ -215,7 +215,7 @@ def main():
     avg_ms = kms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic()
-    roofline = {"bound": "hbm", "kernel": f"k_schur1<{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[args.precision] }>",
+    roofline = {"bound": "hbm", "kernel": f"k_schur1<{ {'fp64': 0, 'fp32': 1, 'bf16': 2}[args.precision] }, 9>",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 5),
@@ -248,6 +248,38 @@ def main():
                               "rel_res_true": s2.rel_res_true, "status": s2.status}
             log(f"variant {name}: {1.0 / dt:.2f} solves/s, {s2.iterations} iterations, "
                 f"residual {s2.rel_res_true:.2e}")
+
+    extrinsics = None
+    if not args.no_variants:
+        # poses of dimension 6 (intrinsics fixed): the same observations, 2 x 6 pose blocks
+        gx = ba.System.from_problem(synth.extrinsics_only(p))
+        v = torch.randn(gx.n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(v)
+        gx.matvec(v, out=y)
+        torch.cuda.synchronize()
+        gx.profile(True)
+        gx.profile_read(reset=True)
+        for _ in range(20):
+            gx.matvec(v, out=y)
+        kx, nx = gx.profile_read(reset=True)
+        gx.profile(False)
+        bx = p.n_obs * (18 * 8 + 4) + p.n_lms * 6 * 8 + gx.n * 8
+        ax = bx / (kx / max(nx, 1) * 1e-3) / 1e9
+        extrinsics = {"d_p": 6, "chunk_kernel_ms": round(kx / max(nx, 1), 5), "bytes_per_launch": int(bx),
+                      "achieved_gbs": round(ax, 1), "frac": round(ax / HBM_PEAK_GBS, 4)}
+        for name, f in [("pcg_fp64", lambda: gx.pcg(eps=1e-6, max_iter=1000)),
+                        ("mcg_fp64_N16", lambda: gx.mcg(16, args.tau, eps=1e-6, max_iter=1000))]:
+            f()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(3):
+                x, s2 = f()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) / 3
+            extrinsics[name] = {"solves_per_s": round(1.0 / dt, 3), "iterations": s2.iterations,
+                                "multi_steps": s2.multi_steps, "rel_res_true": s2.rel_res_true, "status": s2.status}
+        log(f"extrinsics only: {extrinsics}")
+        gx.close()
 
     explicit = None
     if not args.no_variants:
@@ -364,6 +396,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "explicit_schur": explicit,
+        "extrinsics_only": extrinsics,
         "batch": batch,
         "lm": lm,
     }
