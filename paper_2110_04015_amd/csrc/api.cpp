@@ -89,8 +89,8 @@ void free_all(ba_system *s) {
     dfree(s->lmk_store);
     dfree(s->obs_lm);
     dfree(s->h0);
-    dfree(s->bsr_pair_ptr);
-    dfree(s->bsr_pairs);
+    dfree(s->bsr_slot_cam);
+    dfree(s->bsr_obs_slot);
     dfree(s->meta);
     dfree(s->tile_lmk_base);
     dfree(s->chunk_tile);
@@ -460,6 +460,18 @@ void ba_free_system(ba_system *sys) {
     delete sys;
 }
 
+static BsrGather bsr_gather(const ba_system *s) {
+    BsrGather g;
+    g.cam_ptr = s->cam_obs_ptr;
+    g.cam_obs = s->cam_obs;
+    g.obs_lm = s->obs_lm;
+    g.lmk_store = s->lmk_store;
+    g.lmk_first_slot = s->lmk_first_slot;
+    g.lmk_count = s->lmk_count;
+    g.slot_cam = s->bsr_slot_cam;
+    return g;
+}
+
 // Values of a system whose layout is set: checks J_p, J_l, r (device, observation
 // order of the build) for NaN/Inf, packs the Jacobian stream, and forms V_lambda^-1,
 // b_l, U_lambda's damping, D(S), its factor and b~ (eq. (9)-(15)) for s->lambda; the
@@ -487,7 +499,7 @@ static ba_status fill_values(ba_system *s, const double *J_p, const double *J_l,
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
         if (e0) (void)hipEventRecord(e0, q);
-        launch_bsr_assemble(s->np, s->bsr_pair_ptr, s->bsr_pairs, s->J64, s->vinv, s->Dblk, s->bsr_ptr, s->bsr_col,
+        launch_bsr_assemble(s->np, bsr_gather(s), s->bsr_obs_slot, s->J64, s->vinv, s->Dblk, s->bsr_ptr, s->bsr_col,
                             s->bsr_max_row, s->bsr_val, q);
         if (e1) (void)hipEventRecord(e1, q);
         if (hipStreamSynchronize(q) == hipSuccess && e0 && e1) {
@@ -592,29 +604,52 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
         // explicit S in block-sparse rows, assembled from the same blocks (Sec. 3.2, 4.1): the
         // pattern and the contribution pairs depend on the observations only
         if (cam_seg) return bail(fail(BA_ERR_UNSUPPORTED, "batches use the implicit S products"));
-        std::vector<int32_t> rp, cl;
+        // camera of every observation slot and slot of every observation (host, from the plan)
+        std::vector<int32_t> scam((size_t)nslots, 0);
+        std::vector<int64_t> oslot((size_t)m, 0);
+        for (int64_t sl = 0; sl < nslots; ++sl) {
+            const int64_t o = P.slot_obs[(size_t)sl];
+            if (o < 0) continue;
+            scam[(size_t)sl] = P.obs_cam[(size_t)o];
+            oslot[(size_t)o] = sl;
+        }
+        if ((st = upload(&s->bsr_slot_cam, scam, q)) != BA_OK) return bail(st);
+        if ((st = upload(&s->bsr_obs_slot, oslot, q)) != BA_OK) return bail(st);
+        // pattern on the device: block counts per row, then the rows' columns
+        int32_t *d_nnz = nullptr;
+        if ((st = dalloc(&d_nnz, (size_t)s->np)) != BA_OK) return bail(st);
+        launch_bsr_rowcount(s->np, bsr_gather(s), d_nnz, q);
+        std::vector<int32_t> nnz((size_t)s->np);
+        const bool cnt_ok = hipGetLastError() == hipSuccess &&
+                            hipMemcpyAsync(nnz.data(), d_nnz, (size_t)s->np * 4, hipMemcpyDeviceToHost, q) == hipSuccess &&
+                            hipStreamSynchronize(q) == hipSuccess;
+        dfree(d_nnz);
+        if (!cnt_ok) return bail(fail(BA_ERR_HIP, "explicit S: pattern count failed"));
+        std::vector<int32_t> rp((size_t)s->np + 1, 0);
         int max_row = 0;
-        build_bsr_pattern(P, hlm.data(), rp, cl, max_row);
+        for (int j = 0; j < s->np; ++j) {
+            if ((int64_t)rp[(size_t)j] + nnz[(size_t)j] > (int64_t)INT32_MAX)
+                return bail(fail(BA_ERR_UNSUPPORTED, "explicit S: too many nonzero blocks"));
+            rp[(size_t)j + 1] = rp[(size_t)j] + nnz[(size_t)j];
+            max_row = std::max(max_row, (int)nnz[(size_t)j]);
+        }
         int dev = 0, lds_max = 65536;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             return bail(fail(BA_ERR_HIP, "device attribute query failed"));
-        if ((size_t)max_row * 81 * sizeof(double) > (size_t)lds_max)
+        if ((size_t)max_row * (81 * sizeof(double) + sizeof(int32_t)) > (size_t)lds_max)
             return bail(fail(BA_ERR_UNSUPPORTED, "explicit S: a camera is covisible with " + std::to_string(max_row) +
                                                      " cameras, more than one work-group's LDS holds"));
-        if (nslots > (int64_t)INT32_MAX) return bail(fail(BA_ERR_UNSUPPORTED, "explicit S: too many observations"));
-        std::vector<int64_t> pptr;
-        std::vector<int32_t> prs;
-        build_bsr_pairs(P, hlm.data(), rp, cl, pptr, prs);
+        if ((size_t)((s->np + 31) / 32) * 4 > (size_t)lds_max)
+            return bail(fail(BA_ERR_UNSUPPORTED, "explicit S: too many cameras for the pattern bitmap"));
         if ((st = upload(&s->bsr_ptr, rp, q)) != BA_OK) return bail(st);
-        if ((st = upload(&s->bsr_col, cl, q)) != BA_OK) return bail(st);
-        if ((st = upload(&s->bsr_pair_ptr, pptr, q)) != BA_OK) return bail(st);
-        if ((st = upload(&s->bsr_pairs, prs, q)) != BA_OK) return bail(st);
-        s->bsr_nnzb = (int64_t)cl.size();
+        s->bsr_nnzb = (int64_t)rp[(size_t)s->np];
         s->bsr_max_row = max_row;
+        if ((st = dalloc(&s->bsr_col, (size_t)std::max<int64_t>(s->bsr_nnzb, 1))) != BA_OK) return bail(st);
+        launch_bsr_rowfill(s->np, bsr_gather(s), s->bsr_ptr, s->bsr_col, q);
         if ((st = dalloc(&s->bsr_val, (size_t)s->bsr_nnzb * 81)) != BA_OK) return bail(st);
-        if (hipStreamSynchronize(q) != hipSuccess)   // the host vectors above go out of scope
-            return bail(fail(BA_ERR_HIP, "explicit S: pattern upload failed"));
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(q) != hipSuccess)   // host vectors go out of scope
+            return bail(fail(BA_ERR_HIP, "explicit S: pattern failed"));
     }
     if ((st = fill_values(s, d->J_p, d->J_l, d->r)) != BA_OK) return bail(st);
     if ((st = ensure_pinned(s)) != BA_OK) return bail(st);

@@ -97,17 +97,6 @@ struct DevMulti {
 };
 
 // Plan construction (host, plan.cpp).  Returns BA_OK or an error with message.
-// Block pattern of the explicit S: for camera j, the sorted cameras sharing a landmark
-// with it (j included).  max_row: most blocks in a row.
-void build_bsr_pattern(const HostPlan &plan, const int32_t *lm, std::vector<int32_t> &row_ptr,
-                       std::vector<int32_t> &col, int &max_row);
-// Off-diagonal contributions of every block row, in the row's observation order and then
-// observer order: (slot of camera j's observation, slot of the co-observer, landmark
-// storage index, block of the co-observer in the row), four int32 each, padded with
-// block -1 to 64 per row; pair_ptr[j] is the row's first pair.
-void build_bsr_pairs(const HostPlan &plan, const int32_t *lm, const std::vector<int32_t> &row_ptr,
-                     const std::vector<int32_t> &col, std::vector<int64_t> &pair_ptr,
-                     std::vector<int32_t> &pairs);
 // cam_seg (nullable, host, [np], nondecreasing): problem of every camera of a batch
 ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_t *lm,
                      int max_slots, int max_tiles, HostPlan &plan, std::string &err,
@@ -160,8 +149,8 @@ struct ba_system {
     int32_t *lmk_store = nullptr;   // observation -> storage index of its landmark
     int32_t *obs_lm = nullptr;      // copy of the observations' landmarks
     double *h0 = nullptr;           // nl * 3: V^-1 b_l (storage order)
-    int64_t *bsr_pair_ptr = nullptr;// explicit S: contribution pairs per block row
-    int32_t *bsr_pairs = nullptr;
+    int32_t *bsr_slot_cam = nullptr;// explicit S: camera of every observation slot
+    int64_t *bsr_obs_slot = nullptr;// explicit S: slot of every observation
     int bsr_max_row = 0;
     // solver scratch (allocated on demand)
     double *vec = nullptr;          // work vectors

@@ -30,15 +30,95 @@ __device__ __forceinline__ void w_of_slot(const double *__restrict__ J64, int64_
         for (int c = 0; c < 3; ++c) W[r * 3 + c] = v[r] * v[18 + c] + v[9 + r] * v[21 + c];
 }
 
-// One wavefront per block row j.  Its contributions (o, q) -- camera j's observation o
-// of landmark l and co-observer q, in observation then observer order -- come 64 per
-// step; lane i adds -W_o V_l^-1 W_q^T into the row's block of q's camera with LDS
-// atomics.  One wavefront issues all of them, so the additions into one block happen
-// in program order and, within an instruction, in lane order: the sums are
-// reproducible.
-__global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__ pair_ptr,
-                                                     const int4 *__restrict__ pairs, const double *__restrict__ J64,
-                                                     const double *__restrict__ vinv, const double *__restrict__ Dblk,
+// ---- pattern on the device: row j's columns are the cameras that share a landmark
+// with camera j (j included).  One work-group per row marks them in an LDS bitmap of
+// n_cams bits (every observation o of camera j, then every observation slot of o's
+// landmark); the set bits, read in word order, are the row's columns in ascending order.
+__device__ void row_bitmap(int j, const int64_t *__restrict__ cam_ptr, const int64_t *__restrict__ cam_obs,
+                           const int32_t *__restrict__ obs_lm, const int32_t *__restrict__ lmk_store,
+                           const int64_t *__restrict__ lmk_first_slot, const int32_t *__restrict__ lmk_count,
+                           const int32_t *__restrict__ slot_cam, int nwords, uint32_t *bm) {
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) bm[w] = 0u;
+    __syncthreads();
+    for (int64_t u = cam_ptr[j] + threadIdx.x; u < cam_ptr[j + 1]; u += blockDim.x) {
+        const int s = lmk_store[obs_lm[cam_obs[u]]];
+        const int64_t f = lmk_first_slot[s];
+        const int c = lmk_count[s];
+        for (int q = 0; q < c; ++q) {
+            const int k = slot_cam[f + q];
+            atomicOr(&bm[k >> 5], 1u << (k & 31));
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_bsr_rowcount(int nwords, const int64_t *__restrict__ cam_ptr,
+                                                      const int64_t *__restrict__ cam_obs,
+                                                      const int32_t *__restrict__ obs_lm,
+                                                      const int32_t *__restrict__ lmk_store,
+                                                      const int64_t *__restrict__ lmk_first_slot,
+                                                      const int32_t *__restrict__ lmk_count,
+                                                      const int32_t *__restrict__ slot_cam, int32_t *__restrict__ nnz) {
+    extern __shared__ uint32_t bm[];
+    __shared__ int part[256 / 64];
+    const int j = blockIdx.x;
+    row_bitmap(j, cam_ptr, cam_obs, obs_lm, lmk_store, lmk_first_slot, lmk_count, slot_cam, nwords, bm);
+    int c = 0;
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) c += __popc(bm[w]);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) nnz[j] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Writes row j's columns (ascending) at col[row_ptr[j] ...]: words are taken 256 at a
+// time, each thread's set bits go after the set bits of the words before it.
+__global__ __launch_bounds__(256) void k_bsr_rowfill(int nwords, const int64_t *__restrict__ cam_ptr,
+                                                     const int64_t *__restrict__ cam_obs,
+                                                     const int32_t *__restrict__ obs_lm,
+                                                     const int32_t *__restrict__ lmk_store,
+                                                     const int64_t *__restrict__ lmk_first_slot,
+                                                     const int32_t *__restrict__ lmk_count,
+                                                     const int32_t *__restrict__ slot_cam,
+                                                     const int32_t *__restrict__ row_ptr, int32_t *__restrict__ col) {
+    extern __shared__ uint32_t bm[];
+    __shared__ int scan[256];
+    const int j = blockIdx.x;
+    row_bitmap(j, cam_ptr, cam_obs, obs_lm, lmk_store, lmk_first_slot, lmk_count, slot_cam, nwords, bm);
+    int base = row_ptr[j];
+    for (int w0 = 0; w0 < nwords; w0 += 256) {
+        const int w = w0 + (int)threadIdx.x;
+        const uint32_t bits = w < nwords ? bm[w] : 0u;
+        scan[threadIdx.x] = __popc(bits);
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {   // inclusive scan (Hillis-Steele)
+            const int add = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += add;
+            __syncthreads();
+        }
+        int pos = base + scan[threadIdx.x] - __popc(bits);
+        for (uint32_t b = bits; b; b &= b - 1) col[pos++] = w * 32 + __ffs(b) - 1;
+        base += scan[255];
+        __syncthreads();
+    }
+}
+
+// One wavefront per block row j: the row's blocks in LDS; camera j's observations 64 at a
+// time, lane i taking observation o (of landmark l) and adding -W_o V_l^-1 W_q^T into the
+// block of q's camera for every other observation q of l, in slot order.  One wavefront
+// issues all the LDS atomics of a row, so they resolve in program order and, within an
+// instruction, in lane order: the sums are reproducible.  The diagonal block is D(S)_j.
+__global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__ cam_ptr,
+                                                     const int64_t *__restrict__ cam_obs,
+                                                     const int32_t *__restrict__ obs_lm,
+                                                     const int32_t *__restrict__ lmk_store,
+                                                     const int64_t *__restrict__ lmk_first_slot,
+                                                     const int32_t *__restrict__ lmk_count,
+                                                     const int32_t *__restrict__ slot_cam,
+                                                     const int64_t *__restrict__ obs_slot,
+                                                     const double *__restrict__ J64, const double *__restrict__ vinv,
+                                                     const double *__restrict__ Dblk,
                                                      const int32_t *__restrict__ row_ptr,
                                                      const int32_t *__restrict__ col, double *__restrict__ val) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -46,32 +126,46 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
     const int lane = threadIdx.x;
     const int b0 = row_ptr[j], nb = row_ptr[j + 1] - b0;
     double *acc = reinterpret_cast<double *>(smem);
+    int32_t *rc = reinterpret_cast<int32_t *>(acc + (size_t)nb * 81);
     for (int e = lane; e < nb * 81; e += 64) acc[e] = 0.0;
+    for (int e = lane; e < nb; e += 64) rc[e] = col[b0 + e];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int64_t t = pair_ptr[j] + lane; t < pair_ptr[j + 1]; t += 64) {
-        const int4 pr = pairs[t];
-        if (pr.w >= 0) {
-            double Wo[27], Wq[27], G[27];
-            w_of_slot(J64, pr.x, Wo);
-            w_of_slot(J64, pr.y, Wq);
-            const double *vi = vinv + (int64_t)pr.z * 6;
-            const double v0 = vi[0], v1 = vi[1], v2 = vi[2], v3 = vi[3], v4 = vi[4], v5 = vi[5];
+    for (int64_t u = cam_ptr[j] + lane; u < cam_ptr[j + 1]; u += 64) {
+        const int64_t o = cam_obs[u];
+        const int s = lmk_store[obs_lm[o]];
+        const int64_t f = lmk_first_slot[s];
+        const int c = lmk_count[s];
+        double Wo[27], G[27];
+        w_of_slot(J64, obs_slot[o], Wo);
+        const double *vi = vinv + (int64_t)s * 6;
+        const double v0 = vi[0], v1 = vi[1], v2 = vi[2], v3 = vi[3], v4 = vi[4], v5 = vi[5];
 #pragma unroll
-            for (int r = 0; r < 9; ++r) {   // G = W_o V^-1 (V^-1 symmetric, packed)
-                const double x0 = Wo[r * 3], x1 = Wo[r * 3 + 1], x2 = Wo[r * 3 + 2];
-                G[r * 3] = x0 * v0 + x1 * v1 + x2 * v2;
-                G[r * 3 + 1] = x0 * v1 + x1 * v3 + x2 * v4;
-                G[r * 3 + 2] = x0 * v2 + x1 * v4 + x2 * v5;
+        for (int r = 0; r < 9; ++r) {   // G = W_o V^-1 (V^-1 symmetric, packed)
+            const double x0 = Wo[r * 3], x1 = Wo[r * 3 + 1], x2 = Wo[r * 3 + 2];
+            G[r * 3] = x0 * v0 + x1 * v1 + x2 * v2;
+            G[r * 3 + 1] = x0 * v1 + x1 * v3 + x2 * v4;
+            G[r * 3 + 2] = x0 * v2 + x1 * v4 + x2 * v5;
+        }
+        for (int q = 0; q < c; ++q) {
+            const int k = slot_cam[f + q];
+            if (k == j) continue;
+            int lo = 0, hi = nb - 1;   // block of column k (present: k shares landmark l)
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (rc[mid] < k) lo = mid + 1;
+                else hi = mid;
             }
-            double *blk = acc + (size_t)pr.w * 81;
+            double Wq[27];
+            w_of_slot(J64, f + q, Wq);
+            double *blk = acc + (size_t)lo * 81;
 #pragma unroll
             for (int r = 0; r < 9; ++r)
 #pragma unroll
-                for (int c = 0; c < 9; ++c)
-                    atomicAdd(&blk[r * 9 + c],
-                              -(G[r * 3] * Wq[c * 3] + G[r * 3 + 1] * Wq[c * 3 + 1] + G[r * 3 + 2] * Wq[c * 3 + 2]));
+                for (int cc = 0; cc < 9; ++cc)
+                    atomicAdd(&blk[r * 9 + cc],
+                              -(G[r * 3] * Wq[cc * 3] + G[r * 3 + 1] * Wq[cc * 3 + 1] + G[r * 3 + 2] * Wq[cc * 3 + 2]));
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -81,7 +175,7 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
     int lo = 0, hi = nb - 1;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (col[b0 + mid] < j) lo = mid + 1;
+        if (rc[mid] < j) lo = mid + 1;
         else hi = mid;
     }
     for (int e = lane; e < 81; e += 64) acc[(size_t)lo * 81 + e] = Dblk[(int64_t)j * 81 + e];
@@ -173,12 +267,24 @@ __global__ __launch_bounds__(64) void k_bsr_mm_grouped(int np, int N, int64_t n,
     }
 }
 
-void launch_bsr_assemble(int np, const int64_t *pair_ptr, const int32_t *pairs, const double *J64, const double *vinv,
+void launch_bsr_rowcount(int np, const BsrGather &g, int32_t *nnz, hipStream_t s) {
+    const int nwords = (np + 31) / 32;
+    hipLaunchKernelGGL(k_bsr_rowcount, dim3(np), dim3(256), (size_t)nwords * 4, s, nwords, g.cam_ptr, g.cam_obs,
+                       g.obs_lm, g.lmk_store, g.lmk_first_slot, g.lmk_count, g.slot_cam, nnz);
+}
+
+void launch_bsr_rowfill(int np, const BsrGather &g, const int32_t *row_ptr, int32_t *col, hipStream_t s) {
+    const int nwords = (np + 31) / 32;
+    hipLaunchKernelGGL(k_bsr_rowfill, dim3(np), dim3(256), (size_t)nwords * 4, s, nwords, g.cam_ptr, g.cam_obs,
+                       g.obs_lm, g.lmk_store, g.lmk_first_slot, g.lmk_count, g.slot_cam, row_ptr, col);
+}
+
+void launch_bsr_assemble(int np, const BsrGather &g, const int64_t *obs_slot, const double *J64, const double *vinv,
                          const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, double *val,
                          hipStream_t s) {
-    const size_t lds = (size_t)max_row * 81 * sizeof(double);
-    hipLaunchKernelGGL(k_bsr_assemble, dim3(np), dim3(64), lds, s, pair_ptr, reinterpret_cast<const int4 *>(pairs),
-                       J64, vinv, Dblk, row_ptr, col, val);
+    const size_t lds = (size_t)max_row * (81 * sizeof(double) + sizeof(int32_t));
+    hipLaunchKernelGGL(k_bsr_assemble, dim3(np), dim3(64), lds, s, g.cam_ptr, g.cam_obs, g.obs_lm, g.lmk_store,
+                       g.lmk_first_slot, g.lmk_count, g.slot_cam, obs_slot, J64, vinv, Dblk, row_ptr, col, val);
 }
 
 void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,

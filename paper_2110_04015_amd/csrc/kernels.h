@@ -211,8 +211,20 @@ void launch_adam(float *P, const float *g, float *m, float *v, int t, float lr, 
 
 
 // ---------------------------------------------------------------- explicit S (block-sparse rows)
-// rows assembled from the contribution pairs of build_bsr_pairs (pairs: 4 int32 each)
-void launch_bsr_assemble(int np, const int64_t *pair_ptr, const int32_t *pairs, const double *J64, const double *vinv,
+// The observation structure the explicit S is formed from: observations camera by
+// camera, their landmarks' storage index, and each landmark's observation slots
+struct BsrGather {
+    const int64_t *cam_ptr = nullptr, *cam_obs = nullptr;
+    const int32_t *obs_lm = nullptr, *lmk_store = nullptr;
+    const int64_t *lmk_first_slot = nullptr;
+    const int32_t *lmk_count = nullptr;
+    const int32_t *slot_cam = nullptr;        // camera of every observation slot
+};
+// nonzero blocks per block row; then the rows' columns (ascending) at row_ptr
+void launch_bsr_rowcount(int np, const BsrGather &g, int32_t *nnz, hipStream_t s);
+void launch_bsr_rowfill(int np, const BsrGather &g, const int32_t *row_ptr, int32_t *col, hipStream_t s);
+// block values (9 x 9, row-major per block); obs_slot: slot of every observation
+void launch_bsr_assemble(int np, const BsrGather &g, const int64_t *obs_slot, const double *J64, const double *vinv,
                          const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, double *val,
                          hipStream_t s);
 void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,

@@ -382,68 +382,4 @@ ba_status build_multi_plan(const HostPlan &P, int N, int max_out, HostMultiPlan 
     return BA_OK;
 }
 
-void build_bsr_pattern(const HostPlan &P, const int32_t *lm, std::vector<int32_t> &row_ptr,
-                       std::vector<int32_t> &col, int &max_row) {
-    const int np = P.np;
-    row_ptr.assign((size_t)np + 1, 0);
-    col.clear();
-    max_row = 0;
-    std::vector<int32_t> stamp((size_t)np, -1), row;
-    for (int j = 0; j < np; ++j) {
-        row.clear();
-        for (int64_t u = P.cam_obs_ptr[(size_t)j]; u < P.cam_obs_ptr[(size_t)j + 1]; ++u) {
-            const int s = P.lmk_store[(size_t)lm[(size_t)P.cam_obs[(size_t)u]]];
-            const int64_t f = P.lmk_first_slot[(size_t)s];
-            for (int q = 0; q < P.lmk_count[(size_t)s]; ++q) {
-                const int k = P.obs_cam[(size_t)P.slot_obs[(size_t)(f + q)]];
-                if (stamp[(size_t)k] != j) {
-                    stamp[(size_t)k] = j;
-                    row.push_back(k);
-                }
-            }
-        }
-        std::sort(row.begin(), row.end());
-        col.insert(col.end(), row.begin(), row.end());
-        row_ptr[(size_t)j + 1] = (int32_t)col.size();
-        max_row = std::max(max_row, (int)row.size());
-    }
-}
-
-void build_bsr_pairs(const HostPlan &P, const int32_t *lm, const std::vector<int32_t> &row_ptr,
-                     const std::vector<int32_t> &col, std::vector<int64_t> &pair_ptr,
-                     std::vector<int32_t> &pairs) {
-    const int np = P.np;
-    std::vector<int64_t> obs_slot((size_t)P.m, -1);
-    for (size_t sl = 0; sl < P.slot_obs.size(); ++sl)
-        if (P.slot_obs[sl] >= 0) obs_slot[(size_t)P.slot_obs[sl]] = (int64_t)sl;
-    pair_ptr.assign((size_t)np + 1, 0);
-    pairs.clear();
-    for (int j = 0; j < np; ++j) {
-        const int32_t *rc = col.data() + row_ptr[(size_t)j];
-        const int nb = row_ptr[(size_t)j + 1] - row_ptr[(size_t)j];
-        for (int64_t u = P.cam_obs_ptr[(size_t)j]; u < P.cam_obs_ptr[(size_t)j + 1]; ++u) {
-            const int64_t o = P.cam_obs[(size_t)u];
-            const int s = P.lmk_store[(size_t)lm[(size_t)o]];
-            const int64_t f = P.lmk_first_slot[(size_t)s];
-            for (int q = 0; q < P.lmk_count[(size_t)s]; ++q) {
-                const int64_t sq = f + q;
-                const int k = P.obs_cam[(size_t)P.slot_obs[(size_t)sq]];
-                if (k == j) continue;
-                const int b = (int)(std::lower_bound(rc, rc + nb, k) - rc);
-                pairs.push_back((int32_t)obs_slot[(size_t)o]);
-                pairs.push_back((int32_t)sq);
-                pairs.push_back(s);
-                pairs.push_back(b);
-            }
-        }
-        while ((pairs.size() / 4) % kTile != 0) {
-            pairs.push_back(0);
-            pairs.push_back(0);
-            pairs.push_back(0);
-            pairs.push_back(-1);
-        }
-        pair_ptr[(size_t)j + 1] = (int64_t)(pairs.size() / 4);
-    }
-}
-
 }  // namespace ba
