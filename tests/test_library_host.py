@@ -98,7 +98,7 @@ def test_host_argument_errors(L):
     out = C.c_void_p()
     assert L.ba_build_system(None, None, None, C.byref(out)) == _lib.BA_ERR_INVALID_ARG
     d = _lib.ProblemDesc()
-    d.n_cams, d.n_lms, d.n_obs, d.d_p = 4, 10, 20, 6
+    d.n_cams, d.n_lms, d.n_obs, d.d_p = 4, 10, 20, 7          # d_p must be 6 or 9
     assert L.ba_build_system(C.byref(d), None, None, C.byref(out)) == _lib.BA_ERR_INVALID_ARG
     assert "d_p" in L.ba_last_error().decode()
     d.d_p = 9
