@@ -115,6 +115,7 @@ void free_all(ba_system *s) {
     dfree(s->hist);
     dfree(s->small);
     dfree(s->hscratch);
+    dfree(s->tickets);
     dfree(s->refine_buf);
     dfree(s->Ulr);
     dfree(s->degree);
@@ -336,6 +337,19 @@ ba_status ensure_red(ba_system *s, size_t doubles) {
     ba_status st = dalloc(&s->red, doubles);
     if (st != BA_OK) return st;
     s->red_cap = doubles;
+    return BA_OK;
+}
+
+// arrival counters of the last-block reductions: zero on allocation, and every kernel
+// that takes one leaves it zero
+ba_status ensure_tickets(ba_system *s, int64_t count) {
+    if (s->tickets_cap >= count) return BA_OK;
+    dfree(s->tickets);
+    s->tickets_cap = 0;
+    ba_status st = dalloc(&s->tickets, (size_t)count);
+    if (st != BA_OK) return st;
+    HIPCHK(hipMemsetAsync(s->tickets, 0, (size_t)count * sizeof(uint32_t), s->stream));
+    s->tickets_cap = count;
     return BA_OK;
 }
 
@@ -918,24 +932,28 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     }
     const int64_t hc = s->hist_cap_cols;
     double *Ph = s->hist, *Qh = s->hist + hc * n;
-    // small storage: Dp (64 * cap), Phi (cap * max(N, kPhiSeg)), beta (cap * N), gamma, alpha (64 each),
-    // block tables
+    // small storage: Dp (64 * cap), Phi (cap * max(N, kPhiSeg)), beta (cap * hist_ldb(N)), gamma,
+    // alpha (64 each), block tables
     const int phiw = std::max(N, kPhiSeg);
-    const size_t small_need = (size_t)(64 * hc + hc * phiw + hc * N + 128) + (size_t)(3 * hc + 8);
+    const int ldb = hist_ldb(N);
+    const size_t small_need = (size_t)(64 * hc + hc * phiw + hc * ldb + 128) + (size_t)(3 * hc + 8);
     if (s->small_cap < small_need) {
         dfree(s->small);
         s->small_cap = 0;
         if ((st = dalloc(&s->small, small_need)) != BA_OK) return st;
         s->small_cap = small_need;
     }
-    double *Dp = s->small, *Phi = Dp + 64 * hc, *beta = Phi + hc * phiw, *gamma = beta + hc * N, *alpha = gamma + 64;
+    double *Dp = s->small, *Phi = Dp + 64 * hc, *beta = Phi + hc * phiw, *gamma = beta + hc * ldb, *alpha = gamma + 64;
     int32_t *blk_off = reinterpret_cast<int32_t *>(alpha + 64);
     int32_t *blk_k = blk_off + hc;
     int64_t *blk_dp = reinterpret_cast<int64_t *>(blk_k + hc + 2);
     if ((st = ensure_vec(s, (size_t)n * 4 + SC_COUNT)) != BA_OK) return st;
-    if ((st = ensure_red(s, (size_t)kRedBlocks * (64 * 64 + 64))) != BA_OK) return st;
-    // split-K scratch of the history products: at least one column slice of 64 outputs
-    const int64_t hs_need = std::max<int64_t>(kHistScratch, 64 * n);
+    if ((st = ensure_red(s, std::max<size_t>((size_t)kRedBlocks * (64 * 64 + 64),
+                                             2 * (size_t)mcg_xrz_blocks(s->np, s->dp)))) != BA_OK)
+        return st;
+    if ((st = ensure_tickets(s, 1)) != BA_OK) return st;   // the iteration-end kernel's
+    // split-K scratch of the history products: at least one column slice of both matrices
+    const int64_t hs_need = std::max<int64_t>(kHistScratch, hist_scratch_min(n, N));
     if (s->hscratch_cap < hs_need) {
         dfree(s->hscratch);
         s->hscratch_cap = 0;
@@ -995,19 +1013,28 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             // x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i ; Z = D^-1 r_{i+1}, and the
             // tau-test scalars before the single read-back of the iteration:
             // t_i = gamma_i^T alpha_i / (r_{i+1}^T D^-1 r_{i+1})
-            launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
-            launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q, s->dp);
-            if (lowrank) launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
-            launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, N, tau, opts.eps, q);
+            if (lowrank) {
+                launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
+                launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q, s->dp);
+                launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
+                launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, N, tau, opts.eps, q);
+            } else {
+                launch_mcg_xrz(s->np, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, s->Dchol, z,
+                               red, s->tickets, gamma, sc, N, tau, opts.eps, q, s->dp);
+            }
             if ((st = scalars_post(s, sc)) != BA_OK) return st;
-            // Work that does not wait for the tau-test goes ahead of the read-back, so the
-            // device is busy while the host waits for it: Phi_{i,j} = Q_j^T Z_{i+1} per
-            // subset (valid for either outcome), and S Z_{i+1} of a multidirectional step,
-            // which the kernels skip on the device when sc[SC_SKIPM] says the step is not one.
+            // Everything up to the next iteration's Gram products goes ahead of the read-back,
+            // so the device stays busy while the host waits for it: Phi_{i,j} = Q_j^T Z_{i+1}
+            // per subset (valid for either outcome), then the kernels of both outcomes of
+            // the tau-test, each taking the branch from the device's own scalars (the width
+            // sc[SC_KN] of the new block, or skip flags): beta, the new block's P (and, for
+            // a multidirectional block, Q) columns, and S Z_{i+1} or S P_{i+1}.
             double *Pn = Ph + hcols * n, *Qn = Qh + hcols * n;
-            const bool ahead = N > 1 && hcols + N <= hc;
+            const bool ahead = N > 1 && hcols + N <= hc;   // room for a multidirectional block
+            const bool room1 = hcols + 1 <= hc;
+            const int kn_max = ahead ? N : room1 ? 1 : 0;
             launch_phi(n, (int)hcols, Qh, z, N, gs, Phi, q);
-            if (ahead) {
+            if (ahead) {   // Y = S Z, the base of the new Q columns
                 if (use_bsr_multi) {
                     launch_bsr_mm_grouped(s->np, N, s->bsr_ptr, s->bsr_col, s->bsr_val, s->multi.group, z, Qn, q,
                                           sc + SC_SKIPM);
@@ -1017,8 +1044,22 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                     launch_schur_multi(mp, z, Qn, q);
                 }
             }
+            // beta_{i,j} = Delta_j^+ Phi_{i,j}; P_{i+1} = Z - sum P_j beta;
+            // multidirectional: Q_{i+1} = S Z - sum Q_j beta (eq. (19))
+            launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, sc, kn_max, N, beta, q);
+            launch_update_pq(n, (int)hcols, N, kn_max, Ph, Qh, beta, z, gs, sc, Pn, Qn, s->hscratch,
+                             s->hscratch_cap, q);
+            bool spec_pair = false;   // the product's profiling events, dropped if it is skipped
+            if (room1) {   // one-column block: Q_{i+1} = S P_{i+1}
+                SchurArgs s1 = sa;
+                s1.done = sc + SC_SKIPS;
+                const size_t pu0 = s->prof_used;
+                matvec(s, s1, Pn, Qn);
+                spec_pair = s->prof_used != pu0;
+            }
             HIPCHK(hipGetLastError());
             if ((st = scalars_wait(s, h)) != BA_OK) return st;
+            if (spec_pair && h[SC_KN] != 1.0) s->prof_used -= 2;   // a skipped launch is no kernel work
             if (h[SC_RANK] == 0.0) {
                 result = BA_ERR_BREAKDOWN;
                 g_err = "MCG breakdown: Delta_i is numerically zero";
@@ -1032,35 +1073,23 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 if (stats->trace_t) stats->trace_t[ti] = NAN;
                 if (stats->trace_k) stats->trace_k[ti] = 0;
             }
-            if (std::sqrt(rr) < opts.eps * std::sqrt(rr0)) {
+            // the stop test and the tau-test are the device's (sc[SC_KN]: 0 once
+            // |r| < eps |r_0|), so the host follows the blocks the device built
+            const int kn = (int)h[SC_KN];
+            if (kn == 0) {
                 result = BA_OK;
                 break;
             }
             const double t_i = h[SC_T];
-            if (N > 1 && t_i < tau && !ahead) {
-                result = fail(BA_ERR_WORKSPACE, "MCG direction history is full (raise max_history_cols)");
-                break;
-            }
-            // The branch is the one the device took for S Z_{i+1}: the same t_i < tau test on
-            // the same value; its stop test only differs from the host's at an exact tie,
-            // where a one-column step is taken.
-            const bool multi = ahead && h[SC_SKIPM] == 0.0;
-            const int kn = multi ? N : 1;
             if (stats && ti < stats->trace_cap) {
                 if (stats->trace_t) stats->trace_t[ti] = t_i;
                 if (stats->trace_k) stats->trace_k[ti] = kn;
             }
-            if (hcols + kn > hc) {
+            if (kn < 1 || kn > kn_max) {   // the device built nothing
                 result = fail(BA_ERR_WORKSPACE, "MCG direction history is full (raise max_history_cols)");
                 break;
             }
-            // beta_{i,j} = Delta_j^+ Phi_{i,j}
-            launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, kn, N, beta, q);
-            // P_{i+1} = Z - sum P_j beta ; multidirectional: Q_{i+1} = S Z - sum Q_j beta (eq. (19))
-            launch_update_pq(n, (int)hcols, kn, Ph, Qh, beta, z, multi ? 1 : 0, gs, N, multi ? Qn : nullptr, Pn,
-                             multi ? Qn : nullptr, s->hscratch, s->hscratch_cap, q);
-            if (!multi) matvec(s, sa, Pn, Qn);                           // Q_{i+1} = S P_{i+1}
-            HIPCHK(hipGetLastError());
+            const bool multi = kn > 1;
             hoff.push_back((int32_t)hcols);
             hk.push_back(kn);
             hdp.push_back(dp_used);
@@ -1452,7 +1481,7 @@ ba_status ensure_batch_ws(ba_batch *b, int N, int64_t cap) {
     if ((st = dalloc(&b->Qh, (size_t)hb)) != BA_OK) return st;
     if ((st = dalloc(&b->Dp, (size_t)cb * N)) != BA_OK) return st;
     if ((st = dalloc(&b->Phi, (size_t)cb * N)) != BA_OK) return st;
-    if ((st = dalloc(&b->beta, (size_t)cb * N)) != BA_OK) return st;
+    if ((st = dalloc(&b->beta, (size_t)cb * hist_ldb(N))) != BA_OK) return st;
     if ((st = dalloc(&b->blk_off, (size_t)cb)) != BA_OK) return st;
     if ((st = dalloc(&b->blk_k, (size_t)cb)) != BA_OK) return st;
     if ((st = dalloc(&b->blk_dp, (size_t)cb)) != BA_OK) return st;

@@ -160,6 +160,8 @@ struct ba_system {
     double *hist = nullptr;         // MCG history (P then Q)
     int64_t hist_cap_cols = 0;
     double *small = nullptr;        // MCG small dense storage
+    uint32_t *tickets = nullptr;    // arrival counters of last-block reductions (zero between launches)
+    int64_t tickets_cap = 0;
     double *hscratch = nullptr;     // split-K partials of the history products
     int64_t hscratch_cap = 0;       // doubles
     double *refine_buf = nullptr;   // mixed precision: outer residual, inner right-hand side, update

@@ -338,20 +338,60 @@ __global__ __launch_bounds__(kNT) void k_bbeta(int N, const BatchProb *__restric
     const double *D = Dp + P.colbase * N + blk_dp[P.colbase + j];
     const double *F = Phi + P.colbase * N;
     const int kn = d.kn;
-    for (int w = threadIdx.x; w < kj * kn; w += kNT) {
-        const int a = w / kn, p = w - a * kn;
+    // rows of hist_ldb(N) values; a multidirectional block's are padded with zeros
+    const int ldb = hist_ldb(N), w_row = kn == 1 ? 1 : ldb;
+    for (int w = threadIdx.x; w < kj * w_row; w += kNT) {
+        const int a = w / w_row, p = w - a * w_row;
         double s = 0.0;
-        for (int c = 0; c < kj; ++c) {
-            double f;
-            if (kn == 1) {
-                f = 0.0;
-                for (int q = 0; q < N; ++q) f += F[(int64_t)(off + c) * N + q];
-            } else {
-                f = F[(int64_t)(off + c) * N + p];
+        if (p < kn) {
+            for (int c = 0; c < kj; ++c) {
+                double f;
+                if (kn == 1) {
+                    f = 0.0;
+                    for (int q = 0; q < N; ++q) f += F[(int64_t)(off + c) * N + q];
+                } else {
+                    f = F[(int64_t)(off + c) * N + p];
+                }
+                s += D[a * kj + c] * f;
             }
-            s += D[a * kj + c] * f;
         }
-        beta[(P.colbase + off + a) * N + p] = s;
+        beta[(P.colbase + off + a) * ldb + p] = s;
+    }
+}
+
+// Sums over the history of one row: ap[j] += sum_col P_hist[row, col] beta[col][j]
+// (and aq with Q_hist), four columns per step so that four loads per lane are in flight.
+// beta rows are ldb long; outputs beyond the block's width read the zero padding.
+template <int KB, bool WITH_Q>
+__device__ inline void bhist_rows(const double *__restrict__ ph, const double *__restrict__ qh, int64_t n, int h,
+                                  const double *__restrict__ bt, int ldb, double *ap, double *aq) {
+    int col = 0;
+    for (; col + 4 <= h; col += 4) {
+        double hp[4], hq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            hp[u] = ph[(int64_t)(col + u) * n];
+            if (WITH_Q) hq[u] = qh[(int64_t)(col + u) * n];
+        }
+        const double *bc = bt + (int64_t)col * ldb;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int j = 0; j < KB; ++j) {
+                ap[j] += hp[u] * bc[u * ldb + j];
+                if (WITH_Q) aq[j] += hq[u] * bc[u * ldb + j];
+            }
+        }
+    }
+    for (; col < h; ++col) {
+        const double hp = ph[(int64_t)col * n];
+        const double hq = WITH_Q ? qh[(int64_t)col * n] : 0.0;
+        const double *bc = bt + (int64_t)col * ldb;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+            ap[j] += hp * bc[j];
+            if (WITH_Q) aq[j] += hq * bc[j];
+        }
     }
 }
 
@@ -373,42 +413,34 @@ __global__ __launch_bounds__(64) void k_bhist(int N, int64_t ntot, const BatchPr
     const BatchProb P = prob[b];
     const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (row >= P.n) return;
-    const bool multi = d.multi != 0;
-    const double *bt = beta + P.colbase * N;
+    const int ldb = hist_ldb(N);
+    const double *bt = beta + P.colbase * ldb;
+    const double *ph = Ph + P.hbase + row;
+    const double *qh = Qh + P.hbase + row;
+    const double zr = z[P.row0 + row];
+    if (!d.multi) {   // one-column block: P only; S P_new is formed from the staging vector
+        double ap = 0.0;
+        bhist_rows<1, false>(ph, qh, P.n, d.hcols, bt, ldb, &ap, nullptr);
+        const double pn = zr - ap;
+        Ph[P.hbase + (int64_t)d.hcols * P.n + row] = pn;
+        pstage[P.row0 + row] = pn;
+        return;
+    }
     double ap[KB], aq[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
         ap[j] = 0.0;
         aq[j] = 0.0;
     }
-    const double *ph = Ph + P.hbase + row;
-    const double *qh = Qh + P.hbase + row;
-    for (int col = 0; col < d.hcols; ++col) {
-        const double hp = ph[(int64_t)col * P.n];
-        const double hq = multi ? qh[(int64_t)col * P.n] : 0.0;
-        const double *bc = bt + (int64_t)col * N + p0;
-#pragma unroll
-        for (int j = 0; j < KB; ++j) {
-            if (p0 + j < d.kn) {
-                ap[j] += hp * bc[j];
-                aq[j] += hq * bc[j];
-            }
-        }
-    }
-    const double zr = z[P.row0 + row];
+    bhist_rows<KB, true>(ph, qh, P.n, d.hcols, bt + p0, ldb, ap, aq);
     const int grp = subset_of((int)(row / 9), P.gs, N);
 #pragma unroll
     for (int j = 0; j < KB; ++j) {
         const int p = p0 + j;
         if (p >= d.kn) continue;
-        const double base = multi ? (grp == p ? zr : 0.0) : zr;
-        const double pn = base - ap[j];
-        Ph[P.hbase + (int64_t)(d.hcols + p) * P.n + row] = pn;
-        if (multi) {
-            Qh[P.hbase + (int64_t)(d.hcols + p) * P.n + row] = Y[(int64_t)p * ntot + P.row0 + row] - aq[j];
-        } else {
-            pstage[P.row0 + row] = pn;
-        }
+        const double base = grp == p ? zr : 0.0;
+        Ph[P.hbase + (int64_t)(d.hcols + p) * P.n + row] = base - ap[j];
+        Qh[P.hbase + (int64_t)(d.hcols + p) * P.n + row] = Y[(int64_t)p * ntot + P.row0 + row] - aq[j];
     }
 }
 

@@ -484,6 +484,25 @@ void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, co
     hipLaunchKernelGGL(k_update_xr_blk, dim3(kRedBlocks), dim3(kNT), 0, s, n, k, P, Q, alpha, x, r, partials);
 }
 
+// Alg. 2's stop test and tau-test from |r_{i+1}|^2 and rho = r_{i+1}^T M^-1 r_{i+1}:
+// t_i = gamma_i^T alpha_i / rho; sc[SC_SKIPM], sc[SC_KN] and sc[SC_SKIPS] give the next
+// block's width to the kernels launched ahead of the host's read-back (one thread)
+__device__ inline void mcg_scalars_store(double rr, double rho, int k, const double *__restrict__ gamma,
+                                         const double *__restrict__ alpha, double *__restrict__ sc, int N,
+                                         double tau, double eps) {
+    double ga = 0.0;
+    for (int a = 0; a < k; ++a) ga += gamma[a] * alpha[a];
+    const double t = rho > 0.0 ? ga / rho : INFINITY;
+    sc[SC_RR] = rr;
+    sc[SC_RHO] = rho;
+    sc[SC_T] = t;
+    const bool converged = sqrt(rr) < eps * sqrt(sc[SC_RR0]);
+    const bool multi = N > 1 && t < tau && !converged;
+    sc[SC_SKIPM] = multi ? 0.0 : 1.0;
+    sc[SC_KN] = converged ? 0.0 : multi ? (double)N : 1.0;
+    sc[SC_SKIPS] = (!converged && !multi) ? 0.0 : 1.0;
+}
+
 // sc[SC_RR] from the |r|^2 partials; rho = r^T M^-1 r from its partials; t = gamma^T alpha / rho
 __global__ __launch_bounds__(64) void k_mcg_scalars(int k, const double *__restrict__ prr,
                                                     const double *__restrict__ prho,
@@ -493,14 +512,92 @@ __global__ __launch_bounds__(64) void k_mcg_scalars(int k, const double *__restr
     const double rr = wave_partials(prr, 1, kRedBlocks);
     const double rho = wave_partials(prho, 1, kRedBlocks);
     if (threadIdx.x != 0) return;
-    double ga = 0.0;
-    for (int a = 0; a < k; ++a) ga += gamma[a] * alpha[a];
-    const double t = rho > 0.0 ? ga / rho : INFINITY;
-    sc[SC_RR] = rr;
-    sc[SC_RHO] = rho;
-    sc[SC_T] = t;
-    const bool converged = sqrt(rr) < eps * sqrt(sc[SC_RR0]);
-    sc[SC_SKIPM] = (N > 1 && t < tau && !converged) ? 0.0 : 1.0;
+    mcg_scalars_store(rr, rho, k, gamma, alpha, sc, N, tau, eps);
+}
+
+// One kernel for the end of an iteration of Alg. 2 with the block-Jacobi preconditioner:
+// x += P alpha, r -= Q alpha (n x k blocks, column-major), Z = D^-1 r, and the scalars.
+// Block b owns the poses [b CB, (b + 1) CB) (CB = kNT / DP), so the rows it updates are
+// the rows its D^-1 solves read (kept in LDS).  Each block leaves its |r|^2 and r^T z in
+// partials[2 b], [2 b + 1]; the block that arrives last (an agent-scope counter, reset to
+// zero by that block) adds them in block order and stores the scalars.
+template <int DP>
+__global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__restrict__ P,
+                                                 const double *__restrict__ Q, const double *__restrict__ alpha,
+                                                 double *__restrict__ x, double *__restrict__ r,
+                                                 const double *__restrict__ Dchol, double *__restrict__ z,
+                                                 double *__restrict__ partials, uint32_t *__restrict__ ticket,
+                                                 const double *__restrict__ gamma, double *__restrict__ sc, int N,
+                                                 double tau, double eps) {
+    constexpr int CB = kNT / DP;
+    __shared__ double sr[CB * DP];
+    __shared__ double sh[kNT];
+    __shared__ double al[kMaxK];
+    __shared__ int last;
+    const int64_t n = (int64_t)np * DP;
+    const int c0 = blockIdx.x * CB;
+    const int cams = min(CB, np - c0);
+    const int t = threadIdx.x;
+    for (int a = t; a < k; a += kNT) al[a] = alpha[a];
+    __syncthreads();
+    double rr = 0.0;
+    if (t < cams * DP) {
+        const int64_t i = (int64_t)c0 * DP + t;
+        double dx = 0.0, dr = 0.0;
+        for (int a = 0; a < k; ++a) {
+            dx += P[(int64_t)a * n + i] * al[a];
+            dr += Q[(int64_t)a * n + i] * al[a];
+        }
+        x[i] += dx;
+        const double v = r[i] - dr;
+        r[i] = v;
+        sr[t] = v;
+        rr = v * v;
+    }
+    __syncthreads();
+    double rho = 0.0;
+    if (t < cams) {
+        double rc[DP], zc[DP];
+#pragma unroll
+        for (int e = 0; e < DP; ++e) rc[e] = sr[t * DP + e];
+        chol_solve_packed<DP>(Dchol + (int64_t)(c0 + t) * (DP * (DP + 1) / 2), rc, zc);
+#pragma unroll
+        for (int e = 0; e < DP; ++e) {
+            z[(int64_t)(c0 + t) * DP + e] = zc[e];
+            rho += rc[e] * zc[e];
+        }
+    }
+    rr = block_sum(rr, sh);
+    rho = block_sum(rho, sh);
+    if (t == 0) {
+        partials[2 * blockIdx.x] = rr;
+        partials[2 * blockIdx.x + 1] = rho;
+        const uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || t >= 64) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const double srr = wave_partials(partials, 2, gridDim.x);
+    const double srho = wave_partials(partials + 1, 2, gridDim.x);
+    if (t == 0) {
+        mcg_scalars_store(srr, srho, k, gamma, alpha, sc, N, tau, eps);
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+int mcg_xrz_blocks(int np, int dp) { return (np + kNT / dp - 1) / (kNT / dp); }
+
+void launch_mcg_xrz(int np, int k, const double *P, const double *Q, const double *alpha, double *x, double *r,
+                    const double *Dchol, double *z, double *partials, uint32_t *ticket, const double *gamma,
+                    double *sc, int N, double tau, double eps, hipStream_t s, int dp) {
+    const unsigned nb = (unsigned)mcg_xrz_blocks(np, dp);
+    if (dp == 6)
+        hipLaunchKernelGGL(k_mcg_xrz<6>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
+                           ticket, gamma, sc, N, tau, eps);
+    else
+        hipLaunchKernelGGL(k_mcg_xrz<9>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
+                           ticket, gamma, sc, N, tau, eps);
 }
 
 void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
@@ -556,12 +653,23 @@ void launch_phi(int64_t n, int h, const double *Qh, const double *z, int N, int 
                        Phi);
 }
 
+// Width of the block being built, as the device decided it (sc[SC_KN]: 0 once converged,
+// N for a multidirectional block, else 1); 0 as well when it exceeds kn_max, the widest
+// block the host has room for (the host then stops with a workspace error).
+__device__ inline int next_kn(const double *__restrict__ sc, int kn_max) {
+    const int kn = (int)sc[SC_KN];
+    return kn > kn_max ? 0 : kn;
+}
+
 // beta rows of history block j: beta[off_j + a][p] = sum_b Delta_j^+[a][b] Phi[off_j + b][p]
+// for the next block's width kn (next_kn); rows of hist_ldb(kn) values
 __global__ __launch_bounds__(kNT) void k_beta(const int32_t *__restrict__ blk_off, const int32_t *__restrict__ blk_k,
                                               const int64_t *__restrict__ blk_dp, const double *__restrict__ Dp,
-                                              const double *__restrict__ Phi, int kn, int seg,
-                                              double *__restrict__ beta) {
+                                              const double *__restrict__ Phi, const double *__restrict__ sc,
+                                              int kn_max, int seg, double *__restrict__ beta) {
     __shared__ double f1[kMaxK];
+    const int kn = next_kn(sc, kn_max);
+    if (kn == 0) return;
     const int j = blockIdx.x;
     const int off = blk_off[j], kj = blk_k[j];
     const double *D = Dp + blk_dp[j];
@@ -580,125 +688,145 @@ __global__ __launch_bounds__(kNT) void k_beta(const int32_t *__restrict__ blk_of
         }
         return;
     }
-    for (int w = threadIdx.x; w < kj * kn; w += kNT) {   // multidirectional: segment p is subset p
-        const int a = w / kn, p = w - a * kn;
+    // multidirectional: segment p is subset p; rows are padded with zeros to hist_ldb(kn)
+    const int ldb = hist_ldb(kn);
+    for (int w = threadIdx.x; w < kj * ldb; w += kNT) {
+        const int a = w / ldb, p = w - a * ldb;
         double s = 0.0;
-        for (int b = 0; b < kj; ++b) s += D[a * kj + b] * Phi[(int64_t)(off + b) * seg + p];
-        beta[(int64_t)(off + a) * kn + p] = s;
+        if (p < kn)
+            for (int b = 0; b < kj; ++b) s += D[a * kj + b] * Phi[(int64_t)(off + b) * seg + p];
+        beta[(int64_t)(off + a) * ldb + p] = s;
     }
 }
 
 void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int64_t *blk_dp, const double *Dp,
-                 const double *Phi, int kn, int N, double *beta, hipStream_t s) {
-    hipLaunchKernelGGL(k_beta, dim3(nb), dim3(kNT), 0, s, blk_off, blk_k, blk_dp, Dp, Phi, kn, phi_segments(N), beta);
+                 const double *Phi, const double *sc, int kn_max, int N, double *beta, hipStream_t s) {
+    hipLaunchKernelGGL(k_beta, dim3(nb), dim3(kNT), 0, s, blk_off, blk_k, blk_dp, Dp, Phi, sc, kn_max,
+                       phi_segments(N), beta);
 }
 
 // History products of the reorthogonalisation, Out[:, p] = Base[:, p] - sum_col H[:, col] beta[col][p]
 // (Alg. 2: P_{i+1} = Z - sum_j P_j beta_{i,j}; eq. (19): Q_{i+1} = S Z - sum_j Q_j beta_{i,j}).
-// Pass 1: one wavefront per (64-row tile, column slice, block of KB outputs) accumulates
-// its slice; beta is wave-uniform (scalar loads).  Pass 2 adds the slices in slice order
-// and subtracts from the base, so the result is independent of scheduling.
+// The width kn of the new block is read on the device (next_kn), so the launches go
+// ahead of the host's read-back of the tau-test.  Pass 1: one wavefront per (64-row tile,
+// column slice, matrix, block of outputs) accumulates its slice; beta is wave-uniform
+// (scalar loads) and its rows, hist_ldb(kn) long, are padded with zeros, so the inner
+// loops carry no per-output test.  Pass 2 adds the slices in slice order and subtracts
+// from the base, so the result is independent of scheduling.
 template <int KB>
-__global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, int kn, int slice_cols,
-                                                     const double *__restrict__ H,
-                                                     const double *__restrict__ beta,
-                                                     double *__restrict__ scratch) {
-    const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    const int ks = blockIdx.y;
-    const int p0 = blockIdx.z * KB;
-    const int c0 = ks * slice_cols;
-    const int c1 = min(h, c0 + slice_cols);
+__device__ inline void hist_slice(int64_t n, int64_t row, int c0, int c1, int kn, int p0,
+                                  const double *__restrict__ H, const double *__restrict__ beta,
+                                  double *__restrict__ out) {
+    const int ldb = hist_ldb(kn);
     double acc[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) acc[j] = 0.0;
-    if (row < n) {
-        const double *hp = H + row;
-        int c = c0;
-        // eight columns per step: eight loads of the history in flight per lane
-        for (; c + 8 <= c1; c += 8) {
-            double hv[8];
+    const double *hp = H + row;
+    int c = c0;
+    // CU columns per step: CU loads of the history in flight per lane (fewer for wide
+    // output blocks, whose beta values fill the scalar registers)
+    constexpr int CU = KB > 16 ? 4 : 8;
+    for (; c + CU <= c1; c += CU) {
+        double hv[CU];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) hv[u] = hp[(int64_t)(c + u) * n];
-            const double *b0 = beta + (int64_t)c * kn + p0;
+        for (int u = 0; u < CU; ++u) hv[u] = hp[(int64_t)(c + u) * n];
+        const double *b0 = beta + (int64_t)c * ldb + p0;
 #pragma unroll
-            for (int j = 0; j < KB; ++j) {
-                if (p0 + j < kn) {
+        for (int u = 0; u < CU; ++u) {
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) acc[j] += hv[u] * b0[u * kn + j];
-                }
-            }
+            for (int j = 0; j < KB; ++j) acc[j] += hv[u] * b0[u * ldb + j];
         }
-        for (; c < c1; ++c) {
-            const double hv = hp[(int64_t)c * n];
-            const double *b0 = beta + (int64_t)c * kn + p0;
-#pragma unroll
-            for (int j = 0; j < KB; ++j)
-                if (p0 + j < kn) acc[j] += hv * b0[j];
-        }
-#pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (p0 + j < kn) scratch[((int64_t)ks * kn + p0 + j) * n + row] = acc[j];
     }
+    for (; c < c1; ++c) {
+        const double hv = hp[(int64_t)c * n];
+        const double *b0 = beta + (int64_t)c * ldb + p0;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] += hv * b0[j];
+    }
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+        if (p0 + j < kn) out[(int64_t)(p0 + j) * n + row] = acc[j];
 }
 
-__global__ void k_hist_final(int64_t n, int kn, int nslices, const double *__restrict__ scratch,
-                             const double *__restrict__ z, int multi, int gs, int N, const double *__restrict__ Y,
-                             double *__restrict__ Out) {
+// grid (row tiles, slices, 2 * zb): z < zb the P history, z >= zb the Q history (used by
+// multidirectional blocks only); zb output blocks of KBW columns (KBW = 16 or 32)
+template <int KBW>
+__global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, int slice_cols, int nslices, int zb,
+                                                     const double *__restrict__ Ph, const double *__restrict__ Qh,
+                                                     const double *__restrict__ beta, const double *__restrict__ sc,
+                                                     int kn_max, double *__restrict__ scratch) {
+    const int kn = next_kn(sc, kn_max);
+    const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int mat = (int)blockIdx.z / zb, p0 = ((int)blockIdx.z - mat * zb) * KBW;
+    if (kn == 0 || row >= n || p0 >= kn || (mat == 1 && kn == 1)) return;
+    const int ks = blockIdx.y;
+    const int c0 = ks * slice_cols;
+    const int c1 = min(h, c0 + slice_cols);
+    double *out = scratch + ((int64_t)mat * nslices + ks) * kn * n;
+    if (kn == 1) hist_slice<1>(n, row, c0, c1, 1, 0, Ph, beta, out);
+    else hist_slice<KBW>(n, row, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
+}
+
+// grid (x over n * kn_max, 2): y = 0 writes P_new, y = 1 Q_new (multidirectional only,
+// its base Y = S Z already in the Q columns); no slices: P_new = Z_p
+__global__ void k_hist_final(int64_t n, int nslices, const double *__restrict__ scratch,
+                             const double *__restrict__ z, int gs, int N, const double *__restrict__ sc, int kn_max,
+                             double *__restrict__ Pn, double *__restrict__ Qn) {
+    const int kn = next_kn(sc, kn_max);
+    const int mat = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * kn) return;
+    if (kn == 0 || i >= n * kn || (mat == 1 && kn == 1)) return;
     const int p = (int)(i / n);
     const int64_t row = i - (int64_t)p * n;
+    const double *sp = scratch + (int64_t)mat * nslices * kn * n;
     double s = 0.0;
-    for (int ks = 0; ks < nslices; ++ks) s += scratch[((int64_t)ks * kn + p) * n + row];
+    for (int ks = 0; ks < nslices; ++ks) s += sp[((int64_t)ks * kn + p) * n + row];
+    double *out = mat ? Qn : Pn;
     double base;
-    if (Y) {
-        base = Y[i];
+    if (mat) {
+        base = out[i];
     } else {
-        const int grp = multi ? min((int)(row / gs), N - 1) : 0;
-        base = (!multi || grp == p) ? z[row] : 0.0;
+        const int grp = kn > 1 ? min((int)(row / gs), N - 1) : 0;
+        base = (kn == 1 || grp == p) ? z[row] : 0.0;
     }
-    Out[i] = base - s;
+    out[i] = base - s;
 }
 
-int hist_slices(int64_t n, int h, int kn, int64_t scratch_doubles) {
+// column slices of the history products: enough (row tile, slice) wavefronts to fill the
+// device, at least 16 columns each, and both matrices' partials of a kn_max-wide block
+// within the scratch (the caller guarantees room for one slice)
+int hist_slices(int64_t n, int h, int kn_max, int64_t scratch_doubles) {
     const int64_t tiles = (n + 63) / 64;
     int s = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
     s = std::min(s, std::max(1, h / 16));
     s = std::min(s, 64);
-    // the caller guarantees scratch_doubles >= kn * n (one slice)
-    const int64_t per = (int64_t)kn * n;
+    const int64_t per = 2 * (int64_t)kn_max * n;
     if (per > 0) s = (int)std::max<int64_t>(1, std::min<int64_t>(s, scratch_doubles / per));
     return std::max(1, s);
 }
 
-static void launch_hist(int64_t n, int h, int kn, const double *H, const double *beta, const double *z, int multi,
-                        int gs, int N, const double *Y, double *Out, double *scratch, int64_t scratch_doubles,
-                        hipStream_t s) {
-    const int slices = hist_slices(n, h, kn, scratch_doubles);
-    const int slice_cols = (h + slices - 1) / slices;
-    const unsigned tiles = (unsigned)((n + 63) / 64);
+int64_t hist_scratch_min(int64_t n, int kn_max) { return 2 * (int64_t)kn_max * n; }
+
+void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, const double *Qh, const double *beta,
+                      const double *z, int gs, const double *sc, double *Pn, double *Qn, double *scratch,
+                      int64_t scratch_doubles, hipStream_t s) {
+    if (kn_max <= 0) return;
+    const int slices = h > 0 ? hist_slices(n, h, kn_max, scratch_doubles) : 0;
     if (h > 0) {
-        if (kn == 1) {
-            hipLaunchKernelGGL((k_hist_partial<1>), dim3(tiles, slices, 1), dim3(64), 0, s, n, h, kn, slice_cols, H,
-                               beta, scratch);
-        } else if (kn <= 16) {
-            hipLaunchKernelGGL((k_hist_partial<16>), dim3(tiles, slices, 1), dim3(64), 0, s, n, h, kn, slice_cols, H,
-                               beta, scratch);
+        const int slice_cols = (h + slices - 1) / slices;
+        const unsigned tiles = (unsigned)((n + 63) / 64);
+        if (kn_max <= 16) {
+            hipLaunchKernelGGL((k_hist_partial<16>), dim3(tiles, slices, 2), dim3(64), 0, s, n, h, slice_cols, slices,
+                               1, Ph, Qh, beta, sc, kn_max, scratch);
         } else {
-            hipLaunchKernelGGL((k_hist_partial<32>), dim3(tiles, slices, (kn + 31) / 32), dim3(64), 0, s, n, h, kn,
-                               slice_cols, H, beta, scratch);
+            const int zb = (kn_max + 31) / 32;
+            hipLaunchKernelGGL((k_hist_partial<32>), dim3(tiles, slices, 2 * zb), dim3(64), 0, s, n, h, slice_cols,
+                               slices, zb, Ph, Qh, beta, sc, kn_max, scratch);
         }
     }
-    const int64_t tot = n * kn;
-    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, kn, h > 0 ? slices : 0,
-                       scratch, z, multi, gs, N, Y, Out);
-}
-
-void launch_update_pq(int64_t n, int h, int kn, const double *Ph, const double *Qh, const double *beta,
-                      const double *z, int multi, int gs, int N, const double *Y, double *Pn, double *Qn,
-                      double *scratch, int64_t scratch_doubles, hipStream_t s) {
-    launch_hist(n, h, kn, Ph, beta, z, multi, gs, N, nullptr, Pn, scratch, scratch_doubles, s);
-    if (Y && Qn) launch_hist(n, h, kn, Qh, beta, z, multi, gs, N, Y, Qn, scratch, scratch_doubles, s);
+    const int64_t tot = n * kn_max;
+    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256), 2), dim3(256), 0, s, n, slices, scratch, z,
+                       gs, N, sc, kn_max, Pn, Qn);
 }
 
 }  // namespace ba

@@ -25,7 +25,9 @@ enum {
     SC_ITER = 12,    // completed PCG iterations
     SC_STATUS = 13,  // ba_status of the PCG loop
     SC_SKIPM = 14,   // MCG: 1 unless the next block is multidirectional (t < tau, not converged)
-    SC_COUNT = 16
+    SC_KN = 15,      // MCG: width of the next block (0 once converged, N multidirectional, else 1)
+    SC_SKIPS = 16,   // MCG: 1 unless the next block has one column
+    SC_COUNT = 20    // the last two slots: scratch of the true-residual check
 };
 
 // device status word bits
@@ -181,17 +183,36 @@ void launch_precond_rho(int np, const double *Dchol, const double *r, double *z,
 // sc[SC_SKIPM]: 0 when the next block is multidirectional (N > 1, t < tau, not converged)
 void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
                         double *sc, int N, double tau, double eps, hipStream_t s);
+// Fused end of an MCG iteration with the block-Jacobi preconditioner: x += P alpha,
+// r -= Q alpha, z = D^-1 r, and the scalars of launch_mcg_scalars, from
+// mcg_xrz_blocks(np, dp) blocks' partials (2 per block) added by the last block to arrive
+// (ticket: a zero counter, left zero)
+int mcg_xrz_blocks(int np, int dp);
+void launch_mcg_xrz(int np, int k, const double *P, const double *Q, const double *alpha, double *x, double *r,
+                    const double *Dchol, double *z, double *partials, uint32_t *ticket, const double *gamma,
+                    double *sc, int N, double tau, double eps, hipStream_t s, int dp = 9);
 // Phi segments per history column: the N subsets when N > 1 (the same for one-column
 // and multidirectional steps), kPhiSeg row segments when N = 1
 int phi_segments(int N);
 // gs: rows of one subset (subset poses times the pose dimension)
 void launch_phi(int64_t n, int h, const double *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s);
-// beta = Delta^+ Phi per history block; kn = 1 adds Phi's segments, kn = N takes them apart
+// row length of beta for a kn-column step: kn = 1 unpadded, else kn rounded up to the
+// output block of the history products (16 up to 16 columns, then multiples of 32), the
+// padding zero
+__host__ __device__ inline int hist_ldb(int kn) { return kn <= 1 ? 1 : kn <= 16 ? 16 : (kn + 31) / 32 * 32; }
+// beta = Delta^+ Phi per history block (rows of hist_ldb(kn)) for the next block's width
+// kn = sc[SC_KN] as the device decided it (nothing when 0 or above kn_max); kn = 1 adds
+// Phi's segments, kn = N takes them apart
 void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int64_t *blk_dp, const double *Dp,
-                 const double *Phi, int kn, int N, double *beta, hipStream_t s);
-void launch_update_pq(int64_t n, int h, int kn, const double *Ph, const double *Qh, const double *beta,
-                      const double *z, int multi, int gs, int N, const double *Y, double *Pn, double *Qn,
-                      double *scratch, int64_t scratch_doubles, hipStream_t s);
+                 const double *Phi, const double *sc, int kn_max, int N, double *beta, hipStream_t s);
+// The new block's P columns (Pn, kn of them) and, for a multidirectional block, its Q
+// columns (Qn, which hold S Z on entry), kn = sc[SC_KN] read on the device; kn_max is the
+// widest block the history has room for.  The scratch holds at least
+// hist_scratch_min(n, kn_max) doubles.
+void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, const double *Qh, const double *beta,
+                      const double *z, int gs, const double *sc, double *Pn, double *Qn, double *scratch,
+                      int64_t scratch_doubles, hipStream_t s);
+int64_t hist_scratch_min(int64_t n, int kn_max);
 void launch_pinv_sym(int k, const double *A, double *Ap, int32_t *rank, hipStream_t s);
 
 // ---- learned low-rank preconditioner (k_learned.hip)
