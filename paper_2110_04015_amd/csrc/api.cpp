@@ -127,6 +127,7 @@ void free_all(ba_system *s) {
     dfree(s->bsr_val);
     if (s->host_pinned) (void)hipHostFree(s->host_pinned);
     s->host_pinned = nullptr;
+    s->host_pinned_dev = nullptr;
     if (s->sc_event) (void)hipEventDestroy(s->sc_event);
     s->sc_event = nullptr;
     free_multi(s->multi);
@@ -354,8 +355,10 @@ ba_status ensure_tickets(ba_system *s, int64_t count) {
 }
 
 ba_status ensure_pinned(ba_system *s) {
-    if (!s->host_pinned)
-        HIPCHK(hipHostMalloc((void **)&s->host_pinned, SC_COUNT * sizeof(double), hipHostMallocDefault));
+    if (!s->host_pinned) {
+        HIPCHK(hipHostMalloc((void **)&s->host_pinned, SC_COUNT * sizeof(double), hipHostMallocMapped));
+        HIPCHK(hipHostGetDevicePointer((void **)&s->host_pinned_dev, s->host_pinned, 0));
+    }
     if (!s->sc_event) HIPCHK(hipEventCreateWithFlags(&s->sc_event, hipEventDisableTiming));
     return BA_OK;
 }
@@ -365,6 +368,12 @@ ba_status ensure_pinned(ba_system *s) {
 // between keep the device busy while the host waits.
 static ba_status scalars_post(ba_system *s, const double *sc) {
     HIPCHK(hipMemcpyAsync(s->host_pinned, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipEventRecord(s->sc_event, s->stream));
+    return BA_OK;
+}
+
+// Marks the point of the stream after a kernel that wrote the scalars to host_pinned itself.
+static ba_status scalars_mark(ba_system *s) {
     HIPCHK(hipEventRecord(s->sc_event, s->stream));
     return BA_OK;
 }
@@ -1018,11 +1027,12 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q, s->dp);
                 launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
                 launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, N, tau, opts.eps, q);
-            } else {
+                if ((st = scalars_post(s, sc)) != BA_OK) return st;
+            } else {   // the kernel also writes the scalars to the host
                 launch_mcg_xrz(s->np, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, s->Dchol, z,
-                               red, s->tickets, gamma, sc, N, tau, opts.eps, q, s->dp);
+                               red, s->tickets, gamma, sc, s->host_pinned_dev, N, tau, opts.eps, q, s->dp);
+                if ((st = scalars_mark(s)) != BA_OK) return st;
             }
-            if ((st = scalars_post(s, sc)) != BA_OK) return st;
             // Everything up to the next iteration's Gram products goes ahead of the read-back,
             // so the device stays busy while the host waits for it: Phi_{i,j} = Q_j^T Z_{i+1}
             // per subset (valid for either outcome), then the kernels of both outcomes of

@@ -170,6 +170,7 @@ struct ba_system {
     double *lr_proj = nullptr;      // kRedBlocks x 8 projections U^T r
     size_t small_cap = 0;
     double *host_pinned = nullptr;  // pinned host scalars
+    double *host_pinned_dev = nullptr;  // the same memory as kernels address it
     hipEvent_t sc_event = nullptr;  // marks the point of the stream where host_pinned was filled
     ba::DevMulti multi;
     // batches: problem of every camera and of every chunk of the S product (device)

@@ -527,8 +527,8 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
                                                  double *__restrict__ x, double *__restrict__ r,
                                                  const double *__restrict__ Dchol, double *__restrict__ z,
                                                  double *__restrict__ partials, uint32_t *__restrict__ ticket,
-                                                 const double *__restrict__ gamma, double *__restrict__ sc, int N,
-                                                 double tau, double eps) {
+                                                 const double *__restrict__ gamma, double *__restrict__ sc,
+                                                 double *__restrict__ host_sc, int N, double tau, double eps) {
     constexpr int CB = kNT / DP;
     __shared__ double sr[CB * DP];
     __shared__ double sh[kNT];
@@ -584,20 +584,25 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
         mcg_scalars_store(srr, srho, k, gamma, alpha, sc, N, tau, eps);
         __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (host_sc && t < SC_COUNT) {   // all the scalars, for the host's read-back
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        host_sc[t] = sc[t];
+        __threadfence_system();
+    }
 }
 
 int mcg_xrz_blocks(int np, int dp) { return (np + kNT / dp - 1) / (kNT / dp); }
 
 void launch_mcg_xrz(int np, int k, const double *P, const double *Q, const double *alpha, double *x, double *r,
                     const double *Dchol, double *z, double *partials, uint32_t *ticket, const double *gamma,
-                    double *sc, int N, double tau, double eps, hipStream_t s, int dp) {
+                    double *sc, double *host_sc, int N, double tau, double eps, hipStream_t s, int dp) {
     const unsigned nb = (unsigned)mcg_xrz_blocks(np, dp);
     if (dp == 6)
         hipLaunchKernelGGL(k_mcg_xrz<6>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
-                           ticket, gamma, sc, N, tau, eps);
+                           ticket, gamma, sc, host_sc, N, tau, eps);
     else
         hipLaunchKernelGGL(k_mcg_xrz<9>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
-                           ticket, gamma, sc, N, tau, eps);
+                           ticket, gamma, sc, host_sc, N, tau, eps);
 }
 
 void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
@@ -607,19 +612,51 @@ void launch_mcg_scalars(int k, const double *prr, const double *prho, const doub
 
 // Phi[col][p] = Q_hist[:, col]^T z restricted to segment p: with N > 1 subsets the
 // segments are the subsets (gs rows each -- the rows of gs poses --, the last takes the
-// rest), which is Phi of a
-// multidirectional Z; a one-column Z = D^-1 r needs their sum, which k_beta forms.  So
-// Phi does not depend on the tau-test and can run before its outcome is known.  With
-// N = 1 the rows are split into kPhiSeg equal segments (for parallelism only).  One
-// wavefront per (column, segment); four per block.
+// rest), which is Phi of a multidirectional Z; a one-column Z = D^-1 r needs their sum,
+// which k_beta forms.  So Phi does not depend on the tau-test and can run before its
+// outcome is known.  With N = 1 the rows are split into kPhiSeg equal segments (for
+// parallelism only).  One wavefront per (group of kPhiCols columns, segment), segments
+// of a group on consecutive wavefronts; each lane keeps four rows of every column of the
+// group in flight and loads z once for them.
+constexpr int kPhiCols = 4;
+
+template <int NC>
+__device__ inline void phi_group(int64_t n, int64_t lo, int64_t hi, const double *__restrict__ q,
+                                 const double *__restrict__ z, double *acc) {
+    const int lane = threadIdx.x & 63;
+    double a[NC][4];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[c][u] = 0.0;
+    int64_t i = lo + lane;
+    for (; i + 192 < hi; i += 256) {
+        double zv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) zv[u] = z[i + 64 * u];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[c][u] += q[(int64_t)c * n + i + 64 * u] * zv[u];
+    }
+    for (; i < hi; i += 64) {
+        const double zv = z[i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a[c][0] += q[(int64_t)c * n + i] * zv;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = wave_sum((a[c][0] + a[c][1]) + (a[c][2] + a[c][3]));
+}
+
 __global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const double *__restrict__ Qh,
                                              const double *__restrict__ z, int N, int gs,
                                              double *__restrict__ Phi) {
     const int64_t w = (int64_t)blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (w >= (int64_t)h * seg) return;
-    const int64_t col = w / seg;
-    const int p = (int)(w - col * seg);
+    const int64_t groups = (h + kPhiCols - 1) / kPhiCols;
+    if (w >= groups * seg) return;
+    const int64_t g = w / seg;
+    const int p = (int)(w - g * seg);
     int64_t lo, hi;
     if (N > 1) {
         lo = (int64_t)p * gs;
@@ -628,18 +665,18 @@ __global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const do
         lo = n * p / seg;
         hi = n * (p + 1) / seg;
     }
-    const double *q = Qh + col * n;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int64_t i = lo + lane;
-    for (; i + 192 < hi; i += 256) {   // four rows per lane in flight
-        a0 += q[i] * z[i];
-        a1 += q[i + 64] * z[i + 64];
-        a2 += q[i + 128] * z[i + 128];
-        a3 += q[i + 192] * z[i + 192];
+    const int64_t c0 = g * kPhiCols;
+    const int nc = (int)min<int64_t>(kPhiCols, h - c0);
+    const double *q = Qh + c0 * n;
+    double acc[kPhiCols];
+    switch (nc) {
+    case 4: phi_group<4>(n, lo, hi, q, z, acc); break;
+    case 3: phi_group<3>(n, lo, hi, q, z, acc); break;
+    case 2: phi_group<2>(n, lo, hi, q, z, acc); break;
+    default: phi_group<1>(n, lo, hi, q, z, acc); break;
     }
-    for (; i < hi; i += 64) a0 += q[i] * z[i];
-    const double acc = wave_sum((a0 + a1) + (a2 + a3));
-    if (lane == 0) Phi[w] = acc;
+    if (lane == 0)
+        for (int c = 0; c < nc; ++c) Phi[(c0 + c) * seg + p] = acc[c];
 }
 
 int phi_segments(int N) { return N > 1 ? N : kPhiSeg; }
@@ -647,7 +684,7 @@ int phi_segments(int N) { return N > 1 ? N : kPhiSeg; }
 void launch_phi(int64_t n, int h, const double *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s) {
     if (h <= 0) return;
     const int seg = phi_segments(N);
-    const int64_t waves = (int64_t)h * seg;
+    const int64_t waves = (int64_t)(h + kPhiCols - 1) / kPhiCols * seg;
     const int per = kNT / 64;
     hipLaunchKernelGGL(k_phi, dim3((unsigned)((waves + per - 1) / per)), dim3(kNT), 0, s, n, h, seg, Qh, z, N, gs,
                        Phi);

@@ -186,11 +186,12 @@ void launch_mcg_scalars(int k, const double *prr, const double *prho, const doub
 // Fused end of an MCG iteration with the block-Jacobi preconditioner: x += P alpha,
 // r -= Q alpha, z = D^-1 r, and the scalars of launch_mcg_scalars, from
 // mcg_xrz_blocks(np, dp) blocks' partials (2 per block) added by the last block to arrive
-// (ticket: a zero counter, left zero)
+// (ticket: a zero counter, left zero); that block also copies sc[0, SC_COUNT) to host_sc
+// (nullable: mapped host memory)
 int mcg_xrz_blocks(int np, int dp);
 void launch_mcg_xrz(int np, int k, const double *P, const double *Q, const double *alpha, double *x, double *r,
                     const double *Dchol, double *z, double *partials, uint32_t *ticket, const double *gamma,
-                    double *sc, int N, double tau, double eps, hipStream_t s, int dp = 9);
+                    double *sc, double *host_sc, int N, double tau, double eps, hipStream_t s, int dp = 9);
 // Phi segments per history column: the N subsets when N > 1 (the same for one-column
 // and multidirectional steps), kPhiSeg row segments when N = 1
 int phi_segments(int N);
