@@ -1018,7 +1018,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             be.j = nb - 1;
             be.first = off;
             be.dpo = dpo;
-            launch_pinv_alpha(k, red, kRedBlocks, Dp + dpo, gamma, alpha, sc, q, be);
+            launch_pinv_alpha(k, red, gram_blocks(k), Dp + dpo, gamma, alpha, sc, q, be);
             // x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i ; Z = D^-1 r_{i+1}, and the
             // tau-test scalars before the single read-back of the iteration:
             // t_i = gamma_i^T alpha_i / (r_{i+1}^T D^-1 r_{i+1})

@@ -73,7 +73,7 @@ __device__ __forceinline__ void chol9_solve(const double *__restrict__ L, const 
 // the pair (p, q) is skipped when |a_pq| <= (eps / 2) sqrt(|a_pp a_qq|); sweeps stop
 // when a sweep rotates nothing.  On return A holds the eigenvalues on its
 // diagonal and V the eigenvectors in its columns.
-__device__ inline void jacobi_eig(int k, double *A, double *V, double *cs, double *sn, int *flag) {
+__device__ __forceinline__ void jacobi_eig(int k, double *A, double *V, double *cs, double *sn, int *flag) {
     const int tid = threadIdx.x;
     const int kp = k + (k & 1);
     for (int w = tid; w < k * k; w += kNT) V[w] = (w / k == w % k) ? 1.0 : 0.0;
@@ -171,78 +171,107 @@ __device__ inline void jacobi_eig(int k, double *A, double *V, double *cs, doubl
     }
 }
 
-// Lower Cholesky factor of the k x k matrix M in place (right-looking, LDS);
-// returns false when a pivot is not positive.
-__device__ inline bool chol_lds(int k, double *M, int *flag) {
-    const int tid = threadIdx.x;
-    if (tid == 0) *flag = 0;
+// Sum over the block's threads: wavefront butterflies, then the wavefronts in order
+// (one barrier); every thread gets the sum.  sh holds kNT / 64 doubles.
+__device__ __forceinline__ double block_sum_waves(double v, double *sh) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int j = 0; j < k; ++j) {
-        if (tid == 0) {
-            double d = M[j * k + j];
-            if (!(d > 0.0)) {
-                *flag = 1;
-                d = 1.0;
-            }
-            M[j * k + j] = sqrt(d);
-        }
-        __syncthreads();
-        const double piv = M[j * k + j];
-        for (int i = j + 1 + tid; i < k; i += kNT) M[i * k + j] /= piv;
-        __syncthreads();
-        const int rem = k - j - 1;
-        for (int w = tid; w < rem * rem; w += kNT) {
-            const int i = j + 1 + w / rem, m = j + 1 + w % rem;
-            if (m <= i) M[i * k + m] -= M[i * k + j] * M[m * k + j];
-        }
-        __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kNT / 64; ++w) s += sh[w];
+    __syncthreads();
+    return s;
+}
+
+// Inverse of the symmetric k x k matrix A (k <= 64, LDS) into G by Gauss-Jordan
+// elimination on the diagonal pivots, every element updated in parallel (element w by
+// thread w mod kNT).  With pivot p = a_jj the step replaces a_jj by 1 / p, the rest of
+// row j by a_jc / p, the rest of column j by -a_ij / p and every other element by
+// a_ic - a_ij a_jc / p; after the k steps the matrix is A^-1, which is then symmetrised.
+// The steps alternate between G and V (one barrier each), and the thread that computes
+// the next pivot also leaves its reciprocal, so no step waits for a division.  Returns
+// (the same in every thread) whether every pivot was positive (A positive definite) and
+// |A|_F |A^-1|_F < 1e-4 / (k eps): then every eigenvalue lies above the drop threshold
+// k eps max|l| (l_min >= 1 / |A^-1|_F, l_max <= |A|_F), so A^+ = A^-1.
+__device__ __forceinline__ bool inv_gj(int k, const double *A, double *G, double *V, double *sh) {
+    constexpr int U = kMaxK * kMaxK / kNT;   // elements per thread at most
+    __shared__ double ipv[2];
+    __shared__ int nonpos;
+    const int tid = threadIdx.x;
+    const int kk = k * k;
+    int ri[U], ci[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int w = tid + u * kNT;
+        ri[u] = w / k;
+        ci[u] = w - ri[u] * k;
     }
-    return *flag == 0;
+    if (tid == 0) {
+        const double p0 = A[0];
+        nonpos = !(p0 > 0.0);
+        ipv[0] = 1.0 / (p0 > 0.0 ? p0 : 1.0);
+    }
+    __syncthreads();
+    const double *X = A;
+    double *Y = G;
+    for (int j = 0; j < k; ++j) {
+        const double ip = ipv[j & 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int w = tid + u * kNT;
+            if (w < kk) {
+                const int i = ri[u], c = ci[u];
+                const double aij = X[i * k + j], ajc = X[j * k + c];
+                double v;
+                if (i == j) v = (c == j) ? ip : ajc * ip;
+                else if (c == j) v = -aij * ip;
+                else v = X[w] - aij * ajc * ip;
+                Y[w] = v;
+                if (i == j + 1 && c == j + 1) {   // the next pivot
+                    if (!(v > 0.0)) nonpos = 1;
+                    ipv[(j + 1) & 1] = 1.0 / (v > 0.0 ? v : 1.0);
+                }
+            }
+        }
+        __syncthreads();
+        X = Y;
+        Y = (Y == G) ? V : G;
+    }
+    // X holds A^-1 (G when k is odd, V when even)
+    double fa = 0.0, fi = 0.0;
+    double sym[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int w = tid + u * kNT;
+        sym[u] = 0.0;
+        if (w < kk) {
+            sym[u] = 0.5 * (X[w] + X[ci[u] * k + ri[u]]);
+            fa += A[w] * A[w];
+            fi += sym[u] * sym[u];
+        }
+    }
+    fa = block_sum_waves(fa, sh);   // its barriers also separate the reads above from the writes below
+    fi = block_sum_waves(fi, sh);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int w = tid + u * kNT;
+        if (w < kk) G[w] = sym[u];
+    }
+    const bool pos = nonpos == 0;
+    __syncthreads();
+    return pos && sqrt(fa) * sqrt(fi) < 1e-4 / ((double)k * 2.220446049250313e-16);
 }
 
 // Moore-Penrose pseudo-inverse of the symmetric k x k matrix A (LDS, left intact),
-// result in G; V is scratch.  When the Cholesky factorisation succeeds and
-// |A|_F |A^-1|_F < 1e-4 / (k eps), every eigenvalue lies above the drop threshold
-// k eps max|l| (l_min >= 1 / |A^-1|_F, l_max <= |A|_F), so A^+ = A^-1 = L^-T L^-1 is
-// taken from the factor; otherwise the Jacobi eigendecomposition decides.
-__device__ inline void pinv_sym_lds(int k, const double *A, double *V, double *G, double *sh, double *cs, double *sn,
+// result in G; V is scratch.  The Gauss-Jordan inverse (inv_gj) is taken when it is
+// accepted; otherwise the Jacobi eigendecomposition decides.
+__device__ __forceinline__ void pinv_sym_lds(int k, const double *A, double *V, double *G, double *sh, double *cs, double *sn,
                              int *flag, int *rank_sh) {
     const int tid = threadIdx.x;
-    for (int w = tid; w < k * k; w += kNT) V[w] = A[w];
-    __syncthreads();
-    bool ok = chol_lds(k, V, flag);
-    if (ok) {
-        // G = L^-1, one column per thread
-        if (tid < k) {
-            const int c = tid;
-            for (int i = 0; i < c; ++i) G[i * k + c] = 0.0;
-            G[c * k + c] = 1.0 / V[c * k + c];
-            for (int i = c + 1; i < k; ++i) {
-                double s = 0.0;
-                for (int m = c; m < i; ++m) s += V[i * k + m] * G[m * k + c];
-                G[i * k + c] = -s / V[i * k + i];
-            }
-        }
+    if (inv_gj(k, A, G, V, sh)) {
+        if (tid == 0) *rank_sh = k;
         __syncthreads();
-        // V = A^-1 = G^T G
-        double fa = 0.0, fi = 0.0;
-        for (int w = tid; w < k * k; w += kNT) {
-            const int i = w / k, j = w - i * k;
-            double s = 0.0;
-            for (int m = (i > j ? i : j); m < k; ++m) s += G[m * k + i] * G[m * k + j];
-            V[w] = s;
-            fi += s * s;
-            fa += A[w] * A[w];
-        }
-        fa = block_sum(fa, sh);
-        fi = block_sum(fi, sh);
-        ok = sqrt(fa) * sqrt(fi) < 1e-4 / ((double)k * 2.220446049250313e-16);
-        if (ok) {
-            for (int w = tid; w < k * k; w += kNT) G[w] = V[w];
-            if (tid == 0) *rank_sh = k;
-            __syncthreads();
-            return;
-        }
+        return;
     }
     // V and G are free again: eigendecomposition of a copy of A
     for (int w = tid; w < k * k; w += kNT) G[w] = A[w];

@@ -276,6 +276,7 @@ void launch_pcg_update_p(int64_t n, const double *partials_phi, double *sc, cons
 
 constexpr int kGramOut = (kMaxK * kMaxK + kMaxK + kNT - 1) / kNT;   // outputs per thread
 constexpr int kGramLds = 64 * 1024;                                   // bytes of one row chunk
+constexpr int kGramBlocksWide = kRedBlocks;                          // blocks of a k > 1 Gram
 
 // k = 1: partials[b][0] = Q . P, partials[b][1] = P . r over a grid-stride share of
 // the rows (wavefront butterflies, then the four wavefronts in order)
@@ -361,17 +362,22 @@ __global__ __launch_bounds__(kNT) void k_gram(int64_t n, int k, int R, const dou
     }
 }
 
+// blocks of the Gram partials: wider blocks have k (k + 1) outputs per block, so fewer
+// blocks keep the pseudo-inverse kernel's sum over them short
+int gram_blocks(int k) { return k == 1 ? kRedBlocks : kGramBlocksWide; }
+
 void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
                  hipStream_t s) {
     if (k == 1) {
         hipLaunchKernelGGL(k_gram1, dim3(kRedBlocks), dim3(kNT), 0, s, n, P, Q, r, partials);
         return;
     }
-    const int64_t per = (n + kRedBlocks - 1) / kRedBlocks;
+    const int nb = gram_blocks(k);
+    const int64_t per = (n + nb - 1) / nb;
     const int64_t cap = kGramLds / (int64_t)((2 * k + 1) * sizeof(double));
     const int R = (int)std::max<int64_t>(1, std::min(per, cap));
     const size_t lds = (size_t)R * (2 * k + 1) * sizeof(double);
-    hipLaunchKernelGGL(k_gram, dim3(kRedBlocks), dim3(kNT), lds, s, n, k, R, P, Q, r, partials);
+    hipLaunchKernelGGL(k_gram, dim3(nb), dim3(kNT), lds, s, n, k, R, P, Q, r, partials);
 }
 
 // Delta (symmetrised) and gamma from the Gram partials; Delta^+; alpha = Delta^+ gamma
@@ -395,12 +401,15 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
         }
     } else {
         for (int idx = tid; idx < tot; idx += kNT) {
-            // eight independent running sums keep eight loads in flight per thread
+            // eight running sums; 24 loads in flight per thread
             double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             int b = 0;
-            for (; b + 8 <= nblocks; b += 8) {
+            for (; b + 24 <= nblocks; b += 24) {
+                double v[24];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc[u] += partials[(int64_t)(b + u) * tot + idx];
+                for (int u = 0; u < 24; ++u) v[u] = partials[(int64_t)(b + u) * tot + idx];
+#pragma unroll
+                for (int u = 0; u < 24; ++u) acc[u & 7] += v[u];
             }
             for (; b < nblocks; ++b) acc[0] += partials[(int64_t)b * tot + idx];
             const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
@@ -432,9 +441,34 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
     }
 }
 
+// k = 1: Delta^+ = 1 / Delta unless Delta is zero (or not finite), the 1 x 1 case of the
+// pseudo-inverse's rank rule, in a kernel without the k x k working storage
+__global__ __launch_bounds__(64) void k_pinv_alpha1(const double *__restrict__ partials, int nblocks,
+                                                    double *__restrict__ Dp, double *__restrict__ gamma,
+                                                    double *__restrict__ alpha, double *__restrict__ sc,
+                                                    BlockEntry blk) {
+    const double d = wave_partials(partials, 2, nblocks);       // Q^T P
+    const double g = wave_partials(partials + 1, 2, nblocks);   // P^T r
+    if (threadIdx.x != 0) return;
+    const bool nz = fabs(d) > 2.220446049250313e-16 * fabs(d);
+    const double dp = nz ? 1.0 / d : 0.0;
+    Dp[0] = dp;
+    alpha[0] = dp * g;
+    gamma[0] = g;
+    sc[SC_RANK] = nz ? 1.0 : 0.0;
+    if (blk.off) {
+        blk.off[blk.j] = blk.first;
+        blk.k[blk.j] = 1;
+        blk.dp[blk.j] = blk.dpo;
+    }
+}
+
 void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, double *gamma, double *alpha,
                        double *sc, hipStream_t s, BlockEntry blk) {
-    hipLaunchKernelGGL(k_pinv_alpha, dim3(1), dim3(kNT), 0, s, k, partials, nblocks, Dp, gamma, alpha, sc, blk);
+    if (k == 1)
+        hipLaunchKernelGGL(k_pinv_alpha1, dim3(1), dim3(64), 0, s, partials, nblocks, Dp, gamma, alpha, sc, blk);
+    else
+        hipLaunchKernelGGL(k_pinv_alpha, dim3(1), dim3(kNT), 0, s, k, partials, nblocks, Dp, gamma, alpha, sc, blk);
 }
 
 // Stand-alone symmetric pseudo-inverse (test entry point).

@@ -162,6 +162,8 @@ void launch_pcg_update_p(int64_t n, const double *partials_phi, double *sc, cons
 void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s);
 
 // MCG steps
+// partials[b][...] of b < gram_blocks(k) blocks
+int gram_blocks(int k);
 void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
                  hipStream_t s);
 // history block table entry written by the pseudo-inverse kernel (off == nullptr: none)
