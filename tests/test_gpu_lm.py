@@ -6,7 +6,13 @@ same closed forms, rounding only); F at the moved state of every LM iteration wi
 1e-8 of F at the state it moved from (each step comes from an iterative solve whose
 GPU and oracle iterates agree to about 1e-9 relative; F at a point off the
 linearisation's minimum moves to first order with the step, on the scale of the F
-it decreases from); the accept/reject sequence and the damping sequence identical.
+it decreases from), or within 4 x the spread of correct FP64 runs where that is
+larger: the largest difference between the oracle and the oracle on the same scene
+with its landmarks relabelled and its observations reordered (four such orders), which
+changes nothing but the order of the sums.  A solve that
+runs for more iterations than S has rows (the small ring scenes at small lambda, where
+the scene's gauge leaves S nearly singular) amplifies rounding differences that far.
+The accept/reject sequence and the damping sequence are identical.
 The final states are compared through their residual vectors: BA leaves a similarity
 transform of the whole scene (gauge) unfixed, along which the two paths may drift
 apart without changing any residual.
@@ -102,20 +108,36 @@ def test_update_equals_a_fresh_build(scene):
     fresh.close()
 
 
+def _relabelled_oracle_lm(p, seed, **kw):
+    """The oracle's LM loop on the same scene with the landmarks relabelled and the
+    observations reordered: the same arithmetic summed in another order."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(p.n_lms)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(p.n_lms)
+    order = rng.permutation(p.n_obs)
+    return olm.lm(synth.camera_array(p.cams), p.points[perm], p.obs_cam[order], inv[p.obs_lm[order]],
+                  p.u_obs[order], **kw)
+
+
 @pytest.mark.parametrize("solver,N", [("pcg", 1), ("mcg", 4)])
 def test_lm_loop_matches_the_oracle(scene, solver, N):
     name, p, sc, cams, X = scene
     N = min(N, p.n_cams)
     c1, X1, st = sc.lm(cams, X, solver=solver, N=N, tau=3.3)
     ref = olm.lm(synth.camera_array(p.cams), p.points, p.obs_cam, p.obs_lm, p.u_obs, solver=solver, N=N, tau=3.3)
+    alts = [_relabelled_oracle_lm(p, seed, solver=solver, N=N, tau=3.3) for seed in range(4)]
     assert st.status == ba.BA_OK
     assert st.iterations == len(ref.iters)
+    assert all(len(a.iters) == len(ref.iters) for a in alts)
     assert abs(st.cost0 - ref.cost0) < 1e-12 * ref.cost0
     assert [bool(a) for a in st.trace_accepted] == [it.accepted for it in ref.iters]
     assert np.array_equal(st.trace_lambda, [it.lam for it in ref.iters])
-    for got, it in zip(st.trace_cost, ref.iters):
-        assert abs(got - it.cost_new) < 1e-8 * it.cost_before
-    assert abs(st.cost - ref.cost) < 1e-8 * ref.iters[-1].cost_before
+    for i, (got, it) in enumerate(zip(st.trace_cost, ref.iters)):
+        spread = max(abs(a.iters[i].cost_new - it.cost_new) for a in alts)
+        assert abs(got - it.cost_new) < max(1e-8 * it.cost_before, 4.0 * spread), i
+    spread = max(abs(a.cost - ref.cost) for a in alts)
+    assert abs(st.cost - ref.cost) < max(1e-8 * ref.iters[-1].cost_before, 4.0 * spread)
     assert st.accepted == sum(it.accepted for it in ref.iters)
     r1 = _h(sc.project(c1, X1, jacobians=False)[0])
     assert rel(r1, olm.residuals(ref.cams, ref.X, p.obs_cam, p.obs_lm, p.u_obs)) < 1e-6
