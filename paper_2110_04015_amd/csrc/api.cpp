@@ -818,9 +818,11 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
     const int64_t n = (int64_t)s->np * s->dp;
     hipStream_t q = s->stream;
     if ((st = ensure_vec(s, (size_t)n * 6 + SC_COUNT)) != BA_OK) return st;
-    if ((st = ensure_red(s, (size_t)kRedBlocks * 4)) != BA_OK) return st;
+    // red: dot-product partials (pdq), |r|^2 (prr), Phi (pphi), then the camera
+    // reduction's Gram partials (pg)
+    if ((st = ensure_red(s, (size_t)kRedBlocks * 4 + 2 * (size_t)schur_gram_blocks(s->np))) != BA_OK) return st;
     double *r = s->vec, *z = r + n, *P = z + n, *Q = P + n, *tmp = Q + n, *sc = tmp + 2 * n;
-    double *pdq = s->red, *prr = pdq + kRedBlocks * 2, *pphi = prr + kRedBlocks;
+    double *pdq = s->red, *prr = pdq + kRedBlocks * 2, *pphi = prr + kRedBlocks, *pg = pphi + kRedBlocks;
     auto t0 = std::chrono::steady_clock::now();
     if ((st = init_scalars(s, sc)) != BA_OK) return st;
     if (x0) {
@@ -851,6 +853,13 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
         if (lowrank) launch_lowrank_apply(n, s->Ulr, r, P, nullptr, s->lr_proj, nullptr, nullptr, q);
         SchurArgs sa = schur_args(s, prec);
         sa.done = sc + SC_DONE;
+        // Delta_i and gamma_i from the camera reduction of Q_i = S P_i (the explicit-S
+        // product has none: two dot products instead)
+        const bool fuse = !use_bsr(s, sa);
+        if (fuse) {
+            sa.gram = pg;
+            sa.gram_r = r;
+        }
         int enqueued = 0, batch = 4;
         const size_t prof_mark = s->prof_used;
         double rr_prev = rr0;
@@ -858,8 +867,9 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
             const int nb = std::min(batch, opts.max_iter - enqueued);
             for (int b = 0; b < nb; ++b) {
                 matvec(s, sa, P, Q);                                         // Q_i = S P_i
-                launch_dot2(n, Q, P, P, r, pdq, sc + SC_DONE, q);            // Delta_i, gamma_i
-                launch_pcg_update_xr(n, pdq, sc, x, r, P, Q, prr, q);        // alpha_i, x_{i+1}, r_{i+1}
+                if (!fuse) launch_dot2(n, Q, P, P, r, pdq, sc + SC_DONE, q);  // Delta_i, gamma_i
+                launch_pcg_update_xr(n, fuse ? pg : pdq, fuse ? schur_gram_blocks(s->np) : kRedBlocks, sc, x, r, P,
+                                     Q, prr, q);                             // alpha_i, x_{i+1}, r_{i+1}
                 launch_pcg_step_end(prr, sc, opts.eps, opts.max_iter, trace_dev, q);
                 if (!lowrank) {
                     launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q, s->dp);  // Z_{i+1}, Phi_i
@@ -957,8 +967,11 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     int32_t *blk_k = blk_off + hc;
     int64_t *blk_dp = reinterpret_cast<int64_t *>(blk_k + hc + 2);
     if ((st = ensure_vec(s, (size_t)n * 4 + SC_COUNT)) != BA_OK) return st;
+    // red: the Gram partials of wide blocks, or the iteration-end kernel's partials
+    // followed by the one-column Gram partials of the camera reduction (at goff)
+    const size_t goff = 2 * (size_t)mcg_xrz_blocks(s->np, s->dp);
     if ((st = ensure_red(s, std::max<size_t>((size_t)kRedBlocks * (64 * 64 + 64),
-                                             2 * (size_t)mcg_xrz_blocks(s->np, s->dp)))) != BA_OK)
+                                             goff + 2 * (size_t)schur_gram_blocks(s->np)))) != BA_OK)
         return st;
     if ((st = ensure_tickets(s, 1)) != BA_OK) return st;   // the iteration-end kernel's
     // split-K scratch of the history products: at least one column slice of both matrices
@@ -997,9 +1010,17 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     if (rr0 > 0.0) {
         // P_0 = Z_0 = M^-1 r_0 ; Q_0 = S P_0
         const bool lowrank = opts.precond == 1;
+        // one-column blocks take Delta and gamma from the camera reduction of Q = S P
+        // (partials at red + goff), and their Delta^+ and alpha from the iteration-end kernel
+        const bool fuse1 = !lowrank && !use_bsr(s, sa);
+        SchurArgs sag = sa;
+        if (fuse1) {
+            sag.gram = red + goff;
+            sag.gram_r = r;
+        }
         launch_precond(s->np, s->Dchol, r, Ph, q, s->dp);
         if (lowrank) launch_lowrank_apply(n, s->Ulr, r, Ph, nullptr, s->lr_proj, nullptr, nullptr, q);
-        matvec(s, sa, Ph, Qh);
+        matvec(s, sag, Ph, Qh);
         std::vector<int32_t> hoff{0}, hk{1};
         std::vector<int64_t> hdp{0};
         int64_t dp_used = 1;
@@ -1010,7 +1031,6 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             const int off = hoff.back(), k = hk.back();
             const int64_t dpo = hdp.back();
             // Delta_i = Q_i^T P_i, gamma_i = P_i^T r_i, alpha_i = Delta_i^+ gamma_i
-            launch_gram(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, r, red, q);
             BlockEntry be;       // the current block's history table entry, written with its Delta^+
             be.off = blk_off;
             be.k = blk_k;
@@ -1018,7 +1038,16 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             be.j = nb - 1;
             be.first = off;
             be.dpo = dpo;
-            launch_pinv_alpha(k, red, gram_blocks(k), Dp + dpo, gamma, alpha, sc, q, be);
+            XrzGram g1;
+            if (fuse1 && k == 1) {
+                g1.part = red + goff;
+                g1.nb = schur_gram_blocks(s->np);
+                g1.Dp = Dp + dpo;
+                g1.blk = be;
+            } else {
+                launch_gram(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, r, red, q);
+                launch_pinv_alpha(k, red, gram_blocks(k), Dp + dpo, gamma, alpha, sc, q, be);
+            }
             // x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i ; Z = D^-1 r_{i+1}, and the
             // tau-test scalars before the single read-back of the iteration:
             // t_i = gamma_i^T alpha_i / (r_{i+1}^T D^-1 r_{i+1})
@@ -1030,7 +1059,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 if ((st = scalars_post(s, sc)) != BA_OK) return st;
             } else {   // the kernel also writes the scalars to the host
                 launch_mcg_xrz(s->np, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, s->Dchol, z,
-                               red, s->tickets, gamma, sc, s->host_pinned_dev, N, tau, opts.eps, q, s->dp);
+                               red, s->tickets, gamma, sc, s->host_pinned_dev, N, tau, opts.eps, q, s->dp, g1);
                 if ((st = scalars_mark(s)) != BA_OK) return st;
             }
             // Everything up to the next iteration's Gram products goes ahead of the read-back,
@@ -1061,7 +1090,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                              s->hscratch_cap, q);
             bool spec_pair = false;   // the product's profiling events, dropped if it is skipped
             if (room1) {   // one-column block: Q_{i+1} = S P_{i+1}
-                SchurArgs s1 = sa;
+                SchurArgs s1 = sag;
                 s1.done = sc + SC_SKIPS;
                 const size_t pu0 = s->prof_used;
                 matvec(s, s1, Pn, Qn);
@@ -1154,7 +1183,9 @@ static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const dou
     for (;;) {
         // outer residual in FP64: r = -b~ - S x, btp = -r (so that S d = r reads S d = -btp)
         rel = 0.0;
-        if ((st = ensure_red(s, (size_t)kRedBlocks * 4)) != BA_OK) return st;
+        // red: dot-product partials (pdq), |r|^2 (prr), Phi (pphi), then the camera
+    // reduction's Gram partials (pg)
+    if ((st = ensure_red(s, (size_t)kRedBlocks * 4 + 2 * (size_t)schur_gram_blocks(s->np))) != BA_OK) return st;
         matvec(s, schur_args(s, 0), x, tmp);
         launch_residual_refine(n, s->bt, tmp, r, btp, s->red, q);
         double *sc2 = tmp + n;   // 8 scratch doubles after the four work vectors

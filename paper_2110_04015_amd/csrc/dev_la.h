@@ -32,13 +32,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sum of nb block partials a[b * stride] by the calling wavefront (all 64 lanes must
-// call): lane l adds entries l, l + 64, ... in order, then the butterfly.  The loads of
-// all lanes are in flight together instead of one after another in a single thread.
+// call): lane l adds entries l, l + 64, ... into four running sums (entry l + 64 i goes
+// to sum i mod 4, so that four loads per lane are in flight), then the butterfly.  The
+// order is fixed by nb alone.
 __device__ __forceinline__ double wave_partials(const double *__restrict__ a, int64_t stride, int nb) {
     const int lane = threadIdx.x & 63;
-    double s = 0.0;
-    for (int b = lane; b < nb; b += 64) s += a[(int64_t)b * stride];
-    return wave_sum(s);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = lane;
+    for (; b + 192 < nb; b += 256) {
+        s0 += a[(int64_t)b * stride];
+        s1 += a[(int64_t)(b + 64) * stride];
+        s2 += a[(int64_t)(b + 128) * stride];
+        s3 += a[(int64_t)(b + 192) * stride];
+    }
+    if (b < nb) s0 += a[(int64_t)b * stride];
+    if (b + 64 < nb) s1 += a[(int64_t)(b + 64) * stride];
+    if (b + 128 < nb) s2 += a[(int64_t)(b + 128) * stride];
+    return wave_sum((s0 + s1) + (s2 + s3));
 }
 
 // z_c = D_c^-1 r_c with the packed lower Cholesky factor of a DP x DP block (row i

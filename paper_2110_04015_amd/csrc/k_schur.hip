@@ -18,6 +18,7 @@
 // and every observation of l receives a contribution in each such column.
 #include "ba_internal.h"
 #include "kernels.h"
+#include "dev_la.h"
 
 namespace ba {
 
@@ -309,21 +310,48 @@ __device__ __forceinline__ double wave_rows(const double *__restrict__ rows, int
 }
 
 // y_c = lambda diag(U_c) v_c + sum of the partial rows of camera c, which are
-// contiguous (camera-major); one wavefront per camera (wave_rows).
+// contiguous (camera-major); one wavefront per camera (wave_rows).  With gram, block b
+// also leaves gram[2 b] = sum of y_c . v_c and gram[2 b + 1] = sum of v_c . gr_c over its
+// four cameras (the Gram products Q^T P and P^T r of a one-column block, Q = S P).
 template <int DP>
 __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restrict__ ptr,
                                                  const double *__restrict__ partial,
                                                  const double *__restrict__ dU, const double *__restrict__ v,
                                                  double *__restrict__ y, const double *__restrict__ done,
                                                  const int32_t *__restrict__ cam_seg,
-                                                 const int32_t *__restrict__ seg_skip) {
+                                                 const int32_t *__restrict__ seg_skip, double *__restrict__ gram,
+                                                 const double *__restrict__ gr) {
     if (done && *done != 0.0) return;
     __shared__ double sh[4][64];
+    __shared__ double gsum[2][4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + w;
-    if (c >= np || (seg_skip && seg_skip[cam_seg[c]])) return;   // uniform per wavefront
-    const double t = wave_rows<DP>(partial, ptr[c], ptr[c + 1], sh[w]);
-    if (lane < DP) y[(int64_t)c * DP + lane] = dU[(int64_t)c * DP + lane] * v[(int64_t)c * DP + lane] + t;
+    double qp = 0.0, pr = 0.0;
+    if (c < np && !(seg_skip && seg_skip[cam_seg[c]])) {   // uniform per wavefront
+        const double t = wave_rows<DP>(partial, ptr[c], ptr[c + 1], sh[w]);
+        if (lane < DP) {
+            const int64_t i = (int64_t)c * DP + lane;
+            const double vi = v[i];
+            const double yi = dU[i] * vi + t;
+            y[i] = yi;
+            if (gram) {
+                qp = yi * vi;
+                pr = vi * gr[i];
+            }
+        }
+    }
+    if (!gram) return;   // the same for the whole launch
+    qp = wave_sum(qp);
+    pr = wave_sum(pr);
+    if (lane == 0) {
+        gsum[0][w] = qp;
+        gsum[1][w] = pr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        gram[2 * blockIdx.x] = (gsum[0][0] + gsum[0][1]) + (gsum[0][2] + gsum[0][3]);
+        gram[2 * blockIdx.x + 1] = (gsum[1][0] + gsum[1][1]) + (gsum[1][2] + gsum[1][3]);
+    }
 }
 
 void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
@@ -349,13 +377,16 @@ void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
     }
 }
 
+int schur_gram_blocks(int np) { return (np + 3) / 4; }
+
 void launch_schur_reduce(const SchurArgs &a, const double *v, double *y, hipStream_t s) {
+    const dim3 g((unsigned)schur_gram_blocks(a.np)), b(256);
     if (a.dp == 6)
-        hipLaunchKernelGGL(k_reduce1<6>, dim3((a.np + 3) / 4), dim3(256), 0, s, a.np, a.cam_part_ptr, a.partial, a.dU,
-                           v, y, a.done, a.cam_seg, a.seg_skip);
+        hipLaunchKernelGGL(k_reduce1<6>, g, b, 0, s, a.np, a.cam_part_ptr, a.partial, a.dU, v, y, a.done, a.cam_seg,
+                           a.seg_skip, a.gram, a.gram_r);
     else
-        hipLaunchKernelGGL(k_reduce1<9>, dim3((a.np + 3) / 4), dim3(256), 0, s, a.np, a.cam_part_ptr, a.partial, a.dU,
-                           v, y, a.done, a.cam_seg, a.seg_skip);
+        hipLaunchKernelGGL(k_reduce1<9>, g, b, 0, s, a.np, a.cam_part_ptr, a.partial, a.dU, v, y, a.done, a.cam_seg,
+                           a.seg_skip, a.gram, a.gram_r);
 }
 
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s) {

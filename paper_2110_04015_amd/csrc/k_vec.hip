@@ -207,7 +207,7 @@ void launch_pcg_step_end(const double *partials_rr, double *sc, double eps, int 
 
 // Delta = Q^T P, gamma = P^T r from the partials; alpha = gamma / Delta;
 // x += alpha P, r -= alpha Q; partial |r|^2
-__global__ __launch_bounds__(kNT) void k_pcg_update_xr(int64_t n, const double *__restrict__ pdq,
+__global__ __launch_bounds__(kNT) void k_pcg_update_xr(int64_t n, const double *__restrict__ pdq, int npdq,
                                                        double *__restrict__ sc, double *__restrict__ x,
                                                        double *__restrict__ r, const double *__restrict__ P,
                                                        const double *__restrict__ Q,
@@ -216,8 +216,8 @@ __global__ __launch_bounds__(kNT) void k_pcg_update_xr(int64_t n, const double *
     __shared__ double sh[kNT];
     __shared__ double s_alpha;
     if (threadIdx.x < 64) {
-        const double D = wave_partials(pdq, 2, kRedBlocks);
-        const double g = wave_partials(pdq + 1, 2, kRedBlocks);
+        const double D = wave_partials(pdq, 2, npdq);
+        const double g = wave_partials(pdq + 1, 2, npdq);
         const double al = D > 0.0 ? g / D : 0.0;
         if (threadIdx.x == 0) s_alpha = al;
         if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -240,9 +240,9 @@ __global__ __launch_bounds__(kNT) void k_pcg_update_xr(int64_t n, const double *
     if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-void launch_pcg_update_xr(int64_t n, const double *partials_dq, double *sc, double *x, double *r,
+void launch_pcg_update_xr(int64_t n, const double *partials_dq, int n_dq, double *sc, double *x, double *r,
                           const double *P, const double *Q, double *partials_rr, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_update_xr, dim3(kRedBlocks), dim3(kNT), 0, s, n, partials_dq, sc, x, r, P, Q,
+    hipLaunchKernelGGL(k_pcg_update_xr, dim3(kRedBlocks), dim3(kNT), 0, s, n, partials_dq, n_dq, sc, x, r, P, Q,
                        partials_rr);
 }
 
@@ -557,12 +557,13 @@ __global__ __launch_bounds__(64) void k_mcg_scalars(int k, const double *__restr
 // zero by that block) adds them in block order and stores the scalars.
 template <int DP>
 __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__restrict__ P,
-                                                 const double *__restrict__ Q, const double *__restrict__ alpha,
+                                                 const double *__restrict__ Q, double *alpha,
                                                  double *__restrict__ x, double *__restrict__ r,
                                                  const double *__restrict__ Dchol, double *__restrict__ z,
                                                  double *__restrict__ partials, uint32_t *__restrict__ ticket,
-                                                 const double *__restrict__ gamma, double *__restrict__ sc,
-                                                 double *__restrict__ host_sc, int N, double tau, double eps) {
+                                                 double *gamma, double *__restrict__ sc,
+                                                 double *__restrict__ host_sc, int N, double tau, double eps,
+                                                 XrzGram g1) {
     constexpr int CB = kNT / DP;
     __shared__ double sr[CB * DP];
     __shared__ double sh[kNT];
@@ -572,7 +573,34 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
     const int c0 = blockIdx.x * CB;
     const int cams = min(CB, np - c0);
     const int t = threadIdx.x;
-    for (int a = t; a < k; a += kNT) al[a] = alpha[a];
+    if (g1.part) {
+        // one-column block: Delta = Q^T P and gamma = P^T r from the camera reduction's
+        // partials, added in the same order by every block; Delta^+ = 1 / Delta unless
+        // Delta is zero (or not finite), the 1 x 1 case of the pseudo-inverse's rank rule.
+        // Block 0 stores Delta^+, gamma, alpha, the rank and the history block entry.
+        if (t < 64) {
+            const double d = wave_partials(g1.part, 2, g1.nb);
+            const double gg = wave_partials(g1.part + 1, 2, g1.nb);
+            if (t == 0) {
+                const bool nz = fabs(d) > 2.220446049250313e-16 * fabs(d);
+                const double dpv = nz ? 1.0 / d : 0.0;
+                al[0] = dpv * gg;
+                if (blockIdx.x == 0) {
+                    g1.Dp[0] = dpv;
+                    gamma[0] = gg;
+                    alpha[0] = al[0];
+                    sc[SC_RANK] = nz ? 1.0 : 0.0;
+                    if (g1.blk.off) {
+                        g1.blk.off[g1.blk.j] = g1.blk.first;
+                        g1.blk.k[g1.blk.j] = 1;
+                        g1.blk.dp[g1.blk.j] = g1.blk.dpo;
+                    }
+                }
+            }
+        }
+    } else {
+        for (int a = t; a < k; a += kNT) al[a] = alpha[a];
+    }
     __syncthreads();
     double rr = 0.0;
     if (t < cams * DP) {
@@ -627,16 +655,16 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
 
 int mcg_xrz_blocks(int np, int dp) { return (np + kNT / dp - 1) / (kNT / dp); }
 
-void launch_mcg_xrz(int np, int k, const double *P, const double *Q, const double *alpha, double *x, double *r,
-                    const double *Dchol, double *z, double *partials, uint32_t *ticket, const double *gamma,
-                    double *sc, double *host_sc, int N, double tau, double eps, hipStream_t s, int dp) {
+void launch_mcg_xrz(int np, int k, const double *P, const double *Q, double *alpha, double *x, double *r,
+                    const double *Dchol, double *z, double *partials, uint32_t *ticket, double *gamma,
+                    double *sc, double *host_sc, int N, double tau, double eps, hipStream_t s, int dp, XrzGram g1) {
     const unsigned nb = (unsigned)mcg_xrz_blocks(np, dp);
     if (dp == 6)
         hipLaunchKernelGGL(k_mcg_xrz<6>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
-                           ticket, gamma, sc, host_sc, N, tau, eps);
+                           ticket, gamma, sc, host_sc, N, tau, eps, g1);
     else
         hipLaunchKernelGGL(k_mcg_xrz<9>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
-                           ticket, gamma, sc, host_sc, N, tau, eps);
+                           ticket, gamma, sc, host_sc, N, tau, eps, g1);
 }
 
 void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,

@@ -92,7 +92,12 @@ struct SchurArgs {
     // batches (nullable): a chunk / camera of problem b does nothing when seg_skip[b] != 0
     const int32_t *chunk_seg = nullptr, *cam_seg = nullptr, *seg_skip = nullptr;
     int dp = 9;                              // pose dimension: 9, or 6 for extrinsics only
+    // nullable, single systems only: the camera reduction also leaves the partials of
+    // y^T v and v^T gram_r, gram[2 b], gram[2 b + 1] for b < schur_gram_blocks(np)
+    double *gram = nullptr;
+    const double *gram_r = nullptr;
 };
+int schur_gram_blocks(int np);
 // y = S v (partials then the camera reduction)
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s);
 void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s);
@@ -151,7 +156,9 @@ void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s)
 
 // PCG steps (scalars in sc[]: see k_vec.hip for the slot map)
 void launch_pcg_init(int64_t n, const double *bt, const double *Sx, double *r, double *partials, hipStream_t s);
-void launch_pcg_update_xr(int64_t n, const double *partials_dq, double *sc, double *x, double *r,
+// alpha from n_dq pairs of partials of P^T S P and P^T r (the dot products of
+// launch_dot2, or the Gram partials of the camera reduction)
+void launch_pcg_update_xr(int64_t n, const double *partials_dq, int n_dq, double *sc, double *x, double *r,
                           const double *P, const double *Q, double *partials_rr, hipStream_t s);
 void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const double *Q, double *z,
                             double *partials, const double *done, hipStream_t s, int dp = 9);
@@ -190,10 +197,20 @@ void launch_mcg_scalars(int k, const double *prr, const double *prho, const doub
 // mcg_xrz_blocks(np, dp) blocks' partials (2 per block) added by the last block to arrive
 // (ticket: a zero counter, left zero); that block also copies sc[0, SC_COUNT) to host_sc
 // (nullable: mapped host memory)
+// For a one-column block (g1.part set) the kernel also takes the place of the Gram and
+// pseudo-inverse kernels: Delta and gamma from the camera reduction's partials (nb blocks,
+// schur_gram_blocks), then Delta^+ into g1.Dp, gamma, alpha, sc[SC_RANK] and the block entry.
+struct XrzGram {
+    const double *part = nullptr;
+    int nb = 0;
+    double *Dp = nullptr;
+    BlockEntry blk;
+};
 int mcg_xrz_blocks(int np, int dp);
-void launch_mcg_xrz(int np, int k, const double *P, const double *Q, const double *alpha, double *x, double *r,
-                    const double *Dchol, double *z, double *partials, uint32_t *ticket, const double *gamma,
-                    double *sc, double *host_sc, int N, double tau, double eps, hipStream_t s, int dp = 9);
+void launch_mcg_xrz(int np, int k, const double *P, const double *Q, double *alpha, double *x, double *r,
+                    const double *Dchol, double *z, double *partials, uint32_t *ticket, double *gamma,
+                    double *sc, double *host_sc, int N, double tau, double eps, hipStream_t s, int dp = 9,
+                    XrzGram g1 = XrzGram());
 // Phi segments per history column: the N subsets when N > 1 (the same for one-column
 // and multidirectional steps), kPhiSeg row segments when N = 1
 int phi_segments(int N);
