@@ -1062,32 +1062,21 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                                red, s->tickets, gamma, sc, s->host_pinned_dev, N, tau, opts.eps, q, s->dp, g1);
                 if ((st = scalars_mark(s)) != BA_OK) return st;
             }
-            // Everything up to the next iteration's Gram products goes ahead of the read-back,
-            // so the device stays busy while the host waits for it: Phi_{i,j} = Q_j^T Z_{i+1}
-            // per subset (valid for either outcome), then the kernels of both outcomes of
-            // the tau-test, each taking the branch from the device's own scalars (the width
-            // sc[SC_KN] of the new block, or skip flags): beta, the new block's P (and, for
-            // a multidirectional block, Q) columns, and S Z_{i+1} or S P_{i+1}.
+            // Everything up to the next iteration's Gram products that a one-column block
+            // needs goes ahead of the read-back, so the device stays busy while the host
+            // waits for it: Phi_{i,j} = Q_j^T Z_{i+1} per subset (valid for either outcome),
+            // beta, the new block's P columns and the history sums of its Q columns, each
+            // taking the block's width from the device's scalars (sc[SC_KN]), and S P_{i+1},
+            // skipped on the device unless the block has one column.  A multidirectional
+            // block's S Z and Q columns follow the read-back.
             double *Pn = Ph + hcols * n, *Qn = Qh + hcols * n;
             const bool ahead = N > 1 && hcols + N <= hc;   // room for a multidirectional block
             const bool room1 = hcols + 1 <= hc;
             const int kn_max = ahead ? N : room1 ? 1 : 0;
             launch_phi(n, (int)hcols, Qh, z, N, gs, Phi, q);
-            if (ahead) {   // Y = S Z, the base of the new Q columns
-                if (use_bsr_multi) {
-                    launch_bsr_mm_grouped(s->np, N, s->bsr_ptr, s->bsr_col, s->bsr_val, s->multi.group, z, Qn, q,
-                                          sc + SC_SKIPM);
-                } else {
-                    MultiArgs mp = ma;
-                    mp.skip = sc + SC_SKIPM;
-                    launch_schur_multi(mp, z, Qn, q);
-                }
-            }
-            // beta_{i,j} = Delta_j^+ Phi_{i,j}; P_{i+1} = Z - sum P_j beta;
-            // multidirectional: Q_{i+1} = S Z - sum Q_j beta (eq. (19))
+            // beta_{i,j} = Delta_j^+ Phi_{i,j}; P_{i+1} = Z - sum P_j beta
             launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, sc, kn_max, N, beta, q);
-            launch_update_pq(n, (int)hcols, N, kn_max, Ph, Qh, beta, z, gs, sc, Pn, Qn, s->hscratch,
-                             s->hscratch_cap, q);
+            launch_update_pq(n, (int)hcols, N, kn_max, Ph, Qh, beta, z, gs, sc, Pn, s->hscratch, s->hscratch_cap, q);
             bool spec_pair = false;   // the product's profiling events, dropped if it is skipped
             if (room1) {   // one-column block: Q_{i+1} = S P_{i+1}
                 SchurArgs s1 = sag;
@@ -1129,6 +1118,15 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 break;
             }
             const bool multi = kn > 1;
+            if (multi) {   // Q_{i+1} = S Z - sum Q_j beta (eq. (19))
+                if (use_bsr_multi) {
+                    launch_bsr_mm_grouped(s->np, N, s->bsr_ptr, s->bsr_col, s->bsr_val, s->multi.group, z, Qn, q,
+                                          nullptr);
+                } else {
+                    launch_schur_multi(ma, z, Qn, q);
+                }
+                launch_update_q(n, (int)hcols, N, sc, Qn, s->hscratch, s->hscratch_cap, q);
+            }
             hoff.push_back((int32_t)hcols);
             hk.push_back(kn);
             hdp.push_back(dp_used);

@@ -866,13 +866,13 @@ __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, int slice
     else hist_slice<KBW>(n, row, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
 }
 
-// grid (x over n * kn_max, 2): y = 0 writes P_new, y = 1 Q_new (multidirectional only,
-// its base Y = S Z already in the Q columns); no slices: P_new = Z_p
+// y = 0 (mat0 = 0): P_new from the P slices; mat0 = 1: Q_new from the Q slices
+// (multidirectional blocks only, their base Y = S Z already in the Q columns); no
+// slices: P_new = Z_p
 __global__ void k_hist_final(int64_t n, int nslices, const double *__restrict__ scratch,
                              const double *__restrict__ z, int gs, int N, const double *__restrict__ sc, int kn_max,
-                             double *__restrict__ Pn, double *__restrict__ Qn) {
+                             int mat, double *__restrict__ Pn, double *__restrict__ Qn) {
     const int kn = next_kn(sc, kn_max);
-    const int mat = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (kn == 0 || i >= n * kn || (mat == 1 && kn == 1)) return;
     const int p = (int)(i / n);
@@ -907,8 +907,8 @@ int hist_slices(int64_t n, int h, int kn_max, int64_t scratch_doubles) {
 int64_t hist_scratch_min(int64_t n, int kn_max) { return 2 * (int64_t)kn_max * n; }
 
 void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, const double *Qh, const double *beta,
-                      const double *z, int gs, const double *sc, double *Pn, double *Qn, double *scratch,
-                      int64_t scratch_doubles, hipStream_t s) {
+                      const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
+                      hipStream_t s) {
     if (kn_max <= 0) return;
     const int slices = h > 0 ? hist_slices(n, h, kn_max, scratch_doubles) : 0;
     if (h > 0) {
@@ -924,8 +924,16 @@ void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, con
         }
     }
     const int64_t tot = n * kn_max;
-    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256), 2), dim3(256), 0, s, n, slices, scratch, z,
-                       gs, N, sc, kn_max, Pn, Qn);
+    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, slices, scratch, z, gs,
+                       N, sc, kn_max, 0, Pn, nullptr);
+}
+
+void launch_update_q(int64_t n, int h, int N, const double *sc, double *Qn, const double *scratch,
+                     int64_t scratch_doubles, hipStream_t s) {
+    const int slices = h > 0 ? hist_slices(n, h, N, scratch_doubles) : 0;
+    const int64_t tot = n * N;
+    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, slices, scratch,
+                       nullptr, 0, N, sc, N, 1, nullptr, Qn);
 }
 
 }  // namespace ba

@@ -225,13 +225,17 @@ __host__ __device__ inline int hist_ldb(int kn) { return kn <= 1 ? 1 : kn <= 16 
 // Phi's segments, kn = N takes them apart
 void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int64_t *blk_dp, const double *Dp,
                  const double *Phi, const double *sc, int kn_max, int N, double *beta, hipStream_t s);
-// The new block's P columns (Pn, kn of them) and, for a multidirectional block, its Q
-// columns (Qn, which hold S Z on entry), kn = sc[SC_KN] read on the device; kn_max is the
+// The new block's P columns (Pn, kn of them), kn = sc[SC_KN] read on the device, and the
+// history sums of its Q columns in the scratch (kept for launch_update_q); kn_max is the
 // widest block the history has room for.  The scratch holds at least
 // hist_scratch_min(n, kn_max) doubles.
 void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, const double *Qh, const double *beta,
-                      const double *z, int gs, const double *sc, double *Pn, double *Qn, double *scratch,
-                      int64_t scratch_doubles, hipStream_t s);
+                      const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
+                      hipStream_t s);
+// Q columns of a multidirectional block (N of them): Qn holds S Z on entry; the history
+// sums are those launch_update_pq left in the scratch with kn_max = N
+void launch_update_q(int64_t n, int h, int N, const double *sc, double *Qn, const double *scratch,
+                     int64_t scratch_doubles, hipStream_t s);
 int64_t hist_scratch_min(int64_t n, int kn_max);
 void launch_pinv_sym(int k, const double *A, double *Ap, int32_t *rank, hipStream_t s);
 
