@@ -130,6 +130,8 @@ void free_all(ba_system *s) {
     s->host_pinned_dev = nullptr;
     if (s->sc_event) (void)hipEventDestroy(s->sc_event);
     s->sc_event = nullptr;
+    if (s->sc_mark) (void)hipEventDestroy(s->sc_mark);
+    s->sc_mark = nullptr;
     free_multi(s->multi);
     for (hipEvent_t e : s->prof_events) (void)hipEventDestroy(e);
     s->prof_events.clear();
@@ -198,7 +200,8 @@ void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
         if (s->prof_events.size() >= 4096) profile_flush(s);
         while (s->prof_used + 2 > s->prof_events.size()) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) {
+            // timing only: no system-scope fence (no L2 writeback) at each record
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
                 launch_schur_matvec(a, v, y, s->stream);
                 return;
             }
@@ -360,6 +363,9 @@ ba_status ensure_pinned(ba_system *s) {
         HIPCHK(hipHostGetDevicePointer((void **)&s->host_pinned_dev, s->host_pinned, 0));
     }
     if (!s->sc_event) HIPCHK(hipEventCreateWithFlags(&s->sc_event, hipEventDisableTiming));
+    // after a kernel that made its host writes visible itself: no system-scope fence
+    if (!s->sc_mark)
+        HIPCHK(hipEventCreateWithFlags(&s->sc_mark, hipEventDisableTiming | hipEventDisableSystemFence));
     return BA_OK;
 }
 
@@ -369,17 +375,21 @@ ba_status ensure_pinned(ba_system *s) {
 static ba_status scalars_post(ba_system *s, const double *sc) {
     HIPCHK(hipMemcpyAsync(s->host_pinned, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipEventRecord(s->sc_event, s->stream));
+    s->sc_marked = false;
     return BA_OK;
 }
 
-// Marks the point of the stream after a kernel that wrote the scalars to host_pinned itself.
+// Marks the point of the stream after a kernel that wrote the scalars to host_pinned
+// itself and released them at system scope.
 static ba_status scalars_mark(ba_system *s) {
-    HIPCHK(hipEventRecord(s->sc_event, s->stream));
+    HIPCHK(hipEventRecord(s->sc_mark, s->stream));
+    s->sc_marked = true;
     return BA_OK;
 }
 
 static ba_status scalars_wait(ba_system *s, double *out) {
-    HIPCHK(hipEventSynchronize(s->sc_event));
+    HIPCHK(hipEventSynchronize(s->sc_marked ? s->sc_mark : s->sc_event));
+    s->sc_marked = false;
     memcpy(out, s->host_pinned, SC_COUNT * sizeof(double));
     return BA_OK;
 }

@@ -172,6 +172,8 @@ struct ba_system {
     double *host_pinned = nullptr;  // pinned host scalars
     double *host_pinned_dev = nullptr;  // the same memory as kernels address it
     hipEvent_t sc_event = nullptr;  // marks the point of the stream where host_pinned was filled
+    hipEvent_t sc_mark = nullptr;   // the same after a kernel that wrote host_pinned itself
+    bool sc_marked = false;         // the last mark is sc_mark
     ba::DevMulti multi;
     // batches: problem of every camera and of every chunk of the S product (device)
     int32_t *seg_cam = nullptr, *seg_chunk = nullptr;
