@@ -828,11 +828,14 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
     const int64_t n = (int64_t)s->np * s->dp;
     hipStream_t q = s->stream;
     if ((st = ensure_vec(s, (size_t)n * 6 + SC_COUNT)) != BA_OK) return st;
-    // red: dot-product partials (pdq), |r|^2 (prr), Phi (pphi), then the camera
-    // reduction's Gram partials (pg)
-    if ((st = ensure_red(s, (size_t)kRedBlocks * 4 + 2 * (size_t)schur_gram_blocks(s->np))) != BA_OK) return st;
+    // red: dot-product partials (pdq), |r|^2 (prr), Phi (pphi), the camera reduction's
+    // Gram partials (pg), then the fused iteration end's partials (pxz)
+    const size_t ngram = 2 * (size_t)schur_gram_blocks(s->np), nxz = 2 * (size_t)mcg_xrz_blocks(s->np, s->dp);
+    if ((st = ensure_red(s, (size_t)kRedBlocks * 4 + ngram + nxz)) != BA_OK) return st;
+    if ((st = ensure_tickets(s, 1)) != BA_OK) return st;
     double *r = s->vec, *z = r + n, *P = z + n, *Q = P + n, *tmp = Q + n, *sc = tmp + 2 * n;
     double *pdq = s->red, *prr = pdq + kRedBlocks * 2, *pphi = prr + kRedBlocks, *pg = pphi + kRedBlocks;
+    double *pxz = pg + ngram;
     auto t0 = std::chrono::steady_clock::now();
     if ((st = init_scalars(s, sc)) != BA_OK) return st;
     if (x0) {
@@ -878,16 +881,20 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
             for (int b = 0; b < nb; ++b) {
                 matvec(s, sa, P, Q);                                         // Q_i = S P_i
                 if (!fuse) launch_dot2(n, Q, P, P, r, pdq, sc + SC_DONE, q);  // Delta_i, gamma_i
-                launch_pcg_update_xr(n, fuse ? pg : pdq, fuse ? schur_gram_blocks(s->np) : kRedBlocks, sc, x, r, P,
-                                     Q, prr, q);                             // alpha_i, x_{i+1}, r_{i+1}
-                launch_pcg_step_end(prr, sc, opts.eps, opts.max_iter, trace_dev, q);
+                const double *dq = fuse ? pg : pdq;
+                const int ndq = fuse ? schur_gram_blocks(s->np) : kRedBlocks;
                 if (!lowrank) {
-                    launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q, s->dp);  // Z_{i+1}, Phi_i
+                    // alpha_i, x_{i+1}, r_{i+1}, the stop test, Z_{i+1}, Phi_i and beta_i
+                    launch_pcg_xrz(s->np, dq, ndq, sc, x, r, P, Q, s->Dchol, z, pxz, s->tickets, opts.eps,
+                                   opts.max_iter, trace_dev, q, s->dp);
+                    launch_pcg_update_p(n, nullptr, sc, z, P, q);            // P_{i+1}
                 } else {                                                     // M^-1 = D^-1 + U U^T
+                    launch_pcg_update_xr(n, dq, ndq, sc, x, r, P, Q, prr, q);
+                    launch_pcg_step_end(prr, sc, opts.eps, opts.max_iter, trace_dev, q);
                     launch_pcg_precond_phi(s->np, s->Dchol, r, Q, z, pphi, sc + SC_DONE, q, s->dp);
                     launch_lowrank_apply(n, s->Ulr, r, z, Q, s->lr_proj, pphi, sc + SC_DONE, q);
-                }
-                launch_pcg_update_p(n, pphi, sc, z, P, q);                   // beta_i, P_{i+1}
+                    launch_pcg_update_p(n, pphi, sc, z, P, q);
+                }                   // beta_i, P_{i+1}
             }
             enqueued += nb;
             if (hipGetLastError() != hipSuccess) {

@@ -246,13 +246,131 @@ void launch_pcg_update_xr(int64_t n, const double *partials_dq, int n_dq, double
                        partials_rr);
 }
 
-// Phi = Q^T Z from the partials; beta = Phi / Delta; P = Z - beta P
+// One kernel for the end of a PCG iteration (Alg. 1) with the block-Jacobi
+// preconditioner: alpha = gamma / Delta from npdq pairs of partials (pdq), x += alpha P,
+// r -= alpha Q, Z = D^-1 r, and the partial sums of |r|^2 and Phi = Q^T Z.  Block b owns
+// the poses [b CB, (b + 1) CB) (CB = kNT / DP), whose rows it updates and whose D^-1
+// solves it takes.  The block that arrives last (an agent-scope counter, left zero) adds
+// the partials in block order and takes the step-end decisions of k_pcg_step_end (on a
+// breakdown flag, the stop test, the iteration cap), then beta = Phi / Delta into the
+// scalars for k_pcg_update_p.
+template <int DP>
+__global__ __launch_bounds__(kNT) void k_pcg_xrz(int np, const double *__restrict__ pdq, int npdq,
+                                                 double *__restrict__ sc, double *__restrict__ x,
+                                                 double *__restrict__ r, const double *__restrict__ P,
+                                                 const double *__restrict__ Q, const double *__restrict__ Dchol,
+                                                 double *__restrict__ z, double *__restrict__ partials,
+                                                 uint32_t *__restrict__ ticket, double eps, int max_iter,
+                                                 double *__restrict__ trace) {
+    if (sc[SC_DONE] != 0.0) return;
+    constexpr int CB = kNT / DP;
+    __shared__ double sr[CB * DP], sq[CB * DP];
+    __shared__ double sh[kNT];
+    __shared__ double s_alpha;
+    __shared__ int last;
+    const int64_t n = (int64_t)np * DP;
+    const int c0 = blockIdx.x * CB;
+    const int cams = min(CB, np - c0);
+    const int t = threadIdx.x;
+    if (t < 64) {
+        const double D = wave_partials(pdq, 2, npdq);
+        const double g = wave_partials(pdq + 1, 2, npdq);
+        const double al = D > 0.0 ? g / D : 0.0;
+        if (t == 0) {
+            s_alpha = al;
+            if (blockIdx.x == 0) {
+                sc[SC_DELTA] = D;
+                sc[SC_GAMMA] = g;
+                sc[SC_ALPHA] = al;
+                if (!(D > 0.0)) sc[SC_BREAK] = 1.0;
+            }
+        }
+    }
+    __syncthreads();
+    const double al = s_alpha;
+    double rr = 0.0;
+    if (t < cams * DP) {
+        const int64_t i = (int64_t)c0 * DP + t;
+        const double qi = Q[i];
+        x[i] += al * P[i];
+        const double v = r[i] - al * qi;
+        r[i] = v;
+        sr[t] = v;
+        sq[t] = qi;
+        rr = v * v;
+    }
+    __syncthreads();
+    double phi = 0.0;
+    if (t < cams) {
+        double rc[DP], zc[DP];
+#pragma unroll
+        for (int e = 0; e < DP; ++e) rc[e] = sr[t * DP + e];
+        chol_solve_packed<DP>(Dchol + (int64_t)(c0 + t) * (DP * (DP + 1) / 2), rc, zc);
+#pragma unroll
+        for (int e = 0; e < DP; ++e) {
+            z[(int64_t)(c0 + t) * DP + e] = zc[e];
+            phi += sq[t * DP + e] * zc[e];
+        }
+    }
+    rr = block_sum(rr, sh);
+    phi = block_sum(phi, sh);
+    if (t == 0) {
+        partials[2 * blockIdx.x] = rr;
+        partials[2 * blockIdx.x + 1] = phi;
+        const uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || t >= 64) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const double srr = wave_partials(partials, 2, gridDim.x);
+    const double sphi = wave_partials(partials + 1, 2, gridDim.x);
+    if (t != 0) return;
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (sc[SC_BREAK] != 0.0) {
+        sc[SC_DONE] = 1.0;
+        sc[SC_STATUS] = (double)BA_ERR_BREAKDOWN;
+        return;
+    }
+    const double it = sc[SC_ITER] + 1.0;
+    sc[SC_ITER] = it;
+    sc[SC_RR] = srr;
+    const double rr0 = sc[SC_RR0];
+    if (trace) trace[(int)it - 1] = sqrt(srr / rr0);
+    if (sqrt(srr) < eps * sqrt(rr0)) {
+        sc[SC_DONE] = 1.0;
+        sc[SC_STATUS] = (double)BA_OK;
+    } else if (it >= (double)max_iter) {
+        sc[SC_DONE] = 1.0;
+        sc[SC_STATUS] = (double)BA_MAXITER;
+    } else {
+        sc[SC_PHI] = sphi;
+        sc[SC_BETA] = sphi / sc[SC_DELTA];
+    }
+}
+
+void launch_pcg_xrz(int np, const double *pdq, int npdq, double *sc, double *x, double *r, const double *P,
+                    const double *Q, const double *Dchol, double *z, double *partials, uint32_t *ticket, double eps,
+                    int max_iter, double *trace, hipStream_t s, int dp) {
+    const unsigned nb = (unsigned)mcg_xrz_blocks(np, dp);
+    if (dp == 6)
+        hipLaunchKernelGGL(k_pcg_xrz<6>, dim3(nb), dim3(kNT), 0, s, np, pdq, npdq, sc, x, r, P, Q, Dchol, z, partials,
+                           ticket, eps, max_iter, trace);
+    else
+        hipLaunchKernelGGL(k_pcg_xrz<9>, dim3(nb), dim3(kNT), 0, s, np, pdq, npdq, sc, x, r, P, Q, Dchol, z, partials,
+                           ticket, eps, max_iter, trace);
+}
+
+// Phi = Q^T Z from the partials; beta = Phi / Delta; P = Z - beta P.  Without partials
+// (pphi null) beta is the one k_pcg_xrz stored.
 __global__ __launch_bounds__(kNT) void k_pcg_update_p(int64_t n, const double *__restrict__ pphi,
                                                       double *__restrict__ sc, const double *__restrict__ z,
                                                       double *__restrict__ P) {
     if (sc[SC_DONE] != 0.0) return;
     __shared__ double s_beta;
-    if (threadIdx.x < 64) {
+    if (!pphi) {
+        if (threadIdx.x == 0) s_beta = sc[SC_BETA];
+    } else if (threadIdx.x < 64) {
         const double phi = wave_partials(pphi, 1, kRedBlocks);
         const double be = phi / sc[SC_DELTA];
         if (threadIdx.x == 0) s_beta = be;

@@ -164,8 +164,16 @@ void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const 
                             double *partials, const double *done, hipStream_t s, int dp = 9);
 void launch_pcg_step_end(const double *partials_rr, double *sc, double eps, int max_iter, double *trace,
                          hipStream_t s);
+// partials_phi null: beta from sc[SC_BETA] (stored by launch_pcg_xrz)
 void launch_pcg_update_p(int64_t n, const double *partials_phi, double *sc, const double *z, double *P,
                          hipStream_t s);
+// Fused end of a PCG iteration with the block-Jacobi preconditioner: alpha, x and r,
+// z = D^-1 r, the step-end decisions and beta (launch_pcg_update_xr, launch_pcg_step_end,
+// launch_pcg_precond_phi in one launch); partials: 2 mcg_xrz_blocks(np, dp) doubles;
+// ticket: a zero counter, left zero
+void launch_pcg_xrz(int np, const double *pdq, int npdq, double *sc, double *x, double *r, const double *P,
+                    const double *Q, const double *Dchol, double *z, double *partials, uint32_t *ticket, double eps,
+                    int max_iter, double *trace, hipStream_t s, int dp = 9);
 void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s);
 
 // MCG steps
