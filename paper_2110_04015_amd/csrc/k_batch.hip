@@ -82,13 +82,17 @@ __global__ void k_bseed(int B, const BatchProb *__restrict__ prob, const BatchDy
     }
 }
 
-// Delta = Q_cur^T P_cur (k x k) and gamma = P_cur^T r partials over a row range of problem b
+// Delta = Q_cur^T P_cur (k x k) and gamma = P_cur^T r partials over a row range of problem b.
+// k = 1: two dot products with two rows per thread in flight.  k > 1: chunks of R rows
+// (R k <= kBGramChunk) staged in LDS column by column, each column padded by one double so
+// that the threads of an output row read distinct banks.
+constexpr int kBGramChunk = 2048;
 __global__ __launch_bounds__(kNT) void k_bgram(int N, const BatchProb *__restrict__ prob,
                                                const BatchDyn *__restrict__ dyn, const double *__restrict__ Ph,
                                                const double *__restrict__ Qh, const double *__restrict__ r,
                                                double *__restrict__ part) {
-    constexpr int R = 16;
-    __shared__ double sP[R][kMaxK], sQ[R][kMaxK], sr[R];
+    __shared__ double sP[kBGramChunk + kMaxK], sQ[kBGramChunk + kMaxK], sr[kBGramChunk];
+    __shared__ double sh[kNT];
     const int b = blockIdx.y;
     const BatchDyn d = dyn[b];
     if (d.done) return;
@@ -99,36 +103,61 @@ __global__ __launch_bounds__(kNT) void k_bgram(int N, const BatchProb *__restric
     const double *Qc = Qh + P.hbase + (int64_t)d.cur_off * n;
     const double *rb = r + P.row0;
     const int64_t lo = n * blockIdx.x / kBGX, hi = n * (blockIdx.x + 1) / kBGX;
+    double *out = part + ((int64_t)b * kBGX + blockIdx.x) * T;
+    if (k == 1) {
+        double q0 = 0.0, q1 = 0.0, g0 = 0.0, g1 = 0.0;
+        int64_t i = lo + threadIdx.x;
+        for (; i + kNT < hi; i += 2 * kNT) {
+            const double p0 = Pc[i], p1 = Pc[i + kNT];
+            q0 += Qc[i] * p0;
+            q1 += Qc[i + kNT] * p1;
+            g0 += p0 * rb[i];
+            g1 += p1 * rb[i + kNT];
+        }
+        if (i < hi) {
+            q0 += Qc[i] * Pc[i];
+            g0 += Pc[i] * rb[i];
+        }
+        const double qp = block_sum(q0 + q1, sh);
+        const double pr = block_sum(g0 + g1, sh);
+        if (threadIdx.x == 0) {
+            out[0] = qp;
+            out[1] = pr;
+        }
+        return;
+    }
+    const int R = kBGramChunk / k;   // rows per chunk
+    const int ld = R + 1;            // padded column stride
     constexpr int OUT = (kMaxK * kMaxK + kMaxK + kNT - 1) / kNT;
     double acc[OUT];
 #pragma unroll
     for (int o = 0; o < OUT; ++o) acc[o] = 0.0;
     for (int64_t r0 = lo; r0 < hi; r0 += R) {
+        const int rows = (int)min<int64_t>(R, hi - r0);
         for (int w = threadIdx.x; w < R * k; w += kNT) {
-            const int a = w / R, rr = w % R;
-            const int64_t row = r0 + rr;
-            const bool in = row < hi;
-            sP[rr][a] = in ? Pc[(int64_t)a * n + row] : 0.0;
-            sQ[rr][a] = in ? Qc[(int64_t)a * n + row] : 0.0;
+            const int a = w / R, rr = w - a * R;   // consecutive threads: consecutive rows of column a
+            const bool in = rr < rows;
+            sP[a * ld + rr] = in ? Pc[(int64_t)a * n + r0 + rr] : 0.0;
+            sQ[a * ld + rr] = in ? Qc[(int64_t)a * n + r0 + rr] : 0.0;
         }
-        if (threadIdx.x < R) {
-            const int64_t row = r0 + threadIdx.x;
-            sr[threadIdx.x] = row < hi ? rb[row] : 0.0;
-        }
+        for (int rr = threadIdx.x; rr < R; rr += kNT) sr[rr] = rr < rows ? rb[r0 + rr] : 0.0;
         __syncthreads();
 #pragma unroll
         for (int o = 0; o < OUT; ++o) {
             const int idx = threadIdx.x + o * kNT;
-            if (idx < k * k) {
-                const int a = idx / k, c = idx - a * k;
-                double s = 0.0;
-                for (int rr = 0; rr < R; ++rr) s += sQ[rr][a] * sP[rr][c];
-                acc[o] += s;
-            } else if (idx < tot) {
-                const int a = idx - k * k;
-                double s = 0.0;
-                for (int rr = 0; rr < R; ++rr) s += sP[rr][a] * sr[rr];
-                acc[o] += s;
+            if (idx < tot) {
+                const bool pr = idx >= k * k;
+                const int a = pr ? idx - k * k : idx / k;
+                const double *xv = pr ? sP + a * ld : sQ + a * ld;
+                const double *yv = pr ? sr : sP + (idx - a * k) * ld;
+                double s0 = 0.0, s1 = 0.0;
+                int rr = 0;
+                for (; rr + 1 < rows; rr += 2) {
+                    s0 += xv[rr] * yv[rr];
+                    s1 += xv[rr + 1] * yv[rr + 1];
+                }
+                if (rr < rows) s0 += xv[rr] * yv[rr];
+                acc[o] += s0 + s1;
             }
         }
         __syncthreads();
@@ -136,7 +165,7 @@ __global__ __launch_bounds__(kNT) void k_bgram(int N, const BatchProb *__restric
 #pragma unroll
     for (int o = 0; o < OUT; ++o) {
         const int idx = threadIdx.x + o * kNT;
-        if (idx < tot) part[((int64_t)b * kBGX + blockIdx.x) * T + idx] = acc[o];
+        if (idx < tot) out[idx] = acc[o];
     }
 }
 
@@ -192,58 +221,64 @@ __global__ __launch_bounds__(kNT) void k_bpinv(int N, const BatchProb *__restric
     }
 }
 
-// x += P_cur alpha, r -= Q_cur alpha, z = D^-1 r (one camera per thread); partials of
-// r^T r and r^T z over the problem's cameras
-__global__ __launch_bounds__(128) void k_bupdate(const BatchProb *__restrict__ prob, const BatchDyn *__restrict__ dyn,
+// x += P_cur alpha, r -= Q_cur alpha, z = D^-1 r, and partials of r^T r and r^T z per
+// problem.  Each of the kBUX blocks of a problem takes camera blocks of CB = kNT / 9
+// poses in turn: a thread per row for the update (the rows stay in LDS), then a
+// thread per pose for its 9 x 9 solve.
+__global__ __launch_bounds__(kNT) void k_bupdate(const BatchProb *__restrict__ prob, const BatchDyn *__restrict__ dyn,
                                                  const double *__restrict__ Ph, const double *__restrict__ Qh,
                                                  const double *__restrict__ alpha, const double *__restrict__ Dchol,
                                                  double *__restrict__ x, double *__restrict__ r,
                                                  double *__restrict__ z, double *__restrict__ part) {
-    __shared__ double s0[128], s1[128], al[kMaxK];
+    constexpr int CB = kNT / 9;
+    __shared__ double sr[CB * 9], sh[kNT], al[kMaxK];
     const int b = blockIdx.y;
     const BatchDyn d = dyn[b];
     if (d.done) return;
     const BatchProb P = prob[b];
     const int k = d.kcur;
-    for (int a = threadIdx.x; a < k; a += 128) al[a] = alpha[(int64_t)b * kMaxK + a];
+    const int t = threadIdx.x;
+    for (int a = t; a < k; a += kNT) al[a] = alpha[(int64_t)b * kMaxK + a];
     __syncthreads();
     const double *Pc = Ph + P.hbase + (int64_t)d.cur_off * P.n;
     const double *Qc = Qh + P.hbase + (int64_t)d.cur_off * P.n;
     double rr = 0.0, rz = 0.0;
-    for (int c = blockIdx.x * 128 + threadIdx.x; c < P.np; c += gridDim.x * 128) {
-        double rc[9], zc[9];
-        const int64_t g = P.row0 + (int64_t)c * 9;
-        for (int i = 0; i < 9; ++i) {
-            const int64_t row = (int64_t)c * 9 + i;
+    for (int c0 = blockIdx.x * CB; c0 < P.np; c0 += gridDim.x * CB) {
+        const int cams = min(CB, P.np - c0);
+        if (t < cams * 9) {
+            const int64_t row = (int64_t)c0 * 9 + t;
             double dx = 0.0, dr = 0.0;
             for (int a = 0; a < k; ++a) {
                 dx += Pc[(int64_t)a * P.n + row] * al[a];
                 dr += Qc[(int64_t)a * P.n + row] * al[a];
             }
-            x[g + i] += dx;
-            rc[i] = r[g + i] - dr;
-            r[g + i] = rc[i];
-            rr += rc[i] * rc[i];
+            const int64_t g = P.row0 + row;
+            x[g] += dx;
+            const double v = r[g] - dr;
+            r[g] = v;
+            sr[t] = v;
+            rr += v * v;
         }
-        chol9_solve(Dchol + (int64_t)(P.cam0 + c) * 45, rc, zc);
-        for (int i = 0; i < 9; ++i) {
-            z[g + i] = zc[i];
-            rz += rc[i] * zc[i];
-        }
-    }
-    s0[threadIdx.x] = rr;
-    s1[threadIdx.x] = rz;
-    __syncthreads();
-    for (int s = 64; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            s0[threadIdx.x] += s0[threadIdx.x + s];
-            s1[threadIdx.x] += s1[threadIdx.x + s];
+        __syncthreads();
+        if (t < cams) {
+            double rc[9], zc[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) rc[e] = sr[t * 9 + e];
+            chol9_solve(Dchol + (int64_t)(P.cam0 + c0 + t) * 45, rc, zc);
+            const int64_t g = P.row0 + (int64_t)(c0 + t) * 9;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                z[g + e] = zc[e];
+                rz += rc[e] * zc[e];
+            }
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        part[((int64_t)b * kBUX + blockIdx.x) * 2] = s0[0];
-        part[((int64_t)b * kBUX + blockIdx.x) * 2 + 1] = s1[0];
+    rr = block_sum(rr, sh);
+    rz = block_sum(rz, sh);
+    if (t == 0) {
+        part[((int64_t)b * kBUX + blockIdx.x) * 2] = rr;
+        part[((int64_t)b * kBUX + blockIdx.x) * 2 + 1] = rz;
     }
 }
 
@@ -315,9 +350,16 @@ __global__ __launch_bounds__(kNT) void k_bphi(int N, const BatchProb *__restrict
     for (int p = wave; p < N; p += kNT / 64) {
         const int64_t lo = (int64_t)p * P.gs * 9;
         const int64_t hi = (p == N - 1) ? (int64_t)P.n : (int64_t)(p + 1) * P.gs * 9;
-        double acc = 0.0;
-        for (int64_t i = lo + lane; i < hi; i += 64) acc += q[i] * zb[i];
-        acc = wave_sum(acc);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;   // four rows per lane in flight
+        int64_t i = lo + lane;
+        for (; i + 192 < hi; i += 256) {
+            a0 += q[i] * zb[i];
+            a1 += q[i + 64] * zb[i + 64];
+            a2 += q[i + 128] * zb[i + 128];
+            a3 += q[i + 192] * zb[i + 192];
+        }
+        for (; i < hi; i += 64) a0 += q[i] * zb[i];
+        const double acc = wave_sum((a0 + a1) + (a2 + a3));
         if (lane == 0) Phi[(P.colbase + col) * N + p] = acc;
     }
 }
@@ -528,7 +570,7 @@ void launch_biter_head(const BatchLaunch &L, double tau, double eps, int max_ite
     hipLaunchKernelGGL(k_bgram, dim3(kBGX, L.B), dim3(kNT), 0, s, L.N, L.prob, L.dyn, L.Ph, L.Qh, L.r, L.gpart);
     hipLaunchKernelGGL(k_bpinv, dim3(L.B), dim3(kNT), 0, s, L.N, L.prob, L.dyn, L.gpart, L.Dp, L.blk_off, L.blk_k,
                        L.blk_dp, L.alpha, L.gamma);
-    hipLaunchKernelGGL(k_bupdate, dim3(kBUX, L.B), dim3(128), 0, s, L.prob, L.dyn, L.Ph, L.Qh, L.alpha, L.Dchol, L.x,
+    hipLaunchKernelGGL(k_bupdate, dim3(kBUX, L.B), dim3(kNT), 0, s, L.prob, L.dyn, L.Ph, L.Qh, L.alpha, L.Dchol, L.x,
                        L.r, L.z, L.upart);
     hipLaunchKernelGGL(k_bscalars, dim3((L.B + 63) / 64), dim3(64), 0, s, L.B, L.N, tau, eps, max_iter, L.prob, L.dyn,
                        L.upart, L.alpha, L.gamma, L.skip_single, L.skip_multi);
