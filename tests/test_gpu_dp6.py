@@ -8,6 +8,10 @@ reduced-precision products by their rounding (FP32 2e-5, BF16 3e-2).  Once PCG h
 run far below 1e-6, two correct FP64 implementations part by more than 1e-9 (on
 cap120 with d_p = 6 the oracle and SciPy's textbook CG on the oracle's own operator
 differ by 1.7e-6 after 30 iterations): there the iterate bar is 4 x that spread.
+Iterates are compared up to n - 1 iterations only: in exact arithmetic CG reaches the
+solution within n steps (the Krylov space of an n x n system has dimension at most n),
+so from the n-th iterate on the iterates of two FP64 runs differ by their rounding
+noise alone (on tiny, n = 30).
 """
 import numpy as np
 import pytest
@@ -94,7 +98,7 @@ def _textbook_spread(o, k):
 
 def test_solver_iterates(pair):
     name, p, o, g = pair
-    for k in (1, 5, 30):
+    for k in [k for k in (1, 5, 30) if k < o.n]:
         x, st = g.pcg(eps=0.0, max_iter=k)
         xo, so = o.pcg(eps=0.0, imax=k)
         assert relnorm(_h(x), xo) < max(1e-9, 4.0 * _textbook_spread(o, k)), k
