@@ -78,11 +78,14 @@ typedef struct {
     int32_t store_fp32;      /* also keep an FP32 copy of the Jacobian stream (precision FP32) */
     int32_t store_bf16;      /* also keep a BF16 copy with per-camera column scales (precision BF16) */
     int32_t max_slots;       /* cameras per landmark chunk (0 = default 128; 64..440) */
-    int32_t max_tiles;       /* 64-observation tiles per chunk (0 = default 16) */
+    int32_t max_tiles;       /* 64-observation tiles per chunk of the S product; 0: as many as make every
+                                chunk of the FP64 product resident at once on the device */
     int32_t explicit_schur;  /* also form S explicitly in 9x9 block-sparse rows (the paper's representation,
                                 Sec. 3.2 and 4.1); FP64 S products then read it instead of the Jacobians.
                                 BA_ERR_UNSUPPORTED when a block row exceeds the LDS of the assembly (251 blocks) */
-    int32_t reserved[3];
+    int32_t max_tiles_multi; /* tiles per chunk of the multidirectional product; 0: max_tiles when that is
+                                set, else as many as make every chunk of the FP64 product resident at once */
+    int32_t reserved[2];
 } ba_build_opts;
 
 typedef enum { BA_PREC_FP64 = 0, BA_PREC_FP32 = 1, BA_PREC_BF16 = 2 } ba_precision;

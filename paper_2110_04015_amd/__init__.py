@@ -120,7 +120,8 @@ class System:
     """A built reduced camera system (ba_build_system) living on one device."""
 
     def __init__(self, n_cams, n_lms, obs_cam, obs_lm, J_p, J_l, r, lam, stream=None,
-                 max_slots=0, max_tiles=0, store_fp32=False, store_bf16=False, explicit_schur=False):
+                 max_slots=0, max_tiles=0, store_fp32=False, store_bf16=False, explicit_schur=False,
+                 max_tiles_multi=0):
         torch = _torch()
         m = int(obs_cam.numel())
         # pose dimension (Sec. 3.1): 9, or 6 for extrinsics only, from the size of J_p
@@ -135,7 +136,7 @@ class System:
         d.lam = float(lam)
         o = _lib.BuildOpts()
         o.store_fp32, o.store_bf16 = int(store_fp32), int(store_bf16)
-        o.max_slots, o.max_tiles = int(max_slots), int(max_tiles)
+        o.max_slots, o.max_tiles, o.max_tiles_multi = int(max_slots), int(max_tiles), int(max_tiles_multi)
         o.explicit_schur = int(explicit_schur)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         self.device = obs_cam.device

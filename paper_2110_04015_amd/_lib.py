@@ -21,7 +21,8 @@ class ProblemDesc(C.Structure):
 
 class BuildOpts(C.Structure):
     _fields_ = [("store_fp32", C.c_int32), ("store_bf16", C.c_int32), ("max_slots", C.c_int32),
-                ("max_tiles", C.c_int32), ("explicit_schur", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("max_tiles", C.c_int32), ("explicit_schur", C.c_int32), ("max_tiles_multi", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class SolveOpts(C.Structure):

@@ -567,9 +567,13 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
     if (!std::isfinite(d->lambda)) return fail(BA_ERR_NONFINITE, "lambda is not finite");
     if (d->lambda < 0.0) return fail(BA_ERR_INVALID_ARG, "lambda must be >= 0");
     int max_slots = opts && opts->max_slots ? opts->max_slots : 128;
-    int max_tiles = opts && opts->max_tiles ? opts->max_tiles : 16;
+    // max_tiles 0: chunks sized so that the S product's chunks are all resident at once
+    int max_tiles = opts && opts->max_tiles ? opts->max_tiles : 0;
     // the chunk kernel keeps 2 * max_slots camera rows of 9 doubles in LDS (<= 64 KiB)
-    if (max_slots < kTile || max_slots > 440 || max_tiles < 1 || max_tiles > 4096)
+    const int max_tiles_multi = opts ? opts->max_tiles_multi : 0;
+    if (max_tiles_multi < 0 || max_tiles_multi > 4096)
+        return fail(BA_ERR_INVALID_ARG, "max_tiles_multi must be in [0, 4096]");
+    if (max_slots < kTile || max_slots > 440 || max_tiles < 0 || max_tiles > 4096)
         return fail(BA_ERR_INVALID_ARG, "max_slots must be in [64, 440] and max_tiles in [1, 4096]");
 
     ba_system *s = new ba_system();
@@ -594,7 +598,8 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
         return bail(fail(BA_ERR_HIP, "copying the observation indices to the host failed"));
     std::string err;
     ba_status st = build_plan(s->np, s->nl, m, hcam.data(), hlm.data(), max_slots, max_tiles, s->plan, err,
-                              cam_seg);
+                              cam_seg, max_tiles == 0 ? schur1_resident_chunks(d->d_p) : 0, max_tiles_multi,
+                              max_tiles == 0 && max_tiles_multi == 0 ? schur_multi_resident_chunks(d->d_p) : 0);
     if (st != BA_OK) return bail(fail(st, err));
     if (cam_seg) {
         if ((st = upload(&s->seg_cam, s->plan.cam_seg, q)) != BA_OK) return bail(st);

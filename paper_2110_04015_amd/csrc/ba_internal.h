@@ -38,6 +38,7 @@ struct HostPlan {
     int n_chunks = 0;
     int64_t n_part = 0;
     int max_slots = 128, max_tiles = 16;
+    int max_tiles_multi = 16;             // tiles per chunk of the multidirectional product
     int max_used_slots = 0;               // most cameras of one chunk (sizes the chunk kernels' LDS)
     std::vector<int32_t> lmk_order;       // storage index -> landmark id
     std::vector<int32_t> lmk_store;       // landmark id -> storage index
@@ -97,10 +98,15 @@ struct DevMulti {
 };
 
 // Plan construction (host, plan.cpp).  Returns BA_OK or an error with message.
-// cam_seg (nullable, host, [np], nondecreasing): problem of every camera of a batch
+// cam_seg (nullable, host, [np], nondecreasing): problem of every camera of a batch.
+// max_tiles = 0: the S product's chunks take ceil(n_tiles / target_chunks) tiles each
+// (16 when target_chunks is 0), so that all of them are resident at once.  The
+// multidirectional product's chunks take max_tiles_multi tiles (0: max_tiles when it is
+// set, else ceil(n_tiles / target_multi), else 16).
 ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_t *lm,
                      int max_slots, int max_tiles, HostPlan &plan, std::string &err,
-                     const int32_t *cam_seg = nullptr);
+                     const int32_t *cam_seg = nullptr, int target_chunks = 0, int max_tiles_multi = 0,
+                     int target_multi = 0);
 // group (nullable, host, [np]): subset of every camera; default partition_groups(np, N)
 ba_status build_multi_plan(const HostPlan &plan, int N, int max_out, HostMultiPlan &mp,
                            std::string &err, const int32_t *group = nullptr);

@@ -681,4 +681,25 @@ void launch_back_substitute(const double *J64, const uint32_t *meta, const int32
                            chunk_part, part_cam, max_slots, vinv, bl, lmk_order, dxp, dxl);
 }
 
+// Chunk wavefronts of a kernel the device keeps resident at once (register-limited
+// occupancy times compute units); 0 when it cannot be queried
+static int resident_waves(const void *f) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kTile, 0) != hipSuccess)
+        return 0;
+    return per * cus;
+}
+
+int schur1_resident_chunks(int dp) {
+    return resident_waves(dp == 6 ? reinterpret_cast<const void *>(&k_schur1<0, double, 6>)
+                                  : reinterpret_cast<const void *>(&k_schur1<0, double, 9>));
+}
+
+int schur_multi_resident_chunks(int dp) {
+    return resident_waves(dp == 6 ? reinterpret_cast<const void *>(&k_schur_multi<0, double, 6>)
+                                  : reinterpret_cast<const void *>(&k_schur_multi<0, double, 9>));
+}
+
 }  // namespace ba

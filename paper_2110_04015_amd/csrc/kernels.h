@@ -98,6 +98,10 @@ struct SchurArgs {
     const double *gram_r = nullptr;
 };
 int schur_gram_blocks(int np);
+// FP64 chunk wavefronts of the S product (of the multidirectional product) resident at
+// once on the current device (0: unknown)
+int schur1_resident_chunks(int dp);
+int schur_multi_resident_chunks(int dp);
 // y = S v (partials then the camera reduction)
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s);
 void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s);

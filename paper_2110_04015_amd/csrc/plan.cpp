@@ -30,14 +30,16 @@ static void counting_csr(const int32_t *key, int64_t m, int nk, std::vector<int6
 }
 
 ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_t *lm,
-                     int max_slots, int max_tiles, HostPlan &P, std::string &err, const int32_t *cam_seg) {
+                     int max_slots, int max_tiles, HostPlan &P, std::string &err, const int32_t *cam_seg,
+                     int target_chunks, int max_tiles_multi, int target_multi) {
     char buf[256];
     P = HostPlan();
     P.np = np;
     P.nl = nl;
     P.m = m;
     P.max_slots = max_slots;
-    P.max_tiles = max_tiles;
+    P.max_tiles = max_tiles > 0 ? max_tiles : 16;
+    P.max_tiles_multi = max_tiles_multi > 0 ? max_tiles_multi : max_tiles > 0 ? max_tiles : 16;
     for (int64_t o = 0; o < m; ++o) {
         if (cam[o] < 0 || cam[o] >= np || lm[o] < 0 || lm[o] >= nl) {
             snprintf(buf, sizeof buf, "observation %lld has camera %d / landmark %d out of range",
@@ -155,6 +157,12 @@ ba_status build_plan(int np, int nl, int64_t m, const int32_t *cam, const int32_
     }
     const int64_t tiles = (int64_t)P.tile_lmk_base.size();
     P.n_tiles = tiles;
+    auto per_chunk = [&](int target) {
+        return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (tiles + target - 1) / target));
+    };
+    if (max_tiles <= 0 && target_chunks > 0) P.max_tiles = per_chunk(target_chunks);
+    if (max_tiles <= 0 && max_tiles_multi <= 0 && target_multi > 0) P.max_tiles_multi = per_chunk(target_multi);
+    max_tiles = P.max_tiles;
     // chunks of consecutive tiles with at most max_slots distinct cameras
     {
         std::vector<int32_t> stamp((size_t)np, -1), slot_of((size_t)np, 0);
@@ -326,7 +334,7 @@ ba_status build_multi_plan(const HostPlan &P, int N, int max_out, HostMultiPlan 
         if (chunk >= 0)
             for (int64_t k : need) fresh += stamp[(size_t)k] != chunk;
         if ((int)need.size() > max_out) max_out = (int)need.size();
-        if (chunk < 0 || outs + fresh > max_out || ntiles_in >= P.max_tiles ||
+        if (chunk < 0 || outs + fresh > max_out || ntiles_in >= P.max_tiles_multi ||
             P.tile_seg[(size_t)t] != M.chunk_seg.back()) {
             ++chunk;
             outs = 0;
