@@ -184,6 +184,25 @@ def test_matmat_grouped(pair, N):
     assert np.array_equal(grp // 1, np.repeat(ba.partition(p.n_cams, N), 9))
 
 
+@pytest.mark.parametrize("max_tiles,max_tiles_multi", [(1, 1), (16, 0), (0, 3), (2, 40)])
+def test_chunk_shapes(max_tiles, max_tiles_multi):
+    """The chunk size (tiles per chunk of either product, fixed or sized by the plan to the
+    resident wavefronts) changes only how the work is split: the products stay within
+    1e-12 of the oracle."""
+    p = PROBLEMS["walk200"]()
+    o = oracle.System(p)
+    g = ba.System.from_problem(p, max_tiles=max_tiles, max_tiles_multi=max_tiles_multi)
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(g.n)
+    assert rel(_h(g.matvec(_dev(v))), o.matvec(v)) < 1e-12
+    N = 16
+    Y = _h(g.matmat_grouped(N, _dev(v)))
+    grp = np.repeat(oracle.partition(p.n_cams, N), 9)
+    for q in range(N):
+        assert rel(Y[q], o.matvec(np.where(grp == q, v, 0.0))) < 1e-12, q
+    g.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 3e-2)])
 def test_matmat_grouped_reduced_precision(pair, prec, tol):
     name, p, o, g = pair

@@ -104,6 +104,18 @@ def test_host_argument_errors(L):
     d.d_p = 9
     assert L.ba_build_system(C.byref(d), None, None, C.byref(out)) == _lib.BA_ERR_INVALID_ARG
     assert not out.value
+    # chunk shapes are checked before any device memory is touched (the array pointers
+    # below are never dereferenced)
+    d.obs_cam = d.obs_lm = d.J_p = d.J_l = d.r = 4096
+    d.lam = 1e-4
+    b = _lib.BuildOpts()
+    b.max_tiles_multi = -1
+    assert L.ba_build_system(C.byref(d), C.byref(b), None, C.byref(out)) == _lib.BA_ERR_INVALID_ARG
+    assert "max_tiles_multi" in L.ba_last_error().decode()
+    b.max_tiles_multi, b.max_tiles = 0, 4097
+    assert L.ba_build_system(C.byref(d), C.byref(b), None, C.byref(out)) == _lib.BA_ERR_INVALID_ARG
+    assert "max_tiles" in L.ba_last_error().decode()
+    assert not out.value
     assert L.ba_status_string(_lib.BA_ERR_NOT_SPD).decode().startswith("matrix block")
     o = _lib.SolveOpts()
     L.ba_default_solve_opts(C.byref(o))
