@@ -185,7 +185,7 @@ void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
     if (use_bsr(s, a)) {
         const bool ev = s->profiling && s->prof_used + 2 <= s->prof_events.size();
         if (ev) (void)hipEventRecord(s->prof_events[s->prof_used], s->stream);
-        launch_bsr_mv(s->np, s->bsr_ptr, s->bsr_col, s->bsr_val, v, y, a.done, s->stream);
+        launch_bsr_mv(s->np, s->bsr_ptr, s->bsr_col, s->bsr_val, v, y, a.done, s->stream, a.gram, a.gram_r);
         if (ev) {
             (void)hipEventRecord(s->prof_events[s->prof_used + 1], s->stream);
             s->prof_used += 2;
@@ -833,7 +833,7 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
     const int64_t n = (int64_t)s->np * s->dp;
     hipStream_t q = s->stream;
     if ((st = ensure_vec(s, (size_t)n * 6 + SC_COUNT)) != BA_OK) return st;
-    // red: dot-product partials (pdq), |r|^2 (prr), Phi (pphi), the camera reduction's
+    // red: scratch partials (pdq: the true residual), |r|^2 (prr), Phi (pphi), the camera reduction's
     // Gram partials (pg), then the fused iteration end's partials (pxz)
     const size_t ngram = 2 * (size_t)schur_gram_blocks(s->np), nxz = 2 * (size_t)mcg_xrz_blocks(s->np, s->dp);
     if ((st = ensure_red(s, (size_t)kRedBlocks * 4 + ngram + nxz)) != BA_OK) return st;
@@ -871,23 +871,19 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
         if (lowrank) launch_lowrank_apply(n, s->Ulr, r, P, nullptr, s->lr_proj, nullptr, nullptr, q);
         SchurArgs sa = schur_args(s, prec);
         sa.done = sc + SC_DONE;
-        // Delta_i and gamma_i from the camera reduction of Q_i = S P_i (the explicit-S
-        // product has none: two dot products instead)
-        const bool fuse = !use_bsr(s, sa);
-        if (fuse) {
-            sa.gram = pg;
-            sa.gram_r = r;
-        }
+        // Delta_i and gamma_i from the camera reduction of Q_i = S P_i (or from the
+        // explicit-S product, which leaves the same partials)
+        sa.gram = pg;
+        sa.gram_r = r;
         int enqueued = 0, batch = 4;
         const size_t prof_mark = s->prof_used;
         double rr_prev = rr0;
         for (;;) {
             const int nb = std::min(batch, opts.max_iter - enqueued);
             for (int b = 0; b < nb; ++b) {
-                matvec(s, sa, P, Q);                                         // Q_i = S P_i
-                if (!fuse) launch_dot2(n, Q, P, P, r, pdq, sc + SC_DONE, q);  // Delta_i, gamma_i
-                const double *dq = fuse ? pg : pdq;
-                const int ndq = fuse ? schur_gram_blocks(s->np) : kRedBlocks;
+                matvec(s, sa, P, Q);                                         // Q_i = S P_i; Delta_i, gamma_i
+                const double *dq = pg;
+                const int ndq = schur_gram_blocks(s->np);
                 if (!lowrank) {
                     // alpha_i, x_{i+1}, r_{i+1}, the stop test, Z_{i+1}, Phi_i and beta_i
                     launch_pcg_xrz(s->np, dq, ndq, sc, x, r, P, Q, s->Dchol, z, pxz, s->tickets, opts.eps,
@@ -1032,9 +1028,10 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     if (rr0 > 0.0) {
         // P_0 = Z_0 = M^-1 r_0 ; Q_0 = S P_0
         const bool lowrank = opts.precond == 1;
-        // one-column blocks take Delta and gamma from the camera reduction of Q = S P
-        // (partials at red + goff), and their Delta^+ and alpha from the iteration-end kernel
-        const bool fuse1 = !lowrank && !use_bsr(s, sa);
+        // one-column blocks take Delta and gamma from the camera reduction of Q = S P (or
+        // the explicit-S product; partials at red + goff), and their Delta^+ and alpha from
+        // the iteration-end kernel
+        const bool fuse1 = !lowrank;
         SchurArgs sag = sa;
         if (fuse1) {
             sag.gram = red + goff;
@@ -1203,9 +1200,7 @@ static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const dou
     for (;;) {
         // outer residual in FP64: r = -b~ - S x, btp = -r (so that S d = r reads S d = -btp)
         rel = 0.0;
-        // red: dot-product partials (pdq), |r|^2 (prr), Phi (pphi), then the camera
-    // reduction's Gram partials (pg)
-    if ((st = ensure_red(s, (size_t)kRedBlocks * 4 + 2 * (size_t)schur_gram_blocks(s->np))) != BA_OK) return st;
+        if ((st = ensure_red(s, (size_t)kRedBlocks * 4)) != BA_OK) return st;
         matvec(s, schur_args(s, 0), x, tmp);
         launch_residual_refine(n, s->bt, tmp, r, btp, s->red, q);
         double *sc2 = tmp + n;   // 8 scratch doubles after the four work vectors

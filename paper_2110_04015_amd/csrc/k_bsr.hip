@@ -8,6 +8,7 @@
 // row's contributions, 64 at a time, in a fixed order.
 #include "ba_internal.h"
 #include "kernels.h"
+#include "dev_la.h"
 
 namespace ba {
 
@@ -192,9 +193,11 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
 __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
                                                 const double *__restrict__ v, double *__restrict__ y,
-                                                const double *__restrict__ done) {
+                                                const double *__restrict__ done, double *__restrict__ gram,
+                                                const double *__restrict__ gr) {
     if (done && *done != 0.0) return;
     __shared__ double sh[4][64];
+    __shared__ double gsum[2][4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = blockIdx.x * 4 + w;
     double acc = 0.0, acc1 = 0.0;
@@ -222,10 +225,31 @@ __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restric
     }
     sh[w][lane] = acc + acc1;
     __syncthreads();
+    double qp = 0.0, pr = 0.0;
     if (j < np && lane < 9) {
         double s = 0.0;
         for (int t0 = 0; t0 < 7; ++t0) s += sh[w][t0 * 9 + lane];
-        y[(int64_t)j * 9 + lane] = s;
+        const int64_t i = (int64_t)j * 9 + lane;
+        y[i] = s;
+        if (gram) {
+            const double vi = v[i];
+            qp = s * vi;
+            pr = vi * gr[i];
+        }
+    }
+    if (!gram) return;   // the same for the whole launch
+    // the partial sums of y^T v and v^T gr over the block's four rows (the Gram products
+    // Q^T P and P^T r of a one-column block, Q = S P), as the camera reduction leaves them
+    qp = wave_sum(qp);
+    pr = wave_sum(pr);
+    if (lane == 0) {
+        gsum[0][w] = qp;
+        gsum[1][w] = pr;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        gram[2 * blockIdx.x] = (gsum[0][0] + gsum[0][1]) + (gsum[0][2] + gsum[0][3]);
+        gram[2 * blockIdx.x + 1] = (gsum[1][0] + gsum[1][1]) + (gsum[1][2] + gsum[1][3]);
     }
 }
 
@@ -288,8 +312,9 @@ void launch_bsr_assemble(int np, const BsrGather &g, const int64_t *obs_slot, co
 }
 
 void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,
-                   const double *done, hipStream_t s) {
-    hipLaunchKernelGGL(k_bsr_mv, dim3((np + 3) / 4), dim3(256), 0, s, np, row_ptr, col, val, v, y, done);
+                   const double *done, hipStream_t s, double *gram, const double *gram_r) {
+    hipLaunchKernelGGL(k_bsr_mv, dim3((np + 3) / 4), dim3(256), 0, s, np, row_ptr, col, val, v, y, done, gram,
+                       gram_r);
 }
 
 void launch_bsr_mm_grouped(int np, int N, const int32_t *row_ptr, const int32_t *col, const double *val,

@@ -285,7 +285,7 @@ void launch_bsr_assemble(int np, const BsrGather &g, const int64_t *obs_slot, co
                          const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, double *val,
                          hipStream_t s);
 void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,
-                   const double *done, hipStream_t s);
+                   const double *done, hipStream_t s, double *gram = nullptr, const double *gram_r = nullptr);
 void launch_bsr_mm_grouped(int np, int N, const int32_t *row_ptr, const int32_t *col, const double *val,
                            const int32_t *group, const double *z, double *Y, hipStream_t s,
                            const double *skip = nullptr);
