@@ -241,10 +241,13 @@ ba_status ba_mlp_loss_grad(const float *params, const float *F, int32_t rows, co
 ba_status ba_adam_step(float *params, const float *grad, float *m, float *v, int32_t t, float lr, void *stream);
 
 /* Event timing of the dominant kernel, the chunked implicit Schur product of
- * ba_schur_matvec and of the solvers' S v products: while enabled, each of its
- * launches on this system is bracketed by two HIP events recorded on the
- * system's stream.  ba_profile_read (host outputs, nullable) returns the summed
- * kernel time in ms and the number of launches since the last reset. */
+ * ba_schur_matvec and of the solvers' S v products (the block-sparse product with an
+ * explicit S): with on >= 1, every on-th of its launches on this system is bracketed by
+ * two HIP events recorded on the system's stream (on = 1: every launch; a larger on
+ * samples the launches, so fewer event records sit between kernels); on = 0 turns it
+ * off.  ba_profile_read (host outputs, nullable) returns the summed kernel time in ms
+ * and the number of timed launches since the last reset.  BA_ERR_INVALID_ARG for
+ * on < 0. */
 ba_status ba_profile_enable(ba_system *sys, int32_t on);
 ba_status ba_profile_read(ba_system *sys, double *ms_total, int64_t *launches, int32_t reset);
 

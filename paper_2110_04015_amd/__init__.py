@@ -198,8 +198,9 @@ class System:
         _check(lib().ba_explicit_schur_info(self.h, C.byref(nb), C.byref(by), C.byref(ms)), "ba_explicit_schur_info")
         return {"nnz_blocks": nb.value, "bytes": by.value, "assembly_ms": ms.value}
 
-    def profile(self, on: bool = True):
-        _check(lib().ba_profile_enable(self.h, int(on)), "ba_profile_enable")
+    def profile(self, on: bool = True, every: int = 1):
+        """Event timing of the S product kernel: every `every`-th launch while on."""
+        _check(lib().ba_profile_enable(self.h, int(every) if on else 0), "ba_profile_enable")
 
     def profile_read(self, reset: bool = True):
         ms, n = C.c_double(), C.c_int64()

@@ -5,6 +5,7 @@
 // tau-test branch) to choose the next launches.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -130,8 +131,6 @@ void free_all(ba_system *s) {
     s->host_pinned_dev = nullptr;
     if (s->sc_event) (void)hipEventDestroy(s->sc_event);
     s->sc_event = nullptr;
-    if (s->sc_mark) (void)hipEventDestroy(s->sc_mark);
-    s->sc_mark = nullptr;
     free_multi(s->multi);
     for (hipEvent_t e : s->prof_events) (void)hipEventDestroy(e);
     s->prof_events.clear();
@@ -182,8 +181,10 @@ inline bool use_bsr(const ba_system *s, const SchurArgs &a) {
 
 // y = S v; with profiling on, the dominant kernel is bracketed by events on the stream
 void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
+    // a sampled launch (every prof_every-th) gets the events
+    const bool sample = s->profiling && (s->prof_calls++ % s->prof_every) == 0;
     if (use_bsr(s, a)) {
-        const bool ev = s->profiling && s->prof_used + 2 <= s->prof_events.size();
+        const bool ev = sample && s->prof_used + 2 <= s->prof_events.size();
         if (ev) (void)hipEventRecord(s->prof_events[s->prof_used], s->stream);
         launch_bsr_mv(s->np, s->bsr_ptr, s->bsr_col, s->bsr_val, v, y, a.done, s->stream, a.gram, a.gram_r);
         if (ev) {
@@ -192,7 +193,7 @@ void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
         }
         return;
     }
-    if (!s->profiling) {
+    if (!sample) {
         launch_schur_matvec(a, v, y, s->stream);
         return;
     }
@@ -359,13 +360,12 @@ ba_status ensure_tickets(ba_system *s, int64_t count) {
 
 ba_status ensure_pinned(ba_system *s) {
     if (!s->host_pinned) {
-        HIPCHK(hipHostMalloc((void **)&s->host_pinned, SC_COUNT * sizeof(double), hipHostMallocMapped));
+        // SC_COUNT scalars and the tag of the kernel-written copy
+        HIPCHK(hipHostMalloc((void **)&s->host_pinned, (SC_COUNT + 1) * sizeof(double), hipHostMallocMapped));
+        s->host_pinned[SC_COUNT] = 0.0;
         HIPCHK(hipHostGetDevicePointer((void **)&s->host_pinned_dev, s->host_pinned, 0));
     }
     if (!s->sc_event) HIPCHK(hipEventCreateWithFlags(&s->sc_event, hipEventDisableTiming));
-    // after a kernel that made its host writes visible itself: no system-scope fence
-    if (!s->sc_mark)
-        HIPCHK(hipEventCreateWithFlags(&s->sc_mark, hipEventDisableTiming | hipEventDisableSystemFence));
     return BA_OK;
 }
 
@@ -375,21 +375,36 @@ ba_status ensure_pinned(ba_system *s) {
 static ba_status scalars_post(ba_system *s, const double *sc) {
     HIPCHK(hipMemcpyAsync(s->host_pinned, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipEventRecord(s->sc_event, s->stream));
-    s->sc_marked = false;
     return BA_OK;
 }
 
-// Marks the point of the stream after a kernel that wrote the scalars to host_pinned
-// itself and released them at system scope.
-static ba_status scalars_mark(ba_system *s) {
-    HIPCHK(hipEventRecord(s->sc_mark, s->stream));
-    s->sc_marked = true;
+// Waits for the scalars a kernel wrote to host_pinned with the tag `tag` (written after
+// the values, which the kernel released at system scope first): the host polls the tag,
+// with no event between the kernels.  Only when the tag is late (10 ms) does it ask the
+// stream, every 10 ms, whether it failed or drained without the tag (an error either
+// way): a stream query can itself put work on the device's queue.
+static ba_status scalars_wait_tag(ba_system *s, double tag, double *out) {
+    volatile double *t = s->host_pinned + SC_COUNT;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto next = t0 + std::chrono::milliseconds(10);
+    for (int64_t spin = 1; *t != tag; ++spin) {
+        if ((spin & 255) == 0 && std::chrono::steady_clock::now() >= next) {
+            next += std::chrono::milliseconds(10);
+            const hipError_t e = hipStreamQuery(s->stream);
+            if (e != hipSuccess && e != hipErrorNotReady)
+                return fail(BA_ERR_HIP, std::string("waiting for the MCG scalars: ") + hipGetErrorString(e));
+            if (e == hipSuccess && *t != tag) return fail(BA_ERR_HIP, "the MCG scalars were not written");
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60))
+                return fail(BA_ERR_HIP, "timed out waiting for the MCG scalars");
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    memcpy(out, s->host_pinned, SC_COUNT * sizeof(double));
     return BA_OK;
 }
 
 static ba_status scalars_wait(ba_system *s, double *out) {
-    HIPCHK(hipEventSynchronize(s->sc_marked ? s->sc_mark : s->sc_event));
-    s->sc_marked = false;
+    HIPCHK(hipEventSynchronize(s->sc_event));
     memcpy(out, s->host_pinned, SC_COUNT * sizeof(double));
     return BA_OK;
 }
@@ -713,8 +728,11 @@ ba_status ba_update_system(ba_system *s, const double *J_p, const double *J_l, c
 
 ba_status ba_profile_enable(ba_system *s, int32_t on) {
     if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    if (on < 0) return fail(BA_ERR_INVALID_ARG, "on must be >= 0");
     profile_flush(s);
     s->profiling = on != 0;
+    s->prof_every = on > 0 ? on : 1;
+    s->prof_calls = 0;
     return BA_OK;
 }
 
@@ -877,6 +895,7 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
         sa.gram_r = r;
         int enqueued = 0, batch = 4;
         const size_t prof_mark = s->prof_used;
+        const int64_t call_mark = s->prof_calls;
         double rr_prev = rr0;
         for (;;) {
             const int nb = std::min(batch, opts.max_iter - enqueued);
@@ -916,8 +935,15 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
             rr_prev = h[SC_RR];
         }
         it = (int)h[SC_ITER];
-        // event pairs of launches after the stop test (no-ops) are not kernel work
-        if (s->profiling && s->prof_used > prof_mark + 2 * (size_t)it) s->prof_used = prof_mark + 2 * (size_t)it;
+        // event pairs of launches after the stop test (no-ops) are not kernel work: keep the
+        // pairs of the sampled launches among the first `it` (launch j of this loop has call
+        // number call_mark + j and is sampled when that is a multiple of prof_every)
+        if (s->profiling) {
+            const int64_t k = s->prof_every;
+            const auto sampled_below = [k](int64_t c) { return (c + k - 1) / k; };
+            const size_t keep = 2 * (size_t)(sampled_below(call_mark + it) - sampled_below(call_mark));
+            if (s->prof_used > prof_mark + keep) s->prof_used = prof_mark + keep;
+        }
         rr = h[SC_RR];
         result = h[SC_DONE] != 0.0 ? (ba_status)(int)h[SC_STATUS] : BA_MAXITER;
         if (result == BA_ERR_BREAKDOWN) g_err = "PCG breakdown: P^T S P <= 0";
@@ -1076,10 +1102,11 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
                 launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, N, tau, opts.eps, q);
                 if ((st = scalars_post(s, sc)) != BA_OK) return st;
-            } else {   // the kernel also writes the scalars to the host
+            } else {   // the kernel also writes the scalars to the host, with a new tag
+                s->sc_tag += 1.0;
                 launch_mcg_xrz(s->np, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, s->Dchol, z,
-                               red, s->tickets, gamma, sc, s->host_pinned_dev, N, tau, opts.eps, q, s->dp, g1);
-                if ((st = scalars_mark(s)) != BA_OK) return st;
+                               red, s->tickets, gamma, sc, s->host_pinned_dev, s->sc_tag, N, tau, opts.eps, q, s->dp,
+                               g1);
             }
             // Everything up to the next iteration's Gram products that a one-column block
             // needs goes ahead of the read-back, so the device stays busy while the host
@@ -1105,7 +1132,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 spec_pair = s->prof_used != pu0;
             }
             HIPCHK(hipGetLastError());
-            if ((st = scalars_wait(s, h)) != BA_OK) return st;
+            if ((st = lowrank ? scalars_wait(s, h) : scalars_wait_tag(s, s->sc_tag, h)) != BA_OK) return st;
             if (spec_pair && h[SC_KN] != 1.0) s->prof_used -= 2;   // a skipped launch is no kernel work
             if (h[SC_RANK] == 0.0) {
                 result = BA_ERR_BREAKDOWN;

@@ -178,8 +178,7 @@ struct ba_system {
     double *host_pinned = nullptr;  // pinned host scalars
     double *host_pinned_dev = nullptr;  // the same memory as kernels address it
     hipEvent_t sc_event = nullptr;  // marks the point of the stream where host_pinned was filled
-    hipEvent_t sc_mark = nullptr;   // the same after a kernel that wrote host_pinned itself
-    bool sc_marked = false;         // the last mark is sc_mark
+    double sc_tag = 0.0;            // tag of the last scalars a kernel wrote to host_pinned[SC_COUNT]
     ba::DevMulti multi;
     // batches: problem of every camera and of every chunk of the S product (device)
     int32_t *seg_cam = nullptr, *seg_chunk = nullptr;
@@ -190,6 +189,8 @@ struct ba_system {
     double bsr_build_ms = 0.0;
     // optional event timing of the chunked Schur-product kernel
     bool profiling = false;
+    int32_t prof_every = 1;         // time every prof_every-th product launch
+    int64_t prof_calls = 0;
     std::vector<hipEvent_t> prof_events;  // start/stop pairs
     size_t prof_used = 0;                 // events recorded since the last flush
     double prof_ms = 0.0;

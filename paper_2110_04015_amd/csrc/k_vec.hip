@@ -680,8 +680,8 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
                                                  const double *__restrict__ Dchol, double *__restrict__ z,
                                                  double *__restrict__ partials, uint32_t *__restrict__ ticket,
                                                  double *gamma, double *__restrict__ sc,
-                                                 double *__restrict__ host_sc, int N, double tau, double eps,
-                                                 XrzGram g1) {
+                                                 double *__restrict__ host_sc, double tag, int N, double tau,
+                                                 double eps, XrzGram g1) {
     constexpr int CB = kNT / DP;
     __shared__ double sr[CB * DP];
     __shared__ double sh[kNT];
@@ -767,7 +767,8 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
     if (host_sc && t < SC_COUNT) {   // all the scalars, for the host's read-back
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         host_sc[t] = sc[t];
-        __threadfence_system();
+        __threadfence_system();   // the values reach the host before the tag
+        if (t == 0) host_sc[SC_COUNT] = tag;
     }
 }
 
@@ -775,14 +776,15 @@ int mcg_xrz_blocks(int np, int dp) { return (np + kNT / dp - 1) / (kNT / dp); }
 
 void launch_mcg_xrz(int np, int k, const double *P, const double *Q, double *alpha, double *x, double *r,
                     const double *Dchol, double *z, double *partials, uint32_t *ticket, double *gamma,
-                    double *sc, double *host_sc, int N, double tau, double eps, hipStream_t s, int dp, XrzGram g1) {
+                    double *sc, double *host_sc, double tag, int N, double tau, double eps, hipStream_t s, int dp,
+                    XrzGram g1) {
     const unsigned nb = (unsigned)mcg_xrz_blocks(np, dp);
     if (dp == 6)
         hipLaunchKernelGGL(k_mcg_xrz<6>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
-                           ticket, gamma, sc, host_sc, N, tau, eps, g1);
+                           ticket, gamma, sc, host_sc, tag, N, tau, eps, g1);
     else
         hipLaunchKernelGGL(k_mcg_xrz<9>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
-                           ticket, gamma, sc, host_sc, N, tau, eps, g1);
+                           ticket, gamma, sc, host_sc, tag, N, tau, eps, g1);
 }
 
 void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,

@@ -208,7 +208,8 @@ void launch_mcg_scalars(int k, const double *prr, const double *prho, const doub
 // r -= Q alpha, z = D^-1 r, and the scalars of launch_mcg_scalars, from
 // mcg_xrz_blocks(np, dp) blocks' partials (2 per block) added by the last block to arrive
 // (ticket: a zero counter, left zero); that block also copies sc[0, SC_COUNT) to host_sc
-// (nullable: mapped host memory)
+// (nullable: mapped host memory of SC_COUNT + 1 doubles) and, once those values are
+// released at system scope, writes tag to host_sc[SC_COUNT]
 // For a one-column block (g1.part set) the kernel also takes the place of the Gram and
 // pseudo-inverse kernels: Delta and gamma from the camera reduction's partials (nb blocks,
 // schur_gram_blocks), then Delta^+ into g1.Dp, gamma, alpha, sc[SC_RANK] and the block entry.
@@ -221,8 +222,8 @@ struct XrzGram {
 int mcg_xrz_blocks(int np, int dp);
 void launch_mcg_xrz(int np, int k, const double *P, const double *Q, double *alpha, double *x, double *r,
                     const double *Dchol, double *z, double *partials, uint32_t *ticket, double *gamma,
-                    double *sc, double *host_sc, int N, double tau, double eps, hipStream_t s, int dp = 9,
-                    XrzGram g1 = XrzGram());
+                    double *sc, double *host_sc, double tag, int N, double tau, double eps, hipStream_t s,
+                    int dp = 9, XrzGram g1 = XrzGram());
 // Phi segments per history column: the N subsets when N > 1 (the same for one-column
 // and multidirectional steps), kPhiSeg row segments when N = 1
 int phi_segments(int N);

@@ -203,6 +203,22 @@ def test_chunk_shapes(max_tiles, max_tiles_multi):
     g.close()
 
 
+def test_product_timing_sampled(ring):
+    """Event timing of the S product: every launch, or every k-th; a negative k is refused."""
+    p, o, g = ring
+    v = _dev(np.random.default_rng(5).standard_normal(g.n))
+    for every, expect in ((1, 8), (4, 2), (3, 3)):
+        g.profile(True, every=every)
+        g.profile_read(reset=True)
+        for _ in range(8):
+            g.matvec(v)
+        ms, n = g.profile_read(reset=True)
+        g.profile(False)
+        assert n == expect and ms > 0.0, (every, n, ms)
+    with pytest.raises(ba.BAError):
+        g.profile(True, every=-1)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 3e-2)])
 def test_matmat_grouped_reduced_precision(pair, prec, tol):
     name, p, o, g = pair
