@@ -67,29 +67,6 @@ void launch_precond_rho(int np, const double *Dchol, const double *r, double *z,
 
 // ---------------------------------------------------------------- reductions
 
-__global__ __launch_bounds__(kNT) void k_dot2(int64_t n, const double *__restrict__ a0, const double *__restrict__ b0,
-                                              const double *__restrict__ a1, const double *__restrict__ b1,
-                                              double *__restrict__ partials, const double *__restrict__ done) {
-    if (done && *done != 0.0) return;
-    __shared__ double sh[kNT];
-    double s0 = 0.0, s1 = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
-        s0 += a0[i] * b0[i];
-        s1 += a1[i] * b1[i];
-    }
-    s0 = block_sum(s0, sh);
-    s1 = block_sum(s1, sh);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x * 2] = s0;
-        partials[blockIdx.x * 2 + 1] = s1;
-    }
-}
-
-void launch_dot2(int64_t n, const double *a0, const double *b0, const double *a1, const double *b1,
-                 double *partials, const double *done, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot2, dim3(kRedBlocks), dim3(kNT), 0, s, n, a0, b0, a1, b1, partials, done);
-}
-
 // one wavefront per output d
 __global__ __launch_bounds__(64) void k_finalize(const double *__restrict__ partials, int nd,
                                                  double *__restrict__ out) {

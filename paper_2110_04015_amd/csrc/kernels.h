@@ -147,9 +147,6 @@ constexpr int kPhiSeg = 16;        // row segments of a one-column Phi (Alg. 2 r
 
 // DP x DP block-Jacobi solves, dp = 9 or 6 (pose dimension)
 void launch_precond(int np, const double *Dchol, const double *r, double *z, hipStream_t s, int dp = 9);
-// partial dots: out[b * 2 + d] over blocks b < kRedBlocks
-void launch_dot2(int64_t n, const double *a0, const double *b0, const double *a1, const double *b1,
-                 double *partials, const double *done, hipStream_t s);
 // finalize: out[d] = sum_b partials[b * nd + d] (fixed order), d < nd
 void launch_finalize(const double *partials, int nd, double *out, hipStream_t s);
 
@@ -160,8 +157,8 @@ void launch_axpy(int64_t n, double a, const double *x, double *y, hipStream_t s)
 
 // PCG steps (scalars in sc[]: see k_vec.hip for the slot map)
 void launch_pcg_init(int64_t n, const double *bt, const double *Sx, double *r, double *partials, hipStream_t s);
-// alpha from n_dq pairs of partials of P^T S P and P^T r (the dot products of
-// launch_dot2, or the Gram partials of the camera reduction)
+// alpha from n_dq pairs of partials of P^T S P and P^T r (the Gram partials the camera
+// reduction or the explicit-S product leaves)
 void launch_pcg_update_xr(int64_t n, const double *partials_dq, int n_dq, double *sc, double *x, double *r,
                           const double *P, const double *Q, double *partials_rr, hipStream_t s);
 void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const double *Q, double *z,
