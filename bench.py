@@ -359,7 +359,7 @@ def main():
             return time.perf_counter() - t2
         probe = 2
         tp = run(probe)
-        k = max(probe, min(st.iterations, int(15.0 / max(tp / probe, 1e-6))))
+        k = max(probe, min(st.iterations, int(10.0 / max(tp / probe, 1e-6))))
         tk = run(k) if k > probe else tp
         per_it = tk / k
         est_solve = per_it * st.iterations
