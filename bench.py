@@ -3,7 +3,8 @@
 One step = one complete solve of S dx_p = -b~ from x0 = 0 to a 1e-6 relative
 residual (all device kernels of the chosen solver; the system is built once,
 outside the timed region, with its inputs resident in HBM).  Prints one JSON
-line.  See the design doc for the workload recipe and the roofline accounting.
+line, with the dominant kernel's roofline (algorithmic bytes per launch over its
+event-timed average duration) and the CPU oracle's rate on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--solver mcg|pcg] [--N 16] [--tau 3.3]
 """
