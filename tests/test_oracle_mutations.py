@@ -40,7 +40,7 @@ def _rel(a, b):
 
 
 def run_pins(libobj):
-    """Return the names of the checks that fail for this build of the oracle."""
+    """Return the names of the checks that fail for the oracle as built (with any planted mistake)."""
     failed = []
     p = synth.tiny(n_cams=5, n_lms=40, seed=2, c_hi=5)
     p.lam = 1e-2
