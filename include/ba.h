@@ -327,6 +327,19 @@ ba_status ba_explicit_schur_info(const ba_system *sys, int64_t *nnz_blocks, int6
  * successful update). */
 ba_status ba_update_system(ba_system *sys, const double *J_p, const double *J_l, const double *r, double lambda);
 
+/* A new damping coefficient lambda (eq. (6), Marquardt damping D^T D = diag(J^T J))
+ * for the same linearisation: the LM loop's accept/reject step (Sec. 4.1) after a
+ * rejected step.  Recomputes every value that depends on lambda -- V_lambda^-1 and
+ * V_lambda^-1 b_l per landmark, U_lambda's damping, D(S), its factor and b~
+ * (eq. (9)-(15)), and the explicit S when the system keeps one -- from the undamped
+ * blocks J_l^T J_l, J_p^T J_p, b_l and b_p kept at build and the packed Jacobian
+ * stream, without reading J or r again.  The result equals, bit for bit, a fresh
+ * ba_build_system (or ba_update_system) of the same J and r at this lambda.  A
+ * low-rank preconditioner term set before stays as set.  Errors: INVALID_ARG (NULL,
+ * lambda < 0, batch systems), NONFINITE (nothing changed), NOT_SPD (the values are
+ * undefined until a successful ba_set_lambda or ba_update_system), HIP. */
+ba_status ba_set_lambda(ba_system *sys, double lambda);
+
 /* ------------------------------------------------------------------ LM outer loop
  * The Levenberg-Marquardt loop of Sec. 4.1 around the solvers above, for the
  * nine-parameter camera (Sec. 3.1, d_p = 9).  Camera c is 15 doubles: R

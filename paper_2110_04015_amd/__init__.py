@@ -253,6 +253,10 @@ class System:
                                       _dev_ptr(J_l, torch.float64, m * 6, "J_l"),
                                       _dev_ptr(r, torch.float64, m * 2, "r"), float(lam)), "ba_update_system")
 
+    def set_lambda(self, lam):
+        """A new damping lambda for the same linearisation (ba_set_lambda), J is not read again."""
+        _check(lib().ba_set_lambda(self.h, float(lam)), "ba_set_lambda")
+
     def back_substitute(self, dxp):
         torch = _torch()
         out = self._new(self.n_lms * 3)

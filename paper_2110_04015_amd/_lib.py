@@ -105,6 +105,7 @@ SIGNATURES = [
     ("ba_batch_mcg_solve", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
                                      C.POINTER(BatchStats), C.POINTER(C.c_double)]),
     ("ba_update_system", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
+    ("ba_set_lambda", C.c_int, [C.c_void_p, C.c_double]),
     ("ba_default_lm_opts", None, [C.POINTER(LMOpts)]),
     ("ba_project", C.c_int, [C.POINTER(SceneDesc), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.POINTER(C.c_double), C.c_void_p]),

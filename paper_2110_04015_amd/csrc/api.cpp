@@ -90,8 +90,11 @@ void free_all(ba_system *s) {
     dfree(s->lmk_store);
     dfree(s->obs_lm);
     dfree(s->h0);
+    dfree(s->Vraw);
+    dfree(s->Uraw);
+    dfree(s->bp);
+    dfree(s->obs_slot);
     dfree(s->bsr_slot_cam);
-    dfree(s->bsr_obs_slot);
     dfree(s->meta);
     dfree(s->tile_lmk_base);
     dfree(s->chunk_tile);
@@ -460,6 +463,8 @@ void fill_default_opts(ba_solve_opts *o) {
 
 namespace ba {
 ba_status set_error(ba_status st, const std::string &msg) { return fail(st, msg); }
+SchurArgs system_schur_args(ba_system *s, int precision) { return schur_args(s, precision); }
+bool system_uses_bsr(const ba_system *s, const SchurArgs &a) { return use_bsr(s, a); }
 
 ba_status prepare_mcg(ba_system *s, int N, int precision) {
     ba_status st = ensure_precision(s, precision);
@@ -520,10 +525,45 @@ static BsrGather bsr_gather(const ba_system *s) {
     return g;
 }
 
+// The values of a system that depend on lambda (s->lambda), from the lambda-free sums
+// and the packed Jacobian stream: V_lambda^-1 and h0 = V_lambda^-1 b_l per landmark,
+// D(S), its factor, the damping of the S product and b~ per camera (eq. (9)-(15)), and
+// the explicit S when the system keeps one.  Waits for the stream.
+static ba_status apply_lambda(ba_system *s) {
+    hipStream_t q = s->stream;
+    HIPCHK(hipMemsetAsync(s->status, 0, sizeof(int32_t), q));
+    launch_landmarks_lambda(s->nl, s->Vraw, s->bl, s->lambda, s->vinv, s->h0, s->status, q);
+    launch_cameras_lambda(s->np, s->cam_obs_ptr, s->cam_obs, s->obs_lm, s->lmk_store, s->obs_slot, s->J64, s->Uraw,
+                          s->bp, s->vinv, s->h0, s->lambda, s->dU, s->Dblk, s->Dchol, s->bt, s->status, q, s->dp);
+    if (s->bsr_val) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        if (e0) (void)hipEventRecord(e0, q);
+        launch_bsr_assemble(s->np, bsr_gather(s), s->obs_slot, s->J64, s->vinv, s->Dblk, s->bsr_ptr, s->bsr_col,
+                            s->bsr_max_row, s->bsr_val, q);
+        if (e1) (void)hipEventRecord(e1, q);
+        if (hipStreamSynchronize(q) == hipSuccess && e0 && e1) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) s->bsr_build_ms = ms;
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+    HIPCHK(hipGetLastError());
+    int32_t hst = 0;
+    HIPCHK(hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q));
+    HIPCHK(hipStreamSynchronize(q));
+    if (hst & kStatusNotSpdLandmark) return fail(BA_ERR_NOT_SPD, "a landmark block V_lambda is not positive definite");
+    if (hst & kStatusNotSpdCamera)
+        return fail(BA_ERR_NOT_SPD, "a block of D(S) is not positive definite (unobserved camera?)");
+    return BA_OK;
+}
+
 // Values of a system whose layout is set: checks J_p, J_l, r (device, observation
-// order of the build) for NaN/Inf, packs the Jacobian stream, and forms V_lambda^-1,
-// b_l, U_lambda's damping, D(S), its factor and b~ (eq. (9)-(15)) for s->lambda; the
-// explicit S too when the system keeps one.  Waits for the stream.
+// order of the build) for NaN/Inf, packs the Jacobian stream, forms the lambda-free
+// sums (J_l^T J_l, b_l, J_p^T J_p, b_p), then the values for s->lambda.  Waits for the
+// stream.
 static ba_status fill_values(ba_system *s, const double *J_p, const double *J_l, const double *r) {
     hipStream_t q = s->stream;
     const int64_t m = s->m;
@@ -538,32 +578,10 @@ static ba_status fill_values(ba_system *s, const double *J_p, const double *J_l,
     HIPCHK(hipStreamSynchronize(q));
     if (hst & kStatusNonfinite) return fail(BA_ERR_NONFINITE, "NaN or Inf in J_p, J_l or r");
     launch_pack(s->slot_obs, nslots, J_p, J_l, s->J64, s->J32, s->J16, q, s->dp);
-    launch_landmarks(s->nl, s->lmk_first_slot, s->lmk_count, s->slot_obs, J_l, r, s->lambda, s->vinv, s->bl, s->h0,
-                     s->status, q);
-    launch_cameras(s->np, s->cam_obs_ptr, s->cam_obs, s->obs_lm, s->lmk_store, J_p, J_l, r, s->vinv, s->h0,
-                   s->lambda, s->dU, s->Dblk, s->Dchol, s->bt, s->status, q, s->dp);
-    if (s->bsr_val) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
-        if (e0) (void)hipEventRecord(e0, q);
-        launch_bsr_assemble(s->np, bsr_gather(s), s->bsr_obs_slot, s->J64, s->vinv, s->Dblk, s->bsr_ptr, s->bsr_col,
-                            s->bsr_max_row, s->bsr_val, q);
-        if (e1) (void)hipEventRecord(e1, q);
-        if (hipStreamSynchronize(q) == hipSuccess && e0 && e1) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) s->bsr_build_ms = ms;
-        }
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-    }
+    launch_landmarks_base(s->nl, s->lmk_first_slot, s->lmk_count, s->slot_obs, J_l, r, s->Vraw, s->bl, q);
+    launch_cameras_base(s->np, s->cam_obs_ptr, s->cam_obs, J_p, r, s->Uraw, s->bp, q, s->dp);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&hst, s->status, 4, hipMemcpyDeviceToHost, q));
-    HIPCHK(hipStreamSynchronize(q));
-    if (hst & kStatusNotSpdLandmark) return fail(BA_ERR_NOT_SPD, "a landmark block V_lambda is not positive definite");
-    if (hst & kStatusNotSpdCamera)
-        return fail(BA_ERR_NOT_SPD, "a block of D(S) is not positive definite (unobserved camera?)");
-    return BA_OK;
+    return apply_lambda(s);
 }
 
 static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream,
@@ -593,6 +611,10 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
 
     ba_system *s = new ba_system();
     s->stream = (hipStream_t)stream;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(BA_ERR_HIP, "no current HIP device");
+    }
     s->np = d->n_cams;
     s->nl = d->n_lms;
     s->m = d->n_obs;
@@ -631,6 +653,19 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
     if ((st = upload(&s->lmk_store, P.lmk_store, q)) != BA_OK) return bail(st);
     if ((st = upload(&s->obs_lm, hlm, q)) != BA_OK) return bail(st);
     if ((st = dalloc(&s->h0, (size_t)s->nl * 3)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->Vraw, (size_t)s->nl * 6)) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->Uraw, (size_t)s->np * (d->d_p * (d->d_p + 1) / 2))) != BA_OK) return bail(st);
+    if ((st = dalloc(&s->bp, (size_t)s->np * d->d_p)) != BA_OK) return bail(st);
+    {
+        // tile slot of every observation (the lambda kernels read the packed stream by it)
+        std::vector<int64_t> oslot((size_t)m, 0);
+        for (int64_t sl = 0; sl < P.n_tiles * kTile; ++sl) {
+            const int64_t o = P.slot_obs[(size_t)sl];
+            if (o >= 0) oslot[(size_t)o] = sl;
+        }
+        if ((st = upload(&s->obs_slot, oslot, q)) != BA_OK) return bail(st);
+        if (hipStreamSynchronize(q) != hipSuccess) return bail(fail(BA_ERR_HIP, "uploading the slot map failed"));
+    }
     if ((st = upload(&s->meta, P.meta, q)) != BA_OK) return bail(st);
     if ((st = upload(&s->tile_lmk_base, P.tile_lmk_base, q)) != BA_OK) return bail(st);
     if ((st = upload(&s->chunk_tile, P.chunk_tile, q)) != BA_OK) return bail(st);
@@ -657,17 +692,13 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
         // explicit S in block-sparse rows, assembled from the same blocks (Sec. 3.2, 4.1): the
         // pattern and the contribution pairs depend on the observations only
         if (cam_seg) return bail(fail(BA_ERR_UNSUPPORTED, "batches use the implicit S products"));
-        // camera of every observation slot and slot of every observation (host, from the plan)
+        // camera of every observation slot (host, from the plan)
         std::vector<int32_t> scam((size_t)nslots, 0);
-        std::vector<int64_t> oslot((size_t)m, 0);
         for (int64_t sl = 0; sl < nslots; ++sl) {
             const int64_t o = P.slot_obs[(size_t)sl];
-            if (o < 0) continue;
-            scam[(size_t)sl] = P.obs_cam[(size_t)o];
-            oslot[(size_t)o] = sl;
+            if (o >= 0) scam[(size_t)sl] = P.obs_cam[(size_t)o];
         }
         if ((st = upload(&s->bsr_slot_cam, scam, q)) != BA_OK) return bail(st);
-        if ((st = upload(&s->bsr_obs_slot, oslot, q)) != BA_OK) return bail(st);
         // pattern on the device: block counts per row, then the rows' columns
         int32_t *d_nnz = nullptr;
         if ((st = dalloc(&d_nnz, (size_t)s->np)) != BA_OK) return bail(st);
@@ -724,6 +755,15 @@ ba_status ba_update_system(ba_system *s, const double *J_p, const double *J_l, c
     const ba_status st = fill_values(s, J_p, J_l, r);
     if (st == BA_ERR_NONFINITE) s->lambda = prev;   // rejected before any value changed
     return st;
+}
+
+ba_status ba_set_lambda(ba_system *s, double lambda) {
+    if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    if (s->seg_cam) return fail(BA_ERR_INVALID_ARG, "batch systems are not updated in place");
+    if (!std::isfinite(lambda)) return fail(BA_ERR_NONFINITE, "lambda is not finite");
+    if (lambda < 0.0) return fail(BA_ERR_INVALID_ARG, "lambda must be >= 0");
+    s->lambda = lambda;
+    return apply_lambda(s);
 }
 
 ba_status ba_profile_enable(ba_system *s, int32_t on) {

@@ -119,11 +119,18 @@ ba_status set_error(ba_status st, const std::string &msg);
 // Jacobian copy, the partition, the multidirectional product's layout), ahead of the solves.
 ba_status prepare_mcg(ba_system *s, int N, int precision);
 
+struct SchurArgs;
+// Arguments of the system's chunked S product in a precision (partial rows in the
+// system's own buffer), and whether its FP64 products read the explicit S instead.
+SchurArgs system_schur_args(ba_system *s, int precision);
+bool system_uses_bsr(const ba_system *s, const SchurArgs &a);
+
 }  // namespace ba
 
 // The system handle.
 struct ba_system {
     hipStream_t stream = nullptr;
+    int device = 0;                 // HIP device current at the build
     int np = 0, nl = 0;
     int dp = 9;                     // pose dimension d_p (9, or 6 for extrinsics only)
     int64_t m = 0;
@@ -155,8 +162,11 @@ struct ba_system {
     int32_t *lmk_store = nullptr;   // observation -> storage index of its landmark
     int32_t *obs_lm = nullptr;      // copy of the observations' landmarks
     double *h0 = nullptr;           // nl * 3: V^-1 b_l (storage order)
+    double *Vraw = nullptr;         // nl * 6: undamped J_l^T J_l (storage order)
+    double *Uraw = nullptr;         // np * dp (dp + 1) / 2: undamped J_p^T J_p, packed upper triangle
+    double *bp = nullptr;           // np * dp: b_p = J_p^T r0
+    int64_t *obs_slot = nullptr;    // tile slot of every observation
     int32_t *bsr_slot_cam = nullptr;// explicit S: camera of every observation slot
-    int64_t *bsr_obs_slot = nullptr;// explicit S: slot of every observation
     int bsr_max_row = 0;
     // solver scratch (allocated on demand)
     double *vec = nullptr;          // work vectors

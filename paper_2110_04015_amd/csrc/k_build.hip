@@ -100,16 +100,15 @@ void launch_convert(const double *J64, int64_t nslots, float *J32, uint16_t *J16
 
 // ---------------------------------------------------------------- landmarks
 
-// One thread per landmark (storage order): V_lambda = J_l^T J_l + lambda diag(J_l^T J_l)
-// (eq. (10)), b_l = J_l^T r0 (eq. (12)), V_lambda^-1 (symmetric, 6 entries) and
-// h0 = V_lambda^-1 b_l.
-__global__ void k_landmarks(int nl, const int64_t *__restrict__ first_slot, const int32_t *__restrict__ count,
-                            const int64_t *__restrict__ slot_obs, const double *__restrict__ Jl,
-                            const double *__restrict__ r, double lambda, double *__restrict__ vinv,
-                            double *__restrict__ bl, double *__restrict__ h0, int32_t *status) {
+// One thread per landmark (storage order): the undamped block J_l^T J_l of eq. (10)
+// (symmetric, 6 entries: 00 01 02 11 12 22) and b_l = J_l^T r0 (eq. (12)).  Neither
+// depends on lambda, so a new lambda re-uses them.
+__global__ void k_landmarks_base(int nl, const int64_t *__restrict__ first_slot, const int32_t *__restrict__ count,
+                                 const int64_t *__restrict__ slot_obs, const double *__restrict__ Jl,
+                                 const double *__restrict__ r, double *__restrict__ Vraw, double *__restrict__ bl) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nl) return;
-    double V[6] = {0, 0, 0, 0, 0, 0};   // 00 01 02 11 12 22
+    double V[6] = {0, 0, 0, 0, 0, 0};
     double b[3] = {0, 0, 0};
     int64_t f = first_slot[s];
     int c = count[s];
@@ -127,6 +126,21 @@ __global__ void k_landmarks(int nl, const int64_t *__restrict__ first_slot, cons
         b[1] += j[1] * r0 + j[4] * r1;
         b[2] += j[2] * r0 + j[5] * r1;
     }
+    for (int k = 0; k < 6; ++k) Vraw[(int64_t)s * 6 + k] = V[k];
+    for (int k = 0; k < 3; ++k) bl[(int64_t)s * 3 + k] = b[k];
+}
+
+// One thread per landmark: V_lambda = V + lambda diag(V) (eq. (10) with Marquardt
+// damping), V_lambda^-1 (symmetric, 6 entries) by its 3x3 Cholesky factor, and
+// h0 = V_lambda^-1 b_l.
+__global__ void k_landmarks_lambda(int nl, const double *__restrict__ Vraw, const double *__restrict__ bl,
+                                   double lambda, double *__restrict__ vinv, double *__restrict__ h0,
+                                   int32_t *status) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nl) return;
+    double V[6], b[3];
+    for (int k = 0; k < 6; ++k) V[k] = Vraw[(int64_t)s * 6 + k];
+    for (int k = 0; k < 3; ++k) b[k] = bl[(int64_t)s * 3 + k];
     V[0] += lambda * V[0];
     V[3] += lambda * V[3];
     V[5] += lambda * V[5];
@@ -156,7 +170,6 @@ __global__ void k_landmarks(int nl, const int64_t *__restrict__ first_slot, cons
     w[4] = i22 * i21;
     w[5] = i22 * i22;
     for (int k = 0; k < 6; ++k) vinv[(int64_t)s * 6 + k] = w[k];
-    for (int k = 0; k < 3; ++k) bl[(int64_t)s * 3 + k] = b[k];
     h0[(int64_t)s * 3 + 0] = w[0] * b[0] + w[1] * b[1] + w[2] * b[2];
     h0[(int64_t)s * 3 + 1] = w[1] * b[0] + w[3] * b[1] + w[4] * b[2];
     h0[(int64_t)s * 3 + 2] = w[2] * b[0] + w[4] * b[1] + w[5] * b[2];
@@ -169,32 +182,21 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One wavefront per camera.  Pass 1: U = J_p^T J_p and b_p = J_p^T r0 over the
-// camera's observations (eq. (9), (11)).  Pass 2: E = sum_o W_o V^-1 W_o^T and
-// w = sum_o W_o V^-1 b_l with W_o = J_p,o^T J_l,o.  Then
-//   D(S)_c = U + lambda diag(U) - E   (diagonal block of eq. (14))
-//   b~_c   = b_p - w                  (eq. (15))
-// and the Cholesky factor of D(S)_c.  DP x DP blocks (DP = 9, or 6 for extrinsics only).
+// One wavefront per camera: the undamped block U = J_p^T J_p (eq. (9), packed upper
+// triangle) and b_p = J_p^T r0 (eq. (11)) over the camera's observations.  Neither
+// depends on lambda.  DP x DP blocks (DP = 9, or 6 for extrinsics only).
 template <int DP>
-__global__ __launch_bounds__(64) void k_cameras(int np, const int64_t *__restrict__ cam_ptr,
-                                                const int64_t *__restrict__ cam_obs,
-                                                const int32_t *__restrict__ obs_lm,
-                                                const int32_t *__restrict__ lmk_store,
-                                                const double *__restrict__ Jp, const double *__restrict__ Jl,
-                                                const double *__restrict__ r, const double *__restrict__ vinv,
-                                                const double *__restrict__ h0, double lambda,
-                                                double *__restrict__ dU, double *__restrict__ Dblk,
-                                                double *__restrict__ Dchol, double *__restrict__ bt,
-                                                int32_t *status) {
+__global__ __launch_bounds__(64) void k_cameras_base(int np, const int64_t *__restrict__ cam_ptr,
+                                                     const int64_t *__restrict__ cam_obs,
+                                                     const double *__restrict__ Jp, const double *__restrict__ r,
+                                                     double *__restrict__ Uraw, double *__restrict__ bp) {
     constexpr int T = DP * (DP + 1) / 2;   // packed upper triangle
     constexpr int NA = T + DP;
     int c = blockIdx.x;
     int lane = threadIdx.x;
     if (c >= np) return;
-    __shared__ double red[NA];
     int64_t a = cam_ptr[c], b = cam_ptr[c + 1];
     double acc[NA];
-    // pass 1: U (upper triangle) and b_p
     for (int k = 0; k < NA; ++k) acc[k] = 0.0;
     for (int64_t q = a + lane; q < b; q += 64) {
         int64_t o = cam_obs[q];
@@ -207,18 +209,55 @@ __global__ __launch_bounds__(64) void k_cameras(int np, const int64_t *__restric
     }
     for (int k = 0; k < NA; ++k) {
         double v = wave_sum(acc[k]);
-        if (lane == 0) red[k] = v;
+        if (lane == 0) {
+            if (k < T) Uraw[(int64_t)c * T + k] = v;
+            else bp[(int64_t)c * DP + (k - T)] = v;
+        }
     }
-    __syncthreads();
-    double U[T], bp[DP];
-    for (int k = 0; k < T; ++k) U[k] = red[k];
-    for (int k = 0; k < DP; ++k) bp[k] = red[T + k];
-    __syncthreads();
-    // pass 2: E = sum W V^-1 W^T (upper) and w = sum W h0
+}
+
+// One wavefront per camera, for the current lambda: E = sum_o W_o V_lambda^-1 W_o^T and
+// w = sum_o W_o h0 with W_o = J_p,o^T J_l,o read back from the packed tile stream (the
+// observation's slot from obs_slot), then
+//   D(S)_c = U + lambda diag(U) - E   (diagonal block of eq. (14))
+//   b~_c   = b_p - w                  (eq. (15))
+// the damping lambda diag(U) of the S product, and the Cholesky factor of D(S)_c.
+template <int DP>
+__global__ __launch_bounds__(64) void k_cameras_lambda(int np, const int64_t *__restrict__ cam_ptr,
+                                                       const int64_t *__restrict__ cam_obs,
+                                                       const int32_t *__restrict__ obs_lm,
+                                                       const int32_t *__restrict__ lmk_store,
+                                                       const int64_t *__restrict__ obs_slot,
+                                                       const double *__restrict__ J64,
+                                                       const double *__restrict__ Uraw, const double *__restrict__ bpv,
+                                                       const double *__restrict__ vinv,
+                                                       const double *__restrict__ h0, double lambda,
+                                                       double *__restrict__ dU, double *__restrict__ Dblk,
+                                                       double *__restrict__ Dchol, double *__restrict__ bt,
+                                                       int32_t *status) {
+    typedef RecordShape<DP> R;
+    constexpr int T = DP * (DP + 1) / 2;
+    constexpr int NA = T + DP;
+    int c = blockIdx.x;
+    int lane = threadIdx.x;
+    if (c >= np) return;
+    __shared__ double red[NA];
+    int64_t a = cam_ptr[c], b = cam_ptr[c + 1];
+    const double2 *d2 = reinterpret_cast<const double2 *>(J64);
+    double acc[NA];
     for (int k = 0; k < NA; ++k) acc[k] = 0.0;
     for (int64_t q = a + lane; q < b; q += 64) {
         int64_t o = cam_obs[q];
-        const double *jp = Jp + o * 2 * DP, *jl = Jl + o * 6;
+        const int64_t sl = obs_slot[o];
+        const int64_t tile = sl / kTile;
+        const int sl_lane = (int)(sl % kTile);
+        double v[2 * R::kW64];
+        for (int w = 0; w < R::kW64; ++w) {
+            const double2 d = d2[(tile * R::kW64 + w) * kTile + sl_lane];
+            v[2 * w] = d.x;
+            v[2 * w + 1] = d.y;
+        }
+        const double *jp = v, *jl = v + 2 * DP;
         int64_t ls = lmk_store[obs_lm[o]];
         const double *vi = vinv + ls * 6;
         const double *hh = h0 + ls * 3;
@@ -244,6 +283,7 @@ __global__ __launch_bounds__(64) void k_cameras(int np, const int64_t *__restric
     }
     __syncthreads();
     if (lane != 0) return;
+    const double *U = Uraw + (int64_t)c * T;
     double D[DP * DP];
     int t = 0;
     for (int i = 0; i < DP; ++i) {
@@ -258,7 +298,7 @@ __global__ __launch_bounds__(64) void k_cameras(int np, const int64_t *__restric
     for (int i = 0; i < DP; ++i) {
         int diag = i * DP - (i * (i - 1)) / 2;   // index of (i, i) in the packed upper triangle
         dU[(int64_t)c * DP + i] = lambda * U[diag];
-        bt[(int64_t)c * DP + i] = bp[i] - red[T + i];
+        bt[(int64_t)c * DP + i] = bpv[(int64_t)c * DP + i] - red[T + i];
     }
     for (int k = 0; k < DP * DP; ++k) Dblk[(int64_t)c * DP * DP + k] = D[k];
     // packed lower Cholesky factor, row i holds L[i][0..i]
@@ -298,23 +338,36 @@ void launch_pack(const int64_t *slot_obs, int64_t nslots, const double *Jp, cons
     else hipLaunchKernelGGL(k_pack<9>, g, dim3(256), 0, s, slot_obs, nslots, Jp, Jl, J64, J32, J16);
 }
 
-void launch_landmarks(int nl, const int64_t *first_slot, const int32_t *count, const int64_t *slot_obs,
-                      const double *Jl, const double *r, double lambda, double *vinv, double *bl, double *h0,
-                      int32_t *status, hipStream_t s) {
-    hipLaunchKernelGGL(k_landmarks, dim3((nl + 255) / 256), dim3(256), 0, s, nl, first_slot, count, slot_obs, Jl,
-                       r, lambda, vinv, bl, h0, status);
+void launch_landmarks_base(int nl, const int64_t *first_slot, const int32_t *count, const int64_t *slot_obs,
+                           const double *Jl, const double *r, double *Vraw, double *bl, hipStream_t s) {
+    hipLaunchKernelGGL(k_landmarks_base, dim3((nl + 255) / 256), dim3(256), 0, s, nl, first_slot, count, slot_obs, Jl,
+                       r, Vraw, bl);
 }
 
-void launch_cameras(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const int32_t *obs_lm,
-                    const int32_t *lmk_store, const double *Jp, const double *Jl, const double *r,
-                    const double *vinv, const double *h0, double lambda, double *dU, double *Dblk,
-                    double *Dchol, double *bt, int32_t *status, hipStream_t s, int dp) {
+void launch_landmarks_lambda(int nl, const double *Vraw, const double *bl, double lambda, double *vinv, double *h0,
+                             int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_landmarks_lambda, dim3((nl + 255) / 256), dim3(256), 0, s, nl, Vraw, bl, lambda, vinv, h0,
+                       status);
+}
+
+void launch_cameras_base(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const double *Jp, const double *r,
+                         double *Uraw, double *bp, hipStream_t s, int dp) {
     if (dp == 6)
-        hipLaunchKernelGGL(k_cameras<6>, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, obs_lm, lmk_store, Jp, Jl,
-                           r, vinv, h0, lambda, dU, Dblk, Dchol, bt, status);
+        hipLaunchKernelGGL(k_cameras_base<6>, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, Jp, r, Uraw, bp);
     else
-        hipLaunchKernelGGL(k_cameras<9>, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, obs_lm, lmk_store, Jp, Jl,
-                           r, vinv, h0, lambda, dU, Dblk, Dchol, bt, status);
+        hipLaunchKernelGGL(k_cameras_base<9>, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, Jp, r, Uraw, bp);
+}
+
+void launch_cameras_lambda(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const int32_t *obs_lm,
+                           const int32_t *lmk_store, const int64_t *obs_slot, const double *J64, const double *Uraw,
+                           const double *bp, const double *vinv, const double *h0, double lambda, double *dU,
+                           double *Dblk, double *Dchol, double *bt, int32_t *status, hipStream_t s, int dp) {
+    if (dp == 6)
+        hipLaunchKernelGGL(k_cameras_lambda<6>, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, obs_lm, lmk_store,
+                           obs_slot, J64, Uraw, bp, vinv, h0, lambda, dU, Dblk, Dchol, bt, status);
+    else
+        hipLaunchKernelGGL(k_cameras_lambda<9>, dim3(np), dim3(64), 0, s, np, cam_ptr, cam_obs, obs_lm, lmk_store,
+                           obs_slot, J64, Uraw, bp, vinv, h0, lambda, dU, Dblk, Dchol, bt, status);
 }
 
 }  // namespace ba

@@ -66,13 +66,19 @@ void launch_check_finite(const double *a, int64_t count, int32_t *status, hipStr
 void launch_pack(const int64_t *slot_obs, int64_t nslots, const double *Jp, const double *Jl, double *J64,
                  float *J32, uint16_t *J16, hipStream_t s, int dp = 9);
 void launch_convert(const double *J64, int64_t nslots, float *J32, uint16_t *J16, hipStream_t s, int dp = 9);
-void launch_landmarks(int nl, const int64_t *first_slot, const int32_t *count, const int64_t *slot_obs,
-                      const double *Jl, const double *r, double lambda, double *vinv, double *bl, double *h0,
-                      int32_t *status, hipStream_t s);
-void launch_cameras(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const int32_t *obs_lm,
-                    const int32_t *lmk_store, const double *Jp, const double *Jl, const double *r,
-                    const double *vinv, const double *h0, double lambda, double *dU, double *Dblk,
-                    double *Dchol, double *bt, int32_t *status, hipStream_t s, int dp = 9);
+// lambda-independent sums (read the caller's J and r): J_l^T J_l and b_l per landmark,
+// J_p^T J_p (packed upper triangle) and b_p per camera
+void launch_landmarks_base(int nl, const int64_t *first_slot, const int32_t *count, const int64_t *slot_obs,
+                           const double *Jl, const double *r, double *Vraw, double *bl, hipStream_t s);
+void launch_cameras_base(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const double *Jp, const double *r,
+                         double *Uraw, double *bp, hipStream_t s, int dp = 9);
+// the values that depend on lambda, from those sums and the packed tile stream
+void launch_landmarks_lambda(int nl, const double *Vraw, const double *bl, double lambda, double *vinv, double *h0,
+                             int32_t *status, hipStream_t s);
+void launch_cameras_lambda(int np, const int64_t *cam_ptr, const int64_t *cam_obs, const int32_t *obs_lm,
+                           const int32_t *lmk_store, const int64_t *obs_slot, const double *J64, const double *Uraw,
+                           const double *bp, const double *vinv, const double *h0, double lambda, double *dU,
+                           double *Dblk, double *Dchol, double *bt, int32_t *status, hipStream_t s, int dp = 9);
 
 // ---- Schur products (k_schur.hip)
 struct SchurArgs {

@@ -218,7 +218,9 @@ ba_status ba_lm_solve(const ba_scene_desc *sc, double *cams, double *X, const ba
                 result = st;
                 break;
             }
-            if ((st = ba_update_system(sys, b.Jp, b.Jl, b.r, lam)) != BA_OK) {
+            // a rejected step keeps J and r: only the values that depend on lambda change
+            st = accept ? ba_update_system(sys, b.Jp, b.Jl, b.r, lam) : ba_set_lambda(sys, lam);
+            if (st != BA_OK) {
                 result = st;
                 break;
             }
