@@ -502,7 +502,7 @@ int or_pcg(const or_sys *s, const double *x0, double *x, double eps, int imax, o
     double *r = (double *)malloc(sizeof(double) * n), *Z = (double *)malloc(sizeof(double) * n);
     double *P = (double *)malloc(sizeof(double) * n), *Q = (double *)malloc(sizeof(double) * n);
     memset(st, 0, sizeof(*st));
-    /* r0 = -b~ - S x0 */
+    /* residual of the start point (x0 = 0 unless given) */
     if (x0) memcpy(x, x0, sizeof(double) * n); else memset(x, 0, sizeof(double) * n);
     or_schur_matvec(s, x, Q);
     for (int i = 0; i < n; ++i) r[i] = -s->bt[i] - Q[i];
@@ -514,7 +514,7 @@ int or_pcg(const or_sys *s, const double *x0, double *x, double eps, int imax, o
     memcpy(P, Z, sizeof(double) * n);
     status = OR_MAXITER;
     for (it = 0; it < imax; ) {
-        or_schur_matvec(s, P, Q);                         /* Q_i = S P_i */
+        or_schur_matvec(s, P, Q);                         /* image of the direction under S */
         double Delta = dot(Q, P, n), gamma = dot(P, r, n);
         if (!(Delta > 0.0)) { status = OR_ERR_BREAKDOWN; break; }
         double alpha = gamma / Delta;
@@ -523,8 +523,10 @@ int or_pcg(const or_sys *s, const double *x0, double *x, double eps, int imax, o
         rn = sqrt(dot(r, r, n));
         if (trace) trace[it - 1] = rn / r0;
         if (rn < eps * r0) { status = OR_OK; break; }
-        or_precond_apply(s, r, Z);                        /* Z_{i+1} = D(S)^-1 r_{i+1} */
-        double beta = dot(Q, Z, n) / Delta;               /* Phi_i / Delta_i */
+        or_precond_apply(s, r, Z);                        /* preconditioned residual */
+        /* next direction: Z minus its S-projection on the current one, which makes the
+         * two S-conjugate (coefficient (S P)^T Z / P^T S P) */
+        double beta = dot(Q, Z, n) / Delta;
         for (int i = 0; i < n; ++i) P[i] = Z[i] - beta * P[i];
     }
 done:
@@ -569,7 +571,7 @@ int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, doub
     int status = OR_OK, it = 0;
     if (r0 == 0.0) goto done;
 
-    /* P_0 = Z_0 = D(S)^-1 r_0 ; Q_0 = S P_0 */
+    /* first block: the preconditioned residual of the start point, and its image under S */
     H[0].k = 1;
     H[0].P = (double *)malloc(sizeof(double) * n);
     H[0].Q = (double *)malloc(sizeof(double) * n);
@@ -581,7 +583,8 @@ int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, doub
     for (it = 0; it < imax; ) {
         blk_t *B = &H[nb - 1];
         int k = B->k;
-        /* Delta_i = Q_i^T P_i (symmetrised), gamma_i = P_i^T r_i, alpha_i = Delta_i^+ gamma_i */
+        /* step along the whole block: the Galerkin condition P^T (r - S P a) = 0 asks for
+         * (P^T S P) a = P^T r; the Gram block is symmetrised and pseudo-inverted (reading R3) */
         double *Delta = (double *)malloc(sizeof(double) * k * k);
         double *gamma = (double *)malloc(sizeof(double) * k), *alpha = (double *)malloc(sizeof(double) * k);
         for (int a = 0; a < k; ++a)
@@ -602,7 +605,7 @@ int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, doub
             for (int b = 0; b < k; ++b) t += B->Dp[a * k + b] * gamma[b];
             alpha[a] = t;
         }
-        /* x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i */
+        /* move along the block; the residual moves by the stored image S P of the block */
         for (int a = 0; a < k; ++a) {
             const double *Pa = B->P + (size_t)a * n, *Qa = B->Q + (size_t)a * n;
             double al = alpha[a];
@@ -612,7 +615,8 @@ int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, doub
         rn = sqrt(dot(r, r, n));
         if (trace) { trace[(it - 1) * 3 + 0] = rn / r0; trace[(it - 1) * 3 + 1] = NAN; trace[(it - 1) * 3 + 2] = 0; }
         if (rn < eps * r0) { free(gamma); free(alpha); status = OR_OK; break; }
-        /* tau-test: t_i = gamma_i^T alpha_i / (r^T D(S)^-1 r) */
+        /* tau-test (Sec. 3.2): the decrease of the energy error the step achieved, relative
+         * to r^T D(S)^-1 r of the new residual; small values call for more directions */
         or_precond_apply(s, r, z);
         double rho = dot(r, z, n);
         double ga = dot(gamma, alpha, k);
@@ -621,7 +625,8 @@ int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, doub
         int is_multi = (N > 1) && (t_i < tau);
         int kn = is_multi ? N : 1;
         if (trace) { trace[(it - 1) * 3 + 1] = t_i; trace[(it - 1) * 3 + 2] = kn; }
-        /* Z_{i+1}: the global preconditioned residual, or its split into the N subsets */
+        /* candidate directions: the preconditioned residual, or its restriction to each of
+         * the N pose subsets (columns summing to it) */
         double *Z = (double *)calloc((size_t)n * kn, sizeof(double));
         if (is_multi) {
             for (int c = 0; c < np; ++c)
@@ -629,8 +634,11 @@ int or_mcg(const or_sys *s, int N, double tau, const double *x0, double *x, doub
         } else {
             memcpy(Z, z, sizeof(double) * n);
         }
-        /* Phi_{i,j} = Q_j^T Z_{i+1}, beta_{i,j} = Delta_j^+ Phi_{i,j}, j = 0..i
-         * P_{i+1} = Z_{i+1} - sum_j P_j beta_{i,j} */
+        /* full reorthogonalisation: remove from the candidates their S-projection onto every
+         * earlier block, so that the new block is S-conjugate to all of them; the coefficients
+         * solve each earlier block's Gram system with (S P_j)^T Z as right-hand side.  On a
+         * multidirectional step the image S of the new block follows from S Z and the same
+         * coefficients (eq. (19)); otherwise it is formed directly. */
         if (nb == cap) {
             cap *= 2;
             H = (blk_t *)realloc(H, sizeof(blk_t) * (size_t)cap);
