@@ -142,6 +142,21 @@ void ba_free_system(ba_system *sys);
  * v, y: device [n].  precision: ba_precision of the Jacobian stream used. */
 ba_status ba_schur_matvec(ba_system *sys, const double *v, double *y, int32_t precision);
 
+/* The product of ba_schur_matvec, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same result, bit for bit, with the
+ * product's partial camera rows kept in a file-scope device array of the library
+ * (32 MiB, 4,194,304 doubles, one copy per GPU, held until the process ends)
+ * instead of the system's own buffer.  The call allocates nothing and calls no
+ * allocating routine.  v, y: device [n].  The system's device must be current.
+ * Every call on one GPU shares that array, so calls that overlap in time on one GPU
+ * (other host threads, other streams) race.  Errors: INVALID_ARG (NULL, precision
+ * outside 0..2, another device current), UNSUPPORTED (precision 1 or 2 on a system
+ * built without store_fp32 / store_bf16 and not yet used at that precision: the
+ * reduced-precision copy would need an allocation), WORKSPACE (the system's partial
+ * rows, n_part * d_p doubles, exceed the array), HIP. */
+ba_status ba_schur_matvec_noalloc(ba_system *sys, const double *v, double *y, int32_t precision);
+
 /* Y[:, p] = S Z[:, p], p < N, where Z[:, p] equals z on the poses of subset p of
  * the partition into N subsets (ba_partition) and 0 elsewhere -- the
  * multidirectional product of Sec. 3.2, "Optimized implementation", eq. (19).

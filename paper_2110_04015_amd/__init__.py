@@ -216,6 +216,15 @@ class System:
                "ba_schur_matvec")
         return y
 
+    def matvec_noalloc(self, v, out, precision="fp64"):
+        """y = S v through the allocation-free entry point (ba_schur_matvec_noalloc); out is required."""
+        torch = _torch()
+        _check(lib().ba_schur_matvec_noalloc(self.h, _dev_ptr(v, torch.float64, self.n, "v"),
+                                             _dev_ptr(out, torch.float64, self.n, "y"),
+                                             PREC[precision] if isinstance(precision, str) else int(precision)),
+               "ba_schur_matvec_noalloc")
+        return out
+
     def matmat_grouped(self, N, z, precision="fp64"):
         torch = _torch()
         Y = self._new(int(N), self.n)

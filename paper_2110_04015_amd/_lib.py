@@ -72,6 +72,7 @@ SIGNATURES = [
     ("ba_build_system", C.c_int, [C.POINTER(ProblemDesc), C.POINTER(BuildOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
     ("ba_free_system", None, [C.c_void_p]),
     ("ba_schur_matvec", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    ("ba_schur_matvec_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("ba_schur_matmat_grouped", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]),
     ("ba_precond_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ba_get_rhs", C.c_int, [C.c_void_p, C.c_void_p]),

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libba.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["api.cpp", "plan.cpp", "plan_check.cpp", "k_build.hip", "k_schur.hip", "k_vec.hip",
-           "k_learned.hip", "k_batch.hip", "k_bsr.hip", "k_lm.hip", "lm.cpp", "k_probe.hip"]
+           "k_learned.hip", "k_batch.hip", "k_bsr.hip", "k_lm.hip", "lm.cpp", "k_probe.hip",
+           "k_noalloc.hip"]
 ARCH = os.environ.get("BA_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
