@@ -737,13 +737,27 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const double srr = wave_partials(partials, 2, gridDim.x);
     const double srho = wave_partials(partials + 1, 2, gridDim.x);
+    // lane 0 forms and stores the scalars, then holds all SC_COUNT of them in registers
+    // (its own stores, and the other kernels' values it acquired above); the other lanes
+    // receive them by cross-lane broadcast, never by reading what lane 0 just stored
+    double held[SC_COUNT];
     if (t == 0) {
         mcg_scalars_store(srr, srho, k, gamma, alpha, sc, N, tau, eps);
         __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int i = 0; i < SC_COUNT; ++i) held[i] = sc[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < SC_COUNT; ++i) held[i] = 0.0;
     }
-    if (host_sc && t < SC_COUNT) {   // all the scalars, for the host's read-back
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        host_sc[t] = sc[t];
+    if (host_sc) {   // all the scalars, for the host's read-back: lane i writes scalar i
+        double mine = 0.0;
+#pragma unroll
+        for (int i = 0; i < SC_COUNT; ++i) {
+            const double b = __shfl(held[i], 0, 64);
+            if (t == i) mine = b;
+        }
+        if (t < SC_COUNT) host_sc[t] = mine;
         __threadfence_system();   // the values reach the host before the tag
         if (t == 0) host_sc[SC_COUNT] = tag;
     }
