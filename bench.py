@@ -109,6 +109,82 @@ def run_batch(probs, seed, log):
     return out
 
 
+def run_dense(seed, log):
+    """The dense-Schur workload: cap571, shaped like Table 1's Alamo row (571 poses, about
+    0.9M projections, block density near 0.8), with that row's N = 47 and tau = 10.  FP64
+    PCG and MCG, and MCG with FP32 products or BF16-stored Jacobians under FP64
+    refinement, each timed to a 1e-6 relative residual.  Errors are against the GPU's
+    own FP64 PCG solution at 1e-12 (whose parity with the oracle the tests establish),
+    in the energy norm |x - x*|_S / |x*|_S and in the 2-norm."""
+    import numpy as np
+    import torch
+    import paper_2110_04015_amd as ba
+    import synth
+    N, tau = 47, 10.0
+    p = synth.config2(seed=seed)
+    t = time.time()
+    g = ba.System.from_problem(p, store_fp32=True, store_bf16=True)
+    torch.cuda.synchronize()
+    out = {"workload": f"cap571: Alamo-shaped dense-Schur synthetic BA ({p.n_cams} cameras, {p.n_lms} landmarks, "
+                       f"{p.n_obs} observations, Schur block density {synth.schur_block_density(p):.3f}), seed {seed}",
+           "N": N, "tau": tau, "build_s": round(time.time() - t, 3)}
+    t = time.time()
+    for prec in ("fp64", "fp32", "bf16"):
+        g.prepare_mcg(N, prec)
+    torch.cuda.synchronize()
+    out["mcg_plan_s"] = round(time.time() - t, 3)
+    xs, s0 = g.pcg(eps=1e-12, max_iter=5000)
+    xs_S = float(torch.dot(xs, g.matvec(xs)))
+
+    def errors(x):
+        e = x - xs
+        return (float(np.sqrt(max(float(torch.dot(e, g.matvec(e))), 0.0) / xs_S)),
+                float(torch.linalg.norm(e) / torch.linalg.norm(xs)))
+
+    legs = [("pcg_fp64", lambda: g.pcg(eps=1e-6, max_iter=1000)),
+            ("mcg_fp64", lambda: g.mcg(N, tau, eps=1e-6, max_iter=1000)),
+            ("mcg_fp32_refined", lambda: g.mcg(N, tau, eps=1e-6, max_iter=1000, precision="fp32")),
+            ("mcg_bf16_refined", lambda: g.mcg(N, tau, eps=1e-6, max_iter=1000, precision="bf16"))]
+    for name, f in legs:
+        f()
+        ts = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, st = f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        dt = float(np.median(ts))
+        ee, e2 = errors(x)
+        out[name] = {"solves_per_s": round(1.0 / dt, 2), "ms": round(dt * 1e3, 3), "iterations": st.iterations,
+                     "multi_steps": st.multi_steps, "refinement_steps": st.refinement_steps,
+                     "rel_res_true": st.rel_res_true, "status": st.status, "energy_err": ee, "rel_err": e2}
+        log(f"dense {name}: {out[name]}")
+    # S v: the FP64 chunk kernel (event-timed) over the algorithmic bytes of one product;
+    # the 182 MB stream fits in the 256 MB Infinity Cache, so this is not an HBM figure
+    v = torch.randn(g.n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(v)
+    info = g.info()
+    for prec in ("fp64", "fp32", "bf16"):
+        g.matvec(v, precision=prec, out=y)
+        g.profile(True)
+        g.profile_read(reset=True)
+        for _ in range(50):
+            g.matvec(v, precision=prec, out=y)
+        kms, nl = g.profile_read(reset=True)
+        g.profile(False)
+        esz = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+        by = p.n_obs * (24 * esz + 4) + p.n_lms * 6 * 8 + g.n * 8
+        ms = kms / max(nl, 1)
+        out[f"matvec_{prec}"] = {"bytes": int(by), "chunk_kernel_ms": round(ms, 5),
+                                 "gbs": round(by / (ms * 1e-3) / 1e9, 1), "cache_resident": by < 256e6}
+    out["matvec_fp64"]["bytes_reported_by_library"] = info["matvec_bytes_fp64"]
+    out["ratio_mcg_fp64_vs_pcg_fp64"] = round(out["mcg_fp64"]["ms"] / out["pcg_fp64"]["ms"], 4)
+    log(f"dense matvec: {out['matvec_fp64']}")
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,8 +199,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched-serving workload")
     ap.add_argument("--no-lm", action="store_true", help="skip the LM outer-loop runs")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-Schur (cap571) workload")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="K",
-                    help="profiling mode: K FP64 S v products and one 1 GiB copy (counter calibration)")
+                    help="profiling mode: K S v products (at --precision) and one 1 GiB copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1",
@@ -155,7 +232,8 @@ def main():
     log(f"generated {p.name}: {p.n_cams} cameras, {p.n_lms} landmarks, {p.n_obs} observations "
         f"in {time.time() - t:.1f} s")
     t = time.time()
-    g = ba.System.from_problem(p)
+    g = ba.System.from_problem(p, store_fp32=args.matvec_only > 0 and args.precision == "fp32",
+                               store_bf16=args.matvec_only > 0 and args.precision == "bf16")
     torch.cuda.synchronize()
     build_s = time.time() - t
     info = g.info()
@@ -167,7 +245,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.matvec_only):
-            g.matvec(v, out=y)
+            g.matvec(v, out=y, precision=args.precision)
         torch.cuda.synchronize()
         t_mv = (time.perf_counter() - t1) / args.matvec_only
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -177,11 +255,21 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         t_cp = time.perf_counter() - t1
-        print(json.dumps({"mode": "matvec-only", "matvecs": args.matvec_only, "ms_per_matvec": 1e3 * t_mv,
+        print(json.dumps({"mode": "matvec-only", "precision": args.precision, "matvecs": args.matvec_only,
+                          "ms_per_matvec": 1e3 * t_mv,
                           "copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
                           "copy_ms": 1e3 * t_cp, "info": info}), flush=True)
         g.close()
         return
+
+    # MCG's partition and multidirectional-product plan (host, once per N): timed apart
+    plan_s = None
+    if args.solver == "mcg":
+        t = time.time()
+        g.prepare_mcg(args.N, args.precision)
+        torch.cuda.synchronize()
+        plan_s = time.time() - t
+        log(f"MCG plan for N = {args.N} in {plan_s:.3f} s")
 
     def step(precision=args.precision, solver=args.solver, N=args.N, tau=args.tau):
         if solver == "pcg":
@@ -343,6 +431,10 @@ def main():
                                        "solve": round(lm[a]["t_solve_ms"] / lm[b]["t_solve_ms"], 4)}
         del sc, cams0, X0
 
+    dense = None
+    if not args.no_dense and not args.no_variants:
+        dense = run_dense(args.seed, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -395,7 +487,8 @@ def main():
                    "solver": args.solver, "N": args.N if args.solver == "mcg" else None,
                    "tau": args.tau if args.solver == "mcg" else None, "eps": 1e-6,
                    "iterations": st.iterations, "multi_steps": st.multi_steps,
-                   "rel_res_true": st.rel_res_true, "build_s": round(build_s, 3)},
+                   "rel_res_true": st.rel_res_true, "build_s": round(build_s, 3),
+                   "mcg_plan_s": None if plan_s is None else round(plan_s, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
@@ -403,6 +496,7 @@ def main():
         "extrinsics_only": extrinsics,
         "batch": batch,
         "lm": lm,
+        "dense_schur": dense,
     }
     print(json.dumps(out), flush=True)
     if batch is None:

@@ -188,6 +188,16 @@ ba_status ba_pcg_solve(ba_system *sys, const double *x0, double *x, const ba_sol
 ba_status ba_mcg_solve(ba_system *sys, int32_t n_groups, double tau, const double *x0, double *x,
                        const ba_solve_opts *opts, ba_solve_stats *stats);
 
+/* Lays out, ahead of the solves, what ba_mcg_solve with N subsets and the given
+ * precision needs beyond the build: the partition of the poses (Sec. 3.2,
+ * "Optimized implementation"), the layout of the multidirectional product eq. (19)
+ * (planned on the host from the observation indices, once per N; an explicit-S
+ * system needs the partition only) and the reduced-precision Jacobian copy.  The
+ * first ba_mcg_solve with these arguments does the same when it was not called.
+ * Errors: INVALID_ARG (N outside [1, n_cams], precision outside 0..2), UNSUPPORTED,
+ * NOMEM, HIP. */
+ba_status ba_prepare_mcg(ba_system *sys, int32_t n_groups, int32_t precision);
+
 /* Landmark update from a pose update, the second block row of eq. (7):
  * dx_l = -V_lambda^-1 (b_l + W^T dx_p).  (eq. (16) is printed with the sign of
  * b_l flipped.)  dxp: device [n]; dxl: device [n_lms][3], original landmark order. */

@@ -262,6 +262,11 @@ class System:
                                       _dev_ptr(J_l, torch.float64, m * 6, "J_l"),
                                       _dev_ptr(r, torch.float64, m * 2, "r"), float(lam)), "ba_update_system")
 
+    def prepare_mcg(self, N, precision="fp64"):
+        """Lay out MCG's partition, multidirectional-product plan and precision copy (ba_prepare_mcg)."""
+        _check(lib().ba_prepare_mcg(self.h, int(N), PREC[precision] if isinstance(precision, str) else int(precision)),
+               "ba_prepare_mcg")
+
     def set_lambda(self, lam):
         """A new damping lambda for the same linearisation (ba_set_lambda), J is not read again."""
         _check(lib().ba_set_lambda(self.h, float(lam)), "ba_set_lambda")

@@ -81,6 +81,7 @@ SIGNATURES = [
     ("ba_mcg_solve", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts),
                                C.POINTER(SolveStats)]),
     ("ba_back_substitute", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ba_prepare_mcg", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     ("ba_pinv_sym", C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     ("ba_partition", C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     ("ba_system_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64),

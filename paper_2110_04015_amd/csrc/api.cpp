@@ -852,6 +852,15 @@ ba_status ba_get_precond_blocks(ba_system *s, double *D) {
     return BA_OK;
 }
 
+ba_status ba_prepare_mcg(ba_system *s, int32_t N, int32_t precision) {
+    if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
+    if (N < 1 || N > s->np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, n_cams]");
+    const ba_status st = prepare_mcg(s, N, precision);
+    if (st != BA_OK) return st;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return BA_OK;
+}
+
 ba_status ba_back_substitute(ba_system *s, const double *dxp, double *dxl) {
     if (!s || !dxp || !dxl) return fail(BA_ERR_INVALID_ARG, "NULL argument");
     const HostPlan &P = s->plan;
