@@ -1529,6 +1529,22 @@ struct ba_batch {
     int32_t *blk_off = nullptr, *blk_k = nullptr;
     int64_t *blk_dp = nullptr;
     double *btp = nullptr, *d = nullptr, *tmp = nullptr, *xprev = nullptr;
+    int32_t *mask = nullptr;        // [B] problems a restart or refinement step applies to
+    int32_t *mask_skip = nullptr;   // [B] 1 - mask: the S products of such a step skip the others
+    int32_t *max_it = nullptr;      // [B] iterations each problem's next inner solve may take
+    // the window of iterations captured once and replayed; its kernels read every bound they
+    // need from the device, so the graph only depends on the arguments in the key
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        const double *x = nullptr;
+        int precision = -1, window = 0, N = 0;
+        double tau = 0.0, eps = 0.0;
+        int64_t cap = 0;
+        bool operator==(const GraphKey &o) const {
+            return x == o.x && precision == o.precision && window == o.window && N == o.N && tau == o.tau &&
+                   eps == o.eps && cap == o.cap;
+        }
+    } gkey;
     int32_t *host_i = nullptr;      // pinned
     double *host_d = nullptr;       // pinned [2B]
     // graph windows are captured on a stream of the batch (the caller's stream may be
@@ -1568,6 +1584,12 @@ void free_batch_ws(ba_batch *b) {
     dfree(b->d);
     dfree(b->tmp);
     dfree(b->xprev);
+    dfree(b->mask);
+    dfree(b->mask_skip);
+    dfree(b->max_it);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    b->gexec = nullptr;
+    b->gkey = ba_batch::GraphKey();
     b->N = 0;
     b->cap = 0;
 }
@@ -1617,6 +1639,9 @@ ba_status ensure_batch_ws(ba_batch *b, int N, int64_t cap) {
     if ((st = dalloc(&b->blk_off, (size_t)cb)) != BA_OK) return st;
     if ((st = dalloc(&b->blk_k, (size_t)cb)) != BA_OK) return st;
     if ((st = dalloc(&b->blk_dp, (size_t)cb)) != BA_OK) return st;
+    if ((st = dalloc(&b->mask, (size_t)B)) != BA_OK) return st;
+    if ((st = dalloc(&b->mask_skip, (size_t)B)) != BA_OK) return st;
+    if ((st = dalloc(&b->max_it, (size_t)B)) != BA_OK) return st;
     HIPCHK(hipStreamSynchronize(q));   // hp goes out of scope
     b->N = N;
     b->cap = cap;
@@ -1658,82 +1683,98 @@ BatchLaunch batch_launch(ba_batch *b, double *x) {
     return L;
 }
 
-// one iteration of Algorithm 2 for every running problem (it = iterations done so far)
-void batch_iteration(ba_batch *b, const BatchLaunch &L, const SchurArgs &sa, const MultiArgs &ma, double tau,
-                     double eps, int max_iter, int it, hipStream_t q) {
-    launch_biter_head(L, tau, eps, max_iter, q);
+// one iteration of Algorithm 2 for every running problem: the same launches whatever the
+// iteration, the per-problem widths and bounds are read on the device
+void batch_iteration(const BatchLaunch &L, const SchurArgs &sa, const MultiArgs &ma, double tau, double eps,
+                     hipStream_t q) {
+    launch_biter_head(L, tau, eps, q);
     if (L.N > 1) launch_schur_multi(ma, L.z, L.Y, q);
-    const int64_t hmax = std::min<int64_t>(b->cap, 1 + (int64_t)it * L.N);
-    launch_biter_tail(L, (int)hmax, it + 1, q);
+    launch_biter_tail(L, q);
     launch_schur_matvec(sa, L.pstage, L.qstage, q);
     launch_bqcopy_advance(L, q);
 }
 
-// Algorithm 2 on S x = -bt for every problem with off[b] == 0 (x of the others is set
-// to zero); at most max_iter iterations; window > 0 captures window iterations per graph.
-// Per-problem stop times (ms from t0) go to done_ms when it is given.
-ba_status batch_core(ba_batch *b, int precision, const double *bt, double *x, const int32_t *off, double tau,
-                     double eps, int max_iter, int window, std::chrono::steady_clock::time_point t0,
-                     std::vector<double> *done_ms) {
+struct BatchRun {
+    BatchLaunch L;
+    SchurArgs sa;     // one-column product, skipping problems by their flags
+    MultiArgs ma;
+};
+
+BatchRun batch_run(ba_batch *b, int precision, double *x) {
     ba_system *s = b->sys;
-    hipStream_t q = s->stream;
-    BatchLaunch L = batch_launch(b, x);
-    SchurArgs sa = schur_args(s, precision);
-    sa.chunk_seg = s->seg_chunk;
-    sa.cam_seg = s->seg_cam;
-    sa.seg_skip = b->skip_single;
-    MultiArgs ma = b->N > 1 ? multi_args(s, precision) : MultiArgs();
+    BatchRun R;
+    R.L = batch_launch(b, x);
+    R.sa = schur_args(s, precision);
+    R.sa.chunk_seg = s->seg_chunk;
+    R.sa.cam_seg = s->seg_cam;
+    R.sa.seg_skip = b->skip_single;
+    R.ma = b->N > 1 ? multi_args(s, precision) : MultiArgs();
     if (b->N > 1) {
-        ma.chunk_seg = s->multi.chunk_seg;
-        ma.cam_seg = s->seg_cam;
-        ma.seg_skip = b->skip_multi;
+        R.ma.chunk_seg = s->multi.chunk_seg;
+        R.ma.cam_seg = s->seg_cam;
+        R.ma.seg_skip = b->skip_multi;
     }
-    launch_bstart(L, bt, nullptr, off, q);
-    launch_schur_matvec(sa, L.pstage, L.qstage, q);   // Q_0 = S P_0
-    launch_bqcopy_advance(L, q);
+    return R;
+}
+
+// (Re)starts Algorithm 2 on S x = -bt: every problem not flagged in `off` (only == NULL),
+// or just the problems flagged in `only`, whose state is reset; each may take max_it[b]
+// iterations (max_iter when max_it is NULL).  P_0 = D^-1 r_0 and Q_0 = S P_0.
+ba_status batch_start(ba_batch *b, const BatchRun &R, const double *bt, const int32_t *off, const int32_t *only,
+                      const int32_t *only_skip, int max_iter, const int32_t *max_it) {
+    hipStream_t q = b->sys->stream;
+    launch_bstart(R.L, bt, nullptr, off, q, only, max_iter, max_it);
+    SchurArgs s0 = R.sa;
+    if (only) s0.seg_skip = only_skip;   // the problems that keep running are left alone
+    launch_schur_matvec(s0, R.L.pstage, R.L.qstage, q);
+    launch_bqcopy_advance(R.L, q, only);
     HIPCHK(hipGetLastError());
-    const int B = b->B;
-    std::vector<int32_t> was_done((size_t)B, 0);
-    const int W = window > 0 ? window : 8;
-    for (int it = 0; it < max_iter;) {
-        const int w = std::min(W, max_iter - it);
-        if (window > 0) {
-            hipStream_t gs = b->gstream;
-            hipGraph_t g = nullptr;
-            hipGraphExec_t ge = nullptr;
-            HIPCHK(hipEventRecord(b->ev_in, q));
-            HIPCHK(hipStreamWaitEvent(gs, b->ev_in, 0));
-            HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < w; ++k) batch_iteration(b, L, sa, ma, tau, eps, max_iter, it + k, gs);
-            hipError_t e = hipStreamEndCapture(gs, &g);
-            if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            if (e == hipSuccess) e = hipGraphLaunch(ge, gs);
-            if (ge) (void)hipGraphExecDestroy(ge);
-            if (g) (void)hipGraphDestroy(g);
-            if (e != hipSuccess) return fail(BA_ERR_HIP, std::string("batch graph: ") + hipGetErrorString(e));
-            HIPCHK(hipEventRecord(b->ev_out, gs));
-            HIPCHK(hipStreamWaitEvent(q, b->ev_out, 0));
-        } else {
-            for (int k = 0; k < w; ++k) batch_iteration(b, L, sa, ma, tau, eps, max_iter, it + k, q);
-        }
-        it += w;
-        HIPCHK(hipGetLastError());
-        // stop flags of every problem (one read-back per window)
-        std::vector<BatchDyn> hd((size_t)B);
-        HIPCHK(hipMemcpyAsync(hd.data(), b->dyn, sizeof(BatchDyn) * (size_t)B, hipMemcpyDeviceToHost, q));
-        HIPCHK(hipStreamSynchronize(q));
-        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        int running = 0;
-        for (int i = 0; i < B; ++i) {
-            if (hd[(size_t)i].done && !was_done[(size_t)i]) {
-                was_done[(size_t)i] = 1;
-                if (done_ms) (*done_ms)[(size_t)i] = ms;
-            }
-            running += !hd[(size_t)i].done;
-        }
-        if (running == 0) break;
-    }
     return BA_OK;
+}
+
+// `window` iterations for every running problem: replays of one captured graph (window >
+// 0; captured on the batch's stream on first use for these arguments) or eager launches
+ba_status batch_window(ba_batch *b, const BatchRun &R, int precision, double tau, double eps, int window) {
+    hipStream_t q = b->sys->stream;
+    if (window <= 0) {
+        for (int k = 0; k < 8; ++k) batch_iteration(R.L, R.sa, R.ma, tau, eps, q);
+        HIPCHK(hipGetLastError());
+        return BA_OK;
+    }
+    ba_batch::GraphKey key;
+    key.x = R.L.x;
+    key.precision = precision;
+    key.window = window;
+    key.N = b->N;
+    key.tau = tau;
+    key.eps = eps;
+    key.cap = b->cap;
+    hipStream_t gs = b->gstream;
+    if (!b->gexec || !(b->gkey == key)) {
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < window; ++k) batch_iteration(R.L, R.sa, R.ma, tau, eps, gs);
+        hipError_t e = hipStreamEndCapture(gs, &g);
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->gexec = nullptr;
+            return fail(BA_ERR_HIP, std::string("batch graph: ") + hipGetErrorString(e));
+        }
+        b->gkey = key;
+    }
+    HIPCHK(hipEventRecord(b->ev_in, q));
+    HIPCHK(hipStreamWaitEvent(gs, b->ev_in, 0));
+    HIPCHK(hipGraphLaunch(b->gexec, gs));
+    HIPCHK(hipEventRecord(b->ev_out, gs));
+    HIPCHK(hipStreamWaitEvent(q, b->ev_out, 0));
+    return BA_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 ba_status batch_stats_from_device(ba_batch *b, std::vector<BatchDyn> &hd) {
@@ -1743,21 +1784,42 @@ ba_status batch_stats_from_device(ba_batch *b, std::vector<BatchDyn> &hd) {
     return BA_OK;
 }
 
-// per-problem true relative residual |bt + S x| / |bt| in FP64; btp = bt + S x when given
-ba_status batch_true_residual(ba_batch *b, const double *x, double *btp, std::vector<double> &rel) {
+// per-problem true relative residual |bt + S x| / |bt| in FP64; btp = bt + S x when given.
+// With `only` (device mask, and only_skip its complement), just the flagged problems:
+// the FP64 product skips the others and rel keeps their entries.
+ba_status batch_true_residual(ba_batch *b, const double *x, double *btp, std::vector<double> &rel,
+                              const int32_t *only = nullptr, const int32_t *only_skip = nullptr,
+                              const std::vector<int32_t> *only_h = nullptr) {
     ba_system *s = b->sys;
     hipStream_t q = s->stream;
     BatchLaunch L = batch_launch(b, nullptr);
-    launch_schur_matvec(schur_args(s, 0), x, b->tmp, q);
-    launch_bresidual(L, s->bt, b->tmp, btp, b->resid, q);
+    SchurArgs a = schur_args(s, 0);
+    if (only) {
+        a.chunk_seg = s->seg_chunk;
+        a.cam_seg = s->seg_cam;
+        a.seg_skip = only_skip;
+    }
+    launch_schur_matvec(a, x, b->tmp, q);
+    launch_bresidual(L, s->bt, b->tmp, btp, b->resid, q, only);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(b->host_d, b->resid, sizeof(double) * 2 * (size_t)b->B, hipMemcpyDeviceToHost, q));
     HIPCHK(hipStreamSynchronize(q));
-    rel.resize((size_t)b->B);
+    rel.resize((size_t)b->B, 0.0);
     for (int i = 0; i < b->B; ++i) {
+        if (only_h && !(*only_h)[(size_t)i]) continue;
         const double a0 = b->host_d[2 * i], a1 = b->host_d[2 * i + 1];
         rel[(size_t)i] = a1 > 0.0 ? std::sqrt(a0 / a1) : 0.0;
     }
+    return BA_OK;
+}
+
+// Uploads a per-problem mask and its complement (the S products' skip flags).
+ba_status batch_set_mask(ba_batch *b, const std::vector<int32_t> &m, std::vector<int32_t> &skip_h) {
+    hipStream_t q = b->sys->stream;
+    skip_h.resize(m.size());
+    for (size_t i = 0; i < m.size(); ++i) skip_h[i] = m[i] ? 0 : 1;
+    HIPCHK(hipMemcpyAsync(b->mask, m.data(), sizeof(int32_t) * m.size(), hipMemcpyHostToDevice, q));
+    HIPCHK(hipMemcpyAsync(b->mask_skip, skip_h.data(), sizeof(int32_t) * m.size(), hipMemcpyHostToDevice, q));
     return BA_OK;
 }
 
@@ -1855,68 +1917,157 @@ ba_status ba_batch_mcg_solve(ba_batch *b, int32_t N, double tau, double *x, cons
     const int64_t cap = opts.max_history_cols > 0 ? opts.max_history_cols : 1 + (int64_t)inner_max * N;
     if ((st = ensure_batch_ws(b, N, cap)) != BA_OK) return st;
     const int B = b->B;
-    std::vector<double> done_ms((size_t)B, 0.0), rel;
+    std::vector<double> done_ms((size_t)B, 0.0), rel((size_t)B, 0.0);
     std::vector<int32_t> iters((size_t)B, 0), multis((size_t)B, 0), outer((size_t)B, 0), status((size_t)B, BA_MAXITER);
-    std::vector<BatchDyn> hd;
+    std::vector<int32_t> hcols((size_t)B, 0);
+    std::vector<double> rrel((size_t)B, 0.0);
+    std::vector<BatchDyn> hd((size_t)B);
+    const int W = graph_window > 0 ? graph_window : 8;   // iterations between reads of the stop flags
     auto t0 = std::chrono::steady_clock::now();
+    auto read_dyn = [&]() -> ba_status {
+        HIPCHK(hipMemcpyAsync(hd.data(), b->dyn, sizeof(BatchDyn) * (size_t)B, hipMemcpyDeviceToHost, q));
+        HIPCHK(hipStreamSynchronize(q));
+        return BA_OK;
+    };
+    auto note_inner = [&](int i) {
+        const BatchDyn &d = hd[(size_t)i];
+        iters[(size_t)i] += d.iters;
+        multis[(size_t)i] += d.multi_steps;
+        hcols[(size_t)i] = d.hcols;
+        rrel[(size_t)i] = d.rr0 > 0.0 ? std::sqrt(d.rr / d.rr0) : 0.0;
+    };
     if (opts.precision == 0) {
-        if ((st = batch_core(b, 0, s->bt, x, nullptr, tau, opts.eps, opts.max_iter, graph_window, t0, &done_ms)) != BA_OK)
-            return st;
-        if ((st = batch_stats_from_device(b, hd)) != BA_OK) return st;
+        // one Algorithm 2 run per problem on S x = -b~; a problem's time is the end of the
+        // window in which its stop flag was first seen
+        BatchRun R = batch_run(b, 0, x);
+        if ((st = batch_start(b, R, s->bt, nullptr, nullptr, nullptr, opts.max_iter, nullptr)) != BA_OK) return st;
+        std::vector<int32_t> seen((size_t)B, 0);
+        for (int it = 0;; it += W) {
+            if ((st = read_dyn()) != BA_OK) return st;
+            const double ms = ms_since(t0);
+            int running = 0;
+            for (int i = 0; i < B; ++i) {
+                if (hd[(size_t)i].done && !seen[(size_t)i]) {
+                    seen[(size_t)i] = 1;
+                    done_ms[(size_t)i] = ms;
+                }
+                running += !hd[(size_t)i].done;
+            }
+            if (running == 0 || it >= opts.max_iter) break;
+            if ((st = batch_window(b, R, 0, tau, opts.eps, graph_window)) != BA_OK) return st;
+        }
         for (int i = 0; i < B; ++i) {
-            iters[(size_t)i] = hd[(size_t)i].iters;
-            multis[(size_t)i] = hd[(size_t)i].multi_steps;
+            note_inner(i);
             status[(size_t)i] = hd[(size_t)i].status;
         }
         if ((st = batch_true_residual(b, x, nullptr, rel)) != BA_OK) return st;
     } else {
-        // FP64 iterative refinement around reduced-precision inner solves, per problem
+        // FP64 iterative refinement around reduced-precision inner solves, each problem on
+        // its own: when a problem's inner solve stops, its correction is added and its FP64
+        // residual formed at once (the others keep iterating); it then either retires or
+        // restarts its inner solve on the new residual
         const double ieps = opts.inner_eps > 0.0 ? opts.inner_eps : (opts.precision == BA_PREC_FP32 ? 1e-2 : 1e-1);
         HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * (size_t)s->np * 9, q));
-        std::vector<int32_t> offh((size_t)B, 0);
+        BatchRun R = batch_run(b, opts.precision, b->d);
+        // host copies of the masks: one vector per upload in flight (pageable sources)
+        std::vector<int32_t> live((size_t)B, 0), sel((size_t)B, 0), cap_h((size_t)B, inner_max);
+        std::vector<int32_t> skip_sel, skip_rev, skip_again;
         std::vector<double> prev((size_t)B, INFINITY);
-        for (int o = 0;; ++o) {
-            if ((st = batch_true_residual(b, x, b->btp, rel)) != BA_OK) return st;
-            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            int running = 0;
+        // x = 0: btp = b~, every relative residual 1 (0 for a zero right-hand side)
+        if ((st = batch_true_residual(b, x, b->btp, rel)) != BA_OK) return st;
+        int running = 0;
+        for (int i = 0; i < B; ++i) {
+            if (rel[(size_t)i] < opts.eps) {
+                status[(size_t)i] = BA_OK;
+                done_ms[(size_t)i] = ms_since(t0);
+            } else {
+                live[(size_t)i] = 1;
+                ++running;
+            }
+            prev[(size_t)i] = rel[(size_t)i];
+        }
+        auto restart = [&](const std::vector<int32_t> &m) -> ba_status {
+            ba_status r2;
+            if ((r2 = batch_set_mask(b, m, skip_again)) != BA_OK) return r2;
+            HIPCHK(hipMemcpyAsync(b->max_it, cap_h.data(), sizeof(int32_t) * (size_t)B, hipMemcpyHostToDevice, q));
+            return batch_start(b, R, b->btp, nullptr, b->mask, b->mask_skip, inner_max, b->max_it);
+        };
+        if (running > 0) {
+            // the first start resets every problem (those already at eps stay stopped)
+            std::vector<int32_t> offh((size_t)B);
+            for (int i = 0; i < B; ++i) offh[(size_t)i] = !live[(size_t)i];
+            HIPCHK(hipMemcpyAsync(b->off, offh.data(), sizeof(int32_t) * (size_t)B, hipMemcpyHostToDevice, q));
+            HIPCHK(hipMemcpyAsync(b->max_it, cap_h.data(), sizeof(int32_t) * (size_t)B, hipMemcpyHostToDevice, q));
+            if ((st = batch_start(b, R, b->btp, b->off, nullptr, nullptr, inner_max, b->max_it)) != BA_OK) return st;
+            HIPCHK(hipStreamSynchronize(q));   // offh goes out of scope
+        }
+        std::vector<int32_t> reverted((size_t)B, 0), again_h((size_t)B, 0);
+        while (running > 0) {
+            if ((st = batch_window(b, R, opts.precision, tau, ieps, graph_window)) != BA_OK) return st;
+            if ((st = read_dyn()) != BA_OK) return st;
+            // the problems whose inner solve stopped in this window
+            int nsel = 0;
             for (int i = 0; i < B; ++i) {
-                if (offh[(size_t)i]) continue;
+                sel[(size_t)i] = live[(size_t)i] && hd[(size_t)i].done;
+                if (!sel[(size_t)i]) continue;
+                note_inner(i);
+                outer[(size_t)i] += 1;
+                const int32_t ist = hd[(size_t)i].status;
+                if (ist < 0 && ist != BA_ERR_BREAKDOWN) {   // an error ends this problem, x unchanged
+                    status[(size_t)i] = ist;
+                    live[(size_t)i] = 0;
+                    sel[(size_t)i] = 0;
+                    done_ms[(size_t)i] = ms_since(t0);
+                    --running;
+                    continue;
+                }
+                ++nsel;
+            }
+            if (nsel == 0) continue;
+            // x += d on those problems (xprev keeps x), then their FP64 residuals
+            if ((st = batch_set_mask(b, sel, skip_sel)) != BA_OK) return st;
+            launch_bouter_step(R.L, b->mask, x, b->d, b->xprev, q);
+            if ((st = batch_true_residual(b, x, b->btp, rel, b->mask, b->mask_skip, &sel)) != BA_OK) return st;
+            const double ms = ms_since(t0);
+            int nrev = 0, nre = 0;
+            std::vector<int32_t> &again = again_h;
+            std::fill(again.begin(), again.end(), 0);
+            for (int i = 0; i < B; ++i) {
+                reverted[(size_t)i] = 0;
+                if (!sel[(size_t)i]) continue;
+                bool retire = true;
                 if (rel[(size_t)i] < opts.eps) {
                     status[(size_t)i] = BA_OK;
-                    offh[(size_t)i] = 1;
-                } else if (o > 0 && !(rel[(size_t)i] < prev[(size_t)i])) {
-                    // the last correction did not reduce this problem's FP64 residual: keep
-                    // its iterate from before the correction
-                    const size_t r0 = (size_t)b->cam0[(size_t)i] * 9, len = (size_t)b->np[(size_t)i] * 9;
-                    HIPCHK(hipMemcpyAsync(x + r0, b->xprev + r0, len * sizeof(double), hipMemcpyDeviceToDevice, q));
+                } else if (!(rel[(size_t)i] < prev[(size_t)i])) {
+                    // the correction did not reduce this problem's FP64 residual: keep its
+                    // iterate from before it
+                    reverted[(size_t)i] = 1;
+                    ++nrev;
                     rel[(size_t)i] = prev[(size_t)i];
                     status[(size_t)i] = BA_MAXITER;
-                    offh[(size_t)i] = 1;
-                } else if (o >= opts.max_outer || iters[(size_t)i] >= opts.max_iter) {
+                } else if (outer[(size_t)i] >= opts.max_outer || iters[(size_t)i] >= opts.max_iter) {
                     status[(size_t)i] = BA_MAXITER;
-                    offh[(size_t)i] = 1;
+                } else {
+                    retire = false;
+                    again[(size_t)i] = 1;
+                    ++nre;
+                    // the inner solve may take what is left of the problem's budget
+                    cap_h[(size_t)i] = std::min(inner_max, opts.max_iter - iters[(size_t)i]);
                 }
-                if (offh[(size_t)i]) done_ms[(size_t)i] = ms;
                 prev[(size_t)i] = rel[(size_t)i];
-                running += !offh[(size_t)i];
+                if (retire) {
+                    live[(size_t)i] = 0;
+                    done_ms[(size_t)i] = ms;
+                    --running;
+                }
             }
-            if (running == 0) break;
-            HIPCHK(hipMemcpyAsync(b->off, offh.data(), sizeof(int32_t) * (size_t)B, hipMemcpyHostToDevice, q));
-            if ((st = batch_core(b, opts.precision, b->btp, b->d, b->off, tau, ieps, inner_max, graph_window, t0,
-                                 nullptr)) != BA_OK)
-                return st;
-            HIPCHK(hipMemcpyAsync(b->xprev, x, sizeof(double) * (size_t)s->np * 9, hipMemcpyDeviceToDevice, q));
-            launch_axpy((int64_t)s->np * 9, 1.0, b->d, x, q);
-            HIPCHK(hipGetLastError());
-            if ((st = batch_stats_from_device(b, hd)) != BA_OK) return st;
-            for (int i = 0; i < B; ++i) {
-                if (offh[(size_t)i]) continue;
-                iters[(size_t)i] += hd[(size_t)i].iters;
-                multis[(size_t)i] += hd[(size_t)i].multi_steps;
-                outer[(size_t)i] += 1;
-                if (hd[(size_t)i].status < 0 && hd[(size_t)i].status != BA_ERR_BREAKDOWN) status[(size_t)i] = hd[(size_t)i].status;
+            if (nrev > 0) {
+                if ((st = batch_set_mask(b, reverted, skip_rev)) != BA_OK) return st;
+                launch_brevert(R.L, b->mask, x, b->xprev, q);
+                HIPCHK(hipGetLastError());
             }
-            (void)hipStreamSynchronize(q);   // offh is rewritten next pass
+            if (nre > 0 && (st = restart(again)) != BA_OK) return st;
+            HIPCHK(hipStreamSynchronize(q));   // the host masks are rewritten next window
         }
     }
     HIPCHK(hipStreamSynchronize(q));
@@ -1928,11 +2079,11 @@ ba_status ba_batch_mcg_solve(ba_batch *b, int32_t N, double tau, double *x, cons
             ba_batch_stats &o = stats[i];
             o.iterations = iters[(size_t)i];
             o.multi_steps = multis[(size_t)i];
-            o.history_cols = hd.empty() ? 0 : hd[(size_t)i].hcols;
+            o.history_cols = hcols[(size_t)i];
             o.refinement_steps = outer[(size_t)i];
             o.status = status[(size_t)i];
             o.reserved = 0;
-            o.rel_res_recursive = hd.empty() || hd[(size_t)i].rr0 <= 0.0 ? 0.0 : std::sqrt(hd[(size_t)i].rr / hd[(size_t)i].rr0);
+            o.rel_res_recursive = rrel[(size_t)i];
             o.rel_res_true = rel[(size_t)i];
             o.done_ms = done_ms[(size_t)i] > 0.0 ? done_ms[(size_t)i] : ms;
         }

@@ -23,9 +23,11 @@ __device__ __forceinline__ int subset_of(int cam_local, int gs, int N) { return 
 // rr0 partials: sum of r^2 over the rows of problem b (r = -bt)
 __global__ __launch_bounds__(kNT) void k_bstart_rows(const BatchProb *__restrict__ prob, const double *__restrict__ bt,
                                                      const double *__restrict__ x0, double *__restrict__ x,
-                                                     double *__restrict__ r, double *__restrict__ part) {
+                                                     double *__restrict__ r, double *__restrict__ part,
+                                                     const int32_t *__restrict__ only) {
     __shared__ double sh[kNT];
     const int b = blockIdx.y;
+    if (only && !only[b]) return;
     const BatchProb P = prob[b];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * kNT) {
@@ -39,12 +41,16 @@ __global__ __launch_bounds__(kNT) void k_bstart_rows(const BatchProb *__restrict
     if (threadIdx.x == 0) part[(int64_t)b * kBUX + blockIdx.x] = acc;
 }
 
-// resets the per-problem state; problems flagged in `off` start (and stay) stopped
+// resets the per-problem state; problems flagged in `off` start (and stay) stopped.  With
+// `only`, just the flagged problems are (re)started and the others keep their state.  A
+// problem may take max_it[b] iterations (max_iter when max_it is NULL).
 __global__ void k_bstart(int B, const double *__restrict__ part, const int32_t *__restrict__ off,
                          BatchDyn *__restrict__ dyn, int32_t *__restrict__ skip_single,
-                         int32_t *__restrict__ skip_multi) {
+                         int32_t *__restrict__ skip_multi, const int32_t *__restrict__ only, int max_iter,
+                         const int32_t *__restrict__ max_it) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
+    if (only && !only[b]) return;
     double rr = 0.0;
     for (int u = 0; u < kBUX; ++u) rr += part[(int64_t)b * kBUX + u];
     BatchDyn d{};
@@ -52,6 +58,7 @@ __global__ void k_bstart(int B, const double *__restrict__ part, const int32_t *
     d.rr = rr;
     d.kn = 1;
     d.status = BA_MAXITER;
+    d.max_it = max_it ? max_it[b] : max_iter;
     d.done = (off && off[b]) ? 1 : 0;
     if (!d.done && rr == 0.0) {
         d.done = 1;
@@ -66,9 +73,9 @@ __global__ void k_bstart(int B, const double *__restrict__ part, const int32_t *
 // staging vector for Q_0 = S P_0
 __global__ void k_bseed(int B, const BatchProb *__restrict__ prob, const BatchDyn *__restrict__ dyn,
                         const double *__restrict__ Dchol, const double *__restrict__ r, double *__restrict__ Ph,
-                        double *__restrict__ pstage) {
+                        double *__restrict__ pstage, const int32_t *__restrict__ only) {
     const int b = blockIdx.y;
-    if (dyn[b].done) return;
+    if (dyn[b].done || (only && !only[b])) return;
     const BatchProb P = prob[b];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= P.np) return;
@@ -284,7 +291,7 @@ __global__ __launch_bounds__(kNT) void k_bupdate(const BatchProb *__restrict__ p
 
 // stop test, tau-test (t = gamma^T alpha / r^T D^-1 r), width of the next block, the
 // history capacity check and the per-problem launch flags of the S products
-__global__ void k_bscalars(int B, int N, double tau, double eps, int max_iter, const BatchProb *__restrict__ prob,
+__global__ void k_bscalars(int B, int N, double tau, double eps, const BatchProb *__restrict__ prob,
                            BatchDyn *__restrict__ dyn, const double *__restrict__ part,
                            const double *__restrict__ alpha, const double *__restrict__ gamma,
                            int32_t *__restrict__ skip_single, int32_t *__restrict__ skip_multi) {
@@ -323,7 +330,7 @@ __global__ void k_bscalars(int B, int N, double tau, double eps, int max_iter, c
             d.multi = 0;
         } else {
             d.multi_steps += d.multi;
-            if (d.iters >= max_iter) {
+            if (d.iters >= d.max_it) {
                 d.done = 1;
                 d.status = BA_MAXITER;
             }
@@ -340,13 +347,14 @@ __global__ __launch_bounds__(kNT) void k_bphi(int N, const BatchProb *__restrict
                                               const BatchDyn *__restrict__ dyn, const double *__restrict__ Qh,
                                               const double *__restrict__ z, double *__restrict__ Phi) {
     const int b = blockIdx.y;
-    const int col = blockIdx.x;
     const BatchDyn d = dyn[b];
-    if (d.done || col >= d.hcols) return;
+    if (d.done) return;
     const BatchProb P = prob[b];
-    const double *q = Qh + P.hbase + (int64_t)col * P.n;
     const double *zb = z + P.row0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // a fixed grid whatever the history width: block x takes columns x, x + gridDim.x, ...
+    for (int col = blockIdx.x; col < d.hcols; col += gridDim.x) {
+    const double *q = Qh + P.hbase + (int64_t)col * P.n;
     for (int p = wave; p < N; p += kNT / 64) {
         const int64_t lo = (int64_t)p * P.gs * 9;
         const int64_t hi = (p == N - 1) ? (int64_t)P.n : (int64_t)(p + 1) * P.gs * 9;
@@ -362,6 +370,7 @@ __global__ __launch_bounds__(kNT) void k_bphi(int N, const BatchProb *__restrict
         const double acc = wave_sum((a0 + a1) + (a2 + a3));
         if (lane == 0) Phi[(P.colbase + col) * N + p] = acc;
     }
+    }
 }
 
 // beta rows of history block j: beta[off_j + a][p] = sum_c Delta_j^+[a][c] Phi_(off_j + c, p);
@@ -372,10 +381,11 @@ __global__ __launch_bounds__(kNT) void k_bbeta(int N, const BatchProb *__restric
                                                const double *__restrict__ Dp, const double *__restrict__ Phi,
                                                double *__restrict__ beta) {
     const int b = blockIdx.y;
-    const int j = blockIdx.x;
     const BatchDyn d = dyn[b];
-    if (d.done || j >= d.nblk) return;
+    if (d.done) return;
     const BatchProb P = prob[b];
+    // a fixed grid whatever the number of blocks: block x takes blocks x, x + gridDim.x, ...
+    for (int j = blockIdx.x; j < d.nblk; j += gridDim.x) {
     const int off = blk_off[P.colbase + j], kj = blk_k[P.colbase + j];
     const double *D = Dp + P.colbase * N + blk_dp[P.colbase + j];
     const double *F = Phi + P.colbase * N;
@@ -398,6 +408,7 @@ __global__ __launch_bounds__(kNT) void k_bbeta(int N, const BatchProb *__restric
             }
         }
         beta[(P.colbase + off + a) * ldb + p] = s;
+    }
     }
 }
 
@@ -488,19 +499,19 @@ __global__ __launch_bounds__(64) void k_bhist(int N, int64_t ntot, const BatchPr
 
 // Q of a one-column block: copy S P_new from the staging vector into the history
 __global__ void k_bqcopy(const BatchProb *__restrict__ prob, const BatchDyn *__restrict__ dyn,
-                         const double *__restrict__ qstage, double *__restrict__ Qh) {
+                         const double *__restrict__ qstage, double *__restrict__ Qh, const int32_t *__restrict__ only) {
     const int b = blockIdx.y;
     const BatchDyn d = dyn[b];
-    if (d.done || d.multi) return;
+    if (d.done || d.multi || (only && !only[b])) return;
     const BatchProb P = prob[b];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * blockDim.x)
         Qh[P.hbase + (int64_t)d.hcols * P.n + i] = qstage[P.row0 + i];
 }
 
 // the new block becomes the current one
-__global__ void k_badvance(int B, BatchDyn *__restrict__ dyn) {
+__global__ void k_badvance(int B, BatchDyn *__restrict__ dyn, const int32_t *__restrict__ only) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B || dyn[b].done) return;
+    if (b >= B || dyn[b].done || (only && !only[b])) return;
     BatchDyn d = dyn[b];
     d.cur_off = d.hcols;
     d.kcur = d.kn;
@@ -512,9 +523,10 @@ __global__ void k_badvance(int B, BatchDyn *__restrict__ dyn) {
 // correction equation S d = -bt - S x, in the solvers' S x = -bt form) when given
 __global__ __launch_bounds__(kNT) void k_bresid_rows(const BatchProb *__restrict__ prob, const double *__restrict__ bt,
                                                      const double *__restrict__ Sx, double *__restrict__ btp,
-                                                     double *__restrict__ part) {
+                                                     double *__restrict__ part, const int32_t *__restrict__ only) {
     __shared__ double sh[kNT];
     const int b = blockIdx.y;
+    if (only && !only[b]) return;
     const BatchProb P = prob[b];
     double a0 = 0.0, a1 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * kNT) {
@@ -532,9 +544,10 @@ __global__ __launch_bounds__(kNT) void k_bresid_rows(const BatchProb *__restrict
     }
 }
 
-__global__ void k_bresid_sum(int B, const double *__restrict__ part, double *__restrict__ out) {
+__global__ void k_bresid_sum(int B, const double *__restrict__ part, double *__restrict__ out,
+                             const int32_t *__restrict__ only) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    if (b >= B || (only && !only[b])) return;
     double a0 = 0.0, a1 = 0.0;
     for (int u = 0; u < kBUX; ++u) {
         a0 += part[((int64_t)b * kBUX + u) * 2];
@@ -544,44 +557,76 @@ __global__ void k_bresid_sum(int B, const double *__restrict__ part, double *__r
     out[2 * b + 1] = a1;
 }
 
+// FP64 refinement step of the problems flagged in `only`: xprev = x, x += d on their rows
+__global__ void k_bouter_step(const BatchProb *__restrict__ prob, const int32_t *__restrict__ only,
+                              double *__restrict__ x, const double *__restrict__ d, double *__restrict__ xprev) {
+    const int b = blockIdx.y;
+    if (!only[b]) return;
+    const BatchProb P = prob[b];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = P.row0 + i;
+        const double v = x[g];
+        xprev[g] = v;
+        x[g] = v + d[g];
+    }
+}
+
+// x = xprev on the rows of the problems flagged in `only` (a correction that did not help)
+__global__ void k_brevert(const BatchProb *__restrict__ prob, const int32_t *__restrict__ only,
+                          double *__restrict__ x, const double *__restrict__ xprev) {
+    const int b = blockIdx.y;
+    if (!only[b]) return;
+    const BatchProb P = prob[b];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += (int64_t)gridDim.x * blockDim.x)
+        x[P.row0 + i] = xprev[P.row0 + i];
+}
+
 // ---------------------------------------------------------------- launchers
 
+void launch_bouter_step(const BatchLaunch &L, const int32_t *only, double *x, const double *d, double *xprev,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_bouter_step, dim3(kBUX, L.B), dim3(256), 0, s, L.prob, only, x, d, xprev);
+}
+
+void launch_brevert(const BatchLaunch &L, const int32_t *only, double *x, const double *xprev, hipStream_t s) {
+    hipLaunchKernelGGL(k_brevert, dim3(kBUX, L.B), dim3(256), 0, s, L.prob, only, x, xprev);
+}
+
 void launch_bresidual(const BatchLaunch &L, const double *bt, const double *Sx, double *btp, double *out,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(k_bresid_rows, dim3(kBUX, L.B), dim3(kNT), 0, s, L.prob, bt, Sx, btp, L.upart);
-    hipLaunchKernelGGL(k_bresid_sum, dim3((L.B + 63) / 64), dim3(64), 0, s, L.B, L.upart, out);
+                      hipStream_t s, const int32_t *only) {
+    hipLaunchKernelGGL(k_bresid_rows, dim3(kBUX, L.B), dim3(kNT), 0, s, L.prob, bt, Sx, btp, L.upart, only);
+    hipLaunchKernelGGL(k_bresid_sum, dim3((L.B + 63) / 64), dim3(64), 0, s, L.B, L.upart, out, only);
 }
 
-void launch_bstart(const BatchLaunch &L, const double *bt, const double *x0, const int32_t *off, hipStream_t s) {
-    hipLaunchKernelGGL(k_bstart_rows, dim3(kBUX, L.B), dim3(kNT), 0, s, L.prob, bt, x0, L.x, L.r, L.upart);
+void launch_bstart(const BatchLaunch &L, const double *bt, const double *x0, const int32_t *off, hipStream_t s,
+                   const int32_t *only, int max_iter, const int32_t *max_it) {
+    hipLaunchKernelGGL(k_bstart_rows, dim3(kBUX, L.B), dim3(kNT), 0, s, L.prob, bt, x0, L.x, L.r, L.upart, only);
     hipLaunchKernelGGL(k_bstart, dim3((L.B + 63) / 64), dim3(64), 0, s, L.B, L.upart, off, L.dyn, L.skip_single,
-                       L.skip_multi);
+                       L.skip_multi, only, max_iter, max_it);
     hipLaunchKernelGGL(k_bseed, dim3((L.max_np + 127) / 128, L.B), dim3(128), 0, s, L.B, L.prob, L.dyn, L.Dchol, L.r,
-                       L.Ph, L.pstage);
+                       L.Ph, L.pstage, only);
 }
 
-void launch_bqcopy_advance(const BatchLaunch &L, hipStream_t s) {
+void launch_bqcopy_advance(const BatchLaunch &L, hipStream_t s, const int32_t *only) {
     hipLaunchKernelGGL(k_bqcopy, dim3((unsigned)((L.max_n + 255) / 256), L.B), dim3(256), 0, s, L.prob, L.dyn,
-                       L.qstage, L.Qh);
-    hipLaunchKernelGGL(k_badvance, dim3((L.B + 63) / 64), dim3(64), 0, s, L.B, L.dyn);
+                       L.qstage, L.Qh, only);
+    hipLaunchKernelGGL(k_badvance, dim3((L.B + 63) / 64), dim3(64), 0, s, L.B, L.dyn, only);
 }
 
-void launch_biter_head(const BatchLaunch &L, double tau, double eps, int max_iter, hipStream_t s) {
+void launch_biter_head(const BatchLaunch &L, double tau, double eps, hipStream_t s) {
     hipLaunchKernelGGL(k_bgram, dim3(kBGX, L.B), dim3(kNT), 0, s, L.N, L.prob, L.dyn, L.Ph, L.Qh, L.r, L.gpart);
     hipLaunchKernelGGL(k_bpinv, dim3(L.B), dim3(kNT), 0, s, L.N, L.prob, L.dyn, L.gpart, L.Dp, L.blk_off, L.blk_k,
                        L.blk_dp, L.alpha, L.gamma);
     hipLaunchKernelGGL(k_bupdate, dim3(kBUX, L.B), dim3(kNT), 0, s, L.prob, L.dyn, L.Ph, L.Qh, L.alpha, L.Dchol, L.x,
                        L.r, L.z, L.upart);
-    hipLaunchKernelGGL(k_bscalars, dim3((L.B + 63) / 64), dim3(64), 0, s, L.B, L.N, tau, eps, max_iter, L.prob, L.dyn,
+    hipLaunchKernelGGL(k_bscalars, dim3((L.B + 63) / 64), dim3(64), 0, s, L.B, L.N, tau, eps, L.prob, L.dyn,
                        L.upart, L.alpha, L.gamma, L.skip_single, L.skip_multi);
 }
 
-void launch_biter_tail(const BatchLaunch &L, int hmax, int bmax, hipStream_t s) {
-    if (hmax > 0)
-        hipLaunchKernelGGL(k_bphi, dim3(hmax, L.B), dim3(kNT), 0, s, L.N, L.prob, L.dyn, L.Qh, L.z, L.Phi);
-    if (bmax > 0)
-        hipLaunchKernelGGL(k_bbeta, dim3(bmax, L.B), dim3(kNT), 0, s, L.N, L.prob, L.dyn, L.blk_off, L.blk_k, L.blk_dp,
-                           L.Dp, L.Phi, L.beta);
+void launch_biter_tail(const BatchLaunch &L, hipStream_t s) {
+    hipLaunchKernelGGL(k_bphi, dim3(kBatchPhiBlocks, L.B), dim3(kNT), 0, s, L.N, L.prob, L.dyn, L.Qh, L.z, L.Phi);
+    hipLaunchKernelGGL(k_bbeta, dim3(kBatchBetaBlocks, L.B), dim3(kNT), 0, s, L.N, L.prob, L.dyn, L.blk_off, L.blk_k,
+                       L.blk_dp, L.Dp, L.Phi, L.beta);
     const unsigned tiles = (unsigned)((L.max_n + 63) / 64);
     if (L.N <= 16)
         hipLaunchKernelGGL((k_bhist<16>), dim3(tiles, L.B, 1), dim3(64), 0, s, L.N, L.ntot, L.prob, L.dyn, L.Ph,

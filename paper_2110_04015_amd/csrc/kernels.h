@@ -308,7 +308,7 @@ struct BatchProb {            // problem b of a batch (static)
 struct BatchDyn {             // per-problem solver state, advanced by the kernels
     int32_t hcols, nblk, cur_off, kcur;   // history columns and blocks; current block (first column, width)
     int32_t kn, multi, done, status;      // width of the next block, tau-test outcome, stopped, ba_status
-    int32_t iters, multi_steps, rank, pad;
+    int32_t iters, multi_steps, rank, max_it;   // ...; iterations this solve may take
     int64_t dp_used;                      // Delta^+ storage used (doubles)
     double rr0, rr, rho, t;
 };
@@ -329,17 +329,28 @@ struct BatchLaunch {
 constexpr int kMaxBlock = 64;         // widest direction block of Algorithm 2
 constexpr int kBatchGramBlocks = 16;   // partial blocks per problem of the Gram and update reductions
 constexpr int kBatchVecBlocks = 8;
-// r = -bt, x = x0 (or 0), rr0; problems with off[b] != 0 stay stopped; P_0 = D^-1 r_0
-void launch_bstart(const BatchLaunch &L, const double *bt, const double *x0, const int32_t *off, hipStream_t s);
+constexpr int kBatchPhiBlocks = 128;   // fixed grids of the history kernels (per problem), whatever the
+constexpr int kBatchBetaBlocks = 32;   // history width, so an iteration's launches never change
+// r = -bt, x = x0 (or 0), rr0; problems with off[b] != 0 stay stopped; P_0 = D^-1 r_0.  With
+// `only`, just the flagged problems are (re)started.  Each may take max_it[b] iterations
+// (max_iter when max_it is NULL).
+void launch_bstart(const BatchLaunch &L, const double *bt, const double *x0, const int32_t *off, hipStream_t s,
+                   const int32_t *only, int max_iter, const int32_t *max_it);
 // Gram, Delta^+ / alpha, x / r / z update, stop and tau tests
-void launch_biter_head(const BatchLaunch &L, double tau, double eps, int max_iter, hipStream_t s);
-// Phi, beta and the new history block (hmax, bmax: bounds of history columns and blocks)
-void launch_biter_tail(const BatchLaunch &L, int hmax, int bmax, hipStream_t s);
-// Q of one-column blocks from the staging product; the new block becomes current
-void launch_bqcopy_advance(const BatchLaunch &L, hipStream_t s);
+void launch_biter_head(const BatchLaunch &L, double tau, double eps, hipStream_t s);
+// Phi, beta and the new history block
+void launch_biter_tail(const BatchLaunch &L, hipStream_t s);
+// Q of one-column blocks from the staging product; the new block becomes current (`only`:
+// just the flagged problems)
+void launch_bqcopy_advance(const BatchLaunch &L, hipStream_t s, const int32_t *only = nullptr);
 // per-problem |bt + Sx|^2 and |bt|^2 (out [B][2]) and, when btp is given, btp = bt + Sx
+// (`only`: just the flagged problems)
 void launch_bresidual(const BatchLaunch &L, const double *bt, const double *Sx, double *btp, double *out,
-                      hipStream_t s);
+                      hipStream_t s, const int32_t *only = nullptr);
+// FP64 refinement step xprev = x, x += d, and its undoing x = xprev, on the flagged problems
+void launch_bouter_step(const BatchLaunch &L, const int32_t *only, double *x, const double *d, double *xprev,
+                        hipStream_t s);
+void launch_brevert(const BatchLaunch &L, const int32_t *only, double *x, const double *xprev, hipStream_t s);
 // LM outer loop (k_lm.hip): residuals, Jacobian blocks and F of a state; the moved state
 int project_blocks(int64_t m);   // doubles of `partials` launch_project needs
 void launch_project(int64_t m, const int32_t *obs_cam, const int32_t *obs_lm, const double *cams, const double *X,

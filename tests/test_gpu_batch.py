@@ -97,6 +97,18 @@ def test_mixed_precision_refinement(batch):
         assert st.status == ba.BA_OK and true < 1e-6 and st.refinement_steps >= 1
 
 
+def test_mixed_precision_graph_and_eager(batch):
+    """The refinement restarts each problem's inner solve on its own; graph replays and
+    eager launches take the same steps."""
+    probs, orc, b = batch
+    x0, s0, _, rc0 = b.mcg(4, 10.0, precision="fp32", graph_window=0)
+    x1, s1, _, rc1 = b.mcg(4, 10.0, precision="fp32", graph_window=8)
+    assert rc0 == rc1 == ba.BA_OK
+    assert np.array_equal(_h(x0), _h(x1))
+    assert [s.iterations for s in s0] == [s.iterations for s in s1]
+    assert [s.refinement_steps for s in s0] == [s.refinement_steps for s in s1]
+
+
 def test_bad_arguments(batch):
     probs, orc, b = batch
     with pytest.raises(ba.BAError) as e:
