@@ -24,8 +24,9 @@
  *  - A ba_system must not be used from two host threads at once.
  *  - The library allocates its own device memory (hipMalloc) inside
  *    ba_build_system and the solve calls; ba_free_system releases all of it.
- *    Input arrays are copied into the system's own layout: the caller may
- *    free them once ba_build_system has returned.
+ *    ba_build_system_ws takes the memory from a caller-owned workspace instead
+ *    (sized by ba_build_workspace_bytes).  Input arrays are copied into the
+ *    system's own layout: the caller may free them once the build has returned.
  */
 #ifndef BA_H
 #define BA_H
@@ -82,10 +83,13 @@ typedef struct {
                                 chunk of the FP64 product resident at once on the device */
     int32_t explicit_schur;  /* also form S explicitly in 9x9 block-sparse rows (the paper's representation,
                                 Sec. 3.2 and 4.1); FP64 S products then read it instead of the Jacobians.
-                                BA_ERR_UNSUPPORTED when a block row exceeds the LDS of the assembly (251 blocks) */
+                                Rows wider than one wavefront's LDS (251 blocks on gfx950) are assembled in
+                                pieces; BA_ERR_UNSUPPORTED only when a row's column list alone exceeds it */
     int32_t max_tiles_multi; /* tiles per chunk of the multidirectional product; 0: max_tiles when that is
                                 set, else as many as make every chunk of the FP64 product resident at once */
-    int32_t reserved[2];
+    int32_t ws_groups;       /* caller-owned workspace only (ba_build_system_ws): the solves it reserves memory
+                                for -- PCG always, MCG with this many subsets N (0: none) */
+    int32_t ws_max_iter;     /* ... and a direction history for this many iterations (0: 1000) */
 } ba_build_opts;
 
 typedef enum { BA_PREC_FP64 = 0, BA_PREC_FP32 = 1, BA_PREC_BF16 = 2 } ba_precision;
@@ -134,7 +138,37 @@ void ba_default_solve_opts(ba_solve_opts *opts);
 ba_status ba_build_system(const ba_problem_desc *desc, const ba_build_opts *opts, void *stream,
                           ba_system **out);
 
-/* Releases the system and all its device memory.  Null-safe. */
+/* Device bytes that ba_build_system_ws carves out of the caller's workspace for this
+ * problem and these options (the survey of the boundary: sizing only).  The layout is
+ * planned on the host from the observation indices (copied from desc's device arrays on
+ * the null stream), the values are not formed and nothing is allocated on the device.
+ * The count covers the system (Jacobian stream and its layout, the blocks of eq. (8)-
+ * (15), D(S), the explicit S and the FP32 / BF16 copies the options ask for) and the
+ * memory of the solves opts->ws_groups and opts->ws_max_iter reserve: PCG (Alg. 1) with
+ * a residual trace, MCG (Alg. 2) with ws_groups subsets (its multidirectional layout and
+ * a history of 1 + ws_max_iter * ws_groups columns), and the refinement vectors when a
+ * reduced-precision copy is stored.  bytes: host.  Errors as ba_build_system. */
+ba_status ba_build_workspace_bytes(const ba_problem_desc *desc, const ba_build_opts *opts, size_t *bytes);
+
+/* ba_build_system with every device array of the system in the caller's workspace ws
+ * (device, 256-byte aligned, ws_bytes >= ba_build_workspace_bytes of the same desc and
+ * opts).  The handle does not own ws: ws must stay allocated until ba_free_system, which
+ * releases only the host-side parts.  The input arrays are copied into ws, so they may
+ * be freed once the call has returned.  Later calls on the system take device memory
+ * only from ws: the reserved solves run without allocating; anything beyond them
+ * (another N, a longer history, a reduced precision not stored at build, the low-rank
+ * preconditioner) uses what is left of ws or fails with BA_ERR_WORKSPACE.  Errors as
+ * ba_build_system, plus INVALID_ARG (ws NULL or misaligned) and WORKSPACE (ws_bytes too
+ * small). */
+ba_status ba_build_system_ws(const ba_problem_desc *desc, const ba_build_opts *opts, void *ws, size_t ws_bytes,
+                             void *stream, ba_system **out);
+
+/* Bytes of the caller's workspace a system built by ba_build_system_ws has used so far
+ * (0 for other systems).  bytes: host. */
+ba_status ba_system_workspace_used(const ba_system *sys, size_t *bytes);
+
+/* Releases the system and all its device memory (for ba_build_system_ws: the host-side
+ * parts only).  Null-safe. */
 void ba_free_system(ba_system *sys);
 
 /* y = S v for one camera-space vector (the implicit product of eq. (14)):

@@ -121,7 +121,9 @@ class System:
 
     def __init__(self, n_cams, n_lms, obs_cam, obs_lm, J_p, J_l, r, lam, stream=None,
                  max_slots=0, max_tiles=0, store_fp32=False, store_bf16=False, explicit_schur=False,
-                 max_tiles_multi=0):
+                 max_tiles_multi=0, workspace=None, ws_groups=0, ws_max_iter=0, size_only=False):
+        """workspace: a device uint8 tensor for ba_build_system_ws (kept alive by the object);
+        size_only: only run ba_build_workspace_bytes and keep its result in self.ws_bytes."""
         torch = _torch()
         m = int(obs_cam.numel())
         # pose dimension (Sec. 3.1): 9, or 6 for extrinsics only, from the size of J_p
@@ -138,15 +140,36 @@ class System:
         o.store_fp32, o.store_bf16 = int(store_fp32), int(store_bf16)
         o.max_slots, o.max_tiles, o.max_tiles_multi = int(max_slots), int(max_tiles), int(max_tiles_multi)
         o.explicit_schur = int(explicit_schur)
+        o.ws_groups, o.ws_max_iter = int(ws_groups), int(ws_max_iter)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         self.device = obs_cam.device
-        h = C.c_void_p()
-        _check(lib().ba_build_system(C.byref(d), C.byref(o), _stream_handle(self._stream), C.byref(h)),
-               "ba_build_system")
-        self.h = h
         self.n_cams, self.n_lms, self.n_obs = int(n_cams), int(n_lms), m
         self.d_p = dp
         self.n = dp * self.n_cams
+        h = C.c_void_p()
+        self._ws = workspace
+        if size_only:
+            nb = C.c_size_t()
+            _check(lib().ba_build_workspace_bytes(C.byref(d), C.byref(o), C.byref(nb)), "ba_build_workspace_bytes")
+            self.ws_bytes = int(nb.value)
+            self.h = None
+            return
+        if workspace is not None:
+            if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or workspace.dtype != torch.uint8:
+                raise TypeError("workspace must be a device uint8 tensor")
+            _check(lib().ba_build_system_ws(C.byref(d), C.byref(o), C.c_void_p(workspace.data_ptr()),
+                                            C.c_size_t(workspace.numel()), _stream_handle(self._stream), C.byref(h)),
+                   "ba_build_system_ws")
+        else:
+            _check(lib().ba_build_system(C.byref(d), C.byref(o), _stream_handle(self._stream), C.byref(h)),
+                   "ba_build_system")
+        self.h = h
+
+    def workspace_used(self):
+        """Bytes of the caller's workspace used so far (ba_system_workspace_used)."""
+        nb = C.c_size_t()
+        _check(lib().ba_system_workspace_used(self.h, C.byref(nb)), "ba_system_workspace_used")
+        return int(nb.value)
 
     @classmethod
     def from_problem(cls, p, device="cuda", **kw):

@@ -22,7 +22,7 @@ class ProblemDesc(C.Structure):
 class BuildOpts(C.Structure):
     _fields_ = [("store_fp32", C.c_int32), ("store_bf16", C.c_int32), ("max_slots", C.c_int32),
                 ("max_tiles", C.c_int32), ("explicit_schur", C.c_int32), ("max_tiles_multi", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("ws_groups", C.c_int32), ("ws_max_iter", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -70,6 +70,10 @@ class LMStats(C.Structure):
 SIGNATURES = [
     ("ba_default_solve_opts", None, [C.POINTER(SolveOpts)]),
     ("ba_build_system", C.c_int, [C.POINTER(ProblemDesc), C.POINTER(BuildOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("ba_build_workspace_bytes", C.c_int, [C.POINTER(ProblemDesc), C.POINTER(BuildOpts), C.POINTER(C.c_size_t)]),
+    ("ba_build_system_ws", C.c_int, [C.POINTER(ProblemDesc), C.POINTER(BuildOpts), C.c_void_p, C.c_size_t, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    ("ba_system_workspace_used", C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     ("ba_free_system", None, [C.c_void_p]),
     ("ba_schur_matvec", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     ("ba_schur_matvec_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),

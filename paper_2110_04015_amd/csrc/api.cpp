@@ -62,79 +62,120 @@ void dfree(T *&p) {
     p = nullptr;
 }
 
-void free_multi(DevMulti &m) {
-    dfree(m.mmeta);
-    dfree(m.slot_cam);
-    dfree(m.pair_ll);
-    dfree(m.tile_oidx);
-    dfree(m.oidx);
-    dfree(m.slot_ooff);
-    dfree(m.chunk_tile);
-    dfree(m.chunk_part);
-    dfree(m.cg_ptr);
-    dfree(m.cg_idx);
-    dfree(m.part_dst);
-    dfree(m.partial);
-    dfree(m.group);
-    dfree(m.chunk_seg);
+// Device memory of a system: from the caller's workspace when it brought one (a bump
+// allocation, 256-byte aligned; BA_ERR_WORKSPACE when it is used up), else hipMalloc.  In
+// the sizing pass (ws_counting) nothing is allocated: the offsets are only counted and a
+// non-null stand-in address that nothing dereferences is returned.
+template <typename T>
+ba_status salloc(ba_system *s, T **p, size_t count) {
+    if (!s->ws_base && !s->ws_counting) return dalloc(p, count);
+    *p = nullptr;
+    if (count == 0) count = 1;
+    const size_t bytes = count * sizeof(T);
+    const size_t off = (s->ws_used + 255) & ~size_t(255);
+    if (s->ws_counting) {
+        s->ws_used = off + bytes;
+        *p = reinterpret_cast<T *>((uintptr_t)4096 + off);
+        return BA_OK;
+    }
+    if (off + bytes > s->ws_size)
+        return fail(BA_ERR_WORKSPACE, "the caller's workspace is used up: " + std::to_string(off + bytes) +
+                                          " bytes needed, " + std::to_string(s->ws_size) + " given");
+    *p = reinterpret_cast<T *>(s->ws_base + off);
+    s->ws_used = off + bytes;
+    return BA_OK;
+}
+
+template <typename T>
+void sfree(ba_system *s, T *&p) {
+    if (!p) return;
+    if (!s->ws_base && !s->ws_counting) (void)hipFree((void *)p);   // workspace memory is the caller's
+    p = nullptr;
+}
+
+// salloc, then the host vector's contents (no copy in the sizing pass)
+template <typename T>
+ba_status supload(ba_system *s, T **p, const std::vector<T> &v) {
+    ba_status st = salloc(s, p, v.size());
+    if (st != BA_OK) return st;
+    if (!s->ws_counting && !v.empty())
+        HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s->stream));
+    return BA_OK;
+}
+
+void free_multi(ba_system *s, DevMulti &m) {
+    sfree(s, m.mmeta);
+    sfree(s, m.slot_cam);
+    sfree(s, m.pair_ll);
+    sfree(s, m.tile_oidx);
+    sfree(s, m.oidx);
+    sfree(s, m.slot_ooff);
+    sfree(s, m.chunk_tile);
+    sfree(s, m.chunk_part);
+    sfree(s, m.cg_ptr);
+    sfree(s, m.cg_idx);
+    sfree(s, m.part_dst);
+    sfree(s, m.partial);
+    sfree(s, m.group);
+    sfree(s, m.chunk_seg);
     m = DevMulti();
 }
 
 void free_all(ba_system *s) {
-    dfree(s->J64);
-    dfree(s->J32);
-    dfree(s->J16);
-    dfree(s->slot_obs);
-    dfree(s->cam_obs_ptr);
-    dfree(s->cam_obs);
-    dfree(s->lmk_store);
-    dfree(s->obs_lm);
-    dfree(s->h0);
-    dfree(s->Vraw);
-    dfree(s->Uraw);
-    dfree(s->bp);
-    dfree(s->obs_slot);
-    dfree(s->bsr_slot_cam);
-    dfree(s->meta);
-    dfree(s->tile_lmk_base);
-    dfree(s->chunk_tile);
-    dfree(s->chunk_part);
-    dfree(s->part_cam);
-    dfree(s->cam_part_ptr);
-    dfree(s->cam_part_idx);
-    dfree(s->part_dst);
-    dfree(s->partial);
-    dfree(s->vinv);
-    dfree(s->bl);
-    dfree(s->dU);
-    dfree(s->Dblk);
-    dfree(s->Dchol);
-    dfree(s->bt);
-    dfree(s->lmk_order);
-    dfree(s->lmk_first_slot);
-    dfree(s->lmk_count);
-    dfree(s->status);
-    dfree(s->vec);
-    dfree(s->red);
-    dfree(s->hist);
-    dfree(s->small);
-    dfree(s->hscratch);
-    dfree(s->tickets);
-    dfree(s->refine_buf);
-    dfree(s->Ulr);
-    dfree(s->degree);
-    dfree(s->lr_proj);
-    dfree(s->seg_cam);
-    dfree(s->seg_chunk);
-    dfree(s->bsr_ptr);
-    dfree(s->bsr_col);
-    dfree(s->bsr_val);
+    sfree(s, s->J64);
+    sfree(s, s->J32);
+    sfree(s, s->J16);
+    sfree(s, s->slot_obs);
+    sfree(s, s->cam_obs_ptr);
+    sfree(s, s->cam_obs);
+    sfree(s, s->lmk_store);
+    sfree(s, s->obs_lm);
+    sfree(s, s->h0);
+    sfree(s, s->Vraw);
+    sfree(s, s->Uraw);
+    sfree(s, s->bp);
+    sfree(s, s->obs_slot);
+    sfree(s, s->bsr_slot_cam);
+    sfree(s, s->meta);
+    sfree(s, s->tile_lmk_base);
+    sfree(s, s->chunk_tile);
+    sfree(s, s->chunk_part);
+    sfree(s, s->part_cam);
+    sfree(s, s->cam_part_ptr);
+    sfree(s, s->cam_part_idx);
+    sfree(s, s->part_dst);
+    sfree(s, s->partial);
+    sfree(s, s->vinv);
+    sfree(s, s->bl);
+    sfree(s, s->dU);
+    sfree(s, s->Dblk);
+    sfree(s, s->Dchol);
+    sfree(s, s->bt);
+    sfree(s, s->lmk_order);
+    sfree(s, s->lmk_first_slot);
+    sfree(s, s->lmk_count);
+    sfree(s, s->status);
+    sfree(s, s->vec);
+    sfree(s, s->red);
+    sfree(s, s->hist);
+    sfree(s, s->small);
+    sfree(s, s->hscratch);
+    sfree(s, s->tickets);
+    sfree(s, s->refine_buf);
+    sfree(s, s->Ulr);
+    sfree(s, s->degree);
+    sfree(s, s->lr_proj);
+    sfree(s, s->seg_cam);
+    sfree(s, s->seg_chunk);
+    sfree(s, s->bsr_ptr);
+    sfree(s, s->bsr_col);
+    sfree(s, s->bsr_val);
     if (s->host_pinned) (void)hipHostFree(s->host_pinned);
     s->host_pinned = nullptr;
     s->host_pinned_dev = nullptr;
     if (s->sc_event) (void)hipEventDestroy(s->sc_event);
     s->sc_event = nullptr;
-    free_multi(s->multi);
+    free_multi(s, s->multi);
     for (hipEvent_t e : s->prof_events) (void)hipEventDestroy(e);
     s->prof_events.clear();
 }
@@ -182,6 +223,13 @@ inline bool use_bsr(const ba_system *s, const SchurArgs &a) {
     return s->bsr_val && a.precision == 0 && !a.seg_skip;
 }
 
+// partial pairs of the Gram products a product with gram set leaves (camera reduction of
+// the implicit product: one per four cameras; explicit product: one per block row)
+inline int gram_parts(const ba_system *s, const SchurArgs &a) {
+    return use_bsr(s, a) ? bsr_gram_blocks(s->np) : schur_gram_blocks(s->np);
+}
+inline int gram_parts_max(const ba_system *s) { return std::max(bsr_gram_blocks(s->np), schur_gram_blocks(s->np)); }
+
 // y = S v; with profiling on, the dominant kernel is bracketed by events on the stream
 void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
     // a sampled launch (every prof_every-th) gets the events
@@ -223,15 +271,15 @@ ba_status ensure_precision(ba_system *s, int precision) {
     if (precision < 0 || precision > 2) return fail(BA_ERR_INVALID_ARG, "precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
     const int64_t nslots = s->plan.n_tiles * kTile;
     if (precision == 1 && !s->J32) {
-        ba_status st = dalloc(&s->J32, (size_t)nslots * 24);
+        ba_status st = salloc(s, &s->J32, (size_t)nslots * 24);
         if (st != BA_OK) return st;
-        launch_convert(s->J64, nslots, s->J32, nullptr, s->stream, s->dp);
+        if (!s->ws_counting) launch_convert(s->J64, nslots, s->J32, nullptr, s->stream, s->dp);
         HIPCHK(hipGetLastError());
     }
     if (precision == 2 && !s->J16) {
-        ba_status st = dalloc(&s->J16, (size_t)nslots * 24);
+        ba_status st = salloc(s, &s->J16, (size_t)nslots * 24);
         if (st != BA_OK) return st;
-        launch_convert(s->J64, nslots, nullptr, s->J16, s->stream, s->dp);
+        if (!s->ws_counting) launch_convert(s->J64, nslots, nullptr, s->J16, s->stream, s->dp);
         HIPCHK(hipGetLastError());
     }
     return BA_OK;
@@ -241,7 +289,10 @@ ba_status ensure_precision(ba_system *s, int precision) {
 // multidirectional product (the explicit S's grouped product needs the partition only).
 ba_status ensure_multi(ba_system *s, int N, bool plan = true) {
     if (s->multi.N == N && s->multi.group && (!plan || s->multi.partial)) return BA_OK;
-    free_multi(s->multi);
+    if (s->ws_base && s->multi.group)
+        return fail(BA_ERR_WORKSPACE, "the caller's workspace holds the layout of N = " + std::to_string(s->multi.N) +
+                                          " subsets (ba_build_opts.ws_groups), not of N = " + std::to_string(N));
+    free_multi(s, s->multi);
     HostMultiPlan mp;
     std::string err;
     // subsets: Sec. 3.2's partition of the poses; in a batch, of each problem's poses
@@ -260,7 +311,7 @@ ba_status ensure_multi(ba_system *s, int N, bool plan = true) {
     }
     ba_status st;
     if (!plan) {
-        if ((st = upload(&s->multi.group, grp, s->stream)) != BA_OK) return st;
+        if ((st = supload(s, &s->multi.group, grp)) != BA_OK) return st;
         s->multi.N = N;
         HIPCHK(hipStreamSynchronize(s->stream));   // grp goes out of scope
         return BA_OK;
@@ -280,20 +331,20 @@ ba_status ensure_multi(ba_system *s, int N, bool plan = true) {
                                             " fit in LDS");
     DevMulti &m = s->multi;
     hipStream_t q = s->stream;
-    if ((st = upload(&m.mmeta, mp.mmeta, q)) != BA_OK) return st;
-    if ((st = upload(&m.slot_cam, mp.slot_cam, q)) != BA_OK) return st;
-    if ((st = upload(&m.pair_ll, mp.pair_ll, q)) != BA_OK) return st;
-    if ((st = upload(&m.tile_oidx, mp.tile_oidx, q)) != BA_OK) return st;
-    if ((st = upload(&m.oidx, mp.oidx, q)) != BA_OK) return st;
-    if ((st = upload(&m.slot_ooff, mp.slot_ooff, q)) != BA_OK) return st;
-    if ((st = upload(&m.chunk_tile, mp.chunk_tile, q)) != BA_OK) return st;
-    if ((st = upload(&m.chunk_part, mp.chunk_part, q)) != BA_OK) return st;
-    if ((st = upload(&m.cg_ptr, mp.cg_ptr, q)) != BA_OK) return st;
-    if ((st = upload(&m.cg_idx, mp.cg_idx, q)) != BA_OK) return st;
-    if ((st = upload(&m.part_dst, mp.part_dst, q)) != BA_OK) return st;
-    if ((st = upload(&m.group, grp, q)) != BA_OK) return st;
-    if ((st = upload(&m.chunk_seg, mp.chunk_seg, q)) != BA_OK) return st;
-    if ((st = dalloc(&m.partial, (size_t)std::max<int64_t>(mp.n_part, 1) * s->dp)) != BA_OK) return st;
+    if ((st = supload(s, &m.mmeta, mp.mmeta)) != BA_OK) return st;
+    if ((st = supload(s, &m.slot_cam, mp.slot_cam)) != BA_OK) return st;
+    if ((st = supload(s, &m.pair_ll, mp.pair_ll)) != BA_OK) return st;
+    if ((st = supload(s, &m.tile_oidx, mp.tile_oidx)) != BA_OK) return st;
+    if ((st = supload(s, &m.oidx, mp.oidx)) != BA_OK) return st;
+    if ((st = supload(s, &m.slot_ooff, mp.slot_ooff)) != BA_OK) return st;
+    if ((st = supload(s, &m.chunk_tile, mp.chunk_tile)) != BA_OK) return st;
+    if ((st = supload(s, &m.chunk_part, mp.chunk_part)) != BA_OK) return st;
+    if ((st = supload(s, &m.cg_ptr, mp.cg_ptr)) != BA_OK) return st;
+    if ((st = supload(s, &m.cg_idx, mp.cg_idx)) != BA_OK) return st;
+    if ((st = supload(s, &m.part_dst, mp.part_dst)) != BA_OK) return st;
+    if ((st = supload(s, &m.group, grp)) != BA_OK) return st;
+    if ((st = supload(s, &m.chunk_seg, mp.chunk_seg)) != BA_OK) return st;
+    if ((st = salloc(s, &m.partial, (size_t)std::max<int64_t>(mp.n_part, 1) * s->dp)) != BA_OK) return st;
     m.N = N;
     m.n_chunks = mp.n_chunks;
     m.max_out = mp.max_out;
@@ -330,38 +381,39 @@ MultiArgs multi_args(ba_system *s, int precision) {
     return a;
 }
 
-ba_status ensure_vec(ba_system *s, size_t doubles) {
-    if (s->vec_cap >= doubles) return BA_OK;
-    dfree(s->vec);
-    ba_status st = dalloc(&s->vec, doubles);
+// Grows a buffer of the system to `count` elements: the new buffer is allocated before the
+// old one is dropped, so a failure (a used-up workspace) leaves the system as it was.
+template <typename T, typename C>
+ba_status grow(ba_system *s, T *&buf, C &cap, size_t count) {
+    if ((size_t)cap >= count) return BA_OK;
+    T *nb = nullptr;
+    ba_status st = salloc(s, &nb, count);
     if (st != BA_OK) return st;
-    s->vec_cap = doubles;
+    sfree(s, buf);
+    buf = nb;
+    cap = (C)count;
     return BA_OK;
 }
 
-ba_status ensure_red(ba_system *s, size_t doubles) {
-    if (s->red_cap >= doubles) return BA_OK;
-    dfree(s->red);
-    ba_status st = dalloc(&s->red, doubles);
-    if (st != BA_OK) return st;
-    s->red_cap = doubles;
-    return BA_OK;
-}
+ba_status ensure_vec(ba_system *s, size_t doubles) { return grow(s, s->vec, s->vec_cap, doubles); }
+
+ba_status ensure_red(ba_system *s, size_t doubles) { return grow(s, s->red, s->red_cap, doubles); }
+
+// per-iteration residual trace of PCG (device, max_iter doubles)
+ba_status ensure_trace(ba_system *s, int64_t count) { return grow(s, s->trace_buf, s->trace_cap, (size_t)count); }
 
 // arrival counters of the last-block reductions: zero on allocation, and every kernel
 // that takes one leaves it zero
 ba_status ensure_tickets(ba_system *s, int64_t count) {
     if (s->tickets_cap >= count) return BA_OK;
-    dfree(s->tickets);
-    s->tickets_cap = 0;
-    ba_status st = dalloc(&s->tickets, (size_t)count);
+    ba_status st = grow(s, s->tickets, s->tickets_cap, (size_t)count);
     if (st != BA_OK) return st;
-    HIPCHK(hipMemsetAsync(s->tickets, 0, (size_t)count * sizeof(uint32_t), s->stream));
-    s->tickets_cap = count;
+    if (!s->ws_counting) HIPCHK(hipMemsetAsync(s->tickets, 0, (size_t)count * sizeof(uint32_t), s->stream));
     return BA_OK;
 }
 
 ba_status ensure_pinned(ba_system *s) {
+    if (s->ws_counting) return BA_OK;
     if (!s->host_pinned) {
         // SC_COUNT scalars and the tag of the kernel-written copy
         HIPCHK(hipHostMalloc((void **)&s->host_pinned, (SC_COUNT + 1) * sizeof(double), hipHostMallocMapped));
@@ -541,7 +593,7 @@ static ba_status apply_lambda(ba_system *s) {
         (void)hipEventCreate(&e1);
         if (e0) (void)hipEventRecord(e0, q);
         launch_bsr_assemble(s->np, bsr_gather(s), s->obs_slot, s->J64, s->vinv, s->Dblk, s->bsr_ptr, s->bsr_col,
-                            s->bsr_max_row, s->bsr_val, q);
+                            s->bsr_max_row, s->bsr_piece, s->bsr_val, q);
         if (e1) (void)hipEventRecord(e1, q);
         if (hipStreamSynchronize(q) == hipSuccess && e0 && e1) {
             float ms = 0.f;
@@ -584,8 +636,41 @@ static ba_status fill_values(ba_system *s, const double *J_p, const double *J_l,
     return apply_lambda(s);
 }
 
+static ba_status pcg_buffers(ba_system *s, int max_iter, bool trace);
+static ba_status mcg_buffers(ba_system *s, int N, int64_t cap);
+
+// The solver memory a system in a caller's workspace reserves at build, so that the solves
+// the options name never allocate: PCG (with a residual trace), MCG with ws_groups subsets
+// (0: none) and a history for ws_max_iter iterations (0: 1000), the multidirectional
+// layout, and the refinement vectors when a reduced-precision copy is stored.
+static ba_status reserve_solvers(ba_system *s, const ba_build_opts *o) {
+    const int N = o ? o->ws_groups : 0;
+    const int it = o && o->ws_max_iter > 0 ? o->ws_max_iter : 1000;
+    const bool mixed = o && (o->store_fp32 || o->store_bf16);
+    if (N < 0 || N > s->np || it < 1) return fail(BA_ERR_INVALID_ARG, "ws_groups must be in [0, n_cams] and ws_max_iter >= 0");
+    ba_status st;
+    if ((st = pcg_buffers(s, it, true)) != BA_OK) return st;
+    if (N >= 1) {
+        if (N > 1) {
+            // the explicit S's grouped product needs the partition only, reduced-precision
+            // products the implicit layout
+            const bool bsr = s->bsr_val && N <= kMaxBlock;
+            if ((st = ensure_multi(s, N, !bsr || mixed)) != BA_OK) return st;
+        }
+        if ((st = mcg_buffers(s, N, 1 + (int64_t)it * N)) != BA_OK) return st;
+    }
+    if (mixed) {
+        const int64_t n = (int64_t)s->np * s->dp;
+        if ((st = grow(s, s->refine_buf, s->refine_cap, (size_t)n * 5 + 8)) != BA_OK) return st;
+    }
+    return BA_OK;
+}
+
+// ws (nullable): the caller's device workspace of ws_bytes; counting: the sizing pass, which
+// plans the layout on the host and counts the device bytes without allocating or launching.
 static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream,
-                              const int32_t *cam_seg, ba_system **out) {
+                              const int32_t *cam_seg, ba_system **out, char *ws = nullptr, size_t ws_bytes = 0,
+                              bool counting = false) {
     if (!out) return fail(BA_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!d) return fail(BA_ERR_INVALID_ARG, "desc is NULL");
@@ -611,6 +696,9 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
 
     ba_system *s = new ba_system();
     s->stream = (hipStream_t)stream;
+    s->ws_base = ws;
+    s->ws_size = ws_bytes;
+    s->ws_counting = counting;
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return fail(BA_ERR_HIP, "no current HIP device");
@@ -639,23 +727,23 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
                               max_tiles == 0 && max_tiles_multi == 0 ? schur_multi_resident_chunks(d->d_p) : 0);
     if (st != BA_OK) return bail(fail(st, err));
     if (cam_seg) {
-        if ((st = upload(&s->seg_cam, s->plan.cam_seg, q)) != BA_OK) return bail(st);
-        if ((st = upload(&s->seg_chunk, s->plan.chunk_seg, q)) != BA_OK) return bail(st);
+        if ((st = supload(s, &s->seg_cam, s->plan.cam_seg)) != BA_OK) return bail(st);
+        if ((st = supload(s, &s->seg_chunk, s->plan.chunk_seg)) != BA_OK) return bail(st);
     }
     const HostPlan &P = s->plan;
     const int64_t nslots = P.n_tiles * kTile;
 
-    if ((st = dalloc(&s->status, 1)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->status, 1)) != BA_OK) return bail(st);
     // layout on the device (kept for ba_update_system)
-    if ((st = upload(&s->slot_obs, P.slot_obs, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->cam_obs_ptr, P.cam_obs_ptr, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->cam_obs, P.cam_obs, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->lmk_store, P.lmk_store, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->obs_lm, hlm, q)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->h0, (size_t)s->nl * 3)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->Vraw, (size_t)s->nl * 6)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->Uraw, (size_t)s->np * (d->d_p * (d->d_p + 1) / 2))) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->bp, (size_t)s->np * d->d_p)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->slot_obs, P.slot_obs)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->cam_obs_ptr, P.cam_obs_ptr)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->cam_obs, P.cam_obs)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->lmk_store, P.lmk_store)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->obs_lm, hlm)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->h0, (size_t)s->nl * 3)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->Vraw, (size_t)s->nl * 6)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->Uraw, (size_t)s->np * (d->d_p * (d->d_p + 1) / 2))) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->bp, (size_t)s->np * d->d_p)) != BA_OK) return bail(st);
     {
         // tile slot of every observation (the lambda kernels read the packed stream by it)
         std::vector<int64_t> oslot((size_t)m, 0);
@@ -663,31 +751,31 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
             const int64_t o = P.slot_obs[(size_t)sl];
             if (o >= 0) oslot[(size_t)o] = sl;
         }
-        if ((st = upload(&s->obs_slot, oslot, q)) != BA_OK) return bail(st);
+        if ((st = supload(s, &s->obs_slot, oslot)) != BA_OK) return bail(st);
         if (hipStreamSynchronize(q) != hipSuccess) return bail(fail(BA_ERR_HIP, "uploading the slot map failed"));
     }
-    if ((st = upload(&s->meta, P.meta, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->tile_lmk_base, P.tile_lmk_base, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->chunk_tile, P.chunk_tile, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->chunk_part, P.chunk_part, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->part_cam, P.part_cam, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->cam_part_ptr, P.cam_part_ptr, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->cam_part_idx, P.cam_part_idx, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->part_dst, P.part_dst, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->lmk_order, P.lmk_order, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->lmk_first_slot, P.lmk_first_slot, q)) != BA_OK) return bail(st);
-    if ((st = upload(&s->lmk_count, P.lmk_count, q)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->meta, P.meta)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->tile_lmk_base, P.tile_lmk_base)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->chunk_tile, P.chunk_tile)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->chunk_part, P.chunk_part)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->part_cam, P.part_cam)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->cam_part_ptr, P.cam_part_ptr)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->cam_part_idx, P.cam_part_idx)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->part_dst, P.part_dst)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->lmk_order, P.lmk_order)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->lmk_first_slot, P.lmk_first_slot)) != BA_OK) return bail(st);
+    if ((st = supload(s, &s->lmk_count, P.lmk_count)) != BA_OK) return bail(st);
     const int dp = s->dp;
-    if ((st = dalloc(&s->partial, (size_t)std::max<int64_t>(P.n_part, 1) * dp)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->J64, (size_t)nslots * 24)) != BA_OK) return bail(st);
-    if (opts && opts->store_fp32 && (st = dalloc(&s->J32, (size_t)nslots * 24)) != BA_OK) return bail(st);
-    if (opts && opts->store_bf16 && (st = dalloc(&s->J16, (size_t)nslots * 24)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->vinv, (size_t)s->nl * 6)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->bl, (size_t)s->nl * 3)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->dU, (size_t)s->np * dp)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->Dblk, (size_t)s->np * dp * dp)) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->Dchol, (size_t)s->np * (dp * (dp + 1) / 2))) != BA_OK) return bail(st);
-    if ((st = dalloc(&s->bt, (size_t)s->np * dp)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->partial, (size_t)std::max<int64_t>(P.n_part, 1) * dp)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->J64, (size_t)nslots * 24)) != BA_OK) return bail(st);
+    if (opts && opts->store_fp32 && (st = salloc(s, &s->J32, (size_t)nslots * 24)) != BA_OK) return bail(st);
+    if (opts && opts->store_bf16 && (st = salloc(s, &s->J16, (size_t)nslots * 24)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->vinv, (size_t)s->nl * 6)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->bl, (size_t)s->nl * 3)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->dU, (size_t)s->np * dp)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->Dblk, (size_t)s->np * dp * dp)) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->Dchol, (size_t)s->np * (dp * (dp + 1) / 2))) != BA_OK) return bail(st);
+    if ((st = salloc(s, &s->bt, (size_t)s->np * dp)) != BA_OK) return bail(st);
     if (opts && opts->explicit_schur) {
         // explicit S in block-sparse rows, assembled from the same blocks (Sec. 3.2, 4.1): the
         // pattern and the contribution pairs depend on the observations only
@@ -698,17 +786,25 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
             const int64_t o = P.slot_obs[(size_t)sl];
             if (o >= 0) scam[(size_t)sl] = P.obs_cam[(size_t)o];
         }
-        if ((st = upload(&s->bsr_slot_cam, scam, q)) != BA_OK) return bail(st);
+        if ((st = supload(s, &s->bsr_slot_cam, scam)) != BA_OK) return bail(st);
         // pattern on the device: block counts per row, then the rows' columns
         int32_t *d_nnz = nullptr;
-        if ((st = dalloc(&d_nnz, (size_t)s->np)) != BA_OK) return bail(st);
-        launch_bsr_rowcount(s->np, bsr_gather(s), d_nnz, q);
+        if ((st = salloc(s, &d_nnz, (size_t)s->np)) != BA_OK) return bail(st);
         std::vector<int32_t> nnz((size_t)s->np);
-        const bool cnt_ok = hipGetLastError() == hipSuccess &&
-                            hipMemcpyAsync(nnz.data(), d_nnz, (size_t)s->np * 4, hipMemcpyDeviceToHost, q) == hipSuccess &&
-                            hipStreamSynchronize(q) == hipSuccess;
-        dfree(d_nnz);
-        if (!cnt_ok) return bail(fail(BA_ERR_HIP, "explicit S: pattern count failed"));
+        if (counting) {
+            // the same counts from the host plan: a row holds camera j and every camera
+            // sharing a landmark with it
+            covisibility_degree(P, nnz);
+            for (int32_t &c : nnz) c += 1;
+        } else {
+            launch_bsr_rowcount(s->np, bsr_gather(s), d_nnz, q);
+            const bool cnt_ok = hipGetLastError() == hipSuccess &&
+                                hipMemcpyAsync(nnz.data(), d_nnz, (size_t)s->np * 4, hipMemcpyDeviceToHost, q) ==
+                                    hipSuccess &&
+                                hipStreamSynchronize(q) == hipSuccess;
+            if (!cnt_ok) return bail(fail(BA_ERR_HIP, "explicit S: pattern count failed"));
+        }
+        sfree(s, d_nnz);
         std::vector<int32_t> rp((size_t)s->np + 1, 0);
         int max_row = 0;
         for (int j = 0; j < s->np; ++j) {
@@ -721,28 +817,58 @@ static ba_status build_system(const ba_problem_desc *d, const ba_build_opts *opt
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             return bail(fail(BA_ERR_HIP, "device attribute query failed"));
-        if ((size_t)max_row * (81 * sizeof(double) + sizeof(int32_t)) > (size_t)lds_max)
+        // rows wider than one wavefront's LDS are assembled in pieces
+        const int piece = bsr_assembly_piece(max_row, (size_t)lds_max);
+        if (piece < 1)
             return bail(fail(BA_ERR_UNSUPPORTED, "explicit S: a camera is covisible with " + std::to_string(max_row) +
                                                      " cameras, more than one work-group's LDS holds"));
         if ((size_t)((s->np + 31) / 32) * 4 > (size_t)lds_max)
             return bail(fail(BA_ERR_UNSUPPORTED, "explicit S: too many cameras for the pattern bitmap"));
-        if ((st = upload(&s->bsr_ptr, rp, q)) != BA_OK) return bail(st);
+        if ((st = supload(s, &s->bsr_ptr, rp)) != BA_OK) return bail(st);
         s->bsr_nnzb = (int64_t)rp[(size_t)s->np];
         s->bsr_max_row = max_row;
-        if ((st = dalloc(&s->bsr_col, (size_t)std::max<int64_t>(s->bsr_nnzb, 1))) != BA_OK) return bail(st);
-        launch_bsr_rowfill(s->np, bsr_gather(s), s->bsr_ptr, s->bsr_col, q);
-        if ((st = dalloc(&s->bsr_val, (size_t)s->bsr_nnzb * 81)) != BA_OK) return bail(st);
+        s->bsr_piece = piece;
+        if ((st = salloc(s, &s->bsr_col, (size_t)std::max<int64_t>(s->bsr_nnzb, 1))) != BA_OK) return bail(st);
+        if (!counting) launch_bsr_rowfill(s->np, bsr_gather(s), s->bsr_ptr, s->bsr_col, q);
+        if ((st = salloc(s, &s->bsr_val, (size_t)s->bsr_nnzb * 81)) != BA_OK) return bail(st);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(q) != hipSuccess)   // host vectors go out of scope
             return bail(fail(BA_ERR_HIP, "explicit S: pattern failed"));
     }
-    if ((st = fill_values(s, d->J_p, d->J_l, d->r)) != BA_OK) return bail(st);
+    if (!counting && (st = fill_values(s, d->J_p, d->J_l, d->r)) != BA_OK) return bail(st);
     if ((st = ensure_pinned(s)) != BA_OK) return bail(st);
+    if ((ws || counting) && (st = reserve_solvers(s, opts)) != BA_OK) return bail(st);
     *out = s;
     return BA_OK;
 }
 
 ba_status ba_build_system(const ba_problem_desc *d, const ba_build_opts *opts, void *stream, ba_system **out) {
     return build_system(d, opts, stream, nullptr, out);
+}
+
+ba_status ba_build_workspace_bytes(const ba_problem_desc *d, const ba_build_opts *opts, size_t *bytes) {
+    if (!bytes) return fail(BA_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = 0;
+    ba_system *s = nullptr;
+    const ba_status st = build_system(d, opts, nullptr, nullptr, &s, nullptr, 0, true);
+    if (st != BA_OK) return st;
+    *bytes = (s->ws_used + 255) & ~size_t(255);
+    free_all(s);
+    delete s;
+    return BA_OK;
+}
+
+ba_status ba_build_system_ws(const ba_problem_desc *d, const ba_build_opts *opts, void *ws, size_t ws_bytes,
+                             void *stream, ba_system **out) {
+    if (out) *out = nullptr;
+    if (!ws) return fail(BA_ERR_INVALID_ARG, "ws is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(BA_ERR_INVALID_ARG, "ws must be 256-byte aligned");
+    return build_system(d, opts, stream, nullptr, out, static_cast<char *>(ws), ws_bytes, false);
+}
+
+ba_status ba_system_workspace_used(const ba_system *s, size_t *bytes) {
+    if (!s || !bytes) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    *bytes = s->ws_base ? s->ws_used : 0;
+    return BA_OK;
 }
 
 ba_status ba_update_system(ba_system *s, const double *J_p, const double *J_l, const double *r, double lambda) {
@@ -888,6 +1014,56 @@ ba_status ba_pinv_sym(int32_t k, const double *A, double *Ap, int32_t *rank, voi
     return BA_OK;
 }
 
+// ------------------------------------------------------------------ solver buffers
+
+// What Algorithm 1 needs: work vectors, reduction partials, the arrival counter and (for a
+// trace) max_iter doubles of residual history.
+static ba_status pcg_buffers(ba_system *s, int max_iter, bool trace) {
+    const int64_t n = (int64_t)s->np * s->dp;
+    ba_status st;
+    if ((st = ensure_vec(s, (size_t)n * 6 + SC_COUNT)) != BA_OK) return st;
+    // red: scratch partials (the true residual), |r|^2, Phi, the camera reduction's Gram
+    // partials, then the fused iteration end's partials
+    const size_t ngram = 2 * (size_t)gram_parts_max(s), nxz = 2 * (size_t)mcg_xrz_blocks(s->np, s->dp);
+    if ((st = ensure_red(s, (size_t)kRedBlocks * 4 + ngram + nxz)) != BA_OK) return st;
+    if ((st = ensure_tickets(s, 1)) != BA_OK) return st;
+    if (trace && (st = ensure_trace(s, std::max(max_iter, 1))) != BA_OK) return st;
+    return BA_OK;
+}
+
+// What Algorithm 2 with N subsets and a history of `cap` columns needs: the P and Q
+// histories, the small dense storage (Delta^+ blocks, Phi, beta, gamma, alpha, block
+// tables), work vectors, reduction partials, the arrival counter and the split-K scratch
+// of the history products.
+static ba_status mcg_buffers(ba_system *s, int N, int64_t cap) {
+    const int64_t n = (int64_t)s->np * s->dp;
+    if (cap < 1) return fail(BA_ERR_WORKSPACE, "history capacity must hold at least one column");
+    ba_status st;
+    if (s->hist_cap_cols < cap) {
+        double *h = nullptr;
+        if ((st = salloc(s, &h, (size_t)(2 * cap) * (size_t)n)) != BA_OK) return st;
+        sfree(s, s->hist);
+        s->hist = h;
+        s->hist_cap_cols = cap;
+    }
+    const int64_t hc = s->hist_cap_cols;
+    // small storage: Dp (64 * cap), Phi (cap * max(N, kPhiSeg)), beta (cap * hist_ldb(N)), gamma,
+    // alpha (64 each), block tables
+    const size_t small_need = (size_t)(64 * hc + hc * std::max(N, kPhiSeg) + hc * hist_ldb(N) + 128) +
+                              (size_t)(3 * hc + 8);
+    if ((st = grow(s, s->small, s->small_cap, small_need)) != BA_OK) return st;
+    if ((st = ensure_vec(s, (size_t)n * 4 + SC_COUNT)) != BA_OK) return st;
+    // red: the Gram partials of wide blocks, or the iteration-end kernel's partials
+    // followed by the one-column Gram partials of the S product
+    const size_t goff = 2 * (size_t)mcg_xrz_blocks(s->np, s->dp);
+    if ((st = ensure_red(s, std::max<size_t>((size_t)kRedBlocks * (64 * 64 + 64), goff + 2 * (size_t)gram_parts_max(s)))) !=
+        BA_OK)
+        return st;
+    if ((st = ensure_tickets(s, 1)) != BA_OK) return st;   // the iteration-end kernel's
+    // split-K scratch of the history products: at least one column slice of both matrices
+    return grow(s, s->hscratch, s->hscratch_cap, (size_t)std::max<int64_t>(kHistScratch, hist_scratch_min(n, N)));
+}
+
 // ------------------------------------------------------------------ Algorithm 1
 
 // Algorithm 1 on S x = -bt (bt: device [n]).  report_true: also recompute the true
@@ -899,12 +1075,11 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
     if (st != BA_OK) return st;
     const int64_t n = (int64_t)s->np * s->dp;
     hipStream_t q = s->stream;
-    if ((st = ensure_vec(s, (size_t)n * 6 + SC_COUNT)) != BA_OK) return st;
+    const bool want_trace = stats && stats->trace_res && stats->trace_cap > 0;
+    if ((st = pcg_buffers(s, opts.max_iter, want_trace)) != BA_OK) return st;
     // red: scratch partials (pdq: the true residual), |r|^2 (prr), Phi (pphi), the camera reduction's
     // Gram partials (pg), then the fused iteration end's partials (pxz)
-    const size_t ngram = 2 * (size_t)schur_gram_blocks(s->np), nxz = 2 * (size_t)mcg_xrz_blocks(s->np, s->dp);
-    if ((st = ensure_red(s, (size_t)kRedBlocks * 4 + ngram + nxz)) != BA_OK) return st;
-    if ((st = ensure_tickets(s, 1)) != BA_OK) return st;
+    const size_t ngram = 2 * (size_t)gram_parts_max(s);
     double *r = s->vec, *z = r + n, *P = z + n, *Q = P + n, *tmp = Q + n, *sc = tmp + 2 * n;
     double *pdq = s->red, *prr = pdq + kRedBlocks * 2, *pphi = prr + kRedBlocks, *pg = pphi + kRedBlocks;
     double *pxz = pg + ngram;
@@ -930,9 +1105,7 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
         // Iterations are enqueued in batches; the stop test runs on the device and
         // turns the remaining kernels of the batch into no-ops, so the host waits
         // only once per batch.
-        double *trace_dev = nullptr;
-        const bool want_trace = stats && stats->trace_res && stats->trace_cap > 0;
-        if (want_trace && (st = dalloc(&trace_dev, (size_t)opts.max_iter)) != BA_OK) return st;
+        double *trace_dev = want_trace ? s->trace_buf : nullptr;
         const bool lowrank = opts.precond == 1;
         launch_precond(s->np, s->Dchol, r, P, q, s->dp);
         if (lowrank) launch_lowrank_apply(n, s->Ulr, r, P, nullptr, s->lr_proj, nullptr, nullptr, q);
@@ -951,7 +1124,7 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
             for (int b = 0; b < nb; ++b) {
                 matvec(s, sa, P, Q);                                         // Q_i = S P_i; Delta_i, gamma_i
                 const double *dq = pg;
-                const int ndq = schur_gram_blocks(s->np);
+                const int ndq = gram_parts(s, sa);
                 if (!lowrank) {
                     // alpha_i, x_{i+1}, r_{i+1}, the stop test, Z_{i+1}, Phi_i and beta_i
                     launch_pcg_xrz(s->np, dq, ndq, sc, x, r, P, Q, s->Dchol, z, pxz, s->tickets, opts.eps,
@@ -966,14 +1139,8 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
                 }                   // beta_i, P_{i+1}
             }
             enqueued += nb;
-            if (hipGetLastError() != hipSuccess) {
-                dfree(trace_dev);
-                return fail(BA_ERR_HIP, "PCG kernel launch failed");
-            }
-            if ((st = read_scalars(s, sc, h)) != BA_OK) {
-                dfree(trace_dev);
-                return st;
-            }
+            if (hipGetLastError() != hipSuccess) return fail(BA_ERR_HIP, "PCG kernel launch failed");
+            if ((st = read_scalars(s, sc, h)) != BA_OK) return st;
             if (h[SC_DONE] != 0.0 || enqueued >= opts.max_iter) break;
             // next batch: the iterations still needed at the observed rate of decrease
             const double rate = h[SC_RR] > 0.0 && rr_prev > 0.0 ? std::pow(h[SC_RR] / rr_prev, 1.0 / nb) : 1.0;
@@ -999,10 +1166,7 @@ static ba_status pcg_core(ba_system *s, const double *bt, bool report_true, cons
         if (want_trace && it > 0) {
             hipError_t e = hipMemcpy(stats->trace_res, trace_dev, sizeof(double) * (size_t)std::min(it, stats->trace_cap),
                                      hipMemcpyDeviceToHost);
-            dfree(trace_dev);
             if (e != hipSuccess) return fail(BA_ERR_HIP, "trace copy failed");
-        } else {
-            dfree(trace_dev);
         }
     }
     HIPCHK(hipStreamSynchronize(q));
@@ -1035,46 +1199,16 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     const int64_t n = (int64_t)s->np * s->dp;
     hipStream_t q = s->stream;
     const int64_t cap = opts.max_history_cols > 0 ? opts.max_history_cols : 1 + (int64_t)opts.max_iter * N;
-    if (cap < 1) return fail(BA_ERR_WORKSPACE, "history capacity must hold at least one column");
-    if (s->hist_cap_cols < cap) {
-        dfree(s->hist);
-        s->hist_cap_cols = 0;
-        if ((st = dalloc(&s->hist, (size_t)(2 * cap) * (size_t)n)) != BA_OK) return st;
-        s->hist_cap_cols = cap;
-    }
+    if ((st = mcg_buffers(s, N, cap)) != BA_OK) return st;
     const int64_t hc = s->hist_cap_cols;
     double *Ph = s->hist, *Qh = s->hist + hc * n;
-    // small storage: Dp (64 * cap), Phi (cap * max(N, kPhiSeg)), beta (cap * hist_ldb(N)), gamma,
-    // alpha (64 each), block tables
     const int phiw = std::max(N, kPhiSeg);
     const int ldb = hist_ldb(N);
-    const size_t small_need = (size_t)(64 * hc + hc * phiw + hc * ldb + 128) + (size_t)(3 * hc + 8);
-    if (s->small_cap < small_need) {
-        dfree(s->small);
-        s->small_cap = 0;
-        if ((st = dalloc(&s->small, small_need)) != BA_OK) return st;
-        s->small_cap = small_need;
-    }
     double *Dp = s->small, *Phi = Dp + 64 * hc, *beta = Phi + hc * phiw, *gamma = beta + hc * ldb, *alpha = gamma + 64;
     int32_t *blk_off = reinterpret_cast<int32_t *>(alpha + 64);
     int32_t *blk_k = blk_off + hc;
     int64_t *blk_dp = reinterpret_cast<int64_t *>(blk_k + hc + 2);
-    if ((st = ensure_vec(s, (size_t)n * 4 + SC_COUNT)) != BA_OK) return st;
-    // red: the Gram partials of wide blocks, or the iteration-end kernel's partials
-    // followed by the one-column Gram partials of the camera reduction (at goff)
     const size_t goff = 2 * (size_t)mcg_xrz_blocks(s->np, s->dp);
-    if ((st = ensure_red(s, std::max<size_t>((size_t)kRedBlocks * (64 * 64 + 64),
-                                             goff + 2 * (size_t)schur_gram_blocks(s->np)))) != BA_OK)
-        return st;
-    if ((st = ensure_tickets(s, 1)) != BA_OK) return st;   // the iteration-end kernel's
-    // split-K scratch of the history products: at least one column slice of both matrices
-    const int64_t hs_need = std::max<int64_t>(kHistScratch, hist_scratch_min(n, N));
-    if (s->hscratch_cap < hs_need) {
-        dfree(s->hscratch);
-        s->hscratch_cap = 0;
-        if ((st = dalloc(&s->hscratch, (size_t)hs_need)) != BA_OK) return st;
-        s->hscratch_cap = hs_need;
-    }
     double *r = s->vec, *z = r + n, *tmp = z + n, *sc = tmp + 2 * n;
     double *red = s->red;
     const int gs = (s->np / N) * s->dp;   // rows of one subset (Sec. 3.2 partition)
@@ -1135,7 +1269,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             XrzGram g1;
             if (fuse1 && k == 1) {
                 g1.part = red + goff;
-                g1.nb = schur_gram_blocks(s->np);
+                g1.nb = gram_parts(s, sag);
                 g1.Dp = Dp + dpo;
                 g1.blk = be;
             } else {
@@ -1257,7 +1391,7 @@ static ba_status refine(ba_system *s, bool use_mcg, int N, double tau, const dou
     hipStream_t q = s->stream;
     ba_status st = ensure_precision(s, opts.precision);
     if (st != BA_OK) return st;
-    if (!s->refine_buf && (st = dalloc(&s->refine_buf, (size_t)n * 5 + 8)) != BA_OK) return st;
+    if ((st = grow(s, s->refine_buf, s->refine_cap, (size_t)n * 5 + 8)) != BA_OK) return st;
     double *r = s->refine_buf, *btp = r + n, *d = btp + n, *tmp = d + n, *xprev = tmp + n + 8;
     auto t0 = std::chrono::steady_clock::now();
     if (x0) HIPCHK(hipMemcpyAsync(x, x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, q));
@@ -1382,8 +1516,8 @@ static ba_status lowrank_dp_check(const ba_system *s) {
 
 static ba_status ensure_lowrank_storage(ba_system *s) {
     ba_status st;
-    if (!s->Ulr && (st = dalloc(&s->Ulr, (size_t)s->np * 9 * 8)) != BA_OK) return st;
-    if (!s->lr_proj && (st = dalloc(&s->lr_proj, (size_t)kRedBlocks * 8)) != BA_OK) return st;
+    if (!s->Ulr && (st = salloc(s, &s->Ulr, (size_t)s->np * 9 * 8)) != BA_OK) return st;
+    if (!s->lr_proj && (st = salloc(s, &s->lr_proj, (size_t)kRedBlocks * 8)) != BA_OK) return st;
     return BA_OK;
 }
 
@@ -1393,7 +1527,7 @@ ba_status ba_lowrank_features(ba_system *s, float *F) {
     if (!s->degree) {
         std::vector<int32_t> deg;
         covisibility_degree(s->plan, deg);
-        ba_status st = upload(&s->degree, deg, s->stream);
+        ba_status st = supload(s, &s->degree, deg);
         if (st != BA_OK) return st;
         HIPCHK(hipStreamSynchronize(s->stream));
     }
@@ -1434,7 +1568,7 @@ ba_status ba_set_lowrank_precond(ba_system *s, const double *U) {
     if (!s) return fail(BA_ERR_INVALID_ARG, "sys is NULL");
     if (U && lowrank_dp_check(s) != BA_OK) return BA_ERR_UNSUPPORTED;
     if (!U) {
-        dfree(s->Ulr);
+        sfree(s, s->Ulr);
         return BA_OK;
     }
     ba_status st = ensure_lowrank_storage(s);

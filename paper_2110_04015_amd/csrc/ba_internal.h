@@ -168,6 +168,7 @@ struct ba_system {
     int64_t *obs_slot = nullptr;    // tile slot of every observation
     int32_t *bsr_slot_cam = nullptr;// explicit S: camera of every observation slot
     int bsr_max_row = 0;
+    int bsr_piece = 0;              // explicit S: blocks of a row per assembly wavefront
     // solver scratch (allocated on demand)
     double *vec = nullptr;          // work vectors
     size_t vec_cap = 0;
@@ -181,6 +182,13 @@ struct ba_system {
     double *hscratch = nullptr;     // split-K partials of the history products
     int64_t hscratch_cap = 0;       // doubles
     double *refine_buf = nullptr;   // mixed precision: outer residual, inner right-hand side, update
+    size_t refine_cap = 0;
+    double *trace_buf = nullptr;    // PCG residual trace
+    int64_t trace_cap = 0;
+    // caller-owned workspace (ba_build_system_ws): device memory comes from it
+    char *ws_base = nullptr;
+    size_t ws_size = 0, ws_used = 0;
+    bool ws_counting = false;       // sizing pass (ba_build_workspace_bytes): count, allocate nothing
     double *Ulr = nullptr;          // learned low-rank preconditioner term, n x 8 (row-major), or null
     int32_t *degree = nullptr;      // covisibility degree per camera (learned features)
     double *lr_proj = nullptr;      // kRedBlocks x 8 projections U^T r

@@ -105,11 +105,14 @@ __global__ __launch_bounds__(256) void k_bsr_rowfill(int nwords, const int64_t *
     }
 }
 
-// One wavefront per block row j: the row's blocks in LDS; camera j's observations 64 at a
-// time, lane i taking observation o (of landmark l) and adding -W_o V_l^-1 W_q^T into the
-// block of q's camera for every other observation q of l, in slot order.  One wavefront
-// issues all the LDS atomics of a row, so they resolve in program order and, within an
-// instruction, in lane order: the sums are reproducible.  The diagonal block is D(S)_j.
+// One wavefront per (block row j, piece p of at most `piece` of its blocks): the piece's
+// blocks in LDS (and the row's whole column list); camera j's observations 64 at a time,
+// lane i taking observation o (of landmark l) and adding -W_o V_l^-1 W_q^T into the block
+// of q's camera for every other observation q of l whose block lies in the piece, in slot
+// order.  One wavefront issues all the LDS atomics of a block, so they resolve in program
+// order and, within an instruction, in lane order: the sums are reproducible.  Rows wider
+// than one piece (dense S) are assembled by several wavefronts, each re-reading the row's
+// observations.  The diagonal block is D(S)_j.
 __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__ cam_ptr,
                                                      const int64_t *__restrict__ cam_obs,
                                                      const int32_t *__restrict__ obs_lm,
@@ -121,14 +124,18 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
                                                      const double *__restrict__ J64, const double *__restrict__ vinv,
                                                      const double *__restrict__ Dblk,
                                                      const int32_t *__restrict__ row_ptr,
-                                                     const int32_t *__restrict__ col, double *__restrict__ val) {
+                                                     const int32_t *__restrict__ col, double *__restrict__ val,
+                                                     int piece) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int j = blockIdx.x;
     const int lane = threadIdx.x;
     const int b0 = row_ptr[j], nb = row_ptr[j + 1] - b0;
+    const int pb = blockIdx.y * piece;            // first block of this wavefront's piece
+    if (pb >= nb) return;
+    const int pn = min(piece, nb - pb);
     double *acc = reinterpret_cast<double *>(smem);
-    int32_t *rc = reinterpret_cast<int32_t *>(acc + (size_t)nb * 81);
-    for (int e = lane; e < nb * 81; e += 64) acc[e] = 0.0;
+    int32_t *rc = reinterpret_cast<int32_t *>(acc + (size_t)piece * 81);
+    for (int e = lane; e < pn * 81; e += 64) acc[e] = 0.0;
     for (int e = lane; e < nb; e += 64) rc[e] = col[b0 + e];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -158,9 +165,10 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
                 if (rc[mid] < k) lo = mid + 1;
                 else hi = mid;
             }
+            if (lo < pb || lo >= pb + pn) continue;   // another wavefront's piece
             double Wq[27];
             w_of_slot(J64, f + q, Wq);
-            double *blk = acc + (size_t)lo * 81;
+            double *blk = acc + (size_t)(lo - pb) * 81;
 #pragma unroll
             for (int r = 0; r < 9; ++r)
 #pragma unroll
@@ -179,115 +187,113 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
         if (rc[mid] < j) lo = mid + 1;
         else hi = mid;
     }
-    for (int e = lane; e < 81; e += 64) acc[(size_t)lo * 81 + e] = Dblk[(int64_t)j * 81 + e];
+    if (lo >= pb && lo < pb + pn)
+        for (int e = lane; e < 81; e += 64) acc[(size_t)(lo - pb) * 81 + e] = Dblk[(int64_t)j * 81 + e];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int e = lane; e < nb * 81; e += 64) val[(int64_t)b0 * 81 + e] = acc[e];
+    for (int e = lane; e < pn * 81; e += 64) val[(int64_t)(b0 + pb) * 81 + e] = acc[e];
 }
 
-// y_j = sum_t S_(j, col t) v_(col t): one wavefront per block row; lane (t0, r), t0 < 7,
-// r < 9, adds row r of blocks t0, t0 + 7, ... into two running sums (blocks t0 + 14 i
-// and t0 + 7 + 14 i, two blocks in flight); the fourteen partial sums of a row are then
-// added in t0 order.  When `done` is set and nonzero, the launch does nothing.
+// y_j = sum_t S_(j, col t) v_(col t).  One work-group of 256 threads per block row; thread
+// (u, r, c) with u < 3 (243 threads) takes entry (r, c) of blocks u, u + 3, ... of the row,
+// so each step of the work-group reads 3 whole blocks (1,944 contiguous bytes), and keeps
+// four blocks in flight.  The 27 products of each output row r are then added in a fixed
+// order.  With gram, row j also leaves gram[2 j] = y_j . v_j and gram[2 j + 1] = v_j . gr_j
+// (the Gram products Q^T P and P^T r of a one-column block, Q = S P).  When `done` is set
+// and nonzero, the launch does nothing.
 __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
                                                 const double *__restrict__ v, double *__restrict__ y,
                                                 const double *__restrict__ done, double *__restrict__ gram,
                                                 const double *__restrict__ gr) {
     if (done && *done != 0.0) return;
-    __shared__ double sh[4][64];
-    __shared__ double gsum[2][4];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int j = blockIdx.x * 4 + w;
-    double acc = 0.0, acc1 = 0.0;
-    if (j < np && lane < 63) {
-        const int t0 = lane / 9, r = lane - t0 * 9;
+    __shared__ double sh[243];
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (tid < 243) {
+        const int u = tid / 81, rc = tid - u * 81, c = rc % 9;
         const int end = row_ptr[j + 1];
-        int t = row_ptr[j] + t0;
-        for (; t + 7 < end; t += 14) {
-            const double *S = val + (int64_t)t * 81 + r * 9;
-            const double *S1 = S + 7 * 81;
-            const double *vk = v + (int64_t)col[t] * 9;
-            const double *vk1 = v + (int64_t)col[t + 7] * 9;
-#pragma unroll
-            for (int c = 0; c < 9; ++c) {
-                acc += S[c] * vk[c];
-                acc1 += S1[c] * vk1[c];
-            }
+        int t = row_ptr[j] + u;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (; t + 9 < end; t += 12) {
+            const double s0 = __builtin_nontemporal_load(val + (int64_t)t * 81 + rc);
+            const double s1 = __builtin_nontemporal_load(val + (int64_t)(t + 3) * 81 + rc);
+            const double s2 = __builtin_nontemporal_load(val + (int64_t)(t + 6) * 81 + rc);
+            const double s3 = __builtin_nontemporal_load(val + (int64_t)(t + 9) * 81 + rc);
+            a0 += s0 * v[(int64_t)col[t] * 9 + c];
+            a1 += s1 * v[(int64_t)col[t + 3] * 9 + c];
+            a2 += s2 * v[(int64_t)col[t + 6] * 9 + c];
+            a3 += s3 * v[(int64_t)col[t + 9] * 9 + c];
         }
-        if (t < end) {
-            const double *S = val + (int64_t)t * 81 + r * 9;
-            const double *vk = v + (int64_t)col[t] * 9;
-#pragma unroll
-            for (int c = 0; c < 9; ++c) acc += S[c] * vk[c];
-        }
+        for (; t < end; t += 3) a0 += __builtin_nontemporal_load(val + (int64_t)t * 81 + rc) * v[(int64_t)col[t] * 9 + c];
+        sh[tid] = (a0 + a1) + (a2 + a3);
     }
-    sh[w][lane] = acc + acc1;
     __syncthreads();
-    double qp = 0.0, pr = 0.0;
-    if (j < np && lane < 9) {
-        double s = 0.0;
-        for (int t0 = 0; t0 < 7; ++t0) s += sh[w][t0 * 9 + lane];
-        const int64_t i = (int64_t)j * 9 + lane;
-        y[i] = s;
+    if (tid >= 64) return;
+    double yr = 0.0, qp = 0.0, pr = 0.0;
+    if (tid < 9) {
+        for (int u = 0; u < 3; ++u)
+            for (int c = 0; c < 9; ++c) yr += sh[u * 81 + tid * 9 + c];
+        const int64_t i = (int64_t)j * 9 + tid;
+        y[i] = yr;
         if (gram) {
             const double vi = v[i];
-            qp = s * vi;
+            qp = yr * vi;
             pr = vi * gr[i];
         }
     }
     if (!gram) return;   // the same for the whole launch
-    // the partial sums of y^T v and v^T gr over the block's four rows (the Gram products
-    // Q^T P and P^T r of a one-column block, Q = S P), as the camera reduction leaves them
     qp = wave_sum(qp);
     pr = wave_sum(pr);
-    if (lane == 0) {
-        gsum[0][w] = qp;
-        gsum[1][w] = pr;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        gram[2 * blockIdx.x] = (gsum[0][0] + gsum[0][1]) + (gsum[0][2] + gsum[0][3]);
-        gram[2 * blockIdx.x + 1] = (gsum[1][0] + gsum[1][1]) + (gsum[1][2] + gsum[1][3]);
+    if (tid == 0) {
+        gram[2 * j] = qp;
+        gram[2 * j + 1] = pr;
     }
 }
 
 // Y[p][row of j] = sum over blocks t of row j with group(col t) == p of S_(j, col t) z_(col t)
-// (the multidirectional product of eq. (19)'s input): one wavefront per block row,
-// per-subset sums in the wavefront's LDS (one wavefront: program and lane order fixed).
-__global__ __launch_bounds__(64) void k_bsr_mm_grouped(int np, int N, int64_t n, const int32_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ col,
-                                                       const double *__restrict__ val,
-                                                       const int32_t *__restrict__ group,
-                                                       const double *__restrict__ z, double *__restrict__ Y,
-                                                       const double *__restrict__ skip) {
+// (the multidirectional product of eq. (19)'s input).  One work-group of 256 threads per
+// block row, thread (u, r, c) as in k_bsr_mv.  The subsets are ranges of consecutive cameras
+// and a row's columns ascend, so a thread's blocks fall into few subsets in turn: it sums in
+// a register and adds the sum into its wavefront's LDS row of that subset when the subset
+// changes (one wavefront's LDS atomics resolve in program and lane order); the four
+// wavefronts' rows are then added in a fixed order.
+__global__ __launch_bounds__(256) void k_bsr_mm_grouped(int np, int N, int64_t n, const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const double *__restrict__ val,
+                                                        const int32_t *__restrict__ group,
+                                                        const double *__restrict__ z, double *__restrict__ Y,
+                                                        const double *__restrict__ skip) {
     if (skip && *skip != 0.0) return;
-    __shared__ double yl[kMaxBlock * 9];
+    __shared__ double yl[4][kMaxBlock * 9];
     const int j = blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int e = lane; e < N * 9; e += 64) yl[e] = 0.0;
+    const int tid = threadIdx.x, w = tid >> 6;
+    for (int e = tid & 63; e < N * 9; e += 64) yl[w][e] = 0.0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < 63) {
-        const int t0 = lane / 9, r = lane - t0 * 9;
-        for (int t = row_ptr[j] + t0; t < row_ptr[j + 1]; t += 7) {
+    if (tid < 243) {
+        const int u = tid / 81, rc = tid - u * 81, r = rc / 9, c = rc - r * 9;
+        const int end = row_ptr[j + 1];
+        int g = -1;
+        double acc = 0.0;
+        for (int t = row_ptr[j] + u; t < end; t += 3) {
             const int k = col[t];
-            const double *S = val + (int64_t)t * 81 + r * 9;
-            const double *zk = z + (int64_t)k * 9;
-            double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < 9; ++c) s += S[c] * zk[c];
-            atomicAdd(&yl[group[k] * 9 + r], s);
+            const int gk = group[k];
+            if (gk != g) {
+                if (g >= 0) atomicAdd(&yl[w][g * 9 + r], acc);
+                g = gk;
+                acc = 0.0;
+            }
+            acc += __builtin_nontemporal_load(val + (int64_t)t * 81 + rc) * z[(int64_t)k * 9 + c];
         }
+        if (g >= 0) atomicAdd(&yl[w][g * 9 + r], acc);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int e = lane; e < N * 9; e += 64) {
-        const int p = e / 9, r = e - p * 9;
-        Y[(int64_t)p * n + (int64_t)j * 9 + r] = yl[e];
+    __syncthreads();
+    for (int e = tid; e < N * 9; e += 256) {
+        const int p = e / 9, rr = e - p * 9;
+        Y[(int64_t)p * n + (int64_t)j * 9 + rr] = (yl[0][e] + yl[1][e]) + (yl[2][e] + yl[3][e]);
     }
 }
 
@@ -303,24 +309,31 @@ void launch_bsr_rowfill(int np, const BsrGather &g, const int32_t *row_ptr, int3
                        g.obs_lm, g.lmk_store, g.lmk_first_slot, g.lmk_count, g.slot_cam, row_ptr, col);
 }
 
+int bsr_assembly_piece(int max_row, size_t lds_bytes) {
+    const size_t cols = (size_t)max_row * sizeof(int32_t);
+    if (lds_bytes <= cols + 81 * sizeof(double)) return 0;
+    return (int)std::min<size_t>((size_t)max_row, (lds_bytes - cols) / (81 * sizeof(double)));
+}
+
 void launch_bsr_assemble(int np, const BsrGather &g, const int64_t *obs_slot, const double *J64, const double *vinv,
-                         const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, double *val,
-                         hipStream_t s) {
-    const size_t lds = (size_t)max_row * (81 * sizeof(double) + sizeof(int32_t));
-    hipLaunchKernelGGL(k_bsr_assemble, dim3(np), dim3(64), lds, s, g.cam_ptr, g.cam_obs, g.obs_lm, g.lmk_store,
-                       g.lmk_first_slot, g.lmk_count, g.slot_cam, obs_slot, J64, vinv, Dblk, row_ptr, col, val);
+                         const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, int piece,
+                         double *val, hipStream_t s) {
+    const size_t lds = (size_t)piece * 81 * sizeof(double) + (size_t)max_row * sizeof(int32_t);
+    const unsigned pieces = (unsigned)((max_row + piece - 1) / piece);
+    hipLaunchKernelGGL(k_bsr_assemble, dim3(np, pieces), dim3(64), lds, s, g.cam_ptr, g.cam_obs, g.obs_lm,
+                       g.lmk_store, g.lmk_first_slot, g.lmk_count, g.slot_cam, obs_slot, J64, vinv, Dblk, row_ptr,
+                       col, val, piece);
 }
 
 void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,
                    const double *done, hipStream_t s, double *gram, const double *gram_r) {
-    hipLaunchKernelGGL(k_bsr_mv, dim3((np + 3) / 4), dim3(256), 0, s, np, row_ptr, col, val, v, y, done, gram,
-                       gram_r);
+    hipLaunchKernelGGL(k_bsr_mv, dim3(np), dim3(256), 0, s, np, row_ptr, col, val, v, y, done, gram, gram_r);
 }
 
 void launch_bsr_mm_grouped(int np, int N, const int32_t *row_ptr, const int32_t *col, const double *val,
                            const int32_t *group, const double *z, double *Y, hipStream_t s, const double *skip) {
-    hipLaunchKernelGGL(k_bsr_mm_grouped, dim3(np), dim3(64), 0, s, np, N, (int64_t)np * 9, row_ptr, col, val, group, z,
-                       Y, skip);
+    hipLaunchKernelGGL(k_bsr_mm_grouped, dim3(np), dim3(256), 0, s, np, N, (int64_t)np * 9, row_ptr, col, val, group,
+                       z, Y, skip);
 }
 
 }  // namespace ba

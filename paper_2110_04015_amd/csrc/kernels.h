@@ -284,12 +284,19 @@ struct BsrGather {
 // nonzero blocks per block row; then the rows' columns (ascending) at row_ptr
 void launch_bsr_rowcount(int np, const BsrGather &g, int32_t *nnz, hipStream_t s);
 void launch_bsr_rowfill(int np, const BsrGather &g, const int32_t *row_ptr, int32_t *col, hipStream_t s);
-// block values (9 x 9, row-major per block); obs_slot: slot of every observation
+// blocks of a row that one wavefront of the assembly holds in lds_bytes of LDS (with the
+// row's column list); 0 when not even one fits
+int bsr_assembly_piece(int max_row, size_t lds_bytes);
+// block values (9 x 9, row-major per block); obs_slot: slot of every observation; rows are
+// assembled in pieces of at most `piece` blocks (bsr_assembly_piece)
 void launch_bsr_assemble(int np, const BsrGather &g, const int64_t *obs_slot, const double *J64, const double *vinv,
-                         const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, double *val,
-                         hipStream_t s);
+                         const double *Dblk, const int32_t *row_ptr, const int32_t *col, int max_row, int piece,
+                         double *val, hipStream_t s);
+// y = S v; with gram, row j also leaves gram[2 j] = y_j . v_j, gram[2 j + 1] = v_j . gram_r_j
+// (np partial pairs, see bsr_gram_blocks)
 void launch_bsr_mv(int np, const int32_t *row_ptr, const int32_t *col, const double *val, const double *v, double *y,
                    const double *done, hipStream_t s, double *gram = nullptr, const double *gram_r = nullptr);
+inline int bsr_gram_blocks(int np) { return np; }
 void launch_bsr_mm_grouped(int np, int N, const int32_t *row_ptr, const int32_t *col, const double *val,
                            const int32_t *group, const double *z, double *Y, hipStream_t s,
                            const double *skip = nullptr);

@@ -103,3 +103,29 @@ def test_converged_solves(cap, solver, prec):
     res = np.linalg.norm(-bt - o.matvec(_h(x))) / np.linalg.norm(bt)
     assert res < 1.05e-6
     assert abs(res - st.rel_res_true) <= 1e-9
+
+
+def test_explicit_schur_dense_rows(cap):
+    """The explicit S of the dense problem: rows of up to 571 blocks, assembled in pieces."""
+    p, o, g, xs = cap
+    ge = ba.System.from_problem(p, explicit_schur=True)
+    info = ge.explicit_schur_info()
+    assert info["nnz_blocks"] > 0.3 * p.n_cams ** 2
+    v = np.random.default_rng(1).standard_normal(g.n)
+    ref = o.matvec(v)
+    y = _h(ge.matvec(_dev(v)))
+    assert np.abs(y - ref).max() / np.abs(ref).max() < 1e-12
+    assert np.array_equal(y, _h(ge.matvec(_dev(v))))          # run twice, bit for bit
+    Y = _h(ge.matmat_grouped(N, _dev(v)))
+    part = oracle.partition(p.n_cams, N)
+    for q in range(N):
+        zq = np.where(np.repeat(part == q, 9), v, 0.0)
+        rq = o.matvec(zq)
+        assert np.abs(Y[q] - rq).max() <= 1e-12 * np.abs(ref).max()
+    x, st = ge.mcg(N, TAU, eps=0.0, max_iter=8, trace=True)
+    xo, so, tro = o.mcg(N, TAU, eps=0.0, imax=8, trace=True)
+    assert np.array_equal(st.trace_k, tro[:, 2].astype(np.int32))
+    assert np.linalg.norm(_h(x) - xo) / np.linalg.norm(xo) < 1e-9
+    x, st = ge.pcg(eps=1e-10)
+    assert st.status == ba.BA_OK and _energy(o, _h(x), xs) <= 1e-6
+    ge.close()

@@ -101,10 +101,19 @@ def test_solver_iterates(pair):
     assert st.status == ba.BA_OK and st.rel_res_true < 1.05e-6
 
 
-def test_rows_beyond_lds_are_refused():
+def test_rows_beyond_one_wavefront_lds():
+    """Rows wider than one wavefront's LDS (251 blocks) are assembled in pieces by several
+    wavefronts; the products still equal the oracle's operator."""
     p = synth.cap_problem(n_cams=300, n_lms=3000, c_min=30, c_max=40, zipf_s=0.2, seed=7, name="dense300")
     if covis(p).sum(1).max() * (81 * 8 + 4) <= 163840:
         pytest.skip("every row fits in LDS on this problem")
-    with pytest.raises(ba.BAError) as e:
-        ba.System.from_problem(p, explicit_schur=True)
-    assert e.value.status == ba.BA_ERR_UNSUPPORTED
+    o = oracle.System(p)
+    g = ba.System.from_problem(p, explicit_schur=True)
+    v = np.random.default_rng(3).standard_normal(g.n)
+    ref = o.matvec(v)
+    y = g.matvec(torch.from_numpy(v).cuda()).cpu().numpy()
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    x, st = g.pcg(eps=0.0, max_iter=5)
+    xo, so = o.pcg(eps=0.0, imax=5)
+    assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) < 1e-9
+    g.close()
