@@ -167,12 +167,75 @@ __device__ __forceinline__ void fetch_tile(const SchurArgs &a, int t, int lane, 
     for (int q = 0; q < 3; ++q) b.vi[q] = p[q];
 }
 
-// e = J_p v, g_l = sum J_l^T e (LDS), h_l = V_l^-1 g_l, y_c += J_p^T (e - J_l h_l) (LDS).
-// Products are formed in T; the sums g_l and y_c accumulate in FP64 for every
-// precision.  Besides being the more accurate choice, it is the faster one on
-// gfx950: with FP32 LDS accumulators (ds_add_f32) the FP32 product took 370 us on
-// the F-1936-shaped problem, with FP64 ones (ds_add_f64) 131 us.
-template <typename T, int DP>
+// Cross-lane move of a double by a DPP control (lanes whose source lies outside the
+// control's reach, or outside row_mask, read 0).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// Segment layout of a tile's lanes: a landmark's observations occupy consecutive lanes, so
+// each lane's segment is [start, end] of lanes with its landmark index (padding lanes form
+// segments of their own).  up[d] tells whether lane - d still lies in the lane's segment,
+// for the steps of the scan below.
+struct Segs {
+    int end;
+    bool up1, up2, up4, up8, row15, row31;
+};
+
+__device__ __forceinline__ Segs tile_segments(uint32_t mt, int lane) {
+    const int key = mt != kPad ? (int)((mt >> 16) & 63u) : 64 + lane;   // padding: a segment per lane
+    const int prev = __shfl_up(key, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || prev != key);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const int start = 63 - __clzll(heads & upto);
+    const uint64_t above = heads & ~upto;
+    Segs g;
+    g.end = above ? __ffsll((unsigned long long)above) - 2 : 63;
+    g.up1 = lane - 1 >= start;
+    g.up2 = lane - 2 >= start;
+    g.up4 = lane - 4 >= start;
+    g.up8 = lane - 8 >= start;
+    g.row15 = (lane & 16) && start <= (lane & ~15) - 1;   // rows 1, 3 take lane 15 / 47 of the row before
+    g.row31 = lane >= 32 && start <= 31;                  // rows 2, 3 take lane 31
+    return g;
+}
+
+// Sum of x over the lane's segment, returned in every lane of the segment: a segmented
+// inclusive scan (shifts by 1, 2, 4, 8 inside rows of 16 lanes, then the row sums carried
+// across rows by the row broadcasts of lanes 15 and 31), whose segment total at the
+// segment's last lane is read back by every lane of it.  Fixed order: deterministic.
+__device__ __forceinline__ double segment_sum(double x, const Segs &g) {
+    double t;
+    t = dpp_move<0x111>(x);   // row_shr:1
+    if (g.up1) x += t;
+    t = dpp_move<0x112>(x);   // row_shr:2
+    if (g.up2) x += t;
+    t = dpp_move<0x114>(x);   // row_shr:4
+    if (g.up4) x += t;
+    t = dpp_move<0x118>(x);   // row_shr:8
+    if (g.up8) x += t;
+    t = dpp_move<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    if (g.row15) x += t;
+    t = dpp_move<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+    if (g.row31) x += t;
+    return __shfl(x, g.end, 64);
+}
+
+// e = J_p v, g_l = sum J_l^T e, h_l = V_l^-1 g_l, y_c += J_p^T (e - J_l h_l) (LDS).  Products
+// are formed in T; the sums g_l and y_c accumulate in FP64 for every precision.  Besides
+// being the more accurate choice, it is the faster one on gfx950: with FP32 LDS accumulators
+// (ds_add_f32) the FP32 product took 370 us on the F-1936-shaped problem, with FP64 ones
+// (ds_add_f64) 131 us.  Landmark sums: with SEG, segmented sums across the landmark's lanes
+// in registers (no LDS, no wavefront sync; the reduced-precision products, which the LDS
+// work bounds); without, FP64 LDS atomics into a per-landmark row (the FP64 product, which
+// HBM bounds and which keeps three wavefronts per SIMD within its registers).  The camera
+// sums go to LDS, whose atomics one wavefront issues in program order (lane order within
+// an instruction).
+template <typename T, int DP, bool SEG>
 __device__ __forceinline__ void schur_tile(const T (&J)[2 * DP + 6], const dbl2_t (&vi)[3], uint32_t mt, int lane,
                                            const T *vloc, double *yloc, double *gloc) {
     constexpr int L0 = 2 * DP, L1 = 2 * DP + 3;   // J_l rows 0 and 1
@@ -188,19 +251,28 @@ __device__ __forceinline__ void schur_tile(const T (&J)[2 * DP + 6], const dbl2_
         e0 += J[k] * vc[k];
         e1 += J[DP + k] * vc[k];
     }
-    gloc[lane * 3 + 0] = 0;
-    gloc[lane * 3 + 1] = 0;
-    gloc[lane * 3 + 2] = 0;
-    wave_sync();
-    if (valid) {
+    double gs[3];
+    if constexpr (SEG) {
+        const Segs sg = tile_segments(mt, lane);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], (double)(J[L0 + k] * e0 + J[L1 + k] * e1));
+        for (int k = 0; k < 3; ++k) gs[k] = segment_sum(valid ? (double)(J[L0 + k] * e0 + J[L1 + k] * e1) : 0.0, sg);
+    } else {
+        gloc[lane * 3 + 0] = 0;
+        gloc[lane * 3 + 1] = 0;
+        gloc[lane * 3 + 2] = 0;
+        wave_sync();
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[ll * 3 + k], (double)(J[L0 + k] * e0 + J[L1 + k] * e1));
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gs[k] = gloc[ll * 3 + k];
     }
-    wave_sync();
     if (valid) {
         const T w0 = (T)vi[0].x, w1 = (T)vi[0].y, w2 = (T)vi[1].x;
         const T w3 = (T)vi[1].y, w4 = (T)vi[2].x, w5 = (T)vi[2].y;
-        const T g0 = (T)gloc[ll * 3], g1 = (T)gloc[ll * 3 + 1], g2 = (T)gloc[ll * 3 + 2];
+        const T g0 = (T)gs[0], g1 = (T)gs[1], g2 = (T)gs[2];
         const T h0 = w0 * g0 + w1 * g1 + w2 * g2;
         const T h1 = w1 * g0 + w3 * g1 + w4 * g2;
         const T h2 = w2 * g0 + w4 * g1 + w5 * g2;
@@ -209,7 +281,7 @@ __device__ __forceinline__ void schur_tile(const T (&J)[2 * DP + 6], const dbl2_
 #pragma unroll
         for (int k = 0; k < DP; ++k) atomicAdd(&yloc[slot * DP + k], (double)(J[k] * f0 + J[DP + k] * f1));
     }
-    wave_sync();
+    if constexpr (!SEG) wave_sync();   // the landmark rows are reset by the next tile
 }
 
 template <int PREC, typename T, int DP>
@@ -218,9 +290,9 @@ __device__ __forceinline__ void process_tile(const TileBuf<PREC, T, DP> &b, int 
     if constexpr (PREC == 2) {
         T J[2 * DP + 6];
         Stream<2, DP>::template unpack<T>(b.w, J);
-        schur_tile<T, DP>(J, b.vi, b.mt, lane, vloc, yloc, gloc);
+        schur_tile<T, DP, true>(J, b.vi, b.mt, lane, vloc, yloc, gloc);
     } else {
-        schur_tile<T, DP>(b.v, b.vi, b.mt, lane, vloc, yloc, gloc);
+        schur_tile<T, DP, PREC != 0>(b.v, b.vi, b.mt, lane, vloc, yloc, gloc);
     }
 }
 
@@ -233,8 +305,8 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
     if (a.seg_skip && a.seg_skip[a.chunk_seg[blockIdx.x]]) return;
     extern __shared__ __align__(16) unsigned char smem[];
     double *yloc = reinterpret_cast<double *>(smem);
-    double *gloc = yloc + a.max_slots * DP;
-    T *vloc = reinterpret_cast<T *>(gloc + 3 * kTile);
+    double *gloc = yloc + a.max_slots * DP;                                   // FP64: landmark rows
+    T *vloc = reinterpret_cast<T *>(gloc + (PREC == 0 ? 3 * kTile : 0));
     const int chunk = blockIdx.x;
     const int lane = threadIdx.x;
     const int pb = a.chunk_part[chunk];
@@ -356,10 +428,10 @@ __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restri
 
 void launch_schur_chunks(const SchurArgs &a, const double *v, hipStream_t s) {
     if (a.n_chunks > 0) {
-        // FP64 camera rows and landmark sums, v in the product precision
+        // FP64 camera rows (and, for the FP64 product, landmark rows), v in the product precision
         const size_t esz = a.precision == 0 ? sizeof(double) : sizeof(float);
-        const size_t lds =
-            (size_t)(a.max_slots * a.dp + 3 * kTile) * sizeof(double) + (size_t)a.max_slots * a.dp * esz;
+        const size_t lds = (size_t)(a.max_slots * a.dp + (a.precision == 0 ? 3 * kTile : 0)) * sizeof(double) +
+                           (size_t)a.max_slots * a.dp * esz;
         const dim3 g(a.n_chunks), b(kTile);
         if (a.dp == 6) {
             switch (a.precision) {
