@@ -197,7 +197,7 @@ def run_dense(seed, log):
     ge.profile(False)
     ms = kms / max(nl, 1)
     ex["matvec_ms"] = round(ms, 5)
-    ex["matvec_gbs"] = round((ie["bytes"] + ge.n * 8 * 2) / (ms * 1e-3) / 1e9, 1)
+    ex["matvec_gbs"] = round((ie["bytes"] + ge.n * 8 * 2) / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
     for name, f in [("pcg_fp64", lambda: ge.pcg(eps=1e-6, max_iter=1000)),
                     ("mcg_fp64", lambda: ge.mcg(N, tau, eps=1e-6, max_iter=1000))]:
         f()
@@ -235,6 +235,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched-serving workload")
     ap.add_argument("--no-lm", action="store_true", help="skip the LM outer-loop runs")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-Schur (cap571) workload")
+    ap.add_argument("--dense-only", action="store_true", help="profiling mode: only the dense-Schur workload")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="K",
                     help="profiling mode: K S v products (at --precision) and one 1 GiB copy (counter calibration)")
     args = ap.parse_args()
@@ -247,7 +248,7 @@ def main():
     import synth
 
     batch_probs = None
-    if not args.no_batch and not args.matvec_only:
+    if not args.no_batch and not args.matvec_only and not args.dense_only:
         # generated before the GPU is touched: the worker processes are started here
         t = time.time()
         batch_probs = synth.config4(seed=args.seed, workers=16)
@@ -262,6 +263,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(3)
     torch.cuda.set_device(0)
+    if args.dense_only:
+        print(json.dumps({"mode": "dense-only", "dense_schur": run_dense(args.seed, log)}), flush=True)
+        return
     t = time.time()
     p = synth.config1(seed=args.seed)
     log(f"generated {p.name}: {p.n_cams} cameras, {p.n_lms} landmarks, {p.n_obs} observations "

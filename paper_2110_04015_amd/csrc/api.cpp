@@ -230,15 +230,28 @@ inline int gram_parts(const ba_system *s, const SchurArgs &a) {
 }
 inline int gram_parts_max(const ba_system *s) { return std::max(bsr_gram_blocks(s->np), schur_gram_blocks(s->np)); }
 
-// y = S v; with profiling on, the dominant kernel is bracketed by events on the stream
+// Room for one more start/stop pair of profiling events (created on demand, timing only:
+// no system-scope fence, so no L2 writeback at each record); false when none can be made.
+bool profile_room(ba_system *s) {
+    if (s->prof_used + 2 <= s->prof_events.size()) return true;
+    if (s->prof_events.size() >= 4096) profile_flush(s);
+    while (s->prof_used + 2 > s->prof_events.size()) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return false;
+        s->prof_events.push_back(e);
+    }
+    return true;
+}
+
+// y = S v; with profiling on, the dominant kernel (the chunk kernel of the implicit
+// product, or the block-sparse product of an explicit S) is bracketed by events on the
+// stream, on every prof_every-th call
 void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
-    // a sampled launch (every prof_every-th) gets the events
-    const bool sample = s->profiling && (s->prof_calls++ % s->prof_every) == 0;
+    const bool sample = s->profiling && (s->prof_calls++ % s->prof_every) == 0 && profile_room(s);
     if (use_bsr(s, a)) {
-        const bool ev = sample && s->prof_used + 2 <= s->prof_events.size();
-        if (ev) (void)hipEventRecord(s->prof_events[s->prof_used], s->stream);
+        if (sample) (void)hipEventRecord(s->prof_events[s->prof_used], s->stream);
         launch_bsr_mv(s->np, s->bsr_ptr, s->bsr_col, s->bsr_val, v, y, a.done, s->stream, a.gram, a.gram_r);
-        if (ev) {
+        if (sample) {
             (void)hipEventRecord(s->prof_events[s->prof_used + 1], s->stream);
             s->prof_used += 2;
         }
@@ -247,18 +260,6 @@ void matvec(ba_system *s, const SchurArgs &a, const double *v, double *y) {
     if (!sample) {
         launch_schur_matvec(a, v, y, s->stream);
         return;
-    }
-    if (s->prof_used + 2 > s->prof_events.size()) {
-        if (s->prof_events.size() >= 4096) profile_flush(s);
-        while (s->prof_used + 2 > s->prof_events.size()) {
-            hipEvent_t e;
-            // timing only: no system-scope fence (no L2 writeback) at each record
-            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
-                launch_schur_matvec(a, v, y, s->stream);
-                return;
-            }
-            s->prof_events.push_back(e);
-        }
     }
     (void)hipEventRecord(s->prof_events[s->prof_used], s->stream);
     launch_schur_chunks(a, v, s->stream);

@@ -2,6 +2,12 @@
 // paper's own representation of S (Sec. 3.2, "Optimized implementation": S_jk is
 // nonzero iff cameras j and k observe a common point; Sec. 4.1 forms it as a
 // row-major sparse matrix).
+//
+// Value layout of block row j (nb blocks, starting at block b0 = row_ptr[j]): the 81 nb
+// values at val + 81 b0 are stored row-of-the-block-major, [r][t][c] = S_(j, col t)[r][c]
+// at r (9 nb) + 9 t + c.  Each of the nine rows r of the block row is then one contiguous
+// run of 9 nb values, multiplied entry by entry with the same gathered vector
+// (v_(col t))_c, which the products load once for all nine.
 //   S_jj = D(S)_j                                   (already formed by the build)
 //   S_jk = - sum_{l observed by j and k} W_jl V_l^-1 W_kl^T,   W_jl = J_p,jl^T J_l,jl
 // Assembly: one wavefront per block row j holds the row's blocks in LDS and adds the
@@ -192,49 +198,58 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int e = lane; e < pn * 81; e += 64) val[(int64_t)(b0 + pb) * 81 + e] = acc[e];
+    // out in the row-of-the-block-major layout: run r holds 9 nb values
+    const int64_t L = (int64_t)nb * 9;
+    double *out = val + (int64_t)b0 * 81;
+    for (int e = lane; e < pn * 81; e += 64) {
+        const int t = e / 81, rc = e - t * 81, r = rc / 9, c = rc - r * 9;
+        out[r * L + (int64_t)(pb + t) * 9 + c] = acc[e];
+    }
 }
 
 // y_j = sum_t S_(j, col t) v_(col t).  One work-group of 256 threads per block row; thread
-// (u, r, c) with u < 3 (243 threads) takes entry (r, c) of blocks u, u + 3, ... of the row,
-// so each step of the work-group reads 3 whole blocks (1,944 contiguous bytes), and keeps
-// four blocks in flight.  The 27 products of each output row r are then added in a fixed
-// order.  With gram, row j also leaves gram[2 j] = y_j . v_j and gram[2 j + 1] = v_j . gr_j
-// (the Gram products Q^T P and P^T r of a one-column block, Q = S P).  When `done` is set
-// and nonzero, the launch does nothing.
+// i takes positions e = i, i + 256, ... of the row's 9 nb entries per block row r (block t
+// = e / 9, column c = e % 9): it gathers (v_(col t))_c once and multiplies it with the nine
+// entries S[r][e], which the work-group reads as nine coalesced runs.  Each output row r
+// is added over the lanes of a wavefront, then over the four wavefronts in a fixed order.
+// With gram, row j also leaves gram[2 j] = y_j . v_j and gram[2 j + 1] = v_j . gr_j (the
+// Gram products Q^T P and P^T r of a one-column block, Q = S P).  When `done` is set and
+// nonzero, the launch does nothing.
 __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
                                                 const double *__restrict__ v, double *__restrict__ y,
                                                 const double *__restrict__ done, double *__restrict__ gram,
                                                 const double *__restrict__ gr) {
     if (done && *done != 0.0) return;
-    __shared__ double sh[243];
+    __shared__ double sh[4][9];
     const int j = blockIdx.x;
-    const int tid = threadIdx.x;
-    if (tid < 243) {
-        const int u = tid / 81, rc = tid - u * 81, c = rc % 9;
-        const int end = row_ptr[j + 1];
-        int t = row_ptr[j] + u;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (; t + 9 < end; t += 12) {
-            const double s0 = __builtin_nontemporal_load(val + (int64_t)t * 81 + rc);
-            const double s1 = __builtin_nontemporal_load(val + (int64_t)(t + 3) * 81 + rc);
-            const double s2 = __builtin_nontemporal_load(val + (int64_t)(t + 6) * 81 + rc);
-            const double s3 = __builtin_nontemporal_load(val + (int64_t)(t + 9) * 81 + rc);
-            a0 += s0 * v[(int64_t)col[t] * 9 + c];
-            a1 += s1 * v[(int64_t)col[t + 3] * 9 + c];
-            a2 += s2 * v[(int64_t)col[t + 6] * 9 + c];
-            a3 += s3 * v[(int64_t)col[t + 9] * 9 + c];
-        }
-        for (; t < end; t += 3) a0 += __builtin_nontemporal_load(val + (int64_t)t * 81 + rc) * v[(int64_t)col[t] * 9 + c];
-        sh[tid] = (a0 + a1) + (a2 + a3);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int b0 = row_ptr[j];
+    const int L = (row_ptr[j + 1] - b0) * 9;
+    const double *S = val + (int64_t)b0 * 81;
+    const int32_t *cj = col + b0;
+    double acc[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) acc[r] = 0.0;
+    for (int e = tid; e < L; e += 256) {
+        const int t = e / 9;
+        const double vg = v[(int64_t)cj[t] * 9 + (e - t * 9)];
+        double sv[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) sv[r] = __builtin_nontemporal_load(S + (int64_t)r * L + e);
+#pragma unroll
+        for (int r = 0; r < 9; ++r) acc[r] += sv[r] * vg;
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+        const double t = wave_sum(acc[r]);
+        if (lane == 0) sh[w][r] = t;
     }
     __syncthreads();
     if (tid >= 64) return;
     double yr = 0.0, qp = 0.0, pr = 0.0;
     if (tid < 9) {
-        for (int u = 0; u < 3; ++u)
-            for (int c = 0; c < 9; ++c) yr += sh[u * 81 + tid * 9 + c];
+        yr = (sh[0][tid] + sh[1][tid]) + (sh[2][tid] + sh[3][tid]);
         const int64_t i = (int64_t)j * 9 + tid;
         y[i] = yr;
         if (gram) {
@@ -254,11 +269,11 @@ __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restric
 
 // Y[p][row of j] = sum over blocks t of row j with group(col t) == p of S_(j, col t) z_(col t)
 // (the multidirectional product of eq. (19)'s input).  One work-group of 256 threads per
-// block row, thread (u, r, c) as in k_bsr_mv.  The subsets are ranges of consecutive cameras
-// and a row's columns ascend, so a thread's blocks fall into few subsets in turn: it sums in
-// a register and adds the sum into its wavefront's LDS row of that subset when the subset
-// changes (one wavefront's LDS atomics resolve in program and lane order); the four
-// wavefronts' rows are then added in a fixed order.
+// block row, positions as in k_bsr_mv.  The subsets are ranges of consecutive cameras and a
+// row's columns ascend, so a thread's positions fall into few subsets in turn: it sums the
+// nine rows in registers and adds them into its wavefront's LDS rows of that subset when
+// the subset changes (one wavefront's LDS atomics resolve in program and lane order); the
+// four wavefronts' rows are then added in a fixed order.
 __global__ __launch_bounds__(256) void k_bsr_mm_grouped(int np, int N, int64_t n, const int32_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ col,
                                                         const double *__restrict__ val,
@@ -273,22 +288,35 @@ __global__ __launch_bounds__(256) void k_bsr_mm_grouped(int np, int N, int64_t n
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (tid < 243) {
-        const int u = tid / 81, rc = tid - u * 81, r = rc / 9, c = rc - r * 9;
-        const int end = row_ptr[j + 1];
-        int g = -1;
-        double acc = 0.0;
-        for (int t = row_ptr[j] + u; t < end; t += 3) {
-            const int k = col[t];
-            const int gk = group[k];
-            if (gk != g) {
-                if (g >= 0) atomicAdd(&yl[w][g * 9 + r], acc);
-                g = gk;
-                acc = 0.0;
+    const int b0 = row_ptr[j];
+    const int L = (row_ptr[j + 1] - b0) * 9;
+    const double *S = val + (int64_t)b0 * 81;
+    const int32_t *cj = col + b0;
+    int g = -1;
+    double acc[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) acc[r] = 0.0;
+    for (int e = tid; e < L; e += 256) {
+        const int t = e / 9;
+        const int k = cj[t];
+        const int gk = group[k];
+        if (gk != g) {
+            if (g >= 0) {
+#pragma unroll
+                for (int r = 0; r < 9; ++r) {
+                    atomicAdd(&yl[w][g * 9 + r], acc[r]);
+                    acc[r] = 0.0;
+                }
             }
-            acc += __builtin_nontemporal_load(val + (int64_t)t * 81 + rc) * z[(int64_t)k * 9 + c];
+            g = gk;
         }
-        if (g >= 0) atomicAdd(&yl[w][g * 9 + r], acc);
+        const double zg = z[(int64_t)k * 9 + (e - t * 9)];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) acc[r] += __builtin_nontemporal_load(S + (int64_t)r * L + e) * zg;
+    }
+    if (g >= 0) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) atomicAdd(&yl[w][g * 9 + r], acc[r]);
     }
     __syncthreads();
     for (int e = tid; e < N * 9; e += 256) {
