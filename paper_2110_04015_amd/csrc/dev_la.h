@@ -1,6 +1,7 @@
 // Device linear algebra shared by the FP64 solver kernels: fixed-order block
 // reductions, the 9x9 block-Jacobi solve, and the LDS pseudo-inverse of the k x k
-// Gram matrices of Algorithm 2 (Cholesky fast path, Jacobi eigendecomposition).
+// Gram matrices of Algorithm 2 (a Gauss-Jordan inverse when a norm bound proves that no
+// eigenvalue lies below the pseudo-inverse's threshold, else a Jacobi eigendecomposition).
 #pragma once
 #include <hip/hip_runtime.h>
 

@@ -500,6 +500,10 @@ struct MultiBuf {
     uint32_t obase;           // tile_oidx of the tile
 };
 
+// The reduced-precision products sum each pair across its lanes (a pair's observations
+// occupy consecutive lanes: a landmark's slots are in camera order and the subsets are
+// ranges of consecutive cameras), so every lane takes V^-1 of its own observation's
+// landmark; the FP64 product forms h of pair p on lane p, from V^-1 of that pair's landmark.
 template <int PREC, typename T, int DP>
 __device__ __forceinline__ void fetch_mtile(const MultiArgs &a, const double *__restrict__ z, int t, int lane,
                                             const MultiSlot &m, MultiBuf<PREC, T, DP> &b) {
@@ -509,7 +513,13 @@ __device__ __forceinline__ void fetch_mtile(const MultiArgs &a, const double *__
     const double *zc = z + (int64_t)(valid ? m.cam : 0) * DP;
 #pragma unroll
     for (int k = 0; k < DP; ++k) b.z[k] = zc[k];
-    const int ll = m.pll != 0xFFu ? (int)m.pll : 0;
+    int ll;
+    if constexpr (PREC != 0) {
+        const uint32_t mt = a.meta[(int64_t)t * kTile + lane];
+        ll = mt != kPad ? (int)((mt >> 16) & 63u) : 0;
+    } else {
+        ll = m.pll != 0xFFu ? (int)m.pll : 0;
+    }
     const dbl2_t *p = reinterpret_cast<const dbl2_t *>(a.vinv + (int64_t)(a.tile_lmk_base[t] + ll) * 6);
 #pragma unroll
     for (int q = 0; q < 3; ++q) b.vi[q] = p[q];
@@ -517,9 +527,12 @@ __device__ __forceinline__ void fetch_mtile(const MultiArgs &a, const double *__
 }
 
 // One tile: e = J_p z_c; g per (landmark, subset) pair = sum over the pair's
-// observations of J_l^T e (LDS); h = V^-1 g on the pair's lane; every observation of
-// the landmark adds J_p^T (e [own pair] - J_l h_pair) to its (camera, pair subset) row.
-template <typename T, int DP>
+// observations of J_l^T e; h = V^-1 g; every observation of the landmark adds
+// J_p^T (e [own pair] - J_l h_pair) to its (camera, pair subset) row.  With SEG (the
+// reduced-precision products) g is a segmented sum across the pair's lanes in registers
+// and the pair's last lane publishes h; without, g goes through FP64 LDS atomics and lane
+// p forms h of pair p.
+template <typename T, int DP, bool SEG>
 __device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[2 * DP + 6], const double (&zb)[DP],
                                            const dbl2_t (&vi)[3], const MultiSlot &m, uint32_t obase, int lane,
                                            double *yloc, double *gloc, double *hloc) {
@@ -532,22 +545,36 @@ __device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[2 * 
         e1 += J[DP + k] * (T)zb[k];
     }
     const int own = (int)(m.mm & 0xFFu);
-    gloc[lane * 3 + 0] = 0;
-    gloc[lane * 3 + 1] = 0;
-    gloc[lane * 3 + 2] = 0;
-    wave_sync();
-    if (valid) {
+    const T w0 = (T)vi[0].x, w1 = (T)vi[0].y, w2 = (T)vi[1].x;
+    const T w3 = (T)vi[1].y, w4 = (T)vi[2].x, w5 = (T)vi[2].y;
+    if constexpr (SEG) {
+        // segments: the pairs (own pair index), padding lanes one each
+        const Segs sg = tile_segments(valid ? (uint32_t)own << 16 : kPad, lane);
+        double gs[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], (double)(J[L0 + k] * e0 + J[L1 + k] * e1));
-    }
-    wave_sync();
-    if (m.pll != 0xFFu) {
-        const T w0 = (T)vi[0].x, w1 = (T)vi[0].y, w2 = (T)vi[1].x;
-        const T w3 = (T)vi[1].y, w4 = (T)vi[2].x, w5 = (T)vi[2].y;
-        const T g0 = (T)gloc[lane * 3], g1 = (T)gloc[lane * 3 + 1], g2 = (T)gloc[lane * 3 + 2];
-        hloc[lane * 3 + 0] = (double)(w0 * g0 + w1 * g1 + w2 * g2);
-        hloc[lane * 3 + 1] = (double)(w1 * g0 + w3 * g1 + w4 * g2);
-        hloc[lane * 3 + 2] = (double)(w2 * g0 + w4 * g1 + w5 * g2);
+        for (int k = 0; k < 3; ++k) gs[k] = segment_sum(valid ? (double)(J[L0 + k] * e0 + J[L1 + k] * e1) : 0.0, sg);
+        if (valid && sg.end == lane) {
+            const T g0 = (T)gs[0], g1 = (T)gs[1], g2 = (T)gs[2];
+            hloc[own * 3 + 0] = (double)(w0 * g0 + w1 * g1 + w2 * g2);
+            hloc[own * 3 + 1] = (double)(w1 * g0 + w3 * g1 + w4 * g2);
+            hloc[own * 3 + 2] = (double)(w2 * g0 + w4 * g1 + w5 * g2);
+        }
+    } else {
+        gloc[lane * 3 + 0] = 0;
+        gloc[lane * 3 + 1] = 0;
+        gloc[lane * 3 + 2] = 0;
+        wave_sync();
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) atomicAdd(&gloc[own * 3 + k], (double)(J[L0 + k] * e0 + J[L1 + k] * e1));
+        }
+        wave_sync();
+        if (m.pll != 0xFFu) {
+            const T g0 = (T)gloc[lane * 3], g1 = (T)gloc[lane * 3 + 1], g2 = (T)gloc[lane * 3 + 2];
+            hloc[lane * 3 + 0] = (double)(w0 * g0 + w1 * g1 + w2 * g2);
+            hloc[lane * 3 + 1] = (double)(w1 * g0 + w3 * g1 + w4 * g2);
+            hloc[lane * 3 + 2] = (double)(w2 * g0 + w4 * g1 + w5 * g2);
+        }
     }
     wave_sync();
     if (valid) {
@@ -576,9 +603,9 @@ __device__ __forceinline__ void process_mtile(const MultiArgs &a, const MultiBuf
     if constexpr (PREC == 2) {
         T J[2 * DP + 6];
         Stream<2, DP>::template unpack<T>(b.r.w, J);
-        multi_tile<T, DP>(a, J, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
+        multi_tile<T, DP, true>(a, J, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
     } else {
-        multi_tile<T, DP>(a, b.r.v, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
+        multi_tile<T, DP, PREC != 0>(a, b.r.v, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
     }
 }
 

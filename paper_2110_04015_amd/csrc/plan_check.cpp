@@ -119,6 +119,10 @@ bool check_multi(const HostPlan &P, const HostMultiPlan &M, const int32_t *cam) 
                 uint8_t pll = M.pair_ll[(size_t)((int64_t)t * kTile + own)];
                 if (pll != (P.meta[s] >> 16)) return bad("pair landmark", t, own);
                 if (pair_grp[(size_t)own] >= 0 && pair_grp[(size_t)own] != group[(size_t)c]) return bad("pair group", t, own);
+                // a pair's slots are consecutive (the reduced-precision products sum a pair
+                // across its lanes): a pair seen before continues the previous slot's pair
+                if (pair_grp[(size_t)own] >= 0 && (q == 0 || P.slot_obs[s - 1] < 0 || (M.mmeta[s - 1] & 0xFF) != (uint32_t)own))
+                    return bad("pair slots not consecutive", t, q);
                 pair_grp[(size_t)own] = group[(size_t)c];
             }
             for (int q = 0; q < kTile; ++q) {
