@@ -1061,8 +1061,9 @@ static ba_status mcg_buffers(ba_system *s, int N, int64_t cap) {
         BA_OK)
         return st;
     if ((st = ensure_tickets(s, 1)) != BA_OK) return st;   // the iteration-end kernel's
-    // split-K scratch of the history products: at least one column slice of both matrices
-    return grow(s, s->hscratch, s->hscratch_cap, (size_t)std::max<int64_t>(kHistScratch, hist_scratch_min(n, N)));
+    // split-K scratch of the history products: four column slices of both matrices of the
+    // widest block (at least one is required)
+    return grow(s, s->hscratch, s->hscratch_cap, (size_t)std::max<int64_t>(kHistScratch, 4 * hist_scratch_min(n, N)));
 }
 
 // ------------------------------------------------------------------ Algorithm 1

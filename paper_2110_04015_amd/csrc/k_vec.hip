@@ -958,10 +958,18 @@ __device__ inline void hist_slice(int64_t n, int64_t row, int c0, int c1, int kn
         if (p0 + j < kn) out[(int64_t)(p0 + j) * n + row] = acc[j];
 }
 
-// grid (row tiles, slices, 2 * zb): z < zb the P history, z >= zb the Q history (used by
-// multidirectional blocks only); zb output blocks of KBW columns (KBW = 16 or 32)
+// Column slices of the history products for the block width the device chose: a
+// one-column block (P only, one output) splits the history into many more slices than a
+// multidirectional one, whose kn partial outputs per slice fill the scratch much sooner.
+struct HistSlices {
+    int one, one_cols;     // kn == 1
+    int multi, multi_cols; // kn > 1
+};
+
+// grid (row tiles, max slices, 2 * zb): z < zb the P history, z >= zb the Q history (used
+// by multidirectional blocks only); zb output blocks of KBW columns (KBW = 16 or 32)
 template <int KBW>
-__global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, int slice_cols, int nslices, int zb,
+__global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, HistSlices hs, int zb,
                                                      const double *__restrict__ Ph, const double *__restrict__ Qh,
                                                      const double *__restrict__ beta, const double *__restrict__ sc,
                                                      int kn_max, double *__restrict__ scratch) {
@@ -969,7 +977,10 @@ __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, int slice
     const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int mat = (int)blockIdx.z / zb, p0 = ((int)blockIdx.z - mat * zb) * KBW;
     if (kn == 0 || row >= n || p0 >= kn || (mat == 1 && kn == 1)) return;
+    const int nslices = kn == 1 ? hs.one : hs.multi;
+    const int slice_cols = kn == 1 ? hs.one_cols : hs.multi_cols;
     const int ks = blockIdx.y;
+    if (ks >= nslices) return;
     const int c0 = ks * slice_cols;
     const int c1 = min(h, c0 + slice_cols);
     double *out = scratch + ((int64_t)mat * nslices + ks) * kn * n;
@@ -980,12 +991,13 @@ __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, int slice
 // y = 0 (mat0 = 0): P_new from the P slices; mat0 = 1: Q_new from the Q slices
 // (multidirectional blocks only, their base Y = S Z already in the Q columns); no
 // slices: P_new = Z_p
-__global__ void k_hist_final(int64_t n, int nslices, const double *__restrict__ scratch,
+__global__ void k_hist_final(int64_t n, HistSlices hs, const double *__restrict__ scratch,
                              const double *__restrict__ z, int gs, int N, const double *__restrict__ sc, int kn_max,
                              int mat, double *__restrict__ Pn, double *__restrict__ Qn) {
     const int kn = next_kn(sc, kn_max);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (kn == 0 || i >= n * kn || (mat == 1 && kn == 1)) return;
+    const int nslices = kn == 1 ? hs.one : hs.multi;
     const int p = (int)(i / n);
     const int64_t row = i - (int64_t)p * n;
     const double *sp = scratch + (int64_t)mat * nslices * kn * n;
@@ -1002,17 +1014,28 @@ __global__ void k_hist_final(int64_t n, int nslices, const double *__restrict__ 
     out[i] = base - s;
 }
 
-// column slices of the history products: enough (row tile, slice) wavefronts to fill the
-// device, at least 16 columns each, and both matrices' partials of a kn_max-wide block
-// within the scratch (the caller guarantees room for one slice)
-int hist_slices(int64_t n, int h, int kn_max, int64_t scratch_doubles) {
+// column slices of the history products for a block of width kn: enough (row tile, slice)
+// wavefronts to fill the device, at least 16 columns each, and the partials of a
+// kn-wide block (both matrices) within the scratch (the caller guarantees room for one
+// slice of the widest block)
+int hist_slices(int64_t n, int h, int kn, int64_t scratch_doubles) {
     const int64_t tiles = (n + 63) / 64;
     int s = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
     s = std::min(s, std::max(1, h / 16));
     s = std::min(s, 64);
-    const int64_t per = 2 * (int64_t)kn_max * n;
+    const int64_t per = 2 * (int64_t)kn * n;
     if (per > 0) s = (int)std::max<int64_t>(1, std::min<int64_t>(s, scratch_doubles / per));
     return std::max(1, s);
+}
+
+static HistSlices hist_slicing(int64_t n, int h, int kn_max, int64_t scratch_doubles) {
+    HistSlices hs{0, 1, 0, 1};
+    if (h <= 0) return hs;
+    hs.one = hist_slices(n, h, 1, scratch_doubles);
+    hs.one_cols = (h + hs.one - 1) / hs.one;
+    hs.multi = hist_slices(n, h, std::max(kn_max, 1), scratch_doubles);
+    hs.multi_cols = (h + hs.multi - 1) / hs.multi;
+    return hs;
 }
 
 int64_t hist_scratch_min(int64_t n, int kn_max) { return 2 * (int64_t)kn_max * n; }
@@ -1021,30 +1044,30 @@ void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, con
                       const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
                       hipStream_t s) {
     if (kn_max <= 0) return;
-    const int slices = h > 0 ? hist_slices(n, h, kn_max, scratch_doubles) : 0;
+    const HistSlices hs = hist_slicing(n, h, kn_max, scratch_doubles);
     if (h > 0) {
-        const int slice_cols = (h + slices - 1) / slices;
         const unsigned tiles = (unsigned)((n + 63) / 64);
+        const unsigned ys = (unsigned)std::max(hs.one, hs.multi);
         if (kn_max <= 16) {
-            hipLaunchKernelGGL((k_hist_partial<16>), dim3(tiles, slices, 2), dim3(64), 0, s, n, h, slice_cols, slices,
-                               1, Ph, Qh, beta, sc, kn_max, scratch);
+            hipLaunchKernelGGL((k_hist_partial<16>), dim3(tiles, ys, 2), dim3(64), 0, s, n, h, hs, 1, Ph, Qh, beta, sc,
+                               kn_max, scratch);
         } else {
             const int zb = (kn_max + 31) / 32;
-            hipLaunchKernelGGL((k_hist_partial<32>), dim3(tiles, slices, 2 * zb), dim3(64), 0, s, n, h, slice_cols,
-                               slices, zb, Ph, Qh, beta, sc, kn_max, scratch);
+            hipLaunchKernelGGL((k_hist_partial<32>), dim3(tiles, ys, 2 * zb), dim3(64), 0, s, n, h, hs, zb, Ph, Qh,
+                               beta, sc, kn_max, scratch);
         }
     }
     const int64_t tot = n * kn_max;
-    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, slices, scratch, z, gs,
-                       N, sc, kn_max, 0, Pn, nullptr);
+    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, hs, scratch, z, gs, N,
+                       sc, kn_max, 0, Pn, nullptr);
 }
 
 void launch_update_q(int64_t n, int h, int N, const double *sc, double *Qn, const double *scratch,
                      int64_t scratch_doubles, hipStream_t s) {
-    const int slices = h > 0 ? hist_slices(n, h, N, scratch_doubles) : 0;
+    const HistSlices hs = hist_slicing(n, h, N, scratch_doubles);
     const int64_t tot = n * N;
-    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, slices, scratch,
-                       nullptr, 0, N, sc, N, 1, nullptr, Qn);
+    hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, hs, scratch, nullptr, 0,
+                       N, sc, N, 1, nullptr, Qn);
 }
 
 }  // namespace ba
