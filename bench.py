@@ -231,6 +231,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--history-mfma", action="store_true",
+                    help="MCG history products of blocks wider than 16 columns on the FP64 matrix cores")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched-serving workload")
     ap.add_argument("--no-lm", action="store_true", help="skip the LM outer-loop runs")
@@ -313,7 +315,7 @@ def main():
     def step(precision=args.precision, solver=args.solver, N=args.N, tau=args.tau):
         if solver == "pcg":
             return g.pcg(eps=1e-6, max_iter=1000, precision=precision)
-        return g.mcg(N, tau, eps=1e-6, max_iter=1000, precision=precision)
+        return g.mcg(N, tau, eps=1e-6, max_iter=1000, precision=precision, history_mfma=args.history_mfma)
 
     for i in range(args.warmup):
         x, st = step()
@@ -527,7 +529,8 @@ def main():
                    "tau": args.tau if args.solver == "mcg" else None, "eps": 1e-6,
                    "iterations": st.iterations, "multi_steps": st.multi_steps,
                    "rel_res_true": st.rel_res_true, "build_s": round(build_s, 3),
-                   "mcg_plan_s": None if plan_s is None else round(plan_s, 3)},
+                   "mcg_plan_s": None if plan_s is None else round(plan_s, 3),
+                   "history_products": "fp64 matrix cores" if args.history_mfma else "vector FMA"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,

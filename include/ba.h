@@ -100,7 +100,9 @@ typedef struct {
     int32_t precision;       /* ba_precision used for the S products (FP64 default) */
     int32_t precond;         /* 0: block Jacobi D(S); 1: block Jacobi plus the low-rank term set by
                                 ba_set_lowrank_precond */
-    int32_t reserved0;
+    int32_t history_mfma;    /* MCG: 1 runs the history products of multidirectional blocks wider
+                                than 16 columns (P_{i+1} = Z - sum_j P_j beta_ij and eq. (19)) on the
+                                FP64 matrix cores instead of vector FMAs (0, measured faster) */
     int64_t max_history_cols;/* MCG history capacity in columns (0 = 1 + max_iter * N) */
     double inner_eps;        /* mixed precision: inner tolerance relative to the outer residual
                                 (0 = automatic: 1e-2 for FP32 products, 1e-1 for BF16 storage) */

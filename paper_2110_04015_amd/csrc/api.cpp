@@ -1054,10 +1054,10 @@ static ba_status mcg_buffers(ba_system *s, int N, int64_t cap) {
                               (size_t)(3 * hc + 8);
     if ((st = grow(s, s->small, s->small_cap, small_need)) != BA_OK) return st;
     if ((st = ensure_vec(s, (size_t)n * 4 + SC_COUNT)) != BA_OK) return st;
-    // red: the Gram partials of wide blocks, or the iteration-end kernel's partials
-    // followed by the one-column Gram partials of the S product
+    // red: the Gram partials of wide blocks and their sums, or the iteration-end kernel's
+    // partials followed by the one-column Gram partials of the S product
     const size_t goff = 2 * (size_t)mcg_xrz_blocks(s->np, s->dp);
-    if ((st = ensure_red(s, std::max<size_t>((size_t)kRedBlocks * (64 * 64 + 64), goff + 2 * (size_t)gram_parts_max(s)))) !=
+    if ((st = ensure_red(s, std::max<size_t>((size_t)(kRedBlocks + 1) * (64 * 64 + 64), goff + 2 * (size_t)gram_parts_max(s)))) !=
         BA_OK)
         return st;
     if ((st = ensure_tickets(s, 1)) != BA_OK) return st;   // the iteration-end kernel's
@@ -1307,7 +1307,8 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             launch_phi(n, (int)hcols, Qh, z, N, gs, Phi, q);
             // beta_{i,j} = Delta_j^+ Phi_{i,j}; P_{i+1} = Z - sum P_j beta
             launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, sc, kn_max, N, beta, q);
-            launch_update_pq(n, (int)hcols, N, kn_max, Ph, Qh, beta, z, gs, sc, Pn, s->hscratch, s->hscratch_cap, q);
+            launch_update_pq(n, (int)hcols, N, kn_max, Ph, Qh, beta, z, gs, sc, Pn, s->hscratch, s->hscratch_cap, q,
+                             opts.history_mfma != 0);
             bool spec_pair = false;   // the product's profiling events, dropped if it is skipped
             if (room1) {   // one-column block: Q_{i+1} = S P_{i+1}
                 SchurArgs s1 = sag;

@@ -194,61 +194,70 @@ __device__ __forceinline__ double block_sum_waves(double v, double *sh) {
     return s;
 }
 
-// Inverse of the symmetric k x k matrix A (k <= 64, LDS) into G by Gauss-Jordan
-// elimination on the diagonal pivots, every element updated in parallel (element w by
-// thread w mod kNT).  With pivot p = a_jj the step replaces a_jj by 1 / p, the rest of
-// row j by a_jc / p, the rest of column j by -a_ij / p and every other element by
-// a_ic - a_ij a_jc / p; after the k steps the matrix is A^-1, which is then symmetrised.
-// The steps alternate between G and V (one barrier each), and the thread that computes
-// the next pivot also leaves its reciprocal, so no step waits for a division.  Returns
-// (the same in every thread) whether every pivot was positive (A positive definite) and
-// |A|_F |A^-1|_F < 1e-4 / (k eps): then every eigenvalue lies above the drop threshold
-// k eps max|l| (l_min >= 1 / |A^-1|_F, l_max <= |A|_F), so A^+ = A^-1.
-__device__ __forceinline__ bool inv_gj(int k, const double *A, double *G, double *V, double *sh) {
+// Value of v in lane l of the wavefront (l wave-uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Gauss-Jordan inversion of the k x k matrix A (k <= KP, LDS, row-major) by one
+// wavefront, held in registers: lane c keeps column c of A padded to KP x KP with the
+// identity.  Step j, pivot p = a_jj, replaces a_jj by 1 / p, the rest of row j by
+// a_jc / p, the rest of column j by -a_ij / p and every other element by
+// a_ic - a_ij (a_jc / p).  Column j is broadcast from lane j (readlane) and row j is kept
+// in register 0 of every lane: each step moves register i to i - 1 and the new pivot row
+// to register KP - 1, so after the k steps register r holds row (r + k) mod KP.  The
+// result goes to G (row-major k x k); *bad is set when a pivot is not positive.
+template <int KP>
+__device__ __forceinline__ void gj_wave(int k, const double *A, double *G, int *bad) {
+    const int c = threadIdx.x & 63;
+    double col[KP];
+#pragma unroll
+    for (int i = 0; i < KP; ++i) col[i] = (i < k && c < k) ? A[i * k + c] : (i == c ? 1.0 : 0.0);
+    bool nonpos = false;
+    for (int j = 0; j < k; ++j) {
+        const double p = readlane_f64(col[0], j);
+        nonpos |= !(p > 0.0);
+        const double ip = 1.0 / (p > 0.0 ? p : 1.0);
+        const bool piv = c == j;
+        const double t = (piv ? 1.0 : col[0]) * ip;
+#pragma unroll
+        for (int i = 1; i < KP; ++i) {
+            const double aij = readlane_f64(col[i], j);
+            col[i - 1] = (piv ? 0.0 : col[i]) - aij * t;
+        }
+        col[KP - 1] = t;
+    }
+    if (c < k) {
+#pragma unroll
+        for (int r = 0; r < KP; ++r) {
+            int row = r + k;
+            row -= row >= KP ? KP : 0;
+            if (row < k) G[row * k + c] = col[r];
+        }
+    }
+    if (c == 0) *bad = nonpos;
+}
+
+// Inverse of the symmetric k x k matrix A (k <= 64, LDS) into G: Gauss-Jordan elimination
+// on the diagonal pivots by the first wavefront (gj_wave), then the result is
+// symmetrised by the whole block.  Returns (the same in every thread) whether every
+// pivot was positive (A positive definite) and |A|_F |A^-1|_F < 1e-4 / (k eps): then
+// every eigenvalue lies above the drop threshold k eps max|l| (l_min >= 1 / |A^-1|_F,
+// l_max <= |A|_F), so A^+ = A^-1.
+__device__ __forceinline__ bool inv_gj(int k, const double *A, double *G, double *sh) {
     constexpr int U = kMaxK * kMaxK / kNT;   // elements per thread at most
-    __shared__ double ipv[2];
     __shared__ int nonpos;
     const int tid = threadIdx.x;
     const int kk = k * k;
-    int ri[U], ci[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int w = tid + u * kNT;
-        ri[u] = w / k;
-        ci[u] = w - ri[u] * k;
-    }
-    if (tid == 0) {
-        const double p0 = A[0];
-        nonpos = !(p0 > 0.0);
-        ipv[0] = 1.0 / (p0 > 0.0 ? p0 : 1.0);
+    if (tid < 64) {
+        if (k <= 16) gj_wave<16>(k, A, G, &nonpos);
+        else if (k <= 32) gj_wave<32>(k, A, G, &nonpos);
+        else gj_wave<64>(k, A, G, &nonpos);
     }
     __syncthreads();
-    const double *X = A;
-    double *Y = G;
-    for (int j = 0; j < k; ++j) {
-        const double ip = ipv[j & 1];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int w = tid + u * kNT;
-            if (w < kk) {
-                const int i = ri[u], c = ci[u];
-                const double aij = X[i * k + j], ajc = X[j * k + c];
-                double v;
-                if (i == j) v = (c == j) ? ip : ajc * ip;
-                else if (c == j) v = -aij * ip;
-                else v = X[w] - aij * ajc * ip;
-                Y[w] = v;
-                if (i == j + 1 && c == j + 1) {   // the next pivot
-                    if (!(v > 0.0)) nonpos = 1;
-                    ipv[(j + 1) & 1] = 1.0 / (v > 0.0 ? v : 1.0);
-                }
-            }
-        }
-        __syncthreads();
-        X = Y;
-        Y = (Y == G) ? V : G;
-    }
-    // X holds A^-1 (G when k is odd, V when even)
     double fa = 0.0, fi = 0.0;
     double sym[U];
 #pragma unroll
@@ -256,7 +265,8 @@ __device__ __forceinline__ bool inv_gj(int k, const double *A, double *G, double
         const int w = tid + u * kNT;
         sym[u] = 0.0;
         if (w < kk) {
-            sym[u] = 0.5 * (X[w] + X[ci[u] * k + ri[u]]);
+            const int i = w / k, c = w - i * k;
+            sym[u] = 0.5 * (G[w] + G[c * k + i]);
             fa += A[w] * A[w];
             fi += sym[u] * sym[u];
         }
@@ -279,7 +289,7 @@ __device__ __forceinline__ bool inv_gj(int k, const double *A, double *G, double
 __device__ __forceinline__ void pinv_sym_lds(int k, const double *A, double *V, double *G, double *sh, double *cs, double *sn,
                              int *flag, int *rank_sh) {
     const int tid = threadIdx.x;
-    if (inv_gj(k, A, G, V, sh)) {
+    if (inv_gj(k, A, G, sh)) {
         if (tid == 0) *rank_sh = k;
         __syncthreads();
         return;

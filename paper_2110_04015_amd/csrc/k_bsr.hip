@@ -207,6 +207,38 @@ __global__ __launch_bounds__(64) void k_bsr_assemble(const int64_t *__restrict__
     }
 }
 
+// Loads of kBsrAhead positions e0 + 256 u of a block row (its nine runs of L values at S,
+// columns cj): the nine values sv[u][r] = S[r L + e] and the gathered vector entry
+// vg[u] = v[9 col(e / 9) + e mod 9]; with group, also gk[u] = group[col(e / 9)].
+// Positions at or beyond L read nothing and give zeros.
+constexpr int kBsrAhead = 4;
+
+__device__ __forceinline__ void bsr_fetch(const double *__restrict__ S, const int32_t *__restrict__ cj,
+                                          const double *__restrict__ v, int L, int e0, double (&sv)[kBsrAhead][9],
+                                          double (&vg)[kBsrAhead], const int32_t *__restrict__ group = nullptr,
+                                          int *gk = nullptr) {
+    int k[kBsrAhead], c[kBsrAhead];
+#pragma unroll
+    for (int u = 0; u < kBsrAhead; ++u) {
+        const int e = e0 + u * 256;
+        const int t = e < L ? e / 9 : 0;
+        c[u] = e - t * 9;
+        k[u] = cj[t];
+    }
+#pragma unroll
+    for (int u = 0; u < kBsrAhead; ++u) {
+        const int e = e0 + u * 256;
+#pragma unroll
+        for (int r = 0; r < 9; ++r) sv[u][r] = e < L ? S[(int64_t)r * L + e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBsrAhead; ++u) {
+        const bool ok = e0 + u * 256 < L;
+        vg[u] = ok ? v[(int64_t)k[u] * 9 + c[u]] : 0.0;
+        if (group) gk[u] = group[k[u]];
+    }
+}
+
 // y_j = sum_t S_(j, col t) v_(col t).  One work-group of 256 threads per block row; thread
 // i takes positions e = i, i + 256, ... of the row's 9 nb entries per block row r (block t
 // = e / 9, column c = e % 9): it gathers (v_(col t))_c once and multiplies it with the nine
@@ -231,14 +263,15 @@ __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restric
     double acc[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) acc[r] = 0.0;
-    for (int e = tid; e < L; e += 256) {
-        const int t = e / 9;
-        const double vg = v[(int64_t)cj[t] * 9 + (e - t * 9)];
-        double sv[9];
+    // kBsrAhead positions per trip (e0, e0 + 256, ...), all their loads issued before the
+    // first multiply; each thread still adds its positions in ascending order
+    for (int e0 = tid; e0 < L; e0 += kBsrAhead * 256) {
+        double sv[kBsrAhead][9], vg[kBsrAhead];
+        bsr_fetch(S, cj, v, L, e0, sv, vg);
 #pragma unroll
-        for (int r = 0; r < 9; ++r) sv[r] = __builtin_nontemporal_load(S + (int64_t)r * L + e);
+        for (int u = 0; u < kBsrAhead; ++u)
 #pragma unroll
-        for (int r = 0; r < 9; ++r) acc[r] += sv[r] * vg;
+            for (int r = 0; r < 9; ++r) acc[r] += sv[u][r] * vg[u];
     }
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
@@ -296,23 +329,26 @@ __global__ __launch_bounds__(256) void k_bsr_mm_grouped(int np, int N, int64_t n
     double acc[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) acc[r] = 0.0;
-    for (int e = tid; e < L; e += 256) {
-        const int t = e / 9;
-        const int k = cj[t];
-        const int gk = group[k];
-        if (gk != g) {
-            if (g >= 0) {
+    for (int e0 = tid; e0 < L; e0 += kBsrAhead * 256) {
+        double sv[kBsrAhead][9], zg[kBsrAhead];
+        int gk[kBsrAhead];
+        bsr_fetch(S, cj, z, L, e0, sv, zg, group, gk);
 #pragma unroll
-                for (int r = 0; r < 9; ++r) {
-                    atomicAdd(&yl[w][g * 9 + r], acc[r]);
-                    acc[r] = 0.0;
+        for (int u = 0; u < kBsrAhead; ++u) {
+            if (e0 + u * 256 >= L) break;
+            if (gk[u] != g) {
+                if (g >= 0) {
+#pragma unroll
+                    for (int r = 0; r < 9; ++r) {
+                        atomicAdd(&yl[w][g * 9 + r], acc[r]);
+                        acc[r] = 0.0;
+                    }
                 }
+                g = gk[u];
             }
-            g = gk;
-        }
-        const double zg = z[(int64_t)k * 9 + (e - t * 9)];
 #pragma unroll
-        for (int r = 0; r < 9; ++r) acc[r] += __builtin_nontemporal_load(S + (int64_t)r * L + e) * zg;
+            for (int r = 0; r < 9; ++r) acc[r] += sv[u][r] * zg[u];
+        }
     }
     if (g >= 0) {
 #pragma unroll

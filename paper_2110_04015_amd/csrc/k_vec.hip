@@ -457,8 +457,94 @@ __global__ __launch_bounds__(kNT) void k_gram(int64_t n, int k, int R, const dou
     }
 }
 
+// k >= 16: the same partials with the k x k part on the matrix cores.  Delta's 16 x 16
+// tiles (k padded to a multiple of 16) are dealt to the four wavefronts; for each 4 rows of
+// a staged chunk a wavefront issues one v_mfma_f64_16x16x4f64 per tile, with
+// A[i][kk] = Q[row kk][a0 + i] and B[kk][j] = P[row kk][c0 + j] read from LDS (lane l
+// supplies element (l mod 16, l / 16) of A and (l / 16, l mod 16) of B, and holds
+// D[l / 16 + 4 e][l mod 16] in accumulator e).  P^T r stays on the vector units.
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kNT) void k_gram_mfma(int64_t n, int k, int R, const double *__restrict__ P,
+                                                   const double *__restrict__ Q, const double *__restrict__ r,
+                                                   double *__restrict__ partials) {
+    extern __shared__ double gsm[];
+    double *sP = gsm, *sQ = gsm + (int64_t)R * k, *sr = sQ + (int64_t)R * k;
+    const int tot = k * k + k;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int T = (k + 15) / 16;
+    const int li = lane & 15, lk = lane >> 4;
+    dbl4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+    double gacc = 0.0;
+    const int64_t lo = n * blockIdx.x / gridDim.x, hi = n * (blockIdx.x + 1) / gridDim.x;
+    for (int64_t r0 = lo; r0 < hi; r0 += R) {
+        const int rows = (int)(hi - r0 < R ? hi - r0 : R);
+#pragma unroll 4
+        for (int w = tid; w < rows * k; w += kNT) {
+            const int a = w / rows, rr = w - a * rows;   // consecutive threads: consecutive rows of column a
+            sP[rr * k + a] = P[(int64_t)a * n + r0 + rr];
+            sQ[rr * k + a] = Q[(int64_t)a * n + r0 + rr];
+        }
+        for (int rr = tid; rr < rows; rr += kNT) sr[rr] = r[r0 + rr];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int tt = wv + 4 * t;
+            if (tt < T * T) {
+                const int a = (tt / T) * 16 + li, c = (tt - (tt / T) * T) * 16 + li;
+                for (int rr = 0; rr < rows; rr += 4) {
+                    const int row = rr + lk;
+                    const double av = (row < rows && a < k) ? sQ[row * k + a] : 0.0;
+                    const double bv = (row < rows && c < k) ? sP[row * k + c] : 0.0;
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+                }
+            }
+        }
+        if (tid < k)
+            for (int rr = 0; rr < rows; ++rr) gacc += sP[rr * k + tid] * sr[rr];
+        __syncthreads();
+    }
+    double *out = partials + (int64_t)blockIdx.x * tot;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int tt = wv + 4 * t;
+        if (tt < T * T) {
+            const int c = (tt - (tt / T) * T) * 16 + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int a = (tt / T) * 16 + lk + 4 * e;
+                if (a < k && c < k) out[a * k + c] = acc[t][e];
+            }
+        }
+    }
+    if (tid < k) out[k * k + tid] = gacc;
+}
+
+// sums[idx] = sum over b < nb of partials[b][idx] (idx < tot), one thread per output in
+// a fixed order: eight running sums over batches of 24 blocks (24 loads in flight), the
+// remainder into the first, then a fixed tree.  Spread over many work-groups, so the
+// k (k + 1) sums of a wide block do not wait on one work-group's load latency.
+__global__ __launch_bounds__(64) void k_gram_sum(int tot, int nb, const double *__restrict__ partials,
+                                                 double *__restrict__ sums) {
+    const int idx = blockIdx.x * 64 + threadIdx.x;
+    if (idx >= tot) return;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = 0;
+    for (; b + 24 <= nb; b += 24) {
+        double v[24];
+#pragma unroll
+        for (int u = 0; u < 24; ++u) v[u] = partials[(int64_t)(b + u) * tot + idx];
+#pragma unroll
+        for (int u = 0; u < 24; ++u) acc[u & 7] += v[u];
+    }
+    for (; b < nb; ++b) acc[0] += partials[(int64_t)b * tot + idx];
+    sums[idx] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 // blocks of the Gram partials: wider blocks have k (k + 1) outputs per block, so fewer
-// blocks keep the pseudo-inverse kernel's sum over them short
+// blocks keep the sum over them short
 int gram_blocks(int k) { return k == 1 ? kRedBlocks : kGramBlocksWide; }
 
 void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
@@ -472,11 +558,16 @@ void launch_gram(int64_t n, int k, const double *P, const double *Q, const doubl
     const int64_t cap = kGramLds / (int64_t)((2 * k + 1) * sizeof(double));
     const int R = (int)std::max<int64_t>(1, std::min(per, cap));
     const size_t lds = (size_t)R * (2 * k + 1) * sizeof(double);
-    hipLaunchKernelGGL(k_gram, dim3(nb), dim3(kNT), lds, s, n, k, R, P, Q, r, partials);
+    if (k >= 16) hipLaunchKernelGGL(k_gram_mfma, dim3(nb), dim3(kNT), lds, s, n, k, R, P, Q, r, partials);
+    else hipLaunchKernelGGL(k_gram, dim3(nb), dim3(kNT), lds, s, n, k, R, P, Q, r, partials);
+    const int tot = k * k + k;
+    hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, s, tot, nb, partials,
+                       partials + (int64_t)nb * tot);
 }
 
-// Delta (symmetrised) and gamma from the Gram partials; Delta^+; alpha = Delta^+ gamma
-__global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restrict__ partials, int nblocks,
+// Delta (symmetrised) and gamma from the Gram sums (sums[a k + c], then gamma at k k + a);
+// Delta^+; alpha = Delta^+ gamma
+__global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restrict__ sums,
                                                     double *__restrict__ Dp, double *__restrict__ gamma,
                                                     double *__restrict__ alpha, double *__restrict__ sc,
                                                     BlockEntry blk) {
@@ -485,32 +576,10 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
     __shared__ int flag, rank;
     const int tid = threadIdx.x;
     const int tot = k * k + k;
-    if (tot <= 2 * (kNT / 64)) {
-        // few outputs: one wavefront per output, all partials of an output loaded at once
-        for (int idx = tid >> 6; idx < tot; idx += kNT / 64) {
-            const double s = wave_partials(partials + idx, tot, nblocks);
-            if ((tid & 63) == 0) {
-                if (idx < k * k) G[idx] = s;
-                else gam[idx - k * k] = s;
-            }
-        }
-    } else {
-        for (int idx = tid; idx < tot; idx += kNT) {
-            // eight running sums; 24 loads in flight per thread
-            double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int b = 0;
-            for (; b + 24 <= nblocks; b += 24) {
-                double v[24];
-#pragma unroll
-                for (int u = 0; u < 24; ++u) v[u] = partials[(int64_t)(b + u) * tot + idx];
-#pragma unroll
-                for (int u = 0; u < 24; ++u) acc[u & 7] += v[u];
-            }
-            for (; b < nblocks; ++b) acc[0] += partials[(int64_t)b * tot + idx];
-            const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-            if (idx < k * k) G[idx] = s;
-            else gam[idx - k * k] = s;
-        }
+    for (int idx = tid; idx < tot; idx += kNT) {
+        const double s = sums[idx];
+        if (idx < k * k) G[idx] = s;
+        else gam[idx - k * k] = s;
     }
     __syncthreads();
     for (int w = tid; w < k * k; w += kNT) {
@@ -563,7 +632,8 @@ void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, d
     if (k == 1)
         hipLaunchKernelGGL(k_pinv_alpha1, dim3(1), dim3(64), 0, s, partials, nblocks, Dp, gamma, alpha, sc, blk);
     else
-        hipLaunchKernelGGL(k_pinv_alpha, dim3(1), dim3(kNT), 0, s, k, partials, nblocks, Dp, gamma, alpha, sc, blk);
+        hipLaunchKernelGGL(k_pinv_alpha, dim3(1), dim3(kNT), 0, s, k, partials + (int64_t)nblocks * (k * k + k), Dp,
+                           gamma, alpha, sc, blk);
 }
 
 // Stand-alone symmetric pseudo-inverse (test entry point).
@@ -872,40 +942,114 @@ __device__ inline int next_kn(const double *__restrict__ sc, int kn_max) {
 }
 
 // beta rows of history block j: beta[off_j + a][p] = sum_b Delta_j^+[a][b] Phi[off_j + b][p]
-// for the next block's width kn (next_kn); rows of hist_ldb(kn) values
+// for the next block's width kn (next_kn); rows of hist_ldb(kn) values.  One work-group
+// per history block.  A block wider than one column first stages Delta_j^+ (transposed)
+// and its Phi rows in LDS with coalesced loads; each output is then one running sum over
+// b in ascending order, taken from LDS (a multidirectional block's outputs in 4 x 4 tiles
+// per thread).  For a one-column Z, Phi of a history column is the sum of its segments,
+// one wavefront butterfly per column.
 __global__ __launch_bounds__(kNT) void k_beta(const int32_t *__restrict__ blk_off, const int32_t *__restrict__ blk_k,
                                               const int64_t *__restrict__ blk_dp, const double *__restrict__ Dp,
                                               const double *__restrict__ Phi, const double *__restrict__ sc,
                                               int kn_max, int seg, double *__restrict__ beta) {
-    __shared__ double f1[kMaxK];
+    __shared__ double sDt[kMaxK * kMaxK];   // sDt[b * kj + a] = Delta_j^+[a][b]
+    __shared__ double sF[kMaxK * kMaxK];    // sF[b * kn + p] = Phi[off + b][p] (kn > 1; kn == 1: all seg values)
     const int kn = next_kn(sc, kn_max);
     if (kn == 0) return;
     const int j = blockIdx.x;
     const int off = blk_off[j], kj = blk_k[j];
     const double *D = Dp + blk_dp[j];
-    if (kn == 1) {   // one-column Z: Phi of column off + b is the sum of its segments, in order
-        for (int b = threadIdx.x; b < kj; b += kNT) {
-            const double *ph = Phi + (int64_t)(off + b) * seg;
-            double f = 0.0;
-            for (int g = 0; g < seg; ++g) f += ph[g];
-            f1[b] = f;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    if (kj == 1) {   // a one-column history block: Delta^+ is a scalar
+        const double d = D[0];
+        if (kn == 1) {   // one-column Z: Phi of the column is the sum of its seg <= 64 segments
+            if (tid < 64) {
+                const double f = wave_sum(lane < seg ? Phi[(int64_t)off * seg + lane] : 0.0);
+                if (lane == 0) beta[off] = d * f;
+            }
+            return;
+        }
+        const int ldb = hist_ldb(kn);
+        for (int p = tid; p < ldb; p += kNT) beta[(int64_t)off * ldb + p] = p < kn ? d * Phi[(int64_t)off * seg + p] : 0.0;
+        return;
+    }
+    // staging: every load of a thread is issued before its first LDS store (at most
+    // kMaxK * kMaxK / kNT = 16 of each)
+    constexpr int SU = kMaxK * kMaxK / kNT;
+    {
+        double v[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int w = tid + u * kNT;
+            v[u] = w < kj * kj ? D[w] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int w = tid + u * kNT;
+            if (w < kj * kj) {
+                const int a = w / kj, b = w - a * kj;
+                sDt[b * kj + a] = v[u];
+            }
+        }
+    }
+    const int fcols = kn == 1 ? seg : kn;   // Phi values staged per history column
+    {
+        double v[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int w = tid + u * kNT;
+            const int b = w / fcols, p = w - b * fcols;
+            v[u] = w < kj * fcols ? Phi[(int64_t)(off + b) * seg + p] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int w = tid + u * kNT;
+            if (w < kj * fcols) sF[w] = v[u];
+        }
+    }
+    __syncthreads();
+    if (kn == 1) {   // one-column Z: Phi of column off + b is the sum of its segments (one wavefront each)
+        __shared__ double f1[kMaxK];
+        for (int b = tid >> 6; b < kj; b += kNT / 64) {
+            const double f = wave_sum(lane < seg ? sF[b * seg + lane] : 0.0);
+            if (lane == 0) f1[b] = f;
         }
         __syncthreads();
-        for (int a = threadIdx.x; a < kj; a += kNT) {
+        for (int a = tid; a < kj; a += kNT) {
             double s = 0.0;
-            for (int b = 0; b < kj; ++b) s += D[a * kj + b] * f1[b];
+            for (int b = 0; b < kj; ++b) s += sDt[b * kj + a] * f1[b];
             beta[off + a] = s;
         }
         return;
     }
     // multidirectional: segment p is subset p; rows are padded with zeros to hist_ldb(kn)
     const int ldb = hist_ldb(kn);
-    for (int w = threadIdx.x; w < kj * ldb; w += kNT) {
-        const int a = w / ldb, p = w - a * ldb;
-        double s = 0.0;
-        if (p < kn)
-            for (int b = 0; b < kj; ++b) s += D[a * kj + b] * Phi[(int64_t)(off + b) * seg + p];
-        beta[(int64_t)(off + a) * ldb + p] = s;
+    const int ta = (kj + 3) / 4, tp = ldb / 4;
+    for (int t = tid; t < ta * tp; t += kNT) {
+        const int a0 = (t / tp) * 4, p0 = (t - (t / tp) * tp) * 4;
+        double acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+        for (int b = 0; b < kj; ++b) {
+            double dv[4], fv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dv[u] = a0 + u < kj ? sDt[b * kj + a0 + u] : 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) fv[v] = p0 + v < kn ? sF[b * kn + p0 + v] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += dv[u] * fv[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (a0 + u >= kj) break;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) beta[(int64_t)(off + a0 + u) * ldb + p0 + v] = acc[u][v];
+        }
     }
 }
 
@@ -921,7 +1065,8 @@ void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int
 // ahead of the host's read-back of the tau-test.  Pass 1: one wavefront per (64-row tile,
 // column slice, matrix, block of outputs) accumulates its slice; beta is wave-uniform
 // (scalar loads) and its rows, hist_ldb(kn) long, are padded with zeros, so the inner
-// loops carry no per-output test.  Pass 2 adds the slices in slice order and subtracts
+// loops carry no per-output test; blocks wider than 16 columns take the matrix-core path
+// (hist_slice_mfma).  Pass 2 adds the slices in slice order and subtracts
 // from the base, so the result is independent of scheduling.
 template <int KB>
 __device__ inline void hist_slice(int64_t n, int64_t row, int c0, int c1, int kn, int p0,
@@ -958,6 +1103,59 @@ __device__ inline void hist_slice(int64_t n, int64_t row, int c0, int c1, int kn
         if (p0 + j < kn) out[(int64_t)(p0 + j) * n + row] = acc[j];
 }
 
+// The same sums for a multidirectional block on the matrix cores: one wavefront covers 64
+// rows x 32 outputs (8 tiles of 16 x 16) of its column slice; for every 4 history columns
+// it issues one v_mfma_f64_16x16x4f64 per tile with A[i][kk] = H[row0 + 16 m + i][c + kk]
+// and B[kk][j] = beta[c + kk][p0 + 16 q + j] (lane layouts as in the Gram kernel),
+// 4 kHistMG columns' loads in flight.  Rows past n and columns past c1 load zeros.
+constexpr int kHistMG = 2;   // groups of 4 history columns per loop trip
+__device__ inline void hist_slice_mfma(int64_t n, int64_t row0, int c0, int c1, int kn, int p0,
+                                       const double *__restrict__ H, const double *__restrict__ beta,
+                                       double *__restrict__ out) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int ldb = hist_ldb(kn);
+    dbl4_t acc[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[m][q] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+    for (int c = c0; c < c1; c += 4 * kHistMG) {
+        double hv[kHistMG][4], bv[kHistMG][2];
+#pragma unroll
+        for (int g = 0; g < kHistMG; ++g) {
+            const int col = c + 4 * g + lk;
+            const bool okc = col < c1;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int64_t row = row0 + 16 * m + li;
+                hv[g][m] = (okc && row < n) ? H[(int64_t)col * n + row] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int p = p0 + 16 * q + li;
+                bv[g][q] = (okc && p < ldb) ? beta[(int64_t)col * ldb + p] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kHistMG; ++g)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(hv[g][m], bv[g][q], acc[m][q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = row0 + 16 * m + lk + 4 * e;
+                const int p = p0 + 16 * q + li;
+                if (row < n && p < kn) out[(int64_t)p * n + row] = acc[m][q][e];
+            }
+}
+
 // Column slices of the history products for the block width the device chose: a
 // one-column block (P only, one output) splits the history into many more slices than a
 // multidirectional one, whose kn partial outputs per slice fill the scratch much sooner.
@@ -967,7 +1165,10 @@ struct HistSlices {
 };
 
 // grid (row tiles, max slices, 2 * zb): z < zb the P history, z >= zb the Q history (used
-// by multidirectional blocks only); zb output blocks of KBW columns (KBW = 16 or 32)
+// by multidirectional blocks only); zb output blocks of KBW columns.  KBW = 16: blocks of
+// any width up to 16; KBW = 32: one-column blocks only (wider ones are left to
+// k_hist_wide, launched beside it, so that this kernel keeps few registers and many
+// wavefronts in flight for the one-column blocks, the most frequent).
 template <int KBW>
 __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, HistSlices hs, int zb,
                                                      const double *__restrict__ Ph, const double *__restrict__ Qh,
@@ -976,7 +1177,7 @@ __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, HistSlice
     const int kn = next_kn(sc, kn_max);
     const int64_t row = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int mat = (int)blockIdx.z / zb, p0 = ((int)blockIdx.z - mat * zb) * KBW;
-    if (kn == 0 || row >= n || p0 >= kn || (mat == 1 && kn == 1)) return;
+    if (kn == 0 || row >= n || p0 >= kn || (mat == 1 && kn == 1) || (KBW == 32 && kn > 1)) return;
     const int nslices = kn == 1 ? hs.one : hs.multi;
     const int slice_cols = kn == 1 ? hs.one_cols : hs.multi_cols;
     const int ks = blockIdx.y;
@@ -985,7 +1186,30 @@ __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, HistSlice
     const int c1 = min(h, c0 + slice_cols);
     double *out = scratch + ((int64_t)mat * nslices + ks) * kn * n;
     if (kn == 1) hist_slice<1>(n, row, c0, c1, 1, 0, Ph, beta, out);
-    else hist_slice<KBW>(n, row, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
+    else if (KBW == 16) hist_slice<16>(n, row, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
+}
+
+// Multidirectional blocks wider than 16 columns: 32-output blocks of the same grid and
+// outputs as k_hist_partial<32>, with vector FMAs (MFMA = false: hist_slice<32>, beta
+// from scalar loads) or on the matrix cores (MFMA = true: hist_slice_mfma; every lane of
+// a wavefront takes part, rows past n load zeros); one-column blocks return at once.
+template <bool MFMA>
+__global__ __launch_bounds__(64) void k_hist_wide(int64_t n, int h, HistSlices hs, int zb,
+                                                  const double *__restrict__ Ph, const double *__restrict__ Qh,
+                                                  const double *__restrict__ beta, const double *__restrict__ sc,
+                                                  int kn_max, double *__restrict__ scratch) {
+    const int kn = next_kn(sc, kn_max);
+    const int mat = (int)blockIdx.z / zb, p0 = ((int)blockIdx.z - mat * zb) * 32;
+    if (kn <= 1 || p0 >= kn) return;
+    const int ks = blockIdx.y;
+    if (ks >= hs.multi) return;
+    const int64_t row0 = (int64_t)blockIdx.x * 64;
+    if (!MFMA && row0 + threadIdx.x >= n) return;
+    const int c0 = ks * hs.multi_cols;
+    const int c1 = min(h, c0 + hs.multi_cols);
+    double *out = scratch + ((int64_t)mat * hs.multi + ks) * kn * n;
+    if (MFMA) hist_slice_mfma(n, row0, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
+    else hist_slice<32>(n, row0 + threadIdx.x, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
 }
 
 // y = 0 (mat0 = 0): P_new from the P slices; mat0 = 1: Q_new from the Q slices
@@ -1042,7 +1266,7 @@ int64_t hist_scratch_min(int64_t n, int kn_max) { return 2 * (int64_t)kn_max * n
 
 void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, const double *Qh, const double *beta,
                       const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
-                      hipStream_t s) {
+                      hipStream_t s, bool mfma) {
     if (kn_max <= 0) return;
     const HistSlices hs = hist_slicing(n, h, kn_max, scratch_doubles);
     if (h > 0) {
@@ -1053,8 +1277,14 @@ void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, con
                                kn_max, scratch);
         } else {
             const int zb = (kn_max + 31) / 32;
-            hipLaunchKernelGGL((k_hist_partial<32>), dim3(tiles, ys, 2 * zb), dim3(64), 0, s, n, h, hs, zb, Ph, Qh,
+            hipLaunchKernelGGL((k_hist_partial<32>), dim3(tiles, hs.one, 1), dim3(64), 0, s, n, h, hs, zb, Ph, Qh,
                                beta, sc, kn_max, scratch);
+            if (mfma)
+                hipLaunchKernelGGL(k_hist_wide<true>, dim3(tiles, hs.multi, 2 * zb), dim3(64), 0, s, n, h, hs, zb,
+                                   Ph, Qh, beta, sc, kn_max, scratch);
+            else
+                hipLaunchKernelGGL(k_hist_wide<false>, dim3(tiles, hs.multi, 2 * zb), dim3(64), 0, s, n, h, hs, zb,
+                                   Ph, Qh, beta, sc, kn_max, scratch);
         }
     }
     const int64_t tot = n * kn_max;

@@ -184,7 +184,8 @@ void launch_pcg_xrz(int np, const double *pdq, int npdq, double *sc, double *x, 
 void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s);
 
 // MCG steps
-// partials[b][...] of b < gram_blocks(k) blocks
+// partials[b][...] of b < gram_blocks(k) blocks; with k > 1 their sums follow them, at
+// partials + gram_blocks(k) (k k + k)
 int gram_blocks(int k);
 void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
                  hipStream_t s);
@@ -247,7 +248,7 @@ void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int
 // hist_scratch_min(n, kn_max) doubles.
 void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, const double *Qh, const double *beta,
                       const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
-                      hipStream_t s);
+                      hipStream_t s, bool mfma = false);   // mfma: blocks wider than 16 on the FP64 matrix cores
 // Q columns of a multidirectional block (N of them): Qn holds S Z on entry; the history
 // sums are those launch_update_pq left in the scratch with kn_max = N
 void launch_update_q(int64_t n, int h, int N, const double *sc, double *Qn, const double *scratch,

@@ -490,3 +490,21 @@ def test_mixed_precision_refinement(pair, prec, solver):
             return
     assert st.status == ba.BA_OK, st
     assert energy_err(S, _h(x), xs) <= 1e-6
+
+
+def test_mcg_history_on_matrix_cores_matches_the_oracle():
+    """The matrix-core history products (ba_solve_opts.history_mfma, blocks wider than 16
+    columns) give the same iterates as the oracle's Algorithm 2 within 1e-9."""
+    p = synth.walk_problem(n_cams=120, n_lms=8000, seed=5, name="walk120")
+    o = oracle.System(p)
+    g = ba.System.from_problem(p)
+    for N in (40, 64):
+        x, st = g.mcg(N, 10.0, eps=0.0, max_iter=8, history_mfma=True)
+        xo, so = o.mcg(N, 10.0, eps=0.0, imax=8)
+        assert st.multi_steps == so.multi_steps and st.multi_steps > 0
+        assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) < 1e-9, N
+        x2, st2 = g.mcg(N, 10.0, eps=0.0, max_iter=8)
+        assert np.linalg.norm(x2.cpu().numpy() - x.cpu().numpy()) / np.linalg.norm(xo) < 1e-11
+    x, st = g.mcg(64, 10.0, history_mfma=True)
+    assert st.status == ba.BA_OK and st.rel_res_true < 1.05e-6
+    g.close()
