@@ -360,6 +360,7 @@ def main():
     log(f"stream-read ceiling {ceiling:.0f} GB/s; chunk kernel at {achieved / ceiling:.3f} of it")
 
     variants = {}
+    mixed_vs_pcg = None
     if not args.no_variants:
         for name, kw in [("pcg_fp64", dict(solver="pcg", precision="fp64")),
                          ("mcg_fp64_N4", dict(solver="mcg", N=4, precision="fp64")),
@@ -367,7 +368,10 @@ def main():
                          ("mcg_fp64_N64", dict(solver="mcg", N=64, precision="fp64")),
                          ("pcg_fp32_refined", dict(solver="pcg", precision="fp32")),
                          ("pcg_bf16_refined", dict(solver="pcg", precision="bf16")),
-                         ("mcg_fp32_refined_N16", dict(solver="mcg", N=16, precision="fp32"))]:
+                         ("mcg_fp32_refined_N16", dict(solver="mcg", N=16, precision="fp32")),
+                         ("mcg_fp32_refined_N4", dict(solver="mcg", N=4, precision="fp32")),
+                         ("mcg_bf16_refined_N16", dict(solver="mcg", N=16, precision="bf16")),
+                         ("mcg_bf16_refined_N4", dict(solver="mcg", N=4, precision="bf16"))]:
             step(**kw)                         # first call: plan, history and precision buffers
             reps = 3
             torch.cuda.synchronize()
@@ -381,6 +385,10 @@ def main():
                               "rel_res_true": s2.rel_res_true, "status": s2.status}
             log(f"variant {name}: {1.0 / dt:.2f} solves/s, {s2.iterations} iterations, "
                 f"residual {s2.rel_res_true:.2e}")
+        # mixed-precision MCG against plain FP64 PCG on the same GPU (solves/s ratio)
+        base = variants["pcg_fp64"]["solves_per_s"]
+        mixed_vs_pcg = {k: round(v["solves_per_s"] / base, 3) for k, v in variants.items()
+                        if k.startswith("mcg_") and "refined" in k}
 
     extrinsics = None
     if not args.no_variants:
@@ -534,6 +542,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variants": variants,
+        "mixed_mcg_vs_pcg_fp64": mixed_vs_pcg,
         "explicit_schur": explicit,
         "extrinsics_only": extrinsics,
         "batch": batch,

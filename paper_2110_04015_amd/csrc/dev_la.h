@@ -182,6 +182,68 @@ __device__ __forceinline__ void jacobi_eig(int k, double *A, double *V, double *
     }
 }
 
+// Cross-lane move of a double by a DPP control (lanes whose source lies outside the
+// control's reach, or outside row_mask, read 0).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// Segments of a wavefront's lanes by a key that is equal on runs of consecutive lanes
+// (each lane's segment is the run holding its key; a key must not recur after its run
+// ends).  end is the segment's last lane; up<d> tells whether lane - d still lies in the
+// lane's segment, for the steps of the scan below.
+struct Segs {
+    int end;
+    bool up1, up2, up4, up8, row15, row31;
+};
+
+__device__ __forceinline__ Segs key_segments(int key, int lane) {
+    const int prev = __shfl_up(key, 1, 64);
+    const uint64_t heads = __ballot(lane == 0 || prev != key);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+    const int start = 63 - __clzll(heads & upto);
+    const uint64_t above = heads & ~upto;
+    Segs g;
+    g.end = above ? __ffsll((unsigned long long)above) - 2 : 63;
+    g.up1 = lane - 1 >= start;
+    g.up2 = lane - 2 >= start;
+    g.up4 = lane - 4 >= start;
+    g.up8 = lane - 8 >= start;
+    g.row15 = (lane & 16) && start <= (lane & ~15) - 1;   // rows 1, 3 take lane 15 / 47 of the row before
+    g.row31 = lane >= 32 && start <= 31;                  // rows 2, 3 take lane 31
+    return g;
+}
+
+// Segmented inclusive scan of x: shifts by 1, 2, 4, 8 inside rows of 16 lanes, then the
+// row sums carried across rows by the row broadcasts of lanes 15 and 31, each step added
+// only where the source lane lies in the same segment.  The segment's last lane holds
+// the segment total.  Fixed order: deterministic.
+__device__ __forceinline__ double segment_scan(double x, const Segs &g) {
+    double t;
+    t = dpp_move<0x111>(x);   // row_shr:1
+    if (g.up1) x += t;
+    t = dpp_move<0x112>(x);   // row_shr:2
+    if (g.up2) x += t;
+    t = dpp_move<0x114>(x);   // row_shr:4
+    if (g.up4) x += t;
+    t = dpp_move<0x118>(x);   // row_shr:8
+    if (g.up8) x += t;
+    t = dpp_move<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    if (g.row15) x += t;
+    t = dpp_move<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+    if (g.row31) x += t;
+    return x;
+}
+
+// Sum of x over the lane's segment, returned in every lane of the segment.
+__device__ __forceinline__ double segment_sum(double x, const Segs &g) {
+    return __shfl(segment_scan(x, g), g.end, 64);
+}
+
 // Sum over the block's threads: wavefront butterflies, then the wavefronts in order
 // (one barrier); every thread gets the sum.  sh holds kNT / 64 doubles.
 __device__ __forceinline__ double block_sum_waves(double v, double *sh) {

@@ -302,11 +302,13 @@ __global__ __launch_bounds__(256) void k_bsr_mv(int np, const int32_t *__restric
 
 // Y[p][row of j] = sum over blocks t of row j with group(col t) == p of S_(j, col t) z_(col t)
 // (the multidirectional product of eq. (19)'s input).  One work-group of 256 threads per
-// block row, positions as in k_bsr_mv.  The subsets are ranges of consecutive cameras and a
-// row's columns ascend, so a thread's positions fall into few subsets in turn: it sums the
-// nine rows in registers and adds them into its wavefront's LDS rows of that subset when
-// the subset changes (one wavefront's LDS atomics resolve in program and lane order); the
-// four wavefronts' rows are then added in a fixed order.
+// block row, positions as in k_bsr_mv.  The subsets are ranges of consecutive cameras and
+// a row's columns ascend, so within one trip a wavefront's 64 consecutive positions fall
+// into a few runs of equal subset: for each of the nine rows the products are added over
+// each run by a segmented scan across the lanes (segment_scan), and the run's last lane
+// adds the total into the wavefront's LDS row of that subset (distinct subsets per
+// instruction, trips in program order).  The four wavefronts' rows are then added in a
+// fixed order.
 __global__ __launch_bounds__(256) void k_bsr_mm_grouped(int np, int N, int64_t n, const int32_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ col,
                                                         const double *__restrict__ val,
@@ -316,8 +318,8 @@ __global__ __launch_bounds__(256) void k_bsr_mm_grouped(int np, int N, int64_t n
     if (skip && *skip != 0.0) return;
     __shared__ double yl[4][kMaxBlock * 9];
     const int j = blockIdx.x;
-    const int tid = threadIdx.x, w = tid >> 6;
-    for (int e = tid & 63; e < N * 9; e += 64) yl[w][e] = 0.0;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int e = lane; e < N * 9; e += 64) yl[w][e] = 0.0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -325,34 +327,23 @@ __global__ __launch_bounds__(256) void k_bsr_mm_grouped(int np, int N, int64_t n
     const int L = (row_ptr[j + 1] - b0) * 9;
     const double *S = val + (int64_t)b0 * 81;
     const int32_t *cj = col + b0;
-    int g = -1;
-    double acc[9];
-#pragma unroll
-    for (int r = 0; r < 9; ++r) acc[r] = 0.0;
-    for (int e0 = tid; e0 < L; e0 += kBsrAhead * 256) {
+    for (int e0 = tid; e0 - lane < L; e0 += kBsrAhead * 256) {   // whole wavefronts trip together
         double sv[kBsrAhead][9], zg[kBsrAhead];
         int gk[kBsrAhead];
         bsr_fetch(S, cj, z, L, e0, sv, zg, group, gk);
 #pragma unroll
         for (int u = 0; u < kBsrAhead; ++u) {
-            if (e0 + u * 256 >= L) break;
-            if (gk[u] != g) {
-                if (g >= 0) {
+            const int e = e0 + u * 256;
+            if (e - lane >= L) break;   // wave-uniform: no position of this wavefront is left
+            const bool ok = e < L;
+            const Segs sg = key_segments(ok ? gk[u] : 64 + lane, lane);
+            const bool last = ok && sg.end == lane;
 #pragma unroll
-                    for (int r = 0; r < 9; ++r) {
-                        atomicAdd(&yl[w][g * 9 + r], acc[r]);
-                        acc[r] = 0.0;
-                    }
-                }
-                g = gk[u];
+            for (int r = 0; r < 9; ++r) {
+                const double t = segment_scan(sv[u][r] * zg[u], sg);
+                if (last) yl[w][gk[u] * 9 + r] += t;
             }
-#pragma unroll
-            for (int r = 0; r < 9; ++r) acc[r] += sv[u][r] * zg[u];
         }
-    }
-    if (g >= 0) {
-#pragma unroll
-        for (int r = 0; r < 9; ++r) atomicAdd(&yl[w][g * 9 + r], acc[r]);
     }
     __syncthreads();
     for (int e = tid; e < N * 9; e += 256) {

@@ -167,62 +167,11 @@ __device__ __forceinline__ void fetch_tile(const SchurArgs &a, int t, int lane, 
     for (int q = 0; q < 3; ++q) b.vi[q] = p[q];
 }
 
-// Cross-lane move of a double by a DPP control (lanes whose source lies outside the
-// control's reach, or outside row_mask, read 0).
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ double dpp_move(double x) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROW_MASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xf, false);
-    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
-}
-
 // Segment layout of a tile's lanes: a landmark's observations occupy consecutive lanes, so
-// each lane's segment is [start, end] of lanes with its landmark index (padding lanes form
-// segments of their own).  up[d] tells whether lane - d still lies in the lane's segment,
-// for the steps of the scan below.
-struct Segs {
-    int end;
-    bool up1, up2, up4, up8, row15, row31;
-};
-
+// each lane's segment is the run of lanes with its landmark index (padding lanes form
+// segments of their own); the scan itself is in dev_la.h.
 __device__ __forceinline__ Segs tile_segments(uint32_t mt, int lane) {
-    const int key = mt != kPad ? (int)((mt >> 16) & 63u) : 64 + lane;   // padding: a segment per lane
-    const int prev = __shfl_up(key, 1, 64);
-    const uint64_t heads = __ballot(lane == 0 || prev != key);
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-    const int start = 63 - __clzll(heads & upto);
-    const uint64_t above = heads & ~upto;
-    Segs g;
-    g.end = above ? __ffsll((unsigned long long)above) - 2 : 63;
-    g.up1 = lane - 1 >= start;
-    g.up2 = lane - 2 >= start;
-    g.up4 = lane - 4 >= start;
-    g.up8 = lane - 8 >= start;
-    g.row15 = (lane & 16) && start <= (lane & ~15) - 1;   // rows 1, 3 take lane 15 / 47 of the row before
-    g.row31 = lane >= 32 && start <= 31;                  // rows 2, 3 take lane 31
-    return g;
-}
-
-// Sum of x over the lane's segment, returned in every lane of the segment: a segmented
-// inclusive scan (shifts by 1, 2, 4, 8 inside rows of 16 lanes, then the row sums carried
-// across rows by the row broadcasts of lanes 15 and 31), whose segment total at the
-// segment's last lane is read back by every lane of it.  Fixed order: deterministic.
-__device__ __forceinline__ double segment_sum(double x, const Segs &g) {
-    double t;
-    t = dpp_move<0x111>(x);   // row_shr:1
-    if (g.up1) x += t;
-    t = dpp_move<0x112>(x);   // row_shr:2
-    if (g.up2) x += t;
-    t = dpp_move<0x114>(x);   // row_shr:4
-    if (g.up4) x += t;
-    t = dpp_move<0x118>(x);   // row_shr:8
-    if (g.up8) x += t;
-    t = dpp_move<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-    if (g.row15) x += t;
-    t = dpp_move<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
-    if (g.row31) x += t;
-    return __shfl(x, g.end, 64);
+    return key_segments(mt != kPad ? (int)((mt >> 16) & 63u) : 64 + lane, lane);
 }
 
 // e = J_p v, g_l = sum J_l^T e, h_l = V_l^-1 g_l, y_c += J_p^T (e - J_l h_l) (LDS).  Products
