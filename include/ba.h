@@ -105,7 +105,9 @@ typedef struct {
                                 FP64 matrix cores instead of vector FMAs (0, measured faster) */
     int64_t max_history_cols;/* MCG history capacity in columns (0 = 1 + max_iter * N) */
     double inner_eps;        /* mixed precision: inner tolerance relative to the outer residual
-                                (0 = automatic: 1e-2 for FP32 products, 1e-1 for BF16 storage) */
+                                (0 = automatic: 1e-3 for FP32 products, 1e-1 for BF16 storage; batches
+                                use 1e-2 for FP32).  A single solve's inner tolerance is raised so that
+                                the last step stops at half the outer target eps |b~| */
     int32_t max_outer;       /* mixed precision: max refinement steps (20) */
     int32_t max_inner;       /* mixed precision: max inner iterations per step (1000) */
     int32_t reserved[4];
