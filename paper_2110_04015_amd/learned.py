@@ -85,12 +85,54 @@ def collect(seeds, lm_iters: int = 5, n_cams: int = 250, n_probes: int = N_PROBE
     out: List[Sample] = []
 
     def visit(p, g):
-        W, Sw = probe_pairs(g, n_probes, seed=len(out))
+        W, Sw = probe_pairs(g, n_probes, seed=int(p.seed) * 100 + len(out) if hasattr(p, "seed") else len(out))
         out.append(Sample(g.lowrank_features(), W, Sw))
 
     for s in seeds:
         lm_run(training_problem(int(s), n_cams), lm_iters, visit)
     return out
+
+
+def _collect_worker(args):
+    """Worker process: the samples of its seeds, saved as CPU tensors to path."""
+    seeds, lm_iters, n_cams, path = args
+    torch = _torch()
+    torch.cuda.set_device(0)
+    got = collect(seeds, lm_iters, n_cams)
+    torch.save([(s.F.cpu(), s.W.cpu(), s.Sw.cpu()) for s in got], path)
+    return len(got)
+
+
+def _plain_learned_iters_worker(args):
+    """Worker process: iterations to eps of plain and learned MCG on held-out seeds."""
+    seeds, params_path, n_cams, N, tau = args
+    torch = _torch()
+    torch.cuda.set_device(0)
+    params = torch.load(params_path, weights_only=True).to("cuda")
+    rows = []
+    for sd in seeds:
+        g = System.from_problem(training_problem(int(sd), n_cams))
+        try:
+            x, st0 = g.mcg(N, tau, eps=1e-6)
+            g.set_lowrank_from_mlp(mlp_forward(params, g.lowrank_features(), bf16=True))
+            x, st1 = g.mcg(N, tau, eps=1e-6, precond="lowrank")
+            rows.append({"seed": int(sd), "plain_iters": st0.iterations, "learned_iters": st1.iterations,
+                         "plain_status": st0.status, "learned_status": st1.status,
+                         "plain_res": st0.rel_res_true, "learned_res": st1.rel_res_true})
+        finally:
+            g.close()
+    return rows
+
+
+def _pool(workers: int):
+    """Worker processes, started before this process touches the GPU."""
+    import multiprocessing as mp
+    return mp.get_context("spawn").Pool(workers)
+
+
+def _split(seq, k):
+    seq = list(seq)
+    return [seq[i::k] for i in range(k) if seq[i::k]]
 
 
 def mean_loss(params, samples: List[Sample]) -> float:
@@ -166,30 +208,70 @@ def evaluate(params, seeds, n_cams: int = 250, N: int = 16, tau: float = 3.3) ->
 def main(argv=None):
     import argparse
     import json
+    import os
+    import tempfile
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--train-seeds", type=int, default=40)
     ap.add_argument("--eval-seeds", type=int, default=20)
+    ap.add_argument("--timed-seeds", type=int, default=20, help="held-out seeds also timed, one process alone")
     ap.add_argument("--lm-iters", type=int, default=5)
     ap.add_argument("--n-cams", type=int, default=250)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--lr", type=float, default=1e-4)
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--workers", type=int, default=8, help="processes generating systems (each uses the GPU)")
+    ap.add_argument("--out", default=None, help="JSON summary")
+    ap.add_argument("--params-out", default=None, help="trained weights (torch.save of an FP32 tensor)")
     a = ap.parse_args(argv)
     log = lambda s: print(f"[learned] {s}", flush=True)
+    tmp = tempfile.mkdtemp(prefix="lowrank_")
+    pool = _pool(a.workers) if a.workers > 1 else None
     t0 = time.perf_counter()
-    samples = collect(range(a.train_seeds), a.lm_iters, a.n_cams)
-    log(f"{len(samples)} training systems from {a.train_seeds} seeds in {time.perf_counter() - t0:.1f} s")
+    parts = _split(range(a.train_seeds), a.workers)
+    jobs = [(pt, a.lm_iters, a.n_cams, os.path.join(tmp, f"part{i}.pt")) for i, pt in enumerate(parts)]
+    if pool:
+        pool.map(_collect_worker, jobs)
+    else:
+        for j in jobs:
+            _collect_worker(j)
+    torch = _torch()
+    samples = []
+    for j in jobs:
+        for F, W, Sw in torch.load(j[3], weights_only=True):
+            samples.append(Sample(F.cuda(), W.cuda(), Sw.cuda()))
+        os.remove(j[3])
+    gen_s = time.perf_counter() - t0
+    log(f"{len(samples)} training systems from {a.train_seeds} seeds in {gen_s:.1f} s")
     tr = train(samples, a.epochs, a.lr, log=log)
-    held = range(10_000, 10_000 + a.eval_seeds)
-    ev = evaluate(tr["params"], held, a.n_cams)
-    summary = {"train_systems": len(samples), "epochs": a.epochs, "steps": tr["steps"],
-               "train_s": round(tr["train_s"], 2), "loss_first": tr["loss_history"][0],
-               "loss_last": tr["loss_history"][-1],
-               "held_out": {k: v for k, v in ev.items() if k != "rows"}}
+    params_path = a.params_out or os.path.join(tmp, "params.pt")
+    torch.save(tr["params"].detach().cpu(), params_path)
+    # held-out iterations in the worker processes (iteration counts do not depend on timing)
+    held = list(range(10_000, 10_000 + a.eval_seeds))
+    t1 = time.perf_counter()
+    ejobs = [(pt, params_path, a.n_cams, 16, 3.3) for pt in _split(held, a.workers)]
+    rows = [r for part in (pool.map(_plain_learned_iters_worker, ejobs) if pool else
+                           [_plain_learned_iters_worker(j) for j in ejobs]) for r in part]
+    if pool:
+        pool.close()
+        pool.join()
+    rows.sort(key=lambda r: r["seed"])
+    pi = np.array([r["plain_iters"] for r in rows], dtype=float)
+    li = np.array([r["learned_iters"] for r in rows], dtype=float)
+    held_out = {"systems": len(rows), "plain_iters_mean": float(pi.mean()), "learned_iters_mean": float(li.mean()),
+                "iters_change": float(li.mean() / pi.mean() - 1.0),
+                "learned_fewer_or_equal": int((li <= pi).sum()),
+                "all_converged": all(r["plain_status"] == 0 and r["learned_status"] == 0 for r in rows),
+                "eval_s": round(time.perf_counter() - t1, 1)}
+    # time on a subset, this process alone on the GPU
+    timed = evaluate(tr["params"], held[:a.timed_seeds], a.n_cams) if a.timed_seeds > 0 else None
+    summary = {"n_cams": a.n_cams, "n_lms": 336 * a.n_cams, "train_seeds": a.train_seeds,
+               "train_systems": len(samples), "generation_s": round(gen_s, 1), "epochs": a.epochs,
+               "steps": tr["steps"], "train_s": round(tr["train_s"], 2), "loss_first": tr["loss_history"][0],
+               "loss_last": tr["loss_history"][-1], "held_out": held_out,
+               "timed": None if timed is None else {k: v for k, v in timed.items() if k != "rows"}}
     log(json.dumps(summary))
     if a.out:
         with open(a.out, "w") as f:
-            json.dump({"summary": summary, "loss_history": tr["loss_history"], "rows": ev["rows"]}, f, indent=1)
+            json.dump({"summary": summary, "loss_history": tr["loss_history"], "held_out_rows": rows}, f, indent=1)
 
 
 if __name__ == "__main__":
