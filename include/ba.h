@@ -110,7 +110,12 @@ typedef struct {
                                 the last step stops at half the outer target eps |b~| */
     int32_t max_outer;       /* mixed precision: max refinement steps (20) */
     int32_t max_inner;       /* mixed precision: max inner iterations per step (1000) */
-    int32_t reserved[4];
+    int32_t history_fp32;    /* mixed-precision MCG: 1 lets the reorthogonalisation (Phi = Q^T Z and the
+                                history products of Alg. 2 / eq. (19)) read an FP32 copy of the P and Q
+                                history (the storage option of the mixed path); the new block's Gram,
+                                x, r and the S products keep FP64.  Ignored for FP64 solves and by
+                                the batched solver.  ba_default_solve_opts sets 1 */
+    int32_t reserved[3];
 } ba_solve_opts;
 
 /* Solve statistics.  The trace pointers are HOST arrays supplied by the caller

@@ -79,7 +79,7 @@ class Stats:
 
 
 def _opts(eps, max_iter, precision, max_history_cols=0, inner_eps=0.0, max_outer=20, max_inner=1000,
-          precond=0, history_mfma=False):
+          precond=0, history_mfma=False, history_fp32=None):
     o = _lib.SolveOpts()
     lib().ba_default_solve_opts(C.byref(o))
     o.eps = float(eps)
@@ -91,6 +91,8 @@ def _opts(eps, max_iter, precision, max_history_cols=0, inner_eps=0.0, max_outer
     o.max_inner = int(max_inner)
     o.precond = int(precond)
     o.history_mfma = 1 if history_mfma else 0
+    if history_fp32 is not None:   # None keeps the library default (on)
+        o.history_fp32 = 1 if history_fp32 else 0
     return o
 
 
@@ -353,12 +355,13 @@ class System:
 
     def mcg(self, N, tau, eps=1e-6, max_iter=1000, x0=None, precision="fp64", trace=False,
             max_history_cols=0, out=None, inner_eps=0.0, max_outer=20, max_inner=1000, precond="block_jacobi",
-            history_mfma=False):
+            history_mfma=False, history_fp32=None):
         """Algorithm 2 with N subsets and threshold tau (mixed precision as in pcg)."""
         torch = _torch()
         x = out if out is not None else self._new(self.n)
         o = _opts(eps, max_iter, precision, max_history_cols=max_history_cols, inner_eps=inner_eps,
-                  max_outer=max_outer, max_inner=max_inner, precond=_PRECOND[precond], history_mfma=history_mfma)
+                  max_outer=max_outer, max_inner=max_inner, precond=_PRECOND[precond], history_mfma=history_mfma,
+                  history_fp32=history_fp32)
         st = _lib.SolveStats()
         tr = _Trace(max(int(max_iter), 1)) if trace else None
         if tr:

@@ -29,7 +29,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32),
                 ("precond", C.c_int32), ("history_mfma", C.c_int32), ("max_history_cols", C.c_int64),
                 ("inner_eps", C.c_double), ("max_outer", C.c_int32), ("max_inner", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("history_fp32", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class SolveStats(C.Structure):

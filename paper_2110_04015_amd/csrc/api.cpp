@@ -158,6 +158,7 @@ void free_all(ba_system *s) {
     sfree(s, s->vec);
     sfree(s, s->red);
     sfree(s, s->hist);
+    sfree(s, s->hist32);
     sfree(s, s->small);
     sfree(s, s->hscratch);
     sfree(s, s->tickets);
@@ -509,6 +510,7 @@ void fill_default_opts(ba_solve_opts *o) {
     o->max_history_cols = 0;
     o->inner_eps = 0.0;     // automatic: by the precision of the products
     o->max_outer = 20;
+    o->history_fp32 = 1;   // mixed precision: the reorthogonalisation reads the FP32 history copy
     o->max_inner = 1000;
 }
 
@@ -663,6 +665,8 @@ static ba_status reserve_solvers(ba_system *s, const ba_build_opts *o) {
     if (mixed) {
         const int64_t n = (int64_t)s->np * s->dp;
         if ((st = grow(s, s->refine_buf, s->refine_cap, (size_t)n * 5 + 8)) != BA_OK) return st;
+        // the FP32 history copy of mixed-precision MCG (history_fp32, the default)
+        if (N >= 1 && (st = grow(s, s->hist32, s->hist32_cap, (size_t)(s->hist_cap_cols * n))) != BA_OK) return st;
     }
     return BA_OK;
 }
@@ -1204,6 +1208,15 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     if ((st = mcg_buffers(s, N, cap)) != BA_OK) return st;
     const int64_t hc = s->hist_cap_cols;
     double *Ph = s->hist, *Qh = s->hist + hc * n;
+    // mixed precision: the reorthogonalisation reads (Phi and the history products) may
+    // take an FP32 copy of the history, each block copied once it is final
+    const bool h32 = prec != 0 && opts.history_fp32 != 0;
+    float *P32 = nullptr, *Q32 = nullptr;
+    if (h32) {
+        if ((st = grow(s, s->hist32, s->hist32_cap, (size_t)(hc * n))) != BA_OK) return st;
+        P32 = reinterpret_cast<float *>(s->hist32);
+        Q32 = P32 + hc * n;
+    }
     const int phiw = std::max(N, kPhiSeg);
     const int ldb = hist_ldb(N);
     double *Dp = s->small, *Phi = Dp + 64 * hc, *beta = Phi + hc * phiw, *gamma = beta + hc * ldb, *alpha = gamma + 64;
@@ -1304,11 +1317,20 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             const bool ahead = N > 1 && hcols + N <= hc;   // room for a multidirectional block
             const bool room1 = hcols + 1 <= hc;
             const int kn_max = ahead ? N : room1 ? 1 : 0;
-            launch_phi(n, (int)hcols, Qh, z, N, gs, Phi, q);
+            if (h32) {
+                launch_hist_copy32(n, hoff.back(), hk.back(), Ph, Qh, P32, Q32, q);   // the current block
+                launch_phi<float>(n, (int)hcols, Q32, z, N, gs, Phi, q);
+            } else {
+                launch_phi<double>(n, (int)hcols, Qh, z, N, gs, Phi, q);
+            }
             // beta_{i,j} = Delta_j^+ Phi_{i,j}; P_{i+1} = Z - sum P_j beta
             launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, sc, kn_max, N, beta, q);
-            launch_update_pq(n, (int)hcols, N, kn_max, Ph, Qh, beta, z, gs, sc, Pn, s->hscratch, s->hscratch_cap, q,
-                             opts.history_mfma != 0);
+            if (h32)
+                launch_update_pq<float>(n, (int)hcols, N, kn_max, P32, Q32, beta, z, gs, sc, Pn, s->hscratch,
+                                        s->hscratch_cap, q, opts.history_mfma != 0);
+            else
+                launch_update_pq<double>(n, (int)hcols, N, kn_max, Ph, Qh, beta, z, gs, sc, Pn, s->hscratch,
+                                         s->hscratch_cap, q, opts.history_mfma != 0);
             bool spec_pair = false;   // the product's profiling events, dropped if it is skipped
             if (room1) {   // one-column block: Q_{i+1} = S P_{i+1}
                 SchurArgs s1 = sag;

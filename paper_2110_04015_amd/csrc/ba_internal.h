@@ -176,6 +176,8 @@ struct ba_system {
     size_t red_cap = 0;
     double *hist = nullptr;         // MCG history (P then Q)
     int64_t hist_cap_cols = 0;
+    double *hist32 = nullptr;       // FP32 copy of the history (P then Q, floats), mixed path
+    int64_t hist32_cap = 0;         // doubles
     double *small = nullptr;        // MCG small dense storage
     uint32_t *tickets = nullptr;    // arrival counters of last-block reductions (zero between launches)
     int64_t tickets_cap = 0;

@@ -863,8 +863,8 @@ void launch_mcg_scalars(int k, const double *prr, const double *prho, const doub
 // group in flight and loads z once for them.
 constexpr int kPhiCols = 4;
 
-template <int NC>
-__device__ inline void phi_group(int64_t n, int64_t lo, int64_t hi, const double *__restrict__ q,
+template <int NC, typename HT>
+__device__ inline void phi_group(int64_t n, int64_t lo, int64_t hi, const HT *__restrict__ q,
                                  const double *__restrict__ z, double *acc) {
     const int lane = threadIdx.x & 63;
     double a[NC][4];
@@ -880,18 +880,19 @@ __device__ inline void phi_group(int64_t n, int64_t lo, int64_t hi, const double
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[c][u] += q[(int64_t)c * n + i + 64 * u] * zv[u];
+            for (int u = 0; u < 4; ++u) a[c][u] += (double)q[(int64_t)c * n + i + 64 * u] * zv[u];
     }
     for (; i < hi; i += 64) {
         const double zv = z[i];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) a[c][0] += q[(int64_t)c * n + i] * zv;
+        for (int c = 0; c < NC; ++c) a[c][0] += (double)q[(int64_t)c * n + i] * zv;
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = wave_sum((a[c][0] + a[c][1]) + (a[c][2] + a[c][3]));
 }
 
-__global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const double *__restrict__ Qh,
+template <typename HT>
+__global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const HT *__restrict__ Qh,
                                              const double *__restrict__ z, int N, int gs,
                                              double *__restrict__ Phi) {
     const int64_t w = (int64_t)blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
@@ -910,13 +911,13 @@ __global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const do
     }
     const int64_t c0 = g * kPhiCols;
     const int nc = (int)min<int64_t>(kPhiCols, h - c0);
-    const double *q = Qh + c0 * n;
+    const HT *q = Qh + c0 * n;
     double acc[kPhiCols];
     switch (nc) {
-    case 4: phi_group<4>(n, lo, hi, q, z, acc); break;
-    case 3: phi_group<3>(n, lo, hi, q, z, acc); break;
-    case 2: phi_group<2>(n, lo, hi, q, z, acc); break;
-    default: phi_group<1>(n, lo, hi, q, z, acc); break;
+    case 4: phi_group<4, HT>(n, lo, hi, q, z, acc); break;
+    case 3: phi_group<3, HT>(n, lo, hi, q, z, acc); break;
+    case 2: phi_group<2, HT>(n, lo, hi, q, z, acc); break;
+    default: phi_group<1, HT>(n, lo, hi, q, z, acc); break;
     }
     if (lane == 0)
         for (int c = 0; c < nc; ++c) Phi[(c0 + c) * seg + p] = acc[c];
@@ -924,14 +925,17 @@ __global__ __launch_bounds__(kNT) void k_phi(int64_t n, int h, int seg, const do
 
 int phi_segments(int N) { return N > 1 ? N : kPhiSeg; }
 
-void launch_phi(int64_t n, int h, const double *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s) {
+template <typename HT>
+void launch_phi(int64_t n, int h, const HT *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s) {
     if (h <= 0) return;
     const int seg = phi_segments(N);
     const int64_t waves = (int64_t)(h + kPhiCols - 1) / kPhiCols * seg;
     const int per = kNT / 64;
-    hipLaunchKernelGGL(k_phi, dim3((unsigned)((waves + per - 1) / per)), dim3(kNT), 0, s, n, h, seg, Qh, z, N, gs,
+    hipLaunchKernelGGL(k_phi<HT>, dim3((unsigned)((waves + per - 1) / per)), dim3(kNT), 0, s, n, h, seg, Qh, z, N, gs,
                        Phi);
 }
+template void launch_phi<double>(int64_t, int, const double *, const double *, int, int, double *, hipStream_t);
+template void launch_phi<float>(int64_t, int, const float *, const double *, int, int, double *, hipStream_t);
 
 // Width of the block being built, as the device decided it (sc[SC_KN]: 0 once converged,
 // N for a multidirectional block, else 1); 0 as well when it exceeds kn_max, the widest
@@ -1068,15 +1072,15 @@ void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int
 // loops carry no per-output test; blocks wider than 16 columns take the matrix-core path
 // (hist_slice_mfma).  Pass 2 adds the slices in slice order and subtracts
 // from the base, so the result is independent of scheduling.
-template <int KB>
+template <int KB, typename HT>
 __device__ inline void hist_slice(int64_t n, int64_t row, int c0, int c1, int kn, int p0,
-                                  const double *__restrict__ H, const double *__restrict__ beta,
+                                  const HT *__restrict__ H, const double *__restrict__ beta,
                                   double *__restrict__ out) {
     const int ldb = hist_ldb(kn);
     double acc[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) acc[j] = 0.0;
-    const double *hp = H + row;
+    const HT *hp = H + row;
     int c = c0;
     // CU columns per step: CU loads of the history in flight per lane (fewer for wide
     // output blocks, whose beta values fill the scalar registers)
@@ -1084,7 +1088,7 @@ __device__ inline void hist_slice(int64_t n, int64_t row, int c0, int c1, int kn
     for (; c + CU <= c1; c += CU) {
         double hv[CU];
 #pragma unroll
-        for (int u = 0; u < CU; ++u) hv[u] = hp[(int64_t)(c + u) * n];
+        for (int u = 0; u < CU; ++u) hv[u] = (double)hp[(int64_t)(c + u) * n];
         const double *b0 = beta + (int64_t)c * ldb + p0;
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
@@ -1093,7 +1097,7 @@ __device__ inline void hist_slice(int64_t n, int64_t row, int c0, int c1, int kn
         }
     }
     for (; c < c1; ++c) {
-        const double hv = hp[(int64_t)c * n];
+        const double hv = (double)hp[(int64_t)c * n];
         const double *b0 = beta + (int64_t)c * ldb + p0;
 #pragma unroll
         for (int j = 0; j < KB; ++j) acc[j] += hv * b0[j];
@@ -1109,8 +1113,9 @@ __device__ inline void hist_slice(int64_t n, int64_t row, int c0, int c1, int kn
 // and B[kk][j] = beta[c + kk][p0 + 16 q + j] (lane layouts as in the Gram kernel),
 // 4 kHistMG columns' loads in flight.  Rows past n and columns past c1 load zeros.
 constexpr int kHistMG = 2;   // groups of 4 history columns per loop trip
+template <typename HT>
 __device__ inline void hist_slice_mfma(int64_t n, int64_t row0, int c0, int c1, int kn, int p0,
-                                       const double *__restrict__ H, const double *__restrict__ beta,
+                                       const HT *__restrict__ H, const double *__restrict__ beta,
                                        double *__restrict__ out) {
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int ldb = hist_ldb(kn);
@@ -1128,7 +1133,7 @@ __device__ inline void hist_slice_mfma(int64_t n, int64_t row0, int c0, int c1, 
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int64_t row = row0 + 16 * m + li;
-                hv[g][m] = (okc && row < n) ? H[(int64_t)col * n + row] : 0.0;
+                hv[g][m] = (okc && row < n) ? (double)H[(int64_t)col * n + row] : 0.0;
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
@@ -1169,9 +1174,9 @@ struct HistSlices {
 // any width up to 16; KBW = 32: one-column blocks only (wider ones are left to
 // k_hist_wide, launched beside it, so that this kernel keeps few registers and many
 // wavefronts in flight for the one-column blocks, the most frequent).
-template <int KBW>
+template <int KBW, typename HT>
 __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, HistSlices hs, int zb,
-                                                     const double *__restrict__ Ph, const double *__restrict__ Qh,
+                                                     const HT *__restrict__ Ph, const HT *__restrict__ Qh,
                                                      const double *__restrict__ beta, const double *__restrict__ sc,
                                                      int kn_max, double *__restrict__ scratch) {
     const int kn = next_kn(sc, kn_max);
@@ -1185,17 +1190,17 @@ __global__ __launch_bounds__(64) void k_hist_partial(int64_t n, int h, HistSlice
     const int c0 = ks * slice_cols;
     const int c1 = min(h, c0 + slice_cols);
     double *out = scratch + ((int64_t)mat * nslices + ks) * kn * n;
-    if (kn == 1) hist_slice<1>(n, row, c0, c1, 1, 0, Ph, beta, out);
-    else if (KBW == 16) hist_slice<16>(n, row, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
+    if (kn == 1) hist_slice<1, HT>(n, row, c0, c1, 1, 0, Ph, beta, out);
+    else if (KBW == 16) hist_slice<16, HT>(n, row, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
 }
 
 // Multidirectional blocks wider than 16 columns: 32-output blocks of the same grid and
 // outputs as k_hist_partial<32>, with vector FMAs (MFMA = false: hist_slice<32>, beta
 // from scalar loads) or on the matrix cores (MFMA = true: hist_slice_mfma; every lane of
 // a wavefront takes part, rows past n load zeros); one-column blocks return at once.
-template <bool MFMA>
+template <bool MFMA, typename HT>
 __global__ __launch_bounds__(64) void k_hist_wide(int64_t n, int h, HistSlices hs, int zb,
-                                                  const double *__restrict__ Ph, const double *__restrict__ Qh,
+                                                  const HT *__restrict__ Ph, const HT *__restrict__ Qh,
                                                   const double *__restrict__ beta, const double *__restrict__ sc,
                                                   int kn_max, double *__restrict__ scratch) {
     const int kn = next_kn(sc, kn_max);
@@ -1208,8 +1213,8 @@ __global__ __launch_bounds__(64) void k_hist_wide(int64_t n, int h, HistSlices h
     const int c0 = ks * hs.multi_cols;
     const int c1 = min(h, c0 + hs.multi_cols);
     double *out = scratch + ((int64_t)mat * hs.multi + ks) * kn * n;
-    if (MFMA) hist_slice_mfma(n, row0, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
-    else hist_slice<32>(n, row0 + threadIdx.x, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
+    if (MFMA) hist_slice_mfma<HT>(n, row0, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
+    else hist_slice<32, HT>(n, row0 + threadIdx.x, c0, c1, kn, p0, mat ? Qh : Ph, beta, out);
 }
 
 // y = 0 (mat0 = 0): P_new from the P slices; mat0 = 1: Q_new from the Q slices
@@ -1264,7 +1269,8 @@ static HistSlices hist_slicing(int64_t n, int h, int kn_max, int64_t scratch_dou
 
 int64_t hist_scratch_min(int64_t n, int kn_max) { return 2 * (int64_t)kn_max * n; }
 
-void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, const double *Qh, const double *beta,
+template <typename HT>
+void launch_update_pq(int64_t n, int h, int N, int kn_max, const HT *Ph, const HT *Qh, const double *beta,
                       const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
                       hipStream_t s, bool mfma) {
     if (kn_max <= 0) return;
@@ -1273,23 +1279,49 @@ void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, con
         const unsigned tiles = (unsigned)((n + 63) / 64);
         const unsigned ys = (unsigned)std::max(hs.one, hs.multi);
         if (kn_max <= 16) {
-            hipLaunchKernelGGL((k_hist_partial<16>), dim3(tiles, ys, 2), dim3(64), 0, s, n, h, hs, 1, Ph, Qh, beta, sc,
+            hipLaunchKernelGGL((k_hist_partial<16, HT>), dim3(tiles, ys, 2), dim3(64), 0, s, n, h, hs, 1, Ph, Qh, beta, sc,
                                kn_max, scratch);
         } else {
             const int zb = (kn_max + 31) / 32;
-            hipLaunchKernelGGL((k_hist_partial<32>), dim3(tiles, hs.one, 1), dim3(64), 0, s, n, h, hs, zb, Ph, Qh,
+            hipLaunchKernelGGL((k_hist_partial<32, HT>), dim3(tiles, hs.one, 1), dim3(64), 0, s, n, h, hs, zb, Ph, Qh,
                                beta, sc, kn_max, scratch);
             if (mfma)
-                hipLaunchKernelGGL(k_hist_wide<true>, dim3(tiles, hs.multi, 2 * zb), dim3(64), 0, s, n, h, hs, zb,
+                hipLaunchKernelGGL((k_hist_wide<true, HT>), dim3(tiles, hs.multi, 2 * zb), dim3(64), 0, s, n, h, hs, zb,
                                    Ph, Qh, beta, sc, kn_max, scratch);
             else
-                hipLaunchKernelGGL(k_hist_wide<false>, dim3(tiles, hs.multi, 2 * zb), dim3(64), 0, s, n, h, hs, zb,
+                hipLaunchKernelGGL((k_hist_wide<false, HT>), dim3(tiles, hs.multi, 2 * zb), dim3(64), 0, s, n, h, hs, zb,
                                    Ph, Qh, beta, sc, kn_max, scratch);
         }
     }
     const int64_t tot = n * kn_max;
     hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, hs, scratch, z, gs, N,
                        sc, kn_max, 0, Pn, nullptr);
+}
+
+template void launch_update_pq<double>(int64_t, int, int, int, const double *, const double *, const double *,
+                                       const double *, int, const double *, double *, double *, int64_t, hipStream_t,
+                                       bool);
+template void launch_update_pq<float>(int64_t, int, int, int, const float *, const float *, const double *,
+                                      const double *, int, const double *, double *, double *, int64_t, hipStream_t,
+                                      bool);
+
+// FP32 copy of history columns [c0, c0 + k) of P and Q (mixed precision: the
+// reorthogonalisation reads the copy, the block's own Gram and updates the FP64 columns)
+__global__ __launch_bounds__(kNT) void k_hist_copy32(int64_t n, int64_t c0, int k, const double *__restrict__ Ph,
+                                                     const double *__restrict__ Qh, float *__restrict__ P32,
+                                                     float *__restrict__ Q32) {
+    const int64_t tot = (int64_t)k * n, base = c0 * n;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < tot; i += (int64_t)gridDim.x * kNT) {
+        P32[base + i] = (float)Ph[base + i];
+        Q32[base + i] = (float)Qh[base + i];
+    }
+}
+
+void launch_hist_copy32(int64_t n, int64_t c0, int k, const double *Ph, const double *Qh, float *P32, float *Q32,
+                        hipStream_t s) {
+    const int64_t tot = (int64_t)k * n;
+    const unsigned g = (unsigned)std::min<int64_t>((tot + kNT - 1) / kNT, 2048);
+    if (g > 0) hipLaunchKernelGGL(k_hist_copy32, dim3(g), dim3(kNT), 0, s, n, c0, k, Ph, Qh, P32, Q32);
 }
 
 void launch_update_q(int64_t n, int h, int N, const double *sc, double *Qn, const double *scratch,

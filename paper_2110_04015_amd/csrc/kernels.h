@@ -232,7 +232,8 @@ void launch_mcg_xrz(int np, int k, const double *P, const double *Q, double *alp
 // and multidirectional steps), kPhiSeg row segments when N = 1
 int phi_segments(int N);
 // gs: rows of one subset (subset poses times the pose dimension)
-void launch_phi(int64_t n, int h, const double *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s);
+template <typename HT>   // history stored in FP64 (double) or, on the mixed path, as an FP32 copy (float)
+void launch_phi(int64_t n, int h, const HT *Qh, const double *z, int N, int gs, double *Phi, hipStream_t s);
 // row length of beta for a kn-column step: kn = 1 unpadded, else kn rounded up to the
 // output block of the history products (16 up to 16 columns, then multiples of 32), the
 // padding zero
@@ -246,9 +247,13 @@ void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int
 // history sums of its Q columns in the scratch (kept for launch_update_q); kn_max is the
 // widest block the history has room for.  The scratch holds at least
 // hist_scratch_min(n, kn_max) doubles.
-void launch_update_pq(int64_t n, int h, int N, int kn_max, const double *Ph, const double *Qh, const double *beta,
+template <typename HT>   // Ph, Qh: FP64 history or its FP32 copy
+void launch_update_pq(int64_t n, int h, int N, int kn_max, const HT *Ph, const HT *Qh, const double *beta,
                       const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
                       hipStream_t s, bool mfma = false);   // mfma: blocks wider than 16 on the FP64 matrix cores
+// FP32 copy of history columns [c0, c0 + k) of P and Q (column-major, n rows)
+void launch_hist_copy32(int64_t n, int64_t c0, int k, const double *Ph, const double *Qh, float *P32, float *Q32,
+                        hipStream_t s);
 // Q columns of a multidirectional block (N of them): Qn holds S Z on entry; the history
 // sums are those launch_update_pq left in the scratch with kn_max = N
 void launch_update_q(int64_t n, int h, int N, const double *sc, double *Qn, const double *scratch,

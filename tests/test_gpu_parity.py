@@ -453,15 +453,17 @@ def test_build_errors():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("solver", ["pcg", "mcg"])
+@pytest.mark.parametrize("solver", ["pcg", "mcg", "mcg_h32"])
 def test_mixed_precision_refinement(pair, prec, solver):
     """FP64 refinement around reduced-precision S products: the result meets the FP64
     residual target, and run to 1e-10 its error against the dense solution is <= 1e-6
-    (energy norm) -- the stated bound for the mixed form."""
+    (energy norm) -- the stated bound for the mixed form.  mcg_h32: MCG whose
+    reorthogonalisation reads the FP32 copy of the history (ba_solve_opts.history_fp32, the
+    default), mcg: the FP64 history."""
     name, p, o, g = pair
     N = min(4, p.n_cams)
     run = (lambda **kw: g.pcg(precision=prec, **kw)) if solver == "pcg" else \
-        (lambda **kw: g.mcg(N, 10.0, precision=prec, **kw))
+        (lambda **kw: g.mcg(N, 10.0, precision=prec, history_fp32=solver == "mcg_h32", **kw))   # mcg: FP64 history
     x, st = run(max_iter=5000, max_outer=40)
     bt = o.rhs()
     xh = _h(x)
