@@ -79,107 +79,186 @@ __device__ __forceinline__ void chol9_solve(const double *__restrict__ L, const 
     chol_solve_packed<9>(L, r, z);
 }
 
-// Symmetric Jacobi eigendecomposition of the k x k matrix in LDS (k <= 64), with
-// disjoint rotations applied in parallel (round-robin ordering).  A rotation of
-// the pair (p, q) is skipped when |a_pq| <= (eps / 2) sqrt(|a_pp a_qq|); sweeps stop
-// when a sweep rotates nothing.  On return A holds the eigenvalues on its
-// diagonal and V the eigenvectors in its columns.
-__device__ __forceinline__ void jacobi_eig(int k, double *A, double *V, double *cs, double *sn, int *flag) {
-    const int tid = threadIdx.x;
-    const int kp = k + (k & 1);
+// Value of v in lane l of the wavefront (l wave-uniform).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Eigendecomposition of the symmetric k x k matrix A in LDS (k <= 64, row-major) by the
+// block's 256 threads: on return the diagonal of A holds the eigenvalues and the columns
+// of V the eigenvectors.
+//  1. Householder tridiagonalisation, Q^T A Q = T: for column j, the reflector
+//     H = I - b v v^T with H x = alpha e_1 for x = A[j+1.., j]; the trailing block becomes
+//     A - v w^T - w v^T with p = b A v, w = p - (b/2)(v^T p) v.  v_1.. stays in the zeroed
+//     part of column j, v_0 and b in LDS.  Four barriers per column.
+//  2. Q = H_0 H_1 ... formed in V, the reflectors applied from the last to the first.
+//  3. Implicit-shift QL iterations on T (the shift from the leading 2 x 2 block, the
+//     bulge chased with Givens rotations from the bottom of the unreduced block up), by
+//     the first wavefront: lane i keeps d_i and e_i in registers, every lane reads them
+//     with readlane and runs the same scalar recurrence, and lane r applies each rotation
+//     to row r of V.  A subdiagonal entry counts as zero when |e_m| <= eps (|d_m| + |d_m+1|).
+__device__ __forceinline__ void sym_eig(int k, double *A, double *V) {
+    __shared__ double hv0[kMaxK], hb[kMaxK], hp[kMaxK], hd[kMaxK], he[kMaxK + 1];
+    __shared__ double s_alpha, s_K;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int r4 = tid >> 2, q4 = tid & 3;   // 4 threads per row (or column) of a trailing block
     for (int w = tid; w < k * k; w += kNT) V[w] = (w / k == w % k) ? 1.0 : 0.0;
+    if (tid < kMaxK) hb[tid] = 0.0;
     __syncthreads();
-    if (k < 2) return;
-    const int half = kp / 2;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        if (tid == 0) *flag = 0;
-        __syncthreads();
-        for (int step = 0; step < kp - 1; ++step) {
-            // pair t of this step: (step, kp-1) for t = 0, otherwise (step+t, step-t) mod (kp-1)
-            if (tid < half) {
-                int p, q;
-                if (tid == 0) {
-                    p = step;
-                    q = kp - 1;
+    // 1. tridiagonalisation
+    for (int j = 0; j + 2 < k; ++j) {
+        const int m = k - j - 1, o = j + 1;
+        if (tid < 64) {
+            const double xi = lane < m ? A[(o + lane) * k + j] : 0.0;
+            const double sigma = wave_sum(lane >= 1 && lane < m ? xi * xi : 0.0);
+            if (lane == 0) {
+                if (sigma == 0.0) {
+                    hb[j] = 0.0;
                 } else {
-                    p = (step + tid) % (kp - 1);
-                    q = (step - tid + (kp - 1)) % (kp - 1);
+                    const double alpha = -copysign(sqrt(xi * xi + sigma), xi);
+                    const double v0 = xi - alpha;
+                    hv0[j] = v0;
+                    hb[j] = 2.0 / (sigma + v0 * v0);
+                    s_alpha = alpha;
                 }
-                if (p > q) {
-                    int t = p;
-                    p = q;
-                    q = t;
-                }
-                double c = 1.0, s = 0.0;
-                if (q < k) {
-                    double apq = A[p * k + q], app = A[p * k + p], aqq = A[q * k + q];
-                    if (!(fabs(apq) <= 1e-300) && !(fabs(apq) <= 2.2e-16 * 0.5 * sqrt(fabs(app) * fabs(aqq)))) {
-                        double theta = (aqq - app) / (2.0 * apq);
-                        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                        *flag = 1;
-                    }
-                }
-                cs[tid] = c;
-                sn[tid] = s;
             }
-            __syncthreads();
-            // columns: A <- A J and V <- V J
-            for (int w = tid; w < k * half; w += kNT) {
-                int row = w / half, t = w - row * half;
-                int p, q;
-                if (t == 0) {
-                    p = step;
-                    q = kp - 1;
-                } else {
-                    p = (step + t) % (kp - 1);
-                    q = (step - t + (kp - 1)) % (kp - 1);
-                }
-                if (p > q) {
-                    int tt = p;
-                    p = q;
-                    q = tt;
-                }
-                if (q >= k) continue;
-                double c = cs[t], s = sn[t];
-                if (s == 0.0) continue;
-                double arp = A[row * k + p], arq = A[row * k + q];
-                A[row * k + p] = c * arp - s * arq;
-                A[row * k + q] = s * arp + c * arq;
-                double vrp = V[row * k + p], vrq = V[row * k + q];
-                V[row * k + p] = c * vrp - s * vrq;
-                V[row * k + q] = s * vrp + c * vrq;
-            }
-            __syncthreads();
-            // rows: A <- J^T A, rotated off-diagonal entries set to zero
-            for (int w = tid; w < k * half; w += kNT) {
-                int col = w / half, t = w - col * half;
-                int p, q;
-                if (t == 0) {
-                    p = step;
-                    q = kp - 1;
-                } else {
-                    p = (step + t) % (kp - 1);
-                    q = (step - t + (kp - 1)) % (kp - 1);
-                }
-                if (p > q) {
-                    int tt = p;
-                    p = q;
-                    q = tt;
-                }
-                if (q >= k) continue;
-                double c = cs[t], s = sn[t];
-                if (s == 0.0) continue;
-                double apc = A[p * k + col], aqc = A[q * k + col];
-                A[p * k + col] = (col == q) ? 0.0 : c * apc - s * aqc;
-                A[q * k + col] = (col == p) ? 0.0 : s * apc + c * aqc;
-            }
-            __syncthreads();
         }
-        if (*flag == 0) break;
+        __syncthreads();
+        const double b = hb[j];
+        if (b == 0.0) continue;   // column already reduced (uniform)
+        const double v0 = hv0[j];
+        // p = b A_sub v: row r4 of the m x m trailing block, four partial sums per row
+        {
+            double sum = 0.0;
+            if (r4 < m)
+                for (int c = q4; c < m; c += 4) sum += A[(o + r4) * k + o + c] * (c == 0 ? v0 : A[(o + c) * k + j]);
+            sum += __shfl_xor(sum, 1, 64);
+            sum += __shfl_xor(sum, 2, 64);
+            if (q4 == 0 && r4 < m) hp[r4] = b * sum;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const double vr = lane == 0 ? v0 : A[(o + lane) * k + j];
+            const double t = wave_sum(lane < m ? vr * hp[lane] : 0.0);
+            if (lane == 0) s_K = 0.5 * b * t;
+        }
+        __syncthreads();
+        {
+            const double K = s_K;
+            if (r4 < m) {
+                const double vr = r4 == 0 ? v0 : A[(o + r4) * k + j];
+                const double wr = hp[r4] - K * vr;
+                for (int c = q4; c < m; c += 4) {
+                    const double vc = c == 0 ? v0 : A[(o + c) * k + j];
+                    const double wc = hp[c] - K * vc;
+                    A[(o + r4) * k + o + c] -= vr * wc + wr * vc;
+                }
+            }
+            if (tid == 0) {
+                A[o * k + j] = s_alpha;
+                A[j * k + o] = s_alpha;
+            }
+            if (tid >= 64 && tid - 64 < m - 1) A[j * k + o + 1 + (tid - 64)] = 0.0;   // row j past the band
+        }
         __syncthreads();
     }
+    for (int i = tid; i < k; i += kNT) {
+        hd[i] = A[i * k + i];
+        he[i] = i + 1 < k ? A[(i + 1) * k + i] : 0.0;
+    }
+    __syncthreads();
+    // 2. Q = H_0 ... H_{k-3} into V, from the last reflector to the first
+    for (int j = k - 3; j >= 0; --j) {
+        const double b = hb[j];
+        if (b == 0.0) continue;
+        const int m = k - j - 1, o = j + 1;
+        const double v0 = hv0[j];
+        // u_c = v^T V_sub[:, c], four partial sums per column
+        double u = 0.0;
+        if (r4 < m)
+            for (int r = q4; r < m; r += 4) u += (r == 0 ? v0 : A[(o + r) * k + j]) * V[(o + r) * k + o + r4];
+        u += __shfl_xor(u, 1, 64);
+        u += __shfl_xor(u, 2, 64);
+        if (q4 == 0 && r4 < m) hp[r4] = b * u;
+        __syncthreads();
+        if (r4 < m) {
+            const double vr = r4 == 0 ? v0 : A[(o + r4) * k + j];
+            for (int c = q4; c < m; c += 4) V[(o + r4) * k + o + c] -= vr * hp[c];
+        }
+        __syncthreads();
+    }
+    // 3. implicit QL on (d, e): lane i keeps d_i and e_i in registers, every lane reads
+    // them with readlane and runs the same scalar recurrence, and lane r applies each
+    // rotation to row r of V
+    if (tid < 64) {
+        const double eps = 2.220446049250313e-16;
+        double dl = lane < k ? hd[lane] : 0.0, el = lane < k ? he[lane] : 0.0;
+        auto setl = [&](double &reg, int i, double v) {
+            if (lane == i) reg = v;
+        };
+        for (int l = 0; l < k; ++l) {
+            for (int iter = 0; iter < 64; ++iter) {
+                // first m >= l with a negligible e_m (m = k - 1 when none)
+                const double dn = __shfl_down(dl, 1, 64);
+                const bool small = lane + 1 < k && fabs(el) <= eps * (fabs(dl) + fabs(dn));
+                const uint64_t sm = __ballot(small && lane >= l);
+                const int m = sm ? __ffsll((unsigned long long)sm) - 1 : k - 1;
+                if (m == l) break;
+                const double dlv = readlane_f64(dl, l), el_l = readlane_f64(el, l);
+                double g = (readlane_f64(dl, l + 1) - dlv) / (2.0 * el_l);
+                double r = sqrt(g * g + 1.0);
+                g = readlane_f64(dl, m) - dlv + el_l / (g + copysign(r, g));
+                double sn = 1.0, cn = 1.0, p = 0.0;
+                bool early = false;
+                // row `lane` of V: column i + 1 of the rotation in hand is carried in a
+                // register (the previous rotation's new column i), so LDS is only read
+                // ahead and written once per column
+                double carry = lane < k ? V[lane * k + m] : 0.0;
+                int i = m - 1;
+                for (; i >= l; --i) {
+                    const double zi = lane < k ? V[lane * k + i] : 0.0;
+                    const double ei = readlane_f64(el, i);
+                    const double f = sn * ei, bb = cn * ei;
+                    // r = |(f, g)| and 1 / r from the hardware reciprocal square root and one
+                    // Newton step (y <- y + y (1 - x y^2) / 2), which keeps the recurrence's
+                    // dependency chain short
+                    const double x = f * f + g * g;
+                    double ir = __builtin_amdgcn_rsq(x);
+                    ir = fma(0.5 * ir, fma(-x * ir, ir, 1.0), ir);
+                    r = x > 0.0 ? x * ir : 0.0;
+                    setl(el, i + 1, r);
+                    if (r == 0.0) {   // exact split: deflate and restart the block
+                        setl(dl, i + 1, readlane_f64(dl, i + 1) - p);
+                        setl(el, m, 0.0);
+                        early = true;
+                        break;
+                    }
+                    sn = f * ir;
+                    cn = g * ir;
+                    g = readlane_f64(dl, i + 1) - p;
+                    r = (readlane_f64(dl, i) - g) * sn + 2.0 * cn * bb;
+                    p = sn * r;
+                    setl(dl, i + 1, g + p);
+                    g = cn * r - bb;
+                    if (lane < k) V[lane * k + i + 1] = sn * zi + cn * carry;
+                    carry = cn * zi - sn * carry;
+                }
+                if (lane < k) V[lane * k + i + 1] = carry;   // column l, or the split's i + 1
+                if (!early) {
+                    setl(dl, l, readlane_f64(dl, l) - p);
+                    setl(el, l, g);
+                    setl(el, m, 0.0);
+                }
+            }
+        }
+        if (lane < k) hd[lane] = dl;
+    }
+    __syncthreads();
+    for (int i = tid; i < k; i += kNT) A[i * k + i] = hd[i];
+    __syncthreads();
 }
 
 // Cross-lane move of a double by a DPP control (lanes whose source lies outside the
@@ -256,13 +335,6 @@ __device__ __forceinline__ double block_sum_waves(double v, double *sh) {
     return s;
 }
 
-// Value of v in lane l of the wavefront (l wave-uniform).
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
 
 // Gauss-Jordan inversion of the k x k matrix A (k <= KP, LDS, row-major) by one
 // wavefront, held in registers: lane c keeps column c of A padded to KP x KP with the
@@ -347,9 +419,8 @@ __device__ __forceinline__ bool inv_gj(int k, const double *A, double *G, double
 
 // Moore-Penrose pseudo-inverse of the symmetric k x k matrix A (LDS, left intact),
 // result in G; V is scratch.  The Gauss-Jordan inverse (inv_gj) is taken when it is
-// accepted; otherwise the Jacobi eigendecomposition decides.
-__device__ __forceinline__ void pinv_sym_lds(int k, const double *A, double *V, double *G, double *sh, double *cs, double *sn,
-                             int *flag, int *rank_sh) {
+// accepted; otherwise the eigendecomposition (sym_eig) decides.
+__device__ __forceinline__ void pinv_sym_lds(int k, const double *A, double *V, double *G, double *sh, int *rank_sh) {
     const int tid = threadIdx.x;
     if (inv_gj(k, A, G, sh)) {
         if (tid == 0) *rank_sh = k;
@@ -359,7 +430,7 @@ __device__ __forceinline__ void pinv_sym_lds(int k, const double *A, double *V, 
     // V and G are free again: eigendecomposition of a copy of A
     for (int w = tid; w < k * k; w += kNT) G[w] = A[w];
     __syncthreads();
-    jacobi_eig(k, G, V, cs, sn, flag);
+    sym_eig(k, G, V);
     // eigenvalues (diagonal of G) are copied out before G is overwritten
     __shared__ double lam[kMaxK];
     for (int e = tid; e < k; e += kNT) lam[e] = G[e * k + e];

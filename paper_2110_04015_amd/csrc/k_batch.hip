@@ -183,8 +183,8 @@ __global__ __launch_bounds__(kNT) void k_bpinv(int N, const BatchProb *__restric
                                                int64_t *__restrict__ blk_dp, double *__restrict__ alpha,
                                                double *__restrict__ gamma) {
     __shared__ double A[kMaxK * kMaxK], V[kMaxK * kMaxK], G[kMaxK * kMaxK];
-    __shared__ double gam[kMaxK], cs[kMaxK], sn[kMaxK], sh[kNT];
-    __shared__ int flag, rank;
+    __shared__ double gam[kMaxK], sh[kNT];
+    __shared__ int rank;
     const int b = blockIdx.x;
     BatchDyn *dp = dyn + b;
     if (dp->done) return;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kNT) void k_bpinv(int N, const BatchProb *__restric
         A[w] = 0.5 * (G[i * k + j] + G[j * k + i]);
     }
     __syncthreads();
-    pinv_sym_lds(k, A, V, G, sh, cs, sn, &flag, &rank);
+    pinv_sym_lds(k, A, V, G, sh, &rank);
     const int64_t dpo = dp->dp_used;
     double *Dout = Dp + P.colbase * N + dpo;
     for (int w = threadIdx.x; w < k * k; w += kNT) Dout[w] = G[w];

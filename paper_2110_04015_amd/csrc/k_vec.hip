@@ -572,8 +572,8 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
                                                     double *__restrict__ alpha, double *__restrict__ sc,
                                                     BlockEntry blk) {
     __shared__ double A[kMaxK * kMaxK], V[kMaxK * kMaxK], G[kMaxK * kMaxK];
-    __shared__ double gam[kMaxK], cs[kMaxK], sn[kMaxK], sh[kNT];
-    __shared__ int flag, rank;
+    __shared__ double gam[kMaxK], sh[kNT];
+    __shared__ int rank;
     const int tid = threadIdx.x;
     const int tot = k * k + k;
     for (int idx = tid; idx < tot; idx += kNT) {
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
         A[w] = 0.5 * (G[i * k + j] + G[j * k + i]);
     }
     __syncthreads();
-    pinv_sym_lds(k, A, V, G, sh, cs, sn, &flag, &rank);
+    pinv_sym_lds(k, A, V, G, sh, &rank);
     for (int w = tid; w < k * k; w += kNT) Dp[w] = G[w];
     for (int a = tid; a < k; a += kNT) {
         double s = 0.0;
@@ -640,11 +640,11 @@ void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, d
 __global__ __launch_bounds__(kNT) void k_pinv_sym(int k, const double *__restrict__ Ain, double *__restrict__ Ap,
                                                   int32_t *__restrict__ rank_out) {
     __shared__ double A[kMaxK * kMaxK], V[kMaxK * kMaxK], G[kMaxK * kMaxK];
-    __shared__ double cs[kMaxK], sn[kMaxK], sh[kNT];
-    __shared__ int flag, rank;
+    __shared__ double sh[kNT];
+    __shared__ int rank;
     for (int w = threadIdx.x; w < k * k; w += kNT) A[w] = Ain[w];
     __syncthreads();
-    pinv_sym_lds(k, A, V, G, sh, cs, sn, &flag, &rank);
+    pinv_sym_lds(k, A, V, G, sh, &rank);
     for (int w = threadIdx.x; w < k * k; w += kNT) Ap[w] = G[w];
     if (threadIdx.x == 0 && rank_out) *rank_out = rank;
 }
