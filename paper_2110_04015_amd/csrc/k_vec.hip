@@ -950,8 +950,8 @@ __device__ inline int next_kn(const double *__restrict__ sc, int kn_max) {
 // per history block.  A block wider than one column first stages Delta_j^+ (transposed)
 // and its Phi rows in LDS with coalesced loads; each output is then one running sum over
 // b in ascending order, taken from LDS (a multidirectional block's outputs in 4 x 4 tiles
-// per thread).  For a one-column Z, Phi of a history column is the sum of its segments,
-// one wavefront butterfly per column.
+// per thread).  For a one-column Z, Phi of a history column is the sum of its segments
+// and beta_j = Delta_j^+ Phi, each output by four threads and two shuffles.
 __global__ __launch_bounds__(kNT) void k_beta(const int32_t *__restrict__ blk_off, const int32_t *__restrict__ blk_k,
                                               const int64_t *__restrict__ blk_dp, const double *__restrict__ Dp,
                                               const double *__restrict__ Phi, const double *__restrict__ sc,
@@ -1013,18 +1013,24 @@ __global__ __launch_bounds__(kNT) void k_beta(const int32_t *__restrict__ blk_of
         }
     }
     __syncthreads();
-    if (kn == 1) {   // one-column Z: Phi of column off + b is the sum of its segments (one wavefront each)
+    if (kn == 1) {   // one-column Z: Phi of column off + b is the sum of its segments
+        // four threads per column (or per output row): strided partial sums, then two
+        // shuffles within the four, a fixed order
         __shared__ double f1[kMaxK];
-        for (int b = tid >> 6; b < kj; b += kNT / 64) {
-            const double f = wave_sum(lane < seg ? sF[b * seg + lane] : 0.0);
-            if (lane == 0) f1[b] = f;
-        }
+        const int r4 = tid >> 2, q4 = tid & 3;
+        double f = 0.0;
+        if (r4 < kj)
+            for (int g = q4; g < seg; g += 4) f += sF[r4 * seg + g];
+        f += __shfl_xor(f, 1, 64);
+        f += __shfl_xor(f, 2, 64);
+        if (q4 == 0 && r4 < kj) f1[r4] = f;
         __syncthreads();
-        for (int a = tid; a < kj; a += kNT) {
-            double s = 0.0;
-            for (int b = 0; b < kj; ++b) s += sDt[b * kj + a] * f1[b];
-            beta[off + a] = s;
-        }
+        double s = 0.0;
+        if (r4 < kj)
+            for (int b = q4; b < kj; b += 4) s += sDt[b * kj + r4] * f1[b];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (q4 == 0 && r4 < kj) beta[off + r4] = s;
         return;
     }
     // multidirectional: segment p is subset p; rows are padded with zeros to hist_ldb(kn)
