@@ -73,6 +73,8 @@ def main(argv=None) -> int:
     ap.add_argument("--n-cams", type=int, default=240)
     ap.add_argument("--quick", action="store_true", help="three problems, fewer tau and N values")
     ap.add_argument("--implicit-only", action="store_true")
+    ap.add_argument("--taus", default=None, help="comma-separated tau values ('' for none)")
+    ap.add_argument("--ns", default=None, help="comma-separated N values ('' for none)")
     args = ap.parse_args(argv)
     t0 = time.time()
     probs = density_series(args.seed, args.n_cams)
@@ -80,6 +82,10 @@ def main(argv=None) -> int:
         probs = [probs[0], probs[2], probs[4]]
     taus = (0.0, 1.0, 3.3, 10.0, 1e9) if args.quick else TAUS
     Ns = (4, 16, 64) if args.quick else NS
+    if args.taus is not None:
+        taus = tuple(float(t) for t in args.taus.split(",") if t.strip())
+    if args.ns is not None:
+        Ns = tuple(int(n) for n in args.ns.split(",") if n.strip())
 
     def emit(rec):
         print(json.dumps(rec), flush=True)
