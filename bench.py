@@ -188,14 +188,7 @@ def run_dense(seed, log):
     ie = ge.explicit_schur_info()
     ex = {"build_s": round(time.time() - t, 3), "nnz_blocks": ie["nnz_blocks"], "bytes": ie["bytes"],
           "assembly_ms": round(ie["assembly_ms"], 3)}
-    ge.matvec(v, out=y)
-    ge.profile(True)
-    ge.profile_read(reset=True)
-    for _ in range(50):
-        ge.matvec(v, out=y)
-    kms, nl = ge.profile_read(reset=True)
-    ge.profile(False)
-    ms = kms / max(nl, 1)
+    ms = ge.matvec_timed(v, reps=50, out=y)   # back-to-back launches, events around all 50
     ex["matvec_ms"] = round(ms, 5)
     ex["matvec_gbs"] = round((ie["bytes"] + ge.n * 8 * 2) / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
     for name, f in [("pcg_fp64", lambda: ge.pcg(eps=1e-6, max_iter=1000)),
@@ -434,14 +427,7 @@ def main():
                     "bytes": info_e["bytes"], "assembly_ms": round(info_e["assembly_ms"], 3)}
         v = torch.randn(ge.n, dtype=torch.float64, device="cuda")
         y = torch.empty_like(v)
-        ge.matvec(v, out=y)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(50):
-            ge.matvec(v, out=y)
-        e1.record()
-        torch.cuda.synchronize()
-        mv_ms = e0.elapsed_time(e1) / 50
+        mv_ms = ge.matvec_timed(v, reps=50, out=y)   # back-to-back launches, events around all 50
         explicit["matvec_ms"] = round(mv_ms, 4)
         explicit["matvec_gbs"] = round((info_e["bytes"] + ge.n * 8 * 2) / (mv_ms * 1e-3) / 1e9, 1)
         for name, f in [("pcg_fp64", lambda: ge.pcg(eps=1e-6, max_iter=1000)),

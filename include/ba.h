@@ -493,6 +493,15 @@ ba_status ba_lm_solve(const ba_scene_desc *scene, double *cams, double *X, const
  * `reps` launches on `stream`.  The practical ceiling for that kernel's bandwidth. */
 ba_status ba_stream_read_gbs(int64_t bytes, int32_t reps, double *gbs, void *stream);
 
+/* Measurement helper (not part of the method): y = S v, as ba_schur_matvec, launched
+ * `reps` >= 1 times back to back on the system's stream after one untimed launch, with
+ * HIP events around the whole sequence and no synchronisation between launches.
+ * *ms_per (host) receives the elapsed time divided by reps: the kernel time plus the gaps
+ * between consecutive launches, without the host's per-call overhead.  v, y: device [n].
+ * Errors as ba_schur_matvec; INVALID_ARG for reps < 1. */
+ba_status ba_schur_matvec_timed(ba_system *sys, const double *v, double *y, int32_t precision, int32_t reps,
+                                double *ms_per);
+
 const char *ba_status_string(int32_t status);
 const char *ba_last_error(void);
 

@@ -242,6 +242,17 @@ class System:
                "ba_schur_matvec")
         return y
 
+    def matvec_timed(self, v, reps=50, precision="fp64", out=None):
+        """Average ms per S product over `reps` back-to-back launches (ba_schur_matvec_timed)."""
+        torch = _torch()
+        y = out if out is not None else self._new(self.n)
+        ms = C.c_double()
+        _check(lib().ba_schur_matvec_timed(self.h, _dev_ptr(v, torch.float64, self.n, "v"),
+                                           _dev_ptr(y, torch.float64, self.n, "y"),
+                                           PREC[precision] if isinstance(precision, str) else int(precision), int(reps),
+                                           C.byref(ms)), "ba_schur_matvec_timed")
+        return ms.value
+
     def matvec_noalloc(self, v, out, precision="fp64"):
         """y = S v through the allocation-free entry point (ba_schur_matvec_noalloc); out is required."""
         torch = _torch()

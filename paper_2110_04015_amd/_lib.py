@@ -120,6 +120,8 @@ SIGNATURES = [
     ("ba_lm_solve", C.c_int, [C.POINTER(SceneDesc), C.c_void_p, C.c_void_p, C.POINTER(LMOpts), C.c_void_p,
                               C.POINTER(LMStats)]),
     ("ba_stream_read_gbs", C.c_int, [C.c_int64, C.c_int32, C.POINTER(C.c_double), C.c_void_p]),
+    ("ba_schur_matvec_timed", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                        C.POINTER(C.c_double)]),
     ("ba_explicit_schur_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_double)]),
     ("ba_status_string", C.c_char_p, [C.c_int32]),

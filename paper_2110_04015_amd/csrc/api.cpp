@@ -944,6 +944,33 @@ ba_status ba_schur_matvec(ba_system *s, const double *v, double *y, int32_t prec
     return BA_OK;
 }
 
+ba_status ba_schur_matvec_timed(ba_system *s, const double *v, double *y, int32_t precision, int32_t reps,
+                                double *ms_per) {
+    if (!s || !v || !y || !ms_per) return fail(BA_ERR_INVALID_ARG, "NULL argument");
+    if (reps < 1) return fail(BA_ERR_INVALID_ARG, "reps must be >= 1");
+    ba_status st = ensure_precision(s, precision);
+    if (st != BA_OK) return st;
+    const SchurArgs a = schur_args(s, precision);
+    matvec(s, a, v, y);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(BA_ERR_HIP, "hipEventCreate failed");
+    }
+    (void)hipEventRecord(e0, s->stream);
+    for (int i = 0; i < reps; ++i) matvec(s, a, v, y);
+    (void)hipEventRecord(e1, s->stream);
+    const hipError_t err = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (err == hipSuccess) (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return fail(BA_ERR_HIP, std::string("timed S products: ") + hipGetErrorString(err));
+    *ms_per = (double)ms / reps;
+    return BA_OK;
+}
+
 ba_status ba_schur_matmat_grouped(ba_system *s, int32_t N, const double *z, double *Y, int32_t precision) {
     if (!s || !z || !Y) return fail(BA_ERR_INVALID_ARG, "NULL argument");
     if (N < 1 || N > s->np) return fail(BA_ERR_INVALID_ARG, "N must be in [1, n_cams]");

@@ -117,3 +117,19 @@ def test_rows_beyond_one_wavefront_lds():
     xo, so = o.pcg(eps=0.0, imax=5)
     assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) < 1e-9
     g.close()
+
+
+@pytest.mark.parametrize("explicit", [False, True])
+def test_timed_products_equal_the_product(explicit):
+    """ba_schur_matvec_timed (back-to-back launches for measurement) leaves the same y as
+    ba_schur_matvec and reports a positive time; reps < 1 is refused."""
+    p = synth.walk_problem(n_cams=120, n_lms=6000, seed=4, name="walk120")
+    g = ba.System.from_problem(p, explicit_schur=explicit)
+    v = torch.from_numpy(np.random.default_rng(5).standard_normal(g.n)).cuda()
+    y0 = g.matvec(v)
+    y1 = torch.empty_like(y0)
+    ms = g.matvec_timed(v, reps=7, out=y1)
+    assert ms > 0.0 and torch.equal(y0, y1)
+    with pytest.raises(ba.BAError):
+        g.matvec_timed(v, reps=0)
+    g.close()
