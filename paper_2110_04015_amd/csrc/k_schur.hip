@@ -447,6 +447,7 @@ struct MultiBuf {
     dbl2_t vi[3];
     MultiSlot m;
     uint32_t obase;           // tile_oidx of the tile
+    int o0, o1;               // output rows of the slot's first two pairs (kept with the tile's loads)
 };
 
 // The reduced-precision products sum each pair across its lanes (a pair's observations
@@ -473,6 +474,13 @@ __device__ __forceinline__ void fetch_mtile(const MultiArgs &a, const double *__
 #pragma unroll
     for (int q = 0; q < 3; ++q) b.vi[q] = p[q];
     b.obase = a.tile_oidx[t];
+    // The first two output rows travel with the tile: a load issued while the tile is
+    // processed would wait for every load in flight, the next tile's included.  A padding
+    // slot reads the tile's first entry (every tile holds an observation) and ignores it.
+    const uint16_t *oi = a.oidx + b.obase + (valid ? m.ooff : 0u);
+    const int cnt = valid ? (int)((m.mm >> 16) & 0xFFu) : 1;
+    b.o0 = oi[0];
+    b.o1 = oi[cnt > 1 ? 1 : 0];
 }
 
 // One tile: e = J_p z_c; g per (landmark, subset) pair = sum over the pair's
@@ -483,8 +491,8 @@ __device__ __forceinline__ void fetch_mtile(const MultiArgs &a, const double *__
 // p forms h of pair p.
 template <typename T, int DP, bool SEG>
 __device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[2 * DP + 6], const double (&zb)[DP],
-                                           const dbl2_t (&vi)[3], const MultiSlot &m, uint32_t obase, int lane,
-                                           double *yloc, double *gloc, double *hloc) {
+                                           const dbl2_t (&vi)[3], const MultiSlot &m, uint32_t obase, int o0, int o1,
+                                           int lane, double *yloc, double *gloc, double *hloc) {
     constexpr int L0 = 2 * DP, L1 = 2 * DP + 3;   // J_l rows 0 and 1
     const bool valid = m.mm != kPad;
     T e0 = 0, e1 = 0;
@@ -528,9 +536,7 @@ __device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[2 * 
     wave_sync();
     if (valid) {
         const int base = (int)((m.mm >> 8) & 0xFFu), cnt = (int)((m.mm >> 16) & 0xFFu);
-        const uint16_t *oi = a.oidx + obase + m.ooff;
-        for (int j = 0; j < cnt; ++j) {
-            const int pj = base + j;
+        auto add_pair = [&](int pj, int o) {
             const T h0 = (T)hloc[pj * 3], h1 = (T)hloc[pj * 3 + 1], h2 = (T)hloc[pj * 3 + 2];
             T f0 = -(J[L0] * h0 + J[L0 + 1] * h1 + J[L0 + 2] * h2);
             T f1 = -(J[L1] * h0 + J[L1 + 1] * h1 + J[L1 + 2] * h2);
@@ -538,10 +544,14 @@ __device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[2 * 
                 f0 += e0;
                 f1 += e1;
             }
-            const int o = oi[j];
 #pragma unroll
             for (int k = 0; k < DP; ++k) atomicAdd(&yloc[o * DP + k], (double)(J[k] * f0 + J[DP + k] * f1));
-        }
+        };
+        add_pair(base, o0);   // cnt >= 1 on a valid slot
+        if (cnt > 1) add_pair(base + 1, o1);
+        // landmarks spanning three subsets or more: the rest of the rows from memory
+        const uint16_t *oi = a.oidx + obase + m.ooff;
+        for (int j = 2; j < cnt; ++j) add_pair(base + j, oi[j]);
     }
     wave_sync();
 }
@@ -552,9 +562,9 @@ __device__ __forceinline__ void process_mtile(const MultiArgs &a, const MultiBuf
     if constexpr (PREC == 2) {
         T J[2 * DP + 6];
         Stream<2, DP>::template unpack<T>(b.r.w, J);
-        multi_tile<T, DP, true>(a, J, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
+        multi_tile<T, DP, true>(a, J, b.z, b.vi, b.m, b.obase, b.o0, b.o1, lane, yloc, gloc, hloc);
     } else {
-        multi_tile<T, DP, PREC != 0>(a, b.r.v, b.z, b.vi, b.m, b.obase, lane, yloc, gloc, hloc);
+        multi_tile<T, DP, PREC != 0>(a, b.r.v, b.z, b.vi, b.m, b.obase, b.o0, b.o1, lane, yloc, gloc, hloc);
     }
 }
 
