@@ -52,6 +52,34 @@ __device__ __forceinline__ double wave_partials(const double *__restrict__ a, in
     return wave_sum((s0 + s1) + (s2 + s3));
 }
 
+// Sums of the pairs (a[2 b], a[2 b + 1]) over b < nb (16-byte aligned a) by the calling
+// wavefront (all 64 lanes must call): lane l adds pairs l, l + 64, ... in that order, eight
+// 16-byte loads in flight at a time (issued unconditionally, pairs past nb read pair 0 and
+// are dropped), then the butterfly.  The order is fixed by nb alone.
+__device__ __forceinline__ void wave_pair_sums(const double *__restrict__ a, int nb, double &s0, double &s1) {
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x & 63;
+    const d2_t *p = reinterpret_cast<const d2_t *>(a);
+    double x0 = 0.0, x1 = 0.0;
+    for (int b0 = 0; b0 < nb; b0 += 512) {
+        d2_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int b = b0 + 64 * j + lane;
+            v[j] = p[b < nb ? b : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (b0 + 64 * j + lane < nb) {
+                x0 += v[j].x;
+                x1 += v[j].y;
+            }
+        }
+    }
+    s0 = wave_sum(x0);
+    s1 = wave_sum(x1);
+}
+
 // z_c = D_c^-1 r_c with the packed lower Cholesky factor of a DP x DP block (row i
 // holds L[i][0..i]; DP (DP + 1) / 2 values)
 template <int DP>

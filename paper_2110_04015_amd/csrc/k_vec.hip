@@ -611,8 +611,8 @@ __global__ __launch_bounds__(64) void k_pinv_alpha1(const double *__restrict__ p
                                                     double *__restrict__ Dp, double *__restrict__ gamma,
                                                     double *__restrict__ alpha, double *__restrict__ sc,
                                                     BlockEntry blk) {
-    const double d = wave_partials(partials, 2, nblocks);       // Q^T P
-    const double g = wave_partials(partials + 1, 2, nblocks);   // P^T r
+    double d, g;   // Q^T P, P^T r
+    wave_pair_sums(partials, nblocks, d, g);
     if (threadIdx.x != 0) return;
     const bool nz = fabs(d) > 2.220446049250313e-16 * fabs(d);
     const double dp = nz ? 1.0 / d : 0.0;
@@ -684,22 +684,39 @@ void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, co
 }
 
 // Alg. 2's stop test and tau-test from |r_{i+1}|^2 and rho = r_{i+1}^T M^-1 r_{i+1}:
-// t_i = gamma_i^T alpha_i / rho; sc[SC_SKIPM], sc[SC_KN] and sc[SC_SKIPS] give the next
-// block's width to the kernels launched ahead of the host's read-back (one thread)
+// t_i = gamma_i^T alpha_i / rho (ga = gamma_i^T alpha_i); sc[SC_SKIPM], sc[SC_KN] and
+// sc[SC_SKIPS] give the next block's width to the kernels launched ahead of the host's
+// read-back.  One thread; the values are also returned in v (indexed by SC_*).
+struct McgScalars {
+    double rr, rho, t, skipm, kn, skips;
+};
+__device__ inline McgScalars mcg_scalars_form(double rr, double rho, double ga, double rr0, int N, double tau,
+                                              double eps) {
+    McgScalars v;
+    v.rr = rr;
+    v.rho = rho;
+    v.t = rho > 0.0 ? ga / rho : INFINITY;
+    const bool converged = sqrt(rr) < eps * sqrt(rr0);
+    const bool multi = N > 1 && v.t < tau && !converged;
+    v.skipm = multi ? 0.0 : 1.0;
+    v.kn = converged ? 0.0 : multi ? (double)N : 1.0;
+    v.skips = (!converged && !multi) ? 0.0 : 1.0;
+    return v;
+}
+__device__ inline void mcg_scalars_put(const McgScalars &v, double *__restrict__ sc) {
+    sc[SC_RR] = v.rr;
+    sc[SC_RHO] = v.rho;
+    sc[SC_T] = v.t;
+    sc[SC_SKIPM] = v.skipm;
+    sc[SC_KN] = v.kn;
+    sc[SC_SKIPS] = v.skips;
+}
 __device__ inline void mcg_scalars_store(double rr, double rho, int k, const double *__restrict__ gamma,
                                          const double *__restrict__ alpha, double *__restrict__ sc, int N,
                                          double tau, double eps) {
     double ga = 0.0;
     for (int a = 0; a < k; ++a) ga += gamma[a] * alpha[a];
-    const double t = rho > 0.0 ? ga / rho : INFINITY;
-    sc[SC_RR] = rr;
-    sc[SC_RHO] = rho;
-    sc[SC_T] = t;
-    const bool converged = sqrt(rr) < eps * sqrt(sc[SC_RR0]);
-    const bool multi = N > 1 && t < tau && !converged;
-    sc[SC_SKIPM] = multi ? 0.0 : 1.0;
-    sc[SC_KN] = converged ? 0.0 : multi ? (double)N : 1.0;
-    sc[SC_SKIPS] = (!converged && !multi) ? 0.0 : 1.0;
+    mcg_scalars_put(mcg_scalars_form(rr, rho, ga, sc[SC_RR0], N, tau, eps), sc);
 }
 
 // sc[SC_RR] from the |r|^2 partials; rho = r^T M^-1 r from its partials; t = gamma^T alpha / rho
@@ -720,6 +737,12 @@ __global__ __launch_bounds__(64) void k_mcg_scalars(int k, const double *__restr
 // the rows its D^-1 solves read (kept in LDS).  Each block leaves its |r|^2 and r^T z in
 // partials[2 b], [2 b + 1]; the block that arrives last (an agent-scope counter, reset to
 // zero by that block) adds them in block order and stores the scalars.
+// The kernel is a chain of dependent memory round trips, so every load that needs nothing
+// formed here goes first, unconditionally (threads without a row read row 0 and a camera
+// without the block's first camera, and ignore them): x, r, the block's first P and Q
+// columns, the Cholesky factor of the thread's camera, the scalars already in sc, and
+// gamma of a block formed by the pseudo-inverse kernel.  Their latencies then overlap
+// the reduction of the Gram partials.
 template <int DP>
 __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__restrict__ P,
                                                  const double *__restrict__ Q, double *alpha,
@@ -730,31 +753,45 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
                                                  double *__restrict__ host_sc, double tag, int N, double tau,
                                                  double eps, XrzGram g1) {
     constexpr int CB = kNT / DP;
+    constexpr int NL = DP * (DP + 1) / 2;
     __shared__ double sr[CB * DP];
     __shared__ double sh[kNT];
-    __shared__ double al[kMaxK];
+    __shared__ double al[kMaxK], ga_sh[kMaxK];
+    __shared__ double rank_sh;
     __shared__ int last;
     const int64_t n = (int64_t)np * DP;
     const int c0 = blockIdx.x * CB;
     const int cams = min(CB, np - c0);
     const int t = threadIdx.x;
+    const bool row = t < cams * DP;
+    const int64_t i = (int64_t)c0 * DP + (row ? t : 0);
+    const double xi = x[i], ri = r[i], p0 = P[i], q0 = Q[i];
+    double Lc[NL];
+    {
+        const double *Lp = Dchol + (int64_t)(c0 + (t < cams ? t : 0)) * NL;
+#pragma unroll
+        for (int e = 0; e < NL; ++e) Lc[e] = Lp[e];
+    }
+    const double scv = sc[t < SC_COUNT ? t : 0];
     if (g1.part) {
         // one-column block: Delta = Q^T P and gamma = P^T r from the camera reduction's
         // partials, added in the same order by every block; Delta^+ = 1 / Delta unless
         // Delta is zero (or not finite), the 1 x 1 case of the pseudo-inverse's rank rule.
         // Block 0 stores Delta^+, gamma, alpha, the rank and the history block entry.
         if (t < 64) {
-            const double d = wave_partials(g1.part, 2, g1.nb);
-            const double gg = wave_partials(g1.part + 1, 2, g1.nb);
+            double d, gg;
+            wave_pair_sums(g1.part, g1.nb, d, gg);
             if (t == 0) {
                 const bool nz = fabs(d) > 2.220446049250313e-16 * fabs(d);
                 const double dpv = nz ? 1.0 / d : 0.0;
                 al[0] = dpv * gg;
+                ga_sh[0] = gg;
+                rank_sh = nz ? 1.0 : 0.0;
                 if (blockIdx.x == 0) {
                     g1.Dp[0] = dpv;
                     gamma[0] = gg;
                     alpha[0] = al[0];
-                    sc[SC_RANK] = nz ? 1.0 : 0.0;
+                    sc[SC_RANK] = rank_sh;
                     if (g1.blk.off) {
                         g1.blk.off[g1.blk.j] = g1.blk.first;
                         g1.blk.k[g1.blk.j] = 1;
@@ -764,19 +801,24 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
             }
         }
     } else {
-        for (int a = t; a < k; a += kNT) al[a] = alpha[a];
+        for (int a = t; a < k; a += kNT) {
+            al[a] = alpha[a];
+            ga_sh[a] = gamma[a];
+        }
+        if (t == SC_RANK) rank_sh = scv;
     }
     __syncthreads();
     double rr = 0.0;
-    if (t < cams * DP) {
-        const int64_t i = (int64_t)c0 * DP + t;
+    if (row) {
         double dx = 0.0, dr = 0.0;
-        for (int a = 0; a < k; ++a) {
+        dx += p0 * al[0];
+        dr += q0 * al[0];
+        for (int a = 1; a < k; ++a) {
             dx += P[(int64_t)a * n + i] * al[a];
             dr += Q[(int64_t)a * n + i] * al[a];
         }
-        x[i] += dx;
-        const double v = r[i] - dr;
+        x[i] = xi + dx;
+        const double v = ri - dr;
         r[i] = v;
         sr[t] = v;
         rr = v * v;
@@ -787,7 +829,7 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
         double rc[DP], zc[DP];
 #pragma unroll
         for (int e = 0; e < DP; ++e) rc[e] = sr[t * DP + e];
-        chol_solve_packed<DP>(Dchol + (int64_t)(c0 + t) * (DP * (DP + 1) / 2), rc, zc);
+        chol_solve_packed<DP>(Lc, rc, zc);
 #pragma unroll
         for (int e = 0; e < DP; ++e) {
             z[(int64_t)(c0 + t) * DP + e] = zc[e];
@@ -805,28 +847,25 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
     __syncthreads();
     if (!last || t >= 64) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const double srr = wave_partials(partials, 2, gridDim.x);
-    const double srho = wave_partials(partials + 1, 2, gridDim.x);
-    // lane 0 forms and stores the scalars, then holds all SC_COUNT of them in registers
-    // (its own stores, and the other kernels' values it acquired above); the other lanes
-    // receive them by cross-lane broadcast, never by reading what lane 0 just stored
-    double held[SC_COUNT];
+    double srr, srho;
+    wave_pair_sums(partials, gridDim.x, srr, srho);
+    // lane 0 forms and stores the scalars; every lane takes them by cross-lane broadcast
+    // (never by reading what lane 0 just stored), the rest of sc from its early load
+    McgScalars v{};
     if (t == 0) {
-        mcg_scalars_store(srr, srho, k, gamma, alpha, sc, N, tau, eps);
+        double ga = 0.0;
+        for (int a = 0; a < k; ++a) ga += ga_sh[a] * al[a];
+        static_assert(SC_RR0 == 0, "lane 0 loaded |r_0|^2 early");
+        v = mcg_scalars_form(srr, srho, ga, scv, N, tau, eps);
+        mcg_scalars_put(v, sc);
         __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-        for (int i = 0; i < SC_COUNT; ++i) held[i] = sc[i];
-    } else {
-#pragma unroll
-        for (int i = 0; i < SC_COUNT; ++i) held[i] = 0.0;
     }
     if (host_sc) {   // all the scalars, for the host's read-back: lane i writes scalar i
-        double mine = 0.0;
-#pragma unroll
-        for (int i = 0; i < SC_COUNT; ++i) {
-            const double b = __shfl(held[i], 0, 64);
-            if (t == i) mine = b;
-        }
+        const double b_rr = __shfl(v.rr, 0, 64), b_rho = __shfl(v.rho, 0, 64), b_t = __shfl(v.t, 0, 64);
+        const double b_sm = __shfl(v.skipm, 0, 64), b_kn = __shfl(v.kn, 0, 64), b_ss = __shfl(v.skips, 0, 64);
+        double mine = t == SC_RANK ? rank_sh : scv;
+        mine = t == SC_RR ? b_rr : t == SC_RHO ? b_rho : t == SC_T ? b_t : mine;
+        mine = t == SC_SKIPM ? b_sm : t == SC_KN ? b_kn : t == SC_SKIPS ? b_ss : mine;
         if (t < SC_COUNT) host_sc[t] = mine;
         __threadfence_system();   // the values reach the host before the tag
         if (t == 0) host_sc[SC_COUNT] = tag;
