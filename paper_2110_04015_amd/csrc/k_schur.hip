@@ -334,6 +334,9 @@ __device__ __forceinline__ double wave_rows(const double *__restrict__ rows, int
 // contiguous (camera-major); one wavefront per camera (wave_rows).  With gram, block b
 // also leaves gram[2 b] = sum of y_c . v_c and gram[2 b + 1] = sum of v_c . gr_c over its
 // four cameras (the Gram products Q^T P and P^T r of a one-column block, Q = S P).
+// The skip flag, the camera's row range and its entries of v, diag(U) and gr are
+// requested together, before anything waits on one of them (a wavefront past the last
+// camera reads the last camera's and drops them).
 template <int DP>
 __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restrict__ ptr,
                                                  const double *__restrict__ partial,
@@ -342,22 +345,26 @@ __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restri
                                                  const int32_t *__restrict__ cam_seg,
                                                  const int32_t *__restrict__ seg_skip, double *__restrict__ gram,
                                                  const double *__restrict__ gr) {
-    if (done && *done != 0.0) return;
     __shared__ double sh[4][64];
     __shared__ double gsum[2][4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + w;
+    const int cl = c < np ? c : np - 1;
+    const int64_t i = (int64_t)cl * DP + (lane < DP ? lane : 0);
+    const double dn = done ? *done : 0.0;
+    const int32_t ra = ptr[cl], rb = ptr[cl + 1];
+    const double vi = v[i], du = dU[i];
+    const double gi = gram ? gr[i] : 0.0;
+    if (dn != 0.0) return;
     double qp = 0.0, pr = 0.0;
     if (c < np && !(seg_skip && seg_skip[cam_seg[c]])) {   // uniform per wavefront
-        const double t = wave_rows<DP>(partial, ptr[c], ptr[c + 1], sh[w]);
+        const double t = wave_rows<DP>(partial, ra, rb, sh[w]);
         if (lane < DP) {
-            const int64_t i = (int64_t)c * DP + lane;
-            const double vi = v[i];
-            const double yi = dU[i] * vi + t;
+            const double yi = du * vi + t;
             y[i] = yi;
             if (gram) {
                 qp = yi * vi;
-                pr = vi * gr[i];
+                pr = vi * gi;
             }
         }
     }

@@ -1264,7 +1264,8 @@ __global__ __launch_bounds__(64) void k_hist_wide(int64_t n, int h, HistSlices h
 
 // y = 0 (mat0 = 0): P_new from the P slices; mat0 = 1: Q_new from the Q slices
 // (multidirectional blocks only, their base Y = S Z already in the Q columns); no
-// slices: P_new = Z_p
+// slices: P_new = Z_p.  The slices are added in ascending order, eight loads in flight
+// at a time (issued unconditionally: slices past the last read slice 0 and are dropped).
 __global__ void k_hist_final(int64_t n, HistSlices hs, const double *__restrict__ scratch,
                              const double *__restrict__ z, int gs, int N, const double *__restrict__ sc, int kn_max,
                              int mat, double *__restrict__ Pn, double *__restrict__ Qn) {
@@ -1274,9 +1275,17 @@ __global__ void k_hist_final(int64_t n, HistSlices hs, const double *__restrict_
     const int nslices = kn == 1 ? hs.one : hs.multi;
     const int p = (int)(i / n);
     const int64_t row = i - (int64_t)p * n;
-    const double *sp = scratch + (int64_t)mat * nslices * kn * n;
+    const double *sp = scratch + (int64_t)mat * nslices * kn * n + (int64_t)p * n + row;
+    const int64_t sstride = (int64_t)kn * n;
     double s = 0.0;
-    for (int ks = 0; ks < nslices; ++ks) s += sp[((int64_t)ks * kn + p) * n + row];
+    for (int k0 = 0; k0 < nslices; k0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = sp[(k0 + u < nslices ? k0 + u : 0) * sstride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k0 + u < nslices) s += v[u];
+    }
     double *out = mat ? Qn : Pn;
     double base;
     if (mat) {
