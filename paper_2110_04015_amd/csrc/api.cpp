@@ -1236,7 +1236,8 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
     const int64_t hc = s->hist_cap_cols;
     double *Ph = s->hist, *Qh = s->hist + hc * n;
     // mixed precision: the reorthogonalisation reads (Phi and the history products) may
-    // take an FP32 copy of the history, each block copied once it is final
+    // take an FP32 copy of the history: block 0 is copied, every later block's P and Q
+    // columns are written in both precisions by the kernels that finish them
     const bool h32 = prec != 0 && opts.history_fp32 != 0;
     float *P32 = nullptr, *Q32 = nullptr;
     if (h32) {
@@ -1291,6 +1292,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
         launch_precond(s->np, s->Dchol, r, Ph, q, s->dp);
         if (lowrank) launch_lowrank_apply(n, s->Ulr, r, Ph, nullptr, s->lr_proj, nullptr, nullptr, q);
         matvec(s, sag, Ph, Qh);
+        if (h32) launch_hist_copy32(n, 0, 1, Ph, Qh, P32, Q32, q);
         std::vector<int32_t> hoff{0}, hk{1};
         std::vector<int64_t> hdp{0};
         int64_t dp_used = 1;
@@ -1344,8 +1346,8 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             const bool ahead = N > 1 && hcols + N <= hc;   // room for a multidirectional block
             const bool room1 = hcols + 1 <= hc;
             const int kn_max = ahead ? N : room1 ? 1 : 0;
+            float *Pn32 = h32 ? P32 + hcols * n : nullptr, *Qn32 = h32 ? Q32 + hcols * n : nullptr;
             if (h32) {
-                launch_hist_copy32(n, hoff.back(), hk.back(), Ph, Qh, P32, Q32, q);   // the current block
                 launch_phi<float>(n, (int)hcols, Q32, z, N, gs, Phi, q);
             } else {
                 launch_phi<double>(n, (int)hcols, Qh, z, N, gs, Phi, q);
@@ -1354,7 +1356,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             launch_beta(nb, blk_off, blk_k, blk_dp, Dp, Phi, sc, kn_max, N, beta, q);
             if (h32)
                 launch_update_pq<float>(n, (int)hcols, N, kn_max, P32, Q32, beta, z, gs, sc, Pn, s->hscratch,
-                                        s->hscratch_cap, q, opts.history_mfma != 0);
+                                        s->hscratch_cap, q, opts.history_mfma != 0, Pn32);
             else
                 launch_update_pq<double>(n, (int)hcols, N, kn_max, Ph, Qh, beta, z, gs, sc, Pn, s->hscratch,
                                          s->hscratch_cap, q, opts.history_mfma != 0);
@@ -1362,6 +1364,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             if (room1) {   // one-column block: Q_{i+1} = S P_{i+1}
                 SchurArgs s1 = sag;
                 s1.done = sc + SC_SKIPS;
+                s1.y32 = Qn32;
                 const size_t pu0 = s->prof_used;
                 matvec(s, s1, Pn, Qn);
                 spec_pair = s->prof_used != pu0;
@@ -1406,7 +1409,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 } else {
                     launch_schur_multi(ma, z, Qn, q);
                 }
-                launch_update_q(n, (int)hcols, N, sc, Qn, s->hscratch, s->hscratch_cap, q);
+                launch_update_q(n, (int)hcols, N, sc, Qn, s->hscratch, s->hscratch_cap, q, Qn32);
             }
             hoff.push_back((int32_t)hcols);
             hk.push_back(kn);

@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restri
                                                  double *__restrict__ y, const double *__restrict__ done,
                                                  const int32_t *__restrict__ cam_seg,
                                                  const int32_t *__restrict__ seg_skip, double *__restrict__ gram,
-                                                 const double *__restrict__ gr) {
+                                                 const double *__restrict__ gr, float *__restrict__ y32) {
     __shared__ double sh[4][64];
     __shared__ double gsum[2][4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -362,6 +362,7 @@ __global__ __launch_bounds__(256) void k_reduce1(int np, const int32_t *__restri
         if (lane < DP) {
             const double yi = du * vi + t;
             y[i] = yi;
+            if (y32) y32[i] = (float)yi;
             if (gram) {
                 qp = yi * vi;
                 pr = vi * gi;
@@ -411,10 +412,10 @@ void launch_schur_reduce(const SchurArgs &a, const double *v, double *y, hipStre
     const dim3 g((unsigned)schur_gram_blocks(a.np)), b(256);
     if (a.dp == 6)
         hipLaunchKernelGGL(k_reduce1<6>, g, b, 0, s, a.np, a.cam_part_ptr, a.partial, a.dU, v, y, a.done, a.cam_seg,
-                           a.seg_skip, a.gram, a.gram_r);
+                           a.seg_skip, a.gram, a.gram_r, a.y32);
     else
         hipLaunchKernelGGL(k_reduce1<9>, g, b, 0, s, a.np, a.cam_part_ptr, a.partial, a.dU, v, y, a.done, a.cam_seg,
-                           a.seg_skip, a.gram, a.gram_r);
+                           a.seg_skip, a.gram, a.gram_r, a.y32);
 }
 
 void launch_schur_matvec(const SchurArgs &a, const double *v, double *y, hipStream_t s) {

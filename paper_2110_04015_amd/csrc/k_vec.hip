@@ -1266,9 +1266,10 @@ __global__ __launch_bounds__(64) void k_hist_wide(int64_t n, int h, HistSlices h
 // (multidirectional blocks only, their base Y = S Z already in the Q columns); no
 // slices: P_new = Z_p.  The slices are added in ascending order, eight loads in flight
 // at a time (issued unconditionally: slices past the last read slice 0 and are dropped).
+// With out32 the new column is also written rounded to FP32 (mixed precision's history copy).
 __global__ void k_hist_final(int64_t n, HistSlices hs, const double *__restrict__ scratch,
                              const double *__restrict__ z, int gs, int N, const double *__restrict__ sc, int kn_max,
-                             int mat, double *__restrict__ Pn, double *__restrict__ Qn) {
+                             int mat, double *__restrict__ Pn, double *__restrict__ Qn, float *__restrict__ out32) {
     const int kn = next_kn(sc, kn_max);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (kn == 0 || i >= n * kn || (mat == 1 && kn == 1)) return;
@@ -1294,7 +1295,9 @@ __global__ void k_hist_final(int64_t n, HistSlices hs, const double *__restrict_
         const int grp = kn > 1 ? min((int)(row / gs), N - 1) : 0;
         base = (kn == 1 || grp == p) ? z[row] : 0.0;
     }
-    out[i] = base - s;
+    const double o = base - s;
+    out[i] = o;
+    if (out32) out32[i] = (float)o;
 }
 
 // column slices of the history products for a block of width kn: enough (row tile, slice)
@@ -1326,7 +1329,7 @@ int64_t hist_scratch_min(int64_t n, int kn_max) { return 2 * (int64_t)kn_max * n
 template <typename HT>
 void launch_update_pq(int64_t n, int h, int N, int kn_max, const HT *Ph, const HT *Qh, const double *beta,
                       const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
-                      hipStream_t s, bool mfma) {
+                      hipStream_t s, bool mfma, float *Pn32) {
     if (kn_max <= 0) return;
     const HistSlices hs = hist_slicing(n, h, kn_max, scratch_doubles);
     if (h > 0) {
@@ -1349,15 +1352,15 @@ void launch_update_pq(int64_t n, int h, int N, int kn_max, const HT *Ph, const H
     }
     const int64_t tot = n * kn_max;
     hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, hs, scratch, z, gs, N,
-                       sc, kn_max, 0, Pn, nullptr);
+                       sc, kn_max, 0, Pn, nullptr, Pn32);
 }
 
 template void launch_update_pq<double>(int64_t, int, int, int, const double *, const double *, const double *,
                                        const double *, int, const double *, double *, double *, int64_t, hipStream_t,
-                                       bool);
+                                       bool, float *);
 template void launch_update_pq<float>(int64_t, int, int, int, const float *, const float *, const double *,
                                       const double *, int, const double *, double *, double *, int64_t, hipStream_t,
-                                      bool);
+                                      bool, float *);
 
 // FP32 copy of history columns [c0, c0 + k) of P and Q (mixed precision: the
 // reorthogonalisation reads the copy, the block's own Gram and updates the FP64 columns)
@@ -1379,11 +1382,11 @@ void launch_hist_copy32(int64_t n, int64_t c0, int k, const double *Ph, const do
 }
 
 void launch_update_q(int64_t n, int h, int N, const double *sc, double *Qn, const double *scratch,
-                     int64_t scratch_doubles, hipStream_t s) {
+                     int64_t scratch_doubles, hipStream_t s, float *Qn32) {
     const HistSlices hs = hist_slicing(n, h, N, scratch_doubles);
     const int64_t tot = n * N;
     hipLaunchKernelGGL(k_hist_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, hs, scratch, nullptr, 0,
-                       N, sc, N, 1, nullptr, Qn);
+                       N, sc, N, 1, nullptr, Qn, Qn32);
 }
 
 }  // namespace ba

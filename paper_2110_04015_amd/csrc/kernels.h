@@ -102,6 +102,9 @@ struct SchurArgs {
     // y^T v and v^T gram_r, gram[2 b], gram[2 b + 1] for b < schur_gram_blocks(np)
     double *gram = nullptr;
     const double *gram_r = nullptr;
+    // nullable: the camera reduction also writes y rounded to FP32 here (the FP32 history
+    // copy of mixed-precision MCG)
+    float *y32 = nullptr;
 };
 int schur_gram_blocks(int np);
 // FP64 chunk wavefronts of the S product (of the multidirectional product) resident at
@@ -246,18 +249,20 @@ void launch_beta(int nb, const int32_t *blk_off, const int32_t *blk_k, const int
 // The new block's P columns (Pn, kn of them), kn = sc[SC_KN] read on the device, and the
 // history sums of its Q columns in the scratch (kept for launch_update_q); kn_max is the
 // widest block the history has room for.  The scratch holds at least
-// hist_scratch_min(n, kn_max) doubles.
+// hist_scratch_min(n, kn_max) doubles.  mfma: blocks wider than 16 on the FP64 matrix
+// cores.  Pn32 (nullable): the new columns also rounded to FP32 there.
 template <typename HT>   // Ph, Qh: FP64 history or its FP32 copy
 void launch_update_pq(int64_t n, int h, int N, int kn_max, const HT *Ph, const HT *Qh, const double *beta,
                       const double *z, int gs, const double *sc, double *Pn, double *scratch, int64_t scratch_doubles,
-                      hipStream_t s, bool mfma = false);   // mfma: blocks wider than 16 on the FP64 matrix cores
+                      hipStream_t s, bool mfma = false, float *Pn32 = nullptr);
 // FP32 copy of history columns [c0, c0 + k) of P and Q (column-major, n rows)
 void launch_hist_copy32(int64_t n, int64_t c0, int k, const double *Ph, const double *Qh, float *P32, float *Q32,
                         hipStream_t s);
 // Q columns of a multidirectional block (N of them): Qn holds S Z on entry; the history
-// sums are those launch_update_pq left in the scratch with kn_max = N
+// sums are those launch_update_pq left in the scratch with kn_max = N; Qn32 (nullable):
+// the columns also rounded to FP32 there
 void launch_update_q(int64_t n, int h, int N, const double *sc, double *Qn, const double *scratch,
-                     int64_t scratch_doubles, hipStream_t s);
+                     int64_t scratch_doubles, hipStream_t s, float *Qn32 = nullptr);
 int64_t hist_scratch_min(int64_t n, int kn_max);
 void launch_pinv_sym(int k, const double *A, double *Ap, int32_t *rank, hipStream_t s);
 

@@ -494,6 +494,21 @@ def test_mixed_precision_refinement(pair, prec, solver):
     assert energy_err(S, _h(x), xs) <= 1e-6
 
 
+def test_fp32_history_copy_keeps_the_conjugation():
+    """Mixed-precision MCG reading the FP32 copy of the history (block 0 copied, every later
+    block's P and Q written in both precisions by the kernels that finish them) needs about
+    as many iterations as with the FP64 history; a stale or missing column of the copy
+    would drop its block from the reorthogonalisation and multiply them."""
+    p = synth.walk_problem(n_cams=200, n_lms=20000, seed=7, name="walk200")
+    g = ba.System.from_problem(p)
+    for N in (1, 4, 16):
+        _, s64 = g.mcg(N, 3.3, precision="fp32", history_fp32=False)
+        _, s32 = g.mcg(N, 3.3, precision="fp32", history_fp32=True)
+        assert s64.status == ba.BA_OK and s32.status == ba.BA_OK, (N, s64, s32)
+        assert s32.rel_res_true < 1e-6
+        assert abs(s32.iterations - s64.iterations) <= 0.05 * s64.iterations + 2, (N, s64, s32)
+
+
 def test_mcg_history_on_matrix_cores_matches_the_oracle():
     """The matrix-core history products (ba_solve_opts.history_mfma, blocks wider than 16
     columns) give the same iterates as the oracle's Algorithm 2 within 1e-9."""
