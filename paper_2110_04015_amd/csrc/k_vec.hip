@@ -230,7 +230,10 @@ void launch_pcg_update_xr(int64_t n, const double *partials_dq, int n_dq, double
 // solves it takes.  The block that arrives last (an agent-scope counter, left zero) adds
 // the partials in block order and takes the step-end decisions of k_pcg_step_end (on a
 // breakdown flag, the stop test, the iteration cap), then beta = Phi / Delta into the
-// scalars for k_pcg_update_p.
+// scalars for k_pcg_update_p.  As in k_mcg_xrz, the loads that need nothing formed here
+// (x, r, P, Q and the Cholesky factor of the thread's camera; threads without a row or a
+// camera read the block's first and ignore them) go before the reduction of the partials,
+// which are read as pairs with eight loads in flight.
 template <int DP>
 __global__ __launch_bounds__(kNT) void k_pcg_xrz(int np, const double *__restrict__ pdq, int npdq,
                                                  double *__restrict__ sc, double *__restrict__ x,
@@ -241,17 +244,26 @@ __global__ __launch_bounds__(kNT) void k_pcg_xrz(int np, const double *__restric
                                                  double *__restrict__ trace) {
     if (sc[SC_DONE] != 0.0) return;
     constexpr int CB = kNT / DP;
+    constexpr int NL = DP * (DP + 1) / 2;
     __shared__ double sr[CB * DP], sq[CB * DP];
     __shared__ double sh[kNT];
     __shared__ double s_alpha;
     __shared__ int last;
-    const int64_t n = (int64_t)np * DP;
     const int c0 = blockIdx.x * CB;
     const int cams = min(CB, np - c0);
     const int t = threadIdx.x;
+    const bool row = t < cams * DP;
+    const int64_t i = (int64_t)c0 * DP + (row ? t : 0);
+    const double xi = x[i], ri = r[i], pi = P[i], qi = Q[i];
+    double Lc[NL];
+    {
+        const double *Lp = Dchol + (int64_t)(c0 + (t < cams ? t : 0)) * NL;
+#pragma unroll
+        for (int e = 0; e < NL; ++e) Lc[e] = Lp[e];
+    }
     if (t < 64) {
-        const double D = wave_partials(pdq, 2, npdq);
-        const double g = wave_partials(pdq + 1, 2, npdq);
+        double D, g;
+        wave_pair_sums(pdq, npdq, D, g);
         const double al = D > 0.0 ? g / D : 0.0;
         if (t == 0) {
             s_alpha = al;
@@ -266,11 +278,9 @@ __global__ __launch_bounds__(kNT) void k_pcg_xrz(int np, const double *__restric
     __syncthreads();
     const double al = s_alpha;
     double rr = 0.0;
-    if (t < cams * DP) {
-        const int64_t i = (int64_t)c0 * DP + t;
-        const double qi = Q[i];
-        x[i] += al * P[i];
-        const double v = r[i] - al * qi;
+    if (row) {
+        x[i] = xi + al * pi;
+        const double v = ri - al * qi;
         r[i] = v;
         sr[t] = v;
         sq[t] = qi;
@@ -282,7 +292,7 @@ __global__ __launch_bounds__(kNT) void k_pcg_xrz(int np, const double *__restric
         double rc[DP], zc[DP];
 #pragma unroll
         for (int e = 0; e < DP; ++e) rc[e] = sr[t * DP + e];
-        chol_solve_packed<DP>(Dchol + (int64_t)(c0 + t) * (DP * (DP + 1) / 2), rc, zc);
+        chol_solve_packed<DP>(Lc, rc, zc);
 #pragma unroll
         for (int e = 0; e < DP; ++e) {
             z[(int64_t)(c0 + t) * DP + e] = zc[e];
@@ -300,8 +310,8 @@ __global__ __launch_bounds__(kNT) void k_pcg_xrz(int np, const double *__restric
     __syncthreads();
     if (!last || t >= 64) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const double srr = wave_partials(partials, 2, gridDim.x);
-    const double sphi = wave_partials(partials + 1, 2, gridDim.x);
+    double srr, sphi;
+    wave_pair_sums(partials, gridDim.x, srr, sphi);
     if (t != 0) return;
     __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (sc[SC_BREAK] != 0.0) {
