@@ -411,6 +411,40 @@ __global__ __launch_bounds__(kNT) void k_gram1(int64_t n, const double *__restri
     }
 }
 
+// Rows [r0, r0 + rows) of the n x k blocks P and Q (column-major) into LDS row-major
+// (sP[rr * k + a]) and of r into sr, by the work-group: consecutive threads take
+// consecutive rows of a column, eight elements of each block per thread are loaded before
+// any is stored (elements past the end read element 0 and are dropped), so that a
+// thread's loads are in flight together rather than one round trip each.
+__device__ __forceinline__ void gram_stage(int64_t n, int k, int rows, int64_t r0, const double *__restrict__ P,
+                                           const double *__restrict__ Q, const double *__restrict__ r, double *sP,
+                                           double *sQ, double *sr) {
+    const int tid = threadIdx.x;
+    const int tot = rows * k;
+    const double rv = r[r0 + (tid < rows ? tid : 0)];
+    for (int w0 = tid; w0 < tot; w0 += 8 * kNT) {
+        double vp[8], vq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int w = w0 + u * kNT < tot ? w0 + u * kNT : 0;
+            const int a = w / rows, rr = w - a * rows;
+            vp[u] = P[(int64_t)a * n + r0 + rr];
+            vq[u] = Q[(int64_t)a * n + r0 + rr];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int w = w0 + u * kNT;
+            if (w < tot) {
+                const int a = w / rows, rr = w - a * rows;
+                sP[rr * k + a] = vp[u];
+                sQ[rr * k + a] = vq[u];
+            }
+        }
+    }
+    if (tid < rows) sr[tid] = rv;
+    for (int rr = tid + kNT; rr < rows; rr += kNT) sr[rr] = r[r0 + rr];
+}
+
 // k > 1: partials[b][a * k + c] = sum_rows Q[:, a] . P[:, c] ; partials[b][k*k + a] = sum_rows P[:, a] . r
 // over block b's contiguous row range.  The range is staged through LDS in chunks of R
 // rows (R (2k + 1) doubles fit kGramLds), each chunk loaded in one pass so that all its
@@ -427,13 +461,7 @@ __global__ __launch_bounds__(kNT) void k_gram(int64_t n, int k, int R, const dou
     const int64_t lo = n * blockIdx.x / gridDim.x, hi = n * (blockIdx.x + 1) / gridDim.x;
     for (int64_t r0 = lo; r0 < hi; r0 += R) {
         const int rows = (int)(hi - r0 < R ? hi - r0 : R);
-#pragma unroll 4
-        for (int w = threadIdx.x; w < rows * k; w += kNT) {
-            const int a = w / rows, rr = w - a * rows;   // consecutive threads: consecutive rows of column a
-            sP[rr * k + a] = P[(int64_t)a * n + r0 + rr];
-            sQ[rr * k + a] = Q[(int64_t)a * n + r0 + rr];
-        }
-        for (int rr = threadIdx.x; rr < rows; rr += kNT) sr[rr] = r[r0 + rr];
+        gram_stage(n, k, rows, r0, P, Q, r, sP, sQ, sr);
         __syncthreads();
 #pragma unroll
         for (int o = 0; o < kGramOut; ++o) {
@@ -491,13 +519,7 @@ __global__ __launch_bounds__(kNT) void k_gram_mfma(int64_t n, int k, int R, cons
     const int64_t lo = n * blockIdx.x / gridDim.x, hi = n * (blockIdx.x + 1) / gridDim.x;
     for (int64_t r0 = lo; r0 < hi; r0 += R) {
         const int rows = (int)(hi - r0 < R ? hi - r0 : R);
-#pragma unroll 4
-        for (int w = tid; w < rows * k; w += kNT) {
-            const int a = w / rows, rr = w - a * rows;   // consecutive threads: consecutive rows of column a
-            sP[rr * k + a] = P[(int64_t)a * n + r0 + rr];
-            sQ[rr * k + a] = Q[(int64_t)a * n + r0 + rr];
-        }
-        for (int rr = tid; rr < rows; rr += kNT) sr[rr] = r[r0 + rr];
+        gram_stage(n, k, rows, r0, P, Q, r, sP, sQ, sr);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
