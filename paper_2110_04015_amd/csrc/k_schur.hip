@@ -302,25 +302,30 @@ __global__ __launch_bounds__(64) void k_schur1(SchurArgs a, const double *__rest
 
 // Sum of the DP-vectors rows[a..b) by the calling wavefront, R = 64 / DP rows at a
 // time (7 for DP = 9, 10 for DP = 6): lane l < R DP adds component l % DP of rows
-// a + l / DP + R i into two running sums (even and odd i, so that two loads are in
-// flight), then the 2 R sums of a component are added in a fixed order through sh (64
-// doubles of the wavefront).  Every lane returns its component's total (lanes past R DP
-// return component 0's).
+// a + l / DP + R i, eight rows per batch with all eight loads in flight (rows past b read
+// row a and are dropped), row i into running sum i mod 4; then the 4 R sums of a
+// component are added in a fixed order through sh (64 doubles of the wavefront).  Every
+// lane returns its component's total (lanes past R DP return component 0's).
 template <int DP>
 __device__ __forceinline__ double wave_rows(const double *__restrict__ rows, int64_t a, int64_t b, double *sh) {
     constexpr int R = 64 / DP;
     const int lane = threadIdx.x & 63;
-    double s0 = 0.0, s1 = 0.0;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
     if (lane < R * DP) {
         const int r0 = lane / DP, k = lane - r0 * DP;
-        int64_t j = a + r0;
-        for (; j + R < b; j += 2 * R) {
-            s0 += rows[j * DP + k];
-            s1 += rows[(j + R) * DP + k];
+        for (int64_t j = a + r0; j < b; j += 8 * R) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t jj = j + u * R;
+                v[u] = rows[(jj < b ? jj : a) * DP + k];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j + u * R < b) s[u & 3] += v[u];
         }
-        if (j < b) s0 += rows[j * DP + k];
     }
-    sh[lane] = s0 + s1;
+    sh[lane] = (s[0] + s[1]) + (s[2] + s[3]);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
