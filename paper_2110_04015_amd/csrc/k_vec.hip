@@ -608,10 +608,17 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
     __shared__ int rank;
     const int tid = threadIdx.x;
     const int tot = k * k + k;
-    for (int idx = tid; idx < tot; idx += kNT) {
-        const double s = sums[idx];
-        if (idx < k * k) G[idx] = s;
-        else gam[idx - k * k] = s;
+    // eight sums per thread in flight (indices past tot read sum 0 and are dropped)
+    for (int i0 = tid; i0 < tot; i0 += 8 * kNT) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = sums[i0 + u * kNT < tot ? i0 + u * kNT : 0];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = i0 + u * kNT;
+            if (idx < k * k) G[idx] = v[u];
+            else if (idx < tot) gam[idx - k * k] = v[u];
+        }
     }
     __syncthreads();
     for (int w = tid; w < k * k; w += kNT) {
@@ -845,9 +852,23 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
         double dx = 0.0, dr = 0.0;
         dx += p0 * al[0];
         dr += q0 * al[0];
-        for (int a = 1; a < k; ++a) {
-            dx += P[(int64_t)a * n + i] * al[a];
-            dr += Q[(int64_t)a * n + i] * al[a];
+        // the other columns of a wide block, eight of each matrix in flight (columns past
+        // k read column 0 and are dropped)
+        for (int a0 = 1; a0 < k; a0 += 8) {
+            double pv[8], qv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int a = a0 + u < k ? a0 + u : 0;
+                pv[u] = P[(int64_t)a * n + i];
+                qv[u] = Q[(int64_t)a * n + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (a0 + u < k) {
+                    dx += pv[u] * al[a0 + u];
+                    dr += qv[u] * al[a0 + u];
+                }
+            }
         }
         x[i] = xi + dx;
         const double v = ri - dr;
