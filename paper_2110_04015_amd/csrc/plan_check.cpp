@@ -103,6 +103,10 @@ bool check_multi(const HostPlan &P, const HostMultiPlan &M, const int32_t *cam) 
         int pb = M.chunk_part[(size_t)ch], no = M.chunk_part[(size_t)ch + 1] - pb;
         if (no < 1 || no > M.max_out) return bad("multi chunk out count", ch, no);
         for (int t = M.chunk_tile[(size_t)ch]; t < M.chunk_tile[(size_t)ch + 1]; ++t) {
+            // the product loads a tile's first output-row entry with the tile, for every
+            // lane, padding lanes included: every tile's list holds at least one entry
+            if (M.tile_oidx[(size_t)t + 1] <= M.tile_oidx[(size_t)t] || M.tile_oidx[(size_t)t] >= M.oidx.size())
+                return bad("empty tile output list", t);
             // pairs of the tile
             std::vector<int> pair_grp(kTile, -1);
             for (int q = 0; q < kTile; ++q) {
