@@ -109,6 +109,64 @@ def run_batch(probs, seed, log):
     return out
 
 
+def run_learned(g, variants, args, log):
+    """The learned low-rank correction of the block-Jacobi preconditioner on the headline
+    system: a network trained here on the systems of short LM runs over 250-camera
+    walk1936-shaped problems (the library's own features, probes, loss, backpropagation and
+    Adam), then applied to walk1936 (features, BF16 inference, U: the setup of one
+    linearisation) and timed with MCG in FP64 and with FP32 products under FP64
+    refinement, against the plain block-Jacobi solves and FP64 PCG of the variants."""
+    import torch
+    from paper_2110_04015_amd import learned as L
+    t = time.time()
+    samples = L.collect(range(args.learned_seeds), lm_iters=5, n_cams=250)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t
+    tr = L.train(samples, epochs=20, lr=1e-4)
+    out = {"train_systems": len(samples), "train_seeds": args.learned_seeds, "n_cams_train": 250,
+           "generation_s": round(gen_s, 1), "train_s": round(tr["train_s"], 2),
+           "loss_first": tr["loss_history"][0], "loss_last": tr["loss_history"][-1]}
+    del samples
+
+    def setup():
+        g.set_lowrank_from_mlp(L.mlp_forward(tr["params"], g.lowrank_features(), bf16=True))
+
+    setup()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        setup()
+    torch.cuda.synchronize()
+    out["setup_ms"] = round((time.perf_counter() - t1) / 3 * 1e3, 3)
+    for name, kw in [("mcg_fp64_N16", dict(N=16, precision="fp64")),
+                     ("mcg_fp32_refined_N16", dict(N=16, precision="fp32")),
+                     ("mcg_fp32_refined_N4", dict(N=4, precision="fp32"))]:
+        f = lambda: g.mcg(kw["N"], args.tau, eps=1e-6, max_iter=1000, precision=kw["precision"],
+                          precond="lowrank")
+        f()
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, s2 = f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        dt = sorted(ts)[1]   # median of 3
+        log(f"learned {name}: solve times {[round(1e3 * t, 2) for t in ts]} ms")
+        plain = variants.get(name)
+        out[name] = {"solves_per_s": round(1.0 / dt, 3), "iterations": s2.iterations,
+                     "multi_steps": s2.multi_steps, "refinement_steps": s2.refinement_steps,
+                     "rel_res_true": s2.rel_res_true, "status": s2.status,
+                     "plain_iterations": plain["iterations"] if plain else None,
+                     "plain_solves_per_s": plain["solves_per_s"] if plain else None}
+        log(f"learned {name}: {out[name]}")
+    g.set_lowrank(None)
+    base = variants["pcg_fp64"]["solves_per_s"]
+    out["vs_pcg_fp64"] = {k: round(v["solves_per_s"] / base, 3) for k, v in out.items()
+                          if isinstance(v, dict) and "solves_per_s" in v}
+    return out
+
+
 def run_dense(seed, log):
     """The dense-Schur workload: cap571, shaped like Table 1's Alamo row (571 poses, about
     0.9M projections, block density near 0.8), with that row's N = 47 and tau = 10.  FP64
@@ -230,6 +288,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem batched-serving workload")
     ap.add_argument("--no-lm", action="store_true", help="skip the LM outer-loop runs")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense-Schur (cap571) workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned low-rank correction")
+    ap.add_argument("--learned-seeds", type=int, default=4,
+                    help="250-camera problems whose 5 LM systems train the learned correction")
     ap.add_argument("--dense-only", action="store_true", help="profiling mode: only the dense-Schur workload")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="K",
                     help="profiling mode: K S v products (at --precision) and one 1 GiB copy (counter calibration)")
@@ -383,6 +444,10 @@ def main():
         mixed_vs_pcg = {k: round(v["solves_per_s"] / base, 3) for k, v in variants.items()
                         if k.startswith("mcg_") and "refined" in k}
 
+    learned = None
+    if not args.no_variants and not args.no_learned:
+        learned = run_learned(g, variants, args, log)
+
     extrinsics = None
     if not args.no_variants:
         # poses of dimension 6 (intrinsics fixed): the same observations, 2 x 6 pose blocks
@@ -529,6 +594,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "mixed_mcg_vs_pcg_fp64": mixed_vs_pcg,
+        "learned": learned,
         "explicit_schur": explicit,
         "extrinsics_only": extrinsics,
         "batch": batch,

@@ -174,8 +174,6 @@ void free_all(ba_system *s) {
     if (s->host_pinned) (void)hipHostFree(s->host_pinned);
     s->host_pinned = nullptr;
     s->host_pinned_dev = nullptr;
-    if (s->sc_event) (void)hipEventDestroy(s->sc_event);
-    s->sc_event = nullptr;
     free_multi(s, s->multi);
     for (hipEvent_t e : s->prof_events) (void)hipEventDestroy(e);
     s->prof_events.clear();
@@ -422,16 +420,6 @@ ba_status ensure_pinned(ba_system *s) {
         s->host_pinned[SC_COUNT] = 0.0;
         HIPCHK(hipHostGetDevicePointer((void **)&s->host_pinned_dev, s->host_pinned, 0));
     }
-    if (!s->sc_event) HIPCHK(hipEventCreateWithFlags(&s->sc_event, hipEventDisableTiming));
-    return BA_OK;
-}
-
-// Enqueues the copy of the device scalars to the host behind the work enqueued so far
-// and marks that point; scalars_wait() then waits for it only, so kernels launched in
-// between keep the device busy while the host waits.
-static ba_status scalars_post(ba_system *s, const double *sc) {
-    HIPCHK(hipMemcpyAsync(s->host_pinned, sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipEventRecord(s->sc_event, s->stream));
     return BA_OK;
 }
 
@@ -456,12 +444,6 @@ static ba_status scalars_wait_tag(ba_system *s, double tag, double *out) {
         }
     }
     std::atomic_thread_fence(std::memory_order_acquire);
-    memcpy(out, s->host_pinned, SC_COUNT * sizeof(double));
-    return BA_OK;
-}
-
-static ba_status scalars_wait(ba_system *s, double *out) {
-    HIPCHK(hipEventSynchronize(s->sc_event));
     memcpy(out, s->host_pinned, SC_COUNT * sizeof(double));
     return BA_OK;
 }
@@ -1283,11 +1265,15 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
         // one-column blocks take Delta and gamma from the camera reduction of Q = S P (or
         // the explicit-S product; partials at red + goff), and their Delta^+ and alpha from
         // the iteration-end kernel
-        const bool fuse1 = !lowrank;
         SchurArgs sag = sa;
-        if (fuse1) {
-            sag.gram = red + goff;
-            sag.gram_r = r;
+        sag.gram = red + goff;
+        sag.gram_r = r;
+        // the learned term: U^T r partials, then w, in lr_proj (ensure_lowrank_storage)
+        XrzLowrank lr;
+        if (lowrank) {
+            lr.U = s->Ulr;
+            lr.part = s->lr_proj;
+            lr.w = s->lr_proj + (int64_t)kLowRank * mcg_xrz_blocks(s->np, s->dp);
         }
         launch_precond(s->np, s->Dchol, r, Ph, q, s->dp);
         if (lowrank) launch_lowrank_apply(n, s->Ulr, r, Ph, nullptr, s->lr_proj, nullptr, nullptr, q);
@@ -1311,7 +1297,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             be.first = off;
             be.dpo = dpo;
             XrzGram g1;
-            if (fuse1 && k == 1) {
+            if (k == 1) {
                 g1.part = red + goff;
                 g1.nb = gram_parts(s, sag);
                 g1.Dp = Dp + dpo;
@@ -1323,18 +1309,12 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
             // x_{i+1} = x_i + P_i alpha_i ; r_{i+1} = r_i - Q_i alpha_i ; Z = D^-1 r_{i+1}, and the
             // tau-test scalars before the single read-back of the iteration:
             // t_i = gamma_i^T alpha_i / (r_{i+1}^T D^-1 r_{i+1})
-            if (lowrank) {
-                launch_update_xr_blk(n, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, red, q);
-                launch_precond_rho(s->np, s->Dchol, r, z, red + kRedBlocks, q, s->dp);
-                launch_lowrank_apply(n, s->Ulr, r, z, r, s->lr_proj, red + kRedBlocks, nullptr, q);
-                launch_mcg_scalars(k, red, red + kRedBlocks, gamma, alpha, sc, N, tau, opts.eps, q);
-                if ((st = scalars_post(s, sc)) != BA_OK) return st;
-            } else {   // the kernel also writes the scalars to the host, with a new tag
-                s->sc_tag += 1.0;
-                launch_mcg_xrz(s->np, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, s->Dchol, z,
-                               red, s->tickets, gamma, sc, s->host_pinned_dev, s->sc_tag, N, tau, opts.eps, q, s->dp,
-                               g1);
-            }
+            // (the kernel also writes the scalars to the host, with a new tag; with the learned
+            // term, rho = r^T M^-1 r and Z = D^-1 r + U (U^T r), the last by the next kernel)
+            s->sc_tag += 1.0;
+            launch_mcg_xrz(s->np, k, Ph + (int64_t)off * n, Qh + (int64_t)off * n, alpha, x, r, s->Dchol, z, red,
+                           s->tickets, gamma, sc, s->host_pinned_dev, s->sc_tag, N, tau, opts.eps, q, s->dp, g1, lr);
+            if (lowrank) launch_lr_zadd(n, s->Ulr, lr.w, z, q);
             // Everything up to the next iteration's Gram products that a one-column block
             // needs goes ahead of the read-back, so the device stays busy while the host
             // waits for it: Phi_{i,j} = Q_j^T Z_{i+1} per subset (valid for either outcome),
@@ -1370,7 +1350,7 @@ static ba_status mcg_core(ba_system *s, const double *bt, bool report_true, int 
                 spec_pair = s->prof_used != pu0;
             }
             HIPCHK(hipGetLastError());
-            if ((st = lowrank ? scalars_wait(s, h) : scalars_wait_tag(s, s->sc_tag, h)) != BA_OK) return st;
+            if ((st = scalars_wait_tag(s, s->sc_tag, h)) != BA_OK) return st;
             if (spec_pair && h[SC_KN] != 1.0) s->prof_used -= 2;   // a skipped launch is no kernel work
             if (h[SC_RANK] == 0.0) {
                 result = BA_ERR_BREAKDOWN;
@@ -1577,7 +1557,10 @@ static ba_status lowrank_dp_check(const ba_system *s) {
 static ba_status ensure_lowrank_storage(ba_system *s) {
     ba_status st;
     if (!s->Ulr && (st = salloc(s, &s->Ulr, (size_t)s->np * 9 * 8)) != BA_OK) return st;
-    if (!s->lr_proj && (st = salloc(s, &s->lr_proj, (size_t)kRedBlocks * 8)) != BA_OK) return st;
+    // kRedBlocks rows of 8 for PCG's projections; MCG's iteration end keeps one row per
+    // block and w after them
+    const size_t proj = (size_t)std::max(kRedBlocks, mcg_xrz_blocks(s->np, s->dp) + 1) * kLowRank;
+    if (!s->lr_proj && (st = salloc(s, &s->lr_proj, proj)) != BA_OK) return st;
     return BA_OK;
 }
 

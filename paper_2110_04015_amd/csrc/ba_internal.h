@@ -197,7 +197,6 @@ struct ba_system {
     size_t small_cap = 0;
     double *host_pinned = nullptr;  // pinned host scalars
     double *host_pinned_dev = nullptr;  // the same memory as kernels address it
-    hipEvent_t sc_event = nullptr;  // marks the point of the stream where host_pinned was filled
     double sc_tag = 0.0;            // tag of the last scalars a kernel wrote to host_pinned[SC_COUNT]
     ba::DevMulti multi;
     // batches: problem of every camera and of every chunk of the S product (device)

@@ -60,11 +60,6 @@ void launch_pcg_precond_phi(int np, const double *Dchol, const double *r, const 
 }
 
 
-void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials,
-                        hipStream_t s, int dp) {
-    launch_pcg_precond_phi(np, Dchol, r, r, z, partials, nullptr, s, dp);
-}
-
 // ---------------------------------------------------------------- reductions
 
 // one wavefront per output d
@@ -383,34 +378,6 @@ constexpr int kGramOut = (kMaxK * kMaxK + kMaxK + kNT - 1) / kNT;   // outputs p
 constexpr int kGramLds = 64 * 1024;                                   // bytes of one row chunk
 constexpr int kGramBlocksWide = kRedBlocks;                          // blocks of a k > 1 Gram
 
-// k = 1: partials[b][0] = Q . P, partials[b][1] = P . r over a grid-stride share of
-// the rows (wavefront butterflies, then the four wavefronts in order)
-__global__ __launch_bounds__(kNT) void k_gram1(int64_t n, const double *__restrict__ P,
-                                               const double *__restrict__ Q, const double *__restrict__ r,
-                                               double *__restrict__ partials) {
-    __shared__ double sh[2][kNT / 64];
-    double qp = 0.0, pr = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * kNT;
-    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += stride) {
-        const double p = P[i];
-        qp += Q[i] * p;
-        pr += p * r[i];
-    }
-    qp = wave_sum(qp);
-    pr = wave_sum(pr);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sh[0][w] = qp;
-        sh[1][w] = pr;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        double s = 0.0;
-        for (int u = 0; u < kNT / 64; ++u) s += sh[threadIdx.x][u];
-        partials[(int64_t)blockIdx.x * 2 + threadIdx.x] = s;
-    }
-}
-
 // Rows [r0, r0 + rows) of the n x k blocks P and Q (column-major) into LDS row-major
 // (sP[rr * k + a]) and of r into sr, by the work-group: consecutive threads take
 // consecutive rows of a column, eight elements of each block per thread are loaded before
@@ -575,16 +542,11 @@ __global__ __launch_bounds__(64) void k_gram_sum(int tot, int nb, const double *
     sums[idx] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
-// blocks of the Gram partials: wider blocks have k (k + 1) outputs per block, so fewer
-// blocks keep the sum over them short
-int gram_blocks(int k) { return k == 1 ? kRedBlocks : kGramBlocksWide; }
+// blocks of the Gram partials (k > 1)
+int gram_blocks(int) { return kGramBlocksWide; }
 
 void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
                  hipStream_t s) {
-    if (k == 1) {
-        hipLaunchKernelGGL(k_gram1, dim3(kRedBlocks), dim3(kNT), 0, s, n, P, Q, r, partials);
-        return;
-    }
     const int nb = gram_blocks(k);
     const int64_t per = (n + nb - 1) / nb;
     const int64_t cap = kGramLds / (int64_t)((2 * k + 1) * sizeof(double));
@@ -644,35 +606,10 @@ __global__ __launch_bounds__(kNT) void k_pinv_alpha(int k, const double *__restr
     }
 }
 
-// k = 1: Delta^+ = 1 / Delta unless Delta is zero (or not finite), the 1 x 1 case of the
-// pseudo-inverse's rank rule, in a kernel without the k x k working storage
-__global__ __launch_bounds__(64) void k_pinv_alpha1(const double *__restrict__ partials, int nblocks,
-                                                    double *__restrict__ Dp, double *__restrict__ gamma,
-                                                    double *__restrict__ alpha, double *__restrict__ sc,
-                                                    BlockEntry blk) {
-    double d, g;   // Q^T P, P^T r
-    wave_pair_sums(partials, nblocks, d, g);
-    if (threadIdx.x != 0) return;
-    const bool nz = fabs(d) > 2.220446049250313e-16 * fabs(d);
-    const double dp = nz ? 1.0 / d : 0.0;
-    Dp[0] = dp;
-    alpha[0] = dp * g;
-    gamma[0] = g;
-    sc[SC_RANK] = nz ? 1.0 : 0.0;
-    if (blk.off) {
-        blk.off[blk.j] = blk.first;
-        blk.k[blk.j] = 1;
-        blk.dp[blk.j] = blk.dpo;
-    }
-}
-
 void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, double *gamma, double *alpha,
                        double *sc, hipStream_t s, BlockEntry blk) {
-    if (k == 1)
-        hipLaunchKernelGGL(k_pinv_alpha1, dim3(1), dim3(64), 0, s, partials, nblocks, Dp, gamma, alpha, sc, blk);
-    else
-        hipLaunchKernelGGL(k_pinv_alpha, dim3(1), dim3(kNT), 0, s, k, partials + (int64_t)nblocks * (k * k + k), Dp,
-                           gamma, alpha, sc, blk);
+    hipLaunchKernelGGL(k_pinv_alpha, dim3(1), dim3(kNT), 0, s, k, partials + (int64_t)nblocks * (k * k + k), Dp,
+                       gamma, alpha, sc, blk);
 }
 
 // Stand-alone symmetric pseudo-inverse (test entry point).
@@ -690,36 +627,6 @@ __global__ __launch_bounds__(kNT) void k_pinv_sym(int k, const double *__restric
 
 void launch_pinv_sym(int k, const double *A, double *Ap, int32_t *rank, hipStream_t s) {
     hipLaunchKernelGGL(k_pinv_sym, dim3(1), dim3(kNT), 0, s, k, A, Ap, rank);
-}
-
-// x += P alpha ; r -= Q alpha (n x k blocks, column-major) ; partial |r|^2
-__global__ __launch_bounds__(kNT) void k_update_xr_blk(int64_t n, int k, const double *__restrict__ P,
-                                                       const double *__restrict__ Q,
-                                                       const double *__restrict__ alpha, double *__restrict__ x,
-                                                       double *__restrict__ r, double *__restrict__ partials) {
-    __shared__ double sh[kNT];
-    __shared__ double al[kMaxK];
-    for (int a = threadIdx.x; a < k; a += kNT) al[a] = alpha[a];
-    __syncthreads();
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT) {
-        double dx = 0.0, dr = 0.0;
-        for (int a = 0; a < k; ++a) {
-            dx += P[(int64_t)a * n + i] * al[a];
-            dr += Q[(int64_t)a * n + i] * al[a];
-        }
-        x[i] += dx;
-        double v = r[i] - dr;
-        r[i] = v;
-        acc += v * v;
-    }
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
-}
-
-void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, const double *alpha, double *x,
-                          double *r, double *partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_xr_blk, dim3(kRedBlocks), dim3(kNT), 0, s, n, k, P, Q, alpha, x, r, partials);
 }
 
 // Alg. 2's stop test and tau-test from |r_{i+1}|^2 and rho = r_{i+1}^T M^-1 r_{i+1}:
@@ -750,25 +657,6 @@ __device__ inline void mcg_scalars_put(const McgScalars &v, double *__restrict__
     sc[SC_KN] = v.kn;
     sc[SC_SKIPS] = v.skips;
 }
-__device__ inline void mcg_scalars_store(double rr, double rho, int k, const double *__restrict__ gamma,
-                                         const double *__restrict__ alpha, double *__restrict__ sc, int N,
-                                         double tau, double eps) {
-    double ga = 0.0;
-    for (int a = 0; a < k; ++a) ga += gamma[a] * alpha[a];
-    mcg_scalars_put(mcg_scalars_form(rr, rho, ga, sc[SC_RR0], N, tau, eps), sc);
-}
-
-// sc[SC_RR] from the |r|^2 partials; rho = r^T M^-1 r from its partials; t = gamma^T alpha / rho
-__global__ __launch_bounds__(64) void k_mcg_scalars(int k, const double *__restrict__ prr,
-                                                    const double *__restrict__ prho,
-                                                    const double *__restrict__ gamma,
-                                                    const double *__restrict__ alpha, double *__restrict__ sc,
-                                                    int N, double tau, double eps) {
-    const double rr = wave_partials(prr, 1, kRedBlocks);
-    const double rho = wave_partials(prho, 1, kRedBlocks);
-    if (threadIdx.x != 0) return;
-    mcg_scalars_store(rr, rho, k, gamma, alpha, sc, N, tau, eps);
-}
 
 // One kernel for the end of an iteration of Alg. 2 with the block-Jacobi preconditioner:
 // x += P alpha, r -= Q alpha (n x k blocks, column-major), Z = D^-1 r, and the scalars.
@@ -782,7 +670,9 @@ __global__ __launch_bounds__(64) void k_mcg_scalars(int k, const double *__restr
 // columns, the Cholesky factor of the thread's camera, the scalars already in sc, and
 // gamma of a block formed by the pseudo-inverse kernel.  Their latencies then overlap
 // the reduction of the Gram partials.
-template <int DP>
+// LR: with the learned low-rank term (XrzLowrank): the rows' U are loaded with the other
+// early loads, and the block's 8 sums of U^T r go beside its |r|^2 and r^T D^-1 r.
+template <int DP, bool LR>
 __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__restrict__ P,
                                                  const double *__restrict__ Q, double *alpha,
                                                  double *__restrict__ x, double *__restrict__ r,
@@ -790,13 +680,14 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
                                                  double *__restrict__ partials, uint32_t *__restrict__ ticket,
                                                  double *gamma, double *__restrict__ sc,
                                                  double *__restrict__ host_sc, double tag, int N, double tau,
-                                                 double eps, XrzGram g1) {
+                                                 double eps, XrzGram g1, XrzLowrank lr) {
     constexpr int CB = kNT / DP;
     constexpr int NL = DP * (DP + 1) / 2;
     __shared__ double sr[CB * DP];
     __shared__ double sh[kNT];
     __shared__ double al[kMaxK], ga_sh[kMaxK];
     __shared__ double rank_sh;
+    __shared__ double ush[4 * kLowRank];
     __shared__ int last;
     const int64_t n = (int64_t)np * DP;
     const int c0 = blockIdx.x * CB;
@@ -812,6 +703,11 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
         for (int e = 0; e < NL; ++e) Lc[e] = Lp[e];
     }
     const double scv = sc[t < SC_COUNT ? t : 0];
+    double ul[kLowRank];
+    if constexpr (LR) {
+#pragma unroll
+        for (int a = 0; a < kLowRank; ++a) ul[a] = lr.U[i * kLowRank + a];
+    }
     if (g1.part) {
         // one-column block: Delta = Q^T P and gamma = P^T r from the camera reduction's
         // partials, added in the same order by every block; Delta^+ = 1 / Delta unless
@@ -847,7 +743,7 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
         if (t == SC_RANK) rank_sh = scv;
     }
     __syncthreads();
-    double rr = 0.0;
+    double rr = 0.0, rv = 0.0;
     if (row) {
         double dx = 0.0, dr = 0.0;
         dx += p0 * al[0];
@@ -875,6 +771,14 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
         r[i] = v;
         sr[t] = v;
         rr = v * v;
+        rv = v;
+    }
+    if constexpr (LR) {   // the block's U^T r: a butterfly per wavefront, the four in order below
+#pragma unroll
+        for (int a = 0; a < kLowRank; ++a) {
+            const double s = wave_sum(ul[a] * rv);
+            if ((t & 63) == 0) ush[(t >> 6) * kLowRank + a] = s;
+        }
     }
     __syncthreads();
     double rho = 0.0;
@@ -894,6 +798,12 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
     if (t == 0) {
         partials[2 * blockIdx.x] = rr;
         partials[2 * blockIdx.x + 1] = rho;
+        if constexpr (LR) {
+#pragma unroll
+            for (int a = 0; a < kLowRank; ++a)
+                lr.part[blockIdx.x * kLowRank + a] =
+                    (ush[a] + ush[kLowRank + a]) + (ush[2 * kLowRank + a] + ush[3 * kLowRank + a]);
+        }
         const uint32_t prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         last = prev == gridDim.x - 1;
     }
@@ -902,6 +812,26 @@ __global__ __launch_bounds__(kNT) void k_mcg_xrz(int np, int k, const double *__
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     double srr, srho;
     wave_pair_sums(partials, gridDim.x, srr, srho);
+    if constexpr (LR) {
+        // w = U^T r over the blocks in order (lane l: blocks l, l + 64, ...), then
+        // rho = r^T M^-1 r = r^T D^-1 r + |w|^2; lane a stores w_a for the z update
+        double wa[kLowRank];
+#pragma unroll
+        for (int a = 0; a < kLowRank; ++a) wa[a] = 0.0;
+        for (int b = t; b < (int)gridDim.x; b += 64) {
+#pragma unroll
+            for (int a = 0; a < kLowRank; ++a) wa[a] += lr.part[b * kLowRank + a];
+        }
+        double wmine = 0.0, ww = 0.0;
+#pragma unroll
+        for (int a = 0; a < kLowRank; ++a) {
+            const double s = wave_sum(wa[a]);
+            ww += s * s;
+            if (t == a) wmine = s;
+        }
+        if (t < kLowRank) lr.w[t] = wmine;
+        srho += ww;
+    }
     // lane 0 forms and stores the scalars; every lane takes them by cross-lane broadcast
     // (never by reading what lane 0 just stored), the rest of sc from its early load
     McgScalars v{};
@@ -930,19 +860,32 @@ int mcg_xrz_blocks(int np, int dp) { return (np + kNT / dp - 1) / (kNT / dp); }
 void launch_mcg_xrz(int np, int k, const double *P, const double *Q, double *alpha, double *x, double *r,
                     const double *Dchol, double *z, double *partials, uint32_t *ticket, double *gamma,
                     double *sc, double *host_sc, double tag, int N, double tau, double eps, hipStream_t s, int dp,
-                    XrzGram g1) {
+                    XrzGram g1, XrzLowrank lr) {
     const unsigned nb = (unsigned)mcg_xrz_blocks(np, dp);
     if (dp == 6)
-        hipLaunchKernelGGL(k_mcg_xrz<6>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
-                           ticket, gamma, sc, host_sc, tag, N, tau, eps, g1);
+        hipLaunchKernelGGL((k_mcg_xrz<6, false>), dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z,
+                           partials, ticket, gamma, sc, host_sc, tag, N, tau, eps, g1, lr);
+    else if (lr.U)
+        hipLaunchKernelGGL((k_mcg_xrz<9, true>), dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z,
+                           partials, ticket, gamma, sc, host_sc, tag, N, tau, eps, g1, lr);
     else
-        hipLaunchKernelGGL(k_mcg_xrz<9>, dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z, partials,
-                           ticket, gamma, sc, host_sc, tag, N, tau, eps, g1);
+        hipLaunchKernelGGL((k_mcg_xrz<9, false>), dim3(nb), dim3(kNT), 0, s, np, k, P, Q, alpha, x, r, Dchol, z,
+                           partials, ticket, gamma, sc, host_sc, tag, N, tau, eps, g1, lr);
 }
 
-void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
-                        double *sc, int N, double tau, double eps, hipStream_t s) {
-    hipLaunchKernelGGL(k_mcg_scalars, dim3(1), dim3(64), 0, s, k, prr, prho, gamma, alpha, sc, N, tau, eps);
+// z += U w: the learned low-rank part of Z = M^-1 r after k_mcg_xrz formed D^-1 r and w = U^T r
+__global__ __launch_bounds__(kNT) void k_lr_zadd(int64_t n, const double *__restrict__ U,
+                                                 const double *__restrict__ w, double *__restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < kLowRank; ++a) s += U[i * kLowRank + a] * w[a];
+    z[i] = z[i] + s;
+}
+
+void launch_lr_zadd(int64_t n, const double *U, const double *w, double *z, hipStream_t s) {
+    hipLaunchKernelGGL(k_lr_zadd, dim3((unsigned)((n + kNT - 1) / kNT)), dim3(kNT), 0, s, n, U, w, z);
 }
 
 // Phi[col][p] = Q_hist[:, col]^T z restricted to segment p: with N > 1 subsets the

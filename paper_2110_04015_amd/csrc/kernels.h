@@ -187,8 +187,9 @@ void launch_pcg_xrz(int np, const double *pdq, int npdq, double *sc, double *x, 
 void launch_pcg_rr(const double *partials_rr, double *sc, hipStream_t s);
 
 // MCG steps
-// partials[b][...] of b < gram_blocks(k) blocks; with k > 1 their sums follow them, at
-// partials + gram_blocks(k) (k k + k)
+// Gram products of a block of k > 1 columns: partials[b][...] of b < gram_blocks(k)
+// blocks, their sums after them, at partials + gram_blocks(k) (k k + k) (one-column blocks
+// take theirs from the camera reduction of the product, see XrzGram)
 int gram_blocks(int k);
 void launch_gram(int64_t n, int k, const double *P, const double *Q, const double *r, double *partials,
                  hipStream_t s);
@@ -199,20 +200,12 @@ struct BlockEntry {
     int j = 0, first = 0;
     int64_t dpo = 0;
 };
+// k > 1: Delta^+ and alpha from the Gram sums (nblocks partial blocks before them)
 void launch_pinv_alpha(int k, const double *partials, int nblocks, double *Dp, double *gamma, double *alpha,
                        double *sc, hipStream_t s, BlockEntry blk = BlockEntry());
-// x += P alpha, r -= Q alpha (n x k, column-major); |r|^2 partials
-void launch_update_xr_blk(int64_t n, int k, const double *P, const double *Q, const double *alpha, double *x,
-                          double *r, double *partials, hipStream_t s);
-// z = D^-1 r and partials of r^T z
-void launch_precond_rho(int np, const double *Dchol, const double *r, double *z, double *partials, hipStream_t s,
-                        int dp = 9);
-// sc[SC_RR], sc[SC_RHO], sc[SC_T] from the partials (Alg. 2's stop and tau tests), and
-// sc[SC_SKIPM]: 0 when the next block is multidirectional (N > 1, t < tau, not converged)
-void launch_mcg_scalars(int k, const double *prr, const double *prho, const double *gamma, const double *alpha,
-                        double *sc, int N, double tau, double eps, hipStream_t s);
-// Fused end of an MCG iteration with the block-Jacobi preconditioner: x += P alpha,
-// r -= Q alpha, z = D^-1 r, and the scalars of launch_mcg_scalars, from
+// Fused end of an MCG iteration: x += P alpha, r -= Q alpha, z = D^-1 r, and the scalars of
+// Alg. 2's stop and tau tests (sc[SC_RR], [SC_RHO], [SC_T], and the next block's width in
+// sc[SC_SKIPM], [SC_KN], [SC_SKIPS]), from
 // mcg_xrz_blocks(np, dp) blocks' partials (2 per block) added by the last block to arrive
 // (ticket: a zero counter, left zero); that block also copies sc[0, SC_COUNT) to host_sc
 // (nullable: mapped host memory of SC_COUNT + 1 doubles) and, once those values are
@@ -226,11 +219,23 @@ struct XrzGram {
     double *Dp = nullptr;
     BlockEntry blk;
 };
+// The learned low-rank term of the preconditioner, M^-1 = D^-1 + U U^T (U: n x 8,
+// row-major; d_p = 9): each block leaves the 8 partial sums of U^T r in part[8 b ..], the
+// last block adds them into w (8 doubles) and takes rho = r^T D^-1 r + |w|^2; Z = D^-1 r
+// then still needs + U w (launch_lr_zadd, next on the stream).
+constexpr int kLowRank = 8;   // columns of the learned low-rank term U
+struct XrzLowrank {
+    const double *U = nullptr;
+    double *part = nullptr;
+    double *w = nullptr;
+};
 int mcg_xrz_blocks(int np, int dp);
 void launch_mcg_xrz(int np, int k, const double *P, const double *Q, double *alpha, double *x, double *r,
                     const double *Dchol, double *z, double *partials, uint32_t *ticket, double *gamma,
                     double *sc, double *host_sc, double tag, int N, double tau, double eps, hipStream_t s,
-                    int dp = 9, XrzGram g1 = XrzGram());
+                    int dp = 9, XrzGram g1 = XrzGram(), XrzLowrank lr = XrzLowrank());
+// z += U w (n x 8 row-major U, w of 8 doubles)
+void launch_lr_zadd(int64_t n, const double *U, const double *w, double *z, hipStream_t s);
 // Phi segments per history column: the N subsets when N > 1 (the same for one-column
 // and multidirectional steps), kPhiSeg row segments when N = 1
 int phi_segments(int N);
