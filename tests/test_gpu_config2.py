@@ -19,6 +19,7 @@ import pytest
 
 import oracle
 import synth
+from oracle import reduced as R
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -70,6 +71,13 @@ def test_matvec(cap):
     assert np.abs(y32 - ref).max() / scale < 2e-5
     y16 = _h(g.matvec(_dev(v), precision="bf16"))
     assert np.abs(y16 - ref).max() / scale < 3e-2
+    # and per element against the FP64 product with the stored blocks, within 64 u32 of
+    # the absolute sum of its terms (the bound of the parity tests' reduced products)
+    lamd = R.lambda_diag(o.U_blocks(), p.lam)
+    for prec, y in (("fp32", y32), ("bf16", y16)):
+        yr, ya = R.schur_matvec_stored(p.obs_cam, p.obs_lm, p.n_cams, p.n_lms, R.stored(p.J_p, prec),
+                                       R.stored(p.J_l, prec), o.Vinv_blocks(), lamd, v)
+        assert np.all(np.abs(y - yr) <= 64 * 2.0 ** -24 * ya), prec
 
 
 def test_fixed_iterations(cap):

@@ -19,6 +19,7 @@ import scipy.sparse.linalg as spla
 
 import oracle
 import synth
+from oracle import reduced as R
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -74,6 +75,11 @@ def test_products(pair):
     assert rel(_h(g.matvec(_dev(v))), ref) < 1e-12
     assert relnorm(_h(g.matvec(_dev(v), precision="fp32")), ref) < 2e-5
     assert relnorm(_h(g.matvec(_dev(v), precision="bf16")), ref) < 3e-2
+    lamd = R.lambda_diag(o.U_blocks(), p.lam)
+    for prec in ("fp32", "bf16"):   # per element: 64 u32 of the terms' absolute sum
+        yr, ya = R.schur_matvec_stored(p.obs_cam, p.obs_lm, p.n_cams, p.n_lms, R.stored(p.J_p, prec),
+                                       R.stored(p.J_l, prec), o.Vinv_blocks(), lamd, v)
+        assert np.all(np.abs(_h(g.matvec(_dev(v), precision=prec)) - yr) <= 64 * 2.0 ** -24 * ya), prec
     for N in (3, 16):
         if N > p.n_cams:
             continue

@@ -18,12 +18,20 @@ Tolerances (FP64 path):
   up to 5e-8 in x at eps = 1e-10 and up to 5e-7 (energy norm) at eps = 1e-6 on
   these problems: the gauge directions of S are damped only by lambda, so a
   1e-9 gate on such iterates would measure summation order, not correctness.
+Reduced-precision products (FP32 arithmetic on FP32 or BF16 Jacobian blocks, FP64 sums):
+  per element against the FP64 product with the stored blocks (oracle/reduced.py), within
+  64 u (u = 2^-24) times the sum of the absolute values of the terms. The longest chain
+  of FP32 roundings behind one term has about 25 (the FP32 casts of v, V^-1 and g, the
+  9-term e = J_p v, the 3-term V^-1 g, J_l h and the difference, the 2-term J_p^T f), so
+  the first-order bound is about 25 u; 64 u leaves room. A wrong index, sign or dropped
+  term moves elements by the size of the terms, far above it.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from oracle import reduced as R
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -45,6 +53,22 @@ def rel(a, b):
 
 def relnorm(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+U32 = 2.0 ** -24
+
+
+def stored_product(p, o, prec, v):
+    """(S^ v, |S^||v|) of the reduced-precision operator: the blocks as stored, V^-1 and the
+    damping of the FP64 system."""
+    return R.schur_matvec_stored(p.obs_cam, p.obs_lm, p.n_cams, p.n_lms, R.stored(p.J_p, prec),
+                                 R.stored(p.J_l, prec), o.Vinv_blocks(), R.lambda_diag(o.U_blocks(), p.lam), v)
+
+
+def assert_within_rounding(y, ref, bound, what=""):
+    err = np.abs(y - ref)
+    i = int(np.argmax(err / np.maximum(bound, 1e-300)))
+    assert np.all(err <= 64 * U32 * bound), (what, i, err[i], bound[i])
 
 
 PROBLEMS = {
@@ -165,6 +189,8 @@ def test_matvec_reduced_precision(pair, prec, tol):
     v = np.random.default_rng(2).standard_normal(g.n)
     y = _h(g.matvec(_dev(v), precision=prec))
     assert relnorm(y, o.matvec(v)) < tol
+    ref, bound = stored_product(p, o, prec, v)
+    assert_within_rounding(y, ref, bound, (name, prec))
 
 
 # ---------------------------------------------------------------- A3 S Z
@@ -227,7 +253,10 @@ def test_matmat_grouped_reduced_precision(pair, prec, tol):
     Y = _h(g.matmat_grouped(N, _dev(z), precision=prec))
     grp = np.repeat(oracle.partition(p.n_cams, N), 9)
     for q in range(N):
-        assert relnorm(Y[q], o.matvec(np.where(grp == q, z, 0.0))) < tol, q
+        zq = np.where(grp == q, z, 0.0)
+        assert relnorm(Y[q], o.matvec(zq)) < tol, q
+        ref, bound = stored_product(p, o, prec, zq)
+        assert_within_rounding(Y[q], ref, bound, (name, prec, q))
 
 
 def test_matmat_grouped_large_lds():
