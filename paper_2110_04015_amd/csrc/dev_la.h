@@ -403,8 +403,58 @@ __device__ __forceinline__ void gj_wave(int k, const double *A, double *G, int *
     if (c == 0) *bad = nonpos;
 }
 
+// The same elimination by the four wavefronts of the block (k <= 64): wavefront w keeps
+// rows [16 w, 16 w + 16) of the padded 64 x 64 matrix, lane c their entries in column c, in
+// place (no rotation).  Step j: the wavefront holding row j puts it in LDS (two buffers
+// used in turn, so one barrier per step orders each write after the last read of the same
+// buffer), every lane reads its column's pivot-row entry and the pivot, and takes a_ij of
+// its rows from lane j of its own wavefront (readlane).  Each step is 16 FMAs and 16
+// cross-lane reads per lane instead of 63: with wide blocks the one-wavefront form is a
+// chain of k (KP - 1) dependent steps.  Called by every thread of the block.
+__device__ __forceinline__ void gj_block(int k, const double *A, double *G, int *bad, double *prow) {
+    const int tid = threadIdx.x, w = tid >> 6, c = tid & 63;
+    double a[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 16 * w + r;
+        a[r] = (i < k && c < k) ? A[i * k + c] : (i == c ? 1.0 : 0.0);
+    }
+    bool nonpos = false;
+    for (int jb = 0; jb < 4 && 16 * jb < k; ++jb) {
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+            const int j = 16 * jb + jj;
+            if (j < k) {
+                double *buf = prow + (j & 1) * 64;
+                if (w == jb) buf[c] = a[jj];
+                __syncthreads();
+                const double p = buf[j], pj = buf[c];
+                nonpos |= !(p > 0.0);
+                const double ip = 1.0 / (p > 0.0 ? p : 1.0);
+                const bool piv = c == j;
+                const double t = (piv ? 1.0 : pj) * ip;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const double aij = readlane_f64(a[r], j);
+                    a[r] = (piv ? 0.0 : a[r]) - aij * t;
+                }
+                if (w == jb) a[jj] = t;   // the pivot row: a_jc / p, and 1 / p at c = j
+            }
+        }
+    }
+    if (c < k) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 16 * w + r;
+            if (i < k) G[i * k + c] = a[r];
+        }
+    }
+    if (tid == 0) *bad = nonpos;
+}
+
 // Inverse of the symmetric k x k matrix A (k <= 64, LDS) into G: Gauss-Jordan elimination
-// on the diagonal pivots by the first wavefront (gj_wave), then the result is
+// on the diagonal pivots (gj_wave by the first wavefront up to k = 32, gj_block by the
+// four beyond), then the result is
 // symmetrised by the whole block.  Returns (the same in every thread) whether every
 // pivot was positive (A positive definite) and |A|_F |A^-1|_F < 1e-4 / (k eps): then
 // every eigenvalue lies above the drop threshold k eps max|l| (l_min >= 1 / |A^-1|_F,
@@ -412,12 +462,14 @@ __device__ __forceinline__ void gj_wave(int k, const double *A, double *G, int *
 __device__ __forceinline__ bool inv_gj(int k, const double *A, double *G, double *sh) {
     constexpr int U = kMaxK * kMaxK / kNT;   // elements per thread at most
     __shared__ int nonpos;
+    __shared__ double prow[2 * 64];
     const int tid = threadIdx.x;
     const int kk = k * k;
-    if (tid < 64) {
+    if (k > 32) {
+        gj_block(k, A, G, &nonpos, prow);
+    } else if (tid < 64) {
         if (k <= 16) gj_wave<16>(k, A, G, &nonpos);
-        else if (k <= 32) gj_wave<32>(k, A, G, &nonpos);
-        else gj_wave<64>(k, A, G, &nonpos);
+        else gj_wave<32>(k, A, G, &nonpos);
     }
     __syncthreads();
     double fa = 0.0, fi = 0.0;

@@ -296,7 +296,8 @@ def test_back_substitution(pair):
 # ---------------------------------------------------------------- A6 pinv
 
 
-@pytest.mark.parametrize("k,r", [(1, 1), (2, 2), (5, 5), (16, 16), (47, 47), (64, 64), (16, 9), (47, 30), (64, 1)])
+@pytest.mark.parametrize("k,r", [(1, 1), (2, 2), (5, 5), (16, 16), (32, 32), (33, 33), (47, 47), (57, 57), (64, 64),
+                                 (16, 9), (47, 30), (64, 1)])
 def test_pinv(k, r):
     rng = np.random.default_rng(k * 100 + r)
     Qm, _ = np.linalg.qr(rng.standard_normal((k, k)))
