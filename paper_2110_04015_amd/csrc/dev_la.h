@@ -346,9 +346,11 @@ __device__ __forceinline__ double segment_scan(double x, const Segs &g) {
     return x;
 }
 
-// Sum of x over the lane's segment, returned in every lane of the segment.
-__device__ __forceinline__ double segment_sum(double x, const Segs &g) {
-    return __shfl(segment_scan(x, g), g.end, 64);
+// Sum of x over the lane's segment, rounded to T at the segment's last lane and returned
+// in every lane of the segment (a float moves in one cross-lane read, a double in two).
+template <typename T>
+__device__ __forceinline__ T segment_sum(double x, const Segs &g) {
+    return __shfl((T)segment_scan(x, g), g.end, 64);
 }
 
 // Sum over the block's threads: wavefront butterflies, then the wavefronts in order

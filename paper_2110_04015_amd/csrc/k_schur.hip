@@ -200,11 +200,12 @@ __device__ __forceinline__ void schur_tile(const T (&J)[2 * DP + 6], const dbl2_
         e0 += J[k] * vc[k];
         e1 += J[DP + k] * vc[k];
     }
-    double gs[3];
+    T gs[3];   // g_l, rounded to T where h = V^-1 g is formed
     if constexpr (SEG) {
         const Segs sg = tile_segments(mt, lane);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) gs[k] = segment_sum(valid ? (double)(J[L0 + k] * e0 + J[L1 + k] * e1) : 0.0, sg);
+        for (int k = 0; k < 3; ++k)
+            gs[k] = segment_sum<T>(valid ? (double)(J[L0 + k] * e0 + J[L1 + k] * e1) : 0.0, sg);
     } else {
         gloc[lane * 3 + 0] = 0;
         gloc[lane * 3 + 1] = 0;
@@ -216,12 +217,12 @@ __device__ __forceinline__ void schur_tile(const T (&J)[2 * DP + 6], const dbl2_
         }
         wave_sync();
 #pragma unroll
-        for (int k = 0; k < 3; ++k) gs[k] = gloc[ll * 3 + k];
+        for (int k = 0; k < 3; ++k) gs[k] = (T)gloc[ll * 3 + k];
     }
     if (valid) {
         const T w0 = (T)vi[0].x, w1 = (T)vi[0].y, w2 = (T)vi[1].x;
         const T w3 = (T)vi[1].y, w4 = (T)vi[2].x, w5 = (T)vi[2].y;
-        const T g0 = (T)gs[0], g1 = (T)gs[1], g2 = (T)gs[2];
+        const T g0 = gs[0], g1 = gs[1], g2 = gs[2];
         const T h0 = w0 * g0 + w1 * g1 + w2 * g2;
         const T h1 = w1 * g0 + w3 * g1 + w4 * g2;
         const T h2 = w2 * g0 + w4 * g1 + w5 * g2;
@@ -520,9 +521,9 @@ __device__ __forceinline__ void multi_tile(const MultiArgs &a, const T (&J)[2 * 
     if constexpr (SEG) {
         // segments: the pairs (own pair index), padding lanes one each
         const Segs sg = tile_segments(valid ? (uint32_t)own << 16 : kPad, lane);
-        double gs[3];
+        double gs[3];   // the pair's total, in its last lane (the only one that uses it)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) gs[k] = segment_sum(valid ? (double)(J[L0 + k] * e0 + J[L1 + k] * e1) : 0.0, sg);
+        for (int k = 0; k < 3; ++k) gs[k] = segment_scan(valid ? (double)(J[L0 + k] * e0 + J[L1 + k] * e1) : 0.0, sg);
         if (valid && sg.end == lane) {
             const T g0 = (T)gs[0], g1 = (T)gs[1], g2 = (T)gs[2];
             hloc[own * 3 + 0] = (double)(w0 * g0 + w1 * g1 + w2 * g2);
