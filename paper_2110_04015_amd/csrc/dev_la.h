@@ -309,7 +309,9 @@ struct Segs {
 };
 
 __device__ __forceinline__ Segs key_segments(int key, int lane) {
-    const int prev = __shfl_up(key, 1, 64);
+    // the previous lane's key by a DPP whole-wavefront shift (wave_shr:1; lane 0 keeps its
+    // own and is a segment head regardless), not a cross-lane read through the LDS pipe
+    const int prev = __builtin_amdgcn_update_dpp(key, key, 0x138, 0xf, 0xf, false);
     const uint64_t heads = __ballot(lane == 0 || prev != key);
     const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);
     const int start = 63 - __clzll(heads & upto);
