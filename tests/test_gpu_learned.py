@@ -109,8 +109,15 @@ def _lowrank_reduced_precision_case(case):
 
 
 def _check_energy_error(g, S, xs, N, prec):
-    x, st = g.mcg(N, 3.3, eps=1e-10, precision=prec, precond="lowrank", max_iter=20000, max_outer=60)
-    assert st.status == ba.BA_OK, (N, st)
+    x, st = g.mcg(N, 3.3, eps=1e-10, precision=prec, precond="lowrank", max_iter=20000, max_outer=60,
+                  trace=True)
+    # on failure, a digest of the inner solves' recursive residuals (every 20th iteration),
+    # their tau-test values and block widths
+    k = st.iterations
+    digest = dict(res=np.array2string(st.trace_res[:k:20], precision=2),
+                  t=np.array2string(st.trace_t[:k:20], precision=2), widths=np.bincount(st.trace_k[:k]).tolist())
+    assert st.status == ba.BA_OK, (N, st.iterations, st.multi_steps, st.refinement_steps, st.status,
+                                   st.rel_res_recursive, digest)
     e = _h(x) - xs
     assert np.sqrt(e @ S @ e) / np.sqrt(xs @ S @ xs) <= 1e-6, N
 
