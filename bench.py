@@ -115,7 +115,8 @@ def run_learned(g, variants, args, log):
     walk1936-shaped problems (the library's own features, probes, loss, backpropagation and
     Adam), then applied to walk1936 (features, BF16 inference, U: the setup of one
     linearisation) and timed with MCG in FP64 and with FP32 products under FP64
-    refinement, against the plain block-Jacobi solves and FP64 PCG of the variants."""
+    refinement, and with PCG, against the plain block-Jacobi solves and FP64 PCG of the
+    variants."""
     import torch
     from paper_2110_04015_amd import learned as L
     t = time.time()
@@ -140,9 +141,14 @@ def run_learned(g, variants, args, log):
     out["setup_ms"] = round((time.perf_counter() - t1) / 3 * 1e3, 3)
     for name, kw in [("mcg_fp64_N16", dict(N=16, precision="fp64")),
                      ("mcg_fp32_refined_N16", dict(N=16, precision="fp32")),
-                     ("mcg_fp32_refined_N4", dict(N=4, precision="fp32"))]:
-        f = lambda: g.mcg(kw["N"], args.tau, eps=1e-6, max_iter=1000, precision=kw["precision"],
-                          precond="lowrank")
+                     ("mcg_fp32_refined_N4", dict(N=4, precision="fp32")),
+                     ("pcg_fp64", dict(N=0, precision="fp64")),
+                     ("pcg_fp32_refined", dict(N=0, precision="fp32"))]:
+        if kw["N"]:
+            f = lambda: g.mcg(kw["N"], args.tau, eps=1e-6, max_iter=1000, precision=kw["precision"],
+                              precond="lowrank")
+        else:
+            f = lambda: g.pcg(eps=1e-6, max_iter=1000, precision=kw["precision"], precond="lowrank")
         f()
         ts = []
         for _ in range(3):
